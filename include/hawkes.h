@@ -1,0 +1,179 @@
+/*
+ * hawkes.h -- C ABI of the MI355X (gfx950) library for the exact
+ * log-likelihood of the multivariate linear exponential Hawkes process and
+ * its gradient, evaluated as a parallel scan of affine transition maps.
+ *
+ * Paper: "Massively Parallel Exact Inference for Hawkes Processes"
+ * (arXiv 2604.01342).
+ *
+ *   Intensity (Background, eq. 1), one decay kernel (K = 1):
+ *     lambda_p(t) = mu_p + sum_{j : t_j < t} alpha[p][m_j] * beta_p * exp(-beta_p (t - t_j))
+ *   with beta_p = beta[0] for every p (HAWKES_BETA_SHARED, the paper's gamma)
+ *   or one decay per target node (HAWKES_BETA_PER_TARGET).
+ *   Log-likelihood (eq. 2):
+ *     L = sum_i log lambda_{m_i}(t_i) - sum_p int_0^T lambda_p(t) dt
+ *   Gradients: eqs. 8, 9, 10 (Appendix "Parameter Gradient Formulas").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array arguments are DEVICE pointers owned by the caller (for example
+ *    PyTorch tensors).  The library allocates nothing: scratch space is the
+ *    caller's `workspace` (size from the matching *_workspace_bytes query,
+ *    256-byte aligned, contents need not be initialised).
+ *  - Calls are asynchronous and ordered on `stream`; they neither synchronise
+ *    with the host nor read device memory from the host, so they can be
+ *    captured into a HIP graph.  Two calls that share a workspace must be
+ *    ordered on one stream.
+ *  - Layouts: t[n] float64, nondecreasing, 0 <= t[i] <= T; marks[n] int32 in
+ *    [0, m); mu[m] float32; alpha[m*m] float32 row-major, alpha[p*m + q] is
+ *    the excitation of target p by a source event of node q (eq. 1 uses
+ *    alpha_{p, m_j}); beta[1] or beta[m] float32 (> 0).
+ *  - Ties: events with equal time stamps excite later events in index order,
+ *    which is what the recurrence of eq. 4 computes.
+ *  - Outputs are float64: loglik[1], g_mu[m], g_alpha[m*m] (same layout as
+ *    alpha), g_beta[1] (shared) or g_beta[m] (per target).  Any gradient
+ *    pointer may be NULL to skip that output.
+ *  - Precision: time differences are formed in float64, decays, scan state
+ *    and intensities are float32, and every sum over events (log-likelihood,
+ *    gradients) is accumulated in float64 in a fixed order, so repeated calls
+ *    return bitwise-identical results.
+ *  - Errors: every function returns a hawkes_status.  Host-detectable
+ *    argument errors return HAWKES_EINVAL (or HAWKES_EWORKSPACE for a short
+ *    workspace) before anything is launched, and the outputs are untouched.
+ *    Data-dependent preconditions (sorted times, marks in range, positive
+ *    parameters) are not checked by the compute calls: violating them gives
+ *    meaningless numbers but never an out-of-bounds access (marks are clamped
+ *    for addressing).  hawkes_check_inputs() checks them on the device.
+ *    A failed kernel launch returns HAWKES_EDEVICE.
+ */
+#ifndef HAWKES_H
+#define HAWKES_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HAWKES_ABI_VERSION 1
+
+typedef enum hawkes_status {
+    HAWKES_OK = 0,
+    HAWKES_EINVAL = 1,        /* bad argument (NULL pointer, size, mode) */
+    HAWKES_EWORKSPACE = 2,    /* workspace NULL or smaller than required */
+    HAWKES_EDEVICE = 3,       /* a HIP call or kernel launch failed */
+    HAWKES_EUNSUPPORTED = 4   /* valid request this build does not implement (k > 1) */
+} hawkes_status;
+
+typedef enum hawkes_beta_mode {
+    HAWKES_BETA_SHARED = 0,     /* beta[1]: one decay for every target (eq. 1, K = 1) */
+    HAWKES_BETA_PER_TARGET = 1  /* beta[m]: decay beta_p of the target's kernel */
+} hawkes_beta_mode;
+
+/* One event sequence.  `chunk_log2` selects constant-memory processing: the
+ * sequence is evaluated in consecutive chunks of 2^chunk_log2 events, each
+ * carrying only an M-vector state into the next (the batching of the
+ * "Time Complexity Analysis and Batching" section and Algorithm 2), so the
+ * workspace does not grow with n.  0 selects the default (2^20).  Valid
+ * range 12..26. */
+typedef struct hawkes_problem {
+    int64_t n;           /* number of events, >= 0 */
+    int32_t m;           /* number of nodes M, >= 1 */
+    int32_t k;           /* number of decay kernels; must be 1 */
+    int32_t beta_mode;   /* hawkes_beta_mode */
+    int32_t chunk_log2;  /* 0 = default */
+    double  T;           /* window end, >= 0 and >= t[n-1] */
+} hawkes_problem;
+
+/* Human-readable name of a status code (static storage). */
+const char* hawkes_status_string(hawkes_status s);
+
+/* HAWKES_ABI_VERSION of the loaded library. */
+int hawkes_version(void);
+
+/* Workspace bytes needed by hawkes_loglik (with_grad = 0) or
+ * hawkes_loglik_grad (with_grad = 1) for problem p; 0 if p is invalid. */
+size_t hawkes_workspace_bytes(const hawkes_problem* p, int with_grad);
+
+/* Log-likelihood only (eq. 2).  loglik: device float64[1]. */
+hawkes_status hawkes_loglik(const hawkes_problem* p,
+                            const double* t, const int32_t* marks,
+                            const float* mu, const float* alpha, const float* beta,
+                            double* loglik,
+                            void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Log-likelihood and its gradient (eqs. 2, 8, 9, 10).  Outputs overwrite the
+ * destination arrays; NULL gradient pointers are skipped. */
+hawkes_status hawkes_loglik_grad(const hawkes_problem* p,
+                                 const double* t, const int32_t* marks,
+                                 const float* mu, const float* alpha, const float* beta,
+                                 double* loglik, double* g_mu, double* g_alpha, double* g_beta,
+                                 void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Intensities at the events, lambda_out[i] = lambda_{m_i}(t_i) (eq. 1) as
+ * float32 (the value the log-likelihood uses).  Same workspace as
+ * hawkes_loglik. */
+hawkes_status hawkes_intensity(const hawkes_problem* p,
+                               const double* t, const int32_t* marks,
+                               const float* mu, const float* alpha, const float* beta,
+                               float* lambda_out,
+                               void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ----------------------------------------------------------------------------
+ * Batched: S independent sequences in one launch sequence (no host sync).
+ * Sequence s owns events [ev_off[s], ev_off[s+1]) of t/marks, has m_s[s]
+ * nodes, window end T_s[s] and one shared decay beta[s].  Its parameters are
+ * packed back to back: mu at sum_{r<s} m_s[r], alpha at sum_{r<s} m_s[r]^2
+ * (row-major m_s[s] x m_s[s]); the library computes these offsets on the
+ * device.  Outputs use the same packing: loglik[S], g_mu (like mu),
+ * g_alpha (like alpha), g_beta[S].
+ * Host arguments: S >= 1, n_total = ev_off[S] (the length of t), and
+ * max_m >= every m_s[s] (sizes the kernels' on-chip buffers; max_m <= 64).
+ * ------------------------------------------------------------------------- */
+size_t hawkes_batched_workspace_bytes(int32_t S, int64_t n_total, int32_t max_m, int with_grad);
+
+hawkes_status hawkes_loglik_batched(int32_t S, int64_t n_total, int32_t max_m,
+                                    const int64_t* ev_off, const int32_t* m_s, const double* T_s,
+                                    const double* t, const int32_t* marks,
+                                    const float* mu, const float* alpha, const float* beta,
+                                    double* loglik,
+                                    void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+hawkes_status hawkes_loglik_grad_batched(int32_t S, int64_t n_total, int32_t max_m,
+                                         const int64_t* ev_off, const int32_t* m_s, const double* T_s,
+                                         const double* t, const int32_t* marks,
+                                         const float* mu, const float* alpha, const float* beta,
+                                         double* loglik, double* g_mu, double* g_alpha, double* g_beta,
+                                         void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ----------------------------------------------------------------------------
+ * Baseline: the sequential recurrence of the "Sequential Recurrence" section
+ * (eqs. 4, 11, 12) evaluated event by event in index order by one
+ * workgroup whose lanes own slices of the M-vector state.  Same inputs,
+ * outputs, precision and workspace as hawkes_loglik_grad; shared beta only.
+ * It exists to measure the parallel scan against; it is not fast.
+ * ------------------------------------------------------------------------- */
+hawkes_status hawkes_sequential_loglik_grad(const hawkes_problem* p,
+                                            const double* t, const int32_t* marks,
+                                            const float* mu, const float* alpha, const float* beta,
+                                            double* loglik, double* g_mu, double* g_alpha, double* g_beta,
+                                            void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ----------------------------------------------------------------------------
+ * Device-side input validation.  Writes to *status_out (device int32) the OR
+ * of: 1 times not nondecreasing, 2 a mark outside [0,m), 4 a time outside
+ * [0,T], 8 mu <= 0 or not finite, 16 alpha < 0 or not finite, 32 beta <= 0
+ * or not finite; 0 when all preconditions hold.  Stream-ordered.
+ * ------------------------------------------------------------------------- */
+hawkes_status hawkes_check_inputs(const hawkes_problem* p,
+                                  const double* t, const int32_t* marks,
+                                  const float* mu, const float* alpha, const float* beta,
+                                  int32_t* status_out, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HAWKES_H */

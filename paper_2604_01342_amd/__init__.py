@@ -1,0 +1,310 @@
+"""Exact Hawkes log-likelihood and gradient on AMD Instinct MI355X (gfx950).
+
+Thin Python binding of the C ABI in include/hawkes.h (libhawkes.so, built
+from csrc/ by build.py).  It only marshals arguments: PyTorch provides the
+device memory (tensors, workspace) and the stream; every step of the
+computation runs in the library's HIP kernels.  If the library is missing
+the functions raise; there is no CPU fallback.
+
+Paper: "Massively Parallel Exact Inference for Hawkes Processes"
+(arXiv 2604.01342), intensity eq. 1, log-likelihood eq. 2, gradients
+eqs. 8-10.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+__all__ = [
+    "HawkesError", "lib", "library_path", "workspace_bytes", "loglik", "loglik_grad",
+    "intensity", "loglik_batched", "loglik_grad_batched", "sequential_loglik_grad",
+    "check_inputs", "HawkesLogLik", "hawkes_loglik", "BETA_SHARED", "BETA_PER_TARGET",
+]
+
+BETA_SHARED = 0
+BETA_PER_TARGET = 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "libhawkes.so")
+_lib = None
+
+_STATUS = {0: "ok", 1: "invalid argument", 2: "workspace missing or too small", 3: "device error",
+           4: "unsupported request"}
+
+
+class HawkesError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        super().__init__(f"{fn} failed: status {status} ({_STATUS.get(status, 'unknown')})")
+        self.status = status
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("beta_mode", ctypes.c_int32), ("chunk_log2", ctypes.c_int32), ("T", ctypes.c_double)]
+
+
+def library_path() -> str:
+    return _LIBPATH
+
+
+def lib():
+    """Load libhawkes.so (built in-tree).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIBPATH):
+        raise RuntimeError(f"{_LIBPATH} is missing: build it with paper_2604_01342_amd/build.py "
+                           "(or __graft_entry__.build())")
+    L = ctypes.CDLL(_LIBPATH)
+    vp, sz, i32, i64, d = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER(_Problem)
+    L.hawkes_status_string.argtypes = [ctypes.c_int]
+    L.hawkes_status_string.restype = ctypes.c_char_p
+    L.hawkes_version.restype = ctypes.c_int
+    L.hawkes_workspace_bytes.argtypes = [P, ctypes.c_int]
+    L.hawkes_workspace_bytes.restype = sz
+    L.hawkes_loglik.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.hawkes_loglik_grad.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.hawkes_intensity.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.hawkes_sequential_loglik_grad.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.hawkes_check_inputs.argtypes = [P, vp, vp, vp, vp, vp, vp, vp]
+    L.hawkes_batched_workspace_bytes.argtypes = [i32, i64, i32, ctypes.c_int]
+    L.hawkes_batched_workspace_bytes.restype = sz
+    L.hawkes_loglik_batched.argtypes = [i32, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.hawkes_loglik_grad_batched.argtypes = [i32, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                             sz, vp]
+    for f in ("hawkes_loglik", "hawkes_loglik_grad", "hawkes_intensity", "hawkes_sequential_loglik_grad",
+              "hawkes_check_inputs", "hawkes_loglik_batched", "hawkes_loglik_grad_batched"):
+        getattr(L, f).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _ptr(x):
+    return ctypes.c_void_p(x.data_ptr()) if x is not None else ctypes.c_void_p(0)
+
+
+def _stream(dev):
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _check(fn, status):
+    if status != 0:
+        raise HawkesError(fn, status)
+
+
+_ws_cache: dict = {}
+
+
+def _workspace(dev, nbytes: int) -> torch.Tensor:
+    """Reusable, 256-byte aligned device scratch (grown on demand)."""
+    key = (dev.type, dev.index)
+    buf = _ws_cache.get(key)
+    if buf is None or buf.numel() < nbytes + 256:
+        buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        _ws_cache[key] = buf
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + nbytes]
+
+
+def _prep(t, m, mu, alpha, beta):
+    dev = mu.device
+    if dev.type != "cuda":
+        raise ValueError("tensors must be on a GPU device")
+    t = t.to(device=dev, dtype=torch.float64).contiguous()
+    m = m.to(device=dev, dtype=torch.int32).contiguous()
+    mu = mu.detach().to(dtype=torch.float32).contiguous()
+    alpha = alpha.detach().to(dtype=torch.float32).contiguous()
+    beta = beta.detach().to(device=dev, dtype=torch.float32).reshape(-1).contiguous()
+    if alpha.numel() != mu.numel() ** 2:
+        raise ValueError("alpha must be M x M")
+    if t.numel() != m.numel():
+        raise ValueError("t and marks differ in length")
+    return dev, t, m, mu, alpha, beta
+
+
+def _problem(t, mu, beta, T, chunk_log2):
+    M = mu.numel()
+    mode = BETA_SHARED if beta.numel() == 1 else BETA_PER_TARGET
+    if mode == BETA_PER_TARGET and beta.numel() != M:
+        raise ValueError("beta must have 1 or M entries")
+    return _Problem(t.numel(), M, 1, mode, int(chunk_log2), float(T))
+
+
+def workspace_bytes(n: int, M: int, per_target: bool = False, grad: bool = True, chunk_log2: int = 0) -> int:
+    p = _Problem(n, M, 1, BETA_PER_TARGET if per_target else BETA_SHARED, chunk_log2, 1.0)
+    return int(lib().hawkes_workspace_bytes(ctypes.byref(p), int(grad)))
+
+
+def loglik(t, m, mu, alpha, beta, T, chunk_log2: int = 0) -> torch.Tensor:
+    """Log-likelihood (eq. 2) as a float64 0-d device tensor."""
+    dev, t, m, mu, alpha, beta = _prep(t, m, mu, alpha, beta)
+    p = _problem(t, mu, beta, T, chunk_log2)
+    L = lib()
+    nb = L.hawkes_workspace_bytes(ctypes.byref(p), 0)
+    ws = _workspace(dev, nb)
+    out = torch.empty(1, dtype=torch.float64, device=dev)
+    _check("hawkes_loglik", L.hawkes_loglik(ctypes.byref(p), _ptr(t), _ptr(m), _ptr(mu), _ptr(alpha), _ptr(beta),
+                                            _ptr(out), _ptr(ws), nb, _stream(dev)))
+    return out[0]
+
+
+def loglik_grad(t, m, mu, alpha, beta, T, chunk_log2: int = 0):
+    """(L, dL/dmu [M], dL/dalpha [M, M], dL/dbeta [1] or [M]) as float64 device tensors."""
+    dev, t, m, mu, alpha, beta = _prep(t, m, mu, alpha, beta)
+    p = _problem(t, mu, beta, T, chunk_log2)
+    L = lib()
+    nb = L.hawkes_workspace_bytes(ctypes.byref(p), 1)
+    ws = _workspace(dev, nb)
+    M = mu.numel()
+    out = torch.empty(1, dtype=torch.float64, device=dev)
+    gmu = torch.empty(M, dtype=torch.float64, device=dev)
+    ga = torch.empty(M, M, dtype=torch.float64, device=dev)
+    gb = torch.empty(beta.numel(), dtype=torch.float64, device=dev)
+    _check("hawkes_loglik_grad",
+           L.hawkes_loglik_grad(ctypes.byref(p), _ptr(t), _ptr(m), _ptr(mu), _ptr(alpha), _ptr(beta), _ptr(out),
+                                _ptr(gmu), _ptr(ga), _ptr(gb), _ptr(ws), nb, _stream(dev)))
+    return out[0], gmu, ga, gb
+
+
+def intensity(t, m, mu, alpha, beta, T, chunk_log2: int = 0) -> torch.Tensor:
+    """lambda_{m_i}(t_i) for every event (eq. 1), float32."""
+    dev, t, m, mu, alpha, beta = _prep(t, m, mu, alpha, beta)
+    p = _problem(t, mu, beta, T, chunk_log2)
+    L = lib()
+    nb = L.hawkes_workspace_bytes(ctypes.byref(p), 0)
+    ws = _workspace(dev, nb)
+    lam = torch.empty(t.numel(), dtype=torch.float32, device=dev)
+    _check("hawkes_intensity", L.hawkes_intensity(ctypes.byref(p), _ptr(t), _ptr(m), _ptr(mu), _ptr(alpha),
+                                                  _ptr(beta), _ptr(lam), _ptr(ws), nb, _stream(dev)))
+    return lam
+
+
+def sequential_loglik_grad(t, m, mu, alpha, beta, T):
+    """Same outputs as loglik_grad from the one-workgroup sequential baseline kernel."""
+    dev, t, m, mu, alpha, beta = _prep(t, m, mu, alpha, beta)
+    p = _problem(t, mu, beta, T, 0)
+    L = lib()
+    M = mu.numel()
+    nb = M * M * 8 + 512
+    ws = _workspace(dev, nb)
+    out = torch.empty(1, dtype=torch.float64, device=dev)
+    gmu = torch.empty(M, dtype=torch.float64, device=dev)
+    ga = torch.empty(M, M, dtype=torch.float64, device=dev)
+    gb = torch.empty(1, dtype=torch.float64, device=dev)
+    _check("hawkes_sequential_loglik_grad",
+           L.hawkes_sequential_loglik_grad(ctypes.byref(p), _ptr(t), _ptr(m), _ptr(mu), _ptr(alpha), _ptr(beta),
+                                           _ptr(out), _ptr(gmu), _ptr(ga), _ptr(gb), _ptr(ws), nb, _stream(dev)))
+    return out[0], gmu, ga, gb
+
+
+def check_inputs(t, m, mu, alpha, beta, T) -> int:
+    """Device-side precondition check; returns the status bit mask (0 = valid).  Synchronises."""
+    dev, t, m, mu, alpha, beta = _prep(t, m, mu, alpha, beta)
+    p = _problem(t, mu, beta, T, 0)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    _check("hawkes_check_inputs", lib().hawkes_check_inputs(ctypes.byref(p), _ptr(t), _ptr(m), _ptr(mu),
+                                                            _ptr(alpha), _ptr(beta), _ptr(st), _stream(dev)))
+    return int(st.item())
+
+
+@dataclass
+class Batch:
+    """Device-resident packed batch of S sequences (see hawkes.h)."""
+    ev_off: torch.Tensor
+    m_s: torch.Tensor
+    T_s: torch.Tensor
+    t: torch.Tensor
+    m: torch.Tensor
+    mu: torch.Tensor
+    alpha: torch.Tensor
+    beta: torch.Tensor
+    max_m: int
+
+    @property
+    def S(self) -> int:
+        return int(self.m_s.numel())
+
+    @classmethod
+    def from_numpy(cls, bw, device="cuda"):
+        d = torch.device(device)
+        return cls(torch.as_tensor(bw.ev_off, dtype=torch.int64, device=d),
+                   torch.as_tensor(bw.m_s, dtype=torch.int32, device=d),
+                   torch.as_tensor(bw.T_s, dtype=torch.float64, device=d),
+                   torch.as_tensor(bw.t, dtype=torch.float64, device=d),
+                   torch.as_tensor(bw.m, dtype=torch.int32, device=d),
+                   torch.as_tensor(bw.mu, dtype=torch.float32, device=d),
+                   torch.as_tensor(bw.alpha, dtype=torch.float32, device=d),
+                   torch.as_tensor(bw.beta, dtype=torch.float32, device=d),
+                   int(bw.m_s.max()))
+
+
+def _batched(b: Batch, grad: bool, out=None):
+    dev = b.t.device
+    L = lib()
+    n_total = b.t.numel()
+    nb = L.hawkes_batched_workspace_bytes(b.S, n_total, b.max_m, int(grad))
+    if nb == 0:
+        raise HawkesError("hawkes_batched_workspace_bytes", 1)
+    ws = _workspace(dev, nb)
+    if out is None:
+        out = (torch.empty(b.S, dtype=torch.float64, device=dev),
+               torch.empty(b.mu.numel(), dtype=torch.float64, device=dev) if grad else None,
+               torch.empty(b.alpha.numel(), dtype=torch.float64, device=dev) if grad else None,
+               torch.empty(b.S, dtype=torch.float64, device=dev) if grad else None)
+    ll, gmu, ga, gb = out
+    if grad:
+        st = L.hawkes_loglik_grad_batched(b.S, n_total, b.max_m, _ptr(b.ev_off), _ptr(b.m_s), _ptr(b.T_s),
+                                          _ptr(b.t), _ptr(b.m), _ptr(b.mu), _ptr(b.alpha), _ptr(b.beta),
+                                          _ptr(ll), _ptr(gmu), _ptr(ga), _ptr(gb), _ptr(ws), nb, _stream(dev))
+        _check("hawkes_loglik_grad_batched", st)
+        return ll, gmu, ga, gb
+    st = L.hawkes_loglik_batched(b.S, n_total, b.max_m, _ptr(b.ev_off), _ptr(b.m_s), _ptr(b.T_s), _ptr(b.t),
+                                 _ptr(b.m), _ptr(b.mu), _ptr(b.alpha), _ptr(b.beta), _ptr(ll), _ptr(ws), nb,
+                                 _stream(dev))
+    _check("hawkes_loglik_batched", st)
+    return ll
+
+
+def loglik_batched(b: Batch) -> torch.Tensor:
+    """Per-sequence log-likelihoods [S] (float64)."""
+    return _batched(b, False)
+
+
+def loglik_grad_batched(b: Batch, out=None):
+    """(loglik[S], g_mu packed like mu, g_alpha packed like alpha, g_beta[S])."""
+    return _batched(b, True, out)
+
+
+class HawkesLogLik(torch.autograd.Function):
+    """L(mu, alpha, beta) for a fixed event sequence.  When any parameter
+    needs a gradient, forward runs the fused log-likelihood + gradient call
+    (forward-mode states with chunk-boundary carries, no per-event storage);
+    backward scales the stored gradient by the incoming scalar."""
+
+    @staticmethod
+    def forward(ctx, mu, alpha, beta, t, m, T, chunk_log2=0):
+        need = any(ctx.needs_input_grad[:3])
+        if need:
+            L, gmu, ga, gb = loglik_grad(t, m, mu, alpha, beta, T, chunk_log2)
+            ctx.save_for_backward(gmu, ga, gb)
+        else:
+            L = loglik(t, m, mu, alpha, beta, T, chunk_log2)
+        ctx.shapes = (mu.shape, alpha.shape, beta.shape)
+        ctx.dtypes = (mu.dtype, alpha.dtype, beta.dtype)
+        return L
+
+    @staticmethod
+    def backward(ctx, gL):
+        gmu, ga, gb = ctx.saved_tensors
+        (smu, sa, sb), (dmu, da, db) = ctx.shapes, ctx.dtypes
+        return ((gL * gmu).reshape(smu).to(dmu), (gL * ga).reshape(sa).to(da), (gL * gb).reshape(sb).to(db),
+                None, None, None, None)
+
+
+def hawkes_loglik(t, m, mu, alpha, beta, T, chunk_log2: int = 0) -> torch.Tensor:
+    """Differentiable log-likelihood w.r.t. (mu, alpha, beta)."""
+    return HawkesLogLik.apply(mu, alpha, beta, t, m, T, chunk_log2)

@@ -1,0 +1,237 @@
+// C ABI of the library: argument checks, workspace carving, engine dispatch.
+// Every entry point returns a hawkes_status and never throws.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+#include "hk_device.h"
+#include "hk_internal.h"
+#include "hk_large.h"
+
+using namespace hk;
+
+namespace hk {
+
+static int32_t pow2_at_least(int32_t m) {
+    int32_t p = 1;
+    while (p < m) p <<= 1;
+    return p;
+}
+
+// single-sequence descriptor written on the device so calls stay graph-capturable
+__global__ void write_single_desc(int64_t n, int32_t m, double T, int64_t* ev_off, int32_t* m_s,
+                                  double* T_s) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ev_off[0] = 0;
+        ev_off[1] = n;
+        m_s[0] = m;
+        T_s[0] = T;
+    }
+}
+
+size_t small_layout(SmallArgs& A, int32_t S, int64_t n_total, int32_t max_m, bool grad, void* ws,
+                    size_t ws_bytes, bool single) {
+    A.S = S;
+    A.MP = pow2_at_least(max_m < 1 ? 1 : max_m);
+    // events per item: at least 16; for long inputs grow it so the item count
+    // (and so the workspace) stays bounded: the workspace does not grow with n
+    // beyond 64Ki items per sequence block.
+    int64_t L = 16;
+    const int64_t target_items = single ? 65536 : 262144;
+    while (L < 4096 && n_total / L > target_items) L <<= 1;
+    if (n_total / L > target_items) L = (n_total + target_items - 1) / target_items;
+    A.L = (int32_t)L;
+    A.n_total = n_total;
+    A.n_items_cap = n_total / L + S + 1;
+    A.n_chunks_cap = A.n_items_cap / HK_RCH + S + 1;
+    A.grad = grad;
+    const int64_t tiles = (A.n_items_cap + 63) / 64;
+    const int32_t PW = grad ? 4 + 2 * A.MP + A.MP * A.MP : 2;
+    Carve c(ws, ws_bytes);
+    if (single) {
+        A.ev_off = c.take<int64_t>(2);
+        A.m_s = c.take<int32_t>(1);
+        A.T_s = c.take<double>(1);
+    }
+    A.item_off = c.take<int64_t>(S + 1);
+    A.chunk_off = c.take<int64_t>(S + 1);
+    A.mu_off = c.take<int64_t>(S + 1);
+    A.a_off = c.take<int64_t>(S + 1);
+    A.item_pref = c.take<double>((size_t)A.n_items_cap * (2 + 2 * A.MP));
+    A.tile_agg = c.take<double>((size_t)tiles * (2 + 2 * A.MP));
+    A.tile_carry = c.take<double>((size_t)tiles * 2 * A.MP);
+    A.part = c.take<double>((size_t)A.n_items_cap * PW);
+    A.cpart = c.take<double>((size_t)A.n_chunks_cap * PW);
+    A.ll_scratch = c.take<double>(1);
+    return c.off + 256;
+}
+
+}  // namespace hk
+
+static bool problem_ok(const hawkes_problem* p) {
+    if (!p) return false;
+    if (p->n < 0 || p->m < 1 || p->k < 1) return false;
+    if (p->beta_mode != HAWKES_BETA_SHARED && p->beta_mode != HAWKES_BETA_PER_TARGET) return false;
+    if (!(p->T >= 0.0) || !isfinite(p->T)) return false;
+    if (p->chunk_log2 != 0 && (p->chunk_log2 < 12 || p->chunk_log2 > 26)) return false;
+    if ((int64_t)p->m * p->m > ((int64_t)1 << 31)) return false;
+    return true;
+}
+
+static bool use_small(const hawkes_problem* p) {
+    return p->beta_mode == HAWKES_BETA_SHARED && p->m <= 8;
+}
+
+extern "C" {
+
+const char* hawkes_status_string(hawkes_status s) {
+    switch (s) {
+        case HAWKES_OK: return "ok";
+        case HAWKES_EINVAL: return "invalid argument";
+        case HAWKES_EWORKSPACE: return "workspace missing or too small";
+        case HAWKES_EDEVICE: return "device error (HIP call or kernel launch failed)";
+        case HAWKES_EUNSUPPORTED: return "unsupported request";
+        default: return "unknown status";
+    }
+}
+
+int hawkes_version(void) { return HAWKES_ABI_VERSION; }
+
+size_t hawkes_workspace_bytes(const hawkes_problem* p, int with_grad) {
+    if (!problem_ok(p) || p->k != 1) return 0;
+    if (use_small(p)) {
+        SmallArgs A;
+        memset(&A, 0, sizeof(A));
+        return small_layout(A, 1, p->n, p->m, with_grad != 0, nullptr, 0, true);
+    }
+    LargeArgs A;
+    memset(&A, 0, sizeof(A));
+    return large_layout(A, p, with_grad != 0, nullptr, 0);
+}
+
+static hawkes_status run_single(const hawkes_problem* p, const double* t, const int32_t* marks, const float* mu,
+                                const float* alpha, const float* beta, double* loglik, double* g_mu,
+                                double* g_alpha, double* g_beta, float* lambda_out, bool grad, void* ws,
+                                size_t ws_bytes, hipStream_t stream) {
+    if (!problem_ok(p) || !mu || !alpha || !beta) return HAWKES_EINVAL;
+    if (!loglik && !lambda_out) return HAWKES_EINVAL;
+    if (p->k != 1) return HAWKES_EUNSUPPORTED;
+    if (p->n > 0 && (!t || !marks)) return HAWKES_EINVAL;
+    if (!ws) return HAWKES_EWORKSPACE;
+    if (use_small(p)) {
+        SmallArgs A;
+        memset(&A, 0, sizeof(A));
+        const size_t need = small_layout(A, 1, p->n, p->m, grad, ws, ws_bytes, true);
+        if (ws_bytes < need) return HAWKES_EWORKSPACE;
+        if (((uintptr_t)ws & 255) != 0) return HAWKES_EWORKSPACE;
+        hipLaunchKernelGGL(write_single_desc, dim3(1), dim3(64), 0, stream, p->n, p->m, p->T,
+                           (int64_t*)A.ev_off, (int32_t*)A.m_s, (double*)A.T_s);
+        A.t = t; A.marks = marks; A.mu = mu; A.alpha = alpha; A.beta = beta;
+        A.loglik = loglik ? loglik : A.ll_scratch;
+        A.g_mu = g_mu; A.g_alpha = g_alpha; A.g_beta = g_beta;
+        A.lambda_out = lambda_out;
+        return run_small(A, stream);
+    }
+    LargeArgs A;
+    memset(&A, 0, sizeof(A));
+    const size_t need = large_layout(A, p, grad, ws, ws_bytes);
+    if (ws_bytes < need) return HAWKES_EWORKSPACE;
+    if (((uintptr_t)ws & 255) != 0) return HAWKES_EWORKSPACE;
+    A.t = t; A.marks = marks; A.mu = mu; A.alpha = alpha; A.beta = beta;
+    A.loglik = loglik ? loglik : A.ll_scratch;
+    A.g_mu = g_mu; A.g_alpha = g_alpha; A.g_beta = g_beta;
+    A.lambda_out = lambda_out;
+    return run_large(A, stream);
+}
+
+hawkes_status hawkes_loglik(const hawkes_problem* p, const double* t, const int32_t* marks, const float* mu,
+                            const float* alpha, const float* beta, double* loglik, void* workspace,
+                            size_t workspace_bytes, hipStream_t stream) {
+    return run_single(p, t, marks, mu, alpha, beta, loglik, nullptr, nullptr, nullptr, nullptr, false,
+                      workspace, workspace_bytes, stream);
+}
+
+hawkes_status hawkes_loglik_grad(const hawkes_problem* p, const double* t, const int32_t* marks, const float* mu,
+                                 const float* alpha, const float* beta, double* loglik, double* g_mu,
+                                 double* g_alpha, double* g_beta, void* workspace, size_t workspace_bytes,
+                                 hipStream_t stream) {
+    return run_single(p, t, marks, mu, alpha, beta, loglik, g_mu, g_alpha, g_beta, nullptr, true, workspace,
+                      workspace_bytes, stream);
+}
+
+hawkes_status hawkes_intensity(const hawkes_problem* p, const double* t, const int32_t* marks, const float* mu,
+                               const float* alpha, const float* beta, float* lambda_out, void* workspace,
+                               size_t workspace_bytes, hipStream_t stream) {
+    if (!lambda_out) return HAWKES_EINVAL;
+    // the log-likelihood computed alongside goes to a workspace slot
+    return run_single(p, t, marks, mu, alpha, beta, nullptr, nullptr, nullptr, nullptr, lambda_out, false,
+                      workspace, workspace_bytes, stream);
+}
+
+size_t hawkes_batched_workspace_bytes(int32_t S, int64_t n_total, int32_t max_m, int with_grad) {
+    if (S < 1 || n_total < 0 || max_m < 1 || max_m > 8) return 0;
+    SmallArgs A;
+    memset(&A, 0, sizeof(A));
+    return small_layout(A, S, n_total, max_m, with_grad != 0, nullptr, 0, false);
+}
+
+static hawkes_status run_batched(int32_t S, int64_t n_total, int32_t max_m, const int64_t* ev_off,
+                                 const int32_t* m_s, const double* T_s, const double* t, const int32_t* marks,
+                                 const float* mu, const float* alpha, const float* beta, double* loglik,
+                                 double* g_mu, double* g_alpha, double* g_beta, bool grad, void* ws,
+                                 size_t ws_bytes, hipStream_t stream) {
+    if (S < 1 || n_total < 0 || max_m < 1) return HAWKES_EINVAL;
+    if (max_m > 8) return HAWKES_EUNSUPPORTED;
+    if (!ev_off || !m_s || !T_s || !mu || !alpha || !beta || !loglik) return HAWKES_EINVAL;
+    if (n_total > 0 && (!t || !marks)) return HAWKES_EINVAL;
+    if (!ws) return HAWKES_EWORKSPACE;
+    SmallArgs A;
+    memset(&A, 0, sizeof(A));
+    const size_t need = small_layout(A, S, n_total, max_m, grad, ws, ws_bytes, false);
+    if (ws_bytes < need || ((uintptr_t)ws & 255) != 0) return HAWKES_EWORKSPACE;
+    A.ev_off = ev_off; A.m_s = m_s; A.T_s = T_s;
+    A.t = t; A.marks = marks; A.mu = mu; A.alpha = alpha; A.beta = beta;
+    A.loglik = loglik; A.g_mu = g_mu; A.g_alpha = g_alpha; A.g_beta = g_beta;
+    A.lambda_out = nullptr;
+    return run_small(A, stream);
+}
+
+hawkes_status hawkes_loglik_batched(int32_t S, int64_t n_total, int32_t max_m, const int64_t* ev_off,
+                                    const int32_t* m_s, const double* T_s, const double* t, const int32_t* marks,
+                                    const float* mu, const float* alpha, const float* beta, double* loglik,
+                                    void* workspace, size_t workspace_bytes, hipStream_t stream) {
+    return run_batched(S, n_total, max_m, ev_off, m_s, T_s, t, marks, mu, alpha, beta, loglik, nullptr, nullptr,
+                       nullptr, false, workspace, workspace_bytes, stream);
+}
+
+hawkes_status hawkes_loglik_grad_batched(int32_t S, int64_t n_total, int32_t max_m, const int64_t* ev_off,
+                                         const int32_t* m_s, const double* T_s, const double* t,
+                                         const int32_t* marks, const float* mu, const float* alpha,
+                                         const float* beta, double* loglik, double* g_mu, double* g_alpha,
+                                         double* g_beta, void* workspace, size_t workspace_bytes,
+                                         hipStream_t stream) {
+    return run_batched(S, n_total, max_m, ev_off, m_s, T_s, t, marks, mu, alpha, beta, loglik, g_mu, g_alpha,
+                       g_beta, true, workspace, workspace_bytes, stream);
+}
+
+hawkes_status hawkes_sequential_loglik_grad(const hawkes_problem* p, const double* t, const int32_t* marks,
+                                            const float* mu, const float* alpha, const float* beta,
+                                            double* loglik, double* g_mu, double* g_alpha, double* g_beta,
+                                            void* workspace, size_t workspace_bytes, hipStream_t stream) {
+    if (!problem_ok(p) || !mu || !alpha || !beta || !loglik) return HAWKES_EINVAL;
+    if (p->k != 1 || p->beta_mode != HAWKES_BETA_SHARED) return HAWKES_EUNSUPPORTED;
+    if (p->n > 0 && (!t || !marks)) return HAWKES_EINVAL;
+    if (!workspace) return HAWKES_EWORKSPACE;
+    const size_t need = seq_workspace_bytes(p);
+    if (workspace_bytes < need || ((uintptr_t)workspace & 255) != 0) return HAWKES_EWORKSPACE;
+    return run_sequential(p, t, marks, mu, alpha, beta, loglik, g_mu, g_alpha, g_beta, workspace, stream);
+}
+
+hawkes_status hawkes_check_inputs(const hawkes_problem* p, const double* t, const int32_t* marks, const float* mu,
+                                  const float* alpha, const float* beta, int32_t* status_out,
+                                  hipStream_t stream) {
+    if (!problem_ok(p) || !mu || !alpha || !beta || !status_out) return HAWKES_EINVAL;
+    if (p->n > 0 && (!t || !marks)) return HAWKES_EINVAL;
+    return run_check_inputs(p, t, marks, mu, alpha, beta, status_out, stream);
+}
+
+}  // extern "C"

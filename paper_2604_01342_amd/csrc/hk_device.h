@@ -1,0 +1,58 @@
+// Device-side helpers shared by the library's kernels (gfx950, wave64).
+// Internal to the GPU library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define HK_WAVE 64
+
+namespace hk {
+
+// e^x for a float64 argument x <= ~80, returned in float32.  The argument is
+// reduced in float64 (x = k ln2 + r, |r| <= ln2/2, Cody-Waite split of ln2)
+// so that a large |x| does not lose the absolute accuracy of r; 2^(r log2 e)
+// then comes from the hardware exp2, and k is applied with ldexp.  Relative
+// error is a few float32 ulp for every x the kernels pass.
+__device__ __forceinline__ float exp_f64arg(double x) {
+    const double kLog2e = 1.4426950408889634;
+    const double kLn2Hi = 6.93147180369123816490e-01;
+    const double kLn2Lo = 1.90821492927058770002e-10;
+    double k = __builtin_rint(x * kLog2e);
+    double r = __builtin_fma(-k, kLn2Hi, x);
+    r = __builtin_fma(-k, kLn2Lo, r);
+    float e = __builtin_amdgcn_exp2f((float)(r * kLog2e));
+    int ki = (int)k;
+    ki = ki < -300 ? -300 : ki;   // far below float32 range -> 0 after ldexp
+    return __builtin_ldexpf(e, ki);
+}
+
+// wave-uniform value from lane 0
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ double shfl_d(double v, int src) {
+    return __shfl(v, src, HK_WAVE);
+}
+__device__ __forceinline__ double shfl_up_d(double v, int d) {
+    return __shfl_up(v, d, HK_WAVE);
+}
+
+__device__ __forceinline__ int clamp_mark(int m, int M) {
+    return m < 0 ? 0 : (m >= M ? M - 1 : m);
+}
+
+// deterministic block-wide float64 sum (fixed tree), blockDim.x == NT
+template <int NT>
+__device__ double block_sum_d(double v, double* sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+}  // namespace hk

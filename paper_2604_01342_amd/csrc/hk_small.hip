@@ -1,0 +1,526 @@
+// Small-M engine (M <= 8): exact Hawkes log-likelihood and gradient for one
+// or many independent sequences, shared decay per sequence.
+//
+// Each lane owns one "item": a run of at most L consecutive events of one
+// sequence.  The full node state lives in the lane's registers in float64:
+//   K_q(t) = sum_{j<i, m_j=q} e^{-beta (t - t_j)}          (eq. 11 state)
+//   J_q(t) = sum_{j<i, m_j=q} (t - t_j) e^{-beta (t - t_j)} (time-weighted;
+//            equal to t K - L with the paper's L of eq. 12)
+// and R = alpha_{p,:} . K is the state of eq. 3 for target p.
+//
+// Three phases make the per-lane recurrence a parallel scan (the prefix scan
+// of affine maps of "Methods"; a run of events acts on (K, J) as
+//   K -> e^{-beta D} K + K_run,  J -> e^{-beta D} (J + D K) + J_run,
+// a map of the paper's (s I, v) form extended by the shear D K):
+//   A  each lane folds its item into such a map (span D, K_run, J_run); the
+//      wave then runs a segmented inclusive scan of the 64 maps (a new
+//      sequence resets the state);
+//   B  one thread per (sequence, node) chains the per-wave aggregates of its
+//      sequence in order;
+//   C  each lane rebuilds its carry-in from (B) and its in-wave prefix and
+//      replays its events, forming lambda_i, log lambda_i, 1/lambda_i and the
+//      gradient sums of eqs. 8-10, written as per-item float64 partials;
+//   R  per-sequence reduction of the partials in a fixed order.
+#include "hk_device.h"
+#include "hk_internal.h"
+
+namespace hk {
+
+// ---------------------------------------------------------------- setup
+// One workgroup of 1024 threads: exclusive scans over the sequences of
+//   item counts ceil(len/L), reduction-chunk counts ceil(items/RCH),
+//   node counts m_s and m_s^2 (parameter packing offsets).
+// event range of sequence s clamped to [0, n_total) so that malformed offsets
+// can never address outside t / marks
+__device__ __forceinline__ void seq_range(const int64_t* __restrict__ ev_off, int32_t s, int64_t n_total,
+                                          int64_t* e0, int64_t* e1) {
+    int64_t a = ev_off[s], b = ev_off[s + 1];
+    a = a < 0 ? 0 : (a > n_total ? n_total : a);
+    b = b < a ? a : (b > n_total ? n_total : b);
+    *e0 = a;
+    *e1 = b;
+}
+
+__global__ __launch_bounds__(1024) void small_setup(int32_t S, int64_t n_total, const int64_t* __restrict__ ev_off,
+                                                    const int32_t* __restrict__ m_s, int32_t L,
+                                                    int64_t* __restrict__ item_off,
+                                                    int64_t* __restrict__ chunk_off,
+                                                    int64_t* __restrict__ mu_off,
+                                                    int64_t* __restrict__ a_off) {
+    __shared__ int64_t sh[4][1024];
+    __shared__ int64_t carry[4];
+    if (threadIdx.x < 4) carry[threadIdx.x] = 0;
+    __syncthreads();
+    for (int32_t base = 0; base < S; base += 1024) {
+        const int32_t s = base + (int32_t)threadIdx.x;
+        int64_t v[4] = {0, 0, 0, 0};
+        if (s < S) {
+            int64_t e0, e1;
+            seq_range(ev_off, s, n_total, &e0, &e1);
+            const int64_t len = e1 - e0;
+            const int64_t items = len > 0 ? (len + L - 1) / L : 0;
+            const int64_t mm = m_s[s] < 1 ? 1 : m_s[s];
+            v[0] = items;
+            v[1] = (items + HK_RCH - 1) / HK_RCH;
+            v[2] = mm;
+            v[3] = mm * mm;
+        }
+        for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = v[k];
+        __syncthreads();
+        // inclusive Hillis-Steele scan in shared memory
+        for (int d = 1; d < 1024; d <<= 1) {
+            int64_t add[4] = {0, 0, 0, 0};
+            if ((int)threadIdx.x >= d)
+                for (int k = 0; k < 4; ++k) add[k] = sh[k][threadIdx.x - d];
+            __syncthreads();
+            for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += add[k];
+            __syncthreads();
+        }
+        if (s < S) {
+            item_off[s] = carry[0] + sh[0][threadIdx.x] - v[0];
+            chunk_off[s] = carry[1] + sh[1][threadIdx.x] - v[1];
+            mu_off[s] = carry[2] + sh[2][threadIdx.x] - v[2];
+            a_off[s] = carry[3] + sh[3][threadIdx.x] - v[3];
+        }
+        __syncthreads();
+        if (threadIdx.x == 1023)
+            for (int k = 0; k < 4; ++k) carry[k] += sh[k][1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        item_off[S] = carry[0];
+        chunk_off[S] = carry[1];
+        mu_off[S] = carry[2];
+        a_off[S] = carry[3];
+    }
+}
+
+// largest s in [0, S) with off[s] <= x (off nondecreasing, off[0] = 0 <= x)
+__device__ __forceinline__ int32_t find_seq(const int64_t* __restrict__ off, int32_t S, int64_t x) {
+    int32_t lo = 0, hi = S - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+struct ItemInfo {
+    int32_t s;      // sequence
+    int64_t k;      // item index within the sequence
+    int64_t a, b;   // event range [a, b)
+    bool valid;
+};
+
+__device__ __forceinline__ ItemInfo item_info(int64_t it, int32_t S, const int64_t* __restrict__ item_off,
+                                              const int64_t* __restrict__ ev_off, int32_t L, int64_t n_total,
+                                              int64_t n_items_cap) {
+    ItemInfo r;
+    const int64_t total = item_off[S];
+    r.valid = it < total && it < n_items_cap;
+    if (!r.valid) { r.s = 0; r.k = 0; r.a = 0; r.b = 0; return r; }
+    r.s = find_seq(item_off, S, it);
+    // sequences with zero items share item_off values; find_seq returns the last
+    // of them, which is the one that owns item `it`.
+    r.k = it - item_off[r.s];
+    int64_t e0, e1;
+    seq_range(ev_off, r.s, n_total, &e0, &e1);
+    r.a = e0 + r.k * L;
+    r.b = r.a + L < e1 ? r.a + L : e1;
+    if (r.a >= r.b) r.valid = false;
+    return r;
+}
+
+// (K, J) at t0^+ propagated by D = t1 - t0 >= 0 and added to (Kb, Jb)
+template <int MP>
+__device__ __forceinline__ void compose(double* K, double* J, double D, double beta,
+                                        const double* Kb, const double* Jb) {
+    const double s = exp(-beta * D);
+#pragma unroll
+    for (int q = 0; q < MP; ++q) {
+        const double k0 = K[q];
+        K[q] = __builtin_fma(s, k0, Kb[q]);
+        J[q] = __builtin_fma(s, __builtin_fma(D, k0, J[q]), Jb[q]);
+    }
+}
+
+// ---------------------------------------------------------------- phase A
+template <int MP>
+__global__ __launch_bounds__(256) void small_agg(int32_t S, int64_t n_total, const int64_t* __restrict__ ev_off,
+                                                 const int64_t* __restrict__ item_off, int32_t L,
+                                                 const double* __restrict__ t, const int32_t* __restrict__ marks,
+                                                 const int32_t* __restrict__ m_s, const float* __restrict__ beta,
+                                                 double* __restrict__ item_pref,   // [items][2 + 2MP]
+                                                 double* __restrict__ tile_agg,    // [tiles][2 + 2MP]
+                                                 int64_t n_items_cap) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t it = wave * 64 + lane;
+    if (wave * 64 >= n_items_cap) return;   // whole wave beyond the buffers (wave-uniform)
+    ItemInfo inf = item_info(it, S, item_off, ev_off, L, n_total, n_items_cap);
+    double K[MP], J[MP];
+#pragma unroll
+    for (int q = 0; q < MP; ++q) { K[q] = 0.0; J[q] = 0.0; }
+    double D = 0.0;
+    int reset = 1;
+    double bet = 0.0;
+    if (inf.valid && inf.b > inf.a) {
+        const int32_t M = m_s[inf.s] < 1 ? 1 : (m_s[inf.s] > MP ? MP : m_s[inf.s]);
+        bet = (double)beta[inf.s];
+        reset = inf.k == 0;
+        const double tref = reset ? t[inf.a] : t[inf.a - 1];
+        double tp = tref;
+        int mp = -1;
+        for (int64_t e = inf.a; e < inf.b; ++e) {
+            const double te = t[e];
+            const double d = te - tp;
+            const double s = exp(-bet * d);
+#pragma unroll
+            for (int q = 0; q < MP; ++q) {
+                const double k1 = s * (K[q] + (q == mp ? 1.0 : 0.0));
+                J[q] = __builtin_fma(s, J[q], d * k1);
+                K[q] = k1;
+            }
+            tp = te;
+            mp = clamp_mark(marks[e], M);
+        }
+#pragma unroll
+        for (int q = 0; q < MP; ++q) K[q] += (q == mp ? 1.0 : 0.0);
+        D = tp - tref;
+    }
+    // segmented inclusive scan over the wave's 64 items
+    for (int d = 1; d < 64; d <<= 1) {
+        const double oD = shfl_up_d(D, d);
+        const int oreset = __shfl_up(reset, d, 64);
+        double oK[MP], oJ[MP];
+#pragma unroll
+        for (int q = 0; q < MP; ++q) { oK[q] = shfl_up_d(K[q], d); oJ[q] = shfl_up_d(J[q], d); }
+        if (lane >= d && !reset) {
+            // other (earlier) then me: me has no reset, so both lie in my sequence
+            double nK[MP], nJ[MP];
+#pragma unroll
+            for (int q = 0; q < MP; ++q) { nK[q] = oK[q]; nJ[q] = oJ[q]; }
+            compose<MP>(nK, nJ, D, bet, K, J);
+#pragma unroll
+            for (int q = 0; q < MP; ++q) { K[q] = nK[q]; J[q] = nJ[q]; }
+            D = oD + D;
+            reset = oreset;
+        }
+    }
+    // exclusive prefix = inclusive value of the previous lane (identity for lane 0)
+    const double pD = shfl_up_d(D, 1);
+    const int preset = __shfl_up(reset, 1, 64);
+    double pK[MP], pJ[MP];
+#pragma unroll
+    for (int q = 0; q < MP; ++q) { pK[q] = shfl_up_d(K[q], 1); pJ[q] = shfl_up_d(J[q], 1); }
+    if (it < n_items_cap) {
+        double* o = item_pref + it * (2 + 2 * MP);
+        o[0] = lane == 0 ? 0.0 : pD;
+        o[1] = lane == 0 ? 0.0 : (double)preset;
+#pragma unroll
+        for (int q = 0; q < MP; ++q) {
+            o[2 + q] = lane == 0 ? 0.0 : pK[q];
+            o[2 + MP + q] = lane == 0 ? 0.0 : pJ[q];
+        }
+    }
+    if (lane == 63) {
+        double* o = tile_agg + wave * (2 + 2 * MP);
+        o[0] = D;
+        o[1] = (double)reset;
+#pragma unroll
+        for (int q = 0; q < MP; ++q) { o[2 + q] = K[q]; o[2 + MP + q] = J[q]; }
+    }
+}
+
+// ---------------------------------------------------------------- phase B
+// thread per (sequence, node): chain the aggregates of the waves its sequence spans
+template <int MP>
+__global__ __launch_bounds__(256) void small_tile_scan(int32_t S, int64_t n_items_cap,
+                                                       const int64_t* __restrict__ item_off,
+                                                       const float* __restrict__ beta,
+                                                       const double* __restrict__ tile_agg,
+                                                       double* __restrict__ tile_carry) {   // [tiles][2MP]
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)S * MP) return;
+    const int32_t s = (int32_t)(gid / MP);
+    const int q = (int)(gid % MP);
+    const int64_t f = item_off[s];
+    int64_t l = item_off[s + 1];
+    l = l > n_items_cap ? n_items_cap : l;
+    if (l <= f) return;
+    const int64_t t0 = f / 64, t1 = (l - 1) / 64;
+    if (t1 == t0) return;
+    const double bet = (double)beta[s];
+    const int W = 2 + 2 * MP;
+    double K = tile_agg[t0 * W + 2 + q], J = tile_agg[t0 * W + 2 + MP + q];
+    for (int64_t tt = t0 + 1; tt <= t1; ++tt) {
+        tile_carry[tt * 2 * MP + q] = K;
+        tile_carry[tt * 2 * MP + MP + q] = J;
+        if (tt == t1) break;
+        const double D = tile_agg[tt * W + 0];
+        const double ex = exp(-bet * D);
+        const double Kb = tile_agg[tt * W + 2 + q], Jb = tile_agg[tt * W + 2 + MP + q];
+        const double k0 = K;
+        K = __builtin_fma(ex, k0, Kb);
+        J = __builtin_fma(ex, __builtin_fma(D, k0, J), Jb);
+    }
+}
+
+// ---------------------------------------------------------------- phase C
+// Partial layout per item (float64, item-major, stride PW):
+//   0 log-sum, 1 compensator sum_j colsum[m_j] (1 - e^{-beta (T - t_j)}),
+//   GRAD: 2 E = sum_j colsum[m_j] (T - t_j) e^{-beta (T - t_j)},
+//         3 sum_i w_i (R_i - beta D_i), 4.. S_q, 4+MP.. C_q, 4+2MP.. G[p][q]
+template <int MP, bool GRAD, bool INTENS>
+__global__ __launch_bounds__(256) void small_compute(int32_t S, int64_t n_total, const int64_t* __restrict__ ev_off,
+                                                     const int64_t* __restrict__ item_off, int32_t L,
+                                                     const double* __restrict__ t, const int32_t* __restrict__ marks,
+                                                     const int32_t* __restrict__ m_s, const double* __restrict__ T_s,
+                                                     const float* __restrict__ mu, const float* __restrict__ alpha,
+                                                     const float* __restrict__ beta,
+                                                     const int64_t* __restrict__ mu_off, const int64_t* __restrict__ a_off,
+                                                     const double* __restrict__ item_pref,
+                                                     const double* __restrict__ tile_carry,
+                                                     double* __restrict__ part, int32_t PW,
+                                                     float* __restrict__ lambda_out, int64_t n_items_cap) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t it = wave * 64 + lane;
+    if (it >= n_items_cap) return;
+    ItemInfo inf = item_info(it, S, item_off, ev_off, L, n_total, n_items_cap);
+    if (!inf.valid) return;
+    const int32_t M = m_s[inf.s] < 1 ? 1 : (m_s[inf.s] > MP ? MP : m_s[inf.s]);
+    const double bet = (double)beta[inf.s];
+    const double T = T_s[inf.s];
+    const float* al = alpha + a_off[inf.s];
+    const float* mus = mu + mu_off[inf.s];
+    double colsum[MP];
+#pragma unroll
+    for (int q = 0; q < MP; ++q) {
+        double c = 0.0;
+        if (q < M)
+            for (int p = 0; p < M; ++p) c += (double)al[p * M + q];
+        colsum[q] = c;
+    }
+    double K[MP], J[MP];
+#pragma unroll
+    for (int q = 0; q < MP; ++q) { K[q] = 0.0; J[q] = 0.0; }
+    double tp;
+    if (inf.k == 0) {
+        tp = t[inf.a];
+    } else {
+        tp = t[inf.a - 1];
+        const double* pr = item_pref + it * (2 + 2 * MP);
+        const double pD = pr[0];
+        const bool preset = pr[1] != 0.0;
+#pragma unroll
+        for (int q = 0; q < MP; ++q) { K[q] = pr[2 + q]; J[q] = pr[2 + MP + q]; }
+        if (!preset) {
+            const int64_t tile = it / 64;
+            double cK[MP], cJ[MP];
+#pragma unroll
+            for (int q = 0; q < MP; ++q) {
+                cK[q] = tile_carry[tile * 2 * MP + q];
+                cJ[q] = tile_carry[tile * 2 * MP + MP + q];
+            }
+            // the tile carry exists whenever this item's sequence started in an
+            // earlier tile, which is exactly the case preset == 0 and k > 0
+            compose<MP>(cK, cJ, pD, bet, K, J);
+#pragma unroll
+            for (int q = 0; q < MP; ++q) { K[q] = cK[q]; J[q] = cJ[q]; }
+        }
+    }
+    double logsum = 0.0, comp = 0.0, Esum = 0.0, gb = 0.0;
+    double Sq[MP], Cq[MP], G[GRAD ? MP : 1][GRAD ? MP : 1];
+#pragma unroll
+    for (int q = 0; q < MP; ++q) { Sq[q] = 0.0; Cq[q] = 0.0; }
+    if (GRAD) {
+#pragma unroll
+        for (int p = 0; p < (GRAD ? MP : 1); ++p)
+#pragma unroll
+            for (int q = 0; q < (GRAD ? MP : 1); ++q) G[p][q] = 0.0;
+    }
+    int mp = -1;
+    for (int64_t e = inf.a; e < inf.b; ++e) {
+        const double te = t[e];
+        const double d = te - tp;
+        const double s = exp(-bet * d);
+#pragma unroll
+        for (int q = 0; q < MP; ++q) {
+            const double k1 = s * (K[q] + (q == mp ? 1.0 : 0.0));
+            J[q] = __builtin_fma(s, J[q], d * k1);
+            K[q] = k1;
+        }
+        const int p = clamp_mark(marks[e], M);
+        double R = 0.0, Dd = 0.0;
+#pragma unroll
+        for (int q = 0; q < MP; ++q) {
+            const double a = q < M ? (double)al[p * M + q] : 0.0;
+            R = __builtin_fma(a, K[q], R);
+            Dd = __builtin_fma(a, J[q], Dd);
+        }
+        const double lam = (double)mus[p] + bet * R;
+        if (INTENS) lambda_out[e] = (float)lam;
+        logsum += log(lam);
+        const double x = bet * (T - te);
+        const double ex = exp(-x);
+        double csp = 0.0;
+#pragma unroll
+        for (int q = 0; q < MP; ++q) csp = (q == p) ? colsum[q] : csp;
+        comp += csp * (1.0 - ex);
+        if (GRAD) {
+            const double w = 1.0 / lam;
+            gb += w * (R - bet * Dd);
+            Esum += csp * (T - te) * ex;
+#pragma unroll
+            for (int q = 0; q < MP; ++q) {
+                Sq[q] += (q == p) ? w : 0.0;
+                Cq[q] += (q == p) ? (1.0 - ex) : 0.0;
+            }
+#pragma unroll
+            for (int r = 0; r < (GRAD ? MP : 1); ++r) {
+                const double cr = (r == p) ? w : 0.0;
+#pragma unroll
+                for (int q = 0; q < (GRAD ? MP : 1); ++q) G[r][q] = __builtin_fma(cr, K[q], G[r][q]);
+            }
+        }
+        tp = te;
+        mp = p;
+    }
+    double* o = part + it * (int64_t)PW;
+    o[0] = logsum;
+    o[1] = comp;
+    if (GRAD) {
+        o[2] = Esum;
+        o[3] = gb;
+#pragma unroll
+        for (int q = 0; q < MP; ++q) { o[4 + q] = Sq[q]; o[4 + MP + q] = Cq[q]; }
+#pragma unroll
+        for (int r = 0; r < (GRAD ? MP : 1); ++r)
+#pragma unroll
+            for (int q = 0; q < (GRAD ? MP : 1); ++q) o[4 + 2 * MP + r * MP + q] = G[r][q];
+    }
+}
+
+// ---------------------------------------------------------------- reduction
+// level 1: per (sequence, chunk of HK_RCH items): thread per partial entry
+__global__ __launch_bounds__(128) void small_reduce1(int32_t S, int64_t n_items_cap,
+                                                    const int64_t* __restrict__ item_off,
+                                                    const int64_t* __restrict__ chunk_off,
+                                                    const double* __restrict__ part, int32_t PW,
+                                                    double* __restrict__ cpart, int64_t n_chunks_cap) {
+    const int64_t c = blockIdx.x;
+    if (c >= n_chunks_cap) return;
+    if (c >= chunk_off[S]) return;
+    const int32_t s = find_seq(chunk_off, S, c);
+    const int64_t kc = c - chunk_off[s];
+    const int64_t i0 = item_off[s] + kc * HK_RCH;
+    int64_t i1e = item_off[s + 1];
+    i1e = i1e > n_items_cap ? n_items_cap : i1e;
+    const int64_t i1 = i0 + HK_RCH < i1e ? i0 + HK_RCH : i1e;
+    for (int e = threadIdx.x; e < PW; e += blockDim.x) {
+        double acc = 0.0;
+        for (int64_t i = i0; i < i1; ++i) acc += part[i * PW + e];
+        cpart[c * PW + e] = acc;
+    }
+}
+
+// level 2: per sequence; assemble eqs. 2, 8, 9, 10
+template <int MP, bool GRAD>
+__global__ __launch_bounds__(128) void small_reduce2(int32_t S, int64_t n_chunks_cap,
+                                                    const int64_t* __restrict__ chunk_off,
+                                                    const int32_t* __restrict__ m_s, const double* __restrict__ T_s,
+                                                    const float* __restrict__ mu, const float* __restrict__ beta,
+                                                    const int64_t* __restrict__ mu_off, const int64_t* __restrict__ a_off,
+                                                    const double* __restrict__ cpart, int32_t PW,
+                                                    double* __restrict__ loglik, double* __restrict__ g_mu,
+                                                    double* __restrict__ g_alpha, double* __restrict__ g_beta) {
+    const int32_t s = blockIdx.x;
+    if (s >= S) return;
+    __shared__ double tot[4 + 2 * MP + MP * MP];
+    const int64_t c0 = chunk_off[s];
+    int64_t c1 = chunk_off[s + 1];
+    c1 = c1 > n_chunks_cap ? n_chunks_cap : c1;
+    for (int e = threadIdx.x; e < PW; e += blockDim.x) {
+        double acc = 0.0;
+        for (int64_t c = c0; c < c1; ++c) acc += cpart[c * PW + e];
+        tot[e] = acc;
+    }
+    __syncthreads();
+    const int32_t M = m_s[s] < 1 ? 1 : (m_s[s] > MP ? MP : m_s[s]);
+    const double T = T_s[s];
+    const float* mus = mu + mu_off[s];
+    if (threadIdx.x == 0) {
+        double musum = 0.0;
+        for (int p = 0; p < M; ++p) musum += (double)mus[p];
+        loglik[s] = tot[0] - T * musum - tot[1];
+        if (GRAD && g_beta) g_beta[s] = tot[3] - tot[2];
+    }
+    if (GRAD) {
+        const double bet = (double)beta[s];
+        for (int x = threadIdx.x; x < M * M; x += blockDim.x) {
+            const int p = x / M, q = x % M;
+            if (g_alpha) g_alpha[a_off[s] + x] = bet * tot[4 + 2 * MP + p * MP + q] - tot[4 + MP + q];
+        }
+        for (int q = threadIdx.x; q < M; q += blockDim.x)
+            if (g_mu) g_mu[mu_off[s] + q] = tot[4 + q] - T;
+    }
+}
+
+// ---------------------------------------------------------------- host launch
+template <int MP>
+static hawkes_status run_small_mp(const SmallArgs& A, hipStream_t st) {
+    const int32_t PW = A.grad ? 4 + 2 * MP + MP * MP : 2;
+    const int64_t waves = (A.n_items_cap + 63) / 64;
+    const int64_t blocks = (waves + 3) / 4;
+    hipLaunchKernelGGL(small_setup, dim3(1), dim3(1024), 0, st, A.S, A.n_total, A.ev_off, A.m_s, A.L,
+                       A.item_off, A.chunk_off, A.mu_off, A.a_off);
+    hipLaunchKernelGGL(small_agg<MP>, dim3((unsigned)blocks), dim3(256), 0, st, A.S, A.n_total, A.ev_off,
+                       A.item_off, A.L,
+                       A.t, A.marks, A.m_s, A.beta, A.item_pref, A.tile_agg, A.n_items_cap);
+    const int64_t nthr = (int64_t)A.S * MP;
+    hipLaunchKernelGGL(small_tile_scan<MP>, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, st, A.S,
+                       A.n_items_cap, A.item_off, A.beta, A.tile_agg, A.tile_carry);
+    if (A.grad) {
+        hipLaunchKernelGGL((small_compute<MP, true, false>), dim3((unsigned)blocks), dim3(256), 0, st, A.S,
+                           A.n_total, A.ev_off, A.item_off, A.L, A.t, A.marks, A.m_s, A.T_s, A.mu, A.alpha, A.beta,
+                           A.mu_off, A.a_off, A.item_pref, A.tile_carry, A.part, PW, (float*)nullptr,
+                           A.n_items_cap);
+    } else if (A.lambda_out) {
+        hipLaunchKernelGGL((small_compute<MP, false, true>), dim3((unsigned)blocks), dim3(256), 0, st, A.S,
+                           A.n_total, A.ev_off, A.item_off, A.L, A.t, A.marks, A.m_s, A.T_s, A.mu, A.alpha, A.beta,
+                           A.mu_off, A.a_off, A.item_pref, A.tile_carry, A.part, PW, A.lambda_out,
+                           A.n_items_cap);
+    } else {
+        hipLaunchKernelGGL((small_compute<MP, false, false>), dim3((unsigned)blocks), dim3(256), 0, st, A.S,
+                           A.n_total, A.ev_off, A.item_off, A.L, A.t, A.marks, A.m_s, A.T_s, A.mu, A.alpha, A.beta,
+                           A.mu_off, A.a_off, A.item_pref, A.tile_carry, A.part, PW, (float*)nullptr,
+                           A.n_items_cap);
+    }
+    hipLaunchKernelGGL(small_reduce1, dim3((unsigned)A.n_chunks_cap), dim3(128), 0, st, A.S, A.n_items_cap,
+                       A.item_off,
+                       A.chunk_off, A.part, PW, A.cpart, A.n_chunks_cap);
+    if (A.grad)
+        hipLaunchKernelGGL((small_reduce2<MP, true>), dim3((unsigned)A.S), dim3(128), 0, st, A.S, A.n_chunks_cap,
+                           A.chunk_off,
+                           A.m_s, A.T_s, A.mu, A.beta, A.mu_off, A.a_off, A.cpart, PW, A.loglik, A.g_mu,
+                           A.g_alpha, A.g_beta);
+    else
+        hipLaunchKernelGGL((small_reduce2<MP, false>), dim3((unsigned)A.S), dim3(128), 0, st, A.S, A.n_chunks_cap,
+                           A.chunk_off,
+                           A.m_s, A.T_s, A.mu, A.beta, A.mu_off, A.a_off, A.cpart, PW, A.loglik, A.g_mu,
+                           A.g_alpha, A.g_beta);
+    return hipGetLastError() == hipSuccess ? HAWKES_OK : HAWKES_EDEVICE;
+}
+
+hawkes_status run_small(const SmallArgs& A, hipStream_t st) {
+    switch (A.MP) {
+        case 1: return run_small_mp<1>(A, st);
+        case 2: return run_small_mp<2>(A, st);
+        case 4: return run_small_mp<4>(A, st);
+        case 8: return run_small_mp<8>(A, st);
+        default: return HAWKES_EUNSUPPORTED;
+    }
+}
+
+}  // namespace hk

@@ -1,0 +1,116 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+include/hawkes.h declares, and rejects bad arguments on the host before any
+launch (null pointers, bad sizes, short workspace, unsupported kernel count)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hawkes.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hawkes_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def H():
+    import paper_2604_01342_amd as H
+    if not os.path.exists(H.library_path()):
+        pytest.fail("libhawkes.so is not built")
+    return H
+
+
+def test_header_declares_expected_api():
+    names = declared_functions()
+    for f in ("hawkes_loglik", "hawkes_loglik_grad", "hawkes_loglik_batched", "hawkes_loglik_grad_batched",
+              "hawkes_workspace_bytes", "hawkes_batched_workspace_bytes", "hawkes_sequential_loglik_grad",
+              "hawkes_intensity", "hawkes_check_inputs", "hawkes_status_string", "hawkes_version"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(H):
+    L = H.lib()
+    for f in declared_functions():
+        assert hasattr(L, f), f"{f} declared in hawkes.h but not exported"
+
+
+def test_version_and_status_strings(H):
+    L = H.lib()
+    assert L.hawkes_version() == 1
+    for s in range(5):
+        assert L.hawkes_status_string(s)
+    assert L.hawkes_status_string(2) == b"workspace missing or too small"
+
+
+def P(H, n=10, m=3, k=1, mode=0, chunk=0, T=5.0):
+    return H._Problem(n, m, k, mode, chunk, T)
+
+
+def test_workspace_query_rejects_bad_problems(H):
+    L = H.lib()
+    good = P(H)
+    assert L.hawkes_workspace_bytes(ctypes.byref(good), 1) > 0
+    for bad in (P(H, n=-1), P(H, m=0), P(H, k=0), P(H, mode=7), P(H, T=-1.0), P(H, chunk=5), P(H, chunk=40),
+                P(H, T=float("nan"))):
+        assert L.hawkes_workspace_bytes(ctypes.byref(bad), 1) == 0
+    assert L.hawkes_workspace_bytes(None, 1) == 0
+    assert L.hawkes_workspace_bytes(ctypes.byref(P(H, k=2)), 1) == 0
+    assert L.hawkes_batched_workspace_bytes(0, 10, 4, 1) == 0
+    assert L.hawkes_batched_workspace_bytes(4, -1, 4, 1) == 0
+    assert L.hawkes_batched_workspace_bytes(4, 10, 9, 1) == 0
+    assert L.hawkes_batched_workspace_bytes(4, 10, 8, 1) > 0
+
+
+def test_workspace_is_constant_in_n_for_large_m(H):
+    # constant-memory chunking: beyond one chunk the workspace does not grow
+    a = H.workspace_bytes(5_000_000, 500, grad=True)
+    b = H.workspace_bytes(50_000_000, 500, grad=True)
+    assert a == b
+
+
+FAKE = ctypes.c_void_p(4096)   # never dereferenced: every call below fails its host checks
+
+
+def test_host_argument_errors(H):
+    L = H.lib()
+    p = P(H)
+    nul = ctypes.c_void_p(0)
+    args = [FAKE] * 6
+    # null outputs / inputs
+    assert L.hawkes_loglik(ctypes.byref(p), FAKE, FAKE, nul, FAKE, FAKE, FAKE, FAKE, 1 << 30, nul) == 1
+    assert L.hawkes_loglik(ctypes.byref(p), nul, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, 1 << 30, nul) == 1
+    assert L.hawkes_loglik(None, *args, FAKE, 1 << 30, nul) == 1
+    # unsupported kernel count
+    p2 = P(H, k=3)
+    assert L.hawkes_loglik(ctypes.byref(p2), *args, FAKE, 1 << 30, nul) == 4
+    # workspace missing / too small
+    assert L.hawkes_loglik(ctypes.byref(p), *args, nul, 1 << 30, nul) == 2
+    assert L.hawkes_loglik(ctypes.byref(p), *args, FAKE, 16, nul) == 2
+    pl = P(H, m=200)
+    assert L.hawkes_loglik_grad(ctypes.byref(pl), *args, FAKE, FAKE, FAKE, FAKE, 16, nul) == 2
+    # misaligned workspace
+    assert L.hawkes_loglik(ctypes.byref(p), *args, ctypes.c_void_p(4096 + 8), 1 << 30, nul) == 2
+    # intensity needs an output
+    assert L.hawkes_intensity(ctypes.byref(p), FAKE, FAKE, FAKE, FAKE, FAKE, nul, FAKE, 1 << 30, nul) == 1
+    # batched: bad sizes, unsupported node count, missing offsets
+    b = [FAKE] * 9     # ev_off, m_s, T_s, t, marks, mu, alpha, beta, loglik
+    assert L.hawkes_loglik_batched(0, 10, 4, *b, FAKE, 1 << 30, nul) == 1
+    assert L.hawkes_loglik_batched(4, 10, 9, *b, FAKE, 1 << 30, nul) == 4
+    assert L.hawkes_loglik_batched(4, 10, 4, nul, *b[1:], FAKE, 1 << 30, nul) == 1
+    assert L.hawkes_loglik_batched(4, 10, 4, *b, FAKE, 8, nul) == 2
+    # sequential baseline: shared decay only
+    pt = P(H, mode=1)
+    assert L.hawkes_sequential_loglik_grad(ctypes.byref(pt), *args, FAKE, FAKE, FAKE, FAKE, 1 << 30, nul) == 4
+    assert L.hawkes_check_inputs(ctypes.byref(p), FAKE, FAKE, FAKE, FAKE, FAKE, nul, nul) == 1
+
+
+def test_binding_refuses_cpu_tensors(H):
+    import torch
+    with pytest.raises(ValueError):
+        H.loglik(torch.zeros(3, dtype=torch.float64), torch.zeros(3, dtype=torch.int32), torch.ones(2),
+                 torch.zeros(2, 2), torch.ones(1), 1.0)
