@@ -25,7 +25,7 @@ def build(force: bool = False) -> str:
     """Compile the oracle with the host C compiler (plain -O2, no fast-math)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + f".tmp{os.getpid()}"
-        subprocess.run(["gcc", "-O2", "-march=native", "-std=c99", "-shared", "-fPIC",
+        subprocess.run(["gcc", "-O2", "-std=c99", "-shared", "-fPIC",
                         "-o", tmp, _SRC, "-lm"], check=True)
         os.replace(tmp, _LIB)
     return _LIB
