@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Throughput of one fused log-likelihood + gradient pass on one MI355X.
+
+Workload (default): M = 1000 nodes, one sequence of N = 10,000,000 events,
+mu ~ U[0.01, 0.05], alpha 1% dense with U[0,1] entries rescaled to spectral
+radius 0.8, beta = 1, simulated with the branching representation (seeded);
+evaluated in constant-memory chunks of 2^20 events.  A "step" is one call of
+hawkes_loglik_grad over the whole sequence with inputs resident in HBM:
+log-likelihood plus dL/dmu, dense dL/dalpha and dL/dbeta.
+
+Prints one JSON line: events/s, ms per step, the roofline of the dominant
+kernel (dense dL/dalpha) from hipEvents recorded around its launches during
+the timed region, the CPU oracle timed on a prefix of the same workload, the
+sequential-recurrence GPU kernel timed on a prefix, and the error of the GPU
+result against the oracle on that prefix.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "events/sec for loglik+grad (M=1000, N=1e7) at 1e-6 rel err; speedup vs seq recurrence"
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 64 FMA/clk x 2 flop x 2.4 GHz
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def source_hash(*names) -> str:
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2604_01342_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(src_hash: str):
+    """HBM bytes per dense-kernel launch from committed rocprofv3 counter runs,
+    or None when absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "dense_dalpha_c4_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_sha256") != src_hash:
+        return None
+    return d
+
+
+def rel(a, b):
+    import numpy as np
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-events", type=int, default=3_000_000,
+                    help="prefix length for the CPU oracle leg (about 10-15 s single-threaded)")
+    ap.add_argument("--seq-events", type=int, default=20_000,
+                    help="prefix length for the sequential GPU kernel")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-seq", action="store_true")
+    ap.add_argument("--chunk-log2", type=int, default=20)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is a design "
+                                   "(see DESIGN.md), not a measured path", "n_gpus": args.gpus}), flush=True)
+        return 2
+
+    import numpy as np
+    import torch
+    import paper_2604_01342_amd as H
+    from paper_2604_01342_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        log("no GPU visible")
+        return 1
+    dev = torch.device("cuda:0")
+    H.lib()
+
+    t0 = time.time()
+    w = W.cached("c4_full", lambda: W.make_config(4))
+    log(f"workload c4: n={w.n} M={w.M} T={w.T:.2f} ({time.time() - t0:.1f}s)")
+    t = torch.as_tensor(w.t, dtype=torch.float64, device=dev)
+    m = torch.as_tensor(w.m, dtype=torch.int32, device=dev)
+    mu = torch.as_tensor(w.mu, dtype=torch.float32, device=dev)
+    al = torch.as_tensor(w.alpha, dtype=torch.float32, device=dev)
+    be = torch.as_tensor(w.beta, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+
+    def step():
+        return H.loglik_grad(t, m, mu, al, be, w.T, args.chunk_log2)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done")
+
+    H.timing_reset()
+    H.timing_enable(True)
+    torch.cuda.synchronize()
+    tw0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = step()
+    torch.cuda.synchronize()
+    tw1 = time.perf_counter()
+    H.timing_enable(False)
+    kt = H.timing_read()
+    ms_per_step = (tw1 - tw0) * 1e3 / args.steps
+    value = w.n / (ms_per_step / 1e3)
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, {value:.4e} events/s")
+
+    dense_ms, dense_n = kt["dense_dalpha"]
+    src = source_hash("hk_large.hip", "hk_large.h", "hk_device.h")
+    roofline = None
+    if dense_n > 0:
+        avg_ms = dense_ms / dense_n
+        flops_per_launch = 2.0 * w.M * (w.n * args.steps / dense_n)
+        achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+        tr = load_traffic(src)
+        roofline = {"kernel": "large_dense (dense dL/dalpha)", "bound": "alu", "achieved": round(achieved, 3),
+                    "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
+                    "traffic": (tr["bytes_per_launch"] if tr else None),
+                    "avg_launch_ms": round(avg_ms, 4), "launches": dense_n,
+                    "flops_per_launch": flops_per_launch}
+    kernels = {k: {"total_ms": round(v[0] / args.steps, 4), "launches_per_step": v[1] / args.steps}
+               for k, v in kt.items() if v[1] > 0}
+
+    out = {"metric": METRIC, "value": value, "unit": "events/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32 state / f64 sums", "data": "synthetic",
+           "config": {"workload": "c4: M=1000, N=1e7, alpha 1% dense rho=0.8, beta=1, chunks of 2^20",
+                      "n_events": w.n, "n_nodes": w.M, "chunk_log2": args.chunk_log2},
+           "roofline": roofline, "kernels_ms_per_step": kernels}
+
+    # sequential-recurrence GPU kernel on a prefix
+    if not args.no_seq:
+        ns = min(args.seq_events, w.n)
+        Ts = float(w.t[ns - 1])
+        H.sequential_loglik_grad(t[:ns], m[:ns], mu, al, be, Ts)
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        H.sequential_loglik_grad(t[:ns], m[:ns], mu, al, be, Ts)
+        torch.cuda.synchronize()
+        s_dt = time.perf_counter() - s0
+        seq_v = ns / s_dt
+        out["sequential_gpu"] = {"value": seq_v, "unit": "events/s", "sample": f"first {ns} events"}
+        out["speedup_vs_sequential"] = value / seq_v
+        log(f"sequential GPU kernel: {seq_v:.4e} events/s on {ns} events -> speedup {value / seq_v:.1f}x")
+
+    # CPU oracle on a prefix, and GPU-vs-oracle errors on the same prefix
+    if not args.no_cpu:
+        import oracle
+        nc = min(args.cpu_events, w.n)
+        Tc = float(w.t[nc - 1])
+        c0 = time.perf_counter()
+        ref = oracle.forward(w.t[:nc], w.m[:nc], w.mu, w.alpha, w.beta, Tc)
+        c_dt = time.perf_counter() - c0
+        out["cpu_baseline"] = {"value": nc / c_dt, "unit": "events/s", "cores": 1, "kind": "oracle",
+                               "sample": f"first {nc} events of the workload (T = t_{nc}), "
+                                         f"FP64 sequential recurrence, {c_dt:.1f} s"}
+        g = H.loglik_grad(t[:nc], m[:nc], mu, al, be, Tc, args.chunk_log2)
+        torch.cuda.synchronize()
+        errs = {"loglik": abs(g[0].item() - ref[0]) / abs(ref[0]), "g_mu": rel(g[1].cpu().numpy(), ref[1]),
+                "g_alpha": rel(g[2].cpu().numpy(), ref[2][0]), "g_beta": rel(g[3].cpu().numpy(), ref[3])}
+        out["err_vs_oracle"] = {k: float(f"{v:.3e}") for k, v in errs.items()}
+        out["err_vs_oracle"]["sample"] = f"first {nc} events"
+        log(f"CPU oracle: {nc / c_dt:.4e} events/s ({c_dt:.1f}s); errors {errs}")
+
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

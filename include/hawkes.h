@@ -33,10 +33,11 @@
  *  - Outputs are float64: loglik[1], g_mu[m], g_alpha[m*m] (same layout as
  *    alpha), g_beta[1] (shared) or g_beta[m] (per target).  Any gradient
  *    pointer may be NULL to skip that output.
- *  - Precision: time differences are formed in float64, decays, scan state
- *    and intensities are float32, and every sum over events (log-likelihood,
- *    gradients) is accumulated in float64 in a fixed order, so repeated calls
- *    return bitwise-identical results.
+ *  - Precision: time differences are formed in float64.  For m > 8 (the
+ *    large-M engine) decays, scan state and intensities are float32; for
+ *    m <= 8 the few state values per lane are kept in float64.  Every sum over
+ *    events (log-likelihood, gradients) is accumulated in float64 in a fixed
+ *    order, so repeated calls return bitwise-identical results.
  *  - Errors: every function returns a hawkes_status.  Host-detectable
  *    argument errors return HAWKES_EINVAL (or HAWKES_EWORKSPACE for a short
  *    workspace) before anything is launched, and the outputs are untouched.
@@ -130,7 +131,8 @@ hawkes_status hawkes_intensity(const hawkes_problem* p,
  * device.  Outputs use the same packing: loglik[S], g_mu (like mu),
  * g_alpha (like alpha), g_beta[S].
  * Host arguments: S >= 1, n_total = ev_off[S] (the length of t), and
- * max_m >= every m_s[s] (sizes the kernels' on-chip buffers; max_m <= 64).
+ * max_m >= every m_s[s] (sizes the kernels' register state; this build
+ * supports max_m <= 8 and returns HAWKES_EUNSUPPORTED above that).
  * ------------------------------------------------------------------------- */
 size_t hawkes_batched_workspace_bytes(int32_t S, int64_t n_total, int32_t max_m, int with_grad);
 
@@ -171,6 +173,23 @@ hawkes_status hawkes_check_inputs(const hawkes_problem* p,
                                   const double* t, const int32_t* marks,
                                   const float* mu, const float* alpha, const float* beta,
                                   int32_t* status_out, hipStream_t stream);
+
+/* ----------------------------------------------------------------------------
+ * Diagnostics: per-kernel device timing.  While enabled, every call records a
+ * pair of hipEvents on its stream around each launch of the library's main
+ * kernels; hawkes_timing_read waits for those events and returns the summed
+ * milliseconds and the number of launches of one kernel.  Kernel ids:
+ *   0 dense dL/dalpha (large-M engine)   1 forward scan (large-M engine)
+ *   2 segment aggregates (large-M)       3 segment carry scan (large-M)
+ *   4 per-item evaluation (small-M)      5 small-M aggregates and scans
+ * Recording is host-side bookkeeping only (no device allocation); the events
+ * are destroyed by hawkes_timing_read / hawkes_timing_reset.  Not for use
+ * during graph capture.
+ * ------------------------------------------------------------------------- */
+#define HAWKES_TIMING_KERNELS 6
+hawkes_status hawkes_timing_enable(int on);
+hawkes_status hawkes_timing_reset(void);
+hawkes_status hawkes_timing_read(int kernel_id, double* total_ms, int64_t* launches);
 
 #ifdef __cplusplus
 }

@@ -76,6 +76,10 @@ def lib():
     L.hawkes_loglik_batched.argtypes = [i32, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.hawkes_loglik_grad_batched.argtypes = [i32, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                              sz, vp]
+    L.hawkes_timing_enable.argtypes = [ctypes.c_int]
+    L.hawkes_timing_read.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    for f in ("hawkes_timing_enable", "hawkes_timing_reset", "hawkes_timing_read"):
+        getattr(L, f).restype = ctypes.c_int
     for f in ("hawkes_loglik", "hawkes_loglik_grad", "hawkes_intensity", "hawkes_sequential_loglik_grad",
               "hawkes_check_inputs", "hawkes_loglik_batched", "hawkes_loglik_grad_batched"):
         getattr(L, f).restype = ctypes.c_int
@@ -199,6 +203,30 @@ def sequential_loglik_grad(t, m, mu, alpha, beta, T):
            L.hawkes_sequential_loglik_grad(ctypes.byref(p), _ptr(t), _ptr(m), _ptr(mu), _ptr(alpha), _ptr(beta),
                                            _ptr(out), _ptr(gmu), _ptr(ga), _ptr(gb), _ptr(ws), nb, _stream(dev)))
     return out[0], gmu, ga, gb
+
+
+TIMING_KERNELS = {0: "dense_dalpha", 1: "forward", 2: "segment_aggregate", 3: "segment_scan",
+                  4: "small_compute", 5: "small_scan"}
+
+
+def timing_enable(on: bool = True) -> None:
+    """Record hipEvents around the library's main kernels (diagnostics)."""
+    _check("hawkes_timing_enable", lib().hawkes_timing_enable(int(on)))
+
+
+def timing_reset() -> None:
+    _check("hawkes_timing_reset", lib().hawkes_timing_reset())
+
+
+def timing_read() -> dict:
+    """{kernel name: (total_ms, launches)} accumulated since the last reset (waits on the events)."""
+    out = {}
+    for k, name in TIMING_KERNELS.items():
+        ms = ctypes.c_double(0.0)
+        n = ctypes.c_int64(0)
+        _check("hawkes_timing_read", lib().hawkes_timing_read(k, ctypes.byref(ms), ctypes.byref(n)))
+        out[name] = (ms.value, n.value)
+    return out
 
 
 def check_inputs(t, m, mu, alpha, beta, T) -> int:

@@ -49,6 +49,16 @@ struct SmallArgs {
 
 hawkes_status run_small(const SmallArgs& A, hipStream_t st);
 
+// optional per-kernel event timing (hawkes_timing_*)
+void* timing_begin(int id, hipStream_t st);
+void timing_end(void* h, hipStream_t st);
+struct TimedScope {
+    void* h;
+    hipStream_t st;
+    TimedScope(int id, hipStream_t s) : h(timing_begin(id, s)), st(s) {}
+    ~TimedScope() { timing_end(h, st); }
+};
+
 // carve the small-engine workspace; returns bytes needed (A gets pointers when ws != nullptr)
 size_t small_layout(SmallArgs& A, int32_t S, int64_t n_total, int32_t max_m, bool grad, void* ws,
                     size_t ws_bytes, bool single);

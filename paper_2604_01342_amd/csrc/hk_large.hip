@@ -528,10 +528,17 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
         const int64_t c0 = ch * A.CH;
         const int64_t c1 = c0 + A.CH < A.n ? c0 + A.CH : A.n;
         const int32_t nseg = (int32_t)((c1 - c0 + HK_SEG - 1) / HK_SEG);
-        hipLaunchKernelGGL(large_seg_agg, dim3(nseg), dim3(64), lds_agg, st, c0, c1, M, A.t, A.marks, A.beta,
-                           A.agg, A.seg_tend);
-        hipLaunchKernelGGL(large_seg_scan, dim3(gM), dim3(256), 0, st, c0, nseg, M, A.t, A.beta, A.agg,
-                           A.seg_tend, A.carry);
+        {
+            TimedScope ts(2, st);
+            hipLaunchKernelGGL(large_seg_agg, dim3(nseg), dim3(64), lds_agg, st, c0, c1, M, A.t, A.marks, A.beta,
+                               A.agg, A.seg_tend);
+        }
+        {
+            TimedScope ts(3, st);
+            hipLaunchKernelGGL(large_seg_scan, dim3(gM), dim3(256), 0, st, c0, nseg, M, A.t, A.beta, A.agg,
+                               A.seg_tend, A.carry);
+        }
+        TimedScope* tf = new TimedScope(1, st);
         if (A.grad)
             hipLaunchKernelGGL((large_forward<true, false>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1, M, A.T,
                                A.t, A.marks, A.mu, A.beta, A.csr_ptr, A.csr_col, A.csr_val, A.colsum, A.agg,
@@ -547,10 +554,12 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
                                A.t, A.marks, A.mu, A.beta, A.csr_ptr, A.csr_col, A.csr_val, A.colsum, A.agg,
                                A.seg_part, A.ev_m, A.ev_c, A.ev_b, A.ev_w, A.ev_ct, A.batch_rho, A.batch_wide,
                                (float*)nullptr);
+        delete tf;
         hipLaunchKernelGGL(large_chunk_acc, dim3(1), dim3(64), 0, st, nseg, A.seg_part, A.acc);
         if (A.grad) {
             int32_t spr = (nseg + A.ER - 1) / A.ER;
             const unsigned nblk = (unsigned)(A.NB * A.NB * A.ER);
+            TimedScope ts(0, st);
             hipLaunchKernelGGL(large_dense, dim3(nblk), dim3(64), 0, st, c0, c1, M, A.NB, A.ER, spr, A.t, A.beta,
                                A.agg, A.ev_m, A.ev_c, A.ev_b, A.ev_w, A.ev_ct, A.batch_rho, A.batch_wide,
                                A.gpart, A.spart, A.cpart_);

@@ -473,6 +473,7 @@ static hawkes_status run_small_mp(const SmallArgs& A, hipStream_t st) {
     const int32_t PW = A.grad ? 4 + 2 * MP + MP * MP : 2;
     const int64_t waves = (A.n_items_cap + 63) / 64;
     const int64_t blocks = (waves + 3) / 4;
+    TimedScope* t5 = new TimedScope(5, st);
     hipLaunchKernelGGL(small_setup, dim3(1), dim3(1024), 0, st, A.S, A.n_total, A.ev_off, A.m_s, A.L,
                        A.item_off, A.chunk_off, A.mu_off, A.a_off);
     hipLaunchKernelGGL(small_agg<MP>, dim3((unsigned)blocks), dim3(256), 0, st, A.S, A.n_total, A.ev_off,
@@ -481,6 +482,8 @@ static hawkes_status run_small_mp(const SmallArgs& A, hipStream_t st) {
     const int64_t nthr = (int64_t)A.S * MP;
     hipLaunchKernelGGL(small_tile_scan<MP>, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, st, A.S,
                        A.n_items_cap, A.item_off, A.beta, A.tile_agg, A.tile_carry);
+    delete t5;
+    TimedScope* t4 = new TimedScope(4, st);
     if (A.grad) {
         hipLaunchKernelGGL((small_compute<MP, true, false>), dim3((unsigned)blocks), dim3(256), 0, st, A.S,
                            A.n_total, A.ev_off, A.item_off, A.L, A.t, A.marks, A.m_s, A.T_s, A.mu, A.alpha, A.beta,
@@ -497,6 +500,7 @@ static hawkes_status run_small_mp(const SmallArgs& A, hipStream_t st) {
                            A.mu_off, A.a_off, A.item_pref, A.tile_carry, A.part, PW, (float*)nullptr,
                            A.n_items_cap);
     }
+    delete t4;
     hipLaunchKernelGGL(small_reduce1, dim3((unsigned)A.n_chunks_cap), dim3(128), 0, st, A.S, A.n_items_cap,
                        A.item_off,
                        A.chunk_off, A.part, PW, A.cpart, A.n_chunks_cap);
