@@ -28,16 +28,21 @@ struct LargeArgs {
     // workspace
     int32_t *csr_ptr, *csr_col;
     float *csr_val, *colsum;
-    double* agg;          // [nseg][2M]: segment aggregates, then segment carries
-    double* seg_tend;     // [nseg]
+    double* agg;          // [nseg][2M] segment maps (K_run, J_run)
+    double* seg_span;     // [nseg] time from the event before the segment to its last event
+    double* seg_dec;      // [nseg] e^{-beta (span of the segment from the preceding event)}
+    double* carry_seg;    // [nseg][2M] state just after the event preceding segment s
+    int32_t ngr;          // scan groups per chunk
+    double *gagg, *gcarry, *gspan, *gdec;   // group maps, carries, spans, decays
+    int4* node_info;      // [M] (csr begin, csr end, mu, colsum)
     double* carry;        // [2M] chunk carry (K, J) at carry_t
     double* carry_t;      // [1] time of the carry (last event before the chunk)
     double* seg_part;     // [nseg][4]
     double* acc;          // [4] call-level sums: logsum, comp, E, gbeta
     double* ll_scratch;   // [1] log-likelihood slot when the caller wants intensities only
-    int32_t* ev_m;
-    float *ev_c, *ev_b, *ev_w, *ev_ct, *batch_rho;
-    int32_t* batch_wide;
+    int4* ev_rec;         // [CH] per-event (mark, c, b, w) for the dense kernel
+    float* ev_ct;         // [CH] 1 - e^{-beta (T - t_i)} for the dense kernel's row-block 0
+    int2* batch_info;     // [CH/64 + 1] per 64-event batch: (rescale factor bits, wide flag)
     double *gpart, *spart, *cpart_;  // [ER][M][M], [ER][M], [ER][M]
     // outputs
     double *loglik, *g_mu, *g_alpha, *g_beta;

@@ -28,6 +28,7 @@
 //            multiply-add per column; rows accumulate in float64 LDS.
 #include "hk_device.h"
 #include "hk_large.h"
+#include <stdlib.h>
 
 namespace hk {
 
@@ -37,18 +38,27 @@ __global__ void fill_d(double* p, int64_t n, double v) {
         p[i] = v;
 }
 
-// colsum[q] = sum_p alpha[p][q]; csr_ptr[p+1] = nnz of row p
-__global__ void large_colsum_count(int32_t M, const float* __restrict__ alpha, float* __restrict__ colsum,
-                                   int32_t* __restrict__ csr_ptr) {
-    const int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= M) return;
+// colsum[q] = sum_p alpha[p][q] (thread per column, coalesced over q)
+__global__ void large_colsum(int32_t M, const float* __restrict__ alpha, float* __restrict__ colsum) {
+    const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= M) return;
     double c = 0.0;
+    for (int32_t p = 0; p < M; ++p) c += (double)alpha[(int64_t)p * M + q];
+    colsum[q] = (float)c;
+}
+
+// csr_ptr[p+1] = nnz of row p (one wave per row, coalesced)
+__global__ __launch_bounds__(64) void large_rowcount(int32_t M, const float* __restrict__ alpha,
+                                                     int32_t* __restrict__ csr_ptr) {
+    const int32_t p = blockIdx.x;
+    const int lane = threadIdx.x;
     int32_t cnt = 0;
-    for (int32_t p = 0; p < M; ++p) c += (double)alpha[(int64_t)p * M + x];
-    for (int32_t q = 0; q < M; ++q) cnt += alpha[(int64_t)x * M + q] != 0.0f;
-    colsum[x] = (float)c;
-    csr_ptr[x + 1] = cnt;
-    if (x == 0) csr_ptr[0] = 0;
+    for (int32_t q = lane; q < M; q += 64) cnt += alpha[(int64_t)p * M + q] != 0.0f;
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_down(cnt, off, 64);
+    if (lane == 0) {
+        csr_ptr[p + 1] = cnt;
+        if (p == 0) csr_ptr[0] = 0;
+    }
 }
 
 // inclusive scan of csr_ptr[1..M] in one workgroup
@@ -75,22 +85,40 @@ __global__ __launch_bounds__(1024) void large_csr_scan(int32_t M, int32_t* __res
     }
 }
 
-__global__ void large_csr_fill(int32_t M, const float* __restrict__ alpha, const int32_t* __restrict__ csr_ptr,
-                               int32_t* __restrict__ csr_col, float* __restrict__ csr_val) {
+// one wave per row: compact the nonzeros of row p in column order
+__global__ __launch_bounds__(64) void large_csr_fill(int32_t M, const float* __restrict__ alpha,
+                                                     const int32_t* __restrict__ csr_ptr,
+                                                     int32_t* __restrict__ csr_col, float* __restrict__ csr_val) {
+    const int32_t p = blockIdx.x;
+    const int lane = threadIdx.x;
+    int32_t o = csr_ptr[p];
+    for (int32_t q0 = 0; q0 < M; q0 += 64) {
+        const int32_t q = q0 + lane;
+        const float a = q < M ? alpha[(int64_t)p * M + q] : 0.0f;
+        const uint64_t nz = __ballot(a != 0.0f);
+        if (a != 0.0f) {
+            const int32_t r = __builtin_popcountll(nz & (lane ? (~0ull >> (64 - lane)) : 0ull));
+            csr_col[o + r] = q;
+            csr_val[o + r] = a;
+        }
+        o += __builtin_popcountll(nz);
+    }
+}
+
+// node_info[p] = (csr begin, csr end, mu_p, colsum_p): one 16-byte load per event
+__global__ void large_node_info(int32_t M, const int32_t* __restrict__ csr_ptr, const float* __restrict__ mu,
+                                const float* __restrict__ colsum, int4* __restrict__ node_info) {
     const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= M) return;
-    int32_t o = csr_ptr[p];
-    for (int32_t q = 0; q < M; ++q) {
-        const float a = alpha[(int64_t)p * M + q];
-        if (a != 0.0f) { csr_col[o] = q; csr_val[o] = a; ++o; }
-    }
+    node_info[p] = make_int4(csr_ptr[p], csr_ptr[p + 1], __float_as_int(mu[p]), __float_as_int(colsum[p]));
 }
 
 // ------------------------------------------------------------------ agg
 // one wave per segment; LDS: aggK[M], aggJ[M] (float64)
 __global__ __launch_bounds__(64) void large_seg_agg(int64_t c0, int64_t c1, int32_t M, const double* __restrict__ t,
                                                     const int32_t* __restrict__ marks, const float* __restrict__ beta,
-                                                    double* __restrict__ agg, double* __restrict__ seg_tend) {
+                                                    double* __restrict__ agg, double* __restrict__ seg_span,
+                                                    double* __restrict__ seg_dec) {
     extern __shared__ double lds[];
     double* aK = lds;
     double* aJ = lds + M;
@@ -115,35 +143,93 @@ __global__ __launch_bounds__(64) void large_seg_agg(int64_t c0, int64_t c1, int3
     __syncthreads();
     double* o = agg + (int64_t)s * 2 * M;
     for (int32_t q = lane; q < M; q += 64) { o[q] = aK[q]; o[M + q] = aJ[q]; }
-    if (lane == 0) seg_tend[s] = te;
+    if (lane == 0) {
+        // span and decay from the event before the segment to its last event
+        const double tr = a > 0 ? t[a - 1] : t[a];
+        seg_span[s] = te - tr;
+        seg_dec[s] = exp(-bet * (te - tr));
+    }
 }
 
 // ------------------------------------------------------------------ scan
-// thread per node: chain the segment maps; agg[s] is overwritten by the
-// carry-in of segment s (state just after the event preceding the segment).
-__global__ void large_seg_scan(int64_t c0, int32_t nseg, int32_t M, const double* __restrict__ t,
-                               const float* __restrict__ beta, double* __restrict__ agg,
-                               const double* __restrict__ seg_tend, double* __restrict__ carry) {
+// Segment maps are chained in three parallel steps (groups of HK_SG segments):
+//   1 thread per (group, node): exclusive prefix inside the group, group map
+//   2 thread per node: chain the group maps from the chunk carry
+//   3 thread per (segment, node): carry_seg[s] = group carry moved to the
+//     segment start, plus the in-group prefix
+// carry_seg[s] is the state just after the event preceding segment s.
+#define HK_SG 32
+
+__global__ void large_scan_local(int32_t nseg, int32_t M, const double* __restrict__ agg,
+                                 const double* __restrict__ seg_dec, const double* __restrict__ seg_span,
+                                 double* __restrict__ carry_seg, double* __restrict__ gagg) {
+    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int32_t ngr = (nseg + HK_SG - 1) / HK_SG;
+    if (gid >= (int64_t)ngr * M) return;
+    const int32_t g = (int32_t)(gid / M), q = (int32_t)(gid % M);
+    const int32_t s0 = g * HK_SG, s1 = s0 + HK_SG < nseg ? s0 + HK_SG : nseg;
+    double K = 0.0, J = 0.0;
+    for (int32_t s = s0; s < s1; ++s) {
+        const double* row = agg + (int64_t)s * 2 * M;
+        double* o = carry_seg + (int64_t)s * 2 * M;
+        o[q] = K;
+        o[M + q] = J;
+        const double ex = seg_dec[s], D = seg_span[s];
+        const double k0 = K;
+        K = __builtin_fma(ex, k0, row[q]);
+        J = __builtin_fma(ex, __builtin_fma(D, k0, J), row[M + q]);
+    }
+    gagg[(int64_t)g * 2 * M + q] = K;
+    gagg[(int64_t)g * 2 * M + M + q] = J;
+}
+
+// gdec[g], gspan[g]: decay and span of group g (one thread per group)
+__global__ void large_scan_gdec(int32_t nseg, const double* __restrict__ seg_span, const float* __restrict__ beta,
+                                double* __restrict__ gspan, double* __restrict__ gdec) {
+    const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t ngr = (nseg + HK_SG - 1) / HK_SG;
+    if (g >= ngr) return;
+    const int32_t s0 = g * HK_SG, s1 = s0 + HK_SG < nseg ? s0 + HK_SG : nseg;
+    double D = 0.0;
+    for (int32_t s = s0; s < s1; ++s) D += seg_span[s];
+    gspan[g] = D;
+    gdec[g] = exp(-(double)beta[0] * D);
+}
+
+__global__ void large_scan_groups(int32_t nseg, int32_t M, const double* __restrict__ gagg,
+                                  const double* __restrict__ gspan, const double* __restrict__ gdec,
+                                  double* __restrict__ gcarry, double* __restrict__ carry) {
     const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= M) return;
-    const double bet = (double)beta[0];
+    const int32_t ngr = (nseg + HK_SG - 1) / HK_SG;
     double K = carry[q], J = carry[M + q];
-    double tref = c0 > 0 ? t[c0 - 1] : t[c0];
-    for (int32_t s = 0; s < nseg; ++s) {
-        double* row = agg + (int64_t)s * 2 * M;
-        const double aK = row[q], aJ = row[M + q];
-        row[q] = K;
-        row[M + q] = J;
-        const double te = seg_tend[s];
-        const double D = te - tref;
-        const double ex = exp(-bet * D);
+    for (int32_t g = 0; g < ngr; ++g) {
+        gcarry[(int64_t)g * 2 * M + q] = K;
+        gcarry[(int64_t)g * 2 * M + M + q] = J;
+        const double ex = gdec[g], D = gspan[g];
         const double k0 = K;
-        K = __builtin_fma(ex, k0, aK);
-        J = __builtin_fma(ex, __builtin_fma(D, k0, J), aJ);
-        tref = te;
+        K = __builtin_fma(ex, k0, gagg[(int64_t)g * 2 * M + q]);
+        J = __builtin_fma(ex, __builtin_fma(D, k0, J), gagg[(int64_t)g * 2 * M + M + q]);
     }
     carry[q] = K;
     carry[M + q] = J;
+}
+
+__global__ void large_scan_apply(int32_t nseg, int32_t M, const double* __restrict__ seg_span,
+                                 const float* __restrict__ beta, const double* __restrict__ gcarry,
+                                 double* __restrict__ carry_seg) {
+    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)nseg * M) return;
+    const int32_t s = (int32_t)(gid / M), q = (int32_t)(gid % M);
+    const int32_t g = s / HK_SG;
+    double D = 0.0;
+    for (int32_t r = g * HK_SG; r < s; ++r) D += seg_span[r];
+    const double ex = exp(-(double)beta[0] * D);
+    const double Kc = gcarry[(int64_t)g * 2 * M + q], Jc = gcarry[(int64_t)g * 2 * M + M + q];
+    double* o = carry_seg + (int64_t)s * 2 * M;
+    const double Kl = o[q], Jl = o[M + q];
+    o[q] = __builtin_fma(ex, Kc, Kl);
+    o[M + q] = __builtin_fma(ex, __builtin_fma(D, Kc, Jc), Jl);
 }
 
 // ------------------------------------------------------------------ forward
@@ -161,22 +247,19 @@ template <bool GRAD, bool INTENS>
 __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int32_t M, double T,
                                                     const double* __restrict__ t, const int32_t* __restrict__ marks,
                                                     const float* __restrict__ mu, const float* __restrict__ beta,
-                                                    const int32_t* __restrict__ csr_ptr,
+                                                    const int4* __restrict__ node_info,
                                                     const int32_t* __restrict__ csr_col,
                                                     const float* __restrict__ csr_val,
-                                                    const float* __restrict__ colsum,
                                                     const double* __restrict__ carry_seg,
                                                     double* __restrict__ seg_part,
-                                                    int32_t* __restrict__ ev_m, float* __restrict__ ev_c,
-                                                    float* __restrict__ ev_b, float* __restrict__ ev_w,
-                                                    float* __restrict__ ev_ct, float* __restrict__ batch_rho,
-                                                    int32_t* __restrict__ batch_wide,
+                                                    int4* __restrict__ ev_rec, float* __restrict__ ev_ct,
+                                                    int2* __restrict__ batch_info,
                                                     float* __restrict__ lambda_out) {
     extern __shared__ double lds[];
-    double* rtau = lds;                                   // [M]
-    uint64_t* rmask = (uint64_t*)(lds + M);               // [M]
-    float* rK = (float*)(lds + 2 * M);                    // [M]
-    float* rJ = rK + M;                                   // [M]
+    double* rtau = lds;                                   // [M] time of the record
+    uint64_t* rmask = (uint64_t*)(lds + M);               // [M] lanes of this batch with mark q
+    float* rK = (float*)(lds + 2 * M);                    // [M] K_q at rtau (event included)
+    float* rJ = rK + M;                                   // [M] J_q at rtau
     __shared__ double tb[64];
     const int32_t s = blockIdx.x;
     const int lane = threadIdx.x;
@@ -194,83 +277,102 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
     }
     __syncthreads();
     double logsum = 0.0, comp = 0.0, Esum = 0.0, gb = 0.0;
+    // software pipeline: the next batch's times and marks are loaded while
+    // the current one is processed (clamped indices keep the loads valid)
+    double t_nx = t[a + lane < b ? a + lane : b - 1];
+    int m_nx = marks[a + lane < b ? a + lane : b - 1];
     for (int64_t base = a; base < b; base += 64) {
         const int64_t i = base + lane;
         const bool valid = i < b;
-        const double ti = valid ? t[i] : 0.0;
-        const int mi = valid ? clamp_mark(marks[i], M) : 0;
+        const double ti = valid ? t_nx : 0.0;
+        const int mi = valid ? clamp_mark(m_nx, M) : 0;
+        {
+            const int64_t j = base + 64 + lane;
+            const int64_t jc = j < b ? j : b - 1;
+            t_nx = t[jc];
+            m_nx = marks[jc];
+        }
+        const int4 ni = node_info[mi];
         tb[lane] = ti;
         if (valid) atomicOr((unsigned long long*)&rmask[mi], 1ull << lane);
         __syncthreads();
-        float R = 0.0f, Dd = 0.0f;
+        float R = 0.0f, Dd = 0.0f, lam = 1.0f, w = 0.0f, em1 = 0.0f;
         if (valid) {
             const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-            const int32_t k0 = csr_ptr[mi], k1 = csr_ptr[mi + 1];
-            for (int32_t k = k0; k < k1; ++k) {
-                const int32_t q = csr_col[k];
-                const float av = csr_val[k];
-                const double d = ti - rtau[q];
-                const float e = exp_f64arg(-bet * d);
-                const float kq = rK[q];
-                float Kv = e * kq;
-                float Jv = GRAD ? e * __builtin_fmaf((float)d, kq, rJ[q]) : 0.0f;
-                uint64_t bits = rmask[q] & below;
-                while (bits) {
-                    const int j = __builtin_ctzll(bits);
-                    bits &= bits - 1;
-                    const double dj = ti - tb[j];
-                    const float ej = exp_f64arg(-bet * dj);
-                    Kv += ej;
-                    if (GRAD) Jv = __builtin_fmaf((float)dj, ej, Jv);
+            const int32_t k0 = ni.x, k1 = ni.y;
+            for (int32_t kb = k0; kb < k1; kb += 8) {
+                int32_t qv[8];
+                float av[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int32_t k = kb + j;
+                    qv[j] = k < k1 ? csr_col[k] : -1;
+                    av[j] = k < k1 ? csr_val[k] : 0.0f;
                 }
-                R = __builtin_fmaf(av, Kv, R);
-                if (GRAD) Dd = __builtin_fmaf(av, Jv, Dd);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    if (qv[j] < 0) continue;
+                    const int32_t q = qv[j];
+                    const double d = ti - rtau[q];
+                    const float e = exp_f64arg(-bet * d);
+                    const float kq = rK[q];
+                    float Kv = e * kq;
+                    float Jv = GRAD ? e * __builtin_fmaf((float)d, kq, rJ[q]) : 0.0f;
+                    uint64_t bits = rmask[q] & below;
+                    while (bits) {
+                        const int jj = __builtin_ctzll(bits);
+                        bits &= bits - 1;
+                        const double dj = ti - tb[jj];
+                        const float ej = exp_f64arg(-bet * dj);
+                        Kv += ej;
+                        if (GRAD) Jv = __builtin_fmaf((float)dj, ej, Jv);
+                    }
+                    R = __builtin_fmaf(av[j], Kv, R);
+                    if (GRAD) Dd = __builtin_fmaf(av[j], Jv, Dd);
+                }
             }
-            const float lam = __builtin_fmaf(betf, R, mu[mi]);
+            lam = __builtin_fmaf(betf, R, __int_as_float(ni.z));
             if (INTENS) lambda_out[i] = lam;
             logsum += (double)__logf(lam);
             const double x = bet * (T - ti);
-            const float em1 = -expm1f(-(float)x);   // 1 - e^{-x}
-            const float cs_m = colsum[mi];
+            em1 = -expm1f(-(float)x);   // 1 - e^{-x}
+            const float cs_m = __int_as_float(ni.w);
             comp += (double)cs_m * (double)em1;
             if (GRAD) {
-                const float w = 1.0f / lam;
+                w = 1.0f / lam;
                 gb += (double)w * ((double)R - bet * (double)Dd);
                 const float ex = exp_f64arg(-x);
                 Esum += (double)cs_m * (T - ti) * (double)ex;
-                const int64_t ii = i - c0;
-                ev_m[ii] = mi;
-                ev_w[ii] = w;
-                ev_ct[ii] = em1;
             }
         }
         if (GRAD) {
-            // dense-kernel coefficients for this batch, anchored at its first event
+            // dense-kernel record of this event, anchored at the batch's first event
             const int64_t last = base + 63 < b - 1 ? base + 63 : b - 1;
             const double tau = tb[0];
             const bool wide = bet * (tb[last - base] - tau) > HK_WIDE;
             if (valid) {
                 const int64_t ii = i - c0;
-                const float w = ev_w[ii];
+                float cc, bb;
                 if (!wide) {
                     const double xl = bet * (ti - tau);
-                    ev_c[ii] = betf * w * exp_f64arg(-xl);
-                    ev_b[ii] = exp_f64arg(xl);
+                    cc = betf * w * exp_f64arg(-xl);
+                    bb = exp_f64arg(xl);
                 } else {
-                    ev_c[ii] = betf * w;
-                    ev_b[ii] = lane == 0 ? 1.0f : exp_f64arg(-bet * (ti - tb[lane - 1]));
+                    cc = betf * w;
+                    bb = lane == 0 ? 1.0f : exp_f64arg(-bet * (ti - tb[lane - 1]));
                 }
+                ev_rec[ii] = make_int4(mi, __float_as_int(cc), __float_as_int(bb), __float_as_int(w));
+                ev_ct[ii] = em1;
             }
             if (lane == 0) {
                 const int64_t bi = (base - c0) / 64;
-                batch_wide[bi] = wide ? 1 : 0;
                 float rho = 1.0f;
                 if (base - 64 >= c0) {
                     bool pw;
                     const double fe = batch_frame_end(t, base - 64, c1, bet, &pw);
                     rho = exp_f64arg(-bet * (tau - fe));
                 }
-                batch_rho[bi] = rho;
+                batch_info[bi] = make_int2(__float_as_int(rho), wide ? 1 : 0);
             }
         }
         __syncthreads();
@@ -311,120 +413,236 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
     }
 }
 
-// acc[k] += sum over segments of seg_part[s][k], segments in order
-__global__ void large_chunk_acc(int32_t nseg, const double* __restrict__ seg_part, double* __restrict__ acc) {
-    const int k = threadIdx.x;
-    if (k >= 4) return;
-    double v = 0.0;
-    for (int32_t s = 0; s < nseg; ++s) v += seg_part[(int64_t)s * 4 + k];
-    acc[k] += v;
+// acc[k] += sum over segments of seg_part[s][k]; fixed-order tree (deterministic)
+__global__ __launch_bounds__(256) void large_chunk_acc(int32_t nseg, const double* __restrict__ seg_part,
+                                                       double* __restrict__ acc) {
+    __shared__ double sh[256];
+    for (int k = 0; k < 4; ++k) {
+        double v = 0.0;
+        for (int32_t s = threadIdx.x; s < nseg; s += 256) v += seg_part[(int64_t)s * 4 + k];
+        const double tot = block_sum_d<256>(v, sh);
+        if (threadIdx.x == 0) acc[k] += tot;
+    }
 }
 
 // ------------------------------------------------------------------ dense dL/dalpha
 // block = (row block rb, column slab sb, event range er); one wave.
-// LDS G[64][64] float64 accumulates beta * sum_i w_i K_q(t_i) for rows of the
-// block; lane c owns column s0 + c and its anchored state Khat.
+// LDS G[64][64] float64 accumulates sum_i c_i Khat_q for the rows of the
+// block (c_i = beta w_i times the batch anchor factor); lane c owns column
+// s0 + c and its anchored state Khat (float64).  The blocks of one event
+// range are placed on one XCD (blockIdx % 8) so that the range's records stay
+// in that XCD's L2.
+__device__ __forceinline__ int rdl(int v, int k) { return __builtin_amdgcn_readlane(v, k); }
+__device__ __forceinline__ float rdlf(float v, int k) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+
+// A vector register holding 0 that the compiler cannot prove uniform: an
+// index offset by it stays a per-lane (vector memory) load, which is waited
+// for in order with the other prefetched loads, instead of a scalar load.
+__device__ __forceinline__ int opaque_zero() {
+    int z;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+    return z;
+}
+
+// Number of 64-event batches whose loads are in flight ahead of the batch
+// being processed; the ring is indexed with compile-time slots only.
+#define HK_PD 4
+
 __global__ __launch_bounds__(64) void large_dense(int64_t c0, int64_t c1, int32_t M, int32_t NB, int32_t ER,
                                                   int32_t segs_per_range, const double* __restrict__ t,
                                                   const float* __restrict__ beta,
                                                   const double* __restrict__ carry_seg,
-                                                  const int32_t* __restrict__ ev_m, const float* __restrict__ ev_c,
-                                                  const float* __restrict__ ev_b, const float* __restrict__ ev_w,
-                                                  const float* __restrict__ ev_ct, const float* __restrict__ batch_rho,
-                                                  const int32_t* __restrict__ batch_wide,
+                                                  const int4* __restrict__ ev_rec, const float* __restrict__ ev_ct,
+                                                  const int2* __restrict__ batch_info,
                                                   double* __restrict__ gpart, double* __restrict__ spart,
                                                   double* __restrict__ cpart) {
     __shared__ double G[HK_RB * HK_SLAB];
+    __shared__ double KhL[HK_SLAB], SL[HK_SLAB], CL[HK_SLAB];
     const int lane = threadIdx.x;
+    KhL[lane] = 0.0;
+    SL[lane] = 0.0;
+    CL[lane] = 0.0;
     const int32_t blk = blockIdx.x;
-    const int32_t er = blk % ER;
-    const int32_t sb = (blk / ER) % NB;
-    const int32_t rb = blk / (ER * NB);
+    const int32_t nbb = NB * NB;
+    int32_t er, local;
+    if (ER >= 8) {
+        const int32_t slot = blk >> 3;
+        er = (slot / nbb) * 8 + (blk & 7);
+        local = slot % nbb;
+    } else {
+        // 8 / ER XCDs share one event range
+        const int32_t per = 8 / ER, x = blk & 7;
+        er = x / per;
+        local = (blk >> 3) * per + x % per;
+        if (local >= nbb) return;
+    }
+    if (er >= ER) return;
+    const int32_t sb = local % NB;
+    const int32_t rb = local / NB;
     const int32_t r0 = rb * HK_RB, s0 = sb * HK_SLAB;
     const int64_t a = c0 + (int64_t)er * segs_per_range * HK_SEG;
     if (a >= c1) return;
     const int64_t bnd = a + (int64_t)segs_per_range * HK_SEG;
     const int64_t b = bnd < c1 ? bnd : c1;
     const int32_t col = s0 + lane;
-    // load this block's accumulators (accumulated over chunks)
     double* gp = gpart + (int64_t)er * M * M;
-    for (int r = 0; r < HK_RB; ++r) {
-        const int32_t row = r0 + r;
-        G[r * HK_SLAB + lane] = (row < M && col < M) ? gp[(int64_t)row * M + col] : 0.0;
+    {
+        // branch-free block load (all loads in flight together); out-of-range
+        // rows/columns read a clamped valid address and are zeroed
+        const int32_t cc = col < M ? col : M - 1;
+        for (int rg = 0; rg < HK_RB; rg += 16) {
+            double v[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int32_t row = r0 + rg + j;
+                const int32_t rr = row < M ? row : M - 1;
+                v[j] = gp[(int64_t)rr * M + cc];
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int32_t row = r0 + rg + j;
+                G[(rg + j) * HK_SLAB + lane] = (row < M && col < M) ? v[j] : 0.0;
+            }
+        }
     }
     const double bet = (double)beta[0];
-    // carry-in at the event before the range, moved to the first batch frame
     const int32_t seg = (int32_t)((a - c0) / HK_SEG);
     const double tref = a > 0 ? t[a - 1] : t[a];
     double Kh = col < M ? carry_seg[(int64_t)seg * 2 * M + col] : 0.0;
     Kh *= (double)exp_f64arg(-bet * (t[a] - tref));
     double Sacc = 0.0, Cacc = 0.0;
     const bool diag_owner = rb == 0;
-    __syncthreads();
-    for (int64_t base = a; base < b; base += 64) {
-        const int64_t bi = (base - c0) / 64;
-        const int nb = (int)(b - base < 64 ? b - base : 64);
-        const int64_t ii = base - c0 + lane;
-        const int mi = lane < nb ? ev_m[ii] : -1;
-        const float ci = lane < nb ? ev_c[ii] : 0.0f;
-        const float bi_ = lane < nb ? ev_b[ii] : 0.0f;
-        const float wi = lane < nb ? ev_w[ii] : 0.0f;
-        const float cti = lane < nb ? ev_ct[ii] : 0.0f;
-        const int wide = uniform(batch_wide[bi]);
-        if (base != a) Kh *= (double)batch_rho[bi];
+    // Every operand of a batch is read with a clamped (always valid) index,
+    // HK_PD batches ahead, into a ring of registers; past the end of the range
+    // the ring is refilled with the last batch and never used.
+    const int64_t last_ii = b - 1 - c0;
+    const int zv = opaque_zero();
+    auto ld_rec = [&](int64_t base_) -> int4 {
+        const int64_t ii = base_ - c0 + lane;
+        return ev_rec[ii < last_ii ? ii : last_ii];
+    };
+    // only row block 0 uses the compensator terms; the others read one fixed
+    // (cached) word so that the load stays unconditional
+    auto ld_ct = [&](int64_t base_) -> float {
+        const int64_t ii = base_ - c0 + lane;
+        const int64_t ic = diag_owner ? (ii < last_ii ? ii : last_ii) : 0;
+        return ev_ct[ic];
+    };
+    auto ld_inf = [&](int64_t base_) -> int2 { return batch_info[(base_ - c0) / 64 + zv]; };
+    int4 rq[HK_PD];
+    float cq[HK_PD];
+    int2 iq[HK_PD];
+#pragma unroll
+    for (int s = 0; s < HK_PD; ++s) {
+        const int64_t bb = a + 64 * s;
+        const int64_t bc = bb < b ? bb : a;
+        rq[s] = ld_rec(bc);
+        cq[s] = ld_ct(bc);
+        iq[s] = ld_inf(bc);
+    }
+    // One 64-event batch.  Own rows take c_k times Khat as it stands at the
+    // batch start (one ds_add_f64 row update per own event), plus, for every
+    // slab event j earlier in the batch, c_k b_j at (m_k, m_j) (one masked
+    // ds_add_f64 over those lanes): together these are c_k times Khat just
+    // before event k.  The slab events then advance Khat in one vector step
+    // (scatter-add by column into LDS, read back by each column's lane), and
+    // row block 0 accumulates the per-column sums of w and of the compensator
+    // terms the same way.  Wide batches (each event its own anchor) fall back
+    // to a per-event walk.
+    auto batch = [&](const int64_t bb, int4 cur, float ctc, const int2 inf) {
+        if (bb + lane >= b) { cur.x = -1; ctc = 0.0f; }
+        const int wide = uniform(inf.y);
+        if (bb != a) Kh *= (double)__int_as_float(uniform(inf.x));
+        const int mi = cur.x;
+        const float ci = __int_as_float(cur.y);
+        const float bi_ = __int_as_float(cur.z);
+        const float wi = __int_as_float(cur.w);
         const bool own = mi >= r0 && mi < r0 + HK_RB;
         const bool sl = mi >= s0 && mi < s0 + HK_SLAB;
+        const int colj = sl ? mi - s0 : 0;
         if (!wide) {
-            uint64_t mo = __ballot(own), ms = __ballot(sl);
-            uint64_t all = mo | ms;
-            while (all) {
-                const int k = __builtin_ctzll(all);
-                all &= all - 1;
-                const int mk = __shfl(mi, k, 64);
-                if ((mo >> k) & 1ull) {
-                    const double ck = (double)__shfl(ci, k, 64);
-                    atomicAdd(&G[(mk - r0) * HK_SLAB + lane], ck * Kh);
-                }
-                if ((ms >> k) & 1ull) {
-                    const float bk = __shfl(bi_, k, 64);
-                    const float wk = __shfl(wi, k, 64);
-                    const float ctk = __shfl(cti, k, 64);
-                    if (lane == mk - s0) {
-                        Kh += (double)bk;
-                        Sacc += (double)wk;
-                        Cacc += (double)ctk;
+            uint64_t mo = __ballot(own);
+            const uint64_t ms = __ballot(sl);
+            const double bj = (double)bi_;
+            while (mo) {
+                const int k = __builtin_ctzll(mo);
+                mo &= mo - 1;
+                const int rowoff = (rdl(mi, k) - r0) * HK_SLAB;
+                const double ck = (double)rdlf(ci, k);
+                atomicAdd(&G[rowoff + lane], ck * Kh);
+                if (sl && lane < k) atomicAdd(&G[rowoff + colj], ck * bj);
+            }
+            if (ms) {
+                if (sl) {
+                    atomicAdd(&KhL[colj], bj);
+                    if (diag_owner) {
+                        atomicAdd(&SL[colj], (double)wi);
+                        atomicAdd(&CL[colj], (double)ctc);
                     }
                 }
+                __syncthreads();
+                Kh += KhL[lane];
+                KhL[lane] = 0.0;
             }
         } else {
+            const int nb = (int)(b - bb < 64 ? b - bb : 64);
             for (int k = 0; k < nb; ++k) {
-                const float rk = __shfl(bi_, k, 64);
+                const float rk = rdlf(bi_, k);
                 if (k > 0) Kh *= (double)rk;
-                const int mk = __shfl(mi, k, 64);
-                const bool ok = mk >= r0 && mk < r0 + HK_RB;
-                const bool sk = mk >= s0 && mk < s0 + HK_SLAB;
-                if (ok) {
-                    const double ck = (double)__shfl(ci, k, 64);
+                const int mk = rdl(mi, k);
+                if (mk >= r0 && mk < r0 + HK_RB) {
+                    const double ck = (double)rdlf(ci, k);
                     atomicAdd(&G[(mk - r0) * HK_SLAB + lane], ck * Kh);
                 }
-                const float wk = __shfl(wi, k, 64);
-                const float ctk = __shfl(cti, k, 64);
-                if (sk && lane == mk - s0) {
-                    Kh += 1.0;
-                    Sacc += (double)wk;
-                    Cacc += (double)ctk;
+                if (mk >= s0 && mk < s0 + HK_SLAB) {
+                    if (diag_owner) {
+                        const float wk = rdlf(wi, k);
+                        const float ctk = rdlf(ctc, k);
+                        if (lane == mk - s0) { Sacc += (double)wk; Cacc += (double)ctk; }
+                    }
+                    if (lane == mk - s0) Kh += 1.0;
                 }
             }
         }
+    };
+    __syncthreads();
+    int64_t base = a;
+    // full groups of HK_PD batches: no early exit inside, so the loads of
+    // every slot are issued in the same order on every path to the back-edge
+    // and each wait covers only its own slot
+    for (; base + 64 * (HK_PD - 1) < b; base += 64 * HK_PD) {
+#pragma unroll
+        for (int s = 0; s < HK_PD; ++s) {
+            const int64_t bb = base + 64 * s;
+            batch(bb, rq[s], cq[s], iq[s]);
+            // refill the slot only once its batch is consumed, so the new
+            // loads can land in the same registers (no copy that would wait)
+            const int64_t nf = bb + 64 * HK_PD;
+            const int64_t nc = nf < b ? nf : bb;
+            rq[s] = ld_rec(nc);
+            cq[s] = ld_ct(nc);
+            iq[s] = ld_inf(nc);
+        }
+    }
+    // tail: fewer than HK_PD batches left, already in the ring
+#pragma unroll
+    for (int s = 0; s < HK_PD - 1; ++s) {
+        const int64_t bb = base + 64 * s;
+        if (bb < b) batch(bb, rq[s], cq[s], iq[s]);
     }
     __syncthreads();
-    for (int r = 0; r < HK_RB; ++r) {
-        const int32_t row = r0 + r;
-        if (row < M && col < M) gp[(int64_t)row * M + col] = G[r * HK_SLAB + lane];
+    if (col < M) {
+#pragma unroll 16
+        for (int r = 0; r < HK_RB; ++r) {
+            const int32_t row = r0 + r;
+            if (row < M) gp[(int64_t)row * M + col] = G[r * HK_SLAB + lane];
+        }
     }
     if (diag_owner && col < M) {
-        spart[(int64_t)er * M + col] += Sacc;
-        cpart[(int64_t)er * M + col] += Cacc;
+        spart[(int64_t)er * M + col] += Sacc + SL[lane];
+        cpart[(int64_t)er * M + col] += Cacc + CL[lane];
     }
 }
 
@@ -470,9 +688,18 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
     A.nchunks = (A.n + A.CH - 1) / A.CH;
     A.nseg = (int32_t)((A.CH + HK_SEG - 1) / HK_SEG);
     A.NB = (A.M + 63) / 64;
-    int32_t er = (int32_t)((2048 + A.NB * A.NB - 1) / (A.NB * A.NB));
-    if (er < 1) er = 1;
-    if (er > A.nseg) er = A.nseg;
+    // event ranges per chunk for the dense kernel: a power of two so that the
+    // ranges map onto the 8 XCDs evenly; about 2048 blocks in total unless
+    // HAWKES_DENSE_ER (a power of two) overrides it
+    const int64_t nbb = (int64_t)A.NB * A.NB;
+    const int64_t want = (2048 + nbb - 1) / nbb;
+    int32_t er = 1;
+    while (er < want) er <<= 1;
+    if (const char* e = getenv("HAWKES_DENSE_ER")) {
+        const int v = atoi(e);
+        if (v >= 1 && v <= 4096 && (v & (v - 1)) == 0) er = v;
+    }
+    while (er > A.nseg && er > 1) er >>= 1;
     A.ER = er;
     A.grad = grad;
     const int64_t M = A.M, MM = M * M;
@@ -482,20 +709,24 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
     A.csr_val = c.take<float>(MM);
     A.colsum = c.take<float>(M);
     A.agg = c.take<double>((size_t)A.nseg * 2 * M);
-    A.seg_tend = c.take<double>(A.nseg);
+    A.seg_span = c.take<double>(A.nseg);
+    A.seg_dec = c.take<double>(A.nseg);
+    A.ngr = (A.nseg + HK_SG - 1) / HK_SG;
+    A.gagg = c.take<double>((size_t)A.ngr * 2 * M);
+    A.gcarry = c.take<double>((size_t)A.ngr * 2 * M);
+    A.gspan = c.take<double>(A.ngr);
+    A.gdec = c.take<double>(A.ngr);
+    A.node_info = c.take<int4>(M);
+    A.carry_seg = c.take<double>((size_t)A.nseg * 2 * M);
     A.carry = c.take<double>(2 * M);
     A.carry_t = c.take<double>(1);
     A.seg_part = c.take<double>((size_t)A.nseg * 4);
     A.acc = c.take<double>(4);
     A.ll_scratch = c.take<double>(1);
     if (grad) {
-        A.ev_m = c.take<int32_t>(A.CH);
-        A.ev_c = c.take<float>(A.CH);
-        A.ev_b = c.take<float>(A.CH);
-        A.ev_w = c.take<float>(A.CH);
+        A.ev_rec = c.take<int4>(A.CH);
         A.ev_ct = c.take<float>(A.CH);
-        A.batch_rho = c.take<float>(A.CH / 64 + 1);
-        A.batch_wide = c.take<int32_t>(A.CH / 64 + 1);
+        A.batch_info = c.take<int2>(A.CH / 64 + 1);
         A.gpart = c.take<double>((size_t)A.ER * MM);
         A.spart = c.take<double>((size_t)A.ER * M);
         A.cpart_ = c.take<double>((size_t)A.ER * M);
@@ -518,12 +749,14 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
         hipLaunchKernelGGL(fill_d, dim3(64), dim3(256), 0, st, A.spart, (int64_t)A.ER * M, 0.0);
         hipLaunchKernelGGL(fill_d, dim3(64), dim3(256), 0, st, A.cpart_, (int64_t)A.ER * M, 0.0);
     }
-    hipLaunchKernelGGL(large_colsum_count, dim3(gM), dim3(256), 0, st, M, A.alpha, A.colsum, A.csr_ptr);
+    hipLaunchKernelGGL(large_colsum, dim3(gM), dim3(256), 0, st, M, A.alpha, A.colsum);
+    hipLaunchKernelGGL(large_rowcount, dim3(M), dim3(64), 0, st, M, A.alpha, A.csr_ptr);
     hipLaunchKernelGGL(large_csr_scan, dim3(1), dim3(1024), 0, st, M, A.csr_ptr);
-    hipLaunchKernelGGL(large_csr_fill, dim3(gM), dim3(256), 0, st, M, A.alpha, A.csr_ptr, A.csr_col, A.csr_val);
+    hipLaunchKernelGGL(large_csr_fill, dim3(M), dim3(64), 0, st, M, A.alpha, A.csr_ptr, A.csr_col, A.csr_val);
+    hipLaunchKernelGGL(large_node_info, dim3(gM), dim3(256), 0, st, M, A.csr_ptr, A.mu, A.colsum, A.node_info);
     const size_t lds_agg = (size_t)2 * M * sizeof(double);
     const size_t lds_fwd = (size_t)M * (sizeof(double) + sizeof(uint64_t) + 2 * sizeof(float));
-    if (lds_agg > 160 * 1024 || lds_fwd > 150 * 1024) return HAWKES_EUNSUPPORTED;
+    if (lds_agg > 64 * 1024 || lds_fwd > 64 * 1024) return HAWKES_EUNSUPPORTED;
     for (int64_t ch = 0; ch < A.nchunks; ++ch) {
         const int64_t c0 = ch * A.CH;
         const int64_t c1 = c0 + A.CH < A.n ? c0 + A.CH : A.n;
@@ -531,38 +764,49 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
         {
             TimedScope ts(2, st);
             hipLaunchKernelGGL(large_seg_agg, dim3(nseg), dim3(64), lds_agg, st, c0, c1, M, A.t, A.marks, A.beta,
-                               A.agg, A.seg_tend);
+                               A.agg, A.seg_span, A.seg_dec);
         }
         {
             TimedScope ts(3, st);
-            hipLaunchKernelGGL(large_seg_scan, dim3(gM), dim3(256), 0, st, c0, nseg, M, A.t, A.beta, A.agg,
-                               A.seg_tend, A.carry);
+            const int32_t ngr = (nseg + HK_SG - 1) / HK_SG;
+            const int64_t nloc = (int64_t)ngr * M, napp = (int64_t)nseg * M;
+            hipLaunchKernelGGL(large_scan_local, dim3((unsigned)((nloc + 255) / 256)), dim3(256), 0, st, nseg, M,
+                               A.agg, A.seg_dec, A.seg_span, A.carry_seg, A.gagg);
+            hipLaunchKernelGGL(large_scan_gdec, dim3((unsigned)((ngr + 255) / 256)), dim3(256), 0, st, nseg,
+                               A.seg_span, A.beta, A.gspan, A.gdec);
+            hipLaunchKernelGGL(large_scan_groups, dim3(gM), dim3(256), 0, st, nseg, M, A.gagg, A.gspan, A.gdec,
+                               A.gcarry, A.carry);
+            hipLaunchKernelGGL(large_scan_apply, dim3((unsigned)((napp + 255) / 256)), dim3(256), 0, st, nseg, M,
+                               A.seg_span, A.beta, A.gcarry, A.carry_seg);
         }
-        TimedScope* tf = new TimedScope(1, st);
-        if (A.grad)
-            hipLaunchKernelGGL((large_forward<true, false>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1, M, A.T,
-                               A.t, A.marks, A.mu, A.beta, A.csr_ptr, A.csr_col, A.csr_val, A.colsum, A.agg,
-                               A.seg_part, A.ev_m, A.ev_c, A.ev_b, A.ev_w, A.ev_ct, A.batch_rho, A.batch_wide,
-                               (float*)nullptr);
-        else if (A.lambda_out)
-            hipLaunchKernelGGL((large_forward<false, true>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1, M, A.T,
-                               A.t, A.marks, A.mu, A.beta, A.csr_ptr, A.csr_col, A.csr_val, A.colsum, A.agg,
-                               A.seg_part, A.ev_m, A.ev_c, A.ev_b, A.ev_w, A.ev_ct, A.batch_rho, A.batch_wide,
-                               A.lambda_out);
-        else
-            hipLaunchKernelGGL((large_forward<false, false>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1, M, A.T,
-                               A.t, A.marks, A.mu, A.beta, A.csr_ptr, A.csr_col, A.csr_val, A.colsum, A.agg,
-                               A.seg_part, A.ev_m, A.ev_c, A.ev_b, A.ev_w, A.ev_ct, A.batch_rho, A.batch_wide,
-                               (float*)nullptr);
-        delete tf;
-        hipLaunchKernelGGL(large_chunk_acc, dim3(1), dim3(64), 0, st, nseg, A.seg_part, A.acc);
+        {
+            TimedScope ts(1, st);
+            if (A.grad)
+                hipLaunchKernelGGL((large_forward<true, false>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1, M,
+                                   A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
+                                   A.carry_seg, A.seg_part, A.ev_rec, A.ev_ct, A.batch_info,
+                                   (float*)nullptr);
+            else if (A.lambda_out)
+                hipLaunchKernelGGL((large_forward<false, true>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1, M,
+                                   A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
+                                   A.carry_seg, A.seg_part, A.ev_rec, A.ev_ct, A.batch_info,
+                                   A.lambda_out);
+            else
+                hipLaunchKernelGGL((large_forward<false, false>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1, M,
+                                   A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
+                                   A.carry_seg, A.seg_part, A.ev_rec, A.ev_ct, A.batch_info,
+                                   (float*)nullptr);
+        }
+        hipLaunchKernelGGL(large_chunk_acc, dim3(1), dim3(256), 0, st, nseg, A.seg_part, A.acc);
         if (A.grad) {
-            int32_t spr = (nseg + A.ER - 1) / A.ER;
-            const unsigned nblk = (unsigned)(A.NB * A.NB * A.ER);
+            const int32_t spr = (nseg + A.ER - 1) / A.ER;
+            const int32_t nbb = A.NB * A.NB;
+            const unsigned nblk = A.ER >= 8 ? (unsigned)(nbb * ((A.ER + 7) / 8) * 8)
+                                            : (unsigned)(((nbb + 8 / A.ER - 1) / (8 / A.ER)) * 8);
             TimedScope ts(0, st);
             hipLaunchKernelGGL(large_dense, dim3(nblk), dim3(64), 0, st, c0, c1, M, A.NB, A.ER, spr, A.t, A.beta,
-                               A.agg, A.ev_m, A.ev_c, A.ev_b, A.ev_w, A.ev_ct, A.batch_rho, A.batch_wide,
-                               A.gpart, A.spart, A.cpart_);
+                               A.carry_seg, A.ev_rec, A.ev_ct, A.batch_info, A.gpart, A.spart,
+                               A.cpart_);
         }
     }
     const int64_t nfin = A.grad ? (MM > M ? MM : M) : 1;
