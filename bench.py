@@ -68,8 +68,8 @@ def rel(a, b):
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-events", type=int, default=3_000_000,
                     help="prefix length for the CPU oracle leg (about 10-15 s single-threaded)")
     ap.add_argument("--seq-events", type=int, default=20_000,
@@ -115,17 +115,25 @@ def main() -> int:
 
     H.timing_reset()
     H.timing_enable(True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     tw0 = time.perf_counter()
-    for _ in range(args.steps):
+    evs[0].record()
+    for i in range(args.steps):
         res = step()
+        evs[i + 1].record()
     torch.cuda.synchronize()
     tw1 = time.perf_counter()
     H.timing_enable(False)
     kt = H.timing_read()
     ms_per_step = (tw1 - tw0) * 1e3 / args.steps
     value = w.n / (ms_per_step / 1e3)
-    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, {value:.4e} events/s")
+    per = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps))
+    med = per[len(per) // 2] if len(per) % 2 else 0.5 * (per[len(per) // 2 - 1] + per[len(per) // 2])
+    step_stats = {"median_ms": round(med, 4), "min_ms": round(per[0], 4), "max_ms": round(per[-1], 4),
+                  "spread": round((per[-1] - per[0]) / med, 4), "events_per_s_at_median": w.n / (med / 1e3)}
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step (wall), median {med:.3f} ms, "
+        f"min {per[0]:.3f}, max {per[-1]:.3f}; {value:.4e} events/s")
 
     dense_ms, dense_n = kt["dense_dalpha"]
     src = source_hash("hk_large.hip", "hk_large.h", "hk_device.h")
@@ -149,7 +157,7 @@ def main() -> int:
            "vs_baseline": None, "dtype": "f32 state / f64 sums", "data": "synthetic",
            "config": {"workload": "c4: M=1000, N=1e7, alpha 1% dense rho=0.8, beta=1, chunks of 2^20",
                       "n_events": w.n, "n_nodes": w.M, "chunk_log2": args.chunk_log2},
-           "roofline": roofline, "kernels_ms_per_step": kernels}
+           "roofline": roofline, "step_device_time": step_stats, "kernels_ms_per_step": kernels}
 
     # sequential-recurrence GPU kernel on a prefix
     if not args.no_seq:
@@ -179,10 +187,31 @@ def main() -> int:
                                          f"FP64 sequential recurrence, {c_dt:.1f} s"}
         g = H.loglik_grad(t[:nc], m[:nc], mu, al, be, Tc, args.chunk_log2)
         torch.cuda.synchronize()
-        errs = {"loglik": abs(g[0].item() - ref[0]) / abs(ref[0]), "g_mu": rel(g[1].cpu().numpy(), ref[1]),
-                "g_alpha": rel(g[2].cpu().numpy(), ref[2][0]), "g_beta": rel(g[3].cpu().numpy(), ref[3])}
+        gg = [g[1].cpu().numpy(), g[2].cpu().numpy(), g[3].cpu().numpy()]
+        dif = [float(np.linalg.norm(np.ravel(gg[k]) - np.ravel(ref[k + 1]))) for k in range(3)]
+        scales = oracle.addend_scales(w.t[:nc], w.m[:nc], w.mu, w.alpha, w.beta, Tc, ref[1:])
+        errs = {"loglik": abs(g[0].item() - ref[0]) / abs(ref[0]),
+                "g_mu": rel(gg[0], ref[1]), "g_alpha": rel(gg[1], ref[2][0]), "g_beta": rel(gg[2], ref[3]),
+                "g_mu_addend_scaled": dif[0] / scales[0], "g_alpha_addend_scaled": dif[1] / scales[1],
+                "g_beta_addend_scaled": dif[2] / scales[2]}
         out["err_vs_oracle"] = {k: float(f"{v:.3e}") for k, v in errs.items()}
-        out["err_vs_oracle"]["sample"] = f"first {nc} events"
+        out["err_vs_oracle"]["sample"] = (f"first {nc} events at the generating parameters; plain normwise "
+                                          f"relative error per block, and the same error over the norm of the "
+                                          f"block's positive plus negative addends (the 1e-6 gate there)")
+        # the gate point for gradients: theta_pert = (1.25 mu, 0.8 alpha, 1.2 beta)
+        mu_p, al_p, be_p = (1.25 * w.mu).astype(np.float32), (0.8 * w.alpha).astype(np.float32), \
+            (1.2 * w.beta).astype(np.float32)
+        refp = oracle.forward(w.t[:nc], w.m[:nc], mu_p, al_p, be_p, Tc)
+        gp = H.loglik_grad(t[:nc], m[:nc], torch.as_tensor(mu_p, device=dev), torch.as_tensor(al_p, device=dev),
+                           torch.as_tensor(be_p, device=dev), Tc, args.chunk_log2)
+        torch.cuda.synchronize()
+        out["err_vs_oracle_theta_pert"] = {
+            "loglik": float(f"{abs(gp[0].item() - refp[0]) / abs(refp[0]):.3e}"),
+            "g_mu": float(f"{rel(gp[1].cpu().numpy(), refp[1]):.3e}"),
+            "g_alpha": float(f"{rel(gp[2].cpu().numpy(), refp[2][0]):.3e}"),
+            "g_beta": float(f"{rel(gp[3].cpu().numpy(), refp[3]):.3e}"),
+            "sample": f"first {nc} events at (1.25 mu, 0.8 alpha, 1.2 beta)"}
+        errs["theta_pert"] = out["err_vs_oracle_theta_pert"]
         log(f"CPU oracle: {nc / c_dt:.4e} events/s ({c_dt:.1f}s); errors {errs}")
 
     print(json.dumps(out), flush=True)

@@ -152,3 +152,32 @@ def intensity_at(t, m, mu, alpha, beta, idx):
     if rc != 0:
         raise ValueError("oracle_intensity_at rejected its arguments")
     return out
+
+
+def addend_scales(t, m, mu, alpha, beta, T, grads):
+    """Scales for the addend-scaled gradient error at the generating point.
+
+    Each gradient block is a difference of two nonnegative sums (eqs. 8-10):
+    dL/dmu_p = S_p - T, dL/dalpha_pq = G_pq - C_q, dL/dbeta = G_beta - E with
+    C_q = sum_{j: m_j = q} (1 - e^{-beta (T - t_j)}) and
+    E = sum_j colsum_{m_j} (T - t_j) e^{-beta (T - t_j)} (shared decay, one
+    kernel).  Given the oracle's gradients, the positive parts follow as
+    gradient + negative part; the returned scales are the norms of
+    |positive| + |negative| per block, so that error / scale measures the
+    error against the size of the addends rather than against their near-
+    cancelling difference."""
+    t = np.asarray(t, dtype=np.float64)
+    m = np.asarray(m, dtype=np.int64)
+    M = np.asarray(mu).shape[0]
+    a = np.asarray(alpha, dtype=np.float64).reshape(M, M)
+    b = float(np.asarray(beta, dtype=np.float64).ravel()[0])
+    g_mu, g_a, g_b = (np.asarray(x, dtype=np.float64) for x in grads)
+    g_a = g_a.reshape(M, M)
+    x = b * (T - t)
+    C = np.bincount(m, weights=-np.expm1(-x), minlength=M)
+    colsum = a.sum(axis=0)
+    E = float(np.sum(colsum[m] * (T - t) * np.exp(-x)))
+    s_mu = np.linalg.norm(np.abs(g_mu + T) + T)
+    s_a = np.linalg.norm(np.abs(g_a + C[None, :]) + C[None, :])
+    s_b = abs(float(np.ravel(g_b)[0]) + E) + E
+    return float(s_mu), float(s_a), float(s_b)

@@ -253,25 +253,42 @@ def make_config(c: int, n: int | None = None) -> Workload:
                     name=f"c{c}", meta={"per_target": c == 5})
 
 
+def _batched_one(args):
+    """One sequence of the batched workload, seeded by its own spawned child."""
+    child, lo, hi, M, max_len = args
+    rng = np.random.Generator(np.random.PCG64(child))
+    L = int(np.rint(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
+    if max_len is not None:
+        L = min(L, max_len)
+    mu, alpha = random_params(rng, M, 0.05, 0.5, 1.0, 0.6)
+    beta = rng.uniform(0.5, 2.0)
+    mu32, al32 = mu.astype(np.float32), alpha.astype(np.float32)
+    be32 = np.float32(beta)
+    t, m = _simulate_n(rng, mu32.astype(np.float64), al32.astype(np.float64),
+                       np.array([float(be32)]), L)
+    return t, m, mu32, al32.reshape(-1), be32, L
+
+
 def make_batched(S: int = 4096, lo: int = 100, hi: int = 100_000, M: int = 8,
-                 seed: int = 3002, max_len: int | None = None) -> BatchWorkload:
+                 seed: int = 3002, max_len: int | None = None,
+                 workers: int | None = None) -> BatchWorkload:
     """Workload c3: S independent sequences with their own parameters.
-    ``max_len`` caps every length (for quick tests) without changing seeds."""
+    ``max_len`` caps every length (for quick tests) without changing seeds.
+    Sequences are simulated in ``workers`` processes (default: up to 16 host
+    cores); each is seeded by its own child of SeedSequence(seed), so the
+    result does not depend on the worker count."""
     children = np.random.SeedSequence(seed).spawn(S)
-    ts, ms, mus, als, bes, Ts, lens = [], [], [], [], [], [], []
-    for s in range(S):
-        rng = np.random.Generator(np.random.PCG64(children[s]))
-        L = int(np.rint(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
-        if max_len is not None:
-            L = min(L, max_len)
-        mu, alpha = random_params(rng, M, 0.05, 0.5, 1.0, 0.6)
-        beta = rng.uniform(0.5, 2.0)
-        mu32, al32 = mu.astype(np.float32), alpha.astype(np.float32)
-        be32 = np.float32(beta)
-        t, m = _simulate_n(rng, mu32.astype(np.float64), al32.astype(np.float64),
-                           np.array([float(be32)]), L)
-        ts.append(t); ms.append(m); mus.append(mu32); als.append(al32.reshape(-1))
-        bes.append(be32); Ts.append(float(t[-1])); lens.append(L)
+    jobs = [(children[s], lo, hi, M, max_len) for s in range(S)]
+    if workers is None:
+        workers = int(os.environ.get("HAWKES_GEN_WORKERS", min(16, os.cpu_count() or 1)))
+    if workers > 1 and S >= 64:
+        import multiprocessing as mp
+        with mp.get_context("spawn").Pool(workers) as pool:
+            res = pool.map(_batched_one, jobs, chunksize=max(1, S // (8 * workers)))
+    else:
+        res = [_batched_one(j) for j in jobs]
+    ts, ms, mus, als, bes, lens = zip(*res)
+    Ts = [float(t[-1]) for t in ts]
     ev_off = np.zeros(S + 1, dtype=np.int64)
     ev_off[1:] = np.cumsum(lens)
     return BatchWorkload(ev_off, np.full(S, M, dtype=np.int32), np.array(Ts),

@@ -291,3 +291,30 @@ def test_intensity_at_matches_forward_logsum():
                             for k in range(2) for j in range(300))
     assert comp == pytest.approx(ec, rel=1e-12)
     assert L0 == L
+
+
+def test_addend_scales_match_direct_double_sums():
+    """The addend split used for errors at the generating point: positive
+    parts written out as O(N^2) double sums (eqs. 8-10) on a tiny case."""
+    from tests.helpers import rand_problem
+    t, m, mu, al, be, T = rand_problem(11, 60, 3)
+    L, g_mu, g_a, g_b = oracle.forward(t, m, mu, al, be, T)
+    lam = oracle.intensity_at(t, m, mu, al, be, np.arange(len(t)))
+    w = 1.0 / lam
+    b = float(be[0])
+    M = len(mu)
+    S = np.array([w[m == p].sum() for p in range(M)])
+    G = np.zeros((M, M))
+    Gb = 0.0
+    a = np.asarray(al, dtype=np.float64).reshape(M, M)
+    for i in range(len(t)):
+        for j in range(i):
+            e = np.exp(-b * (t[i] - t[j]))
+            G[m[i], m[j]] += b * w[i] * e
+            Gb += w[i] * a[m[i], m[j]] * e * (1.0 - b * (t[i] - t[j]))
+    C = np.array([np.sum(-np.expm1(-b * (T - t[m == q]))) for q in range(M)])
+    E = float(np.sum(a.sum(axis=0)[m] * (T - t) * np.exp(-b * (T - t))))
+    s_mu, s_a, s_b = oracle.addend_scales(t, m, mu, al, be, T, (g_mu, g_a, g_b))
+    assert abs(s_mu - np.linalg.norm(S + T)) <= 1e-12 * s_mu
+    assert abs(s_a - np.linalg.norm(G + C[None, :])) <= 1e-12 * s_a
+    assert abs(s_b - (abs(Gb) + E)) <= 1e-12 * s_b
