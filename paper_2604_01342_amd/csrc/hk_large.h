@@ -44,13 +44,34 @@ struct LargeArgs {
     float* ev_ct;         // [CH] 1 - e^{-beta (T - t_i)} for the dense kernel's row-block 0
     int2* batch_info;     // [CH/64 + 1] per 64-event batch: (rescale factor bits, wide flag)
     double *gpart, *spart, *cpart_;  // [ER][M][M], [ER][M], [ER][M]
+    // per-target decays (R-form forward, reverse adjoint for the gradient)
+    int32_t *csc_ptr, *csc_row;   // alpha by column: targets p of source q
+    float* csc_val;
+    float* wv;            // [n] w_i = 1/lambda_i per event
+    double* ebseg;        // [nseg][M] per segment: sum_j alpha_{p,m_j} (T - t_j) e^{-beta_p (T - t_j)}
+                          //   minus sum_{i: m_i = p} w_i (R_i - beta_p D_i)
+    double* ebacc;        // [M] the same over the whole sequence (= -dL/dbeta_p)
+    double* aggA;         // [nseg][M] reverse segment aggregates of the adjoint state
+    double* rcarry_seg;   // [nseg][M] adjoint state at each segment's first event (events from there on)
+    double *rgagg, *rgcarry;  // [ngr][M] reverse group aggregates and carries
+    double* achunk;       // [M] adjoint state entering the current chunk from the right
     // outputs
     double *loglik, *g_mu, *g_alpha, *g_beta;
     float* lambda_out;
 };
 
+#define HK_SG 32           // segments per scan group
+
 size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, size_t ws_bytes);
 hawkes_status run_large(LargeArgs& A, hipStream_t st);
+hawkes_status run_large_pt(LargeArgs& A, hipStream_t st);
+// helpers shared by the two large-M paths (host side)
+size_t lds_limit();
+hawkes_status allow_lds(const void* kernel, size_t bytes);
+void large_build_index(int32_t M, const float* alpha, int trans, int32_t* ptr, int32_t* idx, float* val,
+                       hipStream_t st);
+void large_scan(LargeArgs& A, int32_t nseg, const float* beta_pt, hipStream_t st);
+void large_chunk_acc_launch(int32_t nseg, const double* seg_part, double* acc, hipStream_t st);
 
 size_t seq_workspace_bytes(const hawkes_problem* p);
 hawkes_status run_sequential(const hawkes_problem* p, const double* t, const int32_t* marks, const float* mu,

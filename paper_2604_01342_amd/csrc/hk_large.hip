@@ -47,13 +47,19 @@ __global__ void large_colsum(int32_t M, const float* __restrict__ alpha, float* 
     colsum[q] = (float)c;
 }
 
-// csr_ptr[p+1] = nnz of row p (one wave per row, coalesced)
+// csr_ptr[p+1] = nnz of row p (one wave per row, coalesced).  With trans != 0
+// the rows are the columns of alpha (compressed-column form, strided reads).
+__device__ __forceinline__ float alpha_at(const float* __restrict__ alpha, int32_t M, int32_t r, int32_t c,
+                                          int trans) {
+    return trans ? alpha[(int64_t)c * M + r] : alpha[(int64_t)r * M + c];
+}
+
 __global__ __launch_bounds__(64) void large_rowcount(int32_t M, const float* __restrict__ alpha,
-                                                     int32_t* __restrict__ csr_ptr) {
+                                                     int32_t* __restrict__ csr_ptr, int trans) {
     const int32_t p = blockIdx.x;
     const int lane = threadIdx.x;
     int32_t cnt = 0;
-    for (int32_t q = lane; q < M; q += 64) cnt += alpha[(int64_t)p * M + q] != 0.0f;
+    for (int32_t q = lane; q < M; q += 64) cnt += alpha_at(alpha, M, p, q, trans) != 0.0f;
     for (int off = 32; off > 0; off >>= 1) cnt += __shfl_down(cnt, off, 64);
     if (lane == 0) {
         csr_ptr[p + 1] = cnt;
@@ -88,13 +94,14 @@ __global__ __launch_bounds__(1024) void large_csr_scan(int32_t M, int32_t* __res
 // one wave per row: compact the nonzeros of row p in column order
 __global__ __launch_bounds__(64) void large_csr_fill(int32_t M, const float* __restrict__ alpha,
                                                      const int32_t* __restrict__ csr_ptr,
-                                                     int32_t* __restrict__ csr_col, float* __restrict__ csr_val) {
+                                                     int32_t* __restrict__ csr_col, float* __restrict__ csr_val,
+                                                     int trans) {
     const int32_t p = blockIdx.x;
     const int lane = threadIdx.x;
     int32_t o = csr_ptr[p];
     for (int32_t q0 = 0; q0 < M; q0 += 64) {
         const int32_t q = q0 + lane;
-        const float a = q < M ? alpha[(int64_t)p * M + q] : 0.0f;
+        const float a = q < M ? alpha_at(alpha, M, p, q, trans) : 0.0f;
         const uint64_t nz = __ballot(a != 0.0f);
         if (a != 0.0f) {
             const int32_t r = __builtin_popcountll(nz & (lane ? (~0ull >> (64 - lane)) : 0ull));
@@ -158,23 +165,27 @@ __global__ __launch_bounds__(64) void large_seg_agg(int64_t c0, int64_t c1, int3
 //   3 thread per (segment, node): carry_seg[s] = group carry moved to the
 //     segment start, plus the in-group prefix
 // carry_seg[s] is the state just after the event preceding segment s.
-#define HK_SG 32
 
+// beta_pt: per-target decays (R-form state) or nullptr (one shared decay,
+// seg_dec / gdec precomputed)
 __global__ void large_scan_local(int32_t nseg, int32_t M, const double* __restrict__ agg,
                                  const double* __restrict__ seg_dec, const double* __restrict__ seg_span,
-                                 double* __restrict__ carry_seg, double* __restrict__ gagg) {
+                                 double* __restrict__ carry_seg, double* __restrict__ gagg,
+                                 const float* __restrict__ beta_pt) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int32_t ngr = (nseg + HK_SG - 1) / HK_SG;
     if (gid >= (int64_t)ngr * M) return;
     const int32_t g = (int32_t)(gid / M), q = (int32_t)(gid % M);
     const int32_t s0 = g * HK_SG, s1 = s0 + HK_SG < nseg ? s0 + HK_SG : nseg;
     double K = 0.0, J = 0.0;
+    const double bq = beta_pt ? (double)beta_pt[q] : 0.0;
     for (int32_t s = s0; s < s1; ++s) {
         const double* row = agg + (int64_t)s * 2 * M;
         double* o = carry_seg + (int64_t)s * 2 * M;
         o[q] = K;
         o[M + q] = J;
-        const double ex = seg_dec[s], D = seg_span[s];
+        const double D = seg_span[s];
+        const double ex = beta_pt ? exp(-bq * D) : seg_dec[s];
         const double k0 = K;
         K = __builtin_fma(ex, k0, row[q]);
         J = __builtin_fma(ex, __builtin_fma(D, k0, J), row[M + q]);
@@ -198,15 +209,18 @@ __global__ void large_scan_gdec(int32_t nseg, const double* __restrict__ seg_spa
 
 __global__ void large_scan_groups(int32_t nseg, int32_t M, const double* __restrict__ gagg,
                                   const double* __restrict__ gspan, const double* __restrict__ gdec,
-                                  double* __restrict__ gcarry, double* __restrict__ carry) {
+                                  double* __restrict__ gcarry, double* __restrict__ carry,
+                                  const float* __restrict__ beta_pt) {
     const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= M) return;
     const int32_t ngr = (nseg + HK_SG - 1) / HK_SG;
     double K = carry[q], J = carry[M + q];
+    const double bq = beta_pt ? (double)beta_pt[q] : 0.0;
     for (int32_t g = 0; g < ngr; ++g) {
         gcarry[(int64_t)g * 2 * M + q] = K;
         gcarry[(int64_t)g * 2 * M + M + q] = J;
-        const double ex = gdec[g], D = gspan[g];
+        const double D = gspan[g];
+        const double ex = beta_pt ? exp(-bq * D) : gdec[g];
         const double k0 = K;
         K = __builtin_fma(ex, k0, gagg[(int64_t)g * 2 * M + q]);
         J = __builtin_fma(ex, __builtin_fma(D, k0, J), gagg[(int64_t)g * 2 * M + M + q]);
@@ -217,14 +231,14 @@ __global__ void large_scan_groups(int32_t nseg, int32_t M, const double* __restr
 
 __global__ void large_scan_apply(int32_t nseg, int32_t M, const double* __restrict__ seg_span,
                                  const float* __restrict__ beta, const double* __restrict__ gcarry,
-                                 double* __restrict__ carry_seg) {
+                                 double* __restrict__ carry_seg, const float* __restrict__ beta_pt) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (gid >= (int64_t)nseg * M) return;
     const int32_t s = (int32_t)(gid / M), q = (int32_t)(gid % M);
     const int32_t g = s / HK_SG;
     double D = 0.0;
     for (int32_t r = g * HK_SG; r < s; ++r) D += seg_span[r];
-    const double ex = exp(-(double)beta[0] * D);
+    const double ex = exp(-(double)(beta_pt ? beta_pt[q] : beta[0]) * D);
     const double Kc = gcarry[(int64_t)g * 2 * M + q], Jc = gcarry[(int64_t)g * 2 * M + M + q];
     double* o = carry_seg + (int64_t)s * 2 * M;
     const double Kl = o[q], Jl = o[M + q];
@@ -723,10 +737,27 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
     A.seg_part = c.take<double>((size_t)A.nseg * 4);
     A.acc = c.take<double>(4);
     A.ll_scratch = c.take<double>(1);
+    if (A.per_target) {
+        A.csc_ptr = c.take<int32_t>(M + 1);
+        A.csc_row = c.take<int32_t>(MM);
+        A.csc_val = c.take<float>(MM);
+        A.ebseg = c.take<double>((size_t)A.nseg * M);
+        A.ebacc = c.take<double>(M);
+        if (grad) {
+            A.wv = c.take<float>((size_t)(A.n > 0 ? A.n : 1));
+            A.aggA = c.take<double>((size_t)A.nseg * M);
+            A.rcarry_seg = c.take<double>((size_t)A.nseg * M);
+            A.rgagg = c.take<double>((size_t)A.ngr * M);
+            A.rgcarry = c.take<double>((size_t)A.ngr * M);
+            A.achunk = c.take<double>(M);
+        }
+    }
     if (grad) {
-        A.ev_rec = c.take<int4>(A.CH);
-        A.ev_ct = c.take<float>(A.CH);
-        A.batch_info = c.take<int2>(A.CH / 64 + 1);
+        if (!A.per_target) {
+            A.ev_rec = c.take<int4>(A.CH);
+            A.ev_ct = c.take<float>(A.CH);
+            A.batch_info = c.take<int2>(A.CH / 64 + 1);
+        }
         A.gpart = c.take<double>((size_t)A.ER * MM);
         A.spart = c.take<double>((size_t)A.ER * M);
         A.cpart_ = c.take<double>((size_t)A.ER * M);
@@ -734,11 +765,60 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
     return c.off + 256;
 }
 
+void large_chunk_acc_launch(int32_t nseg, const double* seg_part, double* acc, hipStream_t st) {
+    hipLaunchKernelGGL(large_chunk_acc, dim3(1), dim3(256), 0, st, nseg, seg_part, acc);
+}
+
+size_t lds_limit() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 64 * 1024;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+        return 64 * 1024;
+    return (size_t)v;
+}
+
+hawkes_status allow_lds(const void* kernel, size_t bytes) {
+    if (bytes > lds_limit()) return HAWKES_EUNSUPPORTED;
+    if (bytes > 64 * 1024 &&
+        hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
+        return HAWKES_EUNSUPPORTED;
+    return HAWKES_OK;
+}
+
+void large_build_index(int32_t M, const float* alpha, int trans, int32_t* ptr, int32_t* idx, float* val,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(large_rowcount, dim3(M), dim3(64), 0, st, M, alpha, ptr, trans);
+    hipLaunchKernelGGL(large_csr_scan, dim3(1), dim3(1024), 0, st, M, ptr);
+    hipLaunchKernelGGL(large_csr_fill, dim3(M), dim3(64), 0, st, M, alpha, ptr, idx, val, trans);
+}
+
+void large_scan(LargeArgs& A, int32_t nseg, const float* beta_pt, hipStream_t st) {
+    const int32_t M = A.M;
+    const unsigned gM = (unsigned)((M + 255) / 256);
+    const int32_t ngr = (nseg + HK_SG - 1) / HK_SG;
+    const int64_t nloc = (int64_t)ngr * M, napp = (int64_t)nseg * M;
+    hipLaunchKernelGGL(large_scan_local, dim3((unsigned)((nloc + 255) / 256)), dim3(256), 0, st, nseg, M, A.agg,
+                       A.seg_dec, A.seg_span, A.carry_seg, A.gagg, beta_pt);
+    hipLaunchKernelGGL(large_scan_gdec, dim3((unsigned)((ngr + 255) / 256)), dim3(256), 0, st, nseg, A.seg_span,
+                       A.beta, A.gspan, A.gdec);
+    hipLaunchKernelGGL(large_scan_groups, dim3(gM), dim3(256), 0, st, nseg, M, A.gagg, A.gspan, A.gdec, A.gcarry,
+                       A.carry, beta_pt);
+    hipLaunchKernelGGL(large_scan_apply, dim3((unsigned)((napp + 255) / 256)), dim3(256), 0, st, nseg, M,
+                       A.seg_span, A.beta, A.gcarry, A.carry_seg, beta_pt);
+}
+
 hawkes_status run_large(LargeArgs& A, hipStream_t st) {
-    if (A.per_target) return HAWKES_EUNSUPPORTED;
+    if (A.per_target) return run_large_pt(A, st);
     const int32_t M = A.M;
     const int64_t MM = (int64_t)M * M;
     const unsigned gM = (unsigned)((M + 255) / 256);
+    const size_t lds_agg = (size_t)2 * M * sizeof(double);
+    const size_t lds_fwd = (size_t)M * (sizeof(double) + sizeof(uint64_t) + 2 * sizeof(float));
+    if (allow_lds((const void*)large_seg_agg, lds_agg) != HAWKES_OK ||
+        allow_lds((const void*)large_forward<true, false>, lds_fwd) != HAWKES_OK ||
+        allow_lds((const void*)large_forward<false, true>, lds_fwd) != HAWKES_OK ||
+        allow_lds((const void*)large_forward<false, false>, lds_fwd) != HAWKES_OK)
+        return HAWKES_EUNSUPPORTED;
     // zero the carried state and accumulators
     hipLaunchKernelGGL(fill_d, dim3(1), dim3(256), 0, st, A.carry, (int64_t)2 * M, 0.0);
     hipLaunchKernelGGL(fill_d, dim3(1), dim3(64), 0, st, A.acc, (int64_t)4, 0.0);
@@ -750,13 +830,8 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
         hipLaunchKernelGGL(fill_d, dim3(64), dim3(256), 0, st, A.cpart_, (int64_t)A.ER * M, 0.0);
     }
     hipLaunchKernelGGL(large_colsum, dim3(gM), dim3(256), 0, st, M, A.alpha, A.colsum);
-    hipLaunchKernelGGL(large_rowcount, dim3(M), dim3(64), 0, st, M, A.alpha, A.csr_ptr);
-    hipLaunchKernelGGL(large_csr_scan, dim3(1), dim3(1024), 0, st, M, A.csr_ptr);
-    hipLaunchKernelGGL(large_csr_fill, dim3(M), dim3(64), 0, st, M, A.alpha, A.csr_ptr, A.csr_col, A.csr_val);
+    large_build_index(M, A.alpha, 0, A.csr_ptr, A.csr_col, A.csr_val, st);
     hipLaunchKernelGGL(large_node_info, dim3(gM), dim3(256), 0, st, M, A.csr_ptr, A.mu, A.colsum, A.node_info);
-    const size_t lds_agg = (size_t)2 * M * sizeof(double);
-    const size_t lds_fwd = (size_t)M * (sizeof(double) + sizeof(uint64_t) + 2 * sizeof(float));
-    if (lds_agg > 64 * 1024 || lds_fwd > 64 * 1024) return HAWKES_EUNSUPPORTED;
     for (int64_t ch = 0; ch < A.nchunks; ++ch) {
         const int64_t c0 = ch * A.CH;
         const int64_t c1 = c0 + A.CH < A.n ? c0 + A.CH : A.n;
@@ -768,16 +843,7 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
         }
         {
             TimedScope ts(3, st);
-            const int32_t ngr = (nseg + HK_SG - 1) / HK_SG;
-            const int64_t nloc = (int64_t)ngr * M, napp = (int64_t)nseg * M;
-            hipLaunchKernelGGL(large_scan_local, dim3((unsigned)((nloc + 255) / 256)), dim3(256), 0, st, nseg, M,
-                               A.agg, A.seg_dec, A.seg_span, A.carry_seg, A.gagg);
-            hipLaunchKernelGGL(large_scan_gdec, dim3((unsigned)((ngr + 255) / 256)), dim3(256), 0, st, nseg,
-                               A.seg_span, A.beta, A.gspan, A.gdec);
-            hipLaunchKernelGGL(large_scan_groups, dim3(gM), dim3(256), 0, st, nseg, M, A.gagg, A.gspan, A.gdec,
-                               A.gcarry, A.carry);
-            hipLaunchKernelGGL(large_scan_apply, dim3((unsigned)((napp + 255) / 256)), dim3(256), 0, st, nseg, M,
-                               A.seg_span, A.beta, A.gcarry, A.carry_seg);
+            large_scan(A, nseg, nullptr, st);
         }
         {
             TimedScope ts(1, st);

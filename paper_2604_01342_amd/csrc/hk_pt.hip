@@ -1,0 +1,632 @@
+// Large-M engine with one decay per target node (beta[M], one kernel).
+//
+// With beta_p depending on the target, the intensity state is target-indexed
+// (R-form): R_p(t) = sum_{j: t_j < t} alpha_{p,m_j} e^{-beta_p (t - t_j)}, so
+// lambda_p(t) = mu_p + beta_p R_p(t) (eq. 1 with gamma -> beta_p).  Its
+// transition map is affine with a diagonal decay diag(e^{-beta_p dt}) instead
+// of a scalar one (eq. 6 with a per-component decay); segment maps compose in
+// closed form per component, so the segmented scan of the shared-decay path
+// carries over with exp(-beta_p span) per (segment, p).
+//
+// Gradient (eqs. 8-10 with beta_p):
+//   dL/dmu_p    = S_p - T,                S_p = sum_{i: m_i = p} w_i, w_i = 1/lambda_i
+//   dL/dbeta_p  = sum_{i: m_i = p} w_i (R_p(t_i) - beta_p D_p(t_i))
+//                 - sum_j alpha_{p,m_j} (T - t_j) e^{-beta_p (T - t_j)},
+//                 D_p(t) = sum_j alpha_{p,m_j} (t - t_j) e^{-beta_p (t - t_j)}
+//   dL/dalpha_pq = sum_{j: m_j = q} beta_p A_p(t_j) - N_q
+// where A_p(t) = sum_{i > j, m_i = p} w_i e^{-beta_p (t_i - t)} + e^{-beta_p (T - t)} / beta_p
+// is the reverse (adjoint) state: the second term, a seed 1/beta_p at T,
+// folds the compensator's alpha-derivative sum_j (1 - e^{-beta_p (T - t_j)})
+// into the sum, and N_q is the number of q-events.  The dense alpha-gradient
+// is then a column update per source event, with target-indexed state in the
+// lanes, so each lane keeps its own decay.
+//
+// Pass 1 (chunks in order): R-form segment maps, their scan, the forward pass
+// (log-likelihood, w_i per event, per-target sums for dL/dbeta), compensator
+// terms.  Decays in this pass use float64 exp: dL/dbeta_p is a difference of
+// near-equal sums, and with float32 decays its error reached 2e-6 on a small
+// dense-alpha case.
+// Pass 2 (chunks in reverse): reverse segment maps of A, their scan from the
+// right (seeded at T), and the dense adjoint kernel.
+#include "hk_device.h"
+#include "hk_large.h"
+
+namespace hk {
+
+// capacity of the per-batch staging of alpha columns in the forward kernel
+#define PT_STAGE 2048
+
+__global__ void pt_fill(double* p, int64_t n, double v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// adjoint seed at T: A_p(T) = 1 / beta_p
+__global__ void pt_seed(int32_t M, const float* __restrict__ beta, double* __restrict__ a) {
+    const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < M) a[p] = 1.0 / (double)beta[p];
+}
+
+__device__ __forceinline__ int pt_rdl(int v, int k) { return __builtin_amdgcn_readlane(v, k); }
+__device__ __forceinline__ double pt_rdl_d(double v, int k) {
+    const int64_t b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), k);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+    return __longlong_as_double(((int64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// ------------------------------------------------------------------ pass 1
+// Segment map in R-form: R and D just after the segment's last event, from the
+// segment's own events.  Also the two compensator sums of the segment:
+// sum_j sum_p alpha_{p,m_j} (1 - e^{-beta_p (T - t_j)}) into seg_part[s][1]
+// and, per target, sum_j alpha_{p,m_j} (T - t_j) e^{-beta_p (T - t_j)}.
+// One wave per segment; lanes take events and push their alpha column.
+// LDS: aR[M], aD[M], aE[M] (float64).
+__global__ __launch_bounds__(64) void pt_seg_agg(int64_t c0, int64_t c1, int32_t M, double T,
+                                                 const double* __restrict__ t, const int32_t* __restrict__ marks,
+                                                 const float* __restrict__ beta, const int32_t* __restrict__ csc_ptr,
+                                                 const int32_t* __restrict__ csc_row,
+                                                 const float* __restrict__ csc_val, double* __restrict__ agg,
+                                                 double* __restrict__ seg_span, double* __restrict__ ebseg,
+                                                 double* __restrict__ seg_part) {
+    extern __shared__ double lds[];
+    double* aR = lds;
+    double* aD = lds + M;
+    double* aE = lds + 2 * M;
+    const int32_t s = blockIdx.x;
+    const int64_t a = c0 + (int64_t)s * HK_SEG;
+    const int64_t b = a + HK_SEG < c1 ? a + HK_SEG : c1;
+    const int lane = threadIdx.x;
+    for (int32_t q = lane; q < M; q += 64) { aR[q] = 0.0; aD[q] = 0.0; aE[q] = 0.0; }
+    __syncthreads();
+    const double te = t[b - 1];
+    double comp = 0.0;
+    for (int64_t base = a; base < b; base += 64) {
+        const int64_t i = base + lane;
+        if (i < b) {
+            const double ti = t[i];
+            const int q = clamp_mark(marks[i], M);
+            const double d = te - ti, x0 = T - ti;
+            const int32_t k0 = csc_ptr[q], k1 = csc_ptr[q + 1];
+            for (int32_t kb = k0; kb < k1; kb += 8) {
+                int32_t pv[8];
+                float av[8], bv[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int32_t k = kb + j < k1 ? kb + j : k1 - 1;
+                    pv[j] = csc_row[k];
+                    av[j] = csc_val[k];
+                }
+#pragma unroll
+                for (int j = 0; j < 8; ++j) bv[j] = beta[pv[j]];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    if (kb + j >= k1) break;
+                    const int32_t p = pv[j];
+                    const double al = (double)av[j], bp = (double)bv[j];
+                    const double e = exp(-bp * d);
+                    atomicAdd(&aR[p], al * e);
+                    atomicAdd(&aD[p], al * d * e);
+                    const double x = bp * x0;
+                    atomicAdd(&aE[p], al * x0 * exp(-x));
+                    comp += al * -expm1(-x);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    double* o = agg + (int64_t)s * 2 * M;
+    double* oe = ebseg + (int64_t)s * M;
+    for (int32_t q = lane; q < M; q += 64) {
+        o[q] = aR[q];
+        o[M + q] = aD[q];
+        oe[q] = aE[q];
+    }
+    for (int off = 32; off > 0; off >>= 1) comp += __shfl_down(comp, off, 64);
+    if (lane == 0) {
+        const double tr = a > 0 ? t[a - 1] : t[a];
+        seg_span[s] = te - tr;
+        seg_part[(int64_t)s * 4 + 1] = comp;
+    }
+}
+
+// Forward pass over one segment (one wave), events in index order.  LDS keeps
+// one lazy record per target (time, R, D at that time), initialised from the
+// scanned carry.  Each event reads its own target's record (R_p, D_p at t_i,
+// from the events before it), then pushes its alpha column into the records
+// of the targets it excites.  The alpha columns of a 64-event batch are first
+// staged in LDS so the serial walk reads no global memory.
+template <bool GRAD, bool INTENS>
+__global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t M, double T,
+                                                 const double* __restrict__ t, const int32_t* __restrict__ marks,
+                                                 const float* __restrict__ mu, const float* __restrict__ beta,
+                                                 const int32_t* __restrict__ csc_ptr,
+                                                 const int32_t* __restrict__ csc_row,
+                                                 const float* __restrict__ csc_val,
+                                                 const double* __restrict__ carry_seg, double* __restrict__ seg_part,
+                                                 double* __restrict__ ebseg, float* __restrict__ wv,
+                                                 float* __restrict__ lambda_out) {
+    extern __shared__ double lds[];
+    double* rtau = lds;
+    double* rR = lds + M;
+    double* rD = lds + 2 * M;
+    double* gbl = lds + 3 * M;   // per-target sum of w_i (R_i - beta_p D_i) over the segment
+    int32_t* st_row = (int32_t*)(lds + 4 * M);
+    float* st_val = (float*)(st_row + PT_STAGE);
+    float* st_bet = st_val + PT_STAGE;
+    const int32_t s = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t a = c0 + (int64_t)s * HK_SEG;
+    const int64_t b = a + HK_SEG < c1 ? a + HK_SEG : c1;
+    const double tref = a > 0 ? t[a - 1] : t[a];
+    const double* cs = carry_seg + (int64_t)s * 2 * M;
+    for (int32_t q = lane; q < M; q += 64) {
+        rtau[q] = tref;
+        rR[q] = cs[q];
+        rD[q] = cs[M + q];
+        gbl[q] = 0.0;
+    }
+    __syncthreads();
+    double logsum = 0.0;
+    for (int64_t base = a; base < b; base += 64) {
+        const int64_t ie = base + lane;
+        const bool ve = ie < b;
+        const int64_t ic = ve ? ie : b - 1;
+        const double tv = t[ic];
+        const int mv = clamp_mark(marks[ic], M);
+        const int nb = (int)(b - base < 64 ? b - base : 64);
+        // column extents of the batch's marks and their exclusive prefix
+        const int32_t cb = csc_ptr[mv];
+        const int32_t cn = ve ? csc_ptr[mv + 1] - cb : 0;
+        int32_t off = cn;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int32_t u = __shfl_up(off, d, 64);
+            if (lane >= d) off += u;
+        }
+        off -= cn;   // exclusive
+        double Rk = 0.0, Dk = 0.0;
+        int k = 0;
+        while (k < nb) {
+            // stage the columns of events [k, k2) (at least one event; an
+            // event whose column alone exceeds the stage reads it directly)
+            const int32_t o0 = pt_rdl(off, k);
+            int k2 = k + 1;
+            while (k2 < nb && pt_rdl(off, k2) + pt_rdl(cn, k2) - o0 <= PT_STAGE) ++k2;
+            const bool staged = pt_rdl(off, k) + pt_rdl(cn, k) - o0 <= PT_STAGE;
+            if (staged) {
+                if (lane >= k && lane < k2) {
+                    for (int32_t j = 0; j < cn; ++j) {
+                        const int32_t pr = csc_row[cb + j];
+                        st_row[off - o0 + j] = pr;
+                        st_val[off - o0 + j] = csc_val[cb + j];
+                        st_bet[off - o0 + j] = beta[pr];
+                    }
+                }
+                __syncthreads();
+            }
+            for (; k < k2; ++k) {
+                const double ti = pt_rdl_d(tv, k);
+                const int p = pt_rdl(mv, k);
+                const double bp = (double)beta[p];
+                // record of the event's own target, moved to t_i
+                const double d = ti - rtau[p];
+                const double e = exp(-bp * d);
+                const double r = rR[p];
+                const double Rv = e * r;
+                const double Dv = e * __builtin_fma(d, r, rD[p]);
+                if (lane == k) { Rk = Rv; Dk = Dv; }
+                // push the event's alpha column (targets excited by mark p)
+                const int32_t n_k = pt_rdl(cn, k);
+                const int32_t ok = pt_rdl(off, k) - o0;
+                const int32_t cbk = pt_rdl(cb, k);
+                for (int32_t j0 = 0; j0 < n_k; j0 += 64) {
+                    const int32_t j = j0 + lane;
+                    if (j < n_k) {
+                        int32_t tp;
+                        float av, bt;
+                        if (staged) {
+                            tp = st_row[ok + j];
+                            av = st_val[ok + j];
+                            bt = st_bet[ok + j];
+                        } else {
+                            tp = csc_row[cbk + j];
+                            av = csc_val[cbk + j];
+                            bt = beta[tp];
+                        }
+                        const double dd = ti - rtau[tp];
+                        const double ee = exp(-(double)bt * dd);
+                        const double r0 = rR[tp];
+                        rD[tp] = ee * __builtin_fma(dd, r0, rD[tp]);
+                        rR[tp] = __builtin_fma(ee, r0, (double)av);
+                        rtau[tp] = ti;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (ve) {
+            const double bm = (double)beta[mv];
+            const double lam = (double)mu[mv] + bm * Rk;
+            logsum += log(lam);
+            if (INTENS) lambda_out[ie] = (float)lam;
+            if (GRAD) {
+                const double w = 1.0 / lam;
+                wv[ie] = (float)w;
+                atomicAdd(&gbl[mv], w * (Rk - bm * Dk));
+            }
+        }
+    }
+    if (GRAD) {
+        // the segment's row of ebseg becomes EB - GB (minus its dL/dbeta share)
+        __syncthreads();
+        double* oe = ebseg + (int64_t)s * M;
+        for (int32_t q = lane; q < M; q += 64) oe[q] -= gbl[q];
+    }
+    for (int off = 32; off > 0; off >>= 1) logsum += __shfl_down(logsum, off, 64);
+    if (lane == 0) {
+        double* o = seg_part + (int64_t)s * 4;
+        o[0] = logsum;
+        o[2] = 0.0;
+        o[3] = 0.0;
+    }
+}
+
+// ebacc[p] += sum over the chunk's segments, in segment order
+__global__ void pt_eb_reduce(int32_t nseg, int32_t M, const double* __restrict__ ebseg, double* __restrict__ ebacc) {
+    const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= M) return;
+    double v = 0.0;
+    for (int32_t s = 0; s < nseg; ++s) v += ebseg[(int64_t)s * M + p];
+    ebacc[p] += v;
+}
+
+// ------------------------------------------------------------------ pass 2
+// time of segment s's first event; for s == nseg, the time the chunk's right
+// carry refers to (the next chunk's first event, or T after the last chunk)
+__device__ __forceinline__ double seg_first_time(const double* __restrict__ t, int64_t c0, int64_t c1, int64_t n,
+                                                 int32_t nseg, int32_t s, double T) {
+    if (s >= nseg) return c1 < n ? t[c1] : T;
+    return t[c0 + (int64_t)s * HK_SEG];
+}
+
+// aggA[s][p] = sum_{i in segment s, m_i = p} w_i e^{-beta_p (t_i - t_first(s))}
+// one wave per segment, LDS aA[M]
+__global__ __launch_bounds__(64) void pt_rev_agg(int64_t c0, int64_t c1, int32_t M, const double* __restrict__ t,
+                                                 const int32_t* __restrict__ marks, const float* __restrict__ beta,
+                                                 const float* __restrict__ wv, double* __restrict__ aggA) {
+    extern __shared__ double lds[];
+    double* aA = lds;
+    const int32_t s = blockIdx.x;
+    const int64_t a = c0 + (int64_t)s * HK_SEG;
+    const int64_t b = a + HK_SEG < c1 ? a + HK_SEG : c1;
+    const int lane = threadIdx.x;
+    for (int32_t q = lane; q < M; q += 64) aA[q] = 0.0;
+    __syncthreads();
+    const double tf = t[a];
+    for (int64_t base = a; base < b; base += 64) {
+        const int64_t i = base + lane;
+        if (i < b) {
+            const int p = clamp_mark(marks[i], M);
+            const double w = (double)wv[i];
+            atomicAdd(&aA[p], w * (double)exp_f64arg(-(double)beta[p] * (t[i] - tf)));
+        }
+    }
+    __syncthreads();
+    double* o = aggA + (int64_t)s * M;
+    for (int32_t q = lane; q < M; q += 64) o[q] = aA[q];
+}
+
+// Reverse scan in three parallel steps, mirroring the forward one:
+//   local   1 thread per (group, target): suffix inside the group
+//   groups  1 thread per target: chain the groups from the chunk's right carry
+//   apply   1 thread per (segment, target): add the group's right carry
+// rcarry_seg[s][p] ends as A_p at t_first(s) from the events of segment s on
+// (this and later chunks, plus the seed).
+__global__ void pt_rscan_local(int64_t c0, int64_t c1, int64_t n, double T, int32_t nseg, int32_t M,
+                               const double* __restrict__ t, const float* __restrict__ beta,
+                               const double* __restrict__ aggA, double* __restrict__ rcarry_seg,
+                               double* __restrict__ rgagg) {
+    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int32_t ngr = (nseg + HK_SG - 1) / HK_SG;
+    if (gid >= (int64_t)ngr * M) return;
+    const int32_t g = (int32_t)(gid / M), p = (int32_t)(gid % M);
+    const int32_t s0 = g * HK_SG, s1 = s0 + HK_SG < nseg ? s0 + HK_SG : nseg;
+    const double bp = (double)beta[p];
+    double A = 0.0, tn = seg_first_time(t, c0, c1, n, nseg, s1, T);
+    for (int32_t s = s1 - 1; s >= s0; --s) {
+        const double ts = seg_first_time(t, c0, c1, n, nseg, s, T);
+        A = __builtin_fma(exp(-bp * (tn - ts)), A, aggA[(int64_t)s * M + p]);
+        rcarry_seg[(int64_t)s * M + p] = A;
+        tn = ts;
+    }
+    rgagg[(int64_t)g * M + p] = A;
+}
+
+__global__ void pt_rscan_groups(int64_t c0, int64_t c1, int64_t n, double T, int32_t nseg, int32_t M,
+                                const double* __restrict__ t, const float* __restrict__ beta,
+                                const double* __restrict__ rgagg, double* __restrict__ rgcarry,
+                                double* __restrict__ achunk) {
+    const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= M) return;
+    const int32_t ngr = (nseg + HK_SG - 1) / HK_SG;
+    const double bp = (double)beta[p];
+    double A = achunk[p], tn = seg_first_time(t, c0, c1, n, nseg, nseg, T);
+    for (int32_t g = ngr - 1; g >= 0; --g) {
+        rgcarry[(int64_t)g * M + p] = A;
+        const double ts = seg_first_time(t, c0, c1, n, nseg, g * HK_SG, T);
+        A = __builtin_fma(exp(-bp * (tn - ts)), A, rgagg[(int64_t)g * M + p]);
+        tn = ts;
+    }
+    achunk[p] = A;
+}
+
+__global__ void pt_rscan_apply(int64_t c0, int64_t c1, int64_t n, double T, int32_t nseg, int32_t M,
+                               const double* __restrict__ t, const float* __restrict__ beta,
+                               const double* __restrict__ rgcarry, double* __restrict__ rcarry_seg) {
+    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)nseg * M) return;
+    const int32_t s = (int32_t)(gid / M), p = (int32_t)(gid % M);
+    const int32_t g = s / HK_SG;
+    const int32_t s1 = (g + 1) * HK_SG < nseg ? (g + 1) * HK_SG : nseg;
+    const double te = seg_first_time(t, c0, c1, n, nseg, s1, T);
+    const double ts = seg_first_time(t, c0, c1, n, nseg, s, T);
+    rcarry_seg[(int64_t)s * M + p] += exp(-(double)beta[p] * (te - ts)) * rgcarry[(int64_t)g * M + p];
+}
+
+// Dense adjoint kernel.  Block = (target block rb, source block sb, event
+// range er), one wave; lane l owns target p = r0 + l and its adjoint state
+// A_p (float64), anchored at the last event of the current 64-event batch.
+// Batches are walked from the end of the range.  For every source event k in
+// the slab (m_k in sb), column m_k of the block takes beta_p A_p(t_k): the
+// anchored state decayed to t_k, plus the events of the same batch after k
+// whose target is in the block (one masked ds_add over those lanes).  Then
+// the batch's own-target events enter the state and the anchor moves to the
+// previous batch.  G is kept in LDS column-major (stride 65 against bank
+// conflicts).  Blocks with sb == 0 also sum w_i and w_i (R_i - beta_p D_i)
+// per target, blocks with rb == 0 count the events per source.
+__global__ __launch_bounds__(64) void pt_dense(int64_t c0, int64_t c1, int64_t n, double T, int32_t M, int32_t NB,
+                                               int32_t ER, int32_t segs_per_range, int32_t nseg,
+                                               const double* __restrict__ t, const int32_t* __restrict__ marks,
+                                               const float* __restrict__ beta, const float* __restrict__ wv,
+                                               const double* __restrict__ rcarry_seg,
+                                               const double* __restrict__ rgcarry, double* __restrict__ gpart,
+                                               double* __restrict__ spart, double* __restrict__ npart) {
+    __shared__ double G[HK_SLAB * 65];
+    __shared__ double AL[64], SL[64], NL[64];
+    const int lane = threadIdx.x;
+    AL[lane] = 0.0;
+    SL[lane] = 0.0;
+    NL[lane] = 0.0;
+    const int32_t blk = blockIdx.x;
+    const int32_t nbb = NB * NB;
+    int32_t er, local;
+    if (ER >= 8) {
+        const int32_t slot = blk >> 3;
+        er = (slot / nbb) * 8 + (blk & 7);
+        local = slot % nbb;
+    } else {
+        const int32_t per = 8 / ER, x = blk & 7;
+        er = x / per;
+        local = (blk >> 3) * per + x % per;
+        if (local >= nbb) return;
+    }
+    if (er >= ER) return;
+    const int32_t sb = local % NB;
+    const int32_t rb = local / NB;
+    const int32_t r0 = rb * HK_RB, s0 = sb * HK_SLAB;
+    const int64_t a = c0 + (int64_t)er * segs_per_range * HK_SEG;
+    if (a >= c1) return;
+    const int64_t bnd = a + (int64_t)segs_per_range * HK_SEG;
+    const int64_t b = bnd < c1 ? bnd : c1;
+    const int32_t p = r0 + lane;
+    const bool pv = p < M;
+    double* gp = gpart + (int64_t)er * M * M;
+    {
+        // lanes over the block's columns (coalesced rows of gpart)
+        const int32_t col = s0 + lane;
+        const int32_t cc = col < M ? col : M - 1;
+        for (int rg = 0; rg < HK_RB; rg += 16) {
+            double v[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int32_t row = r0 + rg + j;
+                const int32_t rr = row < M ? row : M - 1;
+                v[j] = gp[(int64_t)rr * M + cc];
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int32_t row = r0 + rg + j;
+                G[lane * 65 + rg + j] = (row < M && col < M) ? v[j] : 0.0;
+            }
+        }
+    }
+    const double bp = pv ? (double)beta[p] : 0.0;
+    // adjoint state from the events after the range (and the seed), at t[b-1]
+    double Ah = 0.0;
+    {
+        const int32_t segb = (int32_t)((b - c0) / HK_SEG);
+        const bool at_end = b >= c1;
+        const int32_t ngr = (nseg + HK_SG - 1) / HK_SG;
+        const double tn = seg_first_time(t, c0, c1, n, nseg, at_end ? nseg : segb, T);
+        if (pv) {
+            const double Ae = at_end ? rgcarry[(int64_t)(ngr - 1) * M + p] : rcarry_seg[(int64_t)segb * M + p];
+            Ah = Ae * (double)exp_f64arg(-bp * (tn - t[b - 1]));
+        }
+    }
+    __syncthreads();
+    const int64_t nbat = (b - a + 63) / 64;
+    for (int64_t kb = nbat - 1; kb >= 0; --kb) {
+        const int64_t bb = a + 64 * kb;
+        const int64_t be = bb + 64 < b ? bb + 64 : b;
+        const double tau = t[be - 1];
+        const int64_t j = bb + lane;
+        const bool vj = j < be;
+        const int64_t jc = vj ? j : be - 1;
+        const int mj = vj ? clamp_mark(marks[jc], M) : -1;
+        const double tj = t[jc];
+        const double wj = (double)wv[jc];
+        const bool own = vj && mj >= r0 && mj < r0 + HK_RB;
+        const bool sl = vj && mj >= s0 && mj < s0 + HK_SLAB;
+        const double bo = own ? (double)beta[mj] : 0.0;
+        uint64_t ms = __ballot(sl);
+        while (ms) {
+            const int k = __builtin_ctzll(ms);
+            ms &= ms - 1;
+            const int qk = pt_rdl(mj, k) - s0;
+            const double tk = pt_rdl_d(tj, k);
+            const double f = (double)exp_f64arg(-bp * (tau - tk));
+            atomicAdd(&G[qk * 65 + lane], bp * Ah * f);
+            if (own && lane > k)
+                atomicAdd(&G[qk * 65 + (mj - r0)], bo * wj * (double)exp_f64arg(-bo * (tj - tk)));
+        }
+        if (sb == 0 && own) atomicAdd(&SL[mj - r0], wj);
+        if (rb == 0 && sl) atomicAdd(&NL[mj - s0], 1.0);
+        if (kb > 0) {
+            const double tp = t[bb - 1];
+            if (own) atomicAdd(&AL[mj - r0], wj * (double)exp_f64arg(-bo * (tj - tp)));
+            __syncthreads();
+            Ah = __builtin_fma(Ah, (double)exp_f64arg(-bp * (tau - tp)), AL[lane]);
+            AL[lane] = 0.0;
+        }
+    }
+    __syncthreads();
+    {
+        const int32_t col = s0 + lane;
+        if (col < M) {
+#pragma unroll 16
+            for (int r = 0; r < HK_RB; ++r) {
+                const int32_t row = r0 + r;
+                if (row < M) gp[(int64_t)row * M + col] = G[lane * 65 + r];
+            }
+        }
+    }
+    if (sb == 0 && pv) spart[(int64_t)er * M + p] += SL[lane];
+    if (rb == 0 && s0 + lane < M) npart[(int64_t)er * M + s0 + lane] += NL[lane];
+}
+
+__global__ void pt_final(int32_t M, int32_t ER, double T, const float* __restrict__ mu,
+                         const double* __restrict__ acc, const double* __restrict__ gpart,
+                         const double* __restrict__ spart, const double* __restrict__ npart,
+                         const double* __restrict__ ebacc,
+                         double* __restrict__ loglik, double* __restrict__ g_mu, double* __restrict__ g_alpha,
+                         double* __restrict__ g_beta, int grad) {
+    const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t MM = (int64_t)M * M;
+    if (x == 0) {
+        double musum = 0.0;
+        for (int32_t p = 0; p < M; ++p) musum += (double)mu[p];
+        loglik[0] = acc[0] - T * musum - acc[1];
+    }
+    if (!grad) return;
+    if (x < MM && g_alpha) {
+        const int32_t q = (int32_t)(x % M);
+        double g = 0.0, c = 0.0;
+        for (int32_t e = 0; e < ER; ++e) {
+            g += gpart[(int64_t)e * MM + x];
+            c += npart[(int64_t)e * M + q];
+        }
+        g_alpha[x] = g - c;
+    }
+    if (x < M) {
+        double s = 0.0;
+        for (int32_t e = 0; e < ER; ++e) s += spart[(int64_t)e * M + x];
+        if (g_mu) g_mu[x] = s - T;
+        if (g_beta) g_beta[x] = -ebacc[x];
+    }
+}
+
+// ------------------------------------------------------------------ host
+hawkes_status run_large_pt(LargeArgs& A, hipStream_t st) {
+    const int32_t M = A.M;
+    const int64_t MM = (int64_t)M * M;
+    const unsigned gM = (unsigned)((M + 255) / 256);
+    const size_t lds_agg = (size_t)3 * M * sizeof(double);
+    const size_t lds_fwd = (size_t)4 * M * sizeof(double) + (size_t)PT_STAGE * 12;
+    const size_t lds_rev = (size_t)M * sizeof(double);
+    if (allow_lds((const void*)pt_seg_agg, lds_agg) != HAWKES_OK ||
+        allow_lds((const void*)pt_forward<true, false>, lds_fwd) != HAWKES_OK ||
+        allow_lds((const void*)pt_forward<false, true>, lds_fwd) != HAWKES_OK ||
+        allow_lds((const void*)pt_forward<false, false>, lds_fwd) != HAWKES_OK ||
+        allow_lds((const void*)pt_rev_agg, lds_rev) != HAWKES_OK)
+        return HAWKES_EUNSUPPORTED;
+    auto fill = [&](double* p, int64_t cnt, double v) {
+        const int64_t nb = (cnt + 255) / 256;
+        hipLaunchKernelGGL(pt_fill, dim3((unsigned)(nb < 65535 ? (nb > 0 ? nb : 1) : 65535)), dim3(256), 0, st, p,
+                           cnt, v);
+    };
+    fill(A.carry, 2 * (int64_t)M, 0.0);
+    fill(A.acc, 4, 0.0);
+    fill(A.ebacc, M, 0.0);
+    if (A.grad) {
+        fill(A.gpart, (int64_t)A.ER * MM, 0.0);
+        fill(A.spart, (int64_t)A.ER * M, 0.0);
+        fill(A.cpart_, (int64_t)A.ER * M, 0.0);
+    }
+    large_build_index(M, A.alpha, 1, A.csc_ptr, A.csc_row, A.csc_val, st);
+    for (int64_t ch = 0; ch < A.nchunks; ++ch) {
+        const int64_t c0 = ch * A.CH;
+        const int64_t c1 = c0 + A.CH < A.n ? c0 + A.CH : A.n;
+        const int32_t nseg = (int32_t)((c1 - c0 + HK_SEG - 1) / HK_SEG);
+        {
+            TimedScope ts(2, st);
+            hipLaunchKernelGGL(pt_seg_agg, dim3(nseg), dim3(64), lds_agg, st, c0, c1, M, A.T, A.t, A.marks, A.beta,
+                               A.csc_ptr, A.csc_row, A.csc_val, A.agg, A.seg_span, A.ebseg, A.seg_part);
+        }
+        {
+            TimedScope ts(3, st);
+            large_scan(A, nseg, A.beta, st);
+        }
+        {
+            TimedScope ts(1, st);
+            if (A.grad)
+                hipLaunchKernelGGL((pt_forward<true, false>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1, M, A.T, A.t,
+                                   A.marks, A.mu, A.beta, A.csc_ptr, A.csc_row, A.csc_val, A.carry_seg, A.seg_part,
+                                   A.ebseg, A.wv, (float*)nullptr);
+            else if (A.lambda_out)
+                hipLaunchKernelGGL((pt_forward<false, true>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1, M, A.T, A.t,
+                                   A.marks, A.mu, A.beta, A.csc_ptr, A.csc_row, A.csc_val, A.carry_seg, A.seg_part,
+                                   A.ebseg, (float*)nullptr, A.lambda_out);
+            else
+                hipLaunchKernelGGL((pt_forward<false, false>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1, M, A.T,
+                                   A.t, A.marks, A.mu, A.beta, A.csc_ptr, A.csc_row, A.csc_val, A.carry_seg,
+                                   A.seg_part, A.ebseg, (float*)nullptr, (float*)nullptr);
+        }
+        large_chunk_acc_launch(nseg, A.seg_part, A.acc, st);
+        hipLaunchKernelGGL(pt_eb_reduce, dim3(gM), dim3(256), 0, st, nseg, M, A.ebseg, A.ebacc);
+    }
+    if (A.grad && A.n > 0) {
+        hipLaunchKernelGGL(pt_seed, dim3(gM), dim3(256), 0, st, M, A.beta, A.achunk);
+        for (int64_t ch = A.nchunks - 1; ch >= 0; --ch) {
+            const int64_t c0 = ch * A.CH;
+            const int64_t c1 = c0 + A.CH < A.n ? c0 + A.CH : A.n;
+            const int32_t nseg = (int32_t)((c1 - c0 + HK_SEG - 1) / HK_SEG);
+            const int32_t ngr = (nseg + HK_SG - 1) / HK_SG;
+            const int64_t nloc = (int64_t)ngr * M, napp = (int64_t)nseg * M;
+            {
+                TimedScope ts(3, st);
+                hipLaunchKernelGGL(pt_rev_agg, dim3(nseg), dim3(64), lds_rev, st, c0, c1, M, A.t, A.marks, A.beta,
+                                   A.wv, A.aggA);
+                hipLaunchKernelGGL(pt_rscan_local, dim3((unsigned)((nloc + 255) / 256)), dim3(256), 0, st, c0, c1,
+                                   A.n, A.T, nseg, M, A.t, A.beta, A.aggA, A.rcarry_seg, A.rgagg);
+                hipLaunchKernelGGL(pt_rscan_groups, dim3(gM), dim3(256), 0, st, c0, c1, A.n, A.T, nseg, M, A.t,
+                                   A.beta, A.rgagg, A.rgcarry, A.achunk);
+                hipLaunchKernelGGL(pt_rscan_apply, dim3((unsigned)((napp + 255) / 256)), dim3(256), 0, st, c0, c1,
+                                   A.n, A.T, nseg, M, A.t, A.beta, A.rgcarry, A.rcarry_seg);
+            }
+            const int32_t spr = (nseg + A.ER - 1) / A.ER;
+            const int32_t nbb = A.NB * A.NB;
+            const unsigned nblk = A.ER >= 8 ? (unsigned)(nbb * ((A.ER + 7) / 8) * 8)
+                                            : (unsigned)(((nbb + 8 / A.ER - 1) / (8 / A.ER)) * 8);
+            TimedScope ts(0, st);
+            hipLaunchKernelGGL(pt_dense, dim3(nblk), dim3(64), 0, st, c0, c1, A.n, A.T, M, A.NB, A.ER, spr, nseg,
+                               A.t, A.marks, A.beta, A.wv, A.rcarry_seg, A.rgcarry, A.gpart, A.spart, A.cpart_);
+        }
+    }
+    const int64_t nfin = A.grad ? (MM > M ? MM : M) : 1;
+    hipLaunchKernelGGL(pt_final, dim3((unsigned)((nfin + 255) / 256)), dim3(256), 0, st, M, A.ER, A.T, A.mu, A.acc,
+                       A.gpart, A.spart, A.cpart_, A.ebacc, A.loglik, A.g_mu, A.g_alpha, A.g_beta,
+                       A.grad ? 1 : 0);
+    return hipGetLastError() == hipSuccess ? HAWKES_OK : HAWKES_EDEVICE;
+}
+
+}  // namespace hk
