@@ -33,11 +33,19 @@
  *  - Outputs are float64: loglik[1], g_mu[m], g_alpha[m*m] (same layout as
  *    alpha), g_beta[1] (shared) or g_beta[m] (per target).  Any gradient
  *    pointer may be NULL to skip that output.
- *  - Precision: time differences are formed in float64.  For m > 8 (the
- *    large-M engine) decays, scan state and intensities are float32; for
- *    m <= 8 the few state values per lane are kept in float64.  Every sum over
- *    events (log-likelihood, gradients) is accumulated in float64 in a fixed
- *    order, so repeated calls return bitwise-identical results.
+ *  - Precision: time differences are formed in float64.  Shared decay,
+ *    m > 8 (the large-M engine): decays, the forward state and intensities
+ *    are float32, the dense-gradient state float64.  Shared decay, m <= 8:
+ *    the few state values per lane are kept in float64.  Decay per target
+ *    (any m): the forward pass (state, decays, intensities) is float64; the
+ *    reverse pass for dL/dalpha uses float32 decays on a float64 state.
+ *    Every sum over events (log-likelihood, gradients) is accumulated in
+ *    float64 in a fixed order, so repeated calls return bitwise-identical
+ *    results.
+ *  - Size limits (LDS per workgroup, read from the device; 160 KiB on
+ *    MI355X): shared decay m <= 6826, decay per target m <= 4352; larger m
+ *    returns HAWKES_EUNSUPPORTED.  The per-target gradient also keeps one
+ *    float32 per event (4 bytes x n) in the workspace for its reverse pass.
  *  - Errors: every function returns a hawkes_status.  Host-detectable
  *    argument errors return HAWKES_EINVAL (or HAWKES_EWORKSPACE for a short
  *    workspace) before anything is launched, and the outputs are untouched.
@@ -65,7 +73,7 @@ typedef enum hawkes_status {
     HAWKES_EINVAL = 1,        /* bad argument (NULL pointer, size, mode) */
     HAWKES_EWORKSPACE = 2,    /* workspace NULL or smaller than required */
     HAWKES_EDEVICE = 3,       /* a HIP call or kernel launch failed */
-    HAWKES_EUNSUPPORTED = 4   /* valid request this build does not implement (k > 1) */
+    HAWKES_EUNSUPPORTED = 4   /* valid request this build does not implement (k > 1, m above the limits) */
 } hawkes_status;
 
 typedef enum hawkes_beta_mode {
@@ -77,8 +85,8 @@ typedef enum hawkes_beta_mode {
  * sequence is evaluated in consecutive chunks of 2^chunk_log2 events, each
  * carrying only an M-vector state into the next (the batching of the
  * "Time Complexity Analysis and Batching" section and Algorithm 2), so the
- * workspace does not grow with n.  0 selects the default (2^20).  Valid
- * range 12..26. */
+ * workspace does not grow with n (except the per-target gradient's 4 bytes
+ * per event, see above).  0 selects the default (2^20).  Valid range 12..26. */
 typedef struct hawkes_problem {
     int64_t n;           /* number of events, >= 0 */
     int32_t m;           /* number of nodes M, >= 1 */
@@ -120,6 +128,34 @@ hawkes_status hawkes_intensity(const hawkes_problem* p,
                                const double* t, const int32_t* marks,
                                const float* mu, const float* alpha, const float* beta,
                                float* lambda_out,
+                               void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ----------------------------------------------------------------------------
+ * Maximum-likelihood step (the training loop of Algorithm 1: forward pass,
+ * backward pass, optimizer step; the paper's sparsity penalty is not
+ * included).  hawkes_adam_step evaluates the log-likelihood and gradient like
+ * hawkes_loglik_grad (same workspace size), then applies one projected Adam
+ * step to the per-event negative log-likelihood -L/n, in place on mu, alpha
+ * and beta (float32): first and second moments in float32, bias corrections
+ * from a step counter kept in the device state, then mu >= floor_mu,
+ * alpha >= 0, beta >= floor_beta.  All gradient outputs are required (they
+ * hold the gradient of L at the parameters before the step).  The call is
+ * stream-ordered and host-sync-free, so a whole step can be captured in a
+ * HIP graph and replayed; each replay advances the counter.
+ * The state (size from hawkes_adam_state_bytes, caller-owned device memory)
+ * must be zeroed once with hawkes_adam_init before the first step.
+ * ------------------------------------------------------------------------- */
+typedef struct hawkes_adam {
+    float lr, beta1, beta2, eps;   /* step size, moment decays, denominator floor */
+    float floor_mu, floor_beta;    /* projection bounds (floor_beta > 0) */
+} hawkes_adam;
+
+size_t hawkes_adam_state_bytes(const hawkes_problem* p);
+hawkes_status hawkes_adam_init(const hawkes_problem* p, void* state, size_t state_bytes, hipStream_t stream);
+hawkes_status hawkes_adam_step(const hawkes_problem* p, const double* t, const int32_t* marks,
+                               float* mu, float* alpha, float* beta, const hawkes_adam* cfg,
+                               void* state, size_t state_bytes,
+                               double* loglik, double* g_mu, double* g_alpha, double* g_beta,
                                void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* ----------------------------------------------------------------------------
@@ -182,11 +218,12 @@ hawkes_status hawkes_check_inputs(const hawkes_problem* p,
  *   0 dense dL/dalpha (large-M engine)   1 forward scan (large-M engine)
  *   2 segment aggregates (large-M)       3 segment carry scan (large-M)
  *   4 per-item evaluation (small-M)      5 small-M aggregates and scans
+ *   6 partition of a chunk's events by node block (large-M, gradient only)
  * Recording is host-side bookkeeping only (no device allocation); the events
  * are destroyed by hawkes_timing_read / hawkes_timing_reset.  Not for use
  * during graph capture.
  * ------------------------------------------------------------------------- */
-#define HAWKES_TIMING_KERNELS 6
+#define HAWKES_TIMING_KERNELS 7
 hawkes_status hawkes_timing_enable(int on);
 hawkes_status hawkes_timing_reset(void);
 hawkes_status hawkes_timing_read(int kernel_id, double* total_ms, int64_t* launches);

@@ -21,7 +21,7 @@ import torch
 __all__ = [
     "HawkesError", "lib", "library_path", "workspace_bytes", "loglik", "loglik_grad",
     "intensity", "loglik_batched", "loglik_grad_batched", "sequential_loglik_grad",
-    "check_inputs", "HawkesLogLik", "hawkes_loglik", "BETA_SHARED", "BETA_PER_TARGET",
+    "check_inputs", "HawkesLogLik", "hawkes_loglik", "BETA_SHARED", "BETA_PER_TARGET", "AdamMLE",
 ]
 
 BETA_SHARED = 0
@@ -44,6 +44,11 @@ class HawkesError(RuntimeError):
 class _Problem(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int32), ("k", ctypes.c_int32),
                 ("beta_mode", ctypes.c_int32), ("chunk_log2", ctypes.c_int32), ("T", ctypes.c_double)]
+
+
+class _Adam(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("floor_mu", ctypes.c_float), ("floor_beta", ctypes.c_float)]
 
 
 def library_path() -> str:
@@ -80,8 +85,13 @@ def lib():
     L.hawkes_timing_read.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     for f in ("hawkes_timing_enable", "hawkes_timing_reset", "hawkes_timing_read"):
         getattr(L, f).restype = ctypes.c_int
+    L.hawkes_adam_state_bytes.argtypes = [P]
+    L.hawkes_adam_state_bytes.restype = sz
+    L.hawkes_adam_init.argtypes = [P, vp, sz, vp]
+    L.hawkes_adam_step.argtypes = [P, vp, vp, vp, vp, vp, ctypes.POINTER(_Adam), vp, sz, vp, vp, vp, vp, vp, sz, vp]
     for f in ("hawkes_loglik", "hawkes_loglik_grad", "hawkes_intensity", "hawkes_sequential_loglik_grad",
-              "hawkes_check_inputs", "hawkes_loglik_batched", "hawkes_loglik_grad_batched"):
+              "hawkes_check_inputs", "hawkes_loglik_batched", "hawkes_loglik_grad_batched", "hawkes_adam_init",
+              "hawkes_adam_step"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -206,7 +216,7 @@ def sequential_loglik_grad(t, m, mu, alpha, beta, T):
 
 
 TIMING_KERNELS = {0: "dense_dalpha", 1: "forward", 2: "segment_aggregate", 3: "segment_scan",
-                  4: "small_compute", 5: "small_scan"}
+                  4: "small_compute", 5: "small_scan", 6: "bucket"}
 
 
 def timing_enable(on: bool = True) -> None:
@@ -336,3 +346,64 @@ class HawkesLogLik(torch.autograd.Function):
 def hawkes_loglik(t, m, mu, alpha, beta, T, chunk_log2: int = 0) -> torch.Tensor:
     """Differentiable log-likelihood w.r.t. (mu, alpha, beta)."""
     return HawkesLogLik.apply(mu, alpha, beta, t, m, T, chunk_log2)
+
+
+def _aligned(dev, nbytes: int) -> torch.Tensor:
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + nbytes]
+
+
+class AdamMLE:
+    """Maximum-likelihood fit by projected Adam on the per-event negative
+    log-likelihood, one hawkes_adam_step call per step (evaluation, gradient
+    and update on the GPU, no host synchronisation).  Owns float32 copies of
+    the parameters (updated in place), its workspace, the optimizer state and
+    the last step's outputs.  capture() records one step in a HIP graph;
+    replay() runs it again (each replay is one more Adam step)."""
+
+    def __init__(self, t, m, mu, alpha, beta, T, lr=0.05, betas=(0.9, 0.999), eps=1e-8, floor_mu=1e-6,
+                 floor_beta=1e-6, chunk_log2: int = 0):
+        dev, t, m, mu, alpha, beta = _prep(t, m, mu, alpha, beta)
+        self.dev, self.t, self.m = dev, t, m
+        self.mu, self.alpha, self.beta = mu.clone(), alpha.clone(), beta.clone()
+        self.p = _problem(t, self.mu, self.beta, T, chunk_log2)
+        L = lib()
+        self.ws_bytes = int(L.hawkes_workspace_bytes(ctypes.byref(self.p), 1))
+        self.ws = _aligned(dev, self.ws_bytes)
+        self.state_bytes = int(L.hawkes_adam_state_bytes(ctypes.byref(self.p)))
+        if self.state_bytes == 0:
+            raise ValueError("invalid problem for the Adam state")
+        self.state = _aligned(dev, self.state_bytes)
+        self.cfg = _Adam(lr, betas[0], betas[1], eps, floor_mu, floor_beta)
+        M = self.mu.numel()
+        self.loglik = torch.empty(1, dtype=torch.float64, device=dev)
+        self.g_mu = torch.empty(M, dtype=torch.float64, device=dev)
+        self.g_alpha = torch.empty(M, M, dtype=torch.float64, device=dev)
+        self.g_beta = torch.empty(self.beta.numel(), dtype=torch.float64, device=dev)
+        self.graph = None
+        _check("hawkes_adam_init", L.hawkes_adam_init(ctypes.byref(self.p), _ptr(self.state), self.state_bytes,
+                                                      _stream(dev)))
+
+    def step(self):
+        """One evaluation + Adam step on the current stream; returns L at the
+        parameters before the step (device tensor)."""
+        L = lib()
+        _check("hawkes_adam_step",
+               L.hawkes_adam_step(ctypes.byref(self.p), _ptr(self.t), _ptr(self.m), _ptr(self.mu), _ptr(self.alpha),
+                                  _ptr(self.beta), ctypes.byref(self.cfg), _ptr(self.state), self.state_bytes,
+                                  _ptr(self.loglik), _ptr(self.g_mu), _ptr(self.g_alpha), _ptr(self.g_beta),
+                                  _ptr(self.ws), self.ws_bytes, _stream(self.dev)))
+        return self.loglik[0]
+
+    def capture(self):
+        """Record one step into a HIP graph (nothing runs during capture)."""
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.step()
+        self.graph = g
+        return g
+
+    def replay(self):
+        self.graph.replay()
+        return self.loglik[0]

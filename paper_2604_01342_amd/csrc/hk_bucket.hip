@@ -1,0 +1,126 @@
+// Per-chunk partition of the events by node block (64 nodes per block),
+// stable in event order: a counting sort in three steps.
+//   count    one wave per segment: events per (block, segment)
+//   scan     one workgroup per block: start of every (block, segment) run
+//            within the block, boff[block][segment] ([block][nseg] = the
+//            block's size), then bbase[block], the block's start in the
+//            block-major output
+//   scatter  one wave per segment: each event's rank among the events of its
+//            block in the same 64-event batch comes from bit-sliced ballots
+//            (one ballot per bit of the block number), plus the block's
+//            running count in LDS
+// Records: key = (event index in the chunk) << 6 | (mark mod 64), t (float64),
+// w = 1 / lambda (float32).  The dense-gradient kernels stream the records of
+// two blocks (the block of their rows and the block of their columns)
+// instead of filtering every event of the chunk.
+#include "hk_device.h"
+#include "hk_large.h"
+
+namespace hk {
+
+__global__ __launch_bounds__(64) void bucket_count(int64_t c0, int64_t c1, int32_t M, int32_t NB,
+                                                   const int32_t* __restrict__ marks, int32_t nseg,
+                                                   int32_t* __restrict__ cnt) {
+    extern __shared__ int32_t lc[];
+    const int32_t s = blockIdx.x;
+    const int lane = threadIdx.x;
+    for (int32_t k = lane; k < NB; k += 64) lc[k] = 0;
+    __syncthreads();
+    const int64_t a = c0 + (int64_t)s * HK_SEG;
+    const int64_t b = a + HK_SEG < c1 ? a + HK_SEG : c1;
+    for (int64_t i = a + lane; i < b; i += 64) atomicAdd(&lc[clamp_mark(marks[i], M) >> 6], 1);
+    __syncthreads();
+    for (int32_t k = lane; k < NB; k += 64) cnt[(int64_t)k * nseg + s] = lc[k];
+}
+
+// one workgroup per block: exclusive scan of its counts over the segments,
+// boff[block][segment] relative to the block's start, boff[block][nseg] = its
+// total
+__global__ __launch_bounds__(256) void bucket_scan(int32_t nseg, const int32_t* __restrict__ cnt,
+                                                   int32_t* __restrict__ boff) {
+    __shared__ int32_t sh[256];
+    const int32_t k = blockIdx.x;
+    const int tid = threadIdx.x;
+    int32_t carry = 0;
+    for (int32_t base = 0; base < nseg; base += 256) {
+        const int32_t s = base + tid;
+        const int32_t v = s < nseg ? cnt[(int64_t)k * nseg + s] : 0;
+        sh[tid] = v;
+        __syncthreads();
+        for (int d = 1; d < 256; d <<= 1) {
+            const int32_t u = tid >= d ? sh[tid - d] : 0;
+            __syncthreads();
+            sh[tid] += u;
+            __syncthreads();
+        }
+        if (s < nseg) boff[(int64_t)k * (nseg + 1) + s] = carry + sh[tid] - v;
+        carry += sh[255];
+        __syncthreads();
+    }
+    if (tid == 0) boff[(int64_t)k * (nseg + 1) + nseg] = carry;
+}
+
+// bbase[block] = number of records of the blocks before it
+__global__ void bucket_base(int32_t NB, int32_t nseg, const int32_t* __restrict__ boff, int32_t* __restrict__ bbase) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int32_t acc = 0;
+    for (int32_t k = 0; k < NB; ++k) {
+        bbase[k] = acc;
+        acc += boff[(int64_t)k * (nseg + 1) + nseg];
+    }
+}
+
+__global__ __launch_bounds__(64) void bucket_scatter(int64_t c0, int64_t c1, int32_t M, int32_t NB, int32_t nbits,
+                                                     const double* __restrict__ t,
+                                                     const int32_t* __restrict__ marks,
+                                                     const float* __restrict__ wchunk, int32_t nseg,
+                                                     const int32_t* __restrict__ boff,
+                                                     const int32_t* __restrict__ bbase,
+                                                     uint32_t* __restrict__ bk_key, double* __restrict__ bk_t,
+                                                     float* __restrict__ bk_w) {
+    extern __shared__ int32_t run[];
+    const int32_t s = blockIdx.x;
+    const int lane = threadIdx.x;
+    for (int32_t k = lane; k < NB; k += 64) run[k] = 0;
+    __syncthreads();
+    const int64_t a = c0 + (int64_t)s * HK_SEG;
+    const int64_t b = a + HK_SEG < c1 ? a + HK_SEG : c1;
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    for (int64_t base = a; base < b; base += 64) {
+        const int64_t i = base + lane;
+        const bool v = i < b;
+        const int64_t ic = v ? i : b - 1;
+        const int mk = clamp_mark(marks[ic], M);
+        const int blk = mk >> 6;
+        // lanes with the same block: agree on every bit of the block number
+        uint64_t same = __ballot(v);
+        for (int bit = 0; bit < nbits; ++bit) {
+            const uint64_t on = __ballot((blk >> bit) & 1);
+            same &= ((blk >> bit) & 1) ? on : ~on;
+        }
+        const int rank = __builtin_popcountll(same & lt);
+        const int32_t before = run[blk];
+        if (v) {
+            const int64_t pos = (int64_t)bbase[blk] + boff[(int64_t)blk * (nseg + 1) + s] + before + rank;
+            bk_key[pos] = ((uint32_t)(i - c0) << 6) | (uint32_t)(mk & 63);
+            bk_t[pos] = t[i];
+            bk_w[pos] = wchunk[i - c0];
+        }
+        __syncthreads();
+        if (v && (same & lt) == 0) run[blk] = before + __builtin_popcountll(same);
+        __syncthreads();
+    }
+}
+
+void bucket_chunk(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, const float* wchunk, hipStream_t st) {
+    int nbits = 0;
+    while ((1 << nbits) < A.NB) ++nbits;
+    const size_t lds = (size_t)A.NB * sizeof(int32_t);
+    hipLaunchKernelGGL(bucket_count, dim3(nseg), dim3(64), lds, st, c0, c1, A.M, A.NB, A.marks, nseg, A.bk_cnt);
+    hipLaunchKernelGGL(bucket_scan, dim3(A.NB), dim3(256), 0, st, nseg, A.bk_cnt, A.bk_off);
+    hipLaunchKernelGGL(bucket_base, dim3(1), dim3(64), 0, st, A.NB, nseg, A.bk_off, A.bk_base);
+    hipLaunchKernelGGL(bucket_scatter, dim3(nseg), dim3(64), lds, st, c0, c1, A.M, A.NB, nbits, A.t, A.marks, wchunk,
+                       nseg, A.bk_off, A.bk_base, A.bk_key, A.bk_t, A.bk_w);
+}
+
+}  // namespace hk

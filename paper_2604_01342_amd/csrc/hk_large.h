@@ -7,7 +7,7 @@
 #define HK_SEG 2048        // events per forward segment (one wave)
 #define HK_RB 64           // rows per dense-gradient block
 #define HK_SLAB 64         // columns per dense-gradient block (one per lane)
-#define HK_WIDE 60.0       // anchored-exponent limit inside one 64-event batch
+#define HK_WIDE 60.0       // anchored-exponent limit inside one window of the dense kernel
 
 namespace hk {
 
@@ -40,9 +40,6 @@ struct LargeArgs {
     double* seg_part;     // [nseg][4]
     double* acc;          // [4] call-level sums: logsum, comp, E, gbeta
     double* ll_scratch;   // [1] log-likelihood slot when the caller wants intensities only
-    int4* ev_rec;         // [CH] per-event (mark, c, b, w) for the dense kernel
-    float* ev_ct;         // [CH] 1 - e^{-beta (T - t_i)} for the dense kernel's row-block 0
-    int2* batch_info;     // [CH/64 + 1] per 64-event batch: (rescale factor bits, wide flag)
     double *gpart, *spart, *cpart_;  // [ER][M][M], [ER][M], [ER][M]
     // per-target decays (R-form forward, reverse adjoint for the gradient)
     int32_t *csc_ptr, *csc_row;   // alpha by column: targets p of source q
@@ -55,6 +52,14 @@ struct LargeArgs {
     double* rcarry_seg;   // [nseg][M] adjoint state at each segment's first event (events from there on)
     double *rgagg, *rgcarry;  // [ngr][M] reverse group aggregates and carries
     double* achunk;       // [M] adjoint state entering the current chunk from the right
+    // events of the chunk partitioned by node block (64 nodes), in event order
+    int32_t* bk_cnt;      // [NB][nseg] events per (block, segment)
+    int32_t* bk_off;      // [NB][nseg + 1] start of each (block, segment) run within the block
+    int32_t* bk_base;     // [NB] start of each block in the records
+    uint32_t* bk_key;     // [CH] (index in chunk) << 6 | mark mod 64
+    double* bk_t;         // [CH] event time
+    float* bk_w;          // [CH] 1 / lambda
+    float* wchunk;        // [CH] 1 / lambda of the chunk's events (shared decay)
     // outputs
     double *loglik, *g_mu, *g_alpha, *g_beta;
     float* lambda_out;
@@ -72,6 +77,7 @@ void large_build_index(int32_t M, const float* alpha, int trans, int32_t* ptr, i
                        hipStream_t st);
 void large_scan(LargeArgs& A, int32_t nseg, const float* beta_pt, hipStream_t st);
 void large_chunk_acc_launch(int32_t nseg, const double* seg_part, double* acc, hipStream_t st);
+void bucket_chunk(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, const float* wchunk, hipStream_t st);
 
 size_t seq_workspace_bytes(const hawkes_problem* p);
 hawkes_status run_sequential(const hawkes_problem* p, const double* t, const int32_t* marks, const float* mu,

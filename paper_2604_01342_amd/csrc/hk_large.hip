@@ -28,7 +28,9 @@
 //            multiply-add per column; rows accumulate in float64 LDS.
 #include "hk_device.h"
 #include "hk_large.h"
+#include "hk_stream.h"
 #include <stdlib.h>
+#include <mutex>
 
 namespace hk {
 
@@ -247,16 +249,6 @@ __global__ void large_scan_apply(int32_t nseg, int32_t M, const double* __restri
 }
 
 // ------------------------------------------------------------------ forward
-// frame end of the 64-event batch starting at global index g (events [g, min(g+64, c1))):
-// its first event time, or its last one when the batch is "wide"
-__device__ __forceinline__ double batch_frame_end(const double* __restrict__ t, int64_t g, int64_t c1, double bet,
-                                                  bool* wide) {
-    const int64_t l = g + 64 < c1 ? g + 63 : c1 - 1;
-    const double t0 = t[g], tl = t[l];
-    *wide = bet * (tl - t0) > HK_WIDE;
-    return *wide ? tl : t0;
-}
-
 template <bool GRAD, bool INTENS>
 __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int32_t M, double T,
                                                     const double* __restrict__ t, const int32_t* __restrict__ marks,
@@ -266,8 +258,7 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
                                                     const float* __restrict__ csr_val,
                                                     const double* __restrict__ carry_seg,
                                                     double* __restrict__ seg_part,
-                                                    int4* __restrict__ ev_rec, float* __restrict__ ev_ct,
-                                                    int2* __restrict__ batch_info,
+                                                    float* __restrict__ wchunk,
                                                     float* __restrict__ lambda_out) {
     extern __shared__ double lds[];
     double* rtau = lds;                                   // [M] time of the record
@@ -359,36 +350,7 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
                 Esum += (double)cs_m * (T - ti) * (double)ex;
             }
         }
-        if (GRAD) {
-            // dense-kernel record of this event, anchored at the batch's first event
-            const int64_t last = base + 63 < b - 1 ? base + 63 : b - 1;
-            const double tau = tb[0];
-            const bool wide = bet * (tb[last - base] - tau) > HK_WIDE;
-            if (valid) {
-                const int64_t ii = i - c0;
-                float cc, bb;
-                if (!wide) {
-                    const double xl = bet * (ti - tau);
-                    cc = betf * w * exp_f64arg(-xl);
-                    bb = exp_f64arg(xl);
-                } else {
-                    cc = betf * w;
-                    bb = lane == 0 ? 1.0f : exp_f64arg(-bet * (ti - tb[lane - 1]));
-                }
-                ev_rec[ii] = make_int4(mi, __float_as_int(cc), __float_as_int(bb), __float_as_int(w));
-                ev_ct[ii] = em1;
-            }
-            if (lane == 0) {
-                const int64_t bi = (base - c0) / 64;
-                float rho = 1.0f;
-                if (base - 64 >= c0) {
-                    bool pw;
-                    const double fe = batch_frame_end(t, base - 64, c1, bet, &pw);
-                    rho = exp_f64arg(-bet * (tau - fe));
-                }
-                batch_info[bi] = make_int2(__float_as_int(rho), wide ? 1 : 0);
-            }
-        }
+        if (GRAD && valid) wchunk[i - c0] = w;
         __syncthreads();
         // lazy record update, one leader lane per node, events in index order
         if (valid) {
@@ -440,38 +402,36 @@ __global__ __launch_bounds__(256) void large_chunk_acc(int32_t nseg, const doubl
 }
 
 // ------------------------------------------------------------------ dense dL/dalpha
-// block = (row block rb, column slab sb, event range er); one wave.
-// LDS G[64][64] float64 accumulates sum_i c_i Khat_q for the rows of the
-// block (c_i = beta w_i times the batch anchor factor); lane c owns column
-// s0 + c and its anchored state Khat (float64).  The blocks of one event
-// range are placed on one XCD (blockIdx % 8) so that the range's records stay
-// in that XCD's L2.
-__device__ __forceinline__ int rdl(int v, int k) { return __builtin_amdgcn_readlane(v, k); }
-__device__ __forceinline__ float rdlf(float v, int k) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
-}
-
-// A vector register holding 0 that the compiler cannot prove uniform: an
-// index offset by it stays a per-lane (vector memory) load, which is waited
-// for in order with the other prefetched loads, instead of a scalar load.
-__device__ __forceinline__ int opaque_zero() {
-    int z;
-    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
-    return z;
-}
-
-// Number of 64-event batches whose loads are in flight ahead of the batch
-// being processed; the ring is indexed with compile-time slots only.
-#define HK_PD 4
-
+// Block = (row block rb, column block sb, event range er), one wave.  LDS
+// G[64][64] float64 accumulates sum_i beta w_i K_q(t_i) for the block's rows
+// p (targets, m_i in rb) and columns q (sources in sb); lane c owns column
+// s0 + c and its state K (float64), kept in the frame of an anchor time.
+// The block reads only the events of its two node blocks (the bucketed
+// records of rb: "own" events, and of sb: "slab" events), merged by event
+// index in windows of up to 64 + 64 records:
+//   - the window ends where either list's 64th record ends (hi), so every own
+//     event of the window sees all earlier slab events either in K or in the
+//     window;
+//   - K moves to the window's first event time tw; own event k adds
+//     c_k * K to row m_k (c_k = beta w_k e^{-beta (t_k - tw)}, one ds_add_f64
+//     over the 64 columns) plus c_k * b_j at (m_k, m_j) for the window's
+//     slab events j before it (b_j = e^{beta (t_j - tw)}, one masked
+//     ds_add_f64 over those lanes): together c_k times K just before event k;
+//   - then the slab events enter K in one vector step (scatter-add into LDS by
+//     column, read back by each column's lane), and row block 0 sums w and
+//     the compensator terms 1 - e^{-beta (T - t_j)} per column the same way.
+// A window whose time span exceeds HK_WIDE / beta (anchored factors would
+// leave float32 range) is walked event by event with per-event decays.
+// Blocks of one event range are placed on one XCD (blockIdx % 8).
 __global__ __launch_bounds__(64) void large_dense(int64_t c0, int64_t c1, int32_t M, int32_t NB, int32_t ER,
-                                                  int32_t segs_per_range, const double* __restrict__ t,
-                                                  const float* __restrict__ beta,
+                                                  int32_t segs_per_range, int32_t nseg, double T,
+                                                  const double* __restrict__ t, const float* __restrict__ beta,
                                                   const double* __restrict__ carry_seg,
-                                                  const int4* __restrict__ ev_rec, const float* __restrict__ ev_ct,
-                                                  const int2* __restrict__ batch_info,
-                                                  double* __restrict__ gpart, double* __restrict__ spart,
-                                                  double* __restrict__ cpart) {
+                                                  const int32_t* __restrict__ bk_off,
+                                                  const int32_t* __restrict__ bk_base,
+                                                  const uint32_t* __restrict__ bk_key, const double* __restrict__ bk_t,
+                                                  const float* __restrict__ bk_w, double* __restrict__ gpart,
+                                                  double* __restrict__ spart, double* __restrict__ cpart) {
     __shared__ double G[HK_RB * HK_SLAB];
     __shared__ double KhL[HK_SLAB], SL[HK_SLAB], CL[HK_SLAB];
     const int lane = threadIdx.x;
@@ -496,10 +456,10 @@ __global__ __launch_bounds__(64) void large_dense(int64_t c0, int64_t c1, int32_
     const int32_t sb = local % NB;
     const int32_t rb = local / NB;
     const int32_t r0 = rb * HK_RB, s0 = sb * HK_SLAB;
-    const int64_t a = c0 + (int64_t)er * segs_per_range * HK_SEG;
-    if (a >= c1) return;
-    const int64_t bnd = a + (int64_t)segs_per_range * HK_SEG;
-    const int64_t b = bnd < c1 ? bnd : c1;
+    const int32_t sA = er * segs_per_range;
+    if (sA >= nseg) return;
+    const int32_t sB = sA + segs_per_range < nseg ? sA + segs_per_range : nseg;
+    const int64_t a = c0 + (int64_t)sA * HK_SEG;
     const int32_t col = s0 + lane;
     double* gp = gpart + (int64_t)er * M * M;
     {
@@ -522,78 +482,54 @@ __global__ __launch_bounds__(64) void large_dense(int64_t c0, int64_t c1, int32_
         }
     }
     const double bet = (double)beta[0];
-    const int32_t seg = (int32_t)((a - c0) / HK_SEG);
-    const double tref = a > 0 ? t[a - 1] : t[a];
-    double Kh = col < M ? carry_seg[(int64_t)seg * 2 * M + col] : 0.0;
-    Kh *= (double)exp_f64arg(-bet * (t[a] - tref));
+    // K at the range start (just after the event before it)
+    double Kh = col < M ? carry_seg[(int64_t)sA * 2 * M + col] : 0.0;
+    double tau = a > 0 ? t[a - 1] : t[a];
     double Sacc = 0.0, Cacc = 0.0;
     const bool diag_owner = rb == 0;
-    // Every operand of a batch is read with a clamped (always valid) index,
-    // HK_PD batches ahead, into a ring of registers; past the end of the range
-    // the ring is refilled with the last batch and never used.
-    const int64_t last_ii = b - 1 - c0;
-    const int zv = opaque_zero();
-    auto ld_rec = [&](int64_t base_) -> int4 {
-        const int64_t ii = base_ - c0 + lane;
-        return ev_rec[ii < last_ii ? ii : last_ii];
-    };
-    // only row block 0 uses the compensator terms; the others read one fixed
-    // (cached) word so that the load stays unconditional
-    auto ld_ct = [&](int64_t base_) -> float {
-        const int64_t ii = base_ - c0 + lane;
-        const int64_t ic = diag_owner ? (ii < last_ii ? ii : last_ii) : 0;
-        return ev_ct[ic];
-    };
-    auto ld_inf = [&](int64_t base_) -> int2 { return batch_info[(base_ - c0) / 64 + zv]; };
-    int4 rq[HK_PD];
-    float cq[HK_PD];
-    int2 iq[HK_PD];
-#pragma unroll
-    for (int s = 0; s < HK_PD; ++s) {
-        const int64_t bb = a + 64 * s;
-        const int64_t bc = bb < b ? bb : a;
-        rq[s] = ld_rec(bc);
-        cq[s] = ld_ct(bc);
-        iq[s] = ld_inf(bc);
-    }
-    // One 64-event batch.  Own rows take c_k times Khat as it stands at the
-    // batch start (one ds_add_f64 row update per own event), plus, for every
-    // slab event j earlier in the batch, c_k b_j at (m_k, m_j) (one masked
-    // ds_add_f64 over those lanes): together these are c_k times Khat just
-    // before event k.  The slab events then advance Khat in one vector step
-    // (scatter-add by column into LDS, read back by each column's lane), and
-    // row block 0 accumulates the per-column sums of w and of the compensator
-    // terms the same way.  Wide batches (each event its own anchor) fall back
-    // to a per-event walk.
-    auto batch = [&](const int64_t bb, int4 cur, float ctc, const int2 inf) {
-        if (bb + lane >= b) { cur.x = -1; ctc = 0.0f; }
-        const int wide = uniform(inf.y);
-        if (bb != a) Kh *= (double)__int_as_float(uniform(inf.x));
-        const int mi = cur.x;
-        const float ci = __int_as_float(cur.y);
-        const float bi_ = __int_as_float(cur.z);
-        const float wi = __int_as_float(cur.w);
-        const bool own = mi >= r0 && mi < r0 + HK_RB;
-        const bool sl = mi >= s0 && mi < s0 + HK_SLAB;
-        const int colj = sl ? mi - s0 : 0;
-        if (!wide) {
-            uint64_t mo = __ballot(own);
-            const uint64_t ms = __ballot(sl);
-            const double bj = (double)bi_;
-            while (mo) {
-                const int k = __builtin_ctzll(mo);
-                mo &= mo - 1;
-                const int rowoff = (rdl(mi, k) - r0) * HK_SLAB;
-                const double ck = (double)rdlf(ci, k);
+    RecStream<false> O, S;
+    O.init(bk_key, bk_t, bk_w, (int64_t)bk_base[rb] + bk_off[(int64_t)rb * (nseg + 1) + sA],
+           (int64_t)bk_base[rb] + bk_off[(int64_t)rb * (nseg + 1) + sB]);
+    S.init(bk_key, bk_t, bk_w, (int64_t)bk_base[sb] + bk_off[(int64_t)sb * (nseg + 1) + sA],
+           (int64_t)bk_base[sb] + bk_off[(int64_t)sb * (nseg + 1) + sB]);
+    __syncthreads();
+    for (;;) {
+        const int64_t ao = O.avail(), as = S.avail();
+        if (ao <= 0 && as <= 0) break;
+        const int io = (int)(O.ck >> 6), is = (int)(S.ck >> 6);
+        const int lim_o = ao > 64 ? rl_i(io, 63) : 0x7fffffff;
+        const int lim_s = as > 64 ? rl_i(is, 63) : 0x7fffffff;
+        const int hi = lim_o < lim_s ? lim_o : lim_s;
+        const bool own = lane < ao && io <= hi;
+        const bool sl = lane < as && is <= hi;
+        const int no = __builtin_popcountll(__ballot(own));
+        const int ns = __builtin_popcountll(__ballot(sl));
+        double tw = 1e300, te = -1e300;
+        if (no) { tw = rl_d(O.ct, 0); te = rl_d(O.ct, no - 1); }
+        if (ns) {
+            const double a0 = rl_d(S.ct, 0), a1 = rl_d(S.ct, ns - 1);
+            tw = a0 < tw ? a0 : tw;
+            te = a1 > te ? a1 : te;
+        }
+        Kh *= (double)exp_f64arg(-bet * (tw - tau));
+        tau = tw;
+        const int colj = (int)(S.ck & 63u);
+        if (bet * (te - tw) <= HK_WIDE) {
+            const float cf = own ? (float)(bet * (double)O.cw) * exp_f64arg(-bet * (O.ct - tw)) : 0.0f;
+            const double bj = sl ? (double)exp_f64arg(bet * (S.ct - tw)) : 0.0;
+            for (int k = 0; k < no; ++k) {
+                const int rowoff = (int)(rl_i((int)O.ck, k) & 63) * HK_SLAB;
+                const int ik = rl_i(io, k);
+                const double ck = (double)rl_f(cf, k);
                 atomicAdd(&G[rowoff + lane], ck * Kh);
-                if (sl && lane < k) atomicAdd(&G[rowoff + colj], ck * bj);
+                if (sl && is < ik) atomicAdd(&G[rowoff + colj], ck * bj);
             }
-            if (ms) {
+            if (ns) {
                 if (sl) {
                     atomicAdd(&KhL[colj], bj);
                     if (diag_owner) {
-                        atomicAdd(&SL[colj], (double)wi);
-                        atomicAdd(&CL[colj], (double)ctc);
+                        atomicAdd(&SL[colj], (double)S.cw);
+                        atomicAdd(&CL[colj], -expm1(-bet * (T - S.ct)));
                     }
                 }
                 __syncthreads();
@@ -601,50 +537,36 @@ __global__ __launch_bounds__(64) void large_dense(int64_t c0, int64_t c1, int32_
                 KhL[lane] = 0.0;
             }
         } else {
-            const int nb = (int)(b - bb < 64 ? b - bb : 64);
-            for (int k = 0; k < nb; ++k) {
-                const float rk = rdlf(bi_, k);
-                if (k > 0) Kh *= (double)rk;
-                const int mk = rdl(mi, k);
-                if (mk >= r0 && mk < r0 + HK_RB) {
-                    const double ck = (double)rdlf(ci, k);
-                    atomicAdd(&G[(mk - r0) * HK_SLAB + lane], ck * Kh);
-                }
-                if (mk >= s0 && mk < s0 + HK_SLAB) {
-                    if (diag_owner) {
-                        const float wk = rdlf(wi, k);
-                        const float ctk = rdlf(ctc, k);
-                        if (lane == mk - s0) { Sacc += (double)wk; Cacc += (double)ctk; }
+            int ko = 0, ks = 0;
+            while (ko < no || ks < ns) {
+                const int iko = ko < no ? rl_i(io, ko) : 0x7fffffff;
+                const int iks = ks < ns ? rl_i(is, ks) : 0x7fffffff;
+                if (iko <= iks) {
+                    // own first on a tie: the same event as slab event comes after
+                    const double tk = rl_d(O.ct, ko);
+                    Kh *= (double)exp_f64arg(-bet * (tk - tau));
+                    tau = tk;
+                    const int rowoff = (int)(rl_i((int)O.ck, ko) & 63) * HK_SLAB;
+                    atomicAdd(&G[rowoff + lane], bet * (double)rl_f(O.cw, ko) * Kh);
+                    ++ko;
+                } else {
+                    const double tk = rl_d(S.ct, ks);
+                    Kh *= (double)exp_f64arg(-bet * (tk - tau));
+                    tau = tk;
+                    const int ck = (int)(rl_i((int)S.ck, ks) & 63);
+                    if (lane == ck) {
+                        Kh += 1.0;
+                        if (diag_owner) {
+                            Sacc += (double)rl_f(S.cw, ks);
+                            Cacc += -expm1(-bet * (T - tk));
+                        }
                     }
-                    if (lane == mk - s0) Kh += 1.0;
+                    ++ks;
                 }
             }
         }
-    };
-    __syncthreads();
-    int64_t base = a;
-    // full groups of HK_PD batches: no early exit inside, so the loads of
-    // every slot are issued in the same order on every path to the back-edge
-    // and each wait covers only its own slot
-    for (; base + 64 * (HK_PD - 1) < b; base += 64 * HK_PD) {
-#pragma unroll
-        for (int s = 0; s < HK_PD; ++s) {
-            const int64_t bb = base + 64 * s;
-            batch(bb, rq[s], cq[s], iq[s]);
-            // refill the slot only once its batch is consumed, so the new
-            // loads can land in the same registers (no copy that would wait)
-            const int64_t nf = bb + 64 * HK_PD;
-            const int64_t nc = nf < b ? nf : bb;
-            rq[s] = ld_rec(nc);
-            cq[s] = ld_ct(nc);
-            iq[s] = ld_inf(nc);
-        }
-    }
-    // tail: fewer than HK_PD batches left, already in the ring
-#pragma unroll
-    for (int s = 0; s < HK_PD - 1; ++s) {
-        const int64_t bb = base + 64 * s;
-        if (bb < b) batch(bb, rq[s], cq[s], iq[s]);
+        O.consume(no);
+        S.consume(ns);
     }
     __syncthreads();
     if (col < M) {
@@ -753,11 +675,13 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
         }
     }
     if (grad) {
-        if (!A.per_target) {
-            A.ev_rec = c.take<int4>(A.CH);
-            A.ev_ct = c.take<float>(A.CH);
-            A.batch_info = c.take<int2>(A.CH / 64 + 1);
-        }
+        if (!A.per_target) A.wchunk = c.take<float>(A.CH);
+        A.bk_cnt = c.take<int32_t>((size_t)A.NB * A.nseg);
+        A.bk_off = c.take<int32_t>((size_t)A.NB * (A.nseg + 1));
+        A.bk_base = c.take<int32_t>(A.NB);
+        A.bk_key = c.take<uint32_t>(A.CH);
+        A.bk_t = c.take<double>(A.CH);
+        A.bk_w = c.take<float>(A.CH);
         A.gpart = c.take<double>((size_t)A.ER * MM);
         A.spart = c.take<double>((size_t)A.ER * M);
         A.cpart_ = c.take<double>((size_t)A.ER * M);
@@ -777,11 +701,29 @@ size_t lds_limit() {
     return (size_t)v;
 }
 
+// Kernels whose dynamic LDS exceeds 64 KiB are allowed the device maximum
+// once per (kernel, device); later calls (including ones under stream
+// capture) only look the pair up.
 hawkes_status allow_lds(const void* kernel, size_t bytes) {
-    if (bytes > lds_limit()) return HAWKES_EUNSUPPORTED;
-    if (bytes > 64 * 1024 &&
-        hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
+    const size_t lim = lds_limit();
+    if (bytes > lim) return HAWKES_EUNSUPPORTED;
+    if (bytes <= 64 * 1024) return HAWKES_OK;
+    static std::mutex mu;
+    static const void* done_k[128];
+    static int done_d[128];
+    static int n_done = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return HAWKES_EDEVICE;
+    std::lock_guard<std::mutex> g(mu);
+    for (int i = 0; i < n_done; ++i)
+        if (done_k[i] == kernel && done_d[i] == dev) return HAWKES_OK;
+    if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) != hipSuccess)
         return HAWKES_EUNSUPPORTED;
+    if (n_done < 128) {
+        done_k[n_done] = kernel;
+        done_d[n_done] = dev;
+        ++n_done;
+    }
     return HAWKES_OK;
 }
 
@@ -850,29 +792,33 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
             if (A.grad)
                 hipLaunchKernelGGL((large_forward<true, false>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1, M,
                                    A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
-                                   A.carry_seg, A.seg_part, A.ev_rec, A.ev_ct, A.batch_info,
+                                   A.carry_seg, A.seg_part, A.wchunk,
                                    (float*)nullptr);
             else if (A.lambda_out)
                 hipLaunchKernelGGL((large_forward<false, true>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1, M,
                                    A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
-                                   A.carry_seg, A.seg_part, A.ev_rec, A.ev_ct, A.batch_info,
+                                   A.carry_seg, A.seg_part, A.wchunk,
                                    A.lambda_out);
             else
                 hipLaunchKernelGGL((large_forward<false, false>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1, M,
                                    A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
-                                   A.carry_seg, A.seg_part, A.ev_rec, A.ev_ct, A.batch_info,
+                                   A.carry_seg, A.seg_part, A.wchunk,
                                    (float*)nullptr);
         }
         hipLaunchKernelGGL(large_chunk_acc, dim3(1), dim3(256), 0, st, nseg, A.seg_part, A.acc);
         if (A.grad) {
+            {
+                TimedScope tb(6, st);
+                bucket_chunk(A, c0, c1, nseg, A.wchunk, st);
+            }
             const int32_t spr = (nseg + A.ER - 1) / A.ER;
             const int32_t nbb = A.NB * A.NB;
             const unsigned nblk = A.ER >= 8 ? (unsigned)(nbb * ((A.ER + 7) / 8) * 8)
                                             : (unsigned)(((nbb + 8 / A.ER - 1) / (8 / A.ER)) * 8);
             TimedScope ts(0, st);
-            hipLaunchKernelGGL(large_dense, dim3(nblk), dim3(64), 0, st, c0, c1, M, A.NB, A.ER, spr, A.t, A.beta,
-                               A.carry_seg, A.ev_rec, A.ev_ct, A.batch_info, A.gpart, A.spart,
-                               A.cpart_);
+            hipLaunchKernelGGL(large_dense, dim3(nblk), dim3(64), 0, st, c0, c1, M, A.NB, A.ER, spr, nseg, A.T, A.t,
+                               A.beta, A.carry_seg, A.bk_off, A.bk_base, A.bk_key, A.bk_t, A.bk_w, A.gpart,
+                               A.spart, A.cpart_);
         }
     }
     const int64_t nfin = A.grad ? (MM > M ? MM : M) : 1;

@@ -30,6 +30,7 @@
 // right (seeded at T), and the dense adjoint kernel.
 #include "hk_device.h"
 #include "hk_large.h"
+#include "hk_stream.h"
 
 namespace hk {
 
@@ -194,12 +195,27 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
             while (k2 < nb && pt_rdl(off, k2) + pt_rdl(cn, k2) - o0 <= PT_STAGE) ++k2;
             const bool staged = pt_rdl(off, k) + pt_rdl(cn, k) - o0 <= PT_STAGE;
             if (staged) {
-                if (lane >= k && lane < k2) {
+                // short columns: each lane copies its own event's column;
+                // long ones: all lanes copy one column at a time (coalesced)
+                const bool mine = lane >= k && lane < k2;
+                if (mine && cn <= 32) {
                     for (int32_t j = 0; j < cn; ++j) {
                         const int32_t pr = csc_row[cb + j];
                         st_row[off - o0 + j] = pr;
                         st_val[off - o0 + j] = csc_val[cb + j];
                         st_bet[off - o0 + j] = beta[pr];
+                    }
+                }
+                uint64_t big = __ballot(mine && cn > 32);
+                while (big) {
+                    const int kk = __builtin_ctzll(big);
+                    big &= big - 1;
+                    const int32_t nk = pt_rdl(cn, kk), ok = pt_rdl(off, kk) - o0, bk = pt_rdl(cb, kk);
+                    for (int32_t j = lane; j < nk; j += 64) {
+                        const int32_t pr = csc_row[bk + j];
+                        st_row[ok + j] = pr;
+                        st_val[ok + j] = csc_val[bk + j];
+                        st_bet[ok + j] = beta[pr];
                     }
                 }
                 __syncthreads();
@@ -375,24 +391,31 @@ __global__ void pt_rscan_apply(int64_t c0, int64_t c1, int64_t n, double T, int3
 
 // Dense adjoint kernel.  Block = (target block rb, source block sb, event
 // range er), one wave; lane l owns target p = r0 + l and its adjoint state
-// A_p (float64), anchored at the last event of the current 64-event batch.
-// Batches are walked from the end of the range.  For every source event k in
-// the slab (m_k in sb), column m_k of the block takes beta_p A_p(t_k): the
-// anchored state decayed to t_k, plus the events of the same batch after k
-// whose target is in the block (one masked ds_add over those lanes).  Then
-// the batch's own-target events enter the state and the anchor moves to the
-// previous batch.  G is kept in LDS column-major (stride 65 against bank
-// conflicts).  Blocks with sb == 0 also sum w_i and w_i (R_i - beta_p D_i)
-// per target, blocks with rb == 0 count the events per source.
+// A_p (float64) from the events after the current read position, kept at an
+// anchor time.  The block reads only the bucketed records of its two node
+// blocks ("own": targets in rb; "slab": sources in sb), from the end of the
+// range backwards, merged by event index in windows of up to 64 + 64 records
+// (the window starts where either list's 64th record from the end is).  Per
+// window: A moves to the window's latest event time tw; every slab event k
+// adds to column m_k of the block beta_p A_p(t_k): the state decayed to t_k
+// plus the window's own-target events after k (one masked ds_add over those
+// lanes); then the window's own events enter A at its earliest event time.
+// G is kept in LDS column-major (stride 65 against bank conflicts).  Blocks
+// with sb == 0 also sum w_i per target, blocks with rb == 0 count the events
+// per source.
 __global__ __launch_bounds__(64) void pt_dense(int64_t c0, int64_t c1, int64_t n, double T, int32_t M, int32_t NB,
                                                int32_t ER, int32_t segs_per_range, int32_t nseg,
-                                               const double* __restrict__ t, const int32_t* __restrict__ marks,
-                                               const float* __restrict__ beta, const float* __restrict__ wv,
+                                               const double* __restrict__ t, const float* __restrict__ beta,
                                                const double* __restrict__ rcarry_seg,
-                                               const double* __restrict__ rgcarry, double* __restrict__ gpart,
+                                               const double* __restrict__ rgcarry,
+                                               const int32_t* __restrict__ bk_off,
+                                               const int32_t* __restrict__ bk_base,
+                                               const uint32_t* __restrict__ bk_key, const double* __restrict__ bk_t,
+                                               const float* __restrict__ bk_w, double* __restrict__ gpart,
                                                double* __restrict__ spart, double* __restrict__ npart) {
     __shared__ double G[HK_SLAB * 65];
     __shared__ double AL[64], SL[64], NL[64];
+    __shared__ float BL[64];
     const int lane = threadIdx.x;
     AL[lane] = 0.0;
     SL[lane] = 0.0;
@@ -414,12 +437,12 @@ __global__ __launch_bounds__(64) void pt_dense(int64_t c0, int64_t c1, int64_t n
     const int32_t sb = local % NB;
     const int32_t rb = local / NB;
     const int32_t r0 = rb * HK_RB, s0 = sb * HK_SLAB;
-    const int64_t a = c0 + (int64_t)er * segs_per_range * HK_SEG;
-    if (a >= c1) return;
-    const int64_t bnd = a + (int64_t)segs_per_range * HK_SEG;
-    const int64_t b = bnd < c1 ? bnd : c1;
+    const int32_t sA = er * segs_per_range;
+    if (sA >= nseg) return;
+    const int32_t sB = sA + segs_per_range < nseg ? sA + segs_per_range : nseg;
     const int32_t p = r0 + lane;
     const bool pv = p < M;
+    BL[lane] = pv ? beta[p] : 0.0f;
     double* gp = gpart + (int64_t)er * M * M;
     {
         // lanes over the block's columns (coalesced rows of gpart)
@@ -441,53 +464,58 @@ __global__ __launch_bounds__(64) void pt_dense(int64_t c0, int64_t c1, int64_t n
         }
     }
     const double bp = pv ? (double)beta[p] : 0.0;
-    // adjoint state from the events after the range (and the seed), at t[b-1]
+    // adjoint state from the events after the range (and the seed) at tau
+    const bool at_end = sB >= nseg;
+    double tau = seg_first_time(t, c0, c1, n, nseg, at_end ? nseg : sB, T);
     double Ah = 0.0;
-    {
-        const int32_t segb = (int32_t)((b - c0) / HK_SEG);
-        const bool at_end = b >= c1;
+    if (pv) {
         const int32_t ngr = (nseg + HK_SG - 1) / HK_SG;
-        const double tn = seg_first_time(t, c0, c1, n, nseg, at_end ? nseg : segb, T);
-        if (pv) {
-            const double Ae = at_end ? rgcarry[(int64_t)(ngr - 1) * M + p] : rcarry_seg[(int64_t)segb * M + p];
-            Ah = Ae * (double)exp_f64arg(-bp * (tn - t[b - 1]));
-        }
+        Ah = at_end ? rgcarry[(int64_t)(ngr - 1) * M + p] : rcarry_seg[(int64_t)sB * M + p];
     }
+    RecStream<true> O, S;
+    O.init(bk_key, bk_t, bk_w, (int64_t)bk_base[rb] + bk_off[(int64_t)rb * (nseg + 1) + sA],
+           (int64_t)bk_base[rb] + bk_off[(int64_t)rb * (nseg + 1) + sB]);
+    S.init(bk_key, bk_t, bk_w, (int64_t)bk_base[sb] + bk_off[(int64_t)sb * (nseg + 1) + sA],
+           (int64_t)bk_base[sb] + bk_off[(int64_t)sb * (nseg + 1) + sB]);
     __syncthreads();
-    const int64_t nbat = (b - a + 63) / 64;
-    for (int64_t kb = nbat - 1; kb >= 0; --kb) {
-        const int64_t bb = a + 64 * kb;
-        const int64_t be = bb + 64 < b ? bb + 64 : b;
-        const double tau = t[be - 1];
-        const int64_t j = bb + lane;
-        const bool vj = j < be;
-        const int64_t jc = vj ? j : be - 1;
-        const int mj = vj ? clamp_mark(marks[jc], M) : -1;
-        const double tj = t[jc];
-        const double wj = (double)wv[jc];
-        const bool own = vj && mj >= r0 && mj < r0 + HK_RB;
-        const bool sl = vj && mj >= s0 && mj < s0 + HK_SLAB;
-        const double bo = own ? (double)beta[mj] : 0.0;
-        uint64_t ms = __ballot(sl);
-        while (ms) {
-            const int k = __builtin_ctzll(ms);
-            ms &= ms - 1;
-            const int qk = pt_rdl(mj, k) - s0;
-            const double tk = pt_rdl_d(tj, k);
-            const double f = (double)exp_f64arg(-bp * (tau - tk));
-            atomicAdd(&G[qk * 65 + lane], bp * Ah * f);
-            if (own && lane > k)
-                atomicAdd(&G[qk * 65 + (mj - r0)], bo * wj * (double)exp_f64arg(-bo * (tj - tk)));
+    for (;;) {
+        const int64_t ao = O.avail(), as = S.avail();
+        if (ao <= 0 && as <= 0) break;
+        const int io = (int)(O.ck >> 6), is = (int)(S.ck >> 6);
+        const int lim_o = ao > 64 ? rl_i(io, 63) : -1;
+        const int lim_s = as > 64 ? rl_i(is, 63) : -1;
+        const int lo = lim_o > lim_s ? lim_o : lim_s;
+        const bool own = lane < ao && io >= lo;
+        const bool sl = lane < as && is >= lo;
+        const int no = __builtin_popcountll(__ballot(own));
+        const int ns = __builtin_popcountll(__ballot(sl));
+        double tw = -1e300, tl = 1e300;
+        if (no) { tw = rl_d(O.ct, 0); tl = rl_d(O.ct, no - 1); }
+        if (ns) {
+            const double a0 = rl_d(S.ct, 0), a1 = rl_d(S.ct, ns - 1);
+            tw = a0 > tw ? a0 : tw;
+            tl = a1 < tl ? a1 : tl;
         }
-        if (sb == 0 && own) atomicAdd(&SL[mj - r0], wj);
-        if (rb == 0 && sl) atomicAdd(&NL[mj - s0], 1.0);
-        if (kb > 0) {
-            const double tp = t[bb - 1];
-            if (own) atomicAdd(&AL[mj - r0], wj * (double)exp_f64arg(-bo * (tj - tp)));
-            __syncthreads();
-            Ah = __builtin_fma(Ah, (double)exp_f64arg(-bp * (tau - tp)), AL[lane]);
-            AL[lane] = 0.0;
+        Ah *= (double)exp_f64arg(-bp * (tau - tw));
+        const int pi = (int)(O.ck & 63u);
+        const double bo = (double)BL[pi];
+        const double wi = (double)O.cw;
+        for (int k = 0; k < ns; ++k) {
+            const int qoff = (int)(rl_i((int)S.ck, k) & 63) * 65;
+            const double tk = rl_d(S.ct, k);
+            const int ik = rl_i(is, k);
+            atomicAdd(&G[qoff + lane], bp * Ah * (double)exp_f64arg(-bp * (tw - tk)));
+            if (own && io > ik) atomicAdd(&G[qoff + pi], bo * wi * (double)exp_f64arg(-bo * (O.ct - tk)));
         }
+        if (sb == 0 && own) atomicAdd(&SL[pi], wi);
+        if (rb == 0 && sl) atomicAdd(&NL[S.ck & 63u], 1.0);
+        if (own) atomicAdd(&AL[pi], wi * (double)exp_f64arg(-bo * (O.ct - tl)));
+        __syncthreads();
+        Ah = __builtin_fma(Ah, (double)exp_f64arg(-bp * (tw - tl)), AL[lane]);
+        AL[lane] = 0.0;
+        tau = tl;
+        O.consume(no);
+        S.consume(ns);
     }
     __syncthreads();
     {
@@ -613,13 +641,18 @@ hawkes_status run_large_pt(LargeArgs& A, hipStream_t st) {
                 hipLaunchKernelGGL(pt_rscan_apply, dim3((unsigned)((napp + 255) / 256)), dim3(256), 0, st, c0, c1,
                                    A.n, A.T, nseg, M, A.t, A.beta, A.rgcarry, A.rcarry_seg);
             }
+            {
+                TimedScope tb(6, st);
+                bucket_chunk(A, c0, c1, nseg, A.wv + c0, st);
+            }
             const int32_t spr = (nseg + A.ER - 1) / A.ER;
             const int32_t nbb = A.NB * A.NB;
             const unsigned nblk = A.ER >= 8 ? (unsigned)(nbb * ((A.ER + 7) / 8) * 8)
                                             : (unsigned)(((nbb + 8 / A.ER - 1) / (8 / A.ER)) * 8);
             TimedScope ts(0, st);
-            hipLaunchKernelGGL(pt_dense, dim3(nblk), dim3(64), 0, st, c0, c1, A.n, A.T, M, A.NB, A.ER, spr, nseg,
-                               A.t, A.marks, A.beta, A.wv, A.rcarry_seg, A.rgcarry, A.gpart, A.spart, A.cpart_);
+            hipLaunchKernelGGL(pt_dense, dim3(nblk), dim3(64), 0, st, c0, c1, A.n, A.T, M, A.NB, A.ER, spr, nseg, A.t,
+                               A.beta, A.rcarry_seg, A.rgcarry, A.bk_off, A.bk_base, A.bk_key, A.bk_t, A.bk_w, A.gpart,
+                               A.spart, A.cpart_);
         }
     }
     const int64_t nfin = A.grad ? (MM > M ? MM : M) : 1;

@@ -29,7 +29,8 @@ def test_header_declares_expected_api():
     names = declared_functions()
     for f in ("hawkes_loglik", "hawkes_loglik_grad", "hawkes_loglik_batched", "hawkes_loglik_grad_batched",
               "hawkes_workspace_bytes", "hawkes_batched_workspace_bytes", "hawkes_sequential_loglik_grad",
-              "hawkes_intensity", "hawkes_check_inputs", "hawkes_status_string", "hawkes_version"):
+              "hawkes_intensity", "hawkes_check_inputs", "hawkes_status_string", "hawkes_version",
+              "hawkes_adam_state_bytes", "hawkes_adam_init", "hawkes_adam_step"):
         assert f in names
 
 
@@ -107,6 +108,23 @@ def test_host_argument_errors(H):
     pt = P(H, mode=1)
     assert L.hawkes_sequential_loglik_grad(ctypes.byref(pt), *args, FAKE, FAKE, FAKE, FAKE, 1 << 30, nul) == 4
     assert L.hawkes_check_inputs(ctypes.byref(p), FAKE, FAKE, FAKE, FAKE, FAKE, nul, nul) == 1
+    # Adam step: state size, missing state, bad configuration, short workspace
+    assert L.hawkes_adam_state_bytes(None) == 0
+    sb = L.hawkes_adam_state_bytes(ctypes.byref(p))
+    assert sb >= 256 + 8 * (p.m + p.m * p.m + 1)
+    assert L.hawkes_adam_init(ctypes.byref(p), nul, sb, nul) == 1
+    assert L.hawkes_adam_init(ctypes.byref(p), FAKE, 16, nul) == 2
+    good = H._Adam(0.05, 0.9, 0.999, 1e-8, 1e-6, 1e-6)
+    bad = H._Adam(0.0, 0.9, 0.999, 1e-8, 1e-6, 1e-6)
+    out4 = [FAKE] * 4
+    assert L.hawkes_adam_step(ctypes.byref(p), FAKE, FAKE, FAKE, FAKE, FAKE, ctypes.byref(bad), FAKE, sb, *out4,
+                              FAKE, 1 << 30, nul) == 1
+    assert L.hawkes_adam_step(ctypes.byref(p), FAKE, FAKE, FAKE, FAKE, FAKE, None, FAKE, sb, *out4,
+                              FAKE, 1 << 30, nul) == 1
+    assert L.hawkes_adam_step(ctypes.byref(p), FAKE, FAKE, FAKE, FAKE, FAKE, ctypes.byref(good), FAKE, 16, *out4,
+                              FAKE, 1 << 30, nul) == 2
+    assert L.hawkes_adam_step(ctypes.byref(p), FAKE, FAKE, FAKE, FAKE, FAKE, ctypes.byref(good), FAKE, sb, *out4,
+                              FAKE, 16, nul) == 2
 
 
 def test_binding_refuses_cpu_tensors(H):

@@ -1,0 +1,81 @@
+"""The fused maximum-likelihood step (hawkes_adam_step through the AdamMLE
+binding): Adam arithmetic against a NumPy restatement driven by the FP64
+oracle's gradients, and HIP-graph replays against eager steps."""
+import numpy as np
+import pytest
+
+import oracle
+from tests.helpers import rand_problem
+from tests.test_gpu_parity import H  # noqa: F401  (fixture)
+
+pytestmark = pytest.mark.gpu
+
+
+def _adam_reference(t, m, mu, al, be, T, steps, lr=0.05, b1=0.9, b2=0.999, eps=1e-8, floor=1e-6,
+                    per_target=False):
+    """Projected Adam on -L/n with the oracle's gradient; moments and
+    parameters rounded to float32 after each update, as the library stores
+    them."""
+    n = max(len(t), 1)
+    x = [mu.astype(np.float32).copy(), al.astype(np.float32).copy(), be.astype(np.float32).copy()]
+    lo = [floor, 0.0, floor]
+    mom = [np.zeros_like(v) for v in x]
+    vel = [np.zeros_like(v) for v in x]
+    traj = []
+    for k in range(1, steps + 1):
+        f = oracle.adjoint if per_target else oracle.forward
+        L, gmu, ga, gb = f(t, m, x[0], x[1], x[2], T)
+        grads = [np.asarray(gmu), np.reshape(ga, x[1].shape), np.reshape(gb, x[2].shape)]
+        c1, c2 = 1.0 - b1 ** k, 1.0 - b2 ** k
+        for j in range(3):
+            g = -grads[j] / n
+            mn = b1 * mom[j].astype(np.float64) + (1 - b1) * g
+            vn = b2 * vel[j].astype(np.float64) + (1 - b2) * g * g
+            mom[j] = mn.astype(np.float32)
+            vel[j] = vn.astype(np.float32)
+            xn = x[j].astype(np.float64) - lr * (mn / c1) / (np.sqrt(vn / c2) + eps)
+            x[j] = np.maximum(xn, lo[j]).astype(np.float32)
+        traj.append((L, [v.copy() for v in x]))
+    return traj
+
+
+@pytest.mark.parametrize("per_target,M", [(False, 3), (False, 40), (True, 20)])
+def test_adam_steps_match_reference(H, per_target, M):
+    import torch
+    t, m, mu, al, be, T = rand_problem(51 + M, 3000, M, per_target=per_target, density=0.5, rate=10.0)
+    ref = _adam_reference(t, m, mu, al, be, T, 4, per_target=per_target)
+    d = "cuda"
+    opt = H.AdamMLE(torch.as_tensor(t, device=d), torch.as_tensor(m, device=d), torch.as_tensor(mu, device=d),
+                    torch.as_tensor(al, device=d), torch.as_tensor(be, device=d), T)
+    for k, (Lr, xr) in enumerate(ref):
+        L = float(opt.step().item())
+        torch.cuda.synchronize()
+        assert abs(L - Lr) <= 1e-6 * abs(Lr), (k, L, Lr)
+        got = [opt.mu.cpu().numpy(), opt.alpha.cpu().numpy(), opt.beta.cpu().numpy()]
+        for g, r in zip(got, xr):
+            np.testing.assert_allclose(g, r, rtol=2e-6, atol=1e-7)
+
+
+@pytest.mark.parametrize("per_target", [False, True])
+def test_graph_replays_equal_eager_steps(H, per_target):
+    """A captured step, replayed several times with eager work and
+    synchronisations in between, must give bitwise the parameters and
+    log-likelihoods of the same number of eager steps."""
+    import torch
+    t, m, mu, al, be, T = rand_problem(61, 20000, 70, per_target=per_target, density=0.1, rate=20.0)
+    d = "cuda"
+    args = [torch.as_tensor(x, device=d) for x in (t, m, mu, al, be)]
+    eager = H.AdamMLE(*args, T, chunk_log2=12)
+    graph = H.AdamMLE(*args, T, chunk_log2=12)
+    Le = [float(eager.step().item())]
+    Lg = [float(graph.step().item())]
+    torch.cuda.synchronize()
+    graph.capture()
+    for k in range(4):
+        Le.append(float(eager.step().item()))
+        _ = torch.ones(1000, device=d).sum()   # unrelated eager work between replays
+        Lg.append(float(graph.replay().item()))
+        torch.cuda.synchronize()
+        assert Le[-1] == Lg[-1], (k, Le[-1], Lg[-1])
+        for a, b in ((eager.mu, graph.mu), (eager.alpha, graph.alpha), (eager.beta, graph.beta)):
+            assert torch.equal(a, b)
