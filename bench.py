@@ -77,7 +77,19 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-seq", action="store_true")
     ap.add_argument("--chunk-log2", type=int, default=20)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy three times (HBM counter calibration)")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copied {a.numel() * 4} bytes three times")
+        return 0
 
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is a design "
@@ -136,7 +148,7 @@ def main() -> int:
         f"min {per[0]:.3f}, max {per[-1]:.3f}; {value:.4e} events/s")
 
     dense_ms, dense_n = kt["dense_dalpha"]
-    src = source_hash("hk_large.hip", "hk_large.h", "hk_device.h")
+    src = source_hash("hk_dense.hip", "hk_large.h", "hk_device.h", "hk_stream.h")
     roofline = None
     if dense_n > 0:
         avg_ms = dense_ms / dense_n

@@ -5,7 +5,10 @@
 #include "hk_internal.h"
 
 #define HK_SEG 2048        // events per forward segment (one wave)
-#define HK_RB 64           // rows per dense-gradient block
+#define HK_RB 64           // targets per block of the per-target (adjoint) dense kernel
+#ifndef HK_DR
+#define HK_DR 16           // rows per block of the shared-decay dense kernel
+#endif
 #define HK_SLAB 64         // columns per dense-gradient block (one per lane)
 #define HK_WIDE 60.0       // anchored-exponent limit inside one window of the dense kernel
 
@@ -20,7 +23,8 @@ struct LargeArgs {
     int64_t nchunks;
     int32_t nseg;         // segments per chunk
     int32_t ER;           // event ranges of the dense kernel per chunk
-    int32_t NB;           // node blocks of 64 (rows and columns)
+    int32_t NB;           // node blocks of 64 (bucketing; columns of the dense kernels)
+    int32_t NBR;          // row blocks of the dense kernel (HK_DR rows shared decay, HK_RB per target)
     bool grad;
     const double* t;
     const int32_t* marks;
@@ -78,6 +82,7 @@ void large_build_index(int32_t M, const float* alpha, int trans, int32_t* ptr, i
 void large_scan(LargeArgs& A, int32_t nseg, const float* beta_pt, hipStream_t st);
 void large_chunk_acc_launch(int32_t nseg, const double* seg_part, double* acc, hipStream_t st);
 void bucket_chunk(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, const float* wchunk, hipStream_t st);
+void large_dense_launch(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, hipStream_t st);
 
 size_t seq_workspace_bytes(const hawkes_problem* p);
 hawkes_status run_sequential(const hawkes_problem* p, const double* t, const int32_t* marks, const float* mu,

@@ -28,7 +28,6 @@
 //            multiply-add per column; rows accumulate in float64 LDS.
 #include "hk_device.h"
 #include "hk_large.h"
-#include "hk_stream.h"
 #include <stdlib.h>
 #include <mutex>
 
@@ -40,13 +39,23 @@ __global__ void fill_d(double* p, int64_t n, double v) {
         p[i] = v;
 }
 
-// colsum[q] = sum_p alpha[p][q] (thread per column, coalesced over q)
-__global__ void large_colsum(int32_t M, const float* __restrict__ alpha, float* __restrict__ colsum) {
-    const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= M) return;
+// colsum[q] = sum_p alpha[p][q]: a workgroup of 16 waves per 64 columns,
+// wave r sums rows r, r+16, ... (coalesced over q), then a fixed-order sum
+__global__ __launch_bounds__(1024) void large_colsum(int32_t M, const float* __restrict__ alpha,
+                                                     float* __restrict__ colsum) {
+    __shared__ double part[16][64];
+    const int lane = threadIdx.x & 63, r = threadIdx.x >> 6;
+    const int32_t q = blockIdx.x * 64 + lane;
     double c = 0.0;
-    for (int32_t p = 0; p < M; ++p) c += (double)alpha[(int64_t)p * M + q];
-    colsum[q] = (float)c;
+    if (q < M)
+        for (int32_t p = r; p < M; p += 16) c += (double)alpha[(int64_t)p * M + q];
+    part[r][lane] = c;
+    __syncthreads();
+    if (r == 0 && q < M) {
+        double v = 0.0;
+        for (int k = 0; k < 16; ++k) v += part[k][lane];
+        colsum[q] = (float)v;
+    }
 }
 
 // csr_ptr[p+1] = nnz of row p (one wave per row, coalesced).  With trans != 0
@@ -401,187 +410,6 @@ __global__ __launch_bounds__(256) void large_chunk_acc(int32_t nseg, const doubl
     }
 }
 
-// ------------------------------------------------------------------ dense dL/dalpha
-// Block = (row block rb, column block sb, event range er), one wave.  LDS
-// G[64][64] float64 accumulates sum_i beta w_i K_q(t_i) for the block's rows
-// p (targets, m_i in rb) and columns q (sources in sb); lane c owns column
-// s0 + c and its state K (float64), kept in the frame of an anchor time.
-// The block reads only the events of its two node blocks (the bucketed
-// records of rb: "own" events, and of sb: "slab" events), merged by event
-// index in windows of up to 64 + 64 records:
-//   - the window ends where either list's 64th record ends (hi), so every own
-//     event of the window sees all earlier slab events either in K or in the
-//     window;
-//   - K moves to the window's first event time tw; own event k adds
-//     c_k * K to row m_k (c_k = beta w_k e^{-beta (t_k - tw)}, one ds_add_f64
-//     over the 64 columns) plus c_k * b_j at (m_k, m_j) for the window's
-//     slab events j before it (b_j = e^{beta (t_j - tw)}, one masked
-//     ds_add_f64 over those lanes): together c_k times K just before event k;
-//   - then the slab events enter K in one vector step (scatter-add into LDS by
-//     column, read back by each column's lane), and row block 0 sums w and
-//     the compensator terms 1 - e^{-beta (T - t_j)} per column the same way.
-// A window whose time span exceeds HK_WIDE / beta (anchored factors would
-// leave float32 range) is walked event by event with per-event decays.
-// Blocks of one event range are placed on one XCD (blockIdx % 8).
-__global__ __launch_bounds__(64) void large_dense(int64_t c0, int64_t c1, int32_t M, int32_t NB, int32_t ER,
-                                                  int32_t segs_per_range, int32_t nseg, double T,
-                                                  const double* __restrict__ t, const float* __restrict__ beta,
-                                                  const double* __restrict__ carry_seg,
-                                                  const int32_t* __restrict__ bk_off,
-                                                  const int32_t* __restrict__ bk_base,
-                                                  const uint32_t* __restrict__ bk_key, const double* __restrict__ bk_t,
-                                                  const float* __restrict__ bk_w, double* __restrict__ gpart,
-                                                  double* __restrict__ spart, double* __restrict__ cpart) {
-    __shared__ double G[HK_RB * HK_SLAB];
-    __shared__ double KhL[HK_SLAB], SL[HK_SLAB], CL[HK_SLAB];
-    const int lane = threadIdx.x;
-    KhL[lane] = 0.0;
-    SL[lane] = 0.0;
-    CL[lane] = 0.0;
-    const int32_t blk = blockIdx.x;
-    const int32_t nbb = NB * NB;
-    int32_t er, local;
-    if (ER >= 8) {
-        const int32_t slot = blk >> 3;
-        er = (slot / nbb) * 8 + (blk & 7);
-        local = slot % nbb;
-    } else {
-        // 8 / ER XCDs share one event range
-        const int32_t per = 8 / ER, x = blk & 7;
-        er = x / per;
-        local = (blk >> 3) * per + x % per;
-        if (local >= nbb) return;
-    }
-    if (er >= ER) return;
-    const int32_t sb = local % NB;
-    const int32_t rb = local / NB;
-    const int32_t r0 = rb * HK_RB, s0 = sb * HK_SLAB;
-    const int32_t sA = er * segs_per_range;
-    if (sA >= nseg) return;
-    const int32_t sB = sA + segs_per_range < nseg ? sA + segs_per_range : nseg;
-    const int64_t a = c0 + (int64_t)sA * HK_SEG;
-    const int32_t col = s0 + lane;
-    double* gp = gpart + (int64_t)er * M * M;
-    {
-        // branch-free block load (all loads in flight together); out-of-range
-        // rows/columns read a clamped valid address and are zeroed
-        const int32_t cc = col < M ? col : M - 1;
-        for (int rg = 0; rg < HK_RB; rg += 16) {
-            double v[16];
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const int32_t row = r0 + rg + j;
-                const int32_t rr = row < M ? row : M - 1;
-                v[j] = gp[(int64_t)rr * M + cc];
-            }
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const int32_t row = r0 + rg + j;
-                G[(rg + j) * HK_SLAB + lane] = (row < M && col < M) ? v[j] : 0.0;
-            }
-        }
-    }
-    const double bet = (double)beta[0];
-    // K at the range start (just after the event before it)
-    double Kh = col < M ? carry_seg[(int64_t)sA * 2 * M + col] : 0.0;
-    double tau = a > 0 ? t[a - 1] : t[a];
-    double Sacc = 0.0, Cacc = 0.0;
-    const bool diag_owner = rb == 0;
-    RecStream<false> O, S;
-    O.init(bk_key, bk_t, bk_w, (int64_t)bk_base[rb] + bk_off[(int64_t)rb * (nseg + 1) + sA],
-           (int64_t)bk_base[rb] + bk_off[(int64_t)rb * (nseg + 1) + sB]);
-    S.init(bk_key, bk_t, bk_w, (int64_t)bk_base[sb] + bk_off[(int64_t)sb * (nseg + 1) + sA],
-           (int64_t)bk_base[sb] + bk_off[(int64_t)sb * (nseg + 1) + sB]);
-    __syncthreads();
-    for (;;) {
-        const int64_t ao = O.avail(), as = S.avail();
-        if (ao <= 0 && as <= 0) break;
-        const int io = (int)(O.ck >> 6), is = (int)(S.ck >> 6);
-        const int lim_o = ao > 64 ? rl_i(io, 63) : 0x7fffffff;
-        const int lim_s = as > 64 ? rl_i(is, 63) : 0x7fffffff;
-        const int hi = lim_o < lim_s ? lim_o : lim_s;
-        const bool own = lane < ao && io <= hi;
-        const bool sl = lane < as && is <= hi;
-        const int no = __builtin_popcountll(__ballot(own));
-        const int ns = __builtin_popcountll(__ballot(sl));
-        double tw = 1e300, te = -1e300;
-        if (no) { tw = rl_d(O.ct, 0); te = rl_d(O.ct, no - 1); }
-        if (ns) {
-            const double a0 = rl_d(S.ct, 0), a1 = rl_d(S.ct, ns - 1);
-            tw = a0 < tw ? a0 : tw;
-            te = a1 > te ? a1 : te;
-        }
-        Kh *= (double)exp_f64arg(-bet * (tw - tau));
-        tau = tw;
-        const int colj = (int)(S.ck & 63u);
-        if (bet * (te - tw) <= HK_WIDE) {
-            const float cf = own ? (float)(bet * (double)O.cw) * exp_f64arg(-bet * (O.ct - tw)) : 0.0f;
-            const double bj = sl ? (double)exp_f64arg(bet * (S.ct - tw)) : 0.0;
-            for (int k = 0; k < no; ++k) {
-                const int rowoff = (int)(rl_i((int)O.ck, k) & 63) * HK_SLAB;
-                const int ik = rl_i(io, k);
-                const double ck = (double)rl_f(cf, k);
-                atomicAdd(&G[rowoff + lane], ck * Kh);
-                if (sl && is < ik) atomicAdd(&G[rowoff + colj], ck * bj);
-            }
-            if (ns) {
-                if (sl) {
-                    atomicAdd(&KhL[colj], bj);
-                    if (diag_owner) {
-                        atomicAdd(&SL[colj], (double)S.cw);
-                        atomicAdd(&CL[colj], -expm1(-bet * (T - S.ct)));
-                    }
-                }
-                __syncthreads();
-                Kh += KhL[lane];
-                KhL[lane] = 0.0;
-            }
-        } else {
-            int ko = 0, ks = 0;
-            while (ko < no || ks < ns) {
-                const int iko = ko < no ? rl_i(io, ko) : 0x7fffffff;
-                const int iks = ks < ns ? rl_i(is, ks) : 0x7fffffff;
-                if (iko <= iks) {
-                    // own first on a tie: the same event as slab event comes after
-                    const double tk = rl_d(O.ct, ko);
-                    Kh *= (double)exp_f64arg(-bet * (tk - tau));
-                    tau = tk;
-                    const int rowoff = (int)(rl_i((int)O.ck, ko) & 63) * HK_SLAB;
-                    atomicAdd(&G[rowoff + lane], bet * (double)rl_f(O.cw, ko) * Kh);
-                    ++ko;
-                } else {
-                    const double tk = rl_d(S.ct, ks);
-                    Kh *= (double)exp_f64arg(-bet * (tk - tau));
-                    tau = tk;
-                    const int ck = (int)(rl_i((int)S.ck, ks) & 63);
-                    if (lane == ck) {
-                        Kh += 1.0;
-                        if (diag_owner) {
-                            Sacc += (double)rl_f(S.cw, ks);
-                            Cacc += -expm1(-bet * (T - tk));
-                        }
-                    }
-                    ++ks;
-                }
-            }
-        }
-        O.consume(no);
-        S.consume(ns);
-    }
-    __syncthreads();
-    if (col < M) {
-#pragma unroll 16
-        for (int r = 0; r < HK_RB; ++r) {
-            const int32_t row = r0 + r;
-            if (row < M) gp[(int64_t)row * M + col] = G[r * HK_SLAB + lane];
-        }
-    }
-    if (diag_owner && col < M) {
-        spart[(int64_t)er * M + col] += Sacc + SL[lane];
-        cpart[(int64_t)er * M + col] += Cacc + CL[lane];
-    }
-}
-
 // ------------------------------------------------------------------ finalize
 __global__ void large_final(int32_t M, int32_t ER, double T, const float* __restrict__ mu,
                             const double* __restrict__ acc, const double* __restrict__ gpart,
@@ -624,11 +452,14 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
     A.nchunks = (A.n + A.CH - 1) / A.CH;
     A.nseg = (int32_t)((A.CH + HK_SEG - 1) / HK_SEG);
     A.NB = (A.M + 63) / 64;
+    A.NBR = A.per_target ? A.NB : (A.M + HK_DR - 1) / HK_DR;
     // event ranges per chunk for the dense kernel: a power of two so that the
-    // ranges map onto the 8 XCDs evenly; about 2048 blocks in total unless
-    // HAWKES_DENSE_ER (a power of two) overrides it
-    const int64_t nbb = (int64_t)A.NB * A.NB;
-    const int64_t want = (2048 + nbb - 1) / nbb;
+    // ranges map onto the 8 XCDs evenly; about 4096 blocks in total (shared
+    // decay: 17 KiB of LDS each, four per SIMD) or 2048 (per target, 34 KiB)
+    // unless HAWKES_DENSE_ER (a power of two) overrides it
+    const int64_t nbb = (int64_t)A.NBR * A.NB;
+    const int64_t target = A.per_target ? 2048 : 4096;
+    const int64_t want = (target + nbb - 1) / nbb;
     int32_t er = 1;
     while (er < want) er <<= 1;
     if (const char* e = getenv("HAWKES_DENSE_ER")) {
@@ -771,7 +602,7 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
         hipLaunchKernelGGL(fill_d, dim3(64), dim3(256), 0, st, A.spart, (int64_t)A.ER * M, 0.0);
         hipLaunchKernelGGL(fill_d, dim3(64), dim3(256), 0, st, A.cpart_, (int64_t)A.ER * M, 0.0);
     }
-    hipLaunchKernelGGL(large_colsum, dim3(gM), dim3(256), 0, st, M, A.alpha, A.colsum);
+    hipLaunchKernelGGL(large_colsum, dim3((unsigned)((M + 63) / 64)), dim3(1024), 0, st, M, A.alpha, A.colsum);
     large_build_index(M, A.alpha, 0, A.csr_ptr, A.csr_col, A.csr_val, st);
     hipLaunchKernelGGL(large_node_info, dim3(gM), dim3(256), 0, st, M, A.csr_ptr, A.mu, A.colsum, A.node_info);
     for (int64_t ch = 0; ch < A.nchunks; ++ch) {
@@ -811,14 +642,8 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
                 TimedScope tb(6, st);
                 bucket_chunk(A, c0, c1, nseg, A.wchunk, st);
             }
-            const int32_t spr = (nseg + A.ER - 1) / A.ER;
-            const int32_t nbb = A.NB * A.NB;
-            const unsigned nblk = A.ER >= 8 ? (unsigned)(nbb * ((A.ER + 7) / 8) * 8)
-                                            : (unsigned)(((nbb + 8 / A.ER - 1) / (8 / A.ER)) * 8);
             TimedScope ts(0, st);
-            hipLaunchKernelGGL(large_dense, dim3(nblk), dim3(64), 0, st, c0, c1, M, A.NB, A.ER, spr, nseg, A.T, A.t,
-                               A.beta, A.carry_seg, A.bk_off, A.bk_base, A.bk_key, A.bk_t, A.bk_w, A.gpart,
-                               A.spart, A.cpart_);
+            large_dense_launch(A, c0, c1, nseg, st);
         }
     }
     const int64_t nfin = A.grad ? (MM > M ? MM : M) : 1;
