@@ -33,17 +33,16 @@
  *  - Outputs are float64: loglik[1], g_mu[m], g_alpha[m*m] (same layout as
  *    alpha), g_beta[1] (shared) or g_beta[m] (per target).  Any gradient
  *    pointer may be NULL to skip that output.
- *  - Precision: time differences are formed in float64.  Shared decay,
- *    m > 8 (the large-M engine): decays, the forward state and intensities
- *    are float32, the dense-gradient state float64.  Shared decay, m <= 8:
- *    the few state values per lane are kept in float64.  Decay per target
- *    (any m): the forward pass (state, decays, intensities) is float64; the
- *    reverse pass for dL/dalpha uses float32 decays on a float64 state.
+ *  - Precision: time differences are formed in float64.  The forward pass
+ *    (state, decays, intensities, log-likelihood and the dL/dmu, dL/dbeta
+ *    terms) is float64 in every mode.  The dense dL/dalpha kernels keep a
+ *    float64 state and float64 accumulators with float32 decay factors
+ *    (each exponent is formed and range-reduced in float64).
  *    Every sum over events (log-likelihood, gradients) is accumulated in
  *    float64 in a fixed order, so repeated calls return bitwise-identical
  *    results.
  *  - Size limits (LDS per workgroup, read from the device; 160 KiB on
- *    MI355X): shared decay m <= 6826, decay per target m <= 4352; larger m
+ *    MI355X): shared decay m <= 5120, decay per target m <= 4352; larger m
  *    returns HAWKES_EUNSUPPORTED.  The per-target gradient also keeps one
  *    float32 per event (4 bytes x n) in the workspace for its reverse pass.
  *  - Errors: every function returns a hawkes_status.  Host-detectable

@@ -1,4 +1,4 @@
-// Per-chunk partition of the events by node block (64 nodes per block),
+// Per-chunk partition of the events by node block (64 or 128 nodes per block),
 // stable in event order: a counting sort in three steps.
 //   count    one wave per segment: events per (block, segment)
 //   scan     one workgroup per block: start of every (block, segment) run
@@ -9,7 +9,8 @@
 //            block in the same 64-event batch comes from bit-sliced ballots
 //            (one ballot per bit of the block number), plus the block's
 //            running count in LDS
-// Records: key = (event index in the chunk) << 6 | (mark mod 64), t (float64),
+// Records: key = (event index in the chunk) << bs | (mark mod 2^bs) for blocks
+// of 2^bs nodes (bs = 6 or 7), t (float64),
 // w = 1 / lambda (float32).  The dense-gradient kernels stream the records of
 // two blocks (the block of their rows and the block of their columns)
 // instead of filtering every event of the chunk.
@@ -18,7 +19,7 @@
 
 namespace hk {
 
-__global__ __launch_bounds__(64) void bucket_count(int64_t c0, int64_t c1, int32_t M, int32_t NB,
+__global__ __launch_bounds__(64) void bucket_count(int64_t c0, int64_t c1, int32_t M, int32_t NB, int32_t bs,
                                                    const int32_t* __restrict__ marks, int32_t nseg,
                                                    int32_t* __restrict__ cnt) {
     extern __shared__ int32_t lc[];
@@ -28,7 +29,7 @@ __global__ __launch_bounds__(64) void bucket_count(int64_t c0, int64_t c1, int32
     __syncthreads();
     const int64_t a = c0 + (int64_t)s * HK_SEG;
     const int64_t b = a + HK_SEG < c1 ? a + HK_SEG : c1;
-    for (int64_t i = a + lane; i < b; i += 64) atomicAdd(&lc[clamp_mark(marks[i], M) >> 6], 1);
+    for (int64_t i = a + lane; i < b; i += 64) atomicAdd(&lc[clamp_mark(marks[i], M) >> bs], 1);
     __syncthreads();
     for (int32_t k = lane; k < NB; k += 64) cnt[(int64_t)k * nseg + s] = lc[k];
 }
@@ -71,6 +72,7 @@ __global__ void bucket_base(int32_t NB, int32_t nseg, const int32_t* __restrict_
 }
 
 __global__ __launch_bounds__(64) void bucket_scatter(int64_t c0, int64_t c1, int32_t M, int32_t NB, int32_t nbits,
+                                                     int32_t bs,
                                                      const double* __restrict__ t,
                                                      const int32_t* __restrict__ marks,
                                                      const float* __restrict__ wchunk, int32_t nseg,
@@ -91,7 +93,7 @@ __global__ __launch_bounds__(64) void bucket_scatter(int64_t c0, int64_t c1, int
         const bool v = i < b;
         const int64_t ic = v ? i : b - 1;
         const int mk = clamp_mark(marks[ic], M);
-        const int blk = mk >> 6;
+        const int blk = mk >> bs;
         // lanes with the same block: agree on every bit of the block number
         uint64_t same = __ballot(v);
         for (int bit = 0; bit < nbits; ++bit) {
@@ -102,7 +104,7 @@ __global__ __launch_bounds__(64) void bucket_scatter(int64_t c0, int64_t c1, int
         const int32_t before = run[blk];
         if (v) {
             const int64_t pos = (int64_t)bbase[blk] + boff[(int64_t)blk * (nseg + 1) + s] + before + rank;
-            bk_key[pos] = ((uint32_t)(i - c0) << 6) | (uint32_t)(mk & 63);
+            bk_key[pos] = ((uint32_t)(i - c0) << bs) | (uint32_t)(mk & ((1 << bs) - 1));
             bk_t[pos] = t[i];
             bk_w[pos] = wchunk[i - c0];
         }
@@ -112,14 +114,17 @@ __global__ __launch_bounds__(64) void bucket_scatter(int64_t c0, int64_t c1, int
     }
 }
 
-void bucket_chunk(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, const float* wchunk, hipStream_t st) {
+// bs: log2 of the block width (6: 64 nodes, 7: 128 nodes; keys need
+// (events per chunk) << bs < 2^32)
+void bucket_chunk(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, const float* wchunk, int bs, hipStream_t st) {
+    const int32_t nb = (A.M + (1 << bs) - 1) >> bs;
     int nbits = 0;
-    while ((1 << nbits) < A.NB) ++nbits;
-    const size_t lds = (size_t)A.NB * sizeof(int32_t);
-    hipLaunchKernelGGL(bucket_count, dim3(nseg), dim3(64), lds, st, c0, c1, A.M, A.NB, A.marks, nseg, A.bk_cnt);
-    hipLaunchKernelGGL(bucket_scan, dim3(A.NB), dim3(256), 0, st, nseg, A.bk_cnt, A.bk_off);
-    hipLaunchKernelGGL(bucket_base, dim3(1), dim3(64), 0, st, A.NB, nseg, A.bk_off, A.bk_base);
-    hipLaunchKernelGGL(bucket_scatter, dim3(nseg), dim3(64), lds, st, c0, c1, A.M, A.NB, nbits, A.t, A.marks, wchunk,
+    while ((1 << nbits) < nb) ++nbits;
+    const size_t lds = (size_t)nb * sizeof(int32_t);
+    hipLaunchKernelGGL(bucket_count, dim3(nseg), dim3(64), lds, st, c0, c1, A.M, nb, bs, A.marks, nseg, A.bk_cnt);
+    hipLaunchKernelGGL(bucket_scan, dim3(nb), dim3(256), 0, st, nseg, A.bk_cnt, A.bk_off);
+    hipLaunchKernelGGL(bucket_base, dim3(1), dim3(64), 0, st, nb, nseg, A.bk_off, A.bk_base);
+    hipLaunchKernelGGL(bucket_scatter, dim3(nseg), dim3(64), lds, st, c0, c1, A.M, nb, nbits, bs, A.t, A.marks, wchunk,
                        nseg, A.bk_off, A.bk_base, A.bk_key, A.bk_t, A.bk_w);
 }
 

@@ -26,6 +26,35 @@ __device__ __forceinline__ float exp_f64arg(double x) {
     return __builtin_ldexpf(e, ki);
 }
 
+// e^x in float64 for x <= 0 (the decays of the forward passes).  Cody-Waite
+// reduction x = k ln2 + r with |r| <= ln2/2 (ln2 split in two parts), then
+// the Taylor series of e^r through r^12 / 12! by Horner's rule (truncation
+// below 2e-16 relative for |r| <= ln2/2), scaled by 2^k.  Below -708 the
+// result is 0 (float64 underflow).
+__device__ __forceinline__ double exp_f64(double x) {
+    const double kLog2e = 1.4426950408889634;
+    const double kLn2Hi = 6.93147180369123816490e-01;
+    const double kLn2Lo = 1.90821492927058770002e-10;
+    const double k = __builtin_rint(x * kLog2e);
+    double r = __builtin_fma(-k, kLn2Hi, x);
+    r = __builtin_fma(-k, kLn2Lo, r);
+    double p = 1.0 / 479001600.0;             // 1/12!
+    p = __builtin_fma(p, r, 1.0 / 39916800.0);  // 1/11!
+    p = __builtin_fma(p, r, 1.0 / 3628800.0);
+    p = __builtin_fma(p, r, 1.0 / 362880.0);
+    p = __builtin_fma(p, r, 1.0 / 40320.0);
+    p = __builtin_fma(p, r, 1.0 / 5040.0);
+    p = __builtin_fma(p, r, 1.0 / 720.0);
+    p = __builtin_fma(p, r, 1.0 / 120.0);
+    p = __builtin_fma(p, r, 1.0 / 24.0);
+    p = __builtin_fma(p, r, 1.0 / 6.0);
+    p = __builtin_fma(p, r, 0.5);
+    p = __builtin_fma(p, r, 1.0);
+    p = __builtin_fma(p, r, 1.0);
+    const double v = __builtin_ldexp(p, (int)k);
+    return x < -708.0 ? 0.0 : v;
+}
+
 // wave-uniform value from lane 0
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 

@@ -4,7 +4,9 @@
 #include <stdint.h>
 #include "hk_internal.h"
 
-#define HK_SEG 2048        // events per forward segment (one wave)
+#ifndef HK_SEG
+#define HK_SEG 1024        // events per forward segment (one wave)
+#endif
 #define HK_RB 64           // targets per block of the per-target (adjoint) dense kernel
 #ifndef HK_DR
 #define HK_DR 16           // rows per block of the shared-decay dense kernel
@@ -25,6 +27,8 @@ struct LargeArgs {
     int32_t ER;           // event ranges of the dense kernel per chunk
     int32_t NB;           // node blocks of 64 (bucketing; columns of the dense kernels)
     int32_t NBR;          // row blocks of the dense kernel (HK_DR rows shared decay, HK_RB per target)
+    int32_t CPL;          // columns per lane of the shared-decay dense kernel (1 or 2)
+    int32_t NBC;          // column blocks of the dense kernel (64 CPL columns each)
     bool grad;
     const double* t;
     const int32_t* marks;
@@ -60,7 +64,7 @@ struct LargeArgs {
     int32_t* bk_cnt;      // [NB][nseg] events per (block, segment)
     int32_t* bk_off;      // [NB][nseg + 1] start of each (block, segment) run within the block
     int32_t* bk_base;     // [NB] start of each block in the records
-    uint32_t* bk_key;     // [CH] (index in chunk) << 6 | mark mod 64
+    uint32_t* bk_key;     // [CH] (index in chunk) << bs | mark mod 2^bs (blocks of 2^bs nodes)
     double* bk_t;         // [CH] event time
     float* bk_w;          // [CH] 1 / lambda
     float* wchunk;        // [CH] 1 / lambda of the chunk's events (shared decay)
@@ -81,7 +85,7 @@ void large_build_index(int32_t M, const float* alpha, int trans, int32_t* ptr, i
                        hipStream_t st);
 void large_scan(LargeArgs& A, int32_t nseg, const float* beta_pt, hipStream_t st);
 void large_chunk_acc_launch(int32_t nseg, const double* seg_part, double* acc, hipStream_t st);
-void bucket_chunk(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, const float* wchunk, hipStream_t st);
+void bucket_chunk(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, const float* wchunk, int bs, hipStream_t st);
 void large_dense_launch(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, hipStream_t st);
 
 size_t seq_workspace_bytes(const hawkes_problem* p);

@@ -152,10 +152,10 @@ __global__ __launch_bounds__(64) void large_seg_agg(int64_t c0, int64_t c1, int3
         const int64_t i = base + lane;
         if (i < b) {
             const double d = te - t[i];
-            const float e = exp_f64arg(-bet * d);
+            const double e = exp_f64(-bet * d);
             const int mi = clamp_mark(marks[i], M);
-            atomicAdd(&aK[mi], (double)e);
-            atomicAdd(&aJ[mi], d * (double)e);
+            atomicAdd(&aK[mi], e);
+            atomicAdd(&aJ[mi], d * e);
         }
     }
     __syncthreads();
@@ -272,8 +272,8 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
     extern __shared__ double lds[];
     double* rtau = lds;                                   // [M] time of the record
     uint64_t* rmask = (uint64_t*)(lds + M);               // [M] lanes of this batch with mark q
-    float* rK = (float*)(lds + 2 * M);                    // [M] K_q at rtau (event included)
-    float* rJ = rK + M;                                   // [M] J_q at rtau
+    double* rK = lds + 2 * M;                             // [M] K_q at rtau (event included)
+    double* rJ = lds + 3 * M;                             // [M] J_q at rtau
     __shared__ double tb[64];
     const int32_t s = blockIdx.x;
     const int lane = threadIdx.x;
@@ -285,8 +285,8 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
     const double* cs = carry_seg + (int64_t)s * 2 * M;
     for (int32_t q = lane; q < M; q += 64) {
         rtau[q] = tref;
-        rK[q] = (float)cs[q];
-        rJ[q] = (float)cs[M + q];
+        rK[q] = cs[q];
+        rJ[q] = cs[M + q];
         rmask[q] = 0ull;
     }
     __syncthreads();
@@ -310,7 +310,7 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
         tb[lane] = ti;
         if (valid) atomicOr((unsigned long long*)&rmask[mi], 1ull << lane);
         __syncthreads();
-        float R = 0.0f, Dd = 0.0f, lam = 1.0f, w = 0.0f, em1 = 0.0f;
+        double R = 0.0, Dd = 0.0, lam = 1.0, w = 0.0, em1 = 0.0;
         if (valid) {
             const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
             const int32_t k0 = ni.x, k1 = ni.y;
@@ -328,52 +328,51 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
                     if (qv[j] < 0) continue;
                     const int32_t q = qv[j];
                     const double d = ti - rtau[q];
-                    const float e = exp_f64arg(-bet * d);
-                    const float kq = rK[q];
-                    float Kv = e * kq;
-                    float Jv = GRAD ? e * __builtin_fmaf((float)d, kq, rJ[q]) : 0.0f;
+                    const double e = exp_f64(-bet * d);
+                    const double kq = rK[q];
+                    double Kv = e * kq;
+                    double Jv = GRAD ? e * __builtin_fma(d, kq, rJ[q]) : 0.0;
                     uint64_t bits = rmask[q] & below;
                     while (bits) {
                         const int jj = __builtin_ctzll(bits);
                         bits &= bits - 1;
                         const double dj = ti - tb[jj];
-                        const float ej = exp_f64arg(-bet * dj);
+                        const double ej = exp_f64(-bet * dj);
                         Kv += ej;
-                        if (GRAD) Jv = __builtin_fmaf((float)dj, ej, Jv);
+                        if (GRAD) Jv = __builtin_fma(dj, ej, Jv);
                     }
-                    R = __builtin_fmaf(av[j], Kv, R);
-                    if (GRAD) Dd = __builtin_fmaf(av[j], Jv, Dd);
+                    R = __builtin_fma((double)av[j], Kv, R);
+                    if (GRAD) Dd = __builtin_fma((double)av[j], Jv, Dd);
                 }
             }
-            lam = __builtin_fmaf(betf, R, __int_as_float(ni.z));
-            if (INTENS) lambda_out[i] = lam;
-            logsum += (double)__logf(lam);
+            lam = __builtin_fma(bet, R, (double)__int_as_float(ni.z));
+            if (INTENS) lambda_out[i] = (float)lam;
+            logsum += log(lam);
             const double x = bet * (T - ti);
-            em1 = -expm1f(-(float)x);   // 1 - e^{-x}
-            const float cs_m = __int_as_float(ni.w);
-            comp += (double)cs_m * (double)em1;
+            em1 = -expm1(-x);   // 1 - e^{-x}
+            const double cs_m = (double)__int_as_float(ni.w);
+            comp += cs_m * em1;
             if (GRAD) {
-                w = 1.0f / lam;
-                gb += (double)w * ((double)R - bet * (double)Dd);
-                const float ex = exp_f64arg(-x);
-                Esum += (double)cs_m * (T - ti) * (double)ex;
+                w = 1.0 / lam;
+                gb += w * (R - bet * Dd);
+                Esum += cs_m * (T - ti) * exp_f64(-x);
             }
         }
-        if (GRAD && valid) wchunk[i - c0] = w;
+        if (GRAD && valid) wchunk[i - c0] = (float)w;
         __syncthreads();
         // lazy record update, one leader lane per node, events in index order
         if (valid) {
             uint64_t grp = rmask[mi];
             if (__builtin_ctzll(grp) == lane) {
                 double tq = rtau[mi];
-                float kq = rK[mi], jq = rJ[mi];
+                double kq = rK[mi], jq = rJ[mi];
                 while (grp) {
                     const int j = __builtin_ctzll(grp);
                     grp &= grp - 1;
                     const double d = tb[j] - tq;
-                    const float e = exp_f64arg(-bet * d);
-                    jq = e * __builtin_fmaf((float)d, kq, jq);
-                    kq = __builtin_fmaf(e, kq, 1.0f);
+                    const double e = exp_f64(-bet * d);
+                    jq = e * __builtin_fma(d, kq, jq);
+                    kq = __builtin_fma(e, kq, 1.0);
                     tq = tb[j];
                 }
                 rtau[mi] = tq;
@@ -453,11 +452,18 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
     A.nseg = (int32_t)((A.CH + HK_SEG - 1) / HK_SEG);
     A.NB = (A.M + 63) / 64;
     A.NBR = A.per_target ? A.NB : (A.M + HK_DR - 1) / HK_DR;
+    // two columns per lane (128-node blocks) when the chunk's event indices
+    // leave 7 bits of the 32-bit record key
+    A.CPL = (!A.per_target && lg <= 25) ? 2 : 1;
+    if (const char* e = getenv("HAWKES_DENSE_CPL")) {
+        if (atoi(e) == 1) A.CPL = 1;
+    }
+    A.NBC = A.per_target ? A.NB : (A.M + 64 * A.CPL - 1) / (64 * A.CPL);
     // event ranges per chunk for the dense kernel: a power of two so that the
     // ranges map onto the 8 XCDs evenly; about 4096 blocks in total (shared
     // decay: 17 KiB of LDS each, four per SIMD) or 2048 (per target, 34 KiB)
     // unless HAWKES_DENSE_ER (a power of two) overrides it
-    const int64_t nbb = (int64_t)A.NBR * A.NB;
+    const int64_t nbb = (int64_t)A.NBR * A.NBC;
     const int64_t target = A.per_target ? 2048 : 4096;
     const int64_t want = (target + nbb - 1) / nbb;
     int32_t er = 1;
@@ -586,7 +592,7 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
     const int64_t MM = (int64_t)M * M;
     const unsigned gM = (unsigned)((M + 255) / 256);
     const size_t lds_agg = (size_t)2 * M * sizeof(double);
-    const size_t lds_fwd = (size_t)M * (sizeof(double) + sizeof(uint64_t) + 2 * sizeof(float));
+    const size_t lds_fwd = (size_t)M * (sizeof(double) + sizeof(uint64_t) + 2 * sizeof(double));
     if (allow_lds((const void*)large_seg_agg, lds_agg) != HAWKES_OK ||
         allow_lds((const void*)large_forward<true, false>, lds_fwd) != HAWKES_OK ||
         allow_lds((const void*)large_forward<false, true>, lds_fwd) != HAWKES_OK ||
@@ -640,7 +646,7 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
         if (A.grad) {
             {
                 TimedScope tb(6, st);
-                bucket_chunk(A, c0, c1, nseg, A.wchunk, st);
+                bucket_chunk(A, c0, c1, nseg, A.wchunk, A.CPL == 2 ? 7 : 6, st);
             }
             TimedScope ts(0, st);
             large_dense_launch(A, c0, c1, nseg, st);

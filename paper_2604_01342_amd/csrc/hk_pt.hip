@@ -105,11 +105,11 @@ __global__ __launch_bounds__(64) void pt_seg_agg(int64_t c0, int64_t c1, int32_t
                     if (kb + j >= k1) break;
                     const int32_t p = pv[j];
                     const double al = (double)av[j], bp = (double)bv[j];
-                    const double e = exp(-bp * d);
+                    const double e = exp_f64(-bp * d);
                     atomicAdd(&aR[p], al * e);
                     atomicAdd(&aD[p], al * d * e);
                     const double x = bp * x0;
-                    atomicAdd(&aE[p], al * x0 * exp(-x));
+                    atomicAdd(&aE[p], al * x0 * exp_f64(-x));
                     comp += al * -expm1(-x);
                 }
             }
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
                 const double bp = (double)beta[p];
                 // record of the event's own target, moved to t_i
                 const double d = ti - rtau[p];
-                const double e = exp(-bp * d);
+                const double e = exp_f64(-bp * d);
                 const double r = rR[p];
                 const double Rv = e * r;
                 const double Dv = e * __builtin_fma(d, r, rD[p]);
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
                             bt = beta[tp];
                         }
                         const double dd = ti - rtau[tp];
-                        const double ee = exp(-(double)bt * dd);
+                        const double ee = exp_f64(-(double)bt * dd);
                         const double r0 = rR[tp];
                         rD[tp] = ee * __builtin_fma(dd, r0, rD[tp]);
                         rR[tp] = __builtin_fma(ee, r0, (double)av);
@@ -643,7 +643,7 @@ hawkes_status run_large_pt(LargeArgs& A, hipStream_t st) {
             }
             {
                 TimedScope tb(6, st);
-                bucket_chunk(A, c0, c1, nseg, A.wv + c0, st);
+                bucket_chunk(A, c0, c1, nseg, A.wv + c0, 6, st);
             }
             const int32_t spr = (nseg + A.ER - 1) / A.ER;
             const int32_t nbb = A.NB * A.NB;
