@@ -171,18 +171,44 @@ __global__ __launch_bounds__(256) void small_agg(int32_t S, int64_t n_total, con
         const double tref = reset ? t[inf.a] : t[inf.a - 1];
         double tp = tref;
         int mp = -1;
-        for (int64_t e = inf.a; e < inf.b; ++e) {
-            const double te = t[e];
-            const double d = te - tp;
-            const double s = exp(-bet * d);
+        // events in blocks of 8 per lane, the next block's loads in flight
+        // while the current one is processed (clamped indices stay valid)
+        const int64_t last = inf.b - 1;
+        double tn[8];
+        int mn[8];
 #pragma unroll
-            for (int q = 0; q < MP; ++q) {
-                const double k1 = s * (K[q] + (q == mp ? 1.0 : 0.0));
-                J[q] = __builtin_fma(s, J[q], d * k1);
-                K[q] = k1;
+        for (int j = 0; j < 8; ++j) {
+            const int64_t e = inf.a + j < last ? inf.a + j : last;
+            tn[j] = t[e];
+            mn[j] = marks[e];
+        }
+        for (int64_t e0 = inf.a; e0 < inf.b; e0 += 8) {
+            double tv[8];
+            int mv[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                tv[j] = tn[j];
+                mv[j] = mn[j];
+                const int64_t e = e0 + 8 + j < last ? e0 + 8 + j : last;
+                tn[j] = t[e];
+                mn[j] = marks[e];
             }
-            tp = te;
-            mp = clamp_mark(marks[e], M);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (e0 + j < inf.b) {
+                    const double te = tv[j];
+                    const double d = te - tp;
+                    const double s = exp_f64(-bet * d);
+#pragma unroll
+                    for (int q = 0; q < MP; ++q) {
+                        const double k1 = s * (K[q] + (q == mp ? 1.0 : 0.0));
+                        J[q] = __builtin_fma(s, J[q], d * k1);
+                        K[q] = k1;
+                    }
+                    tp = te;
+                    mp = clamp_mark(mv[j], M);
+                }
+            }
         }
 #pragma unroll
         for (int q = 0; q < MP; ++q) K[q] += (q == mp ? 1.0 : 0.0);
@@ -341,17 +367,42 @@ __global__ __launch_bounds__(256) void small_compute(int32_t S, int64_t n_total,
             for (int q = 0; q < (GRAD ? MP : 1); ++q) G[p][q] = 0.0;
     }
     int mp = -1;
-    for (int64_t e = inf.a; e < inf.b; ++e) {
-        const double te = t[e];
+    // events in blocks of 8 per lane, the next block's loads in flight while
+    // the current one is processed (clamped indices stay valid)
+    const int64_t last = inf.b - 1;
+    double tn[8];
+    int mn[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int64_t e = inf.a + j < last ? inf.a + j : last;
+        tn[j] = t[e];
+        mn[j] = marks[e];
+    }
+    for (int64_t e0 = inf.a; e0 < inf.b; e0 += 8) {
+    double tv[8];
+    int mv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        tv[j] = tn[j];
+        mv[j] = mn[j];
+        const int64_t e = e0 + 8 + j < last ? e0 + 8 + j : last;
+        tn[j] = t[e];
+        mn[j] = marks[e];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        if (e0 + j >= inf.b) continue;
+        const int64_t e = e0 + j;
+        const double te = tv[j];
         const double d = te - tp;
-        const double s = exp(-bet * d);
+        const double s = exp_f64(-bet * d);
 #pragma unroll
         for (int q = 0; q < MP; ++q) {
             const double k1 = s * (K[q] + (q == mp ? 1.0 : 0.0));
             J[q] = __builtin_fma(s, J[q], d * k1);
             K[q] = k1;
         }
-        const int p = clamp_mark(marks[e], M);
+        const int p = clamp_mark(mv[j], M);
         double R = 0.0, Dd = 0.0;
 #pragma unroll
         for (int q = 0; q < MP; ++q) {
@@ -363,7 +414,7 @@ __global__ __launch_bounds__(256) void small_compute(int32_t S, int64_t n_total,
         if (INTENS) lambda_out[e] = (float)lam;
         logsum += log(lam);
         const double x = bet * (T - te);
-        const double ex = exp(-x);
+        const double ex = exp_f64(-x);
         double csp = 0.0;
 #pragma unroll
         for (int q = 0; q < MP; ++q) csp = (q == p) ? colsum[q] : csp;
@@ -386,6 +437,7 @@ __global__ __launch_bounds__(256) void small_compute(int32_t S, int64_t n_total,
         }
         tp = te;
         mp = p;
+    }
     }
     double* o = part + it * (int64_t)PW;
     o[0] = logsum;
