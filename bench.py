@@ -103,7 +103,7 @@ def run_single_other(args, name, dev):
     H.timing_enable(False)
     out = {"metric": f"events/sec for loglik+grad ({name})", "value": w.n / (wall / 1e3), "unit": "events/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32 state / f64 sums",
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic", "config": {"workload": f"{name}: M={w.M}, N={w.n}", "n_events": w.n},
            "step_device_time": {"median_ms": per[len(per) // 2], "min_ms": per[0], "max_ms": per[-1]},
            "kernels_ms_per_step": _kernels(H, args.warmup + args.steps)}
@@ -138,7 +138,7 @@ def run_c3(args, dev):
     alg = 24.0 * n
     out = {"metric": "events/sec for batched loglik+grad (c3)", "value": n / (wall / 1e3), "unit": "events/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64 state",
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic", "config": {"workload": "c3: 4096 sequences, M=8", "n_events": n},
            "roofline": {"kernel": "whole batched call", "bound": "hbm",
                         "achieved": round(alg / (per[len(per) // 2] * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
@@ -195,7 +195,7 @@ def run_c5(args, dev):
     nnz = int((opt.alpha != 0).sum().item())
     out = {"metric": "events/sec for loglik+grad (c5 shape, per-target decays)", "value": w.n / (wall / 1e3),
            "unit": "events/s", "n_gpus": 1, "steps": max(2, args.steps // 4), "warmup": 1, "ms_per_step": wall,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64 forward / f64 sums",
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic",
            "config": {"workload": f"c5 shape: M=4096, 0.2% dense, beta per target, N={w.n} (reduced)",
                       "n_events": w.n},
@@ -323,7 +323,7 @@ def main() -> int:
 
     out = {"metric": METRIC, "value": value, "unit": "events/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f32 state / f64 sums", "data": "synthetic",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "c4: M=1000, N=1e7, alpha 1% dense rho=0.8, beta=1, chunks of 2^20",
                       "n_events": w.n, "n_nodes": w.M, "chunk_log2": args.chunk_log2},
            "roofline": roofline, "step_device_time": step_stats, "kernels_ms_per_step": kernels}
