@@ -218,11 +218,12 @@ hawkes_status hawkes_check_inputs(const hawkes_problem* p,
  *   2 segment aggregates (large-M)       3 segment carry scan (large-M)
  *   4 per-item evaluation (small-M)      5 small-M aggregates and scans
  *   6 partition of a chunk's events by node block (large-M, gradient only)
+ *   7 state checkpoints of the dense dL/dalpha (large-M, shared decay)
  * Recording is host-side bookkeeping only (no device allocation); the events
  * are destroyed by hawkes_timing_read / hawkes_timing_reset.  Not for use
  * during graph capture.
  * ------------------------------------------------------------------------- */
-#define HAWKES_TIMING_KERNELS 7
+#define HAWKES_TIMING_KERNELS 8
 hawkes_status hawkes_timing_enable(int on);
 hawkes_status hawkes_timing_reset(void);
 hawkes_status hawkes_timing_read(int kernel_id, double* total_ms, int64_t* launches);

@@ -216,7 +216,7 @@ def sequential_loglik_grad(t, m, mu, alpha, beta, T):
 
 
 TIMING_KERNELS = {0: "dense_dalpha", 1: "forward", 2: "segment_aggregate", 3: "segment_scan",
-                  4: "small_compute", 5: "small_scan", 6: "bucket"}
+                  4: "small_compute", 5: "small_scan", 6: "bucket", 7: "dense_checkpoints"}
 
 
 def timing_enable(on: bool = True) -> None:

@@ -1,4 +1,4 @@
-// Per-chunk partition of the events by node block (64 or 128 nodes per block),
+// Per-chunk partition of the events by node block (16, 64 or 128 nodes per block),
 // stable in event order: a counting sort in three steps.
 //   count    one wave per segment: events per (block, segment)
 //   scan     one workgroup per block: start of every (block, segment) run
@@ -10,7 +10,7 @@
 //            (one ballot per bit of the block number), plus the block's
 //            running count in LDS
 // Records: key = (event index in the chunk) << bs | (mark mod 2^bs) for blocks
-// of 2^bs nodes (bs = 6 or 7), t (float64),
+// of 2^bs nodes (bs = 4, 6 or 7), t (float64),
 // w = 1 / lambda (float32).  The dense-gradient kernels stream the records of
 // two blocks (the block of their rows and the block of their columns)
 // instead of filtering every event of the chunk.
@@ -114,18 +114,24 @@ __global__ __launch_bounds__(64) void bucket_scatter(int64_t c0, int64_t c1, int
     }
 }
 
-// bs: log2 of the block width (6: 64 nodes, 7: 128 nodes; keys need
-// (events per chunk) << bs < 2^32)
-void bucket_chunk(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, const float* wchunk, int bs, hipStream_t st) {
+// bs: log2 of the block width (4: 16 nodes, 6: 64, 7: 128; keys need
+// (events per chunk) << bs < 2^32); records go to the given arrays
+void bucket_chunk_into(const LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, const float* wchunk, int bs,
+                       int32_t* cnt, int32_t* off, int32_t* base, uint32_t* key, double* tt, float* ww,
+                       hipStream_t st) {
     const int32_t nb = (A.M + (1 << bs) - 1) >> bs;
     int nbits = 0;
     while ((1 << nbits) < nb) ++nbits;
     const size_t lds = (size_t)nb * sizeof(int32_t);
-    hipLaunchKernelGGL(bucket_count, dim3(nseg), dim3(64), lds, st, c0, c1, A.M, nb, bs, A.marks, nseg, A.bk_cnt);
-    hipLaunchKernelGGL(bucket_scan, dim3(nb), dim3(256), 0, st, nseg, A.bk_cnt, A.bk_off);
-    hipLaunchKernelGGL(bucket_base, dim3(1), dim3(64), 0, st, nb, nseg, A.bk_off, A.bk_base);
+    hipLaunchKernelGGL(bucket_count, dim3(nseg), dim3(64), lds, st, c0, c1, A.M, nb, bs, A.marks, nseg, cnt);
+    hipLaunchKernelGGL(bucket_scan, dim3(nb), dim3(256), 0, st, nseg, cnt, off);
+    hipLaunchKernelGGL(bucket_base, dim3(1), dim3(64), 0, st, nb, nseg, off, base);
     hipLaunchKernelGGL(bucket_scatter, dim3(nseg), dim3(64), lds, st, c0, c1, A.M, nb, nbits, bs, A.t, A.marks, wchunk,
-                       nseg, A.bk_off, A.bk_base, A.bk_key, A.bk_t, A.bk_w);
+                       nseg, off, base, key, tt, ww);
+}
+
+void bucket_chunk(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, const float* wchunk, int bs, hipStream_t st) {
+    bucket_chunk_into(A, c0, c1, nseg, wchunk, bs, A.bk_cnt, A.bk_off, A.bk_base, A.bk_key, A.bk_t, A.bk_w, st);
 }
 
 }  // namespace hk

@@ -1,60 +1,204 @@
 // Dense dL/dalpha of the shared-decay large-M path (eq. 9): sum over events
-// of beta w_i K(t_i) into row m_i, from the bucketed event streams.
+// of beta w_i K(t_i^-) into row m_i, from the bucketed event streams.
+//
+// Two kernels per chunk.  Column blocks are the buckets of W = 64 CPL nodes,
+// row blocks the buckets of HK_DR = 16 nodes.
+//   dense_ck     one wave per (column block, run of CKR segments): walks the
+//                block's records of the run once, in groups of 64, and stores
+//                the block's state K at the start of every group and after
+//                the last one (a checkpoint: W float64 values and the anchor
+//                time tau of the state, K_q(tau) = sum over the events j of
+//                node q before the group of e^{-beta (tau - t_j)}).  A run
+//                starts from the scan's carry at its first segment, so the
+//                runs are independent.  The same pass sums, per column and
+//                run, the weights w_j (dL/dmu) and the compensator terms
+//                1 - e^{-beta (T - t_j)} (their alpha-derivative).
+//   large_dense  one wave per (row block, column block, event range of whole
+//                runs).  Window g of a run holds the wave's own events (the
+//                events of its row block) with index after group g-1's last
+//                record and up to group g's last record (after the last
+//                group: up to the run's end).  Own event k adds
+//                beta w_k K(t_k^-) to row m_k, where K(t_k^-) is checkpoint g
+//                decayed to t_k plus the events of group g that precede k.
+//                With c_k = beta w_k e^{-beta (t_k - tau_g)} and
+//                b_j = e^{beta (t_j - tau_g)} the window adds
+//                  u K_g^T, u_p = sum of c_k over its own events of row p
+//                (a rank-1 update: 16 x W float64 FMAs into G held in
+//                registers, lane = column), and c_k b_j at (m_k, m_j) for the
+//                group's records j before k (one masked ds_add_f64 per own
+//                event into an LDS tile of pair terms).
+// The state is shared through the checkpoints instead of being rebuilt by
+// every row block.  Every window issues the same loads at the same point
+// (the next window's checkpoint and column group, the next batch of own
+// records), one window ahead, so their latency hides behind a window of work.
 #include "hk_device.h"
 #include "hk_large.h"
 #include "hk_stream.h"
 
 namespace hk {
 
-// ------------------------------------------------------------------ dense dL/dalpha
-// Block = (row block of HK_DR rows, column block of W = 64 CPL columns, event
-// range er), one wave.  LDS G[HK_DR][W] float64 accumulates
-// sum_i beta w_i K_q(t_i) for the block's rows p (targets m_i) and columns q
-// (sources); lane c owns columns s0 + c + 64 j (j < CPL) and their state K
-// (float64), kept in the frame of an anchor time.  Events are bucketed by
-// node blocks of W nodes; the block reads only two bucket streams: the node
-// block holding its rows (the events in its rows are the "own" events) and
-// its column block ("slab" events), merged by event index in windows of up to
-// 64 + 64 records:
-//   - the window ends where either list's 64th record ends (hi), so every own
-//     event of the window sees all earlier slab events either in K or in the
-//     window;
-//   - K moves to the window's first event time tw; own event k adds c_k * K to
-//     row m_k (c_k = beta w_k e^{-beta (t_k - tw)}, CPL ds_add_f64 over the
-//     W columns) plus c_k * b_j at (m_k, m_j) for the window's slab events j
-//     before it (b_j = e^{beta (t_j - tw)}, one masked ds_add_f64 over those
-//     lanes): together c_k times K just before event k;
-//   - then the slab events enter K in one vector step (scatter-add into LDS by
-//     column, read back by each column's lane), and row block 0 sums w and the
-//     compensator terms 1 - e^{-beta (T - t_j)} per column the same way.
-// A window whose time span exceeds HK_WIDE / beta (anchored factors would
-// leave float32 range) is walked event by event with per-event decays.
-// Blocks of one event range are placed on one XCD (blockIdx % 8).  With
-// HK_DR = 16 rows and W = 128 a block uses 19 KiB of LDS.
+static_assert(HK_DR == 16, "row blocks are the 16-node buckets");
+
+// checkpoint slot of group g of (column block sb, run r) whose first column
+// record sits at position P0 of the block-major records: slots of different
+// (sb, r) never overlap, and there are at most CH / 64 + 2 NBC nrun + 1
+__device__ __forceinline__ int64_t ck_slot(int64_t P0, int32_t sb, int32_t nrun, int32_t r) {
+    return (P0 >> 6) + 2 * ((int64_t)sb * nrun + r);
+}
+
 template <int CPL>
-__global__ __launch_bounds__(64) void large_dense(int64_t c0, int64_t c1, int32_t M, int32_t NBC, int32_t NBR,
-                                                  int32_t ER, int32_t segs_per_range, int32_t nseg, double T,
-                                                  const double* __restrict__ t, const float* __restrict__ beta,
-                                                  const double* __restrict__ carry_seg,
-                                                  const int32_t* __restrict__ bk_off,
-                                                  const int32_t* __restrict__ bk_base,
-                                                  const uint32_t* __restrict__ bk_key, const double* __restrict__ bk_t,
-                                                  const float* __restrict__ bk_w, double* __restrict__ gpart,
-                                                  double* __restrict__ spart, double* __restrict__ cpart) {
+__global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t M, int32_t NBC, int32_t nrun, int32_t ckr,
+                                               int32_t nseg, double T, const double* __restrict__ t,
+                                               const float* __restrict__ beta,
+                                               const double* __restrict__ carry_seg,
+                                               const int32_t* __restrict__ bk_off,
+                                               const int32_t* __restrict__ bk_base,
+                                               const uint32_t* __restrict__ bk_key,
+                                               const double* __restrict__ bk_t, const float* __restrict__ bk_w,
+                                               double* __restrict__ kck, double* __restrict__ spart,
+                                               double* __restrict__ cpart) {
     constexpr int W = 64 * CPL;
-    __shared__ double G[HK_DR * W];
-    __shared__ double KhL[W], SL[W], CL[W];
+    constexpr int KS = W + 8;   // slot stride: state, then 8 copies of the anchor time
+    __shared__ double DL[W], SL[W], CL[W];
     const int lane = threadIdx.x;
+    const int32_t sb = (int32_t)(blockIdx.x % (unsigned)NBC);
+    const int32_t r = (int32_t)(blockIdx.x / (unsigned)NBC);
+    const int32_t sA = r * ckr;
+    if (sA >= nseg) return;
+    const int32_t sB = sA + ckr < nseg ? sA + ckr : nseg;
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) DL[j * 64 + lane] = SL[j * 64 + lane] = CL[j * 64 + lane] = 0.0;
+    const int64_t a = c0 + (int64_t)sA * HK_SEG;
+    const int32_t s0 = sb * W;
+    const int64_t cb = bk_base[sb];
+    const int64_t P0 = cb + bk_off[(int64_t)sb * (nseg + 1) + sA];
+    const int64_t P1 = cb + bk_off[(int64_t)sb * (nseg + 1) + sB];
+    const int32_t ng = (int32_t)((P1 - P0 + 63) >> 6);
+    const int64_t slot0 = ck_slot(P0, sb, nrun, r);
+    const double bet = (double)beta[0];
+    double K[CPL];
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
-        KhL[j * 64 + lane] = 0.0;
-        SL[j * 64 + lane] = 0.0;
-        CL[j * 64 + lane] = 0.0;
+        const int32_t col = s0 + j * 64 + lane;
+        K[j] = col < M ? carry_seg[(int64_t)sA * 2 * M + col] : 0.0;
     }
+    double tau = a > 0 ? t[a - 1] : t[a];
+    __syncthreads();
+    // record of this lane in group g (clamped to a valid record)
+    auto rec = [&](int32_t g) -> int64_t {
+        const int64_t e = P0 + 64 * (int64_t)g + lane;
+        return e < P1 ? e : (P1 > P0 ? P1 - 1 : 0);
+    };
+    int64_t e = rec(0);
+    uint32_t key = bk_key[e];
+    double tj = bk_t[e];
+    float wj = bk_w[e];
+    for (int32_t g = 0;; ++g) {
+        double* out = kck + (slot0 + g) * KS;
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) out[j * 64 + lane] = K[j];
+        if (lane < 8) out[W + lane] = tau;
+        if (g == ng) break;
+        // next group's records in flight while this one is folded in
+        const int64_t en = rec(g + 1 < ng ? g + 1 : g);
+        const uint32_t keyn = bk_key[en];
+        const double tjn = bk_t[en];
+        const float wjn = bk_w[en];
+        const int64_t rem = P1 - (P0 + 64 * (int64_t)g);
+        const int nv = rem < 64 ? (int)rem : 64;
+        const double tn = rl_d(tj, nv - 1);
+        const double f = (double)exp_f64arg(-bet * (tn - tau));
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) K[j] *= f;
+        if (lane < nv) {
+            const int col = (int)(key & (uint32_t)(W - 1));
+            atomicAdd(&DL[col], (double)exp_f64arg(-bet * (tn - tj)));
+            atomicAdd(&SL[col], (double)wj);
+            atomicAdd(&CL[col], -expm1(-bet * (T - tj)));
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+            K[j] += DL[j * 64 + lane];
+            DL[j * 64 + lane] = 0.0;
+        }
+        tau = tn;
+        key = keyn;
+        tj = tjn;
+        wj = wjn;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+        const int32_t col = s0 + j * 64 + lane;
+        if (col < M) {
+            spart[(int64_t)r * M + col] += SL[j * 64 + lane];
+            cpart[(int64_t)r * M + col] += CL[j * 64 + lane];
+        }
+    }
+}
+
+// Raw buffer access with 32-bit byte offsets: no 64-bit address arithmetic,
+// and reads past the buffer's size return 0 instead of touching memory.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ uint32_t ld_u32(__amdgpu_buffer_rsrc_t r, uint32_t i) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, i * 4u, 0, 0);
+}
+__device__ __forceinline__ float ld_f32(__amdgpu_buffer_rsrc_t r, uint32_t i) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, i * 4u, 0, 0));
+}
+__device__ __forceinline__ double ld_f64(__amdgpu_buffer_rsrc_t r, uint32_t i) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, i * 8u, 0, 0));
+}
+
+// One batch of 64 consecutive own records (lane l: record qL + l).
+struct OwnBatch {
+    uint32_t key;
+    double t;
+    float w;
+};
+
+// Data of one window: checkpoint (state, anchor time) and the group's column
+// records.
+template <int CPL>
+struct Win {
+    double K[CPL];
+    double tau;   // lanes 0..7 hold it (read from lane 0)
+    uint32_t ckey;
+    double ct;
+};
+
+// A run of the column block: records [P0, P1), ng groups, first slot
+struct Run {
+    int32_t P0, P1, ng, slot0;
+};
+
+template <int CPL>
+__global__ __launch_bounds__(64) void large_dense(int32_t M, int32_t NBC, int32_t NBR, int32_t ER, int32_t rpr,
+                                                  int32_t nrun, int32_t ckr, int32_t nseg, int32_t nrec,
+                                                  int32_t nslot, const float* __restrict__ beta,
+                                                  const int32_t* __restrict__ bk_off,
+                                                  const int32_t* __restrict__ bk_base,
+                                                  const uint32_t* __restrict__ bk_key,
+                                                  const double* __restrict__ bk_t,
+                                                  const int32_t* __restrict__ bo_off,
+                                                  const int32_t* __restrict__ bo_base,
+                                                  const uint32_t* __restrict__ bo_key,
+                                                  const double* __restrict__ bo_t, const float* __restrict__ bo_w,
+                                                  const double* __restrict__ kck, double* __restrict__ gpart) {
+    constexpr int W = 64 * CPL;
+    constexpr int KS = W + 8;
+    constexpr int SH = CPL == 2 ? 7 : 6;   // bits of the local mark in a column record key
+    __shared__ double GP[HK_DR * W];   // pair terms
+    __shared__ double UL[HK_DR];       // the window's u
+    const int lane = threadIdx.x;
     const int32_t blk = blockIdx.x;
     const int32_t nbb = NBR * NBC;
     int32_t er, local;
     if (ER >= 8) {
+        // blocks of one event range on one XCD (blockIdx % 8)
         const int32_t slot = blk >> 3;
         er = (slot / nbb) * 8 + (blk & 7);
         local = slot % nbb;
@@ -66,173 +210,212 @@ __global__ __launch_bounds__(64) void large_dense(int64_t c0, int64_t c1, int32_
         if (local >= nbb) return;
     }
     if (er >= ER) return;
+    const int32_t nrun_c = (nseg + ckr - 1) / ckr;
+    const int32_t rA = er * rpr;
+    if (rA >= nrun_c) return;
+    const int32_t rB = rA + rpr < nrun_c ? rA + rpr : nrun_c;
     const int32_t sb = local % NBC;
     const int32_t rb = local / NBC;
     const int32_t r0 = rb * HK_DR, s0 = sb * W;
-    // own events: the node block holding rows [r0, r0 + HK_DR), part `hf` of it
-    const int32_t ob = r0 / W;
-    const uint32_t hf = (uint32_t)((r0 % W) / HK_DR);
-    const int32_t sA = er * segs_per_range;
-    if (sA >= nseg) return;
-    const int32_t sB = sA + segs_per_range < nseg ? sA + segs_per_range : nseg;
-    const int64_t a = c0 + (int64_t)sA * HK_SEG;
     double* gp = gpart + (int64_t)er * M * M;
-    {
-        // branch-free block load (all loads in flight together); out-of-range
-        // rows/columns read a clamped valid address and are zeroed
-#pragma unroll
-        for (int j = 0; j < CPL; ++j) {
-            const int32_t col = s0 + j * 64 + lane;
-            const int32_t cc = col < M ? col : M - 1;
-            for (int rg = 0; rg < HK_DR; rg += 16) {
-                double v[16];
-#pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    const int32_t row = r0 + rg + i;
-                    const int32_t rr = row < M ? row : M - 1;
-                    v[i] = gp[(int64_t)rr * M + cc];
-                }
-#pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    const int32_t row = r0 + rg + i;
-                    G[(rg + i) * W + j * 64 + lane] = (row < M && col < M) ? v[i] : 0.0;
-                }
-            }
-        }
-    }
-    const double bet = (double)beta[0];
-    // K at the range start (just after the event before it)
-    double Kh[CPL];
+    // main terms of the block in registers (row i, column s0 + 64 j + lane);
+    // branch-free load, out-of-range rows/columns read a clamped valid
+    // address and are zeroed
+    double Gm[HK_DR][CPL];
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
         const int32_t col = s0 + j * 64 + lane;
-        Kh[j] = col < M ? carry_seg[(int64_t)sA * 2 * M + col] : 0.0;
-    }
-    double tau = a > 0 ? t[a - 1] : t[a];
-    double Sacc[CPL], Cacc[CPL];
+        const int32_t cc = col < M ? col : M - 1;
 #pragma unroll
-    for (int j = 0; j < CPL; ++j) Sacc[j] = Cacc[j] = 0.0;
-    const bool diag_owner = rb == 0;
-    RecStream<false> O, S;
-    O.init(bk_key, bk_t, bk_w, (int64_t)bk_base[ob] + bk_off[(int64_t)ob * (nseg + 1) + sA],
-           (int64_t)bk_base[ob] + bk_off[(int64_t)ob * (nseg + 1) + sB]);
-    S.init(bk_key, bk_t, bk_w, (int64_t)bk_base[sb] + bk_off[(int64_t)sb * (nseg + 1) + sA],
-           (int64_t)bk_base[sb] + bk_off[(int64_t)sb * (nseg + 1) + sB]);
-    constexpr int SH = CPL == 2 ? 7 : 6;   // bits of the local mark in a record key
+        for (int i = 0; i < HK_DR; ++i) {
+            const int32_t row = r0 + i;
+            const int32_t rr = row < M ? row : M - 1;
+            Gm[i][j] = gp[(int64_t)rr * M + cc];
+        }
+#pragma unroll
+        for (int i = 0; i < HK_DR; ++i) {
+            if (!(r0 + i < M && col < M)) Gm[i][j] = 0.0;
+            GP[i * W + j * 64 + lane] = 0.0;
+        }
+    }
+    if (lane < HK_DR) UL[lane] = 0.0;
+    const double bet = (double)beta[0];
+    const __amdgpu_buffer_rsrc_t rK = buf(kck, (uint32_t)nslot * KS * 8u);
+    const __amdgpu_buffer_rsrc_t rCk = buf(bk_key, (uint32_t)nrec * 4u);
+    const __amdgpu_buffer_rsrc_t rCt = buf(bk_t, (uint32_t)nrec * 8u);
+    const __amdgpu_buffer_rsrc_t rOk = buf(bo_key, (uint32_t)nrec * 4u);
+    const __amdgpu_buffer_rsrc_t rOt = buf(bo_t, (uint32_t)nrec * 8u);
+    const __amdgpu_buffer_rsrc_t rOw = buf(bo_w, (uint32_t)nrec * 4u);
+    const int32_t cb = bk_base[sb];
+    const int32_t* offc = bk_off + (int64_t)sb * (nseg + 1);
+    auto run_info = [&](int32_t rr) -> Run {
+        Run x;
+        x.P0 = cb + offc[rr * ckr];
+        x.P1 = cb + offc[(rr + 1) * ckr < nseg ? (rr + 1) * ckr : nseg];
+        x.ng = (x.P1 - x.P0 + 63) >> 6;
+        x.slot0 = (x.P0 >> 6) + 2 * (sb * nrun + rr);
+        return x;
+    };
+    // own stream: records [Q0, Q1) of row block rb, q the next unconsumed
+    // one.  o0 holds records [qL, qL + 64).  Every window refills o2 from q
+    // and first moves the previous window's o2 to o1, so o1 (from q1s) is
+    // always one window old: when o0 runs out, o1 usually covers q.
+    const int32_t sA = rA * ckr, sB = rB * ckr < nseg ? rB * ckr : nseg;
+    const int32_t Q0 = bo_base[rb] + bo_off[(int64_t)rb * (nseg + 1) + sA];
+    const int32_t Q1 = bo_base[rb] + bo_off[(int64_t)rb * (nseg + 1) + sB];
+    auto own_load = [&](OwnBatch& o, int32_t from) {
+        const uint32_t e = (uint32_t)(from + lane);
+        o.key = ld_u32(rOk, e);
+        o.t = ld_f64(rOt, e);
+        o.w = ld_f32(rOw, e);
+    };
+    int32_t q = Q0, qL = Q0, q1s = Q0, q2s = Q0;
+    OwnBatch o0, o1, o2;
+    own_load(o0, Q0);
+    own_load(o2, Q0);
+    auto load_win = [&](Win<CPL>& w, const Run& ru, int32_t gg) {
+        const uint32_t sl = (uint32_t)(ru.slot0 + gg) * KS;
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) w.K[j] = ld_f64(rK, sl + j * 64 + lane);
+        w.tau = ld_f64(rK, sl + W + (lane & 7));
+        const uint32_t e = (uint32_t)(ru.P0 + 64 * gg + lane);
+        w.ckey = ld_u32(rCk, e);
+        w.ct = ld_f64(rCt, e);
+    };
+
+    // own records of the window in o0 from lane p on (index <= hi): adds
+    // their c_k to u and their pair terms to GP; returns how many there were
+    auto pass = [&](const Win<CPL>& w, int p, double tw, int hi, double tcl, bool cv, int cidx, int colj,
+                    double bj) -> int {
+        const OwnBatch& b = o0;
+        const bool own = qL + lane < Q1 && lane >= p && (int)(b.key >> 4) <= hi;
+        const int nsel = __builtin_popcountll(__ballot(own));
+        if (nsel == 0) return 0;
+        const int kend = p + nsel;   // own lanes are [p, kend)
+        const double tlo = rl_d(b.t, kend - 1);
+        const double tmax = tlo > tcl ? tlo : tcl;
+        const int rowl = (int)(b.key & (HK_DR - 1));
+        if (bet * (tmax - tw) <= HK_WIDE) {
+            const float cf = own ? (float)(bet * (double)b.w) * exp_f64arg(-bet * (b.t - tw)) : 0.0f;
+            if (own) atomicAdd(&UL[rowl], (double)cf);
+            auto pair = [&](int k) {
+                const uint32_t key = (uint32_t)rl_i((int)b.key, k);
+                const int rofs = (int)(key & (HK_DR - 1)) * W;
+                const double v = (cv && cidx < (int)(key >> 4)) ? (double)rl_f(cf, k) * bj : 0.0;
+                atomicAdd(&GP[rofs + colj], v);
+            };
+            int k = p;
+            for (; k + 1 < kend; k += 2) {
+                pair(k);
+                pair(k + 1);
+            }
+            if (k < kend) pair(k);
+        } else {
+            // wide window (anchored factors would leave float32 range):
+            // float64 decays for u, exact per-pair decays
+            const double cw = bet * (double)b.w;
+            if (own) atomicAdd(&UL[rowl], cw * exp_f64(-bet * (b.t - tw)));
+            for (int k = p; k < kend; ++k) {
+                const uint32_t key = (uint32_t)rl_i((int)b.key, k);
+                const int rofs = (int)(key & (HK_DR - 1)) * W;
+                const double tk = rl_d(b.t, k);
+                const double ck = rl_d(cw, k);
+                if (cv && cidx < (int)(key >> 4))
+                    atomicAdd(&GP[rofs + colj], ck * (double)exp_f64arg(-bet * (tk - w.ct)));
+            }
+        }
+        return nsel;
+    };
+
+    // window position (r, g) and the runs r and r + 1
+    int32_t r = rA, g = 0;
+    Run ru = run_info(rA);
+    Run rn = rA + 1 < rB ? run_info(rA + 1) : ru;
+
+    // one window with data `cur`; loads the next window into `nxt` first (the
+    // same window again after the last one, so that every window issues the
+    // same loads); false after the last window
+    auto body = [&](Win<CPL>& cur, Win<CPL>& nxt) -> bool {
+        const bool same_run = g < ru.ng;
+        const bool has_next = same_run || r + 1 < rB;
+        if (same_run)
+            load_win(nxt, ru, g + 1);
+        else if (has_next)
+            load_win(nxt, rn, 0);
+        else
+            load_win(nxt, ru, g);
+        o1 = o2;
+        q1s = q2s;
+        own_load(o2, q);
+        q2s = q;
+
+        const bool colw = g < ru.ng;
+        int nv = 0, hi;
+        const double tw = rl_d(cur.tau, 0);
+        double tcl = tw;
+        if (colw) {
+            const int rem = ru.P1 - (ru.P0 + 64 * g);
+            nv = rem < 64 ? rem : 64;
+            hi = rl_i((int)(cur.ckey >> SH), nv - 1);
+            tcl = rl_d(cur.ct, nv - 1);
+        } else {
+            const int32_t se = (r + 1) * ckr < nseg ? (r + 1) * ckr : nseg;
+            hi = se * HK_SEG - 1;   // the run's last event index in the chunk
+        }
+        const bool cv = lane < nv;
+        const int cidx = (int)(cur.ckey >> SH);
+        const int colj = (int)(cur.ckey & (uint32_t)(W - 1));
+        const double bj = cv ? (double)exp_f64arg(bet * (cur.ct - tw)) : 0.0;
+        int nown = 0;
+        for (;;) {
+            if (q - qL == 64) {
+                // o0 used up: continue in o1, which covers q unless more than
+                // 64 records went by in two windows (q >= q1s always); then
+                // load o1 now and wait for it here, so that the other path
+                // sees no load in flight
+                if (q >= q1s + 64) {
+                    own_load(o1, q);
+                    q1s = q;
+                    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+                }
+                o0 = o1;
+                qL = q1s;
+            }
+            const int n = pass(cur, q - qL, tw, hi, tcl, cv, cidx, colj, bj);
+            q += n;
+            nown += n;
+            if (n == 0 || q - qL < 64) break;
+        }
+        if (nown) {
+            // rank-1 update G += u K_g^T, then clear u
+            __syncthreads();
+            double u[HK_DR];
+#pragma unroll
+            for (int i = 0; i < HK_DR; ++i) u[i] = UL[i];
+#pragma unroll
+            for (int i = 0; i < HK_DR; ++i)
+#pragma unroll
+                for (int j = 0; j < CPL; ++j) Gm[i][j] = __builtin_fma(u[i], cur.K[j], Gm[i][j]);
+            __syncthreads();
+            if (lane < HK_DR) UL[lane] = 0.0;
+        }
+        if (same_run) {
+            ++g;
+        } else if (has_next) {
+            ++r;
+            g = 0;
+            ru = rn;
+            if (r + 1 < rB) rn = run_info(r + 1);
+        }
+        return has_next;
+    };
+
+    Win<CPL> wa, wb;
+    load_win(wa, ru, 0);
     __syncthreads();
     for (;;) {
-        const int64_t ao = O.avail(), as = S.avail();
-        if (ao <= 0 && as <= 0) break;
-        const int io = (int)(O.ck >> SH), is = (int)(S.ck >> SH);
-        const int lim_o = ao > 64 ? rl_i(io, 63) : 0x7fffffff;
-        const int lim_s = as > 64 ? rl_i(is, 63) : 0x7fffffff;
-        const int hi = lim_o < lim_s ? lim_o : lim_s;
-        const bool inw = lane < ao && io <= hi;   // record of the window (any part of the block)
-        const bool own = inw && ((O.ck & (uint32_t)(W - 1)) / HK_DR) == hf;
-        const bool sl = lane < as && is <= hi;
-        const uint64_t om = __ballot(own);
-        const int nw = __builtin_popcountll(__ballot(inw));
-        const int ns = __builtin_popcountll(__ballot(sl));
-        double tw = 1e300, te = -1e300;
-        if (nw) { tw = rl_d(O.ct, 0); te = rl_d(O.ct, nw - 1); }
-        if (ns) {
-            const double a0 = rl_d(S.ct, 0), a1 = rl_d(S.ct, ns - 1);
-            tw = a0 < tw ? a0 : tw;
-            te = a1 > te ? a1 : te;
-        }
-        {
-            const double f = (double)exp_f64arg(-bet * (tw - tau));
-#pragma unroll
-            for (int j = 0; j < CPL; ++j) Kh[j] *= f;
-        }
-        tau = tw;
-        const int colj = (int)(S.ck & (uint32_t)(W - 1));
-        if (bet * (te - tw) <= HK_WIDE) {
-            const float cf = own ? (float)(bet * (double)O.cw) * exp_f64arg(-bet * (O.ct - tw)) : 0.0f;
-            const double bj = sl ? (double)exp_f64arg(bet * (S.ct - tw)) : 0.0;
-            // own events two at a time: two independent update chains
-            const int rowl = (int)(O.ck & (HK_DR - 1));
-            uint64_t mo = om;
-            while (mo) {
-                const int k1 = __builtin_ctzll(mo);
-                mo &= mo - 1;
-                const int r1 = rl_i(rowl, k1) * W, i1 = rl_i(io, k1);
-                const double c1 = (double)rl_f(cf, k1);
-                if (mo) {
-                    const int k2 = __builtin_ctzll(mo);
-                    mo &= mo - 1;
-                    const int r2 = rl_i(rowl, k2) * W, i2 = rl_i(io, k2);
-                    const double c2 = (double)rl_f(cf, k2);
-#pragma unroll
-                    for (int j = 0; j < CPL; ++j) {
-                        atomicAdd(&G[r1 + j * 64 + lane], c1 * Kh[j]);
-                        atomicAdd(&G[r2 + j * 64 + lane], c2 * Kh[j]);
-                    }
-                    if (sl && is < i1) atomicAdd(&G[r1 + colj], c1 * bj);
-                    if (sl && is < i2) atomicAdd(&G[r2 + colj], c2 * bj);
-                } else {
-#pragma unroll
-                    for (int j = 0; j < CPL; ++j) atomicAdd(&G[r1 + j * 64 + lane], c1 * Kh[j]);
-                    if (sl && is < i1) atomicAdd(&G[r1 + colj], c1 * bj);
-                }
-            }
-            if (ns) {
-                if (sl) {
-                    atomicAdd(&KhL[colj], bj);
-                    if (diag_owner) {
-                        atomicAdd(&SL[colj], (double)S.cw);
-                        atomicAdd(&CL[colj], -expm1(-bet * (T - S.ct)));
-                    }
-                }
-                __syncthreads();
-#pragma unroll
-                for (int j = 0; j < CPL; ++j) {
-                    Kh[j] += KhL[j * 64 + lane];
-                    KhL[j * 64 + lane] = 0.0;
-                }
-            }
-        } else {
-            int ko = 0, ks = 0;
-            while (ko < nw || ks < ns) {
-                const int iko = ko < nw ? rl_i(io, ko) : 0x7fffffff;
-                const int iks = ks < ns ? rl_i(is, ks) : 0x7fffffff;
-                if (iko <= iks) {
-                    // own first on a tie: the same event as slab event comes after
-                    const double tk = rl_d(O.ct, ko);
-                    const double f = (double)exp_f64arg(-bet * (tk - tau));
-#pragma unroll
-                    for (int j = 0; j < CPL; ++j) Kh[j] *= f;
-                    tau = tk;
-                    if ((om >> ko) & 1ull) {
-                        const int r = (int)(rl_i((int)O.ck, ko) & (HK_DR - 1));
-                        const double cw = bet * (double)rl_f(O.cw, ko);
-#pragma unroll
-                        for (int j = 0; j < CPL; ++j) atomicAdd(&G[r * W + j * 64 + lane], cw * Kh[j]);
-                    }
-                    ++ko;
-                } else {
-                    const double tk = rl_d(S.ct, ks);
-                    const double f = (double)exp_f64arg(-bet * (tk - tau));
-#pragma unroll
-                    for (int j = 0; j < CPL; ++j) Kh[j] *= f;
-                    tau = tk;
-                    const int ck = (int)(rl_i((int)S.ck, ks) & (W - 1));
-#pragma unroll
-                    for (int j = 0; j < CPL; ++j) {
-                        if (j * 64 + lane == ck) {
-                            Kh[j] += 1.0;
-                            if (diag_owner) {
-                                Sacc[j] += (double)rl_f(S.cw, ks);
-                                Cacc[j] += -expm1(-bet * (T - tk));
-                            }
-                        }
-                    }
-                    ++ks;
-                }
-            }
-        }
-        O.consume(nw);
-        S.consume(ns);
+        if (!body(wa, wb)) break;
+        if (!body(wb, wa)) break;
     }
     __syncthreads();
 #pragma unroll
@@ -240,31 +423,42 @@ __global__ __launch_bounds__(64) void large_dense(int64_t c0, int64_t c1, int32_
         const int32_t col = s0 + j * 64 + lane;
         if (col < M) {
 #pragma unroll
-            for (int r = 0; r < HK_DR; ++r) {
-                const int32_t row = r0 + r;
-                if (row < M) gp[(int64_t)row * M + col] = G[r * W + j * 64 + lane];
-            }
-            if (diag_owner) {
-                spart[(int64_t)er * M + col] += Sacc[j] + SL[j * 64 + lane];
-                cpart[(int64_t)er * M + col] += Cacc[j] + CL[j * 64 + lane];
+            for (int rr = 0; rr < HK_DR; ++rr) {
+                const int32_t row = r0 + rr;
+                if (row < M) gp[(int64_t)row * M + col] = Gm[rr][j] + GP[rr * W + j * 64 + lane];
             }
         }
     }
 }
 
 void large_dense_launch(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, hipStream_t st) {
-    const int32_t spr = (nseg + A.ER - 1) / A.ER;
+    const int32_t nrun_c = (nseg + A.CKR - 1) / A.CKR;
+    {
+        TimedScope tk(7, st);
+        if (A.CPL == 2)
+            hipLaunchKernelGGL(dense_ck<2>, dim3((unsigned)(A.NBC * nrun_c)), dim3(64), 0, st, c0, A.M, A.NBC,
+                               A.NRUN, A.CKR, nseg, A.T, A.t, A.beta, A.carry_seg, A.bk_off, A.bk_base, A.bk_key,
+                               A.bk_t, A.bk_w, A.kck, A.spart, A.cpart_);
+        else
+            hipLaunchKernelGGL(dense_ck<1>, dim3((unsigned)(A.NBC * nrun_c)), dim3(64), 0, st, c0, A.M, A.NBC,
+                               A.NRUN, A.CKR, nseg, A.T, A.t, A.beta, A.carry_seg, A.bk_off, A.bk_base, A.bk_key,
+                               A.bk_t, A.bk_w, A.kck, A.spart, A.cpart_);
+    }
+    TimedScope ts(0, st);
+    const int32_t rpr = A.NRUN / A.ER;   // runs per event range (both powers of two)
     const int32_t nbb = A.NBR * A.NBC;
     const unsigned nblk = A.ER >= 8 ? (unsigned)(nbb * ((A.ER + 7) / 8) * 8)
                                     : (unsigned)(((nbb + 8 / A.ER - 1) / (8 / A.ER)) * 8);
+    const int32_t nrec = (int32_t)(c1 - c0);
+    const int32_t nslot = (int32_t)A.nslot;
     if (A.CPL == 2)
-        hipLaunchKernelGGL(large_dense<2>, dim3(nblk), dim3(64), 0, st, c0, c1, A.M, A.NBC, A.NBR, A.ER, spr, nseg,
-                           A.T, A.t, A.beta, A.carry_seg, A.bk_off, A.bk_base, A.bk_key, A.bk_t, A.bk_w, A.gpart,
-                           A.spart, A.cpart_);
+        hipLaunchKernelGGL(large_dense<2>, dim3(nblk), dim3(64), 0, st, A.M, A.NBC, A.NBR, A.ER, rpr, A.NRUN,
+                           A.CKR, nseg, nrec, nslot, A.beta, A.bk_off, A.bk_base, A.bk_key, A.bk_t, A.bo_off,
+                           A.bo_base, A.bo_key, A.bo_t, A.bo_w, A.kck, A.gpart);
     else
-        hipLaunchKernelGGL(large_dense<1>, dim3(nblk), dim3(64), 0, st, c0, c1, A.M, A.NBC, A.NBR, A.ER, spr, nseg,
-                           A.T, A.t, A.beta, A.carry_seg, A.bk_off, A.bk_base, A.bk_key, A.bk_t, A.bk_w, A.gpart,
-                           A.spart, A.cpart_);
+        hipLaunchKernelGGL(large_dense<1>, dim3(nblk), dim3(64), 0, st, A.M, A.NBC, A.NBR, A.ER, rpr, A.NRUN,
+                           A.CKR, nseg, nrec, nslot, A.beta, A.bk_off, A.bk_base, A.bk_key, A.bk_t, A.bo_off,
+                           A.bo_base, A.bo_key, A.bo_t, A.bo_w, A.kck, A.gpart);
 }
 
 }  // namespace hk

@@ -12,6 +12,9 @@
 #define HK_DR 16           // rows per block of the shared-decay dense kernel
 #endif
 #define HK_SLAB 64         // columns per dense-gradient block (one per lane)
+#ifndef HK_CKR
+#define HK_CKR 4           // segments per checkpoint run of the shared-decay dense gradient
+#endif
 #define HK_WIDE 60.0       // anchored-exponent limit inside one window of the dense kernel
 
 namespace hk {
@@ -29,6 +32,8 @@ struct LargeArgs {
     int32_t NBR;          // row blocks of the dense kernel (HK_DR rows shared decay, HK_RB per target)
     int32_t CPL;          // columns per lane of the shared-decay dense kernel (1 or 2)
     int32_t NBC;          // column blocks of the dense kernel (64 CPL columns each)
+    int32_t CKR;          // segments per checkpoint run (shared decay)
+    int32_t NRUN;         // checkpoint runs per chunk (nseg / CKR)
     bool grad;
     const double* t;
     const int32_t* marks;
@@ -48,7 +53,10 @@ struct LargeArgs {
     double* seg_part;     // [nseg][4]
     double* acc;          // [4] call-level sums: logsum, comp, E, gbeta
     double* ll_scratch;   // [1] log-likelihood slot when the caller wants intensities only
-    double *gpart, *spart, *cpart_;  // [ER][M][M], [ER][M], [ER][M]
+    double *gpart, *spart, *cpart_;  // [ER][M][M]; [ER][M] per target, [NRUN][M] shared decay
+    int64_t nslot;        // checkpoint slots
+    double* kck;          // [nslot][64 CPL + 8] state checkpoints of the dense gradient (shared
+                          //   decay): the state, then its anchor time (8 copies)
     // per-target decays (R-form forward, reverse adjoint for the gradient)
     int32_t *csc_ptr, *csc_row;   // alpha by column: targets p of source q
     float* csc_val;
@@ -68,6 +76,13 @@ struct LargeArgs {
     double* bk_t;         // [CH] event time
     float* bk_w;          // [CH] 1 / lambda
     float* wchunk;        // [CH] 1 / lambda of the chunk's events (shared decay)
+    // the same events partitioned by blocks of HK_DR nodes (the row blocks of
+    // the shared-decay dense kernel): its own-event streams
+    int32_t NBO;          // row blocks (ceil(M / HK_DR))
+    int32_t *bo_cnt, *bo_off, *bo_base;
+    uint32_t* bo_key;     // [CH] (index in chunk) << 4 | mark mod 16
+    double* bo_t;
+    float* bo_w;
     // outputs
     double *loglik, *g_mu, *g_alpha, *g_beta;
     float* lambda_out;
@@ -86,6 +101,9 @@ void large_build_index(int32_t M, const float* alpha, int trans, int32_t* ptr, i
 void large_scan(LargeArgs& A, int32_t nseg, const float* beta_pt, hipStream_t st);
 void large_chunk_acc_launch(int32_t nseg, const double* seg_part, double* acc, hipStream_t st);
 void bucket_chunk(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, const float* wchunk, int bs, hipStream_t st);
+void bucket_chunk_into(const LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, const float* wchunk, int bs,
+                       int32_t* cnt, int32_t* off, int32_t* base, uint32_t* key, double* tt, float* ww,
+                       hipStream_t st);
 void large_dense_launch(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, hipStream_t st);
 
 size_t seq_workspace_bytes(const hawkes_problem* p);

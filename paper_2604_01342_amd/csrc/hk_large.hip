@@ -410,7 +410,7 @@ __global__ __launch_bounds__(256) void large_chunk_acc(int32_t nseg, const doubl
 }
 
 // ------------------------------------------------------------------ finalize
-__global__ void large_final(int32_t M, int32_t ER, double T, const float* __restrict__ mu,
+__global__ void large_final(int32_t M, int32_t ER, int32_t NSC, double T, const float* __restrict__ mu,
                             const double* __restrict__ acc, const double* __restrict__ gpart,
                             const double* __restrict__ spart, const double* __restrict__ cpart,
                             double* __restrict__ loglik, double* __restrict__ g_mu, double* __restrict__ g_alpha,
@@ -427,15 +427,13 @@ __global__ void large_final(int32_t M, int32_t ER, double T, const float* __rest
     if (x < MM && g_alpha) {
         const int32_t q = (int32_t)(x % M);
         double g = 0.0, c = 0.0;
-        for (int32_t e = 0; e < ER; ++e) {
-            g += gpart[(int64_t)e * MM + x];
-            c += cpart[(int64_t)e * M + q];
-        }
+        for (int32_t e = 0; e < ER; ++e) g += gpart[(int64_t)e * MM + x];
+        for (int32_t e = 0; e < NSC; ++e) c += cpart[(int64_t)e * M + q];
         g_alpha[x] = g - c;
     }
     if (x < M && g_mu) {
         double s = 0.0;
-        for (int32_t e = 0; e < ER; ++e) s += spart[(int64_t)e * M + x];
+        for (int32_t e = 0; e < NSC; ++e) s += spart[(int64_t)e * M + x];
         g_mu[x] = s - T;
     }
 }
@@ -474,6 +472,10 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
     }
     while (er > A.nseg && er > 1) er >>= 1;
     A.ER = er;
+    // checkpoint runs: whole runs per event range (nseg and ER are powers of two)
+    A.CKR = A.nseg / er < HK_CKR ? A.nseg / er : HK_CKR;
+    if (A.CKR < 1) A.CKR = 1;
+    A.NRUN = A.nseg / A.CKR;
     A.grad = grad;
     const int64_t M = A.M, MM = M * M;
     Carve c(ws, ws_bytes);
@@ -520,8 +522,20 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
         A.bk_t = c.take<double>(A.CH);
         A.bk_w = c.take<float>(A.CH);
         A.gpart = c.take<double>((size_t)A.ER * MM);
-        A.spart = c.take<double>((size_t)A.ER * M);
-        A.cpart_ = c.take<double>((size_t)A.ER * M);
+        const int64_t nsp = A.per_target ? A.ER : A.NRUN;
+        A.spart = c.take<double>((size_t)nsp * M);
+        A.cpart_ = c.take<double>((size_t)nsp * M);
+        if (!A.per_target) {
+            A.nslot = A.CH / 64 + 2 * (int64_t)A.NBC * A.NRUN + 2;
+            A.kck = c.take<double>((size_t)A.nslot * (64 * A.CPL + 8));
+            A.NBO = (A.M + HK_DR - 1) / HK_DR;
+            A.bo_cnt = c.take<int32_t>((size_t)A.NBO * A.nseg);
+            A.bo_off = c.take<int32_t>((size_t)A.NBO * (A.nseg + 1));
+            A.bo_base = c.take<int32_t>(A.NBO);
+            A.bo_key = c.take<uint32_t>(A.CH);
+            A.bo_t = c.take<double>(A.CH);
+            A.bo_w = c.take<float>(A.CH);
+        }
     }
     return c.off + 256;
 }
@@ -598,6 +612,10 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
         allow_lds((const void*)large_forward<false, true>, lds_fwd) != HAWKES_OK ||
         allow_lds((const void*)large_forward<false, false>, lds_fwd) != HAWKES_OK)
         return HAWKES_EUNSUPPORTED;
+    // the dense-gradient kernels address checkpoints and records with
+    // 32-bit byte offsets
+    if (A.grad && (uint64_t)A.nslot * (uint64_t)(64 * A.CPL + 8) * 8u >= (1ull << 32))
+        return HAWKES_EUNSUPPORTED;
     // zero the carried state and accumulators
     hipLaunchKernelGGL(fill_d, dim3(1), dim3(256), 0, st, A.carry, (int64_t)2 * M, 0.0);
     hipLaunchKernelGGL(fill_d, dim3(1), dim3(64), 0, st, A.acc, (int64_t)4, 0.0);
@@ -605,8 +623,8 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
         const int64_t ng = (int64_t)A.ER * MM;
         hipLaunchKernelGGL(fill_d, dim3((unsigned)((ng + 255) / 256 < 65535 ? (ng + 255) / 256 : 65535)),
                            dim3(256), 0, st, A.gpart, ng, 0.0);
-        hipLaunchKernelGGL(fill_d, dim3(64), dim3(256), 0, st, A.spart, (int64_t)A.ER * M, 0.0);
-        hipLaunchKernelGGL(fill_d, dim3(64), dim3(256), 0, st, A.cpart_, (int64_t)A.ER * M, 0.0);
+        hipLaunchKernelGGL(fill_d, dim3(64), dim3(256), 0, st, A.spart, (int64_t)A.NRUN * M, 0.0);
+        hipLaunchKernelGGL(fill_d, dim3(64), dim3(256), 0, st, A.cpart_, (int64_t)A.NRUN * M, 0.0);
     }
     hipLaunchKernelGGL(large_colsum, dim3((unsigned)((M + 63) / 64)), dim3(1024), 0, st, M, A.alpha, A.colsum);
     large_build_index(M, A.alpha, 0, A.csr_ptr, A.csr_col, A.csr_val, st);
@@ -647,13 +665,14 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
             {
                 TimedScope tb(6, st);
                 bucket_chunk(A, c0, c1, nseg, A.wchunk, A.CPL == 2 ? 7 : 6, st);
+                bucket_chunk_into(A, c0, c1, nseg, A.wchunk, 4, A.bo_cnt, A.bo_off, A.bo_base, A.bo_key, A.bo_t,
+                                  A.bo_w, st);
             }
-            TimedScope ts(0, st);
             large_dense_launch(A, c0, c1, nseg, st);
         }
     }
     const int64_t nfin = A.grad ? (MM > M ? MM : M) : 1;
-    hipLaunchKernelGGL(large_final, dim3((unsigned)((nfin + 255) / 256)), dim3(256), 0, st, M, A.ER, A.T, A.mu,
+    hipLaunchKernelGGL(large_final, dim3((unsigned)((nfin + 255) / 256)), dim3(256), 0, st, M, A.ER, A.NRUN, A.T, A.mu,
                        A.acc, A.gpart, A.spart, A.cpart_, A.loglik, A.g_mu, A.g_alpha, A.g_beta, A.grad ? 1 : 0);
     return hipGetLastError() == hipSuccess ? HAWKES_OK : HAWKES_EDEVICE;
 }
