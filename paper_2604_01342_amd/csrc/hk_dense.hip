@@ -39,42 +39,70 @@ namespace hk {
 
 static_assert(HK_DR == 16, "row blocks are the 16-node buckets");
 
-// checkpoint slot of group g of (column block sb, run r) whose first column
-// record sits at position P0 of the block-major records: slots of different
-// (sb, r) never overlap, and there are at most CH / 64 + 2 NBC nrun + 1
-__device__ __forceinline__ int64_t ck_slot(int64_t P0, int32_t sb, int32_t nrun, int32_t r) {
-    return (P0 >> 6) + 2 * ((int64_t)sb * nrun + r);
-}
-
+// Checkpoint slots: group g of (column block sb, run r) uses slot
+// (P0 >> 6) + 2 (sb nrun + r) + g, with P0 the position of the run's first
+// record in the column block's share of the 16-node partition; the slots of
+// different (sb, r) never overlap, and there are at most
+// (events) / 64 + 2 NBC nrun + 1.
+// Checkpoint slot record, in float64 words: the state (W), the anchor time
+// (8 copies), the group's 64 record times, then its 64 record keys (u32, two
+// per word; lanes past the group's end hold 0xffffffff).
 template <int CPL>
-__global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t M, int32_t NBC, int32_t nrun, int32_t ckr,
-                                               int32_t nseg, double T, const double* __restrict__ t,
-                                               const float* __restrict__ beta,
+struct Slot {
+    static constexpr int W = 64 * CPL;
+    static constexpr int TAU = W;
+    static constexpr int T = W + 8;
+    static constexpr int KEY = W + 72;
+    static constexpr int SIZE = W + 104;
+};
+
+// One wave per (column block, run): scans the run's events in index order,
+// keeps those of the column block (staged in LDS), and for every group of 64
+// writes the checkpoint and the group's records into its slot, then folds the
+// group into the state.  Runs r with the same r / 8 share an XCD (their
+// column blocks read the same events).  runinfo[sb][r] = (first slot, groups,
+// P0, P1), P0..P1 the run's positions in the column block's share of the
+// 16-node partition.
+template <int CPL>
+__global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t M, int32_t NBC, int32_t NBO,
+                                               int32_t nrun, int32_t ckr, int32_t nseg, double T,
+                                               const double* __restrict__ t, const int32_t* __restrict__ marks,
+                                               const float* __restrict__ wchunk, const float* __restrict__ beta,
                                                const double* __restrict__ carry_seg,
-                                               const int32_t* __restrict__ bk_off,
-                                               const int32_t* __restrict__ bk_base,
-                                               const uint32_t* __restrict__ bk_key,
-                                               const double* __restrict__ bk_t, const float* __restrict__ bk_w,
-                                               double* __restrict__ kck, double* __restrict__ spart,
+                                               const int32_t* __restrict__ bo_off,
+                                               const int32_t* __restrict__ bo_base, double* __restrict__ kck,
+                                               int4* __restrict__ runinfo, double* __restrict__ spart,
                                                double* __restrict__ cpart) {
-    constexpr int W = 64 * CPL;
-    constexpr int KS = W + 8;   // slot stride: state, then 8 copies of the anchor time
+    using S = Slot<CPL>;
+    constexpr int W = S::W;
+    constexpr int SH = CPL == 2 ? 7 : 6;   // bits of the local mark in a record key
     __shared__ double DL[W], SL[W], CL[W];
+    __shared__ uint32_t stK[128];
+    __shared__ double stT[128];
+    __shared__ float stW[128];
     const int lane = threadIdx.x;
-    const int32_t sb = (int32_t)(blockIdx.x % (unsigned)NBC);
-    const int32_t r = (int32_t)(blockIdx.x / (unsigned)NBC);
+    const int32_t x = (int32_t)(blockIdx.x & 7u), grp = (int32_t)(blockIdx.x >> 3);
+    const int32_t sb = grp % NBC;
+    const int32_t r = (grp / NBC) * 8 + x;
     const int32_t sA = r * ckr;
     if (sA >= nseg) return;
     const int32_t sB = sA + ckr < nseg ? sA + ckr : nseg;
 #pragma unroll
     for (int j = 0; j < CPL; ++j) DL[j * 64 + lane] = SL[j * 64 + lane] = CL[j * 64 + lane] = 0.0;
-    const int64_t a = c0 + (int64_t)sA * HK_SEG;
+    const int32_t a = sA * HK_SEG;
+    const int32_t b = sB * HK_SEG < nev ? sB * HK_SEG : nev;
     const int32_t s0 = sb * W;
-    const int64_t cb = bk_base[sb];
-    const int64_t P0 = cb + bk_off[(int64_t)sb * (nseg + 1) + sA];
-    const int64_t P1 = cb + bk_off[(int64_t)sb * (nseg + 1) + sB];
-    const int32_t ng = (int32_t)((P1 - P0 + 63) >> 6);
-    const int64_t slot0 = ck_slot(P0, sb, nrun, r);
+    // the column block's 16-node blocks are consecutive in the partition
+    const int32_t k0 = sb * (W / 16);
+    const int32_t k1 = k0 + W / 16 < NBO ? k0 + W / 16 : NBO;
+    int32_t P0 = bo_base[k0], P1 = bo_base[k0];
+    for (int32_t k = k0; k < k1; ++k) {
+        P0 += bo_off[(int64_t)k * (nseg + 1) + sA];
+        P1 += bo_off[(int64_t)k * (nseg + 1) + sB];
+    }
+    const int32_t ng = (P1 - P0 + 63) >> 6;
+    const int32_t slot0 = (P0 >> 6) + 2 * (sb * nrun + r);
+    if (lane == 0) runinfo[(int64_t)sb * nrun + r] = make_int4(slot0, ng, P0, P1);
     const double bet = (double)beta[0];
     double K[CPL];
 #pragma unroll
@@ -82,35 +110,30 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t M, int32_t NB
         const int32_t col = s0 + j * 64 + lane;
         K[j] = col < M ? carry_seg[(int64_t)sA * 2 * M + col] : 0.0;
     }
-    double tau = a > 0 ? t[a - 1] : t[a];
-    __syncthreads();
-    // record of this lane in group g (clamped to a valid record)
-    auto rec = [&](int32_t g) -> int64_t {
-        const int64_t e = P0 + 64 * (int64_t)g + lane;
-        return e < P1 ? e : (P1 > P0 ? P1 - 1 : 0);
-    };
-    int64_t e = rec(0);
-    uint32_t key = bk_key[e];
-    double tj = bk_t[e];
-    float wj = bk_w[e];
-    for (int32_t g = 0;; ++g) {
-        double* out = kck + (slot0 + g) * KS;
+    double tau = c0 + a > 0 ? t[c0 + a - 1] : t[c0];
+    int32_t g = 0;
+    auto put_state = [&]() {
+        double* out = kck + (int64_t)(slot0 + g) * S::SIZE;
 #pragma unroll
         for (int j = 0; j < CPL; ++j) out[j * 64 + lane] = K[j];
-        if (lane < 8) out[W + lane] = tau;
-        if (g == ng) break;
-        // next group's records in flight while this one is folded in
-        const int64_t en = rec(g + 1 < ng ? g + 1 : g);
-        const uint32_t keyn = bk_key[en];
-        const double tjn = bk_t[en];
-        const float wjn = bk_w[en];
-        const int64_t rem = P1 - (P0 + 64 * (int64_t)g);
-        const int nv = rem < 64 ? (int)rem : 64;
+        if (lane < 8) out[S::TAU + lane] = tau;
+    };
+    // group g = staged records [0, nv): checkpoint, records, then the state
+    // moves past the group
+    auto emit = [&](int nv) {
+        put_state();
+        double* out = kck + (int64_t)(slot0 + g) * S::SIZE;
+        const bool v = lane < nv;
+        const uint32_t key = v ? stK[lane] : 0xffffffffu;
+        const double tj = v ? stT[lane] : 0.0;
+        const float wj = v ? stW[lane] : 0.0f;
+        out[S::T + lane] = tj;
+        reinterpret_cast<uint32_t*>(out + S::KEY)[lane] = key;
         const double tn = rl_d(tj, nv - 1);
         const double f = (double)exp_f64arg(-bet * (tn - tau));
 #pragma unroll
         for (int j = 0; j < CPL; ++j) K[j] *= f;
-        if (lane < nv) {
+        if (v) {
             const int col = (int)(key & (uint32_t)(W - 1));
             atomicAdd(&DL[col], (double)exp_f64arg(-bet * (tn - tj)));
             atomicAdd(&SL[col], (double)wj);
@@ -123,10 +146,55 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t M, int32_t NB
             DL[j * 64 + lane] = 0.0;
         }
         tau = tn;
-        key = keyn;
-        tj = tjn;
-        wj = wjn;
+        ++g;
+    };
+    __syncthreads();
+    int cnt = 0;   // staged records
+    int32_t i = a + lane;
+    int mk = i < b ? clamp_mark(marks[c0 + i], M) : -1;
+    for (int32_t base = a; base < b; base += 64) {
+        // next batch's marks in flight
+        const int32_t in = i + 64;
+        const int mkn = in < b ? clamp_mark(marks[c0 + in], M) : -1;
+        const bool sel = mk >= s0 && mk < s0 + W;
+        const uint64_t bal = __ballot(sel);
+        if (bal) {
+            const int pos = cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+            if (sel) {
+                stK[pos] = ((uint32_t)i << SH) | (uint32_t)(mk - s0);
+                stT[pos] = t[c0 + i];
+                stW[pos] = wchunk[i];
+            }
+            cnt += __builtin_popcountll(bal);
+            if (cnt >= 64) {
+                __syncthreads();
+                emit(64);
+                // keep the overflow [64, cnt) at the front
+                const bool mv = lane < cnt - 64;
+                uint32_t k2 = 0;
+                double t2 = 0.0;
+                float w2 = 0.0f;
+                if (mv) {
+                    k2 = stK[64 + lane];
+                    t2 = stT[64 + lane];
+                    w2 = stW[64 + lane];
+                }
+                __syncthreads();
+                if (mv) {
+                    stK[lane] = k2;
+                    stT[lane] = t2;
+                    stW[lane] = w2;
+                }
+                cnt -= 64;
+            }
+        }
+        i = in;
+        mk = mkn;
     }
+    __syncthreads();
+    if (cnt > 0) emit(cnt);
+    put_state();   // after the last group (g == ng)
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
@@ -179,17 +247,14 @@ template <int CPL>
 __global__ __launch_bounds__(64) void large_dense(int32_t M, int32_t NBC, int32_t NBR, int32_t ER, int32_t rpr,
                                                   int32_t nrun, int32_t ckr, int32_t nseg, int32_t nrec,
                                                   int32_t nslot, const float* __restrict__ beta,
-                                                  const int32_t* __restrict__ bk_off,
-                                                  const int32_t* __restrict__ bk_base,
-                                                  const uint32_t* __restrict__ bk_key,
-                                                  const double* __restrict__ bk_t,
+                                                  const int4* __restrict__ runinfo,
                                                   const int32_t* __restrict__ bo_off,
                                                   const int32_t* __restrict__ bo_base,
                                                   const uint32_t* __restrict__ bo_key,
                                                   const double* __restrict__ bo_t, const float* __restrict__ bo_w,
                                                   const double* __restrict__ kck, double* __restrict__ gpart) {
-    constexpr int W = 64 * CPL;
-    constexpr int KS = W + 8;
+    using S = Slot<CPL>;
+    constexpr int W = S::W;
     constexpr int SH = CPL == 2 ? 7 : 6;   // bits of the local mark in a column record key
     __shared__ double GP[HK_DR * W];   // pair terms
     __shared__ double UL[HK_DR];       // the window's u
@@ -240,20 +305,18 @@ __global__ __launch_bounds__(64) void large_dense(int32_t M, int32_t NBC, int32_
     }
     if (lane < HK_DR) UL[lane] = 0.0;
     const double bet = (double)beta[0];
-    const __amdgpu_buffer_rsrc_t rK = buf(kck, (uint32_t)nslot * KS * 8u);
-    const __amdgpu_buffer_rsrc_t rCk = buf(bk_key, (uint32_t)nrec * 4u);
-    const __amdgpu_buffer_rsrc_t rCt = buf(bk_t, (uint32_t)nrec * 8u);
+    const __amdgpu_buffer_rsrc_t rK = buf(kck, (uint32_t)nslot * S::SIZE * 8u);
     const __amdgpu_buffer_rsrc_t rOk = buf(bo_key, (uint32_t)nrec * 4u);
     const __amdgpu_buffer_rsrc_t rOt = buf(bo_t, (uint32_t)nrec * 8u);
     const __amdgpu_buffer_rsrc_t rOw = buf(bo_w, (uint32_t)nrec * 4u);
-    const int32_t cb = bk_base[sb];
-    const int32_t* offc = bk_off + (int64_t)sb * (nseg + 1);
+    const int4* rinf = runinfo + (int64_t)sb * nrun;
     auto run_info = [&](int32_t rr) -> Run {
+        const int4 v = rinf[rr];
         Run x;
-        x.P0 = cb + offc[rr * ckr];
-        x.P1 = cb + offc[(rr + 1) * ckr < nseg ? (rr + 1) * ckr : nseg];
-        x.ng = (x.P1 - x.P0 + 63) >> 6;
-        x.slot0 = (x.P0 >> 6) + 2 * (sb * nrun + rr);
+        x.slot0 = v.x;
+        x.ng = v.y;
+        x.P0 = v.z;
+        x.P1 = v.w;
         return x;
     };
     // own stream: records [Q0, Q1) of row block rb, q the next unconsumed
@@ -274,13 +337,12 @@ __global__ __launch_bounds__(64) void large_dense(int32_t M, int32_t NBC, int32_
     own_load(o0, Q0);
     own_load(o2, Q0);
     auto load_win = [&](Win<CPL>& w, const Run& ru, int32_t gg) {
-        const uint32_t sl = (uint32_t)(ru.slot0 + gg) * KS;
+        const uint32_t sl = (uint32_t)(ru.slot0 + gg) * S::SIZE;
 #pragma unroll
         for (int j = 0; j < CPL; ++j) w.K[j] = ld_f64(rK, sl + j * 64 + lane);
-        w.tau = ld_f64(rK, sl + W + (lane & 7));
-        const uint32_t e = (uint32_t)(ru.P0 + 64 * gg + lane);
-        w.ckey = ld_u32(rCk, e);
-        w.ct = ld_f64(rCt, e);
+        w.tau = ld_f64(rK, sl + S::TAU + (lane & 7));
+        w.ct = ld_f64(rK, sl + S::T + lane);
+        w.ckey = ld_u32(rK, 2 * (sl + S::KEY) + lane);
     };
 
     // own records of the window in o0 from lane p on (index <= hi): adds
@@ -433,32 +495,33 @@ __global__ __launch_bounds__(64) void large_dense(int32_t M, int32_t NBC, int32_
 
 void large_dense_launch(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, hipStream_t st) {
     const int32_t nrun_c = (nseg + A.CKR - 1) / A.CKR;
+    const int32_t nev = (int32_t)(c1 - c0);
     {
         TimedScope tk(7, st);
+        const unsigned nck = (unsigned)(((nrun_c + 7) / 8) * 8 * A.NBC);
         if (A.CPL == 2)
-            hipLaunchKernelGGL(dense_ck<2>, dim3((unsigned)(A.NBC * nrun_c)), dim3(64), 0, st, c0, A.M, A.NBC,
-                               A.NRUN, A.CKR, nseg, A.T, A.t, A.beta, A.carry_seg, A.bk_off, A.bk_base, A.bk_key,
-                               A.bk_t, A.bk_w, A.kck, A.spart, A.cpart_);
+            hipLaunchKernelGGL(dense_ck<2>, dim3(nck), dim3(64), 0, st, c0, nev, A.M, A.NBC, A.NBO, A.NRUN, A.CKR,
+                               nseg, A.T, A.t, A.marks, A.wchunk, A.beta, A.carry_seg, A.bo_off, A.bo_base, A.kck,
+                               A.runinfo, A.spart, A.cpart_);
         else
-            hipLaunchKernelGGL(dense_ck<1>, dim3((unsigned)(A.NBC * nrun_c)), dim3(64), 0, st, c0, A.M, A.NBC,
-                               A.NRUN, A.CKR, nseg, A.T, A.t, A.beta, A.carry_seg, A.bk_off, A.bk_base, A.bk_key,
-                               A.bk_t, A.bk_w, A.kck, A.spart, A.cpart_);
+            hipLaunchKernelGGL(dense_ck<1>, dim3(nck), dim3(64), 0, st, c0, nev, A.M, A.NBC, A.NBO, A.NRUN, A.CKR,
+                               nseg, A.T, A.t, A.marks, A.wchunk, A.beta, A.carry_seg, A.bo_off, A.bo_base, A.kck,
+                               A.runinfo, A.spart, A.cpart_);
     }
     TimedScope ts(0, st);
     const int32_t rpr = A.NRUN / A.ER;   // runs per event range (both powers of two)
     const int32_t nbb = A.NBR * A.NBC;
     const unsigned nblk = A.ER >= 8 ? (unsigned)(nbb * ((A.ER + 7) / 8) * 8)
                                     : (unsigned)(((nbb + 8 / A.ER - 1) / (8 / A.ER)) * 8);
-    const int32_t nrec = (int32_t)(c1 - c0);
     const int32_t nslot = (int32_t)A.nslot;
     if (A.CPL == 2)
         hipLaunchKernelGGL(large_dense<2>, dim3(nblk), dim3(64), 0, st, A.M, A.NBC, A.NBR, A.ER, rpr, A.NRUN,
-                           A.CKR, nseg, nrec, nslot, A.beta, A.bk_off, A.bk_base, A.bk_key, A.bk_t, A.bo_off,
-                           A.bo_base, A.bo_key, A.bo_t, A.bo_w, A.kck, A.gpart);
+                           A.CKR, nseg, nev, nslot, A.beta, A.runinfo, A.bo_off, A.bo_base, A.bo_key, A.bo_t,
+                           A.bo_w, A.kck, A.gpart);
     else
         hipLaunchKernelGGL(large_dense<1>, dim3(nblk), dim3(64), 0, st, A.M, A.NBC, A.NBR, A.ER, rpr, A.NRUN,
-                           A.CKR, nseg, nrec, nslot, A.beta, A.bk_off, A.bk_base, A.bk_key, A.bk_t, A.bo_off,
-                           A.bo_base, A.bo_key, A.bo_t, A.bo_w, A.kck, A.gpart);
+                           A.CKR, nseg, nev, nslot, A.beta, A.runinfo, A.bo_off, A.bo_base, A.bo_key, A.bo_t,
+                           A.bo_w, A.kck, A.gpart);
 }
 
 }  // namespace hk

@@ -55,8 +55,9 @@ struct LargeArgs {
     double* ll_scratch;   // [1] log-likelihood slot when the caller wants intensities only
     double *gpart, *spart, *cpart_;  // [ER][M][M]; [ER][M] per target, [NRUN][M] shared decay
     int64_t nslot;        // checkpoint slots
-    double* kck;          // [nslot][64 CPL + 8] state checkpoints of the dense gradient (shared
-                          //   decay): the state, then its anchor time (8 copies)
+    double* kck;          // [nslot][64 CPL + 104] state checkpoints of the dense gradient (shared
+                          //   decay) with their groups' records
+    int4* runinfo;        // [NBC][NRUN] per checkpoint run: first slot, groups, P0, P1
     // per-target decays (R-form forward, reverse adjoint for the gradient)
     int32_t *csc_ptr, *csc_row;   // alpha by column: targets p of source q
     float* csc_val;
@@ -69,6 +70,7 @@ struct LargeArgs {
     double *rgagg, *rgcarry;  // [ngr][M] reverse group aggregates and carries
     double* achunk;       // [M] adjoint state entering the current chunk from the right
     // events of the chunk partitioned by node block (64 nodes), in event order
+    // (per-target decays)
     int32_t* bk_cnt;      // [NB][nseg] events per (block, segment)
     int32_t* bk_off;      // [NB][nseg + 1] start of each (block, segment) run within the block
     int32_t* bk_base;     // [NB] start of each block in the records

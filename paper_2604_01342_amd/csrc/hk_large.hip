@@ -515,19 +515,22 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
     }
     if (grad) {
         if (!A.per_target) A.wchunk = c.take<float>(A.CH);
-        A.bk_cnt = c.take<int32_t>((size_t)A.NB * A.nseg);
-        A.bk_off = c.take<int32_t>((size_t)A.NB * (A.nseg + 1));
-        A.bk_base = c.take<int32_t>(A.NB);
-        A.bk_key = c.take<uint32_t>(A.CH);
-        A.bk_t = c.take<double>(A.CH);
-        A.bk_w = c.take<float>(A.CH);
+        if (A.per_target) {
+            A.bk_cnt = c.take<int32_t>((size_t)A.NB * A.nseg);
+            A.bk_off = c.take<int32_t>((size_t)A.NB * (A.nseg + 1));
+            A.bk_base = c.take<int32_t>(A.NB);
+            A.bk_key = c.take<uint32_t>(A.CH);
+            A.bk_t = c.take<double>(A.CH);
+            A.bk_w = c.take<float>(A.CH);
+        }
         A.gpart = c.take<double>((size_t)A.ER * MM);
         const int64_t nsp = A.per_target ? A.ER : A.NRUN;
         A.spart = c.take<double>((size_t)nsp * M);
         A.cpart_ = c.take<double>((size_t)nsp * M);
         if (!A.per_target) {
             A.nslot = A.CH / 64 + 2 * (int64_t)A.NBC * A.NRUN + 2;
-            A.kck = c.take<double>((size_t)A.nslot * (64 * A.CPL + 8));
+            A.kck = c.take<double>((size_t)A.nslot * (64 * A.CPL + 104));
+            A.runinfo = c.take<int4>((size_t)A.NBC * A.NRUN);
             A.NBO = (A.M + HK_DR - 1) / HK_DR;
             A.bo_cnt = c.take<int32_t>((size_t)A.NBO * A.nseg);
             A.bo_off = c.take<int32_t>((size_t)A.NBO * (A.nseg + 1));
@@ -614,7 +617,7 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
         return HAWKES_EUNSUPPORTED;
     // the dense-gradient kernels address checkpoints and records with
     // 32-bit byte offsets
-    if (A.grad && (uint64_t)A.nslot * (uint64_t)(64 * A.CPL + 8) * 8u >= (1ull << 32))
+    if (A.grad && (uint64_t)A.nslot * (uint64_t)(64 * A.CPL + 104) * 8u >= (1ull << 32))
         return HAWKES_EUNSUPPORTED;
     // zero the carried state and accumulators
     hipLaunchKernelGGL(fill_d, dim3(1), dim3(256), 0, st, A.carry, (int64_t)2 * M, 0.0);
@@ -664,7 +667,6 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
         if (A.grad) {
             {
                 TimedScope tb(6, st);
-                bucket_chunk(A, c0, c1, nseg, A.wchunk, A.CPL == 2 ? 7 : 6, st);
                 bucket_chunk_into(A, c0, c1, nseg, A.wchunk, 4, A.bo_cnt, A.bo_off, A.bo_base, A.bo_key, A.bo_t,
                                   A.bo_w, st);
             }
