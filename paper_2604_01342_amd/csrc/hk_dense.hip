@@ -56,13 +56,14 @@ struct Slot {
     static constexpr int SIZE = W + 104;
 };
 
-// One wave per (column block, run): scans the run's events in index order,
-// keeps those of the column block (staged in LDS), and for every group of 64
-// writes the checkpoint and the group's records into its slot, then folds the
-// group into the state.  Runs r with the same r / 8 share an XCD (their
-// column blocks read the same events).  runinfo[sb][r] = (first slot, groups,
-// P0, P1), P0..P1 the run's positions in the column block's share of the
-// 16-node partition.
+// One wave per (column block, run), in two phases.  (1) Scan the run's marks
+// (several batches of 64 in flight) and compact the keys of the column
+// block's events, in index order, into LDS.  (2) For every group of 64 keys
+// (times and weights loaded one group ahead): write the checkpoint and the
+// group's records into its slot, then fold the group into the state.  Runs r
+// with the same r / 8 share an XCD (their column blocks read the same
+// events).  runinfo[sb][r] = (first slot, groups, P0, P1), P0..P1 the run's
+// positions in the column block's share of the 16-node partition.
 template <int CPL>
 __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t M, int32_t NBC, int32_t NBO,
                                                int32_t nrun, int32_t ckr, int32_t nseg, double T,
@@ -76,10 +77,9 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
     using S = Slot<CPL>;
     constexpr int W = S::W;
     constexpr int SH = CPL == 2 ? 7 : 6;   // bits of the local mark in a record key
+    constexpr int UB = 4;                  // batches of marks in flight
     __shared__ double DL[W], SL[W], CL[W];
-    __shared__ uint32_t stK[128];
-    __shared__ double stT[128];
-    __shared__ float stW[128];
+    __shared__ uint32_t keys[HK_CKR * HK_SEG];
     const int lane = threadIdx.x;
     const int32_t x = (int32_t)(blockIdx.x & 7u), grp = (int32_t)(blockIdx.x >> 3);
     const int32_t sb = grp % NBC;
@@ -103,6 +103,30 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
     const int32_t ng = (P1 - P0 + 63) >> 6;
     const int32_t slot0 = (P0 >> 6) + 2 * (sb * nrun + r);
     if (lane == 0) runinfo[(int64_t)sb * nrun + r] = make_int4(slot0, ng, P0, P1);
+
+    // (1) compaction (at most ckr * HK_SEG keys)
+    int cnt = 0;
+    for (int32_t base = a; base < b; base += 64 * UB) {
+        int mk[UB];
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+            const int32_t i = base + 64 * u + lane;
+            mk[u] = i < b ? clamp_mark(marks[c0 + i], M) : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+            const int32_t i = base + 64 * u + lane;
+            const bool sel = mk[u] >= s0 && mk[u] < s0 + W;
+            const uint64_t bal = __ballot(sel);
+            const int pos = cnt + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+            if (sel) keys[pos] = ((uint32_t)i << SH) | (uint32_t)(mk[u] - s0);
+            cnt += __builtin_popcountll(bal);
+        }
+    }
+    __syncthreads();
+
+    // (2) groups
     const double bet = (double)beta[0];
     double K[CPL];
 #pragma unroll
@@ -111,33 +135,43 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
         K[j] = col < M ? carry_seg[(int64_t)sA * 2 * M + col] : 0.0;
     }
     double tau = c0 + a > 0 ? t[c0 + a - 1] : t[c0];
-    int32_t g = 0;
-    auto put_state = [&]() {
+    struct Rec {
+        uint32_t key;
+        double t;
+        float w;
+    };
+    auto load = [&](Rec& q, int32_t g) {
+        const int32_t e = 64 * g + lane;
+        q.key = e < cnt ? keys[e] : 0xffffffffu;
+        const int32_t i = e < cnt ? (int32_t)(q.key >> SH) : a;
+        q.t = t[c0 + i];
+        q.w = wchunk[i];
+    };
+    auto put_state = [&](int32_t g) {
         double* out = kck + (int64_t)(slot0 + g) * S::SIZE;
 #pragma unroll
         for (int j = 0; j < CPL; ++j) out[j * 64 + lane] = K[j];
         if (lane < 8) out[S::TAU + lane] = tau;
     };
-    // group g = staged records [0, nv): checkpoint, records, then the state
-    // moves past the group
-    auto emit = [&](int nv) {
-        put_state();
-        double* out = kck + (int64_t)(slot0 + g) * S::SIZE;
+    // group g with records q: checkpoint, records, then the state moves past
+    // the group
+    auto emit = [&](const Rec& q, int32_t g) {
+        put_state(g);
+        const int rem = cnt - 64 * g;
+        const int nv = rem < 64 ? rem : 64;
         const bool v = lane < nv;
-        const uint32_t key = v ? stK[lane] : 0xffffffffu;
-        const double tj = v ? stT[lane] : 0.0;
-        const float wj = v ? stW[lane] : 0.0f;
-        out[S::T + lane] = tj;
-        reinterpret_cast<uint32_t*>(out + S::KEY)[lane] = key;
-        const double tn = rl_d(tj, nv - 1);
+        double* out = kck + (int64_t)(slot0 + g) * S::SIZE;
+        out[S::T + lane] = v ? q.t : 0.0;
+        reinterpret_cast<uint32_t*>(out + S::KEY)[lane] = q.key;
+        const double tn = rl_d(q.t, nv - 1);
         const double f = (double)exp_f64arg(-bet * (tn - tau));
 #pragma unroll
         for (int j = 0; j < CPL; ++j) K[j] *= f;
         if (v) {
-            const int col = (int)(key & (uint32_t)(W - 1));
-            atomicAdd(&DL[col], (double)exp_f64arg(-bet * (tn - tj)));
-            atomicAdd(&SL[col], (double)wj);
-            atomicAdd(&CL[col], -expm1(-bet * (T - tj)));
+            const int col = (int)(q.key & (uint32_t)(W - 1));
+            atomicAdd(&DL[col], (double)exp_f64arg(-bet * (tn - q.t)));
+            atomicAdd(&SL[col], (double)q.w);
+            atomicAdd(&CL[col], -expm1(-bet * (T - q.t)));
         }
         __syncthreads();
 #pragma unroll
@@ -146,55 +180,20 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
             DL[j * 64 + lane] = 0.0;
         }
         tau = tn;
-        ++g;
     };
-    __syncthreads();
-    int cnt = 0;   // staged records
-    int32_t i = a + lane;
-    int mk = i < b ? clamp_mark(marks[c0 + i], M) : -1;
-    for (int32_t base = a; base < b; base += 64) {
-        // next batch's marks in flight
-        const int32_t in = i + 64;
-        const int mkn = in < b ? clamp_mark(marks[c0 + in], M) : -1;
-        const bool sel = mk >= s0 && mk < s0 + W;
-        const uint64_t bal = __ballot(sel);
-        if (bal) {
-            const int pos = cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-            if (sel) {
-                stK[pos] = ((uint32_t)i << SH) | (uint32_t)(mk - s0);
-                stT[pos] = t[c0 + i];
-                stW[pos] = wchunk[i];
-            }
-            cnt += __builtin_popcountll(bal);
-            if (cnt >= 64) {
-                __syncthreads();
-                emit(64);
-                // keep the overflow [64, cnt) at the front
-                const bool mv = lane < cnt - 64;
-                uint32_t k2 = 0;
-                double t2 = 0.0;
-                float w2 = 0.0f;
-                if (mv) {
-                    k2 = stK[64 + lane];
-                    t2 = stT[64 + lane];
-                    w2 = stW[64 + lane];
-                }
-                __syncthreads();
-                if (mv) {
-                    stK[lane] = k2;
-                    stT[lane] = t2;
-                    stW[lane] = w2;
-                }
-                cnt -= 64;
-            }
-        }
-        i = in;
-        mk = mkn;
+    Rec ra, rb;
+    load(ra, 0);
+    int32_t g = 0;
+    while (g < ng) {
+        load(rb, g + 1);
+        emit(ra, g);
+        ++g;
+        if (g >= ng) break;
+        load(ra, g + 1);
+        emit(rb, g);
+        ++g;
     }
-    __syncthreads();
-    if (cnt > 0) emit(cnt);
-    put_state();   // after the last group (g == ng)
+    put_state(ng);   // after the last group
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
