@@ -77,7 +77,7 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
     using S = Slot<CPL>;
     constexpr int W = S::W;
     constexpr int SH = CPL == 2 ? 7 : 6;   // bits of the local mark in a record key
-    constexpr int UB = 4;                  // batches of marks in flight
+    constexpr int UB = 16;                 // batches of marks in flight
     __shared__ double DL[W], SL[W], CL[W];
     __shared__ uint32_t keys[HK_CKR * HK_SEG];
     const int lane = threadIdx.x;

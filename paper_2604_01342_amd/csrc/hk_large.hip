@@ -291,22 +291,48 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
     }
     __syncthreads();
     double logsum = 0.0, comp = 0.0, Esum = 0.0, gb = 0.0;
-    // software pipeline: the next batch's times and marks are loaded while
-    // the current one is processed (clamped indices keep the loads valid)
-    double t_nx = t[a + lane < b ? a + lane : b - 1];
-    int m_nx = marks[a + lane < b ? a + lane : b - 1];
+    // software pipeline over batches of 64 events: times and marks are loaded
+    // three batches ahead, node records two ahead and the first FW nonzeros
+    // of each event's row of alpha one ahead (clamped indices keep every load
+    // valid), so the gathers' latency hides behind a batch of work
+    constexpr int FW = 16;
+    auto ld_tm = [&](int64_t base, double& tt, int& mm) {
+        const int64_t j = base + lane;
+        const int64_t jc = j < b ? j : b - 1;
+        tt = t[jc];
+        mm = clamp_mark(marks[jc], M);
+    };
+    auto ld_row = [&](const int4& nv, int32_t (&qc)[FW], float (&qa)[FW]) {
+#pragma unroll
+        for (int j = 0; j < FW; ++j) {
+            const int32_t k = nv.x + j < nv.y ? nv.x + j : nv.x;
+            qc[j] = csr_col[k];
+            qa[j] = csr_val[k];
+        }
+    };
+    double t0, t1, t2;
+    int m0, m1, m2;
+    ld_tm(a, t0, m0);
+    ld_tm(a + 64, t1, m1);
+    ld_tm(a + 128, t2, m2);
+    int4 n0 = node_info[m0], n1 = node_info[m1];
+    int32_t qc0[FW];
+    float qa0[FW];
+    ld_row(n0, qc0, qa0);
     for (int64_t base = a; base < b; base += 64) {
         const int64_t i = base + lane;
         const bool valid = i < b;
-        const double ti = valid ? t_nx : 0.0;
-        const int mi = valid ? clamp_mark(m_nx, M) : 0;
-        {
-            const int64_t j = base + 64 + lane;
-            const int64_t jc = j < b ? j : b - 1;
-            t_nx = t[jc];
-            m_nx = marks[jc];
-        }
-        const int4 ni = node_info[mi];
+        const double ti = valid ? t0 : 0.0;
+        const int mi = valid ? m0 : 0;
+        const int4 ni = n0;
+        // loads for the batches ahead
+        double t3;
+        int m3;
+        ld_tm(base + 192, t3, m3);
+        const int4 n2 = node_info[m2];
+        int32_t qc1[FW];
+        float qa1[FW];
+        ld_row(n1, qc1, qa1);
         tb[lane] = ti;
         if (valid) atomicOr((unsigned long long*)&rmask[mi], 1ull << lane);
         __syncthreads();
@@ -314,39 +340,32 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
         if (valid) {
             const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
             const int32_t k0 = ni.x, k1 = ni.y;
-            for (int32_t kb = k0; kb < k1; kb += 8) {
-                int32_t qv[8];
-                float av[8];
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const int32_t k = kb + j;
-                    qv[j] = k < k1 ? csr_col[k] : -1;
-                    av[j] = k < k1 ? csr_val[k] : 0.0f;
+            // contribution of source q with weight av: the record decayed to
+            // ti plus the batch's earlier events of q
+            auto term = [&](int32_t q, float av) {
+                const double d = ti - rtau[q];
+                const double e = exp_f64(-bet * d);
+                const double kq = rK[q];
+                double Kv = e * kq;
+                double Jv = GRAD ? e * __builtin_fma(d, kq, rJ[q]) : 0.0;
+                uint64_t bits = rmask[q] & below;
+                while (bits) {
+                    const int jj = __builtin_ctzll(bits);
+                    bits &= bits - 1;
+                    const double dj = ti - tb[jj];
+                    const double ej = exp_f64(-bet * dj);
+                    Kv += ej;
+                    if (GRAD) Jv = __builtin_fma(dj, ej, Jv);
                 }
+                R = __builtin_fma((double)av, Kv, R);
+                if (GRAD) Dd = __builtin_fma((double)av, Jv, Dd);
+            };
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    if (qv[j] < 0) continue;
-                    const int32_t q = qv[j];
-                    const double d = ti - rtau[q];
-                    const double e = exp_f64(-bet * d);
-                    const double kq = rK[q];
-                    double Kv = e * kq;
-                    double Jv = GRAD ? e * __builtin_fma(d, kq, rJ[q]) : 0.0;
-                    uint64_t bits = rmask[q] & below;
-                    while (bits) {
-                        const int jj = __builtin_ctzll(bits);
-                        bits &= bits - 1;
-                        const double dj = ti - tb[jj];
-                        const double ej = exp_f64(-bet * dj);
-                        Kv += ej;
-                        if (GRAD) Jv = __builtin_fma(dj, ej, Jv);
-                    }
-                    R = __builtin_fma((double)av[j], Kv, R);
-                    if (GRAD) Dd = __builtin_fma((double)av[j], Jv, Dd);
-                }
-            }
+            for (int j = 0; j < FW; ++j)
+                if (k0 + j < k1) term(qc0[j], qa0[j]);
+            for (int32_t k = k0 + FW; k < k1; ++k) term(csr_col[k], csr_val[k]);
             lam = __builtin_fma(bet, R, (double)__int_as_float(ni.z));
-            if (INTENS) lambda_out[i] = (float)lam;
+        if (INTENS) lambda_out[i] = (float)lam;
             logsum += log(lam);
             const double x = bet * (T - ti);
             em1 = -expm1(-x);   // 1 - e^{-x}
@@ -383,6 +402,19 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
         __syncthreads();
         if (valid) rmask[mi] = 0ull;
         __syncthreads();
+        t0 = t1;
+        m0 = m1;
+        t1 = t2;
+        m1 = m2;
+        t2 = t3;
+        m2 = m3;
+        n0 = n1;
+        n1 = n2;
+#pragma unroll
+        for (int j = 0; j < FW; ++j) {
+            qc0[j] = qc1[j];
+            qa0[j] = qa1[j];
+        }
     }
     // deterministic wave reduction of the float64 partials
     for (int off = 32; off > 0; off >>= 1) {
