@@ -61,13 +61,27 @@ __global__ __launch_bounds__(256) void bucket_scan(int32_t nseg, const int32_t* 
     if (tid == 0) boff[(int64_t)k * (nseg + 1) + nseg] = carry;
 }
 
-// bbase[block] = number of records of the blocks before it
-__global__ void bucket_base(int32_t NB, int32_t nseg, const int32_t* __restrict__ boff, int32_t* __restrict__ bbase) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int32_t acc = 0;
-    for (int32_t k = 0; k < NB; ++k) {
-        bbase[k] = acc;
-        acc += boff[(int64_t)k * (nseg + 1) + nseg];
+// bbase[block] = number of records of the blocks before it (one workgroup,
+// exclusive scan of the blocks' totals 256 at a time)
+__global__ __launch_bounds__(256) void bucket_base(int32_t NB, int32_t nseg, const int32_t* __restrict__ boff,
+                                                   int32_t* __restrict__ bbase) {
+    __shared__ int32_t sh[256];
+    const int tid = threadIdx.x;
+    int32_t carry = 0;
+    for (int32_t base = 0; base < NB; base += 256) {
+        const int32_t k = base + tid;
+        const int32_t v = k < NB ? boff[(int64_t)k * (nseg + 1) + nseg] : 0;
+        sh[tid] = v;
+        __syncthreads();
+        for (int d = 1; d < 256; d <<= 1) {
+            const int32_t u = tid >= d ? sh[tid - d] : 0;
+            __syncthreads();
+            sh[tid] += u;
+            __syncthreads();
+        }
+        if (k < NB) bbase[k] = carry + sh[tid] - v;
+        carry += sh[255];
+        __syncthreads();
     }
 }
 
@@ -125,7 +139,7 @@ void bucket_chunk_into(const LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg,
     const size_t lds = (size_t)nb * sizeof(int32_t);
     hipLaunchKernelGGL(bucket_count, dim3(nseg), dim3(64), lds, st, c0, c1, A.M, nb, bs, A.marks, nseg, cnt);
     hipLaunchKernelGGL(bucket_scan, dim3(nb), dim3(256), 0, st, nseg, cnt, off);
-    hipLaunchKernelGGL(bucket_base, dim3(1), dim3(64), 0, st, nb, nseg, off, base);
+    hipLaunchKernelGGL(bucket_base, dim3(1), dim3(256), 0, st, nb, nseg, off, base);
     hipLaunchKernelGGL(bucket_scatter, dim3(nseg), dim3(64), lds, st, c0, c1, A.M, nb, nbits, bs, A.t, A.marks, wchunk,
                        nseg, off, base, key, tt, ww);
 }

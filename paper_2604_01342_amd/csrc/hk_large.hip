@@ -442,6 +442,20 @@ __global__ __launch_bounds__(256) void large_chunk_acc(int32_t nseg, const doubl
 }
 
 // ------------------------------------------------------------------ finalize
+// column sums of the per-run partials (dL/dmu sums, compensator terms),
+// folded into row 0, each in a fixed order
+__global__ void large_colfold(int32_t M, int32_t NSC, double* __restrict__ spart, double* __restrict__ cpart) {
+    const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= M) return;
+    double s = 0.0, c = 0.0;
+    for (int32_t e = 0; e < NSC; ++e) {
+        s += spart[(int64_t)e * M + q];
+        c += cpart[(int64_t)e * M + q];
+    }
+    spart[q] = s;
+    cpart[q] = c;
+}
+
 __global__ void large_final(int32_t M, int32_t ER, int32_t NSC, double T, const float* __restrict__ mu,
                             const double* __restrict__ acc, const double* __restrict__ gpart,
                             const double* __restrict__ spart, const double* __restrict__ cpart,
@@ -706,7 +720,8 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
         }
     }
     const int64_t nfin = A.grad ? (MM > M ? MM : M) : 1;
-    hipLaunchKernelGGL(large_final, dim3((unsigned)((nfin + 255) / 256)), dim3(256), 0, st, M, A.ER, A.NRUN, A.T, A.mu,
+    if (A.grad) hipLaunchKernelGGL(large_colfold, dim3(gM), dim3(256), 0, st, M, A.NRUN, A.spart, A.cpart_);
+    hipLaunchKernelGGL(large_final, dim3((unsigned)((nfin + 255) / 256)), dim3(256), 0, st, M, A.ER, 1, A.T, A.mu,
                        A.acc, A.gpart, A.spart, A.cpart_, A.loglik, A.g_mu, A.g_alpha, A.g_beta, A.grad ? 1 : 0);
     return hipGetLastError() == hipSuccess ? HAWKES_OK : HAWKES_EDEVICE;
 }
