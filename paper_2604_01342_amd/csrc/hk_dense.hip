@@ -243,7 +243,7 @@ struct Run {
 };
 
 template <int CPL>
-__global__ __launch_bounds__(64) void large_dense(int32_t M, int32_t NBC, int32_t NBR, int32_t ER, int32_t rpr,
+__global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu(3))) void large_dense(int32_t M, int32_t NBC, int32_t NBR, int32_t ER, int32_t rpr,
                                                   int32_t nrun, int32_t ckr, int32_t nseg, int32_t nrec,
                                                   int32_t nslot, const float* __restrict__ beta,
                                                   const int4* __restrict__ runinfo,
@@ -255,9 +255,13 @@ __global__ __launch_bounds__(64) void large_dense(int32_t M, int32_t NBC, int32_
     using S = Slot<CPL>;
     constexpr int W = S::W;
     constexpr int SH = CPL == 2 ? 7 : 6;   // bits of the local mark in a column record key
-    __shared__ double GP[HK_DR * W];   // pair terms
-    __shared__ double UL[HK_DR];       // the window's u
-    const int lane = threadIdx.x;
+    __shared__ double GP[HK_DR * W];          // pair terms, shared by the group's waves
+    __shared__ double ULs[HK_DW][HK_DR];      // per wave: the window's u
+    __shared__ double2 ODs[HK_DW][66];        // per wave: own events of a pass (+2 read ahead)
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    double* UL = ULs[wv];
+    double2* OD = ODs[wv];
     const int32_t blk = blockIdx.x;
     const int32_t nbb = NBR * NBC;
     int32_t er, local;
@@ -275,16 +279,20 @@ __global__ __launch_bounds__(64) void large_dense(int32_t M, int32_t NBC, int32_
     }
     if (er >= ER) return;
     const int32_t nrun_c = (nseg + ckr - 1) / ckr;
-    const int32_t rA = er * rpr;
-    if (rA >= nrun_c) return;
-    const int32_t rB = rA + rpr < nrun_c ? rA + rpr : nrun_c;
+    const int32_t gA = er * rpr;
+    if (gA >= nrun_c) return;
+    const int32_t gB = gA + rpr < nrun_c ? gA + rpr : nrun_c;
+    // this wave's share of the range's runs (possibly none)
+    const int32_t rA = gA + (wv * (gB - gA)) / HK_DW;
+    const int32_t rB = gA + ((wv + 1) * (gB - gA)) / HK_DW;
     const int32_t sb = local % NBC;
     const int32_t rb = local / NBC;
     const int32_t r0 = rb * HK_DR, s0 = sb * W;
     double* gp = gpart + (int64_t)er * M * M;
-    // main terms of the block in registers (row i, column s0 + 64 j + lane);
-    // branch-free load, out-of-range rows/columns read a clamped valid
-    // address and are zeroed
+    // main terms of the block in registers (row i, column s0 + 64 j + lane),
+    // wave 0 from the partials so far, the others from zero; branch-free
+    // load, out-of-range rows/columns read a clamped valid address and are
+    // zeroed
     double Gm[HK_DR][CPL];
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
@@ -294,12 +302,12 @@ __global__ __launch_bounds__(64) void large_dense(int32_t M, int32_t NBC, int32_
         for (int i = 0; i < HK_DR; ++i) {
             const int32_t row = r0 + i;
             const int32_t rr = row < M ? row : M - 1;
-            Gm[i][j] = gp[(int64_t)rr * M + cc];
+            Gm[i][j] = wv == 0 ? gp[(int64_t)rr * M + cc] : 0.0;
         }
 #pragma unroll
         for (int i = 0; i < HK_DR; ++i) {
             if (!(r0 + i < M && col < M)) Gm[i][j] = 0.0;
-            GP[i * W + j * 64 + lane] = 0.0;
+            if (i % HK_DW == wv) GP[i * W + j * 64 + lane] = 0.0;
         }
     }
     if (lane < HK_DR) UL[lane] = 0.0;
@@ -358,19 +366,29 @@ __global__ __launch_bounds__(64) void large_dense(int32_t M, int32_t NBC, int32_
         const int rowl = (int)(b.key & (HK_DR - 1));
         if (bet * (tmax - tw) <= HK_WIDE) {
             const float cf = own ? (float)(bet * (double)b.w) * exp_f64arg(-bet * (b.t - tw)) : 0.0f;
-            if (own) atomicAdd(&UL[rowl], (double)cf);
-            auto pair = [&](int k) {
-                const uint32_t key = (uint32_t)rl_i((int)b.key, k);
-                const int rofs = (int)(key & (HK_DR - 1)) * W;
-                const double v = (cv && cidx < (int)(key >> 4)) ? (double)rl_f(cf, k) * bj : 0.0;
+            if (own) {
+                atomicAdd(&UL[rowl], (double)cf);
+                // (row offset, index, c_k) of this own event for the pair
+                // loop, read back by every lane (broadcast)
+                OD[lane] = make_double2(__hiloint2double(rowl * W, (int)(b.key >> 4)), (double)cf);
+            }
+            // pair terms: own event k adds c_k b_j at (row_k, m_j) for the
+            // group's records j before it (zero elsewhere)
+            auto pair = [&](const double2 od) {
+                const int rofs = __double2hiint(od.x), ik = __double2loint(od.x);
+                const double v = cidx < ik ? od.y * bj : 0.0;
                 atomicAdd(&GP[rofs + colj], v);
             };
-            int k = p;
-            for (; k + 1 < kend; k += 2) {
-                pair(k);
-                pair(k + 1);
+            // two at a time, the next two entries read before this pair's
+            // atomics (entries past kend are read but not used)
+            double2 d1 = OD[p], d2 = OD[p + 1];
+            for (int k = p; k < kend; k += 2) {
+                const double2 n1 = OD[k + 2], n2 = OD[k + 3];
+                pair(d1);
+                if (k + 1 < kend) pair(d2);
+                d1 = n1;
+                d2 = n2;
             }
-            if (k < kend) pair(k);
         } else {
             // wide window (anchored factors would leave float32 range):
             // float64 decays for u, exact per-pair decays
@@ -390,7 +408,7 @@ __global__ __launch_bounds__(64) void large_dense(int32_t M, int32_t NBC, int32_
 
     // window position (r, g) and the runs r and r + 1
     int32_t r = rA, g = 0;
-    Run ru = run_info(rA);
+    Run ru = run_info(rA < rB ? rA : gA);
     Run rn = rA + 1 < rB ? run_info(rA + 1) : ru;
 
     // one window with data `cur`; loads the next window into `nxt` first (the
@@ -424,7 +442,7 @@ __global__ __launch_bounds__(64) void large_dense(int32_t M, int32_t NBC, int32_
             hi = se * HK_SEG - 1;   // the run's last event index in the chunk
         }
         const bool cv = lane < nv;
-        const int cidx = (int)(cur.ckey >> SH);
+        const int cidx = cv ? (int)(cur.ckey >> SH) : 0x7fffffff;
         const int colj = (int)(cur.ckey & (uint32_t)(W - 1));
         const double bj = cv ? (double)exp_f64arg(bet * (cur.ct - tw)) : 0.0;
         int nown = 0;
@@ -448,8 +466,10 @@ __global__ __launch_bounds__(64) void large_dense(int32_t M, int32_t NBC, int32_
             if (n == 0 || q - qL < 64) break;
         }
         if (nown) {
-            // rank-1 update G += u K_g^T, then clear u
-            __syncthreads();
+            // rank-1 update G += u K_g^T, then clear u (u is this wave's:
+            // its LDS operations complete in order, so only the compiler
+            // must not move them)
+            __builtin_amdgcn_wave_barrier();
             double u[HK_DR];
 #pragma unroll
             for (int i = 0; i < HK_DR; ++i) u[i] = UL[i];
@@ -457,8 +477,9 @@ __global__ __launch_bounds__(64) void large_dense(int32_t M, int32_t NBC, int32_
             for (int i = 0; i < HK_DR; ++i)
 #pragma unroll
                 for (int j = 0; j < CPL; ++j) Gm[i][j] = __builtin_fma(u[i], cur.K[j], Gm[i][j]);
-            __syncthreads();
+            __builtin_amdgcn_wave_barrier();
             if (lane < HK_DR) UL[lane] = 0.0;
+            __builtin_amdgcn_wave_barrier();
         }
         if (same_run) {
             ++g;
@@ -471,14 +492,26 @@ __global__ __launch_bounds__(64) void large_dense(int32_t M, int32_t NBC, int32_
         return has_next;
     };
 
-    Win<CPL> wa, wb;
-    load_win(wa, ru, 0);
     __syncthreads();
-    for (;;) {
-        if (!body(wa, wb)) break;
-        if (!body(wb, wa)) break;
+    if (rA < rB) {
+        Win<CPL> wa, wb;
+        load_win(wa, ru, 0);
+        for (;;) {
+            if (!body(wa, wb)) break;
+            if (!body(wb, wa)) break;
+        }
+    }
+    // the group's sum: the other waves add their main terms to the pair
+    // tile, wave 0 writes its own plus the tile
+    __syncthreads();
+    if (wv != 0) {
+#pragma unroll
+        for (int i = 0; i < HK_DR; ++i)
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) atomicAdd(&GP[i * W + j * 64 + lane], Gm[i][j]);
     }
     __syncthreads();
+    if (wv != 0) return;
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
         const int32_t col = s0 + j * 64 + lane;
@@ -514,11 +547,11 @@ void large_dense_launch(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, hipS
                                     : (unsigned)(((nbb + 8 / A.ER - 1) / (8 / A.ER)) * 8);
     const int32_t nslot = (int32_t)A.nslot;
     if (A.CPL == 2)
-        hipLaunchKernelGGL(large_dense<2>, dim3(nblk), dim3(64), 0, st, A.M, A.NBC, A.NBR, A.ER, rpr, A.NRUN,
+        hipLaunchKernelGGL(large_dense<2>, dim3(nblk), dim3(64 * HK_DW), 0, st, A.M, A.NBC, A.NBR, A.ER, rpr, A.NRUN,
                            A.CKR, nseg, nev, nslot, A.beta, A.runinfo, A.bo_off, A.bo_base, A.bo_key, A.bo_t,
                            A.bo_w, A.kck, A.gpart);
     else
-        hipLaunchKernelGGL(large_dense<1>, dim3(nblk), dim3(64), 0, st, A.M, A.NBC, A.NBR, A.ER, rpr, A.NRUN,
+        hipLaunchKernelGGL(large_dense<1>, dim3(nblk), dim3(64 * HK_DW), 0, st, A.M, A.NBC, A.NBR, A.ER, rpr, A.NRUN,
                            A.CKR, nseg, nev, nslot, A.beta, A.runinfo, A.bo_off, A.bo_base, A.bo_key, A.bo_t,
                            A.bo_w, A.kck, A.gpart);
 }

@@ -12,6 +12,9 @@
 #define HK_DR 16           // rows per block of the shared-decay dense kernel
 #endif
 #define HK_SLAB 64         // columns per dense-gradient block (one per lane)
+#ifndef HK_DW
+#define HK_DW 2            // waves per workgroup of the shared-decay dense kernel
+#endif
 #ifndef HK_CKR
 #define HK_CKR 4           // segments per checkpoint run of the shared-decay dense gradient
 #endif

@@ -504,8 +504,9 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
     }
     A.NBC = A.per_target ? A.NB : (A.M + 64 * A.CPL - 1) / (64 * A.CPL);
     // event ranges per chunk for the dense kernel: a power of two so that the
-    // ranges map onto the 8 XCDs evenly; about 4096 blocks in total (shared
-    // decay: 17 KiB of LDS each, four per SIMD) or 2048 (per target, 34 KiB)
+    // ranges map onto the 8 XCDs evenly; about 4096 workgroups in total
+    // (shared decay: two waves each, 18 KiB of LDS per group, so that several
+    // rounds balance the waves' uneven work) or 2048 (per target, 34 KiB)
     // unless HAWKES_DENSE_ER (a power of two) overrides it
     const int64_t nbb = (int64_t)A.NBR * A.NBC;
     const int64_t target = A.per_target ? 2048 : 4096;
