@@ -47,6 +47,8 @@ struct LargeArgs {
     double* agg;          // [nseg][2M] segment maps (K_run, J_run)
     double* seg_span;     // [nseg] time from the event before the segment to its last event
     double* seg_dec;      // [nseg] e^{-beta (span of the segment from the preceding event)}
+    double* seg_off;      // [nseg] time from the event before the segment's scan group to the event before it
+    double* seg_offdec;   // [nseg] e^{-beta seg_off} (shared decay)
     double* carry_seg;    // [nseg][2M] state just after the event preceding segment s
     int32_t ngr;          // scan groups per chunk
     double *gagg, *gcarry, *gspan, *gdec;   // group maps, carries, spans, decays

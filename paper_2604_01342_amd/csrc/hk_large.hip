@@ -190,6 +190,7 @@ __global__ void large_scan_local(int32_t nseg, int32_t M, const double* __restri
     const int32_t s0 = g * HK_SG, s1 = s0 + HK_SG < nseg ? s0 + HK_SG : nseg;
     double K = 0.0, J = 0.0;
     const double bq = beta_pt ? (double)beta_pt[q] : 0.0;
+#pragma unroll 8
     for (int32_t s = s0; s < s1; ++s) {
         const double* row = agg + (int64_t)s * 2 * M;
         double* o = carry_seg + (int64_t)s * 2 * M;
@@ -205,17 +206,25 @@ __global__ void large_scan_local(int32_t nseg, int32_t M, const double* __restri
     gagg[(int64_t)g * 2 * M + M + q] = J;
 }
 
-// gdec[g], gspan[g]: decay and span of group g (one thread per group)
+// gdec[g], gspan[g]: decay and span of group g; seg_off[s]: time from the
+// event before s's group to the event before s, seg_offdec[s] its decay
+// (shared decay); one thread per group
 __global__ void large_scan_gdec(int32_t nseg, const double* __restrict__ seg_span, const float* __restrict__ beta,
-                                double* __restrict__ gspan, double* __restrict__ gdec) {
+                                double* __restrict__ gspan, double* __restrict__ gdec, double* __restrict__ seg_off,
+                                double* __restrict__ seg_offdec) {
     const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t ngr = (nseg + HK_SG - 1) / HK_SG;
     if (g >= ngr) return;
     const int32_t s0 = g * HK_SG, s1 = s0 + HK_SG < nseg ? s0 + HK_SG : nseg;
+    const double b0 = (double)beta[0];
     double D = 0.0;
-    for (int32_t s = s0; s < s1; ++s) D += seg_span[s];
+    for (int32_t s = s0; s < s1; ++s) {
+        seg_off[s] = D;
+        seg_offdec[s] = exp(-b0 * D);
+        D += seg_span[s];
+    }
     gspan[g] = D;
-    gdec[g] = exp(-(double)beta[0] * D);
+    gdec[g] = exp(-b0 * D);
 }
 
 __global__ void large_scan_groups(int32_t nseg, int32_t M, const double* __restrict__ gagg,
@@ -227,6 +236,7 @@ __global__ void large_scan_groups(int32_t nseg, int32_t M, const double* __restr
     const int32_t ngr = (nseg + HK_SG - 1) / HK_SG;
     double K = carry[q], J = carry[M + q];
     const double bq = beta_pt ? (double)beta_pt[q] : 0.0;
+#pragma unroll 8
     for (int32_t g = 0; g < ngr; ++g) {
         gcarry[(int64_t)g * 2 * M + q] = K;
         gcarry[(int64_t)g * 2 * M + M + q] = J;
@@ -240,16 +250,15 @@ __global__ void large_scan_groups(int32_t nseg, int32_t M, const double* __restr
     carry[M + q] = J;
 }
 
-__global__ void large_scan_apply(int32_t nseg, int32_t M, const double* __restrict__ seg_span,
-                                 const float* __restrict__ beta, const double* __restrict__ gcarry,
+__global__ void large_scan_apply(int32_t nseg, int32_t M, const double* __restrict__ seg_off,
+                                 const double* __restrict__ seg_offdec, const double* __restrict__ gcarry,
                                  double* __restrict__ carry_seg, const float* __restrict__ beta_pt) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (gid >= (int64_t)nseg * M) return;
     const int32_t s = (int32_t)(gid / M), q = (int32_t)(gid % M);
     const int32_t g = s / HK_SG;
-    double D = 0.0;
-    for (int32_t r = g * HK_SG; r < s; ++r) D += seg_span[r];
-    const double ex = exp(-(double)(beta_pt ? beta_pt[q] : beta[0]) * D);
+    const double D = seg_off[s];
+    const double ex = beta_pt ? exp(-(double)beta_pt[q] * D) : seg_offdec[s];
     const double Kc = gcarry[(int64_t)g * 2 * M + q], Jc = gcarry[(int64_t)g * 2 * M + M + q];
     double* o = carry_seg + (int64_t)s * 2 * M;
     const double Kl = o[q], Jl = o[M + q];
@@ -518,9 +527,13 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
         if (v >= 1 && v <= 4096 && (v & (v - 1)) == 0) er = v;
     }
     while (er > A.nseg && er > 1) er >>= 1;
+    // shared decay: every wave of a dense workgroup gets at least one run
+    while (!A.per_target && er > 1 && A.nseg / er < HK_DW) er >>= 1;
     A.ER = er;
-    // checkpoint runs: whole runs per event range (nseg and ER are powers of two)
-    A.CKR = A.nseg / er < HK_CKR ? A.nseg / er : HK_CKR;
+    // checkpoint runs: whole runs per event range, HK_DW or more per range
+    // (nseg and ER are powers of two)
+    A.CKR = A.nseg / (er * HK_DW);
+    if (A.CKR > HK_CKR) A.CKR = HK_CKR;
     if (A.CKR < 1) A.CKR = 1;
     A.NRUN = A.nseg / A.CKR;
     A.grad = grad;
@@ -533,6 +546,8 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
     A.agg = c.take<double>((size_t)A.nseg * 2 * M);
     A.seg_span = c.take<double>(A.nseg);
     A.seg_dec = c.take<double>(A.nseg);
+    A.seg_off = c.take<double>(A.nseg);
+    A.seg_offdec = c.take<double>(A.nseg);
     A.ngr = (A.nseg + HK_SG - 1) / HK_SG;
     A.gagg = c.take<double>((size_t)A.ngr * 2 * M);
     A.gcarry = c.take<double>((size_t)A.ngr * 2 * M);
@@ -643,11 +658,11 @@ void large_scan(LargeArgs& A, int32_t nseg, const float* beta_pt, hipStream_t st
     hipLaunchKernelGGL(large_scan_local, dim3((unsigned)((nloc + 255) / 256)), dim3(256), 0, st, nseg, M, A.agg,
                        A.seg_dec, A.seg_span, A.carry_seg, A.gagg, beta_pt);
     hipLaunchKernelGGL(large_scan_gdec, dim3((unsigned)((ngr + 255) / 256)), dim3(256), 0, st, nseg, A.seg_span,
-                       A.beta, A.gspan, A.gdec);
+                       A.beta, A.gspan, A.gdec, A.seg_off, A.seg_offdec);
     hipLaunchKernelGGL(large_scan_groups, dim3(gM), dim3(256), 0, st, nseg, M, A.gagg, A.gspan, A.gdec, A.gcarry,
                        A.carry, beta_pt);
     hipLaunchKernelGGL(large_scan_apply, dim3((unsigned)((napp + 255) / 256)), dim3(256), 0, st, nseg, M,
-                       A.seg_span, A.beta, A.gcarry, A.carry_seg, beta_pt);
+                       A.seg_off, A.seg_offdec, A.gcarry, A.carry_seg, beta_pt);
 }
 
 hawkes_status run_large(LargeArgs& A, hipStream_t st) {
