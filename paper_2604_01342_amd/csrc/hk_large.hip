@@ -283,19 +283,27 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
     uint64_t* rmask = (uint64_t*)(lds + M);               // [M] lanes of this batch with mark q
     double* rK = lds + 2 * M;                             // [M] K_q at rtau (event included)
     double* rJ = lds + 3 * M;                             // [M] J_q at rtau
-    __shared__ double tb[64];
+    __shared__ double tb[64], eb[64];
     const int32_t s = blockIdx.x;
     const int lane = threadIdx.x;
     const int64_t a = c0 + (int64_t)s * HK_SEG;
     const int64_t b = a + HK_SEG < c1 ? a + HK_SEG : c1;
     const double bet = (double)beta[0];
-    const float betf = beta[0];
     const double tref = a > 0 ? t[a - 1] : t[a];
+    // anchored records when the segment's span allows: with u = t - tref,
+    // rK[q] = S0_q = sum_j e^{beta u_j}, rJ[q] = S1_q = sum_j u_j e^{beta u_j}
+    // over the node's events so far (the carry enters as S0 = K(tref),
+    // S1 = -J(tref)); then K_q(t) = e^{-beta u} S0_q and
+    // J_q(t) = e^{-beta u} (u S0_q - S1_q): one exponential per event instead
+    // of one per nonzero of alpha's row, and records grow by plain additions.
+    // Otherwise (beta u could overflow float64) each record keeps its own
+    // time rtau[q] and is decayed on use.
+    const bool anch = bet * (t[b - 1] - tref) <= 600.0;
     const double* cs = carry_seg + (int64_t)s * 2 * M;
     for (int32_t q = lane; q < M; q += 64) {
         rtau[q] = tref;
         rK[q] = cs[q];
-        rJ[q] = cs[M + q];
+        rJ[q] = anch ? -cs[M + q] : cs[M + q];
         rmask[q] = 0ull;
     }
     __syncthreads();
@@ -342,13 +350,41 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
         int32_t qc1[FW];
         float qa1[FW];
         ld_row(n1, qc1, qa1);
+        const double ui = ti - tref;
+        const double eti = anch && valid ? exp_f64(bet * ui) : 0.0;   // e^{beta u_i}
         tb[lane] = ti;
+        eb[lane] = eti;
         if (valid) atomicOr((unsigned long long*)&rmask[mi], 1ull << lane);
         __syncthreads();
         double R = 0.0, Dd = 0.0, lam = 1.0, w = 0.0, em1 = 0.0;
         if (valid) {
             const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
             const int32_t k0 = ni.x, k1 = ni.y;
+            if (anch) {
+                // anchored sums of source q (records plus the batch's earlier
+                // events of q), weight av
+                auto terma = [&](int32_t q, float av) {
+                    double s0 = rK[q];
+                    double s1 = GRAD ? rJ[q] : 0.0;
+                    uint64_t bits = rmask[q] & below;
+                    while (bits) {
+                        const int jj = __builtin_ctzll(bits);
+                        bits &= bits - 1;
+                        const double ej = eb[jj];
+                        s0 += ej;
+                        if (GRAD) s1 = __builtin_fma(tb[jj] - tref, ej, s1);
+                    }
+                    R = __builtin_fma((double)av, s0, R);
+                    if (GRAD) Dd = __builtin_fma((double)av, __builtin_fma(ui, s0, -s1), Dd);
+                };
+#pragma unroll
+                for (int j = 0; j < FW; ++j)
+                    if (k0 + j < k1) terma(qc0[j], qa0[j]);
+                for (int32_t k = k0 + FW; k < k1; ++k) terma(csr_col[k], csr_val[k]);
+                const double ei = exp_f64(-bet * ui);   // e^{-beta u_i}
+                R *= ei;
+                Dd *= ei;
+            } else {
             // contribution of source q with weight av: the record decayed to
             // ti plus the batch's earlier events of q
             auto term = [&](int32_t q, float av) {
@@ -373,6 +409,7 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
             for (int j = 0; j < FW; ++j)
                 if (k0 + j < k1) term(qc0[j], qa0[j]);
             for (int32_t k = k0 + FW; k < k1; ++k) term(csr_col[k], csr_val[k]);
+            }
             lam = __builtin_fma(bet, R, (double)__int_as_float(ni.z));
         if (INTENS) lambda_out[i] = (float)lam;
             logsum += log(lam);
@@ -388,8 +425,25 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
         }
         if (GRAD && valid) wchunk[i - c0] = (float)w;
         __syncthreads();
-        // lazy record update, one leader lane per node, events in index order
-        if (valid) {
+        if (anch) {
+            // anchored records: the batch's events of a node add their terms,
+            // in index order, through one leader lane per node
+            if (valid) {
+                uint64_t grp = rmask[mi];
+                if (__builtin_ctzll(grp) == lane) {
+                    double s0 = rK[mi], s1 = rJ[mi];
+                    while (grp) {
+                        const int j = __builtin_ctzll(grp);
+                        grp &= grp - 1;
+                        s0 += eb[j];
+                        if (GRAD) s1 = __builtin_fma(tb[j] - tref, eb[j], s1);
+                    }
+                    rK[mi] = s0;
+                    if (GRAD) rJ[mi] = s1;
+                }
+            }
+        } else if (valid) {
+            // lazy record update, one leader lane per node, events in index order
             uint64_t grp = rmask[mi];
             if (__builtin_ctzll(grp) == lane) {
                 double tq = rtau[mi];
