@@ -511,6 +511,7 @@ __global__ void large_colfold(int32_t M, int32_t NSC, double* __restrict__ spart
     const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= M) return;
     double s = 0.0, c = 0.0;
+#pragma unroll 16
     for (int32_t e = 0; e < NSC; ++e) {
         s += spart[(int64_t)e * M + q];
         c += cpart[(int64_t)e * M + q];
