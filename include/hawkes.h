@@ -40,7 +40,9 @@
  *    (each exponent is formed and range-reduced in float64).
  *    Every sum over events (log-likelihood, gradients) is accumulated in
  *    float64 in a fixed order, so repeated calls return bitwise-identical
- *    results.
+ *    results, with one exception: in the large-M engine, dL/dalpha sums its
+ *    terms through LDS atomics of several waves, whose order (hence
+ *    last-bit rounding) can vary between calls.
  *  - Size limits (LDS per workgroup, read from the device; 160 KiB on
  *    MI355X): shared decay m <= 5120, decay per target m <= 4352; larger m
  *    returns HAWKES_EUNSUPPORTED.  The per-target gradient also keeps one

@@ -403,7 +403,7 @@ __global__ void pt_rscan_apply(int64_t c0, int64_t c1, int64_t n, double T, int3
 // G is kept in LDS column-major (stride 65 against bank conflicts).  Blocks
 // with sb == 0 also sum w_i per target, blocks with rb == 0 count the events
 // per source.
-__global__ __launch_bounds__(64) void pt_dense(int64_t c0, int64_t c1, int64_t n, double T, int32_t M, int32_t NB,
+__global__ __launch_bounds__(64 * HK_DWP) void pt_dense(int64_t c0, int64_t c1, int64_t n, double T, int32_t M, int32_t NB,
                                                int32_t ER, int32_t segs_per_range, int32_t nseg,
                                                const double* __restrict__ t, const float* __restrict__ beta,
                                                const double* __restrict__ rcarry_seg,
@@ -413,10 +413,14 @@ __global__ __launch_bounds__(64) void pt_dense(int64_t c0, int64_t c1, int64_t n
                                                const uint32_t* __restrict__ bk_key, const double* __restrict__ bk_t,
                                                const float* __restrict__ bk_w, double* __restrict__ gpart,
                                                double* __restrict__ spart, double* __restrict__ npart) {
-    __shared__ double G[HK_SLAB * 65];
-    __shared__ double AL[64], SL[64], NL[64];
+    __shared__ double G[HK_SLAB * 65];   // shared by the group's waves
+    __shared__ double ALs[HK_DWP][64], SLs[HK_DWP][64], NLs[HK_DWP][64];
     __shared__ float BL[64];
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    double* AL = ALs[wv];
+    double* SL = SLs[wv];
+    double* NL = NLs[wv];
     AL[lane] = 0.0;
     SL[lane] = 0.0;
     NL[lane] = 0.0;
@@ -437,9 +441,12 @@ __global__ __launch_bounds__(64) void pt_dense(int64_t c0, int64_t c1, int64_t n
     const int32_t sb = local % NB;
     const int32_t rb = local / NB;
     const int32_t r0 = rb * HK_RB, s0 = sb * HK_SLAB;
-    const int32_t sA = er * segs_per_range;
-    if (sA >= nseg) return;
-    const int32_t sB = sA + segs_per_range < nseg ? sA + segs_per_range : nseg;
+    const int32_t gA = er * segs_per_range;
+    if (gA >= nseg) return;
+    const int32_t gB = gA + segs_per_range < nseg ? gA + segs_per_range : nseg;
+    // this wave's share of the range's segments (possibly none)
+    const int32_t sA = gA + (wv * (gB - gA)) / HK_DWP;
+    const int32_t sB = gA + ((wv + 1) * (gB - gA)) / HK_DWP;
     const int32_t p = r0 + lane;
     const bool pv = p < M;
     BL[lane] = pv ? beta[p] : 0.0f;
@@ -448,7 +455,7 @@ __global__ __launch_bounds__(64) void pt_dense(int64_t c0, int64_t c1, int64_t n
         // lanes over the block's columns (coalesced rows of gpart)
         const int32_t col = s0 + lane;
         const int32_t cc = col < M ? col : M - 1;
-        for (int rg = 0; rg < HK_RB; rg += 16) {
+        for (int rg = wv * 16; rg < HK_RB; rg += 16 * HK_DWP) {
             double v[16];
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
@@ -464,6 +471,13 @@ __global__ __launch_bounds__(64) void pt_dense(int64_t c0, int64_t c1, int64_t n
         }
     }
     const double bp = pv ? (double)beta[p] : 0.0;
+    const float bpl = (float)(bp * 1.4426950408889634);   // beta_p log2(e)
+    // largest decay of the block's targets
+    double bmax = bp;
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(bmax, off, 64);
+        bmax = o > bmax ? o : bmax;
+    }
     // adjoint state from the events after the range (and the seed) at tau
     const bool at_end = sB >= nseg;
     double tau = seg_first_time(t, c0, c1, n, nseg, at_end ? nseg : sB, T);
@@ -479,6 +493,7 @@ __global__ __launch_bounds__(64) void pt_dense(int64_t c0, int64_t c1, int64_t n
            (int64_t)bk_base[sb] + bk_off[(int64_t)sb * (nseg + 1) + sB]);
     __syncthreads();
     for (;;) {
+        if (sA >= sB) break;
         const int64_t ao = O.avail(), as = S.avail();
         if (ao <= 0 && as <= 0) break;
         const int io = (int)(O.ck >> 6), is = (int)(S.ck >> 6);
@@ -499,20 +514,40 @@ __global__ __launch_bounds__(64) void pt_dense(int64_t c0, int64_t c1, int64_t n
         Ah *= (double)exp_f64arg(-bp * (tau - tw));
         const int pi = (int)(O.ck & 63u);
         const double bo = (double)BL[pi];
+        const float bol = (float)(bo * 1.4426950408889634);
         const double wi = (double)O.cw;
-        for (int k = 0; k < ns; ++k) {
-            const int qoff = (int)(rl_i((int)S.ck, k) & 63) * 65;
-            const double tk = rl_d(S.ct, k);
-            const int ik = rl_i(is, k);
-            atomicAdd(&G[qoff + lane], bp * Ah * (double)exp_f64arg(-bp * (tw - tk)));
-            if (own && io > ik) atomicAdd(&G[qoff + pi], bo * wi * (double)exp_f64arg(-bo * (O.ct - tk)));
+        if (bmax * (tw - tl) <= 0.5) {
+            // short window: every decay exponent is at most 0.5, so its
+            // float32 rounding costs at most 3e-8 relative and the hardware
+            // exp2 applies directly (the time differences are float64)
+            const double bA = bp * Ah, bw = bo * wi;
+            for (int k = 0; k < ns; ++k) {
+                const int qoff = (int)(rl_i((int)S.ck, k) & 63) * 65;
+                const double tk = rl_d(S.ct, k);
+                const int ik = rl_i(is, k);
+                const float dk = (float)(tw - tk);
+                atomicAdd(&G[qoff + lane], bA * (double)__builtin_amdgcn_exp2f(-bpl * dk));
+                if (own && io > ik)
+                    atomicAdd(&G[qoff + pi], bw * (double)__builtin_amdgcn_exp2f(-bol * (float)(O.ct - tk)));
+            }
+        } else {
+            for (int k = 0; k < ns; ++k) {
+                const int qoff = (int)(rl_i((int)S.ck, k) & 63) * 65;
+                const double tk = rl_d(S.ct, k);
+                const int ik = rl_i(is, k);
+                atomicAdd(&G[qoff + lane], bp * Ah * (double)exp_f64arg(-bp * (tw - tk)));
+                if (own && io > ik) atomicAdd(&G[qoff + pi], bo * wi * (double)exp_f64arg(-bo * (O.ct - tk)));
+            }
         }
         if (sb == 0 && own) atomicAdd(&SL[pi], wi);
         if (rb == 0 && sl) atomicAdd(&NL[S.ck & 63u], 1.0);
         if (own) atomicAdd(&AL[pi], wi * (double)exp_f64arg(-bo * (O.ct - tl)));
-        __syncthreads();
+        // AL is this wave's: its LDS operations complete in order
+        __builtin_amdgcn_wave_barrier();
         Ah = __builtin_fma(Ah, (double)exp_f64arg(-bp * (tw - tl)), AL[lane]);
+        __builtin_amdgcn_wave_barrier();
         AL[lane] = 0.0;
+        __builtin_amdgcn_wave_barrier();
         tau = tl;
         O.consume(no);
         S.consume(ns);
@@ -522,14 +557,21 @@ __global__ __launch_bounds__(64) void pt_dense(int64_t c0, int64_t c1, int64_t n
         const int32_t col = s0 + lane;
         if (col < M) {
 #pragma unroll 16
-            for (int r = 0; r < HK_RB; ++r) {
+            for (int r = wv; r < HK_RB; r += HK_DWP) {
                 const int32_t row = r0 + r;
                 if (row < M) gp[(int64_t)row * M + col] = G[lane * 65 + r];
             }
         }
     }
-    if (sb == 0 && pv) spart[(int64_t)er * M + p] += SL[lane];
-    if (rb == 0 && s0 + lane < M) npart[(int64_t)er * M + s0 + lane] += NL[lane];
+    if (wv != 0) return;
+    // the waves' sums, in wave order
+    double sl = 0.0, nl = 0.0;
+    for (int v = 0; v < HK_DWP; ++v) {
+        sl += SLs[v][lane];
+        nl += NLs[v][lane];
+    }
+    if (sb == 0 && pv) spart[(int64_t)er * M + p] += sl;
+    if (rb == 0 && s0 + lane < M) npart[(int64_t)er * M + s0 + lane] += nl;
 }
 
 __global__ void pt_final(int32_t M, int32_t ER, double T, const float* __restrict__ mu,
@@ -650,7 +692,7 @@ hawkes_status run_large_pt(LargeArgs& A, hipStream_t st) {
             const unsigned nblk = A.ER >= 8 ? (unsigned)(nbb * ((A.ER + 7) / 8) * 8)
                                             : (unsigned)(((nbb + 8 / A.ER - 1) / (8 / A.ER)) * 8);
             TimedScope ts(0, st);
-            hipLaunchKernelGGL(pt_dense, dim3(nblk), dim3(64), 0, st, c0, c1, A.n, A.T, M, A.NB, A.ER, spr, nseg, A.t,
+            hipLaunchKernelGGL(pt_dense, dim3(nblk), dim3(64 * HK_DWP), 0, st, c0, c1, A.n, A.T, M, A.NB, A.ER, spr, nseg, A.t,
                                A.beta, A.rcarry_seg, A.rgcarry, A.bk_off, A.bk_base, A.bk_key, A.bk_t, A.bk_w, A.gpart,
                                A.spart, A.cpart_);
         }

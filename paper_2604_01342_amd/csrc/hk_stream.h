@@ -51,7 +51,7 @@ struct RecStream {
         lo = lo_;
         hi = hi_;
         pos = REV ? hi : lo;
-        const int lane = threadIdx.x;
+        const int lane = threadIdx.x & 63;
         const int64_t a = at(lane), b = at(64 + lane);
         ck = K[a];
         ct = Tm[a];
@@ -64,7 +64,7 @@ struct RecStream {
     __device__ __forceinline__ int64_t avail() const { return REV ? pos - lo : hi - pos; }
     __device__ __forceinline__ void consume(int n) {
         if (n <= 0) return;
-        const int lane = threadIdx.x;
+        const int lane = threadIdx.x & 63;
         if (lane >= split) {
             nk = pk;
             nt = pt;

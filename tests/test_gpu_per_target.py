@@ -53,9 +53,11 @@ def test_per_target_chunk_invariance_and_determinism(H):
     assert scalar_rel(a[0], b[0]) < 1e-9
     for x, y in zip(a[1:], b[1:]):
         assert rel_err(x, y) < 1e-7
+    # repeatable bitwise except dL/dalpha (several waves add into one LDS
+    # tile in a varying order): to rounding there
     assert a[0] == c[0]
-    for x, y in zip(a[1:], c[1:]):
-        assert np.array_equal(x, y)
+    assert np.array_equal(a[1], c[1]) and np.array_equal(a[3], c[3])
+    assert rel_err(a[2], c[2]) < 1e-13
 
 
 def test_per_target_loglik_only_and_intensity(H):
