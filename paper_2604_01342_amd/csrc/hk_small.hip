@@ -454,6 +454,194 @@ __global__ __launch_bounds__(256) void small_compute(int32_t S, int64_t n_total,
     }
 }
 
+// Column-split phase C for the gradient (MP >= 4): LPI lanes per item; lane
+// c of the item's group holds the state K_q, J_q of its CL = MP / LPI nodes
+// q = c CL .. c CL + CL - 1 and those columns of the item's dL/dalpha block,
+// so the block needs MP CL instead of MP^2 float64 per lane and more waves
+// share a SIMD.  Events go in blocks of 8: the block's decays
+// e^{-beta (t_j - t_{j-1})} and e^{-beta (T - t_j)} are computed once, by
+// lane j mod LPI, before the in-order pass over the block and fetched from it
+// by the other lanes; R = alpha_{p,:} . K and D = alpha_{p,:} . J are summed
+// over the group (a butterfly, identical in every lane); the block's
+// logarithms are taken afterwards, again one event per lane.  The lanes'
+// scalar partials are summed in lane order.
+template <int MP, int LPI>
+__global__ __launch_bounds__(256) void small_compute_c(int32_t S, int64_t n_total, const int64_t* __restrict__ ev_off,
+                                                       const int64_t* __restrict__ item_off, int32_t L,
+                                                       const double* __restrict__ t,
+                                                       const int32_t* __restrict__ marks,
+                                                       const int32_t* __restrict__ m_s,
+                                                       const double* __restrict__ T_s, const float* __restrict__ mu,
+                                                       const float* __restrict__ alpha,
+                                                       const float* __restrict__ beta,
+                                                       const int64_t* __restrict__ mu_off,
+                                                       const int64_t* __restrict__ a_off,
+                                                       const double* __restrict__ item_pref,
+                                                       const double* __restrict__ tile_carry,
+                                                       double* __restrict__ part, int32_t PW, int64_t n_items_cap) {
+    constexpr int IPW = 64 / LPI;  // items per wave
+    constexpr int CL = MP / LPI;   // nodes (columns) per lane
+    constexpr int NB = 8;          // events per block
+    constexpr int NO = NB / LPI;   // block events whose decays and logarithm a lane takes
+    const int lane = threadIdx.x & 63;
+    const int c = lane % LPI;
+    const int g0 = lane - c;       // the group's first lane
+    const int qa = c * CL;         // this lane's first node
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t it = wave * IPW + lane / LPI;
+    if (it >= n_items_cap) return;   // the whole group
+    const ItemInfo inf = item_info(it, S, item_off, ev_off, L, n_total, n_items_cap);
+    if (!inf.valid) return;          // the whole group
+    const int32_t M = m_s[inf.s] < 1 ? 1 : (m_s[inf.s] > MP ? MP : m_s[inf.s]);
+    const double bet = (double)beta[inf.s];
+    const double T = T_s[inf.s];
+    const float* al = alpha + a_off[inf.s];
+    const float* mus = mu + mu_off[inf.s];
+    double colsum[MP];
+#pragma unroll
+    for (int q = 0; q < MP; ++q) {
+        double cs = 0.0;
+        if (q < M)
+            for (int p = 0; p < M; ++p) cs += (double)al[p * M + q];
+        colsum[q] = cs;
+    }
+    double K[CL], J[CL];
+#pragma unroll
+    for (int u = 0; u < CL; ++u) { K[u] = 0.0; J[u] = 0.0; }
+    double tp;
+    if (inf.k == 0) {
+        tp = t[inf.a];
+    } else {
+        tp = t[inf.a - 1];
+        const double* pr = item_pref + it * (2 + 2 * MP);
+        const double pD = pr[0];
+        const bool preset = pr[1] != 0.0;
+#pragma unroll
+        for (int u = 0; u < CL; ++u) { K[u] = pr[2 + qa + u]; J[u] = pr[2 + MP + qa + u]; }
+        if (!preset) {
+            // the tile carry exists whenever this item's sequence started in
+            // an earlier tile, which is exactly the case preset == 0, k > 0
+            const int64_t tile = it / 64;
+            const double sd = exp(-bet * pD);
+#pragma unroll
+            for (int u = 0; u < CL; ++u) {
+                const double cK = tile_carry[tile * 2 * MP + qa + u];
+                const double cJ = tile_carry[tile * 2 * MP + MP + qa + u];
+                const double nK = __builtin_fma(sd, cK, K[u]);
+                J[u] = __builtin_fma(sd, __builtin_fma(pD, cK, cJ), J[u]);
+                K[u] = nK;
+            }
+        }
+    }
+    double lsum = 0.0, comp = 0.0, Esum = 0.0, gbs = 0.0;
+    double Sq[CL], Cq[CL], Gc[MP][CL];
+#pragma unroll
+    for (int u = 0; u < CL; ++u) {
+        Sq[u] = 0.0;
+        Cq[u] = 0.0;
+#pragma unroll
+        for (int r = 0; r < MP; ++r) Gc[r][u] = 0.0;
+    }
+    int mp = -1;
+    const int64_t last = inf.b - 1;
+    auto ld = [&](int64_t e) { return e < last ? e : last; };
+    for (int64_t e0 = inf.a; e0 < inf.b; e0 += NB) {
+        double tv[NB];
+        int mv[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            tv[j] = t[ld(e0 + j)];
+            mv[j] = marks[ld(e0 + j)];
+        }
+        // this lane's events of the block: j = c + LPI o
+        double so[NO], xo[NO];
+#pragma unroll
+        for (int o = 0; o < NO; ++o) {
+            const int j = c + LPI * o;
+            const double tj = t[ld(e0 + j)];
+            const double tjm = j == 0 ? tp : t[ld(e0 + j - 1)];
+            so[o] = exp_f64(-bet * (tj - tjm));
+            xo[o] = exp_f64(-bet * (T - tj));
+        }
+        double lo[NO], ro[NO];
+#pragma unroll
+        for (int o = 0; o < NO; ++o) { lo[o] = 1.0; ro[o] = 0.0; }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            if (e0 + j >= inf.b) break;
+            const int src = g0 + j % LPI;
+            const double sj = __shfl(so[j / LPI], src, 64);
+            const double ex = __shfl(xo[j / LPI], src, 64);
+            const double te = tv[j];
+            const double d = te - tp;
+            const int p = clamp_mark(mv[j], M);
+            double R = 0.0, Dd = 0.0;
+#pragma unroll
+            for (int u = 0; u < CL; ++u) {
+                const double k1 = sj * (K[u] + (qa + u == mp ? 1.0 : 0.0));
+                J[u] = __builtin_fma(sj, J[u], d * k1);
+                K[u] = k1;
+                const double a = qa + u < M ? (double)al[p * M + qa + u] : 0.0;
+                R = __builtin_fma(a, K[u], R);
+                Dd = __builtin_fma(a, J[u], Dd);
+            }
+#pragma unroll
+            for (int off = 1; off < LPI; off <<= 1) {
+                R += __shfl_xor(R, off, 64);
+                Dd += __shfl_xor(Dd, off, 64);
+            }
+            const double lam = (double)mus[p] + bet * R;
+            const double w = 1.0 / lam;
+            double csp = 0.0;
+#pragma unroll
+            for (int q = 0; q < MP; ++q) csp = (q == p) ? colsum[q] : csp;
+            if (c == j % LPI) {
+                lo[j / LPI] = lam;
+                ro[j / LPI] = w * (R - bet * Dd);
+                comp += csp * (1.0 - ex);
+                Esum += csp * (T - te) * ex;
+            }
+#pragma unroll
+            for (int u = 0; u < CL; ++u) {
+                Sq[u] += qa + u == p ? w : 0.0;
+                Cq[u] += qa + u == p ? 1.0 - ex : 0.0;
+#pragma unroll
+                for (int r = 0; r < MP; ++r) Gc[r][u] = __builtin_fma(r == p ? w : 0.0, K[u], Gc[r][u]);
+            }
+            tp = te;
+            mp = p;
+        }
+#pragma unroll
+        for (int o = 0; o < NO; ++o) {
+            lsum += log(lo[o]);
+            gbs += ro[o];
+        }
+    }
+    // the group's scalar partials, summed in lane order
+    double tl = 0.0, tc = 0.0, te2 = 0.0, tg = 0.0;
+#pragma unroll
+    for (int i = 0; i < LPI; ++i) {
+        tl += __shfl(lsum, g0 + i, 64);
+        tc += __shfl(comp, g0 + i, 64);
+        te2 += __shfl(Esum, g0 + i, 64);
+        tg += __shfl(gbs, g0 + i, 64);
+    }
+    double* o = part + it * (int64_t)PW;
+    if (c == 0) {
+        o[0] = tl;
+        o[1] = tc;
+        o[2] = te2;
+        o[3] = tg;
+    }
+#pragma unroll
+    for (int u = 0; u < CL; ++u) {
+        o[4 + qa + u] = Sq[u];
+        o[4 + MP + qa + u] = Cq[u];
+#pragma unroll
+        for (int r = 0; r < MP; ++r) o[4 + 2 * MP + r * MP + qa + u] = Gc[r][u];
+    }
+}
+
 // ---------------------------------------------------------------- reduction
 // level 1: per (sequence, chunk of HK_RCH items): thread per partial entry
 __global__ __launch_bounds__(128) void small_reduce1(int32_t S, int64_t n_items_cap,
@@ -536,7 +724,19 @@ static hawkes_status run_small_mp(const SmallArgs& A, hipStream_t st) {
                        A.n_items_cap, A.item_off, A.beta, A.tile_agg, A.tile_carry);
     delete t5;
     TimedScope* t4 = new TimedScope(4, st);
-    if (A.grad) {
+    bool done = false;
+    if constexpr (MP >= 4) {
+        if (A.grad) {
+            constexpr int LPI = 2;   // lanes per item (4 measured slower for MP = 8)
+            const int64_t wc = (A.n_items_cap * LPI + 63) / 64;
+            hipLaunchKernelGGL((small_compute_c<MP, LPI>), dim3((unsigned)((wc + 3) / 4)), dim3(256), 0, st, A.S,
+                               A.n_total, A.ev_off, A.item_off, A.L, A.t, A.marks, A.m_s, A.T_s, A.mu, A.alpha,
+                               A.beta, A.mu_off, A.a_off, A.item_pref, A.tile_carry, A.part, PW, A.n_items_cap);
+            done = true;
+        }
+    }
+    if (done) {
+    } else if (A.grad) {
         hipLaunchKernelGGL((small_compute<MP, true, false>), dim3((unsigned)blocks), dim3(256), 0, st, A.S,
                            A.n_total, A.ev_off, A.item_off, A.L, A.t, A.marks, A.m_s, A.T_s, A.mu, A.alpha, A.beta,
                            A.mu_off, A.a_off, A.item_pref, A.tile_carry, A.part, PW, (float*)nullptr,
