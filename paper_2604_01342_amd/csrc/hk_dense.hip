@@ -2,7 +2,8 @@
 // of beta w_i K(t_i^-) into row m_i, from the bucketed event streams.
 //
 // Two kernels per chunk.  Column blocks are the buckets of W = 64 CPL nodes,
-// row blocks the buckets of HK_DR = 16 nodes.
+// row blocks the buckets of DR = 2^DRB nodes (tiles of 16 x 256 nodes, or
+// 16 x 128 and 16 x 64 for chunks whose event indices need more key bits).
 //   dense_ck     one wave per (column block, run of CKR segments): walks the
 //                block's records of the run once, in groups of 64, and stores
 //                the block's state K at the start of every group and after
@@ -23,10 +24,12 @@
 //                With c_k = beta w_k e^{-beta (t_k - tau_g)} and
 //                b_j = e^{beta (t_j - tau_g)} the window adds
 //                  u K_g^T, u_p = sum of c_k over its own events of row p
-//                (a rank-1 update: 16 x W float64 FMAs into G held in
+//                (a rank-1 update: DR x W float64 FMAs into G held in
 //                registers, lane = column), and c_k b_j at (m_k, m_j) for the
 //                group's records j before k (one masked ds_add_f64 per own
-//                event into an LDS tile of pair terms).
+//                event into an LDS tile of pair terms).  The pair terms cost
+//                a wave instruction per own event and column block, so the
+//                wide tiles (fewer column blocks) are the fast ones.
 // The state is shared through the checkpoints instead of being rebuilt by
 // every row block.  Every window issues the same loads at the same point
 // (the next window's checkpoint and column group, the next batch of own
@@ -37,11 +40,9 @@
 
 namespace hk {
 
-static_assert(HK_DR == 16, "row blocks are the 16-node buckets");
-
 // Checkpoint slots: group g of (column block sb, run r) uses slot
 // (P0 >> 6) + 2 (sb nrun + r) + g, with P0 the position of the run's first
-// record in the column block's share of the 16-node partition; the slots of
+// record in the column block's share of the DR-node partition; the slots of
 // different (sb, r) never overlap, and there are at most
 // (events) / 64 + 2 NBC nrun + 1.
 // Checkpoint slot record, in float64 words: the state (W), the anchor time
@@ -63,8 +64,8 @@ struct Slot {
 // group's records into its slot, then fold the group into the state.  Runs r
 // with the same r / 8 share an XCD (their column blocks read the same
 // events).  runinfo[sb][r] = (first slot, groups, P0, P1), P0..P1 the run's
-// positions in the column block's share of the 16-node partition.
-template <int CPL>
+// positions in the column block's share of the DR-node partition.
+template <int CPL, int DRB>
 __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t M, int32_t NBC, int32_t NBO,
                                                int32_t nrun, int32_t ckr, int32_t nseg, double T,
                                                const double* __restrict__ t, const int32_t* __restrict__ marks,
@@ -76,7 +77,8 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
                                                double* __restrict__ cpart) {
     using S = Slot<CPL>;
     constexpr int W = S::W;
-    constexpr int SH = CPL == 2 ? 7 : 6;   // bits of the local mark in a record key
+    constexpr int DR = 1 << DRB;
+    constexpr int SH = CPL == 4 ? 8 : CPL == 2 ? 7 : 6;   // bits of the local mark in a record key
     constexpr int UB = 16;                 // batches of marks in flight
     __shared__ double DL[W], SL[W], CL[W];
     __shared__ uint32_t keys[HK_CKR * HK_SEG];
@@ -92,9 +94,9 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
     const int32_t a = sA * HK_SEG;
     const int32_t b = sB * HK_SEG < nev ? sB * HK_SEG : nev;
     const int32_t s0 = sb * W;
-    // the column block's 16-node blocks are consecutive in the partition
-    const int32_t k0 = sb * (W / 16);
-    const int32_t k1 = k0 + W / 16 < NBO ? k0 + W / 16 : NBO;
+    // the column block's DR-node blocks are consecutive in the partition
+    const int32_t k0 = sb * (W / DR);
+    const int32_t k1 = k0 + W / DR < NBO ? k0 + W / DR : NBO;
     int32_t P0 = bo_base[k0], P1 = bo_base[k0];
     for (int32_t k = k0; k < k1; ++k) {
         P0 += bo_off[(int64_t)k * (nseg + 1) + sA];
@@ -242,8 +244,8 @@ struct Run {
     int32_t P0, P1, ng, slot0;
 };
 
-template <int CPL>
-__global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu(3))) void large_dense(int32_t M, int32_t NBC, int32_t NBR, int32_t ER, int32_t rpr,
+template <int CPL, int DRB>
+__global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 << DRB) * CPL > 32 ? 2 : 3))) void large_dense(int32_t M, int32_t NBC, int32_t NBR, int32_t ER, int32_t rpr,
                                                   int32_t nrun, int32_t ckr, int32_t nseg, int32_t nrec,
                                                   int32_t nslot, const float* __restrict__ beta,
                                                   const int4* __restrict__ runinfo,
@@ -254,9 +256,10 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu(3)))
                                                   const double* __restrict__ kck, double* __restrict__ gpart) {
     using S = Slot<CPL>;
     constexpr int W = S::W;
-    constexpr int SH = CPL == 2 ? 7 : 6;   // bits of the local mark in a column record key
-    __shared__ double GP[HK_DR * W];          // pair terms, shared by the group's waves
-    __shared__ double ULs[HK_DW][HK_DR];      // per wave: the window's u
+    constexpr int DR = 1 << DRB;
+    constexpr int SH = CPL == 4 ? 8 : CPL == 2 ? 7 : 6;   // bits of the local mark in a column record key
+    __shared__ double GP[DR * W];             // pair terms, shared by the group's waves
+    __shared__ double ULs[HK_DW][DR];         // per wave: the window's u
     __shared__ double2 ODs[HK_DW][66];        // per wave: own events of a pass (+2 read ahead)
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -287,30 +290,30 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu(3)))
     const int32_t rB = gA + ((wv + 1) * (gB - gA)) / HK_DW;
     const int32_t sb = local % NBC;
     const int32_t rb = local / NBC;
-    const int32_t r0 = rb * HK_DR, s0 = sb * W;
+    const int32_t r0 = rb * DR, s0 = sb * W;
     double* gp = gpart + (int64_t)er * M * M;
     // main terms of the block in registers (row i, column s0 + 64 j + lane),
     // wave 0 from the partials so far, the others from zero; branch-free
     // load, out-of-range rows/columns read a clamped valid address and are
     // zeroed
-    double Gm[HK_DR][CPL];
+    double Gm[DR][CPL];
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
         const int32_t col = s0 + j * 64 + lane;
         const int32_t cc = col < M ? col : M - 1;
 #pragma unroll
-        for (int i = 0; i < HK_DR; ++i) {
+        for (int i = 0; i < DR; ++i) {
             const int32_t row = r0 + i;
             const int32_t rr = row < M ? row : M - 1;
             Gm[i][j] = wv == 0 ? gp[(int64_t)rr * M + cc] : 0.0;
         }
 #pragma unroll
-        for (int i = 0; i < HK_DR; ++i) {
+        for (int i = 0; i < DR; ++i) {
             if (!(r0 + i < M && col < M)) Gm[i][j] = 0.0;
             if (i % HK_DW == wv) GP[i * W + j * 64 + lane] = 0.0;
         }
     }
-    if (lane < HK_DR) UL[lane] = 0.0;
+    if (lane < DR) UL[lane] = 0.0;
     const double bet = (double)beta[0];
     const __amdgpu_buffer_rsrc_t rK = buf(kck, (uint32_t)nslot * S::SIZE * 8u);
     const __amdgpu_buffer_rsrc_t rOk = buf(bo_key, (uint32_t)nrec * 4u);
@@ -357,20 +360,20 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu(3)))
     auto pass = [&](const Win<CPL>& w, int p, double tw, int hi, double tcl, bool cv, int cidx, int colj,
                     double bj) -> int {
         const OwnBatch& b = o0;
-        const bool own = qL + lane < Q1 && lane >= p && (int)(b.key >> 4) <= hi;
+        const bool own = qL + lane < Q1 && lane >= p && (int)(b.key >> DRB) <= hi;
         const int nsel = __builtin_popcountll(__ballot(own));
         if (nsel == 0) return 0;
         const int kend = p + nsel;   // own lanes are [p, kend)
         const double tlo = rl_d(b.t, kend - 1);
         const double tmax = tlo > tcl ? tlo : tcl;
-        const int rowl = (int)(b.key & (HK_DR - 1));
+        const int rowl = (int)(b.key & (DR - 1));
         if (bet * (tmax - tw) <= HK_WIDE) {
             const float cf = own ? (float)(bet * (double)b.w) * exp_f64arg(-bet * (b.t - tw)) : 0.0f;
             if (own) {
                 atomicAdd(&UL[rowl], (double)cf);
                 // (row offset, index, c_k) of this own event for the pair
                 // loop, read back by every lane (broadcast)
-                OD[lane] = make_double2(__hiloint2double(rowl * W, (int)(b.key >> 4)), (double)cf);
+                OD[lane] = make_double2(__hiloint2double(rowl * W, (int)(b.key >> DRB)), (double)cf);
             }
             // pair terms: own event k adds c_k b_j at (row_k, m_j) for the
             // group's records j before it (zero elsewhere)
@@ -396,10 +399,10 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu(3)))
             if (own) atomicAdd(&UL[rowl], cw * exp_f64(-bet * (b.t - tw)));
             for (int k = p; k < kend; ++k) {
                 const uint32_t key = (uint32_t)rl_i((int)b.key, k);
-                const int rofs = (int)(key & (HK_DR - 1)) * W;
+                const int rofs = (int)(key & (DR - 1)) * W;
                 const double tk = rl_d(b.t, k);
                 const double ck = rl_d(cw, k);
-                if (cv && cidx < (int)(key >> 4))
+                if (cv && cidx < (int)(key >> DRB))
                     atomicAdd(&GP[rofs + colj], ck * (double)exp_f64arg(-bet * (tk - w.ct)));
             }
         }
@@ -470,15 +473,15 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu(3)))
             // its LDS operations complete in order, so only the compiler
             // must not move them)
             __builtin_amdgcn_wave_barrier();
-            double u[HK_DR];
+            double u[DR];
 #pragma unroll
-            for (int i = 0; i < HK_DR; ++i) u[i] = UL[i];
+            for (int i = 0; i < DR; ++i) u[i] = UL[i];
 #pragma unroll
-            for (int i = 0; i < HK_DR; ++i)
+            for (int i = 0; i < DR; ++i)
 #pragma unroll
                 for (int j = 0; j < CPL; ++j) Gm[i][j] = __builtin_fma(u[i], cur.K[j], Gm[i][j]);
             __builtin_amdgcn_wave_barrier();
-            if (lane < HK_DR) UL[lane] = 0.0;
+            if (lane < DR) UL[lane] = 0.0;
             __builtin_amdgcn_wave_barrier();
         }
         if (same_run) {
@@ -506,7 +509,7 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu(3)))
     __syncthreads();
     if (wv != 0) {
 #pragma unroll
-        for (int i = 0; i < HK_DR; ++i)
+        for (int i = 0; i < DR; ++i)
 #pragma unroll
             for (int j = 0; j < CPL; ++j) atomicAdd(&GP[i * W + j * 64 + lane], Gm[i][j]);
     }
@@ -517,7 +520,7 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu(3)))
         const int32_t col = s0 + j * 64 + lane;
         if (col < M) {
 #pragma unroll
-            for (int rr = 0; rr < HK_DR; ++rr) {
+            for (int rr = 0; rr < DR; ++rr) {
                 const int32_t row = r0 + rr;
                 if (row < M) gp[(int64_t)row * M + col] = Gm[rr][j] + GP[rr * W + j * 64 + lane];
             }
@@ -525,35 +528,36 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu(3)))
     }
 }
 
-void large_dense_launch(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, hipStream_t st) {
-    const int32_t nrun_c = (nseg + A.CKR - 1) / A.CKR;
-    const int32_t nev = (int32_t)(c1 - c0);
+template <int CPL, int DRB>
+static void dense_launch_t(LargeArgs& A, int64_t c0, int32_t nev, int32_t nseg, int32_t nrun_c, hipStream_t st) {
     {
         TimedScope tk(7, st);
         const unsigned nck = (unsigned)(((nrun_c + 7) / 8) * 8 * A.NBC);
-        if (A.CPL == 2)
-            hipLaunchKernelGGL(dense_ck<2>, dim3(nck), dim3(64), 0, st, c0, nev, A.M, A.NBC, A.NBO, A.NRUN, A.CKR,
-                               nseg, A.T, A.t, A.marks, A.wchunk, A.beta, A.carry_seg, A.bo_off, A.bo_base, A.kck,
-                               A.runinfo, A.spart, A.cpart_);
-        else
-            hipLaunchKernelGGL(dense_ck<1>, dim3(nck), dim3(64), 0, st, c0, nev, A.M, A.NBC, A.NBO, A.NRUN, A.CKR,
-                               nseg, A.T, A.t, A.marks, A.wchunk, A.beta, A.carry_seg, A.bo_off, A.bo_base, A.kck,
-                               A.runinfo, A.spart, A.cpart_);
+        hipLaunchKernelGGL((dense_ck<CPL, DRB>), dim3(nck), dim3(64), 0, st, c0, nev, A.M, A.NBC, A.NBO, A.NRUN,
+                           A.CKR, nseg, A.T, A.t, A.marks, A.wchunk, A.beta, A.carry_seg, A.bo_off, A.bo_base,
+                           A.kck, A.runinfo, A.spart, A.cpart_);
     }
     TimedScope ts(0, st);
     const int32_t rpr = A.NRUN / A.ER;   // runs per event range (both powers of two)
     const int32_t nbb = A.NBR * A.NBC;
     const unsigned nblk = A.ER >= 8 ? (unsigned)(nbb * ((A.ER + 7) / 8) * 8)
                                     : (unsigned)(((nbb + 8 / A.ER - 1) / (8 / A.ER)) * 8);
-    const int32_t nslot = (int32_t)A.nslot;
-    if (A.CPL == 2)
-        hipLaunchKernelGGL(large_dense<2>, dim3(nblk), dim3(64 * HK_DW), 0, st, A.M, A.NBC, A.NBR, A.ER, rpr, A.NRUN,
-                           A.CKR, nseg, nev, nslot, A.beta, A.runinfo, A.bo_off, A.bo_base, A.bo_key, A.bo_t,
-                           A.bo_w, A.kck, A.gpart);
+    hipLaunchKernelGGL((large_dense<CPL, DRB>), dim3(nblk), dim3(64 * HK_DW), 0, st, A.M, A.NBC, A.NBR, A.ER, rpr,
+                       A.NRUN, A.CKR, nseg, nev, (int32_t)A.nslot, A.beta, A.runinfo, A.bo_off, A.bo_base, A.bo_key,
+                       A.bo_t, A.bo_w, A.kck, A.gpart);
+}
+
+void large_dense_launch(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, hipStream_t st) {
+    const int32_t nrun_c = (nseg + A.CKR - 1) / A.CKR;
+    const int32_t nev = (int32_t)(c1 - c0);
+    // the tiles the layout selects: 16 x 256, 8 x 256, 16 x 128, 16 x 64
+    if (A.CPL == 4)
+        A.DRB == 3 ? dense_launch_t<4, 3>(A, c0, nev, nseg, nrun_c, st)
+                   : dense_launch_t<4, 4>(A, c0, nev, nseg, nrun_c, st);
+    else if (A.CPL == 2)
+        dense_launch_t<2, 4>(A, c0, nev, nseg, nrun_c, st);
     else
-        hipLaunchKernelGGL(large_dense<1>, dim3(nblk), dim3(64 * HK_DW), 0, st, A.M, A.NBC, A.NBR, A.ER, rpr, A.NRUN,
-                           A.CKR, nseg, nev, nslot, A.beta, A.runinfo, A.bo_off, A.bo_base, A.bo_key, A.bo_t,
-                           A.bo_w, A.kck, A.gpart);
+        dense_launch_t<1, 4>(A, c0, nev, nseg, nrun_c, st);
 }
 
 }  // namespace hk

@@ -8,9 +8,6 @@
 #define HK_SEG 1024        // events per forward segment (one wave)
 #endif
 #define HK_RB 64           // targets per block of the per-target (adjoint) dense kernel
-#ifndef HK_DR
-#define HK_DR 16           // rows per block of the shared-decay dense kernel
-#endif
 #define HK_SLAB 64         // columns per dense-gradient block (one per lane)
 #ifndef HK_DW
 #define HK_DW 2            // waves per workgroup of the shared-decay dense kernel
@@ -35,8 +32,9 @@ struct LargeArgs {
     int32_t nseg;         // segments per chunk
     int32_t ER;           // event ranges of the dense kernel per chunk
     int32_t NB;           // node blocks of 64 (bucketing; columns of the dense kernels)
-    int32_t NBR;          // row blocks of the dense kernel (HK_DR rows shared decay, HK_RB per target)
-    int32_t CPL;          // columns per lane of the shared-decay dense kernel (1 or 2)
+    int32_t NBR;          // row blocks of the dense kernel (DR rows shared decay, HK_RB per target)
+    int32_t CPL;          // columns per lane of the shared-decay dense kernel (1, 2, 4 or 8)
+    int32_t DRB;          // log2 of DR, the rows per block of the shared-decay dense kernel
     int32_t NBC;          // column blocks of the dense kernel (64 CPL columns each)
     int32_t CKR;          // segments per checkpoint run (shared decay)
     int32_t NRUN;         // checkpoint runs per chunk (nseg / CKR)
@@ -86,11 +84,11 @@ struct LargeArgs {
     double* bk_t;         // [CH] event time
     float* bk_w;          // [CH] 1 / lambda
     float* wchunk;        // [CH] 1 / lambda of the chunk's events (shared decay)
-    // the same events partitioned by blocks of HK_DR nodes (the row blocks of
+    // the same events partitioned by blocks of DR nodes (the row blocks of
     // the shared-decay dense kernel): its own-event streams
-    int32_t NBO;          // row blocks (ceil(M / HK_DR))
+    int32_t NBO;          // row blocks (ceil(M / DR))
     int32_t *bo_cnt, *bo_off, *bo_base;
-    uint32_t* bo_key;     // [CH] (index in chunk) << 4 | mark mod 16
+    uint32_t* bo_key;     // [CH] (index in chunk) << DRB | mark mod DR
     double* bo_t;
     float* bo_w;
     // outputs

@@ -559,13 +559,26 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
     A.nchunks = (A.n + A.CH - 1) / A.CH;
     A.nseg = (int32_t)((A.CH + HK_SEG - 1) / HK_SEG);
     A.NB = (A.M + 63) / 64;
-    A.NBR = A.per_target ? A.NB : (A.M + HK_DR - 1) / HK_DR;
-    // two columns per lane (128-node blocks) when the chunk's event indices
-    // leave 7 bits of the 32-bit record key
-    A.CPL = (!A.per_target && lg <= 25) ? 2 : 1;
+    // shared decay: tiles of DR = 2^DRB rows x W = 64 CPL columns.  Every
+    // own event is visited once per column block (a pair-term instruction
+    // each), every window once per row block (state loads and the rank-1
+    // update), and G takes DR CPL float64 registers per lane: 16 x 256 is the
+    // fastest that fits (two waves per SIMD), with 16 x 128 and 16 x 64 for the
+    // longer chunks, since a column record key holds the event index above
+    // log2(W) bits.  HAWKES_DENSE_CPL / HAWKES_DENSE_DRB select another built
+    // tile (8 x 256 among them) for tests.
+    A.CPL = A.per_target ? 1 : lg <= 24 ? 4 : lg <= 25 ? 2 : 1;
+    A.DRB = 4;
     if (const char* e = getenv("HAWKES_DENSE_CPL")) {
-        if (atoi(e) == 1) A.CPL = 1;
+        const int v = atoi(e);
+        const int vlg = v == 4 ? 24 : v == 2 ? 25 : 26;
+        if (!A.per_target && (v == 1 || v == 2 || v == 4) && lg <= vlg) A.CPL = v;
     }
+    if (const char* e = getenv("HAWKES_DENSE_DRB")) {
+        const int v = atoi(e);
+        if (!A.per_target && (v == 4 || (v == 3 && A.CPL == 4))) A.DRB = v;
+    }
+    A.NBR = A.per_target ? A.NB : (A.M + (1 << A.DRB) - 1) >> A.DRB;
     A.NBC = A.per_target ? A.NB : (A.M + 64 * A.CPL - 1) / (64 * A.CPL);
     // event ranges per chunk for the dense kernel: a power of two so that the
     // ranges map onto the 8 XCDs evenly; about 4096 workgroups in total
@@ -648,7 +661,7 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
             A.nslot = A.CH / 64 + 2 * (int64_t)A.NBC * A.NRUN + 2;
             A.kck = c.take<double>((size_t)A.nslot * (64 * A.CPL + 104));
             A.runinfo = c.take<int4>((size_t)A.NBC * A.NRUN);
-            A.NBO = (A.M + HK_DR - 1) / HK_DR;
+            A.NBO = (A.M + (1 << A.DRB) - 1) >> A.DRB;
             A.bo_cnt = c.take<int32_t>((size_t)A.NBO * A.nseg);
             A.bo_off = c.take<int32_t>((size_t)A.NBO * (A.nseg + 1));
             A.bo_base = c.take<int32_t>(A.NBO);
@@ -784,7 +797,7 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
         if (A.grad) {
             {
                 TimedScope tb(6, st);
-                bucket_chunk_into(A, c0, c1, nseg, A.wchunk, 4, A.bo_cnt, A.bo_off, A.bo_base, A.bo_key, A.bo_t,
+                bucket_chunk_into(A, c0, c1, nseg, A.wchunk, A.DRB, A.bo_cnt, A.bo_off, A.bo_base, A.bo_key, A.bo_t,
                                   A.bo_w, st);
             }
             large_dense_launch(A, c0, c1, nseg, st);

@@ -87,18 +87,21 @@ def test_large_engine_matches_oracle(H, seed, n, M, density, ties, chunk):
     check(run_gpu(H, t, m, mu, alpha, beta, T, chunk), ref, label=f"large n={n} M={M} chunk={chunk}")
 
 
-@pytest.mark.parametrize("cpl,er,chunk", [("1", "", 0), ("1", "2", 12), ("", "1", 0), ("", "2", 12),
-                                           ("", "64", 0), ("", "1024", 0)])
-def test_dense_layouts_match_oracle(H, cpl, er, chunk):
-    # the dense dL/dalpha kernel's column-block width (64 or 128 nodes) and
+@pytest.mark.parametrize("cpl,drb,er,chunk", [("1", "", "", 0), ("1", "", "2", 12), ("2", "", "", 0),
+                                               ("2", "", "2", 12), ("", "", "1", 0), ("", "", "2", 12),
+                                               ("", "", "64", 0), ("", "", "1024", 0), ("4", "3", "", 0),
+                                               ("4", "3", "2", 12)])
+def test_dense_layouts_match_oracle(H, cpl, drb, er, chunk):
+    # the dense dL/dalpha kernel's tile (DR rows x 64 CPL columns) and
     # event-range count change its run, slot and workgroup layout, never the
     # result
     import os
     t, m, mu, alpha, beta, T = rand_problem(17, 30000, 200, density=0.1, rate=40.0)
     ref = oracle.forward(t, m, mu, alpha, beta, T)
-    old = {k: os.environ.get(k) for k in ("HAWKES_DENSE_CPL", "HAWKES_DENSE_ER")}
+    keys = ("HAWKES_DENSE_CPL", "HAWKES_DENSE_DRB", "HAWKES_DENSE_ER")
+    old = {k: os.environ.get(k) for k in keys}
     try:
-        for k, v in (("HAWKES_DENSE_CPL", cpl), ("HAWKES_DENSE_ER", er)):
+        for k, v in zip(keys, (cpl, drb, er)):
             if v:
                 os.environ[k] = v
             else:
@@ -110,7 +113,7 @@ def test_dense_layouts_match_oracle(H, cpl, er, chunk):
                 os.environ.pop(k, None)
             else:
                 os.environ[k] = v
-    check(got, ref, label=f"dense layout cpl={cpl or 2} er={er or 'auto'} chunk={chunk}")
+    check(got, ref, label=f"dense layout cpl={cpl or 'auto'} drb={drb or 'auto'} er={er or 'auto'} chunk={chunk}")
 
 
 def test_chunk_size_invariance(H):
