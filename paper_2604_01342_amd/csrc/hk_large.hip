@@ -568,6 +568,7 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
     // log2(W) bits.  HAWKES_DENSE_CPL / HAWKES_DENSE_DRB select another built
     // tile (8 x 256 among them) for tests.
     A.CPL = A.per_target ? 1 : lg <= 24 ? 4 : lg <= 25 ? 2 : 1;
+    while (A.CPL > 1 && 32 * A.CPL >= A.M) A.CPL >>= 1;   // no wider than the nodes need
     A.DRB = 4;
     if (const char* e = getenv("HAWKES_DENSE_CPL")) {
         const int v = atoi(e);
@@ -583,10 +584,11 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
     // event ranges per chunk for the dense kernel: a power of two so that the
     // ranges map onto the 8 XCDs evenly; about 4096 workgroups in total
     // (shared decay: two waves each, 18 KiB of LDS per group, so that several
-    // rounds balance the waves' uneven work) or 2048 (per target, 34 KiB)
-    // unless HAWKES_DENSE_ER (a power of two) overrides it
+    // rounds balance the waves' uneven work) or 2048 (per target, 34 KiB;
+    // 16 x 256 tiles, 34 KiB and two waves per SIMD: measured best at c4's
+    // size) unless HAWKES_DENSE_ER (a power of two) overrides it
     const int64_t nbb = (int64_t)A.NBR * A.NBC;
-    const int64_t target = A.per_target ? 2048 : 4096;
+    const int64_t target = A.per_target || A.CPL == 4 ? 2048 : 4096;
     const int64_t want = (target + nbb - 1) / nbb;
     int32_t er = 1;
     while (er < want) er <<= 1;
