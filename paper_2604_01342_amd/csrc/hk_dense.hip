@@ -262,7 +262,7 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
     __shared__ double ULs[HK_DW][DR];         // per wave: the window's u
     __shared__ double2 ODs[HK_DW][66];        // per wave: own events of a pass (+2 read ahead)
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     double* UL = ULs[wv];
     double2* OD = ODs[wv];
     const int32_t blk = blockIdx.x;
@@ -394,9 +394,11 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
             }
         } else {
             // wide window (anchored factors would leave float32 range):
-            // float64 decays for u, exact per-pair decays
+            // c_k decayed from the window's anchor (below float32 range it
+            // is zero, and so is its product with the state), exact
+            // per-pair decays
             const double cw = bet * (double)b.w;
-            if (own) atomicAdd(&UL[rowl], cw * exp_f64(-bet * (b.t - tw)));
+            if (own) atomicAdd(&UL[rowl], cw * (double)exp_f64arg(-bet * (b.t - tw)));
             for (int k = p; k < kend; ++k) {
                 const uint32_t key = (uint32_t)rl_i((int)b.key, k);
                 const int rofs = (int)(key & (DR - 1)) * W;
