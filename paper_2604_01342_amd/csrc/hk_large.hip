@@ -44,7 +44,7 @@ __global__ void fill_d(double* p, int64_t n, double v) {
 __global__ __launch_bounds__(1024) void large_colsum(int32_t M, const float* __restrict__ alpha,
                                                      float* __restrict__ colsum) {
     __shared__ double part[16][64];
-    const int lane = threadIdx.x & 63, r = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int32_t q = blockIdx.x * 64 + lane;
     double c = 0.0;
     if (q < M)

@@ -417,7 +417,7 @@ __global__ __launch_bounds__(64 * HK_DWP) void pt_dense(int64_t c0, int64_t c1, 
     __shared__ double ALs[HK_DWP][64], SLs[HK_DWP][64], NLs[HK_DWP][64];
     __shared__ float BL[64];
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     double* AL = ALs[wv];
     double* SL = SLs[wv];
     double* NL = NLs[wv];

@@ -154,7 +154,8 @@ __global__ __launch_bounds__(256) void small_agg(int32_t S, int64_t n_total, con
                                                  double* __restrict__ tile_agg,    // [tiles][2 + 2MP]
                                                  int64_t n_items_cap) {
     const int lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) +
+                         __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int64_t it = wave * 64 + lane;
     if (wave * 64 >= n_items_cap) return;   // whole wave beyond the buffers (wave-uniform)
     ItemInfo inf = item_info(it, S, item_off, ev_off, L, n_total, n_items_cap);
@@ -310,7 +311,8 @@ __global__ __launch_bounds__(256) void small_compute(int32_t S, int64_t n_total,
                                                      double* __restrict__ part, int32_t PW,
                                                      float* __restrict__ lambda_out, int64_t n_items_cap) {
     const int lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) +
+                         __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int64_t it = wave * 64 + lane;
     if (it >= n_items_cap) return;
     ItemInfo inf = item_info(it, S, item_off, ev_off, L, n_total, n_items_cap);
@@ -487,7 +489,8 @@ __global__ __launch_bounds__(256) void small_compute_c(int32_t S, int64_t n_tota
     const int c = lane % LPI;
     const int g0 = lane - c;       // the group's first lane
     const int qa = c * CL;         // this lane's first node
-    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) +
+                         __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int64_t it = wave * IPW + lane / LPI;
     if (it >= n_items_cap) return;   // the whole group
     const ItemInfo inf = item_info(it, S, item_off, ev_off, L, n_total, n_items_cap);
