@@ -29,7 +29,16 @@ __global__ __launch_bounds__(64) void bucket_count(int64_t c0, int64_t c1, int32
     __syncthreads();
     const int64_t a = c0 + (int64_t)s * HK_SEG;
     const int64_t b = a + HK_SEG < c1 ? a + HK_SEG : c1;
-    for (int64_t i = a + lane; i < b; i += 64) atomicAdd(&lc[clamp_mark(marks[i], M) >> bs], 1);
+    constexpr int NBT = HK_SEG / 64;
+    int mks[NBT];   // all loads up front (past the end: a valid index, not counted)
+#pragma unroll
+    for (int u = 0; u < NBT; ++u) {
+        const int64_t i = a + 64 * u + lane;
+        mks[u] = marks[i < b ? i : b - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < NBT; ++u)
+        if (a + 64 * u + lane < b) atomicAdd(&lc[clamp_mark(mks[u], M) >> bs], 1);
     __syncthreads();
     for (int32_t k = lane; k < NB; k += 64) cnt[(int64_t)k * nseg + s] = lc[k];
 }
@@ -102,11 +111,26 @@ __global__ __launch_bounds__(64) void bucket_scatter(int64_t c0, int64_t c1, int
     const int64_t a = c0 + (int64_t)s * HK_SEG;
     const int64_t b = a + HK_SEG < c1 ? a + HK_SEG : c1;
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-    for (int64_t base = a; base < b; base += 64) {
+    // the segment's marks, times and weights, all loads issued up front
+    constexpr int NBT = HK_SEG / 64;
+    int mks[NBT];
+    double ts[NBT];
+    float ws[NBT];
+#pragma unroll
+    for (int u = 0; u < NBT; ++u) {
+        const int64_t i = a + 64 * u + lane;
+        const int64_t ic = i < b ? i : b - 1;
+        mks[u] = marks[ic];
+        ts[u] = t[ic];
+        ws[u] = wchunk[ic - c0];
+    }
+#pragma unroll
+    for (int u = 0; u < NBT; ++u) {
+        const int64_t base = a + 64 * u;
+        if (base >= b) break;
         const int64_t i = base + lane;
         const bool v = i < b;
-        const int64_t ic = v ? i : b - 1;
-        const int mk = clamp_mark(marks[ic], M);
+        const int mk = clamp_mark(mks[u], M);
         const int blk = mk >> bs;
         // lanes with the same block: agree on every bit of the block number
         uint64_t same = __ballot(v);
@@ -119,8 +143,8 @@ __global__ __launch_bounds__(64) void bucket_scatter(int64_t c0, int64_t c1, int
         if (v) {
             const int64_t pos = (int64_t)bbase[blk] + boff[(int64_t)blk * (nseg + 1) + s] + before + rank;
             bk_key[pos] = ((uint32_t)(i - c0) << bs) | (uint32_t)(mk & ((1 << bs) - 1));
-            bk_t[pos] = t[i];
-            bk_w[pos] = wchunk[i - c0];
+            bk_t[pos] = ts[u];
+            bk_w[pos] = ws[u];
         }
         __syncthreads();
         if (v && (same & lt) == 0) run[blk] = before + __builtin_popcountll(same);

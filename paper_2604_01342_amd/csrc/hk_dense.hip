@@ -183,16 +183,25 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
         }
         tau = tn;
     };
-    Rec ra, rb;
-    load(ra, 0);
+    // records of four groups in flight (a group's wait then covers loads
+    // issued three groups earlier)
+    Rec r0, r1, r2, r3;
+    load(r0, 0);
+    load(r1, 1);
+    load(r2, 2);
     int32_t g = 0;
     while (g < ng) {
-        load(rb, g + 1);
-        emit(ra, g);
-        ++g;
-        if (g >= ng) break;
-        load(ra, g + 1);
-        emit(rb, g);
+        load(r3, g + 3);
+        emit(r0, g);
+        if (++g >= ng) break;
+        load(r0, g + 3);
+        emit(r1, g);
+        if (++g >= ng) break;
+        load(r1, g + 3);
+        emit(r2, g);
+        if (++g >= ng) break;
+        load(r2, g + 3);
+        emit(r3, g);
         ++g;
     }
     put_state(ng);   // after the last group

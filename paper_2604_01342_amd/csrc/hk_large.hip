@@ -47,8 +47,10 @@ __global__ __launch_bounds__(1024) void large_colsum(int32_t M, const float* __r
     const int lane = threadIdx.x & 63, r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int32_t q = blockIdx.x * 64 + lane;
     double c = 0.0;
-    if (q < M)
+    if (q < M) {
+#pragma unroll 8
         for (int32_t p = r; p < M; p += 16) c += (double)alpha[(int64_t)p * M + q];
+    }
     part[r][lane] = c;
     __syncthreads();
     if (r == 0 && q < M) {
@@ -148,12 +150,24 @@ __global__ __launch_bounds__(64) void large_seg_agg(int64_t c0, int64_t c1, int3
     __syncthreads();
     const double bet = (double)beta[0];
     const double te = t[b - 1];
-    for (int64_t base = a; base < b; base += 64) {
-        const int64_t i = base + lane;
-        if (i < b) {
-            const double d = te - t[i];
+    // the segment's times and marks, all loads issued up front (past the
+    // end: a valid index, not added)
+    constexpr int NBT = HK_SEG / 64;
+    double ts[NBT];
+    int mks[NBT];
+#pragma unroll
+    for (int u = 0; u < NBT; ++u) {
+        const int64_t i = a + 64 * u + lane;
+        const int64_t ic = i < b ? i : b - 1;
+        ts[u] = t[ic];
+        mks[u] = marks[ic];
+    }
+#pragma unroll
+    for (int u = 0; u < NBT; ++u) {
+        if (a + 64 * u + lane < b) {
+            const double d = te - ts[u];
             const double e = exp_f64(-bet * d);
-            const int mi = clamp_mark(marks[i], M);
+            const int mi = clamp_mark(mks[u], M);
             atomicAdd(&aK[mi], e);
             atomicAdd(&aJ[mi], d * e);
         }
@@ -179,7 +193,7 @@ __global__ __launch_bounds__(64) void large_seg_agg(int64_t c0, int64_t c1, int3
 
 // beta_pt: per-target decays (R-form state) or nullptr (one shared decay,
 // seg_dec / gdec precomputed)
-__global__ void large_scan_local(int32_t nseg, int32_t M, const double* __restrict__ agg,
+__global__ __launch_bounds__(256) void large_scan_local(int32_t nseg, int32_t M, const double* __restrict__ agg,
                                  const double* __restrict__ seg_dec, const double* __restrict__ seg_span,
                                  double* __restrict__ carry_seg, double* __restrict__ gagg,
                                  const float* __restrict__ beta_pt) {
@@ -190,17 +204,27 @@ __global__ void large_scan_local(int32_t nseg, int32_t M, const double* __restri
     const int32_t s0 = g * HK_SG, s1 = s0 + HK_SG < nseg ? s0 + HK_SG : nseg;
     double K = 0.0, J = 0.0;
     const double bq = beta_pt ? (double)beta_pt[q] : 0.0;
-#pragma unroll 8
-    for (int32_t s = s0; s < s1; ++s) {
-        const double* row = agg + (int64_t)s * 2 * M;
-        double* o = carry_seg + (int64_t)s * 2 * M;
-        o[q] = K;
-        o[M + q] = J;
-        const double D = seg_span[s];
-        const double ex = beta_pt ? exp(-bq * D) : seg_dec[s];
-        const double k0 = K;
-        K = __builtin_fma(ex, k0, row[q]);
-        J = __builtin_fma(ex, __builtin_fma(D, k0, J), row[M + q]);
+    // the group's segment maps of node q, all loads issued up front
+    double rk[HK_SG], rj[HK_SG];
+#pragma unroll
+    for (int u = 0; u < HK_SG; ++u) {
+        const int32_t s = s0 + u < s1 ? s0 + u : s1 - 1;
+        rk[u] = agg[(int64_t)s * 2 * M + q];
+        rj[u] = agg[(int64_t)s * 2 * M + M + q];
+    }
+#pragma unroll
+    for (int u = 0; u < HK_SG; ++u) {
+        const int32_t s = s0 + u;
+        if (s < s1) {
+            double* o = carry_seg + (int64_t)s * 2 * M;
+            o[q] = K;
+            o[M + q] = J;
+            const double D = seg_span[s];
+            const double ex = beta_pt ? exp(-bq * D) : seg_dec[s];
+            const double k0 = K;
+            K = __builtin_fma(ex, k0, rk[u]);
+            J = __builtin_fma(ex, __builtin_fma(D, k0, J), rj[u]);
+        }
     }
     gagg[(int64_t)g * 2 * M + q] = K;
     gagg[(int64_t)g * 2 * M + M + q] = J;
@@ -227,7 +251,7 @@ __global__ void large_scan_gdec(int32_t nseg, const double* __restrict__ seg_spa
     gdec[g] = exp(-b0 * D);
 }
 
-__global__ void large_scan_groups(int32_t nseg, int32_t M, const double* __restrict__ gagg,
+__global__ __launch_bounds__(256) void large_scan_groups(int32_t nseg, int32_t M, const double* __restrict__ gagg,
                                   const double* __restrict__ gspan, const double* __restrict__ gdec,
                                   double* __restrict__ gcarry, double* __restrict__ carry,
                                   const float* __restrict__ beta_pt) {
@@ -236,15 +260,29 @@ __global__ void large_scan_groups(int32_t nseg, int32_t M, const double* __restr
     const int32_t ngr = (nseg + HK_SG - 1) / HK_SG;
     double K = carry[q], J = carry[M + q];
     const double bq = beta_pt ? (double)beta_pt[q] : 0.0;
-#pragma unroll 8
-    for (int32_t g = 0; g < ngr; ++g) {
-        gcarry[(int64_t)g * 2 * M + q] = K;
-        gcarry[(int64_t)g * 2 * M + M + q] = J;
-        const double D = gspan[g];
-        const double ex = beta_pt ? exp(-bq * D) : gdec[g];
-        const double k0 = K;
-        K = __builtin_fma(ex, k0, gagg[(int64_t)g * 2 * M + q]);
-        J = __builtin_fma(ex, __builtin_fma(D, k0, J), gagg[(int64_t)g * 2 * M + M + q]);
+    // 16 group maps of node q at a time, their loads issued up front
+    constexpr int PF = 16;
+    for (int32_t g0 = 0; g0 < ngr; g0 += PF) {
+        double gk[PF], gj[PF];
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int32_t g = g0 + u < ngr ? g0 + u : ngr - 1;
+            gk[u] = gagg[(int64_t)g * 2 * M + q];
+            gj[u] = gagg[(int64_t)g * 2 * M + M + q];
+        }
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int32_t g = g0 + u;
+            if (g < ngr) {
+                gcarry[(int64_t)g * 2 * M + q] = K;
+                gcarry[(int64_t)g * 2 * M + M + q] = J;
+                const double D = gspan[g];
+                const double ex = beta_pt ? exp(-bq * D) : gdec[g];
+                const double k0 = K;
+                K = __builtin_fma(ex, k0, gk[u]);
+                J = __builtin_fma(ex, __builtin_fma(D, k0, J), gj[u]);
+            }
+        }
     }
     carry[q] = K;
     carry[M + q] = J;
@@ -520,18 +558,28 @@ __global__ void large_colfold(int32_t M, int32_t NSC, double* __restrict__ spart
     cpart[q] = c;
 }
 
-__global__ void large_final(int32_t M, int32_t ER, int32_t NSC, double T, const float* __restrict__ mu,
+__global__ __launch_bounds__(256) void large_final(int32_t M, int32_t ER, int32_t NSC, double T, const float* __restrict__ mu,
                             const double* __restrict__ acc, const double* __restrict__ gpart,
                             const double* __restrict__ spart, const double* __restrict__ cpart,
                             double* __restrict__ loglik, double* __restrict__ g_mu, double* __restrict__ g_alpha,
                             double* __restrict__ g_beta, int grad) {
     const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t MM = (int64_t)M * M;
-    if (x == 0) {
-        double musum = 0.0;
-        for (int32_t p = 0; p < M; ++p) musum += (double)mu[p];
-        loglik[0] = acc[0] - T * musum - acc[1];
-        if (grad && g_beta) g_beta[0] = acc[3] - acc[2];
+    if (blockIdx.x == 0) {
+        // sum of mu in a fixed order: strided partial sums, then a tree
+        __shared__ double ps[256];
+        double v = 0.0;
+        for (int32_t p = threadIdx.x; p < M; p += 256) v += (double)mu[p];
+        ps[threadIdx.x] = v;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) ps[threadIdx.x] += ps[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            loglik[0] = acc[0] - T * ps[0] - acc[1];
+            if (grad && g_beta) g_beta[0] = acc[3] - acc[2];
+        }
     }
     if (!grad) return;
     if (x < MM && g_alpha) {

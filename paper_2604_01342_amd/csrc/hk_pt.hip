@@ -574,7 +574,7 @@ __global__ __launch_bounds__(64 * HK_DWP) void pt_dense(int64_t c0, int64_t c1, 
     if (rb == 0 && s0 + lane < M) npart[(int64_t)er * M + s0 + lane] += nl;
 }
 
-__global__ void pt_final(int32_t M, int32_t ER, double T, const float* __restrict__ mu,
+__global__ __launch_bounds__(256) void pt_final(int32_t M, int32_t ER, double T, const float* __restrict__ mu,
                          const double* __restrict__ acc, const double* __restrict__ gpart,
                          const double* __restrict__ spart, const double* __restrict__ npart,
                          const double* __restrict__ ebacc,
@@ -582,10 +582,18 @@ __global__ void pt_final(int32_t M, int32_t ER, double T, const float* __restric
                          double* __restrict__ g_beta, int grad) {
     const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t MM = (int64_t)M * M;
-    if (x == 0) {
-        double musum = 0.0;
-        for (int32_t p = 0; p < M; ++p) musum += (double)mu[p];
-        loglik[0] = acc[0] - T * musum - acc[1];
+    if (blockIdx.x == 0) {
+        // sum of mu in a fixed order: strided partial sums, then a tree
+        __shared__ double ps[256];
+        double v = 0.0;
+        for (int32_t p = threadIdx.x; p < M; p += 256) v += (double)mu[p];
+        ps[threadIdx.x] = v;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) ps[threadIdx.x] += ps[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) loglik[0] = acc[0] - T * ps[0] - acc[1];
     }
     if (!grad) return;
     if (x < MM && g_alpha) {
