@@ -130,6 +130,7 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
 
     // (2) groups
     const double bet = (double)beta[0];
+    const double bl2 = bet * HK_LOG2E;   // decays as powers of 2
     double K[CPL];
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
@@ -166,12 +167,12 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
         out[S::T + lane] = v ? q.t : 0.0;
         reinterpret_cast<uint32_t*>(out + S::KEY)[lane] = q.key;
         const double tn = rl_d(q.t, nv - 1);
-        const double f = (double)exp_f64arg(-bet * (tn - tau));
+        const double f = (double)exp2_f64arg((tau - tn) * bl2);
 #pragma unroll
         for (int j = 0; j < CPL; ++j) K[j] *= f;
         if (v) {
             const int col = (int)(q.key & (uint32_t)(W - 1));
-            atomicAdd(&DL[col], (double)exp_f64arg(-bet * (tn - q.t)));
+            atomicAdd(&DL[col], (double)exp2_f64arg((q.t - tn) * bl2));
             atomicAdd(&SL[col], (double)q.w);
             atomicAdd(&CL[col], -expm1(-bet * (T - q.t)));
         }
@@ -324,6 +325,7 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
     }
     if (lane < DR) UL[lane] = 0.0;
     const double bet = (double)beta[0];
+    const double bl2 = bet * HK_LOG2E;   // decays as powers of 2
     const __amdgpu_buffer_rsrc_t rK = buf(kck, (uint32_t)nslot * S::SIZE * 8u);
     const __amdgpu_buffer_rsrc_t rOk = buf(bo_key, (uint32_t)nrec * 4u);
     const __amdgpu_buffer_rsrc_t rOt = buf(bo_t, (uint32_t)nrec * 8u);
@@ -377,7 +379,7 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
         const double tmax = tlo > tcl ? tlo : tcl;
         const int rowl = (int)(b.key & (DR - 1));
         if (bet * (tmax - tw) <= HK_WIDE) {
-            const float cf = own ? (float)(bet * (double)b.w) * exp_f64arg(-bet * (b.t - tw)) : 0.0f;
+            const float cf = own ? (float)(bet * (double)b.w) * exp2_f64arg((tw - b.t) * bl2) : 0.0f;
             if (own) {
                 atomicAdd(&UL[rowl], (double)cf);
                 // (row offset, index, c_k) of this own event for the pair
@@ -407,14 +409,14 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
             // is zero, and so is its product with the state), exact
             // per-pair decays
             const double cw = bet * (double)b.w;
-            if (own) atomicAdd(&UL[rowl], cw * (double)exp_f64arg(-bet * (b.t - tw)));
+            if (own) atomicAdd(&UL[rowl], cw * (double)exp2_f64arg((tw - b.t) * bl2));
             for (int k = p; k < kend; ++k) {
                 const uint32_t key = (uint32_t)rl_i((int)b.key, k);
                 const int rofs = (int)(key & (DR - 1)) * W;
                 const double tk = rl_d(b.t, k);
                 const double ck = rl_d(cw, k);
                 if (cv && cidx < (int)(key >> DRB))
-                    atomicAdd(&GP[rofs + colj], ck * (double)exp_f64arg(-bet * (tk - w.ct)));
+                    atomicAdd(&GP[rofs + colj], ck * (double)exp2_f64arg((w.ct - tk) * bl2));
             }
         }
         return nsel;
@@ -458,7 +460,7 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
         const bool cv = lane < nv;
         const int cidx = cv ? (int)(cur.ckey >> SH) : 0x7fffffff;
         const int colj = (int)(cur.ckey & (uint32_t)(W - 1));
-        const double bj = cv ? (double)exp_f64arg(bet * (cur.ct - tw)) : 0.0;
+        const double bj = cv ? (double)exp2_f64arg((cur.ct - tw) * bl2) : 0.0;
         int nown = 0;
         for (;;) {
             if (q - qL == 64) {

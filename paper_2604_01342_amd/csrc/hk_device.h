@@ -8,23 +8,19 @@
 
 namespace hk {
 
-// e^x for a float64 argument x <= ~80, returned in float32.  The argument is
-// reduced in float64 (x = k ln2 + r, |r| <= ln2/2, Cody-Waite split of ln2)
-// so that a large |x| does not lose the absolute accuracy of r; 2^(r log2 e)
-// then comes from the hardware exp2, and k is applied with ldexp.  Relative
-// error is a few float32 ulp for every x the kernels pass.
-__device__ __forceinline__ float exp_f64arg(double x) {
-    const double kLog2e = 1.4426950408889634;
-    const double kLn2Hi = 6.93147180369123816490e-01;
-    const double kLn2Lo = 1.90821492927058770002e-10;
-    double k = __builtin_rint(x * kLog2e);
-    double r = __builtin_fma(-k, kLn2Hi, x);
-    r = __builtin_fma(-k, kLn2Lo, r);
-    float e = __builtin_amdgcn_exp2f((float)(r * kLog2e));
+// 2^y for a float64 argument y (|y| up to a few hundred), returned in
+// float32: y = k + r with k = rint(y) and r = y - k (exact in float64), 2^r
+// from the hardware exp2, k applied with ldexp (far below float32 range: 0).
+// Callers fold log2(e) into the rate, so that e^{b x} costs one float64
+// multiply before this; relative error a few float32 ulp.
+__device__ __forceinline__ float exp2_f64arg(double y) {
+    const double k = __builtin_rint(y);
+    const float e = __builtin_amdgcn_exp2f((float)(y - k));
     int ki = (int)k;
-    ki = ki < -300 ? -300 : ki;   // far below float32 range -> 0 after ldexp
+    ki = ki < -300 ? -300 : ki;
     return __builtin_ldexpf(e, ki);
 }
+#define HK_LOG2E 1.4426950408889634
 
 // e^x in float64 for x <= 0 (the decays of the forward passes).  Cody-Waite
 // reduction x = k ln2 + r with |r| <= ln2/2 (ln2 split in two parts), then

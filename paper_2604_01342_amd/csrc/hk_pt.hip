@@ -324,7 +324,7 @@ __global__ __launch_bounds__(64) void pt_rev_agg(int64_t c0, int64_t c1, int32_t
         if (i < b) {
             const int p = clamp_mark(marks[i], M);
             const double w = (double)wv[i];
-            atomicAdd(&aA[p], w * (double)exp_f64arg(-(double)beta[p] * (t[i] - tf)));
+            atomicAdd(&aA[p], w * (double)exp2_f64arg((tf - t[i]) * ((double)beta[p] * HK_LOG2E)));
         }
     }
     __syncthreads();
@@ -471,7 +471,8 @@ __global__ __launch_bounds__(64 * HK_DWP) void pt_dense(int64_t c0, int64_t c1, 
         }
     }
     const double bp = pv ? (double)beta[p] : 0.0;
-    const float bpl = (float)(bp * 1.4426950408889634);   // beta_p log2(e)
+    const double bp2 = bp * HK_LOG2E;                      // beta_p log2(e)
+    const float bpl = (float)bp2;
     // largest decay of the block's targets
     double bmax = bp;
     for (int off = 32; off > 0; off >>= 1) {
@@ -511,10 +512,11 @@ __global__ __launch_bounds__(64 * HK_DWP) void pt_dense(int64_t c0, int64_t c1, 
             tw = a0 > tw ? a0 : tw;
             tl = a1 < tl ? a1 : tl;
         }
-        Ah *= (double)exp_f64arg(-bp * (tau - tw));
+        Ah *= (double)exp2_f64arg((tw - tau) * bp2);
         const int pi = (int)(O.ck & 63u);
         const double bo = (double)BL[pi];
-        const float bol = (float)(bo * 1.4426950408889634);
+        const double bo2 = bo * HK_LOG2E;
+        const float bol = (float)bo2;
         const double wi = (double)O.cw;
         if (bmax * (tw - tl) <= 0.5) {
             // short window: every decay exponent is at most 0.5, so its
@@ -535,16 +537,16 @@ __global__ __launch_bounds__(64 * HK_DWP) void pt_dense(int64_t c0, int64_t c1, 
                 const int qoff = (int)(rl_i((int)S.ck, k) & 63) * 65;
                 const double tk = rl_d(S.ct, k);
                 const int ik = rl_i(is, k);
-                atomicAdd(&G[qoff + lane], bp * Ah * (double)exp_f64arg(-bp * (tw - tk)));
-                if (own && io > ik) atomicAdd(&G[qoff + pi], bo * wi * (double)exp_f64arg(-bo * (O.ct - tk)));
+                atomicAdd(&G[qoff + lane], bp * Ah * (double)exp2_f64arg((tk - tw) * bp2));
+                if (own && io > ik) atomicAdd(&G[qoff + pi], bo * wi * (double)exp2_f64arg((tk - O.ct) * bo2));
             }
         }
         if (sb == 0 && own) atomicAdd(&SL[pi], wi);
         if (rb == 0 && sl) atomicAdd(&NL[S.ck & 63u], 1.0);
-        if (own) atomicAdd(&AL[pi], wi * (double)exp_f64arg(-bo * (O.ct - tl)));
+        if (own) atomicAdd(&AL[pi], wi * (double)exp2_f64arg((tl - O.ct) * bo2));
         // AL is this wave's: its LDS operations complete in order
         __builtin_amdgcn_wave_barrier();
-        Ah = __builtin_fma(Ah, (double)exp_f64arg(-bp * (tw - tl)), AL[lane]);
+        Ah = __builtin_fma(Ah, (double)exp2_f64arg((tl - tw) * bp2), AL[lane]);
         __builtin_amdgcn_wave_barrier();
         AL[lane] = 0.0;
         __builtin_amdgcn_wave_barrier();
