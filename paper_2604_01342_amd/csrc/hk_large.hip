@@ -319,8 +319,7 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
     extern __shared__ double lds[];
     double* rtau = lds;                                   // [M] time of the record
     uint64_t* rmask = (uint64_t*)(lds + M);               // [M] lanes of this batch with mark q
-    double* rK = lds + 2 * M;                             // [M] K_q at rtau (event included)
-    double* rJ = lds + 3 * M;                             // [M] J_q at rtau
+    double2* rKJ = reinterpret_cast<double2*>(lds + 2 * M);   // [M] (K_q, J_q) at rtau (event included)
     __shared__ double tb[64], eb[64];
     const int32_t s = blockIdx.x;
     const int lane = threadIdx.x;
@@ -329,7 +328,7 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
     const double bet = (double)beta[0];
     const double tref = a > 0 ? t[a - 1] : t[a];
     // anchored records when the segment's span allows: with u = t - tref,
-    // rK[q] = S0_q = sum_j e^{beta u_j}, rJ[q] = S1_q = sum_j u_j e^{beta u_j}
+    // rKJ[q] = (S0_q, S1_q) with S0_q = sum_j e^{beta u_j}, S1_q = sum_j u_j e^{beta u_j}
     // over the node's events so far (the carry enters as S0 = K(tref),
     // S1 = -J(tref)); then K_q(t) = e^{-beta u} S0_q and
     // J_q(t) = e^{-beta u} (u S0_q - S1_q): one exponential per event instead
@@ -340,8 +339,7 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
     const double* cs = carry_seg + (int64_t)s * 2 * M;
     for (int32_t q = lane; q < M; q += 64) {
         rtau[q] = tref;
-        rK[q] = cs[q];
-        rJ[q] = anch ? -cs[M + q] : cs[M + q];
+        rKJ[q] = make_double2(cs[q], anch ? -cs[M + q] : cs[M + q]);
         rmask[q] = 0ull;
     }
     __syncthreads();
@@ -402,8 +400,9 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
                 // anchored sums of source q (records plus the batch's earlier
                 // events of q), weight av
                 auto terma = [&](int32_t q, float av) {
-                    double s0 = rK[q];
-                    double s1 = GRAD ? rJ[q] : 0.0;
+                    const double2 kj = rKJ[q];   // one LDS read for both
+                    double s0 = kj.x;
+                    double s1 = GRAD ? kj.y : 0.0;
                     uint64_t bits = rmask[q] & below;
                     while (bits) {
                         const int jj = __builtin_ctzll(bits);
@@ -428,9 +427,10 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
             auto term = [&](int32_t q, float av) {
                 const double d = ti - rtau[q];
                 const double e = exp_f64(-bet * d);
-                const double kq = rK[q];
+                const double2 kj = rKJ[q];
+                const double kq = kj.x;
                 double Kv = e * kq;
-                double Jv = GRAD ? e * __builtin_fma(d, kq, rJ[q]) : 0.0;
+                double Jv = GRAD ? e * __builtin_fma(d, kq, kj.y) : 0.0;
                 uint64_t bits = rmask[q] & below;
                 while (bits) {
                     const int jj = __builtin_ctzll(bits);
@@ -469,15 +469,15 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
             if (valid) {
                 uint64_t grp = rmask[mi];
                 if (__builtin_ctzll(grp) == lane) {
-                    double s0 = rK[mi], s1 = rJ[mi];
+                    const double2 kj = rKJ[mi];
+                    double s0 = kj.x, s1 = kj.y;
                     while (grp) {
                         const int j = __builtin_ctzll(grp);
                         grp &= grp - 1;
                         s0 += eb[j];
                         if (GRAD) s1 = __builtin_fma(tb[j] - tref, eb[j], s1);
                     }
-                    rK[mi] = s0;
-                    if (GRAD) rJ[mi] = s1;
+                    rKJ[mi] = make_double2(s0, s1);
                 }
             }
         } else if (valid) {
@@ -485,7 +485,8 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
             uint64_t grp = rmask[mi];
             if (__builtin_ctzll(grp) == lane) {
                 double tq = rtau[mi];
-                double kq = rK[mi], jq = rJ[mi];
+                const double2 kj = rKJ[mi];
+                double kq = kj.x, jq = kj.y;
                 while (grp) {
                     const int j = __builtin_ctzll(grp);
                     grp &= grp - 1;
@@ -496,8 +497,7 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
                     tq = tb[j];
                 }
                 rtau[mi] = tq;
-                rK[mi] = kq;
-                rJ[mi] = jq;
+                rKJ[mi] = make_double2(kq, jq);
             }
         }
         __syncthreads();
