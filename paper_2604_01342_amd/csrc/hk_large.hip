@@ -193,15 +193,31 @@ __global__ __launch_bounds__(64) void large_seg_agg(int64_t c0, int64_t c1, int3
 
 // beta_pt: per-target decays (R-form state) or nullptr (one shared decay,
 // seg_dec / gdec precomputed)
+// The thread of node 0 also writes its group's gspan/gdec and every
+// segment's seg_off/seg_offdec: the time from the event before the group to
+// the event before the segment, and its decay (shared decay beta[0]).
 __global__ __launch_bounds__(256) void large_scan_local(int32_t nseg, int32_t M, const double* __restrict__ agg,
                                  const double* __restrict__ seg_dec, const double* __restrict__ seg_span,
                                  double* __restrict__ carry_seg, double* __restrict__ gagg,
-                                 const float* __restrict__ beta_pt) {
+                                 const float* __restrict__ beta_pt, const float* __restrict__ beta,
+                                 double* __restrict__ gspan, double* __restrict__ gdec,
+                                 double* __restrict__ seg_off, double* __restrict__ seg_offdec) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int32_t ngr = (nseg + HK_SG - 1) / HK_SG;
     if (gid >= (int64_t)ngr * M) return;
     const int32_t g = (int32_t)(gid / M), q = (int32_t)(gid % M);
     const int32_t s0 = g * HK_SG, s1 = s0 + HK_SG < nseg ? s0 + HK_SG : nseg;
+    if (q == 0) {
+        const double b0 = (double)beta[0];
+        double D = 0.0;
+        for (int32_t s = s0; s < s1; ++s) {
+            seg_off[s] = D;
+            seg_offdec[s] = exp(-b0 * D);
+            D += seg_span[s];
+        }
+        gspan[g] = D;
+        gdec[g] = exp(-b0 * D);
+    }
     double K = 0.0, J = 0.0;
     const double bq = beta_pt ? (double)beta_pt[q] : 0.0;
     // the group's segment maps of node q, all loads issued up front
@@ -228,27 +244,6 @@ __global__ __launch_bounds__(256) void large_scan_local(int32_t nseg, int32_t M,
     }
     gagg[(int64_t)g * 2 * M + q] = K;
     gagg[(int64_t)g * 2 * M + M + q] = J;
-}
-
-// gdec[g], gspan[g]: decay and span of group g; seg_off[s]: time from the
-// event before s's group to the event before s, seg_offdec[s] its decay
-// (shared decay); one thread per group
-__global__ void large_scan_gdec(int32_t nseg, const double* __restrict__ seg_span, const float* __restrict__ beta,
-                                double* __restrict__ gspan, double* __restrict__ gdec, double* __restrict__ seg_off,
-                                double* __restrict__ seg_offdec) {
-    const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-    const int32_t ngr = (nseg + HK_SG - 1) / HK_SG;
-    if (g >= ngr) return;
-    const int32_t s0 = g * HK_SG, s1 = s0 + HK_SG < nseg ? s0 + HK_SG : nseg;
-    const double b0 = (double)beta[0];
-    double D = 0.0;
-    for (int32_t s = s0; s < s1; ++s) {
-        seg_off[s] = D;
-        seg_offdec[s] = exp(-b0 * D);
-        D += seg_span[s];
-    }
-    gspan[g] = D;
-    gdec[g] = exp(-b0 * D);
 }
 
 __global__ __launch_bounds__(256) void large_scan_groups(int32_t nseg, int32_t M, const double* __restrict__ gagg,
@@ -774,9 +769,8 @@ void large_scan(LargeArgs& A, int32_t nseg, const float* beta_pt, hipStream_t st
     const int32_t ngr = (nseg + HK_SG - 1) / HK_SG;
     const int64_t nloc = (int64_t)ngr * M, napp = (int64_t)nseg * M;
     hipLaunchKernelGGL(large_scan_local, dim3((unsigned)((nloc + 255) / 256)), dim3(256), 0, st, nseg, M, A.agg,
-                       A.seg_dec, A.seg_span, A.carry_seg, A.gagg, beta_pt);
-    hipLaunchKernelGGL(large_scan_gdec, dim3((unsigned)((ngr + 255) / 256)), dim3(256), 0, st, nseg, A.seg_span,
-                       A.beta, A.gspan, A.gdec, A.seg_off, A.seg_offdec);
+                       A.seg_dec, A.seg_span, A.carry_seg, A.gagg, beta_pt, A.beta, A.gspan, A.gdec, A.seg_off,
+                       A.seg_offdec);
     hipLaunchKernelGGL(large_scan_groups, dim3(gM), dim3(256), 0, st, nseg, M, A.gagg, A.gspan, A.gdec, A.gcarry,
                        A.carry, beta_pt);
     hipLaunchKernelGGL(large_scan_apply, dim3((unsigned)((napp + 255) / 256)), dim3(256), 0, st, nseg, M,
