@@ -500,12 +500,29 @@ __global__ __launch_bounds__(256) void small_compute_c(int32_t S, int64_t n_tota
     const double T = T_s[inf.s];
     const float* al = alpha + a_off[inf.s];
     const float* mus = mu + mu_off[inf.s];
+    // the item's alpha (MP x MP, zero past M) and mu in LDS, written by its
+    // LPI lanes and read by them only (the events' rows are then LDS reads
+    // instead of dependent global loads)
+    constexpr int AW = MP * MP + (MP < 4 ? 4 : MP);   // floats per item, a multiple of 4
+    __shared__ __align__(16) float ALs[4 * IPW][AW];
+    float* A_ = ALs[(threadIdx.x >> 6) * IPW + lane / LPI];
+    for (int e = c; e < AW; e += LPI) {
+        const int pr = e / MP, qc = e % MP;
+        float v = 0.0f;
+        if (e < MP * MP) {
+            if (pr < M && qc < M) v = al[pr * M + qc];
+        } else if (e - MP * MP < M) {
+            v = mus[e - MP * MP];
+        }
+        A_[e] = v;
+    }
+    __builtin_amdgcn_wave_barrier();
     double colsum[MP];
 #pragma unroll
     for (int q = 0; q < MP; ++q) {
         double cs = 0.0;
-        if (q < M)
-            for (int p = 0; p < M; ++p) cs += (double)al[p * M + q];
+#pragma unroll
+        for (int p = 0; p < MP; ++p) cs += (double)A_[p * MP + q];
         colsum[q] = cs;
     }
     double K[CL], J[CL];
@@ -584,7 +601,7 @@ __global__ __launch_bounds__(256) void small_compute_c(int32_t S, int64_t n_tota
                 const double k1 = sj * (K[u] + (qa + u == mp ? 1.0 : 0.0));
                 J[u] = __builtin_fma(sj, J[u], d * k1);
                 K[u] = k1;
-                const double a = qa + u < M ? (double)al[p * M + qa + u] : 0.0;
+                const double a = (double)A_[p * MP + qa + u];
                 R = __builtin_fma(a, K[u], R);
                 Dd = __builtin_fma(a, J[u], Dd);
             }
@@ -593,7 +610,7 @@ __global__ __launch_bounds__(256) void small_compute_c(int32_t S, int64_t n_tota
                 R += __shfl_xor(R, off, 64);
                 Dd += __shfl_xor(Dd, off, 64);
             }
-            const double lam = (double)mus[p] + bet * R;
+            const double lam = (double)A_[MP * MP + p] + bet * R;
             const double w = 1.0 / lam;
             double csp = 0.0;
 #pragma unroll
