@@ -144,6 +144,59 @@ __device__ __forceinline__ void compose(double* K, double* J, double D, double b
     }
 }
 
+// Coalesced staging of the items' events.  A wave's items are consecutive,
+// so their events are one contiguous range, but each lane walks its own
+// item: lane-strided loads would touch a cache line per lane per load.
+// Instead, in round r the wave loads event 8 r + j of each of its NI items
+// with eight lanes per item (slot v of lane l: item 8 v + l / 8, event
+// l mod 8, i.e. 64 contiguous bytes of times per item), writes them to LDS
+// as [item][8] and every lane reads its item's 8 events back.  Indices past
+// an item's last event repeat the last one, and slots of invalid items load
+// nothing, so all loads stay in range.
+template <int NI>
+struct Stage {
+    static constexpr int NV = NI / 8;   // load slots per lane
+    int64_t base;                       // the wave's first event (items are consecutive)
+    int32_t a[NV], last[NV];            // relative to base; last < 0: invalid item
+    double tv[NV];
+    int mv[NV];
+    // lane `owner(i)` holds item i's range [ia, ib)
+    template <typename F>
+    __device__ __forceinline__ void init(int lane, int64_t ia, int64_t ib, bool valid, F owner) {
+        base = (int64_t)__shfl((long long)(valid ? ia : 0), owner(0), 64);
+        base = ((int64_t)__builtin_amdgcn_readfirstlane((int)(base >> 32)) << 32) |
+               (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)base);
+        const int32_t a0 = valid ? (int32_t)(ia - base) : 0, l0 = valid ? (int32_t)(ib - 1 - base) : -1;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int src = owner(8 * v + (lane >> 3));
+            a[v] = __shfl(a0, src, 64);
+            last[v] = __shfl(l0, src, 64);
+        }
+    }
+    __device__ __forceinline__ void load(const double* __restrict__ t, const int32_t* __restrict__ marks, int lane,
+                                         int r) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            int32_t e = a[v] + 8 * r + (lane & 7);
+            e = e < last[v] ? e : last[v];
+            tv[v] = 0.0;
+            mv[v] = 0;
+            if (last[v] >= 0) {
+                tv[v] = t[base + e];
+                mv[v] = marks[base + e];
+            }
+        }
+    }
+    __device__ __forceinline__ void put(double* Ts, int* Ms, int lane) const {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            Ts[64 * v + lane] = tv[v];
+            Ms[64 * v + lane] = mv[v];
+        }
+    }
+};
+
 // ---------------------------------------------------------------- phase A
 template <int MP>
 __global__ __launch_bounds__(256) void small_agg(int32_t S, int64_t n_total, const int64_t* __restrict__ ev_off,
@@ -165,35 +218,41 @@ __global__ __launch_bounds__(256) void small_agg(int32_t S, int64_t n_total, con
     double D = 0.0;
     int reset = 1;
     double bet = 0.0;
-    if (inf.valid && inf.b > inf.a) {
-        const int32_t M = m_s[inf.s] < 1 ? 1 : (m_s[inf.s] > MP ? MP : m_s[inf.s]);
+    const bool work = inf.valid && inf.b > inf.a;
+    int32_t M = 1;
+    double tref = 0.0;
+    if (work) {
+        M = m_s[inf.s] < 1 ? 1 : (m_s[inf.s] > MP ? MP : m_s[inf.s]);
         bet = (double)beta[inf.s];
         reset = inf.k == 0;
-        const double tref = reset ? t[inf.a] : t[inf.a - 1];
-        double tp = tref;
-        int mp = -1;
-        // events in blocks of 8 per lane, the next block's loads in flight
-        // while the current one is processed (clamped indices stay valid)
-        const int64_t last = inf.b - 1;
-        double tn[8];
-        int mn[8];
+        tref = reset ? t[inf.a] : t[inf.a - 1];
+    }
+    double tp = tref;
+    int mp = -1;
+    // the wave's events in rounds of 8 per item, staged through LDS, the next
+    // round's loads in flight while the current one is processed
+    __shared__ double Tst[4][512];
+    __shared__ int Mst[4][512];
+    double* Ts = Tst[threadIdx.x >> 6];
+    int* Ms = Mst[threadIdx.x >> 6];
+    Stage<64> stg;
+    stg.init(lane, inf.a, inf.b, work, [](int i) { return i; });
+    stg.load(t, marks, lane, 0);
+    const int rounds = (L + 7) / 8;
+    for (int r = 0; r < rounds; ++r) {
+        stg.put(Ts, Ms, lane);
+        if (r + 1 < rounds) stg.load(t, marks, lane, r + 1);
+        __builtin_amdgcn_wave_barrier();
+        double tv[8];
+        int mv[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const int64_t e = inf.a + j < last ? inf.a + j : last;
-            tn[j] = t[e];
-            mn[j] = marks[e];
+            tv[j] = Ts[8 * lane + j];
+            mv[j] = Ms[8 * lane + j];
         }
-        for (int64_t e0 = inf.a; e0 < inf.b; e0 += 8) {
-            double tv[8];
-            int mv[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                tv[j] = tn[j];
-                mv[j] = mn[j];
-                const int64_t e = e0 + 8 + j < last ? e0 + 8 + j : last;
-                tn[j] = t[e];
-                mn[j] = marks[e];
-            }
+        __builtin_amdgcn_wave_barrier();
+        const int64_t e0 = inf.a + 8 * r;
+        if (work && e0 < inf.b) {
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 if (e0 + j < inf.b) {
@@ -211,6 +270,8 @@ __global__ __launch_bounds__(256) void small_agg(int32_t S, int64_t n_total, con
                 }
             }
         }
+    }
+    if (work) {
 #pragma unroll
         for (int q = 0; q < MP; ++q) K[q] += (q == mp ? 1.0 : 0.0);
         D = tp - tref;
@@ -492,9 +553,11 @@ __global__ __launch_bounds__(256) void small_compute_c(int32_t S, int64_t n_tota
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) +
                          __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int64_t it = wave * IPW + lane / LPI;
-    if (it >= n_items_cap) return;   // the whole group
+    if (wave * IPW >= n_items_cap) return;   // the whole wave (wave-uniform)
+    // every lane stays to the end (the event loads are cooperative); lanes
+    // of invalid items (sequence 0's parameters, no events) write nothing
     const ItemInfo inf = item_info(it, S, item_off, ev_off, L, n_total, n_items_cap);
-    if (!inf.valid) return;          // the whole group
+    const bool work = inf.valid;
     const int32_t M = m_s[inf.s] < 1 ? 1 : (m_s[inf.s] > MP ? MP : m_s[inf.s]);
     const double bet = (double)beta[inf.s];
     const double T = T_s[inf.s];
@@ -528,8 +591,9 @@ __global__ __launch_bounds__(256) void small_compute_c(int32_t S, int64_t n_tota
     double K[CL], J[CL];
 #pragma unroll
     for (int u = 0; u < CL; ++u) { K[u] = 0.0; J[u] = 0.0; }
-    double tp;
-    if (inf.k == 0) {
+    double tp = 0.0;
+    if (!work) {
+    } else if (inf.k == 0) {
         tp = t[inf.a];
     } else {
         tp = t[inf.a - 1];
@@ -563,23 +627,39 @@ __global__ __launch_bounds__(256) void small_compute_c(int32_t S, int64_t n_tota
         for (int r = 0; r < MP; ++r) Gc[r][u] = 0.0;
     }
     int mp = -1;
-    const int64_t last = inf.b - 1;
-    auto ld = [&](int64_t e) { return e < last ? e : last; };
-    for (int64_t e0 = inf.a; e0 < inf.b; e0 += NB) {
+    // the items' events in rounds of NB, staged through LDS (coalesced
+    // loads), the next round's loads in flight while one is processed
+    static_assert(NB == 8, "rounds of the staging are 8 events");
+    __shared__ double Tst[4][IPW * 8];
+    __shared__ int Mst[4][IPW * 8];
+    double* Ts = Tst[threadIdx.x >> 6];
+    int* Ms = Mst[threadIdx.x >> 6];
+    Stage<IPW> stg;
+    stg.init(lane, inf.a, inf.b, work, [](int i) { return i * LPI; });
+    stg.load(t, marks, lane, 0);
+    const int rounds = (L + NB - 1) / NB;
+    for (int rd = 0; rd < rounds; ++rd) {
+        stg.put(Ts, Ms, lane);
+        if (rd + 1 < rounds) stg.load(t, marks, lane, rd + 1);
+        __builtin_amdgcn_wave_barrier();
         double tv[NB];
         int mv[NB];
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
-            tv[j] = t[ld(e0 + j)];
-            mv[j] = marks[ld(e0 + j)];
+            tv[j] = Ts[8 * (lane / LPI) + j];
+            mv[j] = Ms[8 * (lane / LPI) + j];
         }
-        // this lane's events of the block: j = c + LPI o
+        __builtin_amdgcn_wave_barrier();
+        const int64_t e0 = inf.a + (int64_t)NB * rd;
+        if (!work || e0 >= inf.b) continue;
+        // this lane's events of the block: j = c + LPI o (past the item's
+        // end the staged values repeat its last event and are not used)
         double so[NO], xo[NO];
 #pragma unroll
         for (int o = 0; o < NO; ++o) {
             const int j = c + LPI * o;
-            const double tj = t[ld(e0 + j)];
-            const double tjm = j == 0 ? tp : t[ld(e0 + j - 1)];
+            const double tj = tv[j];
+            const double tjm = j == 0 ? tp : tv[j - 1];
             so[o] = exp_f64(-bet * (tj - tjm));
             xo[o] = exp_f64(-bet * (T - tj));
         }
@@ -646,6 +726,7 @@ __global__ __launch_bounds__(256) void small_compute_c(int32_t S, int64_t n_tota
         te2 += __shfl(Esum, g0 + i, 64);
         tg += __shfl(gbs, g0 + i, 64);
     }
+    if (!work) return;
     double* o = part + it * (int64_t)PW;
     if (c == 0) {
         o[0] = tl;
