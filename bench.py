@@ -44,7 +44,7 @@ def source_hash(*names) -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(src_hash: str):
+def load_traffic(src_hash: str, tuning=None):
     """HBM bytes per dense-kernel launch from committed rocprofv3 counter runs,
     or None when absent or taken on a different kernel source."""
     path = os.path.join(ROOT, "profiles", "dense_dalpha_c4_traffic.json")
@@ -54,7 +54,25 @@ def load_traffic(src_hash: str):
         d = json.load(f)
     if d.get("source_sha256") != src_hash:
         return None
+    if tuning is not None and d.get("tuning", {}) != tuning:
+        return None
     return d
+
+
+def _autotune(args, tune):
+    """Apply the autotuner's choice (outside the timed region) and return the
+    launch tuning in effect; --no-autotune keeps the library's rules."""
+    import paper_2604_01342_amd as H
+    if args.tuning:
+        cols, ranges, item = (int(x) for x in args.tuning.split(","))
+        H.set_tuning(dense_cols=cols, dense_ranges=ranges, item_log2=item)
+    elif args.no_autotune:
+        H.set_tuning()
+    else:
+        from paper_2604_01342_amd import autotune as AT
+        r = tune(AT)
+        log(f"autotune: {r['tuning']} ({r['ms']:.3f} ms per call; library rule {r['default_ms']:.3f} ms)")
+    return H.get_tuning()
 
 
 def rel(a, b):
@@ -97,6 +115,7 @@ def run_single_other(args, name, dev):
     from paper_2604_01342_amd import workloads as W
     w = W.cached(f"{name}_full", lambda: W.make_config(int(name[1])))
     d = [torch.as_tensor(x, device=dev) for x in (w.t, w.m, w.mu, w.alpha, w.beta)]
+    tuning = _autotune(args, lambda AT: AT.tune_single(*d, w.T, args.chunk_log2, log=log))
     H.timing_reset()
     H.timing_enable(True)
     wall, per = _timed(lambda: H.loglik_grad(*d, w.T, args.chunk_log2), args.steps, args.warmup)
@@ -104,7 +123,8 @@ def run_single_other(args, name, dev):
     out = {"metric": f"events/sec for loglik+grad ({name})", "value": w.n / (wall / 1e3), "unit": "events/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-           "data": "synthetic", "config": {"workload": f"{name}: M={w.M}, N={w.n}", "n_events": w.n},
+           "data": "synthetic", "config": {"workload": f"{name}: M={w.M}, N={w.n}", "n_events": w.n,
+                                           "tuning": tuning},
            "step_device_time": {"median_ms": per[len(per) // 2], "min_ms": per[0], "max_ms": per[-1]},
            "kernels_ms_per_step": _kernels(H, args.warmup + args.steps)}
     if not args.no_cpu:
@@ -130,6 +150,7 @@ def run_c3(args, dev):
     bw = W.cached("c3_full", lambda: W.make_batched())
     b = H.Batch.from_numpy(bw)
     n = int(bw.ev_off[-1])
+    tuning = _autotune(args, lambda AT: AT.tune_batched(b, log=log))
     H.timing_reset()
     H.timing_enable(True)
     wall, per = _timed(lambda: H.loglik_grad_batched(b), args.steps, args.warmup)
@@ -139,7 +160,7 @@ def run_c3(args, dev):
     out = {"metric": "events/sec for batched loglik+grad (c3)", "value": n / (wall / 1e3), "unit": "events/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-           "data": "synthetic", "config": {"workload": "c3: 4096 sequences, M=8", "n_events": n},
+           "data": "synthetic", "config": {"workload": "c3: 4096 sequences, M=8", "n_events": n, "tuning": tuning},
            "roofline": {"kernel": "whole batched call", "bound": "hbm",
                         "achieved": round(alg / (per[len(per) // 2] * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(alg / (per[len(per) // 2] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -220,6 +241,10 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-seq", action="store_true")
     ap.add_argument("--chunk-log2", type=int, default=20)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's own launch rules instead of timing the tuning candidates first")
+    ap.add_argument("--tuning", default="",
+                    help="dense_cols,dense_ranges,item_log2 to use as given (no autotuning), e.g. 256,16,0")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (HBM counter calibration)")
     ap.add_argument("--workload", choices=["c4", "c2", "c3", "c5"], default="c4",
@@ -273,6 +298,7 @@ def main() -> int:
     al = torch.as_tensor(w.alpha, dtype=torch.float32, device=dev)
     be = torch.as_tensor(w.beta, dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
+    tuning = _autotune(args, lambda AT: AT.tune_single(t, m, mu, al, be, w.T, args.chunk_log2, log=log))
 
     def step():
         return H.loglik_grad(t, m, mu, al, be, w.T, args.chunk_log2)
@@ -311,7 +337,7 @@ def main() -> int:
         avg_ms = dense_ms / dense_n
         flops_per_launch = 2.0 * w.M * (w.n * args.steps / dense_n)
         achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
-        tr = load_traffic(src)
+        tr = load_traffic(src, tuning)
         roofline = {"kernel": "large_dense (dense dL/dalpha)", "bound": "alu", "achieved": round(achieved, 3),
                     "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
@@ -325,7 +351,7 @@ def main() -> int:
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "c4: M=1000, N=1e7, alpha 1% dense rho=0.8, beta=1, chunks of 2^20",
-                      "n_events": w.n, "n_nodes": w.M, "chunk_log2": args.chunk_log2},
+                      "n_events": w.n, "n_nodes": w.M, "chunk_log2": args.chunk_log2, "tuning": tuning},
            "roofline": roofline, "step_device_time": step_stats, "kernels_ms_per_step": kernels}
 
     # sequential-recurrence GPU kernel on a prefix

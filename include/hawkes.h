@@ -67,7 +67,7 @@
 extern "C" {
 #endif
 
-#define HAWKES_ABI_VERSION 1
+#define HAWKES_ABI_VERSION 2
 
 typedef enum hawkes_status {
     HAWKES_OK = 0,
@@ -96,6 +96,41 @@ typedef struct hawkes_problem {
     int32_t chunk_log2;  /* 0 = default */
     double  T;           /* window end, >= 0 and >= t[n-1] */
 } hawkes_problem;
+
+/* Launch parameters that an autotuner may choose; 0 keeps the library's own
+ * rule.  They change how the work is laid out, never what is computed:
+ * results agree to rounding whatever the values.  Process-wide:
+ * hawkes_set_tuning() applies to every later call, the workspace queries
+ * included, whose sizes depend on it (query again after changing it; a call
+ * whose workspace was sized under other values returns HAWKES_EWORKSPACE if
+ * it is too small).  Set it between calls, not while calls run on other
+ * threads.  Intended for callers that time candidate values on their own
+ * inputs, as the Python package's autotuner does.
+ *   dense_cols    shared-decay large-M engine: width in nodes of the tiles of
+ *                 the dense dL/dalpha kernel: 64, 128 or 256 (128 needs
+ *                 chunk_log2 <= 25 and 256 <= 24; otherwise the library's
+ *                 rule applies)
+ *   dense_ranges  the same kernel: event ranges per chunk, each with its own
+ *                 partial sums: a power of two, 1..4096 (fewer if a chunk
+ *                 has fewer segments)
+ *   item_log2     small-M engine: log2 of the events per lane item, 4..16; a
+ *                 value too small for the engine's bound on the item count
+ *                 (and so on its workspace) is raised to the smallest that
+ *                 fits */
+typedef struct hawkes_tuning {
+    int32_t dense_cols;
+    int32_t dense_ranges;
+    int32_t item_log2;
+    int32_t reserved;   /* must be 0 */
+} hawkes_tuning;
+
+/* Replace the process-wide tuning (NULL: all zero, the library's rules).
+ * HAWKES_EINVAL for a value outside the ranges above; the tuning is then
+ * unchanged. */
+hawkes_status hawkes_set_tuning(const hawkes_tuning* t);
+
+/* Copy the current tuning to *t.  HAWKES_EINVAL if t is NULL. */
+hawkes_status hawkes_get_tuning(hawkes_tuning* t);
 
 /* Human-readable name of a status code (static storage). */
 const char* hawkes_status_string(hawkes_status s);

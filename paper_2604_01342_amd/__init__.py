@@ -46,6 +46,11 @@ class _Problem(ctypes.Structure):
                 ("beta_mode", ctypes.c_int32), ("chunk_log2", ctypes.c_int32), ("T", ctypes.c_double)]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("dense_cols", ctypes.c_int32), ("dense_ranges", ctypes.c_int32), ("item_log2", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 class _Adam(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
                 ("eps", ctypes.c_float), ("floor_mu", ctypes.c_float), ("floor_beta", ctypes.c_float)]
@@ -81,6 +86,10 @@ def lib():
     L.hawkes_loglik_batched.argtypes = [i32, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.hawkes_loglik_grad_batched.argtypes = [i32, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                              sz, vp]
+    L.hawkes_set_tuning.argtypes = [ctypes.POINTER(_Tuning)]
+    L.hawkes_get_tuning.argtypes = [ctypes.POINTER(_Tuning)]
+    L.hawkes_set_tuning.restype = ctypes.c_int
+    L.hawkes_get_tuning.restype = ctypes.c_int
     L.hawkes_timing_enable.argtypes = [ctypes.c_int]
     L.hawkes_timing_read.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     for f in ("hawkes_timing_enable", "hawkes_timing_reset", "hawkes_timing_read"):
@@ -146,6 +155,21 @@ def _problem(t, mu, beta, T, chunk_log2):
     if mode == BETA_PER_TARGET and beta.numel() != M:
         raise ValueError("beta must have 1 or M entries")
     return _Problem(t.numel(), M, 1, mode, int(chunk_log2), float(T))
+
+
+def set_tuning(dense_cols: int = 0, dense_ranges: int = 0, item_log2: int = 0) -> None:
+    """Process-wide launch tuning (hawkes_set_tuning): 0 keeps the library's
+    rule.  dense_cols in {64, 128, 256}, dense_ranges a power of two up to
+    4096, item_log2 in 4..16.  Results agree to rounding whatever the values."""
+    t = _Tuning(int(dense_cols), int(dense_ranges), int(item_log2), 0)
+    _check("hawkes_set_tuning", lib().hawkes_set_tuning(ctypes.byref(t)))
+
+
+def get_tuning() -> dict:
+    """The current process-wide launch tuning (hawkes_get_tuning)."""
+    t = _Tuning()
+    _check("hawkes_get_tuning", lib().hawkes_get_tuning(ctypes.byref(t)))
+    return {"dense_cols": t.dense_cols, "dense_ranges": t.dense_ranges, "item_log2": t.item_log2}
 
 
 def workspace_bytes(n: int, M: int, per_target: bool = False, grad: bool = True, chunk_log2: int = 0) -> int:

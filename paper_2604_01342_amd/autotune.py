@@ -1,0 +1,168 @@
+"""Autotuner for the library's launch parameters (hawkes_set_tuning).
+
+For a problem shape it times each candidate setting on the caller's own
+inputs (a few calls each, device time from HIP events on the current
+stream), checks that every candidate reproduces the default setting's
+log-likelihood to rounding, keeps the fastest, applies it with
+``set_tuning`` and stores it in a JSON cache keyed by the device and a shape
+class, so that later processes skip the timing.
+
+Knobs (see include/hawkes.h):
+  dense_cols, dense_ranges   the shared-decay large-M engine (M > 8): tile width
+                             of the dense dL/dalpha kernel and its event ranges
+  item_log2                  the small-M engine (M <= 8, single or batched):
+                             events per lane item
+
+The per-target engine has no knobs.  The cache file is
+$HAWKES_TUNE_CACHE, else ~/.cache/paper_2604_01342_amd/tuning.json.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from typing import Callable, Iterable
+
+import torch
+
+from . import Batch, get_tuning, loglik_grad, loglik_grad_batched, set_tuning
+
+TOL = 1e-9   # candidates must agree with the default setting to rounding
+
+
+def cache_path() -> str:
+    return os.environ.get("HAWKES_TUNE_CACHE") or os.path.join(
+        os.path.expanduser("~"), ".cache", "paper_2604_01342_amd", "tuning.json")
+
+
+def _device_key(dev) -> str:
+    p = torch.cuda.get_device_properties(dev)
+    return f"{p.name}|{getattr(p, 'gcnArchName', '')}|{p.multi_processor_count}"
+
+
+def _bucket(x: int) -> int:
+    return int(math.floor(math.log2(max(1, x))))
+
+
+def shape_class_single(n: int, M: int, per_target: bool, chunk_log2: int) -> str:
+    """Shapes that share a setting: M and n by powers of two, the decay mode,
+    the chunk size (it bounds the dense tile width)."""
+    return f"single|M{_bucket(M)}|n{_bucket(n)}|pt{int(per_target)}|ch{chunk_log2 or 20}"
+
+
+def shape_class_batched(S: int, n_total: int, max_m: int) -> str:
+    return f"batched|S{_bucket(S)}|n{_bucket(n_total)}|M{_bucket(max_m)}"
+
+
+def candidates_single(n: int, M: int, per_target: bool, chunk_log2: int) -> list[dict]:
+    lg = chunk_log2 or 20
+    if per_target:
+        return [{}]
+    if M <= 8:
+        return [{"item_log2": k} for k in range(4, 11)]
+    cols = [c for c in (64, 128, 256) if c <= max(64, 2 * M) and (c < 128 or lg <= (25 if c == 128 else 24))]
+    return [{"dense_cols": c, "dense_ranges": r} for c in cols for r in (4, 8, 16, 32, 64)]
+
+
+def candidates_batched(n_total: int) -> list[dict]:
+    return [{"item_log2": k} for k in range(5, 12)]
+
+
+def _load() -> dict:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(cache: dict) -> None:
+    path = cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = f"{path}.tmp{os.getpid()}"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def _time_ms(fn: Callable[[], object], reps: int) -> float:
+    fn()   # warm (and size the workspace)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b))
+    return best
+
+
+def _search(key: str, cands: Iterable[dict], run: Callable[[], float], reps: int, use_cache: bool,
+            log: Callable[[str], None] | None) -> dict:
+    dev = torch.cuda.current_device()
+    dkey = _device_key(dev)
+    cache = _load() if use_cache else {}
+    hit = cache.get(dkey, {}).get(key)
+    if hit is not None:
+        set_tuning(**hit["tuning"])
+        return hit
+    set_tuning()
+    ref = run()
+    results = []
+    for c in cands:
+        set_tuning(**c)
+        got = run()
+        if not math.isfinite(got) or abs(got - ref) > TOL * max(1.0, abs(ref)):
+            raise RuntimeError(f"tuning {c} changed the log-likelihood: {got!r} vs {ref!r}")
+        ms = _time_ms(run, reps)
+        results.append((ms, c))
+        if log:
+            log(f"tune {key}: {c} {ms:.3f} ms")
+    set_tuning()
+    base_ms = _time_ms(run, reps)
+    ms, best = min(results, key=lambda r: r[0])
+    if base_ms <= ms:
+        ms, best = base_ms, {}
+    out = {"tuning": {"dense_cols": best.get("dense_cols", 0), "dense_ranges": best.get("dense_ranges", 0),
+                      "item_log2": best.get("item_log2", 0)},
+           "ms": ms, "default_ms": base_ms}
+    set_tuning(**out["tuning"])
+    if use_cache:
+        cache.setdefault(dkey, {})[key] = out
+        _store(cache)
+    return out
+
+
+def tune_single(t, m, mu, alpha, beta, T, chunk_log2: int = 0, reps: int = 3, use_cache: bool = True,
+                log: Callable[[str], None] | None = None) -> dict:
+    """Choose and apply the setting for loglik_grad on this sequence; returns
+    {"tuning": ..., "ms": best time per call, "default_ms": the library's own
+    rule}.  The inputs must be on the GPU."""
+    M = int(mu.numel())
+    per_target = int(beta.numel()) == M and M > 1
+    n = int(t.numel())
+    key = shape_class_single(n, M, per_target, chunk_log2)
+
+    def run() -> float:
+        return float(loglik_grad(t, m, mu, alpha, beta, T, chunk_log2)[0].item())
+
+    return _search(key, candidates_single(n, M, per_target, chunk_log2), run, reps, use_cache, log)
+
+
+def tune_batched(b: Batch, reps: int = 3, use_cache: bool = True,
+                 log: Callable[[str], None] | None = None) -> dict:
+    """Choose and apply the item length for loglik_grad_batched on this batch."""
+    n_total = int(b.t.numel())
+    key = shape_class_batched(b.S, n_total, b.max_m)
+
+    def run() -> float:
+        return float(loglik_grad_batched(b)[0].double().sum().item())
+
+    return _search(key, candidates_batched(n_total), run, reps, use_cache, log)
+
+
+def current() -> dict:
+    return get_tuning()

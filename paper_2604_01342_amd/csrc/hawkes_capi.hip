@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
+#include <mutex>
 #include "hk_device.h"
 #include "hk_internal.h"
 #include "hk_large.h"
@@ -10,6 +11,14 @@
 using namespace hk;
 
 namespace hk {
+
+static std::mutex g_tuning_mu;
+static hawkes_tuning g_tuning = {0, 0, 0, 0};
+
+hawkes_tuning tuning_snapshot() {
+    std::lock_guard<std::mutex> g(g_tuning_mu);
+    return g_tuning;
+}
 
 static int32_t pow2_at_least(int32_t m) {
     int32_t p = 1;
@@ -39,6 +48,12 @@ size_t small_layout(SmallArgs& A, int32_t S, int64_t n_total, int32_t max_m, boo
     const int64_t target_items = single ? 65536 : 262144;
     while (L < 4096 && n_total / L > target_items) L <<= 1;
     if (n_total / L > target_items) L = (n_total + target_items - 1) / target_items;
+    // a tuned item length replaces this one unless it breaks the item bound
+    const hawkes_tuning tu = tuning_snapshot();
+    if (tu.item_log2 > 0) {
+        const int64_t Lt = (int64_t)1 << tu.item_log2;
+        if (Lt >= L || n_total / Lt <= target_items) L = Lt;
+    }
     A.L = (int32_t)L;
     A.n_total = n_total;
     A.n_items_cap = n_total / L + S + 1;
@@ -95,6 +110,27 @@ const char* hawkes_status_string(hawkes_status s) {
 }
 
 int hawkes_version(void) { return HAWKES_ABI_VERSION; }
+
+hawkes_status hawkes_set_tuning(const hawkes_tuning* t) {
+    hawkes_tuning v = {0, 0, 0, 0};
+    if (t) {
+        v = *t;
+        const bool cols_ok = v.dense_cols == 0 || v.dense_cols == 64 || v.dense_cols == 128 || v.dense_cols == 256;
+        const bool er_ok = v.dense_ranges == 0 ||
+                           (v.dense_ranges >= 1 && v.dense_ranges <= 4096 && (v.dense_ranges & (v.dense_ranges - 1)) == 0);
+        const bool item_ok = v.item_log2 == 0 || (v.item_log2 >= 4 && v.item_log2 <= 16);
+        if (!cols_ok || !er_ok || !item_ok || v.reserved != 0) return HAWKES_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(g_tuning_mu);
+    g_tuning = v;
+    return HAWKES_OK;
+}
+
+hawkes_status hawkes_get_tuning(hawkes_tuning* t) {
+    if (!t) return HAWKES_EINVAL;
+    *t = tuning_snapshot();
+    return HAWKES_OK;
+}
 
 size_t hawkes_workspace_bytes(const hawkes_problem* p, int with_grad) {
     if (!problem_ok(p) || p->k != 1) return 0;

@@ -563,10 +563,9 @@ static void dense_launch_t(LargeArgs& A, int64_t c0, int32_t nev, int32_t nseg, 
 void large_dense_launch(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, hipStream_t st) {
     const int32_t nrun_c = (nseg + A.CKR - 1) / A.CKR;
     const int32_t nev = (int32_t)(c1 - c0);
-    // the tiles the layout selects: 16 x 256, 8 x 256, 16 x 128, 16 x 64
+    // the tiles the layout selects: 16 x 256, 16 x 128, 16 x 64
     if (A.CPL == 4)
-        A.DRB == 3 ? dense_launch_t<4, 3>(A, c0, nev, nseg, nrun_c, st)
-                   : dense_launch_t<4, 4>(A, c0, nev, nseg, nrun_c, st);
+        dense_launch_t<4, 4>(A, c0, nev, nseg, nrun_c, st);
     else if (A.CPL == 2)
         dense_launch_t<2, 4>(A, c0, nev, nseg, nrun_c, st);
     else

@@ -59,6 +59,9 @@ struct TimedScope {
     ~TimedScope() { timing_end(h, st); }
 };
 
+// the process-wide launch tuning (hawkes_set_tuning), copied under a lock
+hawkes_tuning tuning_snapshot();
+
 // carve the small-engine workspace; returns bytes needed (A gets pointers when ws != nullptr)
 size_t small_layout(SmallArgs& A, int32_t S, int64_t n_total, int32_t max_m, bool grad, void* ws,
                     size_t ws_bytes, bool single);

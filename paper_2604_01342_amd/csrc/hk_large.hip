@@ -602,26 +602,23 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
     A.nchunks = (A.n + A.CH - 1) / A.CH;
     A.nseg = (int32_t)((A.CH + HK_SEG - 1) / HK_SEG);
     A.NB = (A.M + 63) / 64;
-    // shared decay: tiles of DR = 2^DRB rows x W = 64 CPL columns.  Every
-    // own event is visited once per column block (a pair-term instruction
-    // each), every window once per row block (state loads and the rank-1
-    // update), and G takes DR CPL float64 registers per lane: 16 x 256 is the
-    // fastest that fits (two waves per SIMD), with 16 x 128 and 16 x 64 for the
+    // shared decay: tiles of DR = 16 rows x W = 64 CPL columns.  Every own
+    // event is visited once per column block (a pair-term instruction each),
+    // every window once per row block (state loads and the rank-1 update),
+    // and G takes 16 CPL float64 registers per lane: 16 x 256 is the fastest
+    // that fits (two waves per SIMD), with 16 x 128 and 16 x 64 for the
     // longer chunks, since a column record key holds the event index above
-    // log2(W) bits.  HAWKES_DENSE_CPL / HAWKES_DENSE_DRB select another built
-    // tile (8 x 256 among them) for tests.
+    // log2(W) bits, and no wider than the nodes need.  A tuned width
+    // (hawkes_set_tuning) replaces the rule where the chunk allows it.
+    const hawkes_tuning tu = tuning_snapshot();
     A.CPL = A.per_target ? 1 : lg <= 24 ? 4 : lg <= 25 ? 2 : 1;
-    while (A.CPL > 1 && 32 * A.CPL >= A.M) A.CPL >>= 1;   // no wider than the nodes need
-    A.DRB = 4;
-    if (const char* e = getenv("HAWKES_DENSE_CPL")) {
-        const int v = atoi(e);
+    while (A.CPL > 1 && 32 * A.CPL >= A.M) A.CPL >>= 1;
+    if (!A.per_target && tu.dense_cols > 0) {
+        const int v = tu.dense_cols / 64;
         const int vlg = v == 4 ? 24 : v == 2 ? 25 : 26;
-        if (!A.per_target && (v == 1 || v == 2 || v == 4) && lg <= vlg) A.CPL = v;
+        if (lg <= vlg) A.CPL = v;
     }
-    if (const char* e = getenv("HAWKES_DENSE_DRB")) {
-        const int v = atoi(e);
-        if (!A.per_target && (v == 4 || (v == 3 && A.CPL == 4))) A.DRB = v;
-    }
+    A.DRB = 4;
     A.NBR = A.per_target ? A.NB : (A.M + (1 << A.DRB) - 1) >> A.DRB;
     A.NBC = A.per_target ? A.NB : (A.M + 64 * A.CPL - 1) / (64 * A.CPL);
     // event ranges per chunk for the dense kernel: a power of two so that the
@@ -629,16 +626,13 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
     // (shared decay: two waves each, 18 KiB of LDS per group, so that several
     // rounds balance the waves' uneven work) or 2048 (per target, 34 KiB;
     // 16 x 256 tiles, 34 KiB and two waves per SIMD: measured best at c4's
-    // size) unless HAWKES_DENSE_ER (a power of two) overrides it
+    // size) unless the tuning (hawkes_set_tuning) sets it
     const int64_t nbb = (int64_t)A.NBR * A.NBC;
     const int64_t target = A.per_target || A.CPL == 4 ? 2048 : 4096;
     const int64_t want = (target + nbb - 1) / nbb;
     int32_t er = 1;
     while (er < want) er <<= 1;
-    if (const char* e = getenv("HAWKES_DENSE_ER")) {
-        const int v = atoi(e);
-        if (v >= 1 && v <= 4096 && (v & (v - 1)) == 0) er = v;
-    }
+    if (tu.dense_ranges > 0) er = tu.dense_ranges;
     while (er > A.nseg && er > 1) er >>= 1;
     // shared decay: every wave of a dense workgroup gets at least one run
     while (!A.per_target && er > 1 && A.nseg / er < HK_DW) er >>= 1;

@@ -30,7 +30,8 @@ def test_header_declares_expected_api():
     for f in ("hawkes_loglik", "hawkes_loglik_grad", "hawkes_loglik_batched", "hawkes_loglik_grad_batched",
               "hawkes_workspace_bytes", "hawkes_batched_workspace_bytes", "hawkes_sequential_loglik_grad",
               "hawkes_intensity", "hawkes_check_inputs", "hawkes_status_string", "hawkes_version",
-              "hawkes_adam_state_bytes", "hawkes_adam_init", "hawkes_adam_step"):
+              "hawkes_adam_state_bytes", "hawkes_adam_init", "hawkes_adam_step", "hawkes_set_tuning",
+              "hawkes_get_tuning"):
         assert f in names
 
 
@@ -42,7 +43,7 @@ def test_library_exports_every_declared_symbol(H):
 
 def test_version_and_status_strings(H):
     L = H.lib()
-    assert L.hawkes_version() == 1
+    assert L.hawkes_version() == 2
     for s in range(5):
         assert L.hawkes_status_string(s)
     assert L.hawkes_status_string(2) == b"workspace missing or too small"
@@ -65,6 +66,47 @@ def test_workspace_query_rejects_bad_problems(H):
     assert L.hawkes_batched_workspace_bytes(4, -1, 4, 1) == 0
     assert L.hawkes_batched_workspace_bytes(4, 10, 9, 1) == 0
     assert L.hawkes_batched_workspace_bytes(4, 10, 8, 1) > 0
+
+
+def test_tuning_round_trip_and_validation(H):
+    # the launch tuning is host state: set, read back, reject bad values
+    # (leaving the tuning unchanged), reset
+    try:
+        H.set_tuning(dense_cols=128, dense_ranges=8, item_log2=7)
+        assert H.get_tuning() == {"dense_cols": 128, "dense_ranges": 8, "item_log2": 7}
+        for bad in ({"dense_cols": 96}, {"dense_cols": 512}, {"dense_ranges": 3}, {"dense_ranges": 8192},
+                    {"item_log2": 3}, {"item_log2": 17}, {"dense_ranges": -2}):
+            with pytest.raises(H.HawkesError) as e:
+                H.set_tuning(**bad)
+            assert e.value.status == 1
+            assert H.get_tuning() == {"dense_cols": 128, "dense_ranges": 8, "item_log2": 7}
+        L = H.lib()
+        assert L.hawkes_get_tuning(None) == 1
+    finally:
+        H.set_tuning()
+    assert H.get_tuning() == {"dense_cols": 0, "dense_ranges": 0, "item_log2": 0}
+
+
+def test_tuning_changes_the_workspace_layout(H):
+    # the workspace follows the tuning (the dense kernel's checkpoint slots
+    # hold 64 x cols + 104 words; the small engine's items depend on their
+    # length), and zero restores the library's rule
+    try:
+        base = H.workspace_bytes(3_000_000, 1000, grad=True)
+        H.set_tuning(dense_cols=64)
+        narrow = H.workspace_bytes(3_000_000, 1000, grad=True)
+        H.set_tuning(dense_cols=256)
+        wide = H.workspace_bytes(3_000_000, 1000, grad=True)
+        assert narrow < wide and wide == base
+        H.set_tuning()
+        s0 = H.workspace_bytes(200_000, 5, grad=True)
+        H.set_tuning(item_log2=8)
+        s1 = H.workspace_bytes(200_000, 5, grad=True)
+        assert s1 < s0   # items of 256 events instead of 16: fewer of them
+        H.set_tuning()
+        assert H.workspace_bytes(3_000_000, 1000, grad=True) == base
+    finally:
+        H.set_tuning()
 
 
 def test_workspace_is_constant_in_n_for_large_m(H):

@@ -87,33 +87,34 @@ def test_large_engine_matches_oracle(H, seed, n, M, density, ties, chunk):
     check(run_gpu(H, t, m, mu, alpha, beta, T, chunk), ref, label=f"large n={n} M={M} chunk={chunk}")
 
 
-@pytest.mark.parametrize("cpl,drb,er,chunk", [("1", "", "", 0), ("1", "", "2", 12), ("2", "", "", 0),
-                                               ("2", "", "2", 12), ("", "", "1", 0), ("", "", "2", 12),
-                                               ("", "", "64", 0), ("", "", "1024", 0), ("4", "3", "", 0),
-                                               ("4", "3", "2", 12)])
-def test_dense_layouts_match_oracle(H, cpl, drb, er, chunk):
-    # the dense dL/dalpha kernel's tile (DR rows x 64 CPL columns) and
-    # event-range count change its run, slot and workgroup layout, never the
-    # result
-    import os
+@pytest.mark.parametrize("cols,ranges,chunk", [(64, 0, 0), (64, 2, 12), (128, 0, 0), (128, 2, 12), (0, 1, 0),
+                                              (0, 2, 12), (0, 64, 0), (0, 1024, 0), (256, 0, 0), (256, 8, 12)])
+def test_dense_layouts_match_oracle(H, cols, ranges, chunk):
+    # the dense dL/dalpha kernel's tile width (64, 128 or 256 nodes, set
+    # through the launch tuning) and event-range count change its run, slot
+    # and workgroup layout, never the result
     t, m, mu, alpha, beta, T = rand_problem(17, 30000, 200, density=0.1, rate=40.0)
     ref = oracle.forward(t, m, mu, alpha, beta, T)
-    keys = ("HAWKES_DENSE_CPL", "HAWKES_DENSE_DRB", "HAWKES_DENSE_ER")
-    old = {k: os.environ.get(k) for k in keys}
     try:
-        for k, v in zip(keys, (cpl, drb, er)):
-            if v:
-                os.environ[k] = v
-            else:
-                os.environ.pop(k, None)
+        H.set_tuning(dense_cols=cols, dense_ranges=ranges)
         got = run_gpu(H, t, m, mu, alpha, beta, T, chunk)
     finally:
-        for k, v in old.items():
-            if v is None:
-                os.environ.pop(k, None)
-            else:
-                os.environ[k] = v
-    check(got, ref, label=f"dense layout cpl={cpl or 'auto'} drb={drb or 'auto'} er={er or 'auto'} chunk={chunk}")
+        H.set_tuning()
+    check(got, ref, label=f"dense layout cols={cols or 'auto'} ranges={ranges or 'auto'} chunk={chunk}")
+
+
+@pytest.mark.parametrize("item_log2", [4, 6, 9, 12])
+def test_small_item_lengths_match_oracle(H, item_log2):
+    # the small-M engine's events per lane item (launch tuning) change its
+    # item, tile and reduction layout, never the result
+    t, m, mu, alpha, beta, T = rand_problem(5, 20000, 6, ties=True, rate=3.0)
+    ref = oracle.forward(t, m, mu, alpha, beta, T)
+    try:
+        H.set_tuning(item_log2=item_log2)
+        got = run_gpu(H, t, m, mu, alpha, beta, T)
+    finally:
+        H.set_tuning()
+    check(got, ref, label=f"small item_log2={item_log2}")
 
 
 def test_chunk_size_invariance(H):
