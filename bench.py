@@ -155,6 +155,9 @@ def run_c3(args, dev):
     H.timing_enable(True)
     wall, per = _timed(lambda: H.loglik_grad_batched(b), args.steps, args.warmup)
     H.timing_enable(False)
+    # the same call captured in a HIP graph and replayed
+    gr = H.BatchedGraph(b)
+    gwall, gper = _timed(gr.replay, args.steps, args.warmup)
     # algorithmic HBM bytes: times and marks read twice (aggregate pass, evaluation pass)
     alg = 24.0 * n
     out = {"metric": "events/sec for batched loglik+grad (c3)", "value": n / (wall / 1e3), "unit": "events/s",
@@ -166,6 +169,8 @@ def run_c3(args, dev):
                         "unit": "GB/s", "frac": round(alg / (per[len(per) // 2] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                         "traffic": None, "bytes_per_event": 24},
            "step_device_time": {"median_ms": per[len(per) // 2], "min_ms": per[0], "max_ms": per[-1]},
+           "hip_graph": {"ms_per_step": gwall, "median_ms": gper[len(gper) // 2],
+                         "events_per_s": n / (gwall / 1e3)},
            "kernels_ms_per_step": _kernels(H, args.warmup + args.steps)}
     if not args.no_cpu:
         ll = H.loglik_grad_batched(b)[0].cpu().numpy()

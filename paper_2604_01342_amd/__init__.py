@@ -341,6 +341,35 @@ def loglik_grad_batched(b: Batch, out=None):
     return _batched(b, True, out)
 
 
+class BatchedGraph:
+    """One batched loglik+grad call recorded in a HIP graph, then replayed.
+
+    Every replay reads the batch's device arrays in place (new values of the
+    same shapes written into them are picked up) and writes the same output
+    tensors, ``out``.  The launch tuning in effect at capture is baked in:
+    capture again after changing it."""
+
+    def __init__(self, b: Batch):
+        self.b = b
+        dev = b.t.device
+        self.out = (torch.empty(b.S, dtype=torch.float64, device=dev),
+                    torch.empty(b.mu.numel(), dtype=torch.float64, device=dev),
+                    torch.empty(b.alpha.numel(), dtype=torch.float64, device=dev),
+                    torch.empty(b.S, dtype=torch.float64, device=dev))
+        # an eager call first: loads the library, sizes the workspace and sets
+        # kernel attributes, so that nothing allocates during capture
+        _batched(b, True, self.out)
+        torch.cuda.synchronize(dev)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            _batched(b, True, self.out)
+
+    def replay(self):
+        """(loglik[S], g_mu, g_alpha, g_beta[S]) of the batch's current values."""
+        self.graph.replay()
+        return self.out
+
+
 class HawkesLogLik(torch.autograd.Function):
     """L(mu, alpha, beta) for a fixed event sequence.  When any parameter
     needs a gradient, forward runs the fused log-likelihood + gradient call

@@ -243,6 +243,31 @@ def test_batched_matches_oracle_per_sequence(H):
     print(f"batched worst {worst:.2e}")
 
 
+def test_batched_graph_replays_equal_eager_calls(H):
+    # the batched call captured in a HIP graph: every replay (with eager
+    # calls and synchronizations between them) gives the eager result bit
+    # for bit, and values written into the batch in place are picked up
+    import torch
+    bw = _batch(20, 4000, seed=5)
+    b = H.Batch.from_numpy(bw)
+    eager = [x.clone() for x in H.loglik_grad_batched(b)]
+    g = H.BatchedGraph(b)
+    for _ in range(3):
+        H.loglik_grad_batched(b)
+        torch.cuda.synchronize()
+        got = g.replay()
+        torch.cuda.synchronize()
+        for x, e in zip(got, eager):
+            assert torch.equal(x, e)
+    b.mu.mul_(1.1)
+    eager2 = [x.clone() for x in H.loglik_grad_batched(b)]
+    got = g.replay()
+    torch.cuda.synchronize()
+    for x, e in zip(got, eager2):
+        assert torch.equal(x, e)
+    assert not torch.equal(eager2[0], eager[0])
+
+
 def test_batched_equals_single_calls(H):
     import torch
     bw = _batch(12, 5000, seed=77)
