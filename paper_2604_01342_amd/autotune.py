@@ -76,13 +76,18 @@ def _load() -> dict:
         return {}
 
 
-def _store(cache: dict) -> None:
+def _store(cache: dict) -> bool:
+    """Write the cache; False (and no cache) where the path is not writable."""
     path = cache_path()
-    os.makedirs(os.path.dirname(path), exist_ok=True)
-    tmp = f"{path}.tmp{os.getpid()}"
-    with open(tmp, "w") as f:
-        json.dump(cache, f, indent=1, sort_keys=True)
-    os.replace(tmp, path)
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = f"{path}.tmp{os.getpid()}"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+        return True
+    except OSError:
+        return False
 
 
 def _time_ms(fn: Callable[[], object], reps: int) -> float:
