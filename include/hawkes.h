@@ -248,9 +248,13 @@ hawkes_status hawkes_check_inputs(const hawkes_problem* p,
 
 /* ----------------------------------------------------------------------------
  * Diagnostics: per-kernel device timing.  While enabled, every call records a
- * pair of hipEvents on its stream around each launch of the library's main
- * kernels; hawkes_timing_read waits for those events and returns the summed
- * milliseconds and the number of launches of one kernel.  Kernel ids:
+ * pair of hipEvents on its stream around each launch of the selected kernels;
+ * hawkes_timing_read waits for those events and returns the summed
+ * milliseconds and the number of launches of one kernel.
+ * hawkes_timing_enable(on): 0 stops recording, a negative value selects every
+ * kernel, a positive value is a bit mask of kernel ids (bit k: kernel k), so
+ * that a caller can time one kernel without the others' bookkeeping.  Kernel
+ * ids:
  *   0 dense dL/dalpha (large-M engine)   1 forward scan (large-M engine)
  *   2 segment aggregates (large-M)       3 segment carry scan (large-M)
  *   4 per-item evaluation (small-M)      5 small-M aggregates and scans

@@ -243,9 +243,18 @@ TIMING_KERNELS = {0: "dense_dalpha", 1: "forward", 2: "segment_aggregate", 3: "s
                   4: "small_compute", 5: "small_scan", 6: "bucket", 7: "dense_checkpoints"}
 
 
-def timing_enable(on: bool = True) -> None:
-    """Record hipEvents around the library's main kernels (diagnostics)."""
-    _check("hawkes_timing_enable", lib().hawkes_timing_enable(int(on)))
+def timing_enable(on: bool = True, kernels=None) -> None:
+    """Record hipEvents around the library's main kernels (diagnostics):
+    every kernel, or only the ids in ``kernels`` (see TIMING_KERNELS)."""
+    if not on:
+        v = 0
+    elif kernels is None:
+        v = -1
+    else:
+        v = 0
+        for k in kernels:
+            v |= 1 << int(k)
+    _check("hawkes_timing_enable", lib().hawkes_timing_enable(v))
 
 
 def timing_reset() -> None:

@@ -12,7 +12,7 @@ struct TimedLaunch {
 };
 
 static std::mutex g_mu;
-static bool g_on = false;
+static uint32_t g_mask = 0;   // kernels whose launches are timed
 static std::vector<TimedLaunch> g_pending;
 static double g_ms[HAWKES_TIMING_KERNELS];
 static int64_t g_cnt[HAWKES_TIMING_KERNELS];
@@ -30,10 +30,10 @@ static void drain_locked() {
     g_pending.clear();
 }
 
-bool timing_on() { return g_on; }
+bool timing_on() { return g_mask != 0; }
 
 void* timing_begin(int id, hipStream_t st) {
-    if (!g_on || id < 0 || id >= HAWKES_TIMING_KERNELS) return nullptr;
+    if (id < 0 || id >= HAWKES_TIMING_KERNELS || !((g_mask >> id) & 1u)) return nullptr;
     TimedLaunch* L = new TimedLaunch{id, nullptr, nullptr};
     if (hipEventCreate(&L->a) != hipSuccess || hipEventCreate(&L->b) != hipSuccess ||
         hipEventRecord(L->a, st) != hipSuccess) {
@@ -59,7 +59,7 @@ extern "C" {
 
 hawkes_status hawkes_timing_enable(int on) {
     std::lock_guard<std::mutex> g(hk::g_mu);
-    hk::g_on = on != 0;
+    hk::g_mask = on < 0 ? 0xffffffffu : (uint32_t)on;
     return HAWKES_OK;
 }
 
