@@ -22,10 +22,11 @@
 //            plus the same-batch events found through a per-node lane mask.
 //            It writes lambda_i / per-segment float64 partials and, for the
 //            gradient, per-event coefficients for the dense kernel.
-//   dense    dense dL/dalpha (first term of eq. 9): block (64 rows x 64
-//            columns x event range) per wave; column state K in registers,
-//            anchored per 64-event batch so that each event costs one
-//            multiply-add per column; rows accumulate in float64 LDS.
+//   bucket   the chunk's events partitioned by blocks of 16 nodes (hk_bucket.hip)
+//   dense    dense dL/dalpha (first term of eq. 9, hk_dense.hip): state
+//            checkpoints per column block, then tiles of 16 rows x up to 256
+//            columns per event range, the rank-1 part of each window in
+//            registers and its pair terms in float64 LDS.
 #include "hk_device.h"
 #include "hk_large.h"
 #include <stdlib.h>
