@@ -67,7 +67,7 @@
 extern "C" {
 #endif
 
-#define HAWKES_ABI_VERSION 2
+#define HAWKES_ABI_VERSION 3
 
 typedef enum hawkes_status {
     HAWKES_OK = 0,
@@ -168,14 +168,20 @@ hawkes_status hawkes_intensity(const hawkes_problem* p,
 
 /* ----------------------------------------------------------------------------
  * Maximum-likelihood step (the training loop of Algorithm 1: forward pass,
- * backward pass, optimizer step; the paper's sparsity penalty is not
- * included).  hawkes_adam_step evaluates the log-likelihood and gradient like
- * hawkes_loglik_grad (same workspace size), then applies one projected Adam
- * step to the per-event negative log-likelihood -L/n, in place on mu, alpha
- * and beta (float32): first and second moments in float32, bias corrections
- * from a step counter kept in the device state, then mu >= floor_mu,
- * alpha >= 0, beta >= floor_beta.  All gradient outputs are required (they
- * hold the gradient of L at the parameters before the step).  The call is
+ * backward pass, optimizer step).  hawkes_adam_step evaluates the
+ * log-likelihood and gradient like hawkes_loglik_grad (same workspace size),
+ * then applies one projected Adam step to the training objective of
+ * section "Background", the per-event negative log-likelihood plus the
+ * hinge-l1 sparsity penalty
+ *     -L/n + lambda1 * sum_{p != q} alpha_pq 1{alpha_pq < h}
+ * (off-diagonal entries only: self-excitation is not penalised), in place
+ * on mu, alpha and beta (float32).  The penalty's gradient is lambda1 on the
+ * off-diagonal entries below h (compared as float32) and 0 elsewhere;
+ * lambda1 = 0 gives the plain per-event NLL.  First and second moments are
+ * float32, bias corrections come from a step counter kept in the device
+ * state, then mu >= floor_mu, alpha >= 0, beta >= floor_beta.  All gradient
+ * outputs are required (they hold the gradient of L, without the penalty,
+ * at the parameters before the step; so is loglik).  The call is
  * stream-ordered and host-sync-free, so a whole step can be captured in a
  * HIP graph and replayed; each replay advances the counter.
  * The state (size from hawkes_adam_state_bytes, caller-owned device memory)
@@ -184,6 +190,7 @@ hawkes_status hawkes_intensity(const hawkes_problem* p,
 typedef struct hawkes_adam {
     float lr, beta1, beta2, eps;   /* step size, moment decays, denominator floor */
     float floor_mu, floor_beta;    /* projection bounds (floor_beta > 0) */
+    float lambda1, h;              /* penalty weight (>= 0) and hinge point (> 0 when lambda1 > 0) */
 } hawkes_adam;
 
 size_t hawkes_adam_state_bytes(const hawkes_problem* p);

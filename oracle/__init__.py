@@ -181,3 +181,24 @@ def addend_scales(t, m, mu, alpha, beta, T, grads):
     s_a = np.linalg.norm(np.abs(g_a + C[None, :]) + C[None, :])
     s_b = abs(float(np.ravel(g_b)[0]) + E) + E
     return float(s_mu), float(s_a), float(s_b)
+
+
+def sparsity_penalty(alpha, lam, h):
+    """Hinge-l1 sparsity penalty of the training objective (section
+    "Background": the per-event NLL plus lam times the sum of alpha's
+    off-diagonal entries that lie below the hinge point h) and its gradient
+    with respect to alpha: lam at those entries, zero on the diagonal and at
+    or above h (the indicator's jump at h is ignored, as a gradient step
+    does).  The comparison alpha < h is made on the values as given, so a
+    float32 alpha and a float32 h decide as the library does.  Returns
+    (value, grad), grad in float64 and shaped like alpha (M x M)."""
+    a = np.asarray(alpha)
+    M = a.shape[0]
+    value = 0.0
+    grad = np.zeros((M, M), dtype=np.float64)
+    for p in range(M):
+        for q in range(M):
+            if p != q and a[p, q] < h:
+                value += float(a[p, q])
+                grad[p, q] = lam
+    return lam * value, grad

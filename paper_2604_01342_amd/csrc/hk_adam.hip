@@ -1,7 +1,8 @@
-// Projected Adam step on the per-event negative log-likelihood, fused after a
-// log-likelihood + gradient evaluation: the maximum-likelihood loop the paper
-// trains with (Algorithm 1: forward pass, backward pass, optimizer step),
-// without its sparsity penalty.  Everything is stream-ordered and reads no
+// Projected Adam step on the training objective of section "Background" (the
+// per-event negative log-likelihood plus the hinge-l1 penalty on alpha's
+// off-diagonal entries below h), fused after a log-likelihood + gradient
+// evaluation: the maximum-likelihood loop the paper trains with (Algorithm 1:
+// forward pass, backward pass, optimizer step).  Everything is stream-ordered and reads no
 // device memory from the host, so a whole step can be captured in a HIP graph
 // and replayed: the step counter used for the bias corrections lives in the
 // device state and is advanced by a kernel.
@@ -58,8 +59,13 @@ __global__ void adam_update(int64_t M, int64_t MM, int64_t nb, double scale, haw
         } else {
             x = beta + (i - M - MM); g = g_beta[i - M - MM]; lo = cfg.floor_beta;
         }
-        // gradient of the loss -L / scale
-        const double gl = -g / scale;
+        // gradient of the loss -L / scale, plus the penalty's lambda1 on the
+        // off-diagonal alpha entries below the hinge point (float32 compare)
+        double gl = -g / scale;
+        if (i >= M && i < M + MM) {
+            const int64_t a = i - M;
+            if (a / M != a % M && *x < cfg.h) gl += (double)cfg.lambda1;
+        }
         float* m = mom + i;
         float* v = mom + np + i;
         const double mn = cfg.beta1 * (double)*m + (1.0 - cfg.beta1) * gl;
@@ -100,7 +106,7 @@ hawkes_status hawkes_adam_step(const hawkes_problem* p, const double* t, const i
         return HAWKES_EINVAL;
     if (!(cfg->lr > 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) ||
         !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) || !(cfg->eps > 0.0f) || !(cfg->floor_mu >= 0.0f) ||
-        !(cfg->floor_beta > 0.0f))
+        !(cfg->floor_beta > 0.0f) || !(cfg->lambda1 >= 0.0f) || (cfg->lambda1 > 0.0f && !(cfg->h > 0.0f)))
         return HAWKES_EINVAL;
     const AdamLayout L = adam_layout(p);
     if (state_bytes < L.bytes) return HAWKES_EWORKSPACE;

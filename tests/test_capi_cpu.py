@@ -43,7 +43,7 @@ def test_library_exports_every_declared_symbol(H):
 
 def test_version_and_status_strings(H):
     L = H.lib()
-    assert L.hawkes_version() == 2
+    assert L.hawkes_version() == 3
     for s in range(5):
         assert L.hawkes_status_string(s)
     assert L.hawkes_status_string(2) == b"workspace missing or too small"
@@ -166,6 +166,15 @@ def test_host_argument_errors(H):
     assert L.hawkes_adam_step(ctypes.byref(p), FAKE, FAKE, FAKE, FAKE, FAKE, ctypes.byref(good), FAKE, 16, *out4,
                               FAKE, 1 << 30, nul) == 2
     assert L.hawkes_adam_step(ctypes.byref(p), FAKE, FAKE, FAKE, FAKE, FAKE, ctypes.byref(good), FAKE, sb, *out4,
+                              FAKE, 16, nul) == 2
+    # sparsity penalty: lambda1 < 0, or lambda1 > 0 without a positive hinge
+    # point, is rejected; lambda1 = 0 ignores h
+    for lam, h in ((-0.1, 0.05), (0.1, 0.0), (0.1, float("nan"))):
+        pen = H._Adam(0.05, 0.9, 0.999, 1e-8, 1e-6, 1e-6, lam, h)
+        assert L.hawkes_adam_step(ctypes.byref(p), FAKE, FAKE, FAKE, FAKE, FAKE, ctypes.byref(pen), FAKE, sb,
+                                  *out4, FAKE, 1 << 30, nul) == 1
+    pen0 = H._Adam(0.05, 0.9, 0.999, 1e-8, 1e-6, 1e-6, 0.0, 0.0)
+    assert L.hawkes_adam_step(ctypes.byref(p), FAKE, FAKE, FAKE, FAKE, FAKE, ctypes.byref(pen0), FAKE, sb, *out4,
                               FAKE, 16, nul) == 2
 
 

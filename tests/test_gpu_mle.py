@@ -12,8 +12,9 @@ pytestmark = pytest.mark.gpu
 
 
 def _adam_reference(t, m, mu, al, be, T, steps, lr=0.05, b1=0.9, b2=0.999, eps=1e-8, floor=1e-6,
-                    per_target=False):
-    """Projected Adam on -L/n with the oracle's gradient; moments and
+                    per_target=False, lam=0.0, h=0.05):
+    """Projected Adam on -L/n plus the oracle's hinge-l1 penalty (weight lam,
+    hinge h, decided in float32), with the oracle's gradient; moments and
     parameters rounded to float32 after each update, as the library stores
     them."""
     n = max(len(t), 1)
@@ -27,8 +28,9 @@ def _adam_reference(t, m, mu, al, be, T, steps, lr=0.05, b1=0.9, b2=0.999, eps=1
         L, gmu, ga, gb = f(t, m, x[0], x[1], x[2], T)
         grads = [np.asarray(gmu), np.reshape(ga, x[1].shape), np.reshape(gb, x[2].shape)]
         c1, c2 = 1.0 - b1 ** k, 1.0 - b2 ** k
+        pen = oracle.sparsity_penalty(x[1], lam, np.float32(h))[1]
         for j in range(3):
-            g = -grads[j] / n
+            g = -grads[j] / n + (pen if j == 1 else 0.0)
             mn = b1 * mom[j].astype(np.float64) + (1 - b1) * g
             vn = b2 * vel[j].astype(np.float64) + (1 - b2) * g * g
             mom[j] = mn.astype(np.float32)
@@ -39,14 +41,18 @@ def _adam_reference(t, m, mu, al, be, T, steps, lr=0.05, b1=0.9, b2=0.999, eps=1
     return traj
 
 
-@pytest.mark.parametrize("per_target,M", [(False, 3), (False, 40), (True, 20)])
-def test_adam_steps_match_reference(H, per_target, M):
+# lam > 0: the penalised objective; the hinge 0.07 is no multiple of the
+# learning rate, so that no entry lands on it exactly (an entry one float32
+# ulp either side of h would take different branches on the two sides)
+@pytest.mark.parametrize("per_target,M,lam", [(False, 3, 0.0), (False, 40, 0.0), (True, 20, 0.0),
+                                              (False, 3, 0.1), (False, 40, 0.1), (True, 20, 0.1)])
+def test_adam_steps_match_reference(H, per_target, M, lam):
     import torch
     t, m, mu, al, be, T = rand_problem(51 + M, 3000, M, per_target=per_target, density=0.5, rate=10.0)
-    ref = _adam_reference(t, m, mu, al, be, T, 4, per_target=per_target)
+    ref = _adam_reference(t, m, mu, al, be, T, 4, per_target=per_target, lam=lam, h=0.07)
     d = "cuda"
     opt = H.AdamMLE(torch.as_tensor(t, device=d), torch.as_tensor(m, device=d), torch.as_tensor(mu, device=d),
-                    torch.as_tensor(al, device=d), torch.as_tensor(be, device=d), T)
+                    torch.as_tensor(al, device=d), torch.as_tensor(be, device=d), T, lambda1=lam, h=0.07)
     for k, (Lr, xr) in enumerate(ref):
         L = float(opt.step().item())
         torch.cuda.synchronize()

@@ -318,3 +318,42 @@ def test_addend_scales_match_direct_double_sums():
     assert abs(s_mu - np.linalg.norm(S + T)) <= 1e-12 * s_mu
     assert abs(s_a - np.linalg.norm(G + C[None, :])) <= 1e-12 * s_a
     assert abs(s_b - (abs(Gb) + E)) <= 1e-12 * s_b
+
+
+def test_sparsity_penalty_hand_example():
+    # off-diagonal 0.03 < h counts, 0.2 >= h does not; the diagonal never does
+    a = np.array([[0.01, 0.2], [0.03, 0.04]])
+    v, g = oracle.sparsity_penalty(a, 0.1, 0.05)
+    assert v == pytest.approx(0.1 * 0.03, rel=1e-15)
+    np.testing.assert_array_equal(g, [[0.0, 0.0], [0.1, 0.0]])
+    # the hinge is strict: an entry equal to h is not penalised
+    v, g = oracle.sparsity_penalty(np.array([[0.0, 0.05], [0.0, 0.0]]), 2.0, 0.05)
+    assert v == 0.0 and g[0, 1] == 0.0 and g[1, 0] == 2.0
+
+
+def test_sparsity_penalty_without_hinge_is_offdiagonal_l1():
+    # h above every entry: lam (sum of all entries - trace), the plain l1
+    # norm of the off-diagonal part for nonnegative alpha
+    rng = np.random.default_rng(3)
+    a = rng.uniform(0.0, 1.0, (7, 7))
+    v, g = oracle.sparsity_penalty(a, 0.3, 2.0)
+    assert v == pytest.approx(0.3 * (a.sum() - np.trace(a)), rel=1e-13)
+    np.testing.assert_array_equal(g, 0.3 * (1.0 - np.eye(7)))
+    assert oracle.sparsity_penalty(a, 0.0, 2.0)[0] == 0.0
+
+
+def test_sparsity_penalty_gradient_matches_differences():
+    # away from the hinge the penalty is linear in each entry
+    rng = np.random.default_rng(4)
+    a = rng.uniform(0.0, 0.2, (5, 5))
+    lam, h = 0.7, 0.1
+    v0, g = oracle.sparsity_penalty(a, lam, h)
+    eps = 1e-6
+    for p in range(5):
+        for q in range(5):
+            if abs(a[p, q] - h) < 10 * eps:
+                continue
+            b = a.copy()
+            b[p, q] += eps
+            d = (oracle.sparsity_penalty(b, lam, h)[0] - v0) / eps
+            assert d == pytest.approx(g[p, q], abs=1e-7)
