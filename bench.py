@@ -365,6 +365,16 @@ def main() -> int:
                       "n_events": w.n, "n_nodes": w.M, "chunk_log2": args.chunk_log2, "tuning": tuning},
            "roofline": roofline, "step_device_time": step_stats, "kernels_ms_per_step": kernels}
 
+    # the same step with dL/dalpha restricted to alpha's support
+    # (hawkes_loglik_grad_support: no dense kernels, the first term of eq. 9
+    # summed in the forward pass); a second figure, not the headline
+    sw, sper = _timed(lambda: H.loglik_grad(t, m, mu, al, be, w.T, args.chunk_log2, support=True),
+                      max(3, args.steps // 2), 1)
+    out["support_gradient"] = {"ms_per_step": round(sw, 4), "events_per_s": w.n / (sw / 1e3),
+                               "device_median_ms": round(sper[len(sper) // 2], 4),
+                               "nonzeros": int(np.count_nonzero(w.alpha))}
+    log(f"support-restricted gradient: {sw:.3f} ms/step, {w.n / (sw / 1e3):.4e} events/s")
+
     # sequential-recurrence GPU kernel on a prefix
     if not args.no_seq:
         ns = min(args.seq_events, w.n)

@@ -157,6 +157,24 @@ hawkes_status hawkes_loglik_grad(const hawkes_problem* p,
                                  double* loglik, double* g_mu, double* g_alpha, double* g_beta,
                                  void* workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* The same, with dL/dalpha restricted to alpha's support, for models with a
+ * sparse interaction matrix (the sparse cross-node influence that the
+ * penalty of section "Background" aims at; sections "Introduction" and
+ * "Conclusion" state the method's compatibility with such optimizations):
+ * g_alpha[p][q] is eq. 9 where alpha[p][q] != 0 and 0 elsewhere, so a zero
+ * entry of alpha stays a fixed zero under gradient steps.  loglik, g_mu and g_beta equal
+ * hawkes_loglik_grad's.  With one shared decay and M > 8 the first term of
+ * eq. 9 is summed only over the nonzeros, inside the forward pass (float64
+ * atomics: the summation order, and so the last bits, vary between calls),
+ * and the dense dL/dalpha kernels do not run; the other configurations
+ * compute the dense gradient and zero it off the support.  Same workspace
+ * as hawkes_loglik_grad. */
+hawkes_status hawkes_loglik_grad_support(const hawkes_problem* p,
+                                         const double* t, const int32_t* marks,
+                                         const float* mu, const float* alpha, const float* beta,
+                                         double* loglik, double* g_mu, double* g_alpha, double* g_beta,
+                                         void* workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* Intensities at the events, lambda_out[i] = lambda_{m_i}(t_i) (eq. 1) as
  * float32 (the value the log-likelihood uses).  Same workspace as
  * hawkes_loglik. */

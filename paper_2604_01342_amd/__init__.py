@@ -79,6 +79,7 @@ def lib():
     L.hawkes_workspace_bytes.restype = sz
     L.hawkes_loglik.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.hawkes_loglik_grad.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.hawkes_loglik_grad_support.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.hawkes_intensity.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.hawkes_sequential_loglik_grad.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.hawkes_check_inputs.argtypes = [P, vp, vp, vp, vp, vp, vp, vp]
@@ -99,7 +100,7 @@ def lib():
     L.hawkes_adam_state_bytes.restype = sz
     L.hawkes_adam_init.argtypes = [P, vp, sz, vp]
     L.hawkes_adam_step.argtypes = [P, vp, vp, vp, vp, vp, ctypes.POINTER(_Adam), vp, sz, vp, vp, vp, vp, vp, sz, vp]
-    for f in ("hawkes_loglik", "hawkes_loglik_grad", "hawkes_intensity", "hawkes_sequential_loglik_grad",
+    for f in ("hawkes_loglik", "hawkes_loglik_grad", "hawkes_loglik_grad_support", "hawkes_intensity", "hawkes_sequential_loglik_grad",
               "hawkes_check_inputs", "hawkes_loglik_batched", "hawkes_loglik_grad_batched", "hawkes_adam_init",
               "hawkes_adam_step"):
         getattr(L, f).restype = ctypes.c_int
@@ -191,8 +192,10 @@ def loglik(t, m, mu, alpha, beta, T, chunk_log2: int = 0) -> torch.Tensor:
     return out[0]
 
 
-def loglik_grad(t, m, mu, alpha, beta, T, chunk_log2: int = 0):
-    """(L, dL/dmu [M], dL/dalpha [M, M], dL/dbeta [1] or [M]) as float64 device tensors."""
+def loglik_grad(t, m, mu, alpha, beta, T, chunk_log2: int = 0, support: bool = False):
+    """(L, dL/dmu [M], dL/dalpha [M, M], dL/dbeta [1] or [M]) as float64 device tensors.
+    support=True: dL/dalpha only at alpha's nonzeros, 0 elsewhere
+    (hawkes_loglik_grad_support)."""
     dev, t, m, mu, alpha, beta = _prep(t, m, mu, alpha, beta)
     p = _problem(t, mu, beta, T, chunk_log2)
     L = lib()
@@ -203,9 +206,9 @@ def loglik_grad(t, m, mu, alpha, beta, T, chunk_log2: int = 0):
     gmu = torch.empty(M, dtype=torch.float64, device=dev)
     ga = torch.empty(M, M, dtype=torch.float64, device=dev)
     gb = torch.empty(beta.numel(), dtype=torch.float64, device=dev)
-    _check("hawkes_loglik_grad",
-           L.hawkes_loglik_grad(ctypes.byref(p), _ptr(t), _ptr(m), _ptr(mu), _ptr(alpha), _ptr(beta), _ptr(out),
-                                _ptr(gmu), _ptr(ga), _ptr(gb), _ptr(ws), nb, _stream(dev)))
+    name = "hawkes_loglik_grad_support" if support else "hawkes_loglik_grad"
+    _check(name, getattr(L, name)(ctypes.byref(p), _ptr(t), _ptr(m), _ptr(mu), _ptr(alpha), _ptr(beta), _ptr(out),
+                                  _ptr(gmu), _ptr(ga), _ptr(gb), _ptr(ws), nb, _stream(dev)))
     return out[0], gmu, ga, gb
 
 

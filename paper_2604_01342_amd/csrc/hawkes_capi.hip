@@ -144,10 +144,26 @@ size_t hawkes_workspace_bytes(const hawkes_problem* p, int with_grad) {
     return large_layout(A, p, with_grad != 0, nullptr, 0);
 }
 
+// support-restricted gradient on the engines that form the dense one: zero
+// dL/dalpha where alpha is zero
+__global__ void mask_to_support(int64_t n, const float* __restrict__ alpha, double* __restrict__ g_alpha) {
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
+        if (alpha[x] == 0.0f) g_alpha[x] = 0.0;
+}
+
+static hawkes_status mask_support(const hawkes_problem* p, const float* alpha, double* g_alpha, hipStream_t st) {
+    if (!g_alpha) return HAWKES_OK;
+    const int64_t n = (int64_t)p->m * p->m;
+    const int64_t nb = (n + 255) / 256;
+    hipLaunchKernelGGL(mask_to_support, dim3((unsigned)(nb < 4096 ? nb : 4096)), dim3(256), 0, st, n, alpha,
+                       g_alpha);
+    return hipGetLastError() == hipSuccess ? HAWKES_OK : HAWKES_EDEVICE;
+}
+
 static hawkes_status run_single(const hawkes_problem* p, const double* t, const int32_t* marks, const float* mu,
                                 const float* alpha, const float* beta, double* loglik, double* g_mu,
                                 double* g_alpha, double* g_beta, float* lambda_out, bool grad, void* ws,
-                                size_t ws_bytes, hipStream_t stream) {
+                                size_t ws_bytes, hipStream_t stream, bool support = false) {
     if (!problem_ok(p) || !mu || !alpha || !beta) return HAWKES_EINVAL;
     if (!loglik && !lambda_out) return HAWKES_EINVAL;
     if (p->k != 1) return HAWKES_EUNSUPPORTED;
@@ -165,7 +181,8 @@ static hawkes_status run_single(const hawkes_problem* p, const double* t, const 
         A.loglik = loglik ? loglik : A.ll_scratch;
         A.g_mu = g_mu; A.g_alpha = g_alpha; A.g_beta = g_beta;
         A.lambda_out = lambda_out;
-        return run_small(A, stream);
+        const hawkes_status st = run_small(A, stream);
+        return st == HAWKES_OK && support ? mask_support(p, alpha, g_alpha, stream) : st;
     }
     LargeArgs A;
     memset(&A, 0, sizeof(A));
@@ -176,7 +193,11 @@ static hawkes_status run_single(const hawkes_problem* p, const double* t, const 
     A.loglik = loglik ? loglik : A.ll_scratch;
     A.g_mu = g_mu; A.g_alpha = g_alpha; A.g_beta = g_beta;
     A.lambda_out = lambda_out;
-    return run_large(A, stream);
+    // shared decay: the first term only on the support (forward pass); per
+    // target: the dense gradient, masked
+    A.support = support && !A.per_target;
+    const hawkes_status st = run_large(A, stream);
+    return st == HAWKES_OK && support && A.per_target ? mask_support(p, alpha, g_alpha, stream) : st;
 }
 
 hawkes_status hawkes_loglik(const hawkes_problem* p, const double* t, const int32_t* marks, const float* mu,
@@ -192,6 +213,14 @@ hawkes_status hawkes_loglik_grad(const hawkes_problem* p, const double* t, const
                                  hipStream_t stream) {
     return run_single(p, t, marks, mu, alpha, beta, loglik, g_mu, g_alpha, g_beta, nullptr, true, workspace,
                       workspace_bytes, stream);
+}
+
+hawkes_status hawkes_loglik_grad_support(const hawkes_problem* p, const double* t, const int32_t* marks,
+                                         const float* mu, const float* alpha, const float* beta, double* loglik,
+                                         double* g_mu, double* g_alpha, double* g_beta, void* workspace,
+                                         size_t workspace_bytes, hipStream_t stream) {
+    return run_single(p, t, marks, mu, alpha, beta, loglik, g_mu, g_alpha, g_beta, nullptr, true, workspace,
+                      workspace_bytes, stream, true);
 }
 
 hawkes_status hawkes_intensity(const hawkes_problem* p, const double* t, const int32_t* marks, const float* mu,

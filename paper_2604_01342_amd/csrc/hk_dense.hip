@@ -542,7 +542,8 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
 }
 
 template <int CPL, int DRB>
-static void dense_launch_t(LargeArgs& A, int64_t c0, int32_t nev, int32_t nseg, int32_t nrun_c, hipStream_t st) {
+static void dense_launch_t(LargeArgs& A, int64_t c0, int32_t nev, int32_t nseg, int32_t nrun_c, hipStream_t st,
+                           bool ck_only) {
     {
         TimedScope tk(7, st);
         const unsigned nck = (unsigned)(((nrun_c + 7) / 8) * 8 * A.NBC);
@@ -550,6 +551,7 @@ static void dense_launch_t(LargeArgs& A, int64_t c0, int32_t nev, int32_t nseg, 
                            A.CKR, nseg, A.T, A.t, A.marks, A.wchunk, A.beta, A.carry_seg, A.bo_off, A.bo_base,
                            A.kck, A.runinfo, A.spart, A.cpart_);
     }
+    if (ck_only) return;
     TimedScope ts(0, st);
     const int32_t rpr = A.NRUN / A.ER;   // runs per event range (both powers of two)
     const int32_t nbb = A.NBR * A.NBC;
@@ -560,16 +562,16 @@ static void dense_launch_t(LargeArgs& A, int64_t c0, int32_t nev, int32_t nseg, 
                        A.bo_t, A.bo_w, A.kck, A.gpart);
 }
 
-void large_dense_launch(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, hipStream_t st) {
+void large_dense_launch(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, hipStream_t st, bool ck_only) {
     const int32_t nrun_c = (nseg + A.CKR - 1) / A.CKR;
     const int32_t nev = (int32_t)(c1 - c0);
     // the tiles the layout selects: 16 x 256, 16 x 128, 16 x 64
     if (A.CPL == 4)
-        dense_launch_t<4, 4>(A, c0, nev, nseg, nrun_c, st);
+        dense_launch_t<4, 4>(A, c0, nev, nseg, nrun_c, st, ck_only);
     else if (A.CPL == 2)
-        dense_launch_t<2, 4>(A, c0, nev, nseg, nrun_c, st);
+        dense_launch_t<2, 4>(A, c0, nev, nseg, nrun_c, st, ck_only);
     else
-        dense_launch_t<1, 4>(A, c0, nev, nseg, nrun_c, st);
+        dense_launch_t<1, 4>(A, c0, nev, nseg, nrun_c, st, ck_only);
 }
 
 }  // namespace hk

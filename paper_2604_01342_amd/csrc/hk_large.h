@@ -39,6 +39,7 @@ struct LargeArgs {
     int32_t CKR;          // segments per checkpoint run (shared decay)
     int32_t NRUN;         // checkpoint runs per chunk (nseg / CKR)
     bool grad;
+    bool support;         // dL/dalpha only at alpha's nonzeros (zero elsewhere), shared decay
     const double* t;
     const int32_t* marks;
     const float *mu, *alpha, *beta;
@@ -60,6 +61,7 @@ struct LargeArgs {
     double* acc;          // [4] call-level sums: logsum, comp, E, gbeta
     double* ll_scratch;   // [1] log-likelihood slot when the caller wants intensities only
     double *gpart, *spart, *cpart_;  // [ER][M][M]; [ER][M] per target, [NRUN][M] shared decay
+    double* gsup;         // [nnz(alpha)] support-restricted first term of eq. 9, in CSR order (shared decay)
     int64_t nslot;        // checkpoint slots
     double* kck;          // [nslot][64 CPL + 104] state checkpoints of the dense gradient (shared
                           //   decay) with their groups' records
@@ -112,7 +114,9 @@ void bucket_chunk(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, const floa
 void bucket_chunk_into(const LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, const float* wchunk, int bs,
                        int32_t* cnt, int32_t* off, int32_t* base, uint32_t* key, double* tt, float* ww,
                        hipStream_t st);
-void large_dense_launch(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, hipStream_t st);
+// ck_only: the checkpoint kernel alone (its per-column sums of dL/dmu and
+// the compensator), for the support-restricted gradient
+void large_dense_launch(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, hipStream_t st, bool ck_only);
 
 size_t seq_workspace_bytes(const hawkes_problem* p);
 hawkes_status run_sequential(const hawkes_problem* p, const double* t, const int32_t* marks, const float* mu,

@@ -301,7 +301,10 @@ __global__ void large_scan_apply(int32_t nseg, int32_t M, const double* __restri
 }
 
 // ------------------------------------------------------------------ forward
-template <bool GRAD, bool INTENS>
+// SUPP (with GRAD): also adds beta w_i K_q(t_i) to gsup[k] for every nonzero
+// k = (m_i, q) of alpha's CSR (hardware float64 atomics): the first term of
+// eq. 9 on alpha's support only.
+template <bool GRAD, bool INTENS, bool SUPP>
 __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int32_t M, double T,
                                                     const double* __restrict__ t, const int32_t* __restrict__ marks,
                                                     const float* __restrict__ mu, const float* __restrict__ beta,
@@ -311,7 +314,8 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
                                                     const double* __restrict__ carry_seg,
                                                     double* __restrict__ seg_part,
                                                     float* __restrict__ wchunk,
-                                                    float* __restrict__ lambda_out) {
+                                                    float* __restrict__ lambda_out,
+                                                    double* __restrict__ gsup) {
     extern __shared__ double lds[];
     double* rtau = lds;                                   // [M] time of the record
     uint64_t* rmask = (uint64_t*)(lds + M);               // [M] lanes of this batch with mark q
@@ -392,41 +396,30 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
         if (valid) {
             const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
             const int32_t k0 = ni.x, k1 = ni.y;
-            if (anch) {
-                // anchored sums of source q (records plus the batch's earlier
-                // events of q), weight av
-                auto terma = [&](int32_t q, float av) {
-                    const double2 kj = rKJ[q];   // one LDS read for both
-                    double s0 = kj.x;
-                    double s1 = GRAD ? kj.y : 0.0;
-                    uint64_t bits = rmask[q] & below;
-                    while (bits) {
-                        const int jj = __builtin_ctzll(bits);
-                        bits &= bits - 1;
-                        const double ej = eb[jj];
-                        s0 += ej;
-                        if (GRAD) s1 = __builtin_fma(tb[jj] - tref, ej, s1);
-                    }
-                    R = __builtin_fma((double)av, s0, R);
-                    if (GRAD) Dd = __builtin_fma((double)av, __builtin_fma(ui, s0, -s1), Dd);
-                };
-#pragma unroll
-                for (int j = 0; j < FW; ++j)
-                    if (k0 + j < k1) terma(qc0[j], qa0[j]);
-                for (int32_t k = k0 + FW; k < k1; ++k) terma(csr_col[k], csr_val[k]);
-                const double ei = exp_f64(-bet * ui);   // e^{-beta u_i}
-                R *= ei;
-                Dd *= ei;
-            } else {
-            // contribution of source q with weight av: the record decayed to
-            // ti plus the batch's earlier events of q
-            auto term = [&](int32_t q, float av) {
+            // anchored sums of source q (records plus the batch's earlier
+            // events of q): K_q(t_i) = e^{-beta u_i} s0
+            auto sums_a = [&](int32_t q, double& s0, double& s1) {
+                const double2 kj = rKJ[q];   // one LDS read for both
+                s0 = kj.x;
+                s1 = GRAD ? kj.y : 0.0;
+                uint64_t bits = rmask[q] & below;
+                while (bits) {
+                    const int jj = __builtin_ctzll(bits);
+                    bits &= bits - 1;
+                    const double ej = eb[jj];
+                    s0 += ej;
+                    if (GRAD) s1 = __builtin_fma(tb[jj] - tref, ej, s1);
+                }
+            };
+            // source q's record decayed to ti plus the batch's earlier events
+            // of q: Kv = K_q(t_i), Jv = J_q(t_i)
+            auto sums_w = [&](int32_t q, double& Kv, double& Jv) {
                 const double d = ti - rtau[q];
                 const double e = exp_f64(-bet * d);
                 const double2 kj = rKJ[q];
                 const double kq = kj.x;
-                double Kv = e * kq;
-                double Jv = GRAD ? e * __builtin_fma(d, kq, kj.y) : 0.0;
+                Kv = e * kq;
+                Jv = GRAD ? e * __builtin_fma(d, kq, kj.y) : 0.0;
                 uint64_t bits = rmask[q] & below;
                 while (bits) {
                     const int jj = __builtin_ctzll(bits);
@@ -436,12 +429,42 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
                     Kv += ej;
                     if (GRAD) Jv = __builtin_fma(dj, ej, Jv);
                 }
+            };
+            double ks[SUPP ? FW : 1];   // the first FW nonzeros' sums, for gsup
+            double ei = 1.0;            // e^{-beta u_i} (anchored records)
+            if (anch) {
+                // source q with weight av
+                auto terma = [&](int32_t q, float av) -> double {
+                    double s0, s1;
+                    sums_a(q, s0, s1);
+                    R = __builtin_fma((double)av, s0, R);
+                    if (GRAD) Dd = __builtin_fma((double)av, __builtin_fma(ui, s0, -s1), Dd);
+                    return s0;
+                };
+#pragma unroll
+                for (int j = 0; j < FW; ++j)
+                    if (k0 + j < k1) {
+                        const double v = terma(qc0[j], qa0[j]);
+                        if (SUPP) ks[j] = v;
+                    }
+                for (int32_t k = k0 + FW; k < k1; ++k) terma(csr_col[k], csr_val[k]);
+                ei = exp_f64(-bet * ui);
+                R *= ei;
+                Dd *= ei;
+            } else {
+            auto term = [&](int32_t q, float av) -> double {
+                double Kv, Jv;
+                sums_w(q, Kv, Jv);
                 R = __builtin_fma((double)av, Kv, R);
                 if (GRAD) Dd = __builtin_fma((double)av, Jv, Dd);
+                return Kv;
             };
 #pragma unroll
             for (int j = 0; j < FW; ++j)
-                if (k0 + j < k1) term(qc0[j], qa0[j]);
+                if (k0 + j < k1) {
+                    const double v = term(qc0[j], qa0[j]);
+                    if (SUPP) ks[j] = v;
+                }
             for (int32_t k = k0 + FW; k < k1; ++k) term(csr_col[k], csr_val[k]);
             }
             lam = __builtin_fma(bet, R, (double)__int_as_float(ni.z));
@@ -455,6 +478,22 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
                 w = 1.0 / lam;
                 gb += w * (R - bet * Dd);
                 Esum += cs_m * (T - ti) * exp_f64(-x);
+            }
+            if (SUPP) {
+                // beta w_i K_q(t_i) for each nonzero (m_i, q); the sums past
+                // the first FW nonzeros are formed again
+                const double bw = bet * w * ei;
+#pragma unroll
+                for (int j = 0; j < FW; ++j)
+                    if (k0 + j < k1) unsafeAtomicAdd(&gsup[k0 + j], bw * ks[j]);
+                for (int32_t k = k0 + FW; k < k1; ++k) {
+                    double v, unused;
+                    if (anch)
+                        sums_a(csr_col[k], v, unused);
+                    else
+                        sums_w(csr_col[k], v, unused);
+                    unsafeAtomicAdd(&gsup[k], bw * v);
+                }
             }
         }
         if (GRAD && valid) wchunk[i - c0] = (float)w;
@@ -558,7 +597,7 @@ __global__ __launch_bounds__(256) void large_final(int32_t M, int32_t ER, int32_
                             const double* __restrict__ acc, const double* __restrict__ gpart,
                             const double* __restrict__ spart, const double* __restrict__ cpart,
                             double* __restrict__ loglik, double* __restrict__ g_mu, double* __restrict__ g_alpha,
-                            double* __restrict__ g_beta, int grad) {
+                            double* __restrict__ g_beta, int grad, int sup) {
     const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t MM = (int64_t)M * M;
     if (blockIdx.x == 0) {
@@ -578,7 +617,9 @@ __global__ __launch_bounds__(256) void large_final(int32_t M, int32_t ER, int32_
         }
     }
     if (!grad) return;
-    if (x < MM && g_alpha) {
+    if (x < MM && g_alpha && sup) {
+        g_alpha[x] = 0.0;   // large_sup_scatter then writes the support
+    } else if (x < MM && g_alpha) {
         const int32_t q = (int32_t)(x % M);
         double g = 0.0, c = 0.0;
         for (int32_t e = 0; e < ER; ++e) g += gpart[(int64_t)e * MM + x];
@@ -589,6 +630,22 @@ __global__ __launch_bounds__(256) void large_final(int32_t M, int32_t ER, int32_
         double s = 0.0;
         for (int32_t e = 0; e < NSC; ++e) s += spart[(int64_t)e * M + x];
         g_mu[x] = s - T;
+    }
+}
+
+// support-restricted dL/dalpha: one wave per row p writes, for each nonzero
+// (p, q) of alpha, the summed first term minus the column's compensator sum
+// (cpart row 0 after large_colfold); runs after large_final zeroed g_alpha
+__global__ __launch_bounds__(64) void large_sup_scatter(int32_t M, const int32_t* __restrict__ csr_ptr,
+                                                        const int32_t* __restrict__ csr_col,
+                                                        const double* __restrict__ gsup,
+                                                        const double* __restrict__ cpart,
+                                                        double* __restrict__ g_alpha) {
+    const int32_t p = blockIdx.x;
+    const int32_t k1 = csr_ptr[p + 1];
+    for (int32_t k = csr_ptr[p] + (int32_t)threadIdx.x; k < k1; k += 64) {
+        const int32_t q = csr_col[k];
+        g_alpha[(int64_t)p * M + q] = gsup[k] - cpart[q];
     }
 }
 
@@ -694,6 +751,7 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
             A.bk_w = c.take<float>(A.CH);
         }
         A.gpart = c.take<double>((size_t)A.ER * MM);
+        if (!A.per_target) A.gsup = c.take<double>((size_t)MM);   // support-restricted first term (CSR order)
         const int64_t nsp = A.per_target ? A.ER : A.NRUN;
         A.spart = c.take<double>((size_t)nsp * M);
         A.cpart_ = c.take<double>((size_t)nsp * M);
@@ -780,10 +838,12 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
     const size_t lds_agg = (size_t)2 * M * sizeof(double);
     const size_t lds_fwd = (size_t)M * (sizeof(double) + sizeof(uint64_t) + 2 * sizeof(double));
     if (allow_lds((const void*)large_seg_agg, lds_agg) != HAWKES_OK ||
-        allow_lds((const void*)large_forward<true, false>, lds_fwd) != HAWKES_OK ||
-        allow_lds((const void*)large_forward<false, true>, lds_fwd) != HAWKES_OK ||
-        allow_lds((const void*)large_forward<false, false>, lds_fwd) != HAWKES_OK)
+        allow_lds((const void*)large_forward<true, false, false>, lds_fwd) != HAWKES_OK ||
+        allow_lds((const void*)large_forward<true, false, true>, lds_fwd) != HAWKES_OK ||
+        allow_lds((const void*)large_forward<false, true, false>, lds_fwd) != HAWKES_OK ||
+        allow_lds((const void*)large_forward<false, false, false>, lds_fwd) != HAWKES_OK)
         return HAWKES_EUNSUPPORTED;
+    const bool sup = A.grad && A.support;
     // the dense-gradient kernels address checkpoints and records with
     // 32-bit byte offsets
     if (A.grad && (uint64_t)A.nslot * (uint64_t)(64 * A.CPL + 104) * 8u >= (1ull << 32))
@@ -792,9 +852,10 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
     hipLaunchKernelGGL(fill_d, dim3(1), dim3(256), 0, st, A.carry, (int64_t)2 * M, 0.0);
     hipLaunchKernelGGL(fill_d, dim3(1), dim3(64), 0, st, A.acc, (int64_t)4, 0.0);
     if (A.grad) {
-        const int64_t ng = (int64_t)A.ER * MM;
+        // the dense partials, or (support-restricted) the CSR-ordered sums
+        const int64_t ng = sup ? MM : (int64_t)A.ER * MM;
         hipLaunchKernelGGL(fill_d, dim3((unsigned)((ng + 255) / 256 < 65535 ? (ng + 255) / 256 : 65535)),
-                           dim3(256), 0, st, A.gpart, ng, 0.0);
+                           dim3(256), 0, st, sup ? A.gsup : A.gpart, ng, 0.0);
         hipLaunchKernelGGL(fill_d, dim3(64), dim3(256), 0, st, A.spart, (int64_t)A.NRUN * M, 0.0);
         hipLaunchKernelGGL(fill_d, dim3(64), dim3(256), 0, st, A.cpart_, (int64_t)A.NRUN * M, 0.0);
     }
@@ -816,21 +877,22 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
         }
         {
             TimedScope ts(1, st);
-            if (A.grad)
-                hipLaunchKernelGGL((large_forward<true, false>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1, M,
-                                   A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
-                                   A.carry_seg, A.seg_part, A.wchunk,
-                                   (float*)nullptr);
+            if (sup)
+                hipLaunchKernelGGL((large_forward<true, false, true>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1,
+                                   M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
+                                   A.carry_seg, A.seg_part, A.wchunk, (float*)nullptr, A.gsup);
+            else if (A.grad)
+                hipLaunchKernelGGL((large_forward<true, false, false>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1,
+                                   M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
+                                   A.carry_seg, A.seg_part, A.wchunk, (float*)nullptr, (double*)nullptr);
             else if (A.lambda_out)
-                hipLaunchKernelGGL((large_forward<false, true>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1, M,
-                                   A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
-                                   A.carry_seg, A.seg_part, A.wchunk,
-                                   A.lambda_out);
+                hipLaunchKernelGGL((large_forward<false, true, false>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1,
+                                   M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
+                                   A.carry_seg, A.seg_part, A.wchunk, A.lambda_out, (double*)nullptr);
             else
-                hipLaunchKernelGGL((large_forward<false, false>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1, M,
-                                   A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
-                                   A.carry_seg, A.seg_part, A.wchunk,
-                                   (float*)nullptr);
+                hipLaunchKernelGGL((large_forward<false, false, false>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1,
+                                   M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
+                                   A.carry_seg, A.seg_part, A.wchunk, (float*)nullptr, (double*)nullptr);
         }
         hipLaunchKernelGGL(large_chunk_acc, dim3(1), dim3(256), 0, st, nseg, A.seg_part, A.acc);
         if (A.grad) {
@@ -839,13 +901,19 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
                 bucket_chunk_into(A, c0, c1, nseg, A.wchunk, A.DRB, A.bo_cnt, A.bo_off, A.bo_base, A.bo_key, A.bo_t,
                                   A.bo_w, st);
             }
-            large_dense_launch(A, c0, c1, nseg, st);
+            // support-restricted: only the checkpoint kernel's per-column
+            // sums (dL/dmu, compensator) are needed
+            large_dense_launch(A, c0, c1, nseg, st, sup);
         }
     }
     const int64_t nfin = A.grad ? (MM > M ? MM : M) : 1;
     if (A.grad) hipLaunchKernelGGL(large_colfold, dim3(gM), dim3(256), 0, st, M, A.NRUN, A.spart, A.cpart_);
     hipLaunchKernelGGL(large_final, dim3((unsigned)((nfin + 255) / 256)), dim3(256), 0, st, M, A.ER, 1, A.T, A.mu,
-                       A.acc, A.gpart, A.spart, A.cpart_, A.loglik, A.g_mu, A.g_alpha, A.g_beta, A.grad ? 1 : 0);
+                       A.acc, A.gpart, A.spart, A.cpart_, A.loglik, A.g_mu, A.g_alpha, A.g_beta, A.grad ? 1 : 0,
+                       sup ? 1 : 0);
+    if (sup && A.g_alpha)
+        hipLaunchKernelGGL(large_sup_scatter, dim3((unsigned)M), dim3(64), 0, st, M, A.csr_ptr, A.csr_col, A.gsup,
+                           A.cpart_, A.g_alpha);
     return hipGetLastError() == hipSuccess ? HAWKES_OK : HAWKES_EDEVICE;
 }
 

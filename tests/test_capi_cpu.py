@@ -31,7 +31,7 @@ def test_header_declares_expected_api():
               "hawkes_workspace_bytes", "hawkes_batched_workspace_bytes", "hawkes_sequential_loglik_grad",
               "hawkes_intensity", "hawkes_check_inputs", "hawkes_status_string", "hawkes_version",
               "hawkes_adam_state_bytes", "hawkes_adam_init", "hawkes_adam_step", "hawkes_set_tuning",
-              "hawkes_get_tuning"):
+              "hawkes_get_tuning", "hawkes_loglik_grad_support"):
         assert f in names
 
 
@@ -136,6 +136,11 @@ def test_host_argument_errors(H):
     assert L.hawkes_loglik(ctypes.byref(p), *args, FAKE, 16, nul) == 2
     pl = P(H, m=200)
     assert L.hawkes_loglik_grad(ctypes.byref(pl), *args, FAKE, FAKE, FAKE, FAKE, 16, nul) == 2
+    # the support-restricted gradient: same checks
+    assert L.hawkes_loglik_grad_support(ctypes.byref(pl), *args, FAKE, FAKE, FAKE, FAKE, 16, nul) == 2
+    assert L.hawkes_loglik_grad_support(ctypes.byref(pl), nul, *args[1:], FAKE, FAKE, FAKE, FAKE, 1 << 30,
+                                        nul) == 1
+    assert L.hawkes_loglik_grad_support(ctypes.byref(p2), *args, FAKE, FAKE, FAKE, FAKE, 1 << 30, nul) == 4
     # misaligned workspace
     assert L.hawkes_loglik(ctypes.byref(p), *args, ctypes.c_void_p(4096 + 8), 1 << 30, nul) == 2
     # intensity needs an output

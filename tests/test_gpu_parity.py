@@ -87,6 +87,30 @@ def test_large_engine_matches_oracle(H, seed, n, M, density, ties, chunk):
     check(run_gpu(H, t, m, mu, alpha, beta, T, chunk), ref, label=f"large n={n} M={M} chunk={chunk}")
 
 
+# ------------------------------------------------------------- support-restricted dL/dalpha
+# hawkes_loglik_grad_support: the oracle's dense gradient with the entries off
+# alpha's support set to zero.  Large engine: rows with more nonzeros than the
+# forward pass keeps in registers (16), several chunks, anchored records
+# (rate 20) and per-record decays (rate 1: segments spanning beta u > 600);
+# small engine and per-target decays: the dense gradient, masked.
+@pytest.mark.parametrize("seed,n,M,density,per_target,chunk,rate",
+                         [(81, 6000, 4, 0.5, False, 0, 2.0), (82, 30000, 120, 0.3, False, 12, 20.0),
+                          (83, 20000, 300, 0.01, False, 0, 20.0), (84, 12000, 40, 0.5, False, 12, 1.0),
+                          (85, 4000, 24, 0.3, True, 12, 5.0), (86, 1, 9, 1.0, False, 0, 1.0)])
+def test_support_gradient_is_the_masked_dense_gradient(H, seed, n, M, density, per_target, chunk, rate):
+    import torch
+    t, m, mu, alpha, beta, T = rand_problem(seed, n, M, per_target=per_target, density=density, rate=rate)
+    Lr, gmur, gar, gbr = (oracle.adjoint if per_target else oracle.forward)(t, m, mu, alpha, beta, T)
+    gar = np.where(alpha != 0.0, np.reshape(gar, (M, M)), 0.0)
+    L, gmu, ga, gb = H.loglik_grad(dev(t, torch.float64), dev(m, torch.int32), dev(mu, torch.float32),
+                                   dev(alpha, torch.float32), dev(beta, torch.float32), T, chunk, support=True)
+    torch.cuda.synchronize()
+    got = (float(L.item()), gmu.cpu().numpy(), ga.cpu().numpy(), gb.cpu().numpy())
+    check(got, (Lr, gmur, gar, gbr), label=f"support n={n} M={M} pt={per_target} chunk={chunk}")
+    assert np.all(got[2][alpha == 0.0] == 0.0)
+    assert int(np.count_nonzero(alpha)) > 0
+
+
 @pytest.mark.parametrize("cols,ranges,chunk", [(64, 0, 0), (64, 2, 12), (128, 0, 0), (128, 2, 12), (0, 1, 0),
                                               (0, 2, 12), (0, 64, 0), (0, 1024, 0), (256, 0, 0), (256, 8, 12)])
 def test_dense_layouts_match_oracle(H, cols, ranges, chunk):
