@@ -61,7 +61,8 @@ struct LargeArgs {
     double* acc;          // [4] call-level sums: logsum, comp, E, gbeta
     double* ll_scratch;   // [1] log-likelihood slot when the caller wants intensities only
     double *gpart, *spart, *cpart_;  // [ER][M][M]; [ER][M] per target, [NRUN][M] shared decay
-    double* gsup;         // [nnz(alpha)] support-restricted first term of eq. 9, in CSR order (shared decay)
+    double* gsup;         // [min(8, ER)][M*M] support-restricted first term of eq. 9 in CSR order (the
+                          //   first nnz(alpha) entries of each copy; shares gpart's space)
     int64_t nslot;        // checkpoint slots
     double* kck;          // [nslot][64 CPL + 104] state checkpoints of the dense gradient (shared
                           //   decay) with their groups' records

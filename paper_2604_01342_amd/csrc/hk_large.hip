@@ -303,7 +303,10 @@ __global__ void large_scan_apply(int32_t nseg, int32_t M, const double* __restri
 // ------------------------------------------------------------------ forward
 // SUPP (with GRAD): also adds beta w_i K_q(t_i) to gsup[k] for every nonzero
 // k = (m_i, q) of alpha's CSR (hardware float64 atomics): the first term of
-// eq. 9 on alpha's support only.
+// eq. 9 on alpha's support only.  Segment s adds into copy s & cmask (copies
+// MM apart): consecutive workgroups go to different XCDs, so each copy sees
+// mostly one XCD's atomics and a copy's addresses see a fraction of the
+// contention.
 template <bool GRAD, bool INTENS, bool SUPP>
 __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int32_t M, double T,
                                                     const double* __restrict__ t, const int32_t* __restrict__ marks,
@@ -315,7 +318,7 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
                                                     double* __restrict__ seg_part,
                                                     float* __restrict__ wchunk,
                                                     float* __restrict__ lambda_out,
-                                                    double* __restrict__ gsup) {
+                                                    double* __restrict__ gsup, int32_t cmask) {
     extern __shared__ double lds[];
     double* rtau = lds;                                   // [M] time of the record
     uint64_t* rmask = (uint64_t*)(lds + M);               // [M] lanes of this batch with mark q
@@ -483,16 +486,17 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
                 // beta w_i K_q(t_i) for each nonzero (m_i, q); the sums past
                 // the first FW nonzeros are formed again
                 const double bw = bet * w * ei;
+                double* gs = gsup + (int64_t)(s & cmask) * M * M;
 #pragma unroll
                 for (int j = 0; j < FW; ++j)
-                    if (k0 + j < k1) unsafeAtomicAdd(&gsup[k0 + j], bw * ks[j]);
+                    if (k0 + j < k1) unsafeAtomicAdd(&gs[k0 + j], bw * ks[j]);
                 for (int32_t k = k0 + FW; k < k1; ++k) {
                     double v, unused;
                     if (anch)
                         sums_a(csr_col[k], v, unused);
                     else
                         sums_w(csr_col[k], v, unused);
-                    unsafeAtomicAdd(&gsup[k], bw * v);
+                    unsafeAtomicAdd(&gs[k], bw * v);
                 }
             }
         }
@@ -634,18 +638,23 @@ __global__ __launch_bounds__(256) void large_final(int32_t M, int32_t ER, int32_
 }
 
 // support-restricted dL/dalpha: one wave per row p writes, for each nonzero
-// (p, q) of alpha, the summed first term minus the column's compensator sum
-// (cpart row 0 after large_colfold); runs after large_final zeroed g_alpha
-__global__ __launch_bounds__(64) void large_sup_scatter(int32_t M, const int32_t* __restrict__ csr_ptr,
+// (p, q) of alpha, the first term summed over the ncopy copies (in order)
+// minus the column's compensator sum (cpart row 0 after large_colfold); runs
+// after large_final zeroed g_alpha
+__global__ __launch_bounds__(64) void large_sup_scatter(int32_t M, int32_t ncopy,
+                                                        const int32_t* __restrict__ csr_ptr,
                                                         const int32_t* __restrict__ csr_col,
                                                         const double* __restrict__ gsup,
                                                         const double* __restrict__ cpart,
                                                         double* __restrict__ g_alpha) {
     const int32_t p = blockIdx.x;
+    const int64_t MM = (int64_t)M * M;
     const int32_t k1 = csr_ptr[p + 1];
     for (int32_t k = csr_ptr[p] + (int32_t)threadIdx.x; k < k1; k += 64) {
         const int32_t q = csr_col[k];
-        g_alpha[(int64_t)p * M + q] = gsup[k] - cpart[q];
+        double g = 0.0;
+        for (int32_t c = 0; c < ncopy; ++c) g += gsup[c * MM + k];
+        g_alpha[(int64_t)p * M + q] = g - cpart[q];
     }
 }
 
@@ -751,7 +760,6 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
             A.bk_w = c.take<float>(A.CH);
         }
         A.gpart = c.take<double>((size_t)A.ER * MM);
-        if (!A.per_target) A.gsup = c.take<double>((size_t)MM);   // support-restricted first term (CSR order)
         const int64_t nsp = A.per_target ? A.ER : A.NRUN;
         A.spart = c.take<double>((size_t)nsp * M);
         A.cpart_ = c.take<double>((size_t)nsp * M);
@@ -844,6 +852,10 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
         allow_lds((const void*)large_forward<false, false, false>, lds_fwd) != HAWKES_OK)
         return HAWKES_EUNSUPPORTED;
     const bool sup = A.grad && A.support;
+    // support-restricted: the first term's copies (CSR order) take the place
+    // of the dense partials, min(8, ER) of them (ER is a power of two)
+    const int32_t ncopy = A.ER < 8 ? A.ER : 8;
+    if (sup) A.gsup = A.gpart;
     // the dense-gradient kernels address checkpoints and records with
     // 32-bit byte offsets
     if (A.grad && (uint64_t)A.nslot * (uint64_t)(64 * A.CPL + 104) * 8u >= (1ull << 32))
@@ -853,7 +865,7 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
     hipLaunchKernelGGL(fill_d, dim3(1), dim3(64), 0, st, A.acc, (int64_t)4, 0.0);
     if (A.grad) {
         // the dense partials, or (support-restricted) the CSR-ordered sums
-        const int64_t ng = sup ? MM : (int64_t)A.ER * MM;
+        const int64_t ng = (sup ? ncopy : A.ER) * MM;
         hipLaunchKernelGGL(fill_d, dim3((unsigned)((ng + 255) / 256 < 65535 ? (ng + 255) / 256 : 65535)),
                            dim3(256), 0, st, sup ? A.gsup : A.gpart, ng, 0.0);
         hipLaunchKernelGGL(fill_d, dim3(64), dim3(256), 0, st, A.spart, (int64_t)A.NRUN * M, 0.0);
@@ -880,19 +892,19 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
             if (sup)
                 hipLaunchKernelGGL((large_forward<true, false, true>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1,
                                    M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
-                                   A.carry_seg, A.seg_part, A.wchunk, (float*)nullptr, A.gsup);
+                                   A.carry_seg, A.seg_part, A.wchunk, (float*)nullptr, A.gsup, ncopy - 1);
             else if (A.grad)
                 hipLaunchKernelGGL((large_forward<true, false, false>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1,
                                    M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
-                                   A.carry_seg, A.seg_part, A.wchunk, (float*)nullptr, (double*)nullptr);
+                                   A.carry_seg, A.seg_part, A.wchunk, (float*)nullptr, (double*)nullptr, 0);
             else if (A.lambda_out)
                 hipLaunchKernelGGL((large_forward<false, true, false>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1,
                                    M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
-                                   A.carry_seg, A.seg_part, A.wchunk, A.lambda_out, (double*)nullptr);
+                                   A.carry_seg, A.seg_part, A.wchunk, A.lambda_out, (double*)nullptr, 0);
             else
                 hipLaunchKernelGGL((large_forward<false, false, false>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1,
                                    M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
-                                   A.carry_seg, A.seg_part, A.wchunk, (float*)nullptr, (double*)nullptr);
+                                   A.carry_seg, A.seg_part, A.wchunk, (float*)nullptr, (double*)nullptr, 0);
         }
         hipLaunchKernelGGL(large_chunk_acc, dim3(1), dim3(256), 0, st, nseg, A.seg_part, A.acc);
         if (A.grad) {
@@ -912,8 +924,8 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
                        A.acc, A.gpart, A.spart, A.cpart_, A.loglik, A.g_mu, A.g_alpha, A.g_beta, A.grad ? 1 : 0,
                        sup ? 1 : 0);
     if (sup && A.g_alpha)
-        hipLaunchKernelGGL(large_sup_scatter, dim3((unsigned)M), dim3(64), 0, st, M, A.csr_ptr, A.csr_col, A.gsup,
-                           A.cpart_, A.g_alpha);
+        hipLaunchKernelGGL(large_sup_scatter, dim3((unsigned)M), dim3(64), 0, st, M, ncopy, A.csr_ptr, A.csr_col,
+                           A.gsup, A.cpart_, A.g_alpha);
     return hipGetLastError() == hipSuccess ? HAWKES_OK : HAWKES_EDEVICE;
 }
 
