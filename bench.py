@@ -247,6 +247,8 @@ def main() -> int:
                     help="prefix length for the sequential GPU kernel")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-seq", action="store_true")
+    ap.add_argument("--no-support", action="store_true",
+                    help="skip the support-restricted gradient's timing (c4), e.g. under a profiler")
     ap.add_argument("--chunk-log2", type=int, default=20)
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's own launch rules instead of timing the tuning candidates first")
@@ -368,12 +370,13 @@ def main() -> int:
     # the same step with dL/dalpha restricted to alpha's support
     # (hawkes_loglik_grad_support: no dense kernels, the first term of eq. 9
     # summed in the forward pass); a second figure, not the headline
-    sw, sper = _timed(lambda: H.loglik_grad(t, m, mu, al, be, w.T, args.chunk_log2, support=True),
-                      max(3, args.steps // 2), 1)
-    out["support_gradient"] = {"ms_per_step": round(sw, 4), "events_per_s": w.n / (sw / 1e3),
-                               "device_median_ms": round(sper[len(sper) // 2], 4),
-                               "nonzeros": int(np.count_nonzero(w.alpha))}
-    log(f"support-restricted gradient: {sw:.3f} ms/step, {w.n / (sw / 1e3):.4e} events/s")
+    if not args.no_support:
+        sw, sper = _timed(lambda: H.loglik_grad(t, m, mu, al, be, w.T, args.chunk_log2, support=True),
+                          max(3, args.steps // 2), 1)
+        out["support_gradient"] = {"ms_per_step": round(sw, 4), "events_per_s": w.n / (sw / 1e3),
+                                   "device_median_ms": round(sper[len(sper) // 2], 4),
+                                   "nonzeros": int(np.count_nonzero(w.alpha))}
+        log(f"support-restricted gradient: {sw:.3f} ms/step, {w.n / (sw / 1e3):.4e} events/s")
 
     # sequential-recurrence GPU kernel on a prefix
     if not args.no_seq:
