@@ -32,8 +32,11 @@
 //                wide tiles (fewer column blocks) are the fast ones.
 // The state is shared through the checkpoints instead of being rebuilt by
 // every row block.  Every window issues the same loads at the same point
-// (the next window's checkpoint and column group, the next batch of own
-// records), one window ahead, so their latency hides behind a window of work.
+// (the next window's checkpoint, column group and header, the next batch of
+// own records), one window ahead, so their latency hides behind a window of
+// work.  dense_ck writes each window's bounds into its slot's header (the
+// group's last record, the record count, the next slot of the walk), so the
+// window loop reads them with scalar loads instead of tracking runs.
 #include "hk_device.h"
 #include "hk_large.h"
 #include "hk_stream.h"
@@ -45,9 +48,13 @@ namespace hk {
 // record in the column block's share of the DR-node partition; the slots of
 // different (sb, r) never overlap, and there are at most
 // (events) / 64 + 2 NBC nrun + 1.
-// Checkpoint slot record, in float64 words: the state (W), the anchor time
-// (8 copies), the group's 64 record times, then its 64 record keys (u32, two
-// per word; lanes past the group's end hold 0xffffffff).
+// Checkpoint slot record, in float64 words: the state (W); the window's
+// header (8 words: the anchor time, the time of the group's last record,
+// then int32 the event index of that record, the record count, the next
+// slot of the column block's walk (-1: none) and the run); the group's 64
+// record times; then its 64 record keys (u32, two per word; lanes past the
+// group's end hold 0xffffffff).  The slot after a run's last group has
+// state and header only (count 0; its window runs to the run's end).
 template <int CPL>
 struct Slot {
     static constexpr int W = 64 * CPL;
@@ -150,23 +157,34 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
         q.t = t[c0 + i];
         q.w = wchunk[i];
     };
-    auto put_state = [&](int32_t g) {
+    // the state and the window's header: anchor time, time and event index
+    // of the group's last record (after the last group: the anchor and the
+    // run's last event), record count, next slot (-1: none), run
+    auto put_state = [&](int32_t g, double tcl, int32_t hi, int32_t nv, int32_t nxt) {
         double* out = kck + (int64_t)(slot0 + g) * S::SIZE;
 #pragma unroll
         for (int j = 0; j < CPL; ++j) out[j * 64 + lane] = K[j];
-        if (lane < 8) out[S::TAU + lane] = tau;
+        if (lane == 0) {
+            out[S::TAU] = tau;
+            out[S::TAU + 1] = tcl;
+            int32_t* h = reinterpret_cast<int32_t*>(out + S::TAU + 2);
+            h[0] = hi;
+            h[1] = nv;
+            h[2] = nxt;
+            h[3] = r;
+        }
     };
     // group g with records q: checkpoint, records, then the state moves past
     // the group
     auto emit = [&](const Rec& q, int32_t g) {
-        put_state(g);
         const int rem = cnt - 64 * g;
         const int nv = rem < 64 ? rem : 64;
         const bool v = lane < nv;
+        const double tn = rl_d(q.t, nv - 1);
+        put_state(g, tn, (int32_t)((uint32_t)rl_i((int)q.key, nv - 1) >> SH), nv, slot0 + g + 1);
         double* out = kck + (int64_t)(slot0 + g) * S::SIZE;
         out[S::T + lane] = v ? q.t : 0.0;
         reinterpret_cast<uint32_t*>(out + S::KEY)[lane] = q.key;
-        const double tn = rl_d(q.t, nv - 1);
         const double f = (double)exp2_f64arg((tau - tn) * bl2);
 #pragma unroll
         for (int j = 0; j < CPL; ++j) K[j] *= f;
@@ -205,7 +223,9 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
         emit(r3, g);
         ++g;
     }
-    put_state(ng);   // after the last group
+    // after the last group: the window up to the run's end, then the next
+    // run's first slot (its P0 is this run's P1)
+    put_state(ng, tau, sB * HK_SEG - 1, 0, sB < nseg ? (P1 >> 6) + 2 * (sb * nrun + r + 1) : -1);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
@@ -244,14 +264,14 @@ struct OwnBatch {
 template <int CPL>
 struct Win {
     double K[CPL];
-    double tau;   // lanes 0..7 hold it (read from lane 0)
     uint32_t ckey;
     double ct;
 };
 
-// A run of the column block: records [P0, P1), ng groups, first slot
-struct Run {
-    int32_t P0, P1, ng, slot0;
+// a window's header (wave-uniform, scalar loads)
+struct Hdr {
+    double tau, tcl;
+    int32_t hi, nv, next, run;
 };
 
 template <int CPL, int DRB>
@@ -331,15 +351,6 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
     const __amdgpu_buffer_rsrc_t rOt = buf(bo_t, (uint32_t)nrec * 8u);
     const __amdgpu_buffer_rsrc_t rOw = buf(bo_w, (uint32_t)nrec * 4u);
     const int4* rinf = runinfo + (int64_t)sb * nrun;
-    auto run_info = [&](int32_t rr) -> Run {
-        const int4 v = rinf[rr];
-        Run x;
-        x.slot0 = v.x;
-        x.ng = v.y;
-        x.P0 = v.z;
-        x.P1 = v.w;
-        return x;
-    };
     // own stream: records [Q0, Q1) of row block rb, q the next unconsumed
     // one.  o0 holds records [qL, qL + 64).  Every window refills o2 from q
     // and first moves the previous window's o2 to o1, so o1 (from q1s) is
@@ -357,13 +368,24 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
     OwnBatch o0, o1, o2;
     own_load(o0, Q0);
     own_load(o2, Q0);
-    auto load_win = [&](Win<CPL>& w, const Run& ru, int32_t gg) {
-        const uint32_t sl = (uint32_t)(ru.slot0 + gg) * S::SIZE;
+    auto load_win = [&](Win<CPL>& w, int32_t slot) {
+        const uint32_t sl = (uint32_t)slot * S::SIZE;
 #pragma unroll
         for (int j = 0; j < CPL; ++j) w.K[j] = ld_f64(rK, sl + j * 64 + lane);
-        w.tau = ld_f64(rK, sl + S::TAU + (lane & 7));
         w.ct = ld_f64(rK, sl + S::T + lane);
         w.ckey = ld_u32(rK, 2 * (sl + S::KEY) + lane);
+    };
+    auto load_hdr = [&](int32_t slot) -> Hdr {
+        const double* hp = kck + (int64_t)slot * S::SIZE + S::TAU;
+        const int32_t* hq = reinterpret_cast<const int32_t*>(hp + 2);
+        Hdr h;
+        h.tau = hp[0];
+        h.tcl = hp[1];
+        h.hi = hq[0];
+        h.nv = hq[1];
+        h.next = hq[2];
+        h.run = hq[3];
+        return h;
     };
 
     // own records of the window in o0 from lane p on (index <= hi): adds
@@ -422,41 +444,25 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
         return nsel;
     };
 
-    // window position (r, g) and the runs r and r + 1
-    int32_t r = rA, g = 0;
-    Run ru = run_info(rA < rB ? rA : gA);
-    Run rn = rA + 1 < rB ? run_info(rA + 1) : ru;
-
-    // one window with data `cur`; loads the next window into `nxt` first (the
-    // same window again after the last one, so that every window issues the
-    // same loads); false after the last window
+    // the current window: slot sc with header hc; each window loads the next
+    // one's data and header first (the same window again after the wave's
+    // last one, so that every window issues the same loads)
+    int32_t sc = 0;
+    Hdr hc;
     auto body = [&](Win<CPL>& cur, Win<CPL>& nxt) -> bool {
-        const bool same_run = g < ru.ng;
-        const bool has_next = same_run || r + 1 < rB;
-        if (same_run)
-            load_win(nxt, ru, g + 1);
-        else if (has_next)
-            load_win(nxt, rn, 0);
-        else
-            load_win(nxt, ru, g);
+        const bool last = hc.nv == 0 && hc.run >= rB - 1;
+        const int32_t sn = last ? sc : hc.next;
+        load_win(nxt, sn);
+        const Hdr hn = load_hdr(sn);
         o1 = o2;
         q1s = q2s;
         own_load(o2, q);
         q2s = q;
 
-        const bool colw = g < ru.ng;
-        int nv = 0, hi;
-        const double tw = rl_d(cur.tau, 0);
-        double tcl = tw;
-        if (colw) {
-            const int rem = ru.P1 - (ru.P0 + 64 * g);
-            nv = rem < 64 ? rem : 64;
-            hi = rl_i((int)(cur.ckey >> SH), nv - 1);
-            tcl = rl_d(cur.ct, nv - 1);
-        } else {
-            const int32_t se = (r + 1) * ckr < nseg ? (r + 1) * ckr : nseg;
-            hi = se * HK_SEG - 1;   // the run's last event index in the chunk
-        }
+        const int nv = hc.nv;
+        const int hi = hc.hi;
+        const double tw = hc.tau;
+        const double tcl = hc.tcl;
         const bool cv = lane < nv;
         const int cidx = cv ? (int)(cur.ckey >> SH) : 0x7fffffff;
         const int colj = (int)(cur.ckey & (uint32_t)(W - 1));
@@ -497,21 +503,17 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
             if (lane < DR) UL[lane] = 0.0;
             __builtin_amdgcn_wave_barrier();
         }
-        if (same_run) {
-            ++g;
-        } else if (has_next) {
-            ++r;
-            g = 0;
-            ru = rn;
-            if (r + 1 < rB) rn = run_info(r + 1);
-        }
-        return has_next;
+        sc = sn;
+        hc = hn;
+        return !last;
     };
 
     __syncthreads();
     if (rA < rB) {
+        sc = rinf[rA].x;   // the first slot of the wave's first run
+        hc = load_hdr(sc);
         Win<CPL> wa, wb;
-        load_win(wa, ru, 0);
+        load_win(wa, sc);
         for (;;) {
             if (!body(wa, wb)) break;
             if (!body(wb, wa)) break;
