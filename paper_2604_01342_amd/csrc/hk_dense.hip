@@ -52,16 +52,20 @@ namespace hk {
 // header (8 words: the anchor time, the time of the group's last record,
 // then int32 the event index of that record, the record count, the next
 // slot of the column block's walk (-1: none) and the run); the group's 64
-// record times; then its 64 record keys (u32, two per word; lanes past the
-// group's end hold 0xffffffff).  The slot after a run's last group has
-// state and header only (count 0; its window runs to the run's end).
+// record times; its 64 record keys (u32, two per word; lanes past the
+// group's end hold 0xffffffff); then the records' factors
+// e^{beta (t_j - tau)} against the window's anchor (float32, two per word,
+// 0 past the group's end), formed once here instead of once per row block.
+// The slot after a run's last group has state and header only (count 0;
+// its window runs to the run's end).
 template <int CPL>
 struct Slot {
     static constexpr int W = 64 * CPL;
     static constexpr int TAU = W;
     static constexpr int T = W + 8;
     static constexpr int KEY = W + 72;
-    static constexpr int SIZE = W + 104;
+    static constexpr int BJ = W + 104;
+    static constexpr int SIZE = W + HK_SLOT_EXTRA;
 };
 
 // One wave per (column block, run), in two phases.  (1) Scan the run's marks
@@ -185,6 +189,8 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
         double* out = kck + (int64_t)(slot0 + g) * S::SIZE;
         out[S::T + lane] = v ? q.t : 0.0;
         reinterpret_cast<uint32_t*>(out + S::KEY)[lane] = q.key;
+        // the record's factor e^{beta (t_j - tau)} against the window's anchor
+        reinterpret_cast<float*>(out + S::BJ)[lane] = v ? exp2_f64arg((q.t - tau) * bl2) : 0.0f;
         const double f = (double)exp2_f64arg((tau - tn) * bl2);
 #pragma unroll
         for (int j = 0; j < CPL; ++j) K[j] *= f;
@@ -265,7 +271,7 @@ template <int CPL>
 struct Win {
     double K[CPL];
     uint32_t ckey;
-    double ct;
+    float bj;   // e^{beta (t_j - tau)} of the group's record j (0 past the group's end)
 };
 
 // a window's header (wave-uniform, scalar loads)
@@ -372,7 +378,7 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
         const uint32_t sl = (uint32_t)slot * S::SIZE;
 #pragma unroll
         for (int j = 0; j < CPL; ++j) w.K[j] = ld_f64(rK, sl + j * 64 + lane);
-        w.ct = ld_f64(rK, sl + S::T + lane);
+        w.bj = ld_f32(rK, 2 * (sl + S::BJ) + lane);
         w.ckey = ld_u32(rK, 2 * (sl + S::KEY) + lane);
     };
     auto load_hdr = [&](int32_t slot) -> Hdr {
@@ -388,6 +394,8 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
         return h;
     };
 
+    int32_t sc = 0;   // the current window's slot
+    Hdr hc;           // and its header
     // own records of the window in o0 from lane p on (index <= hi): adds
     // their c_k to u and their pair terms to GP; returns how many there were
     auto pass = [&](const Win<CPL>& w, int p, double tw, int hi, double tcl, bool cv, int cidx, int colj,
@@ -432,13 +440,17 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
             // per-pair decays
             const double cw = bet * (double)b.w;
             if (own) atomicAdd(&UL[rowl], cw * (double)exp2_f64arg((tw - b.t) * bl2));
+            // the records' times, waited for here so that no load of this
+            // rare path stays in flight
+            const double ct = ld_f64(rK, (uint32_t)sc * S::SIZE + S::T + lane);
+            __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
             for (int k = p; k < kend; ++k) {
                 const uint32_t key = (uint32_t)rl_i((int)b.key, k);
                 const int rofs = (int)(key & (DR - 1)) * W;
                 const double tk = rl_d(b.t, k);
                 const double ck = rl_d(cw, k);
                 if (cv && cidx < (int)(key >> DRB))
-                    atomicAdd(&GP[rofs + colj], ck * (double)exp2_f64arg((w.ct - tk) * bl2));
+                    atomicAdd(&GP[rofs + colj], ck * (double)exp2_f64arg((ct - tk) * bl2));
             }
         }
         return nsel;
@@ -447,8 +459,6 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
     // the current window: slot sc with header hc; each window loads the next
     // one's data and header first (the same window again after the wave's
     // last one, so that every window issues the same loads)
-    int32_t sc = 0;
-    Hdr hc;
     auto body = [&](Win<CPL>& cur, Win<CPL>& nxt) -> bool {
         const bool last = hc.nv == 0 && hc.run >= rB - 1;
         const int32_t sn = last ? sc : hc.next;
@@ -466,7 +476,7 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
         const bool cv = lane < nv;
         const int cidx = cv ? (int)(cur.ckey >> SH) : 0x7fffffff;
         const int colj = (int)(cur.ckey & (uint32_t)(W - 1));
-        const double bj = cv ? (double)exp2_f64arg((cur.ct - tw) * bl2) : 0.0;
+        const double bj = (double)cur.bj;
         int nown = 0;
         for (;;) {
             if (q - qL == 64) {

@@ -19,6 +19,7 @@
 #define HK_CKR 4           // segments per checkpoint run of the shared-decay dense gradient
 #endif
 #define HK_WIDE 60.0       // anchored-exponent limit inside one window of the dense kernel
+#define HK_SLOT_EXTRA 136  // float64 words of a dense-gradient checkpoint slot besides the state
 
 namespace hk {
 
@@ -64,7 +65,7 @@ struct LargeArgs {
     double* gsup;         // [min(8, ER)][M*M] support-restricted first term of eq. 9 in CSR order (the
                           //   first nnz(alpha) entries of each copy; shares gpart's space)
     int64_t nslot;        // checkpoint slots
-    double* kck;          // [nslot][64 CPL + 104] state checkpoints of the dense gradient (shared
+    double* kck;          // [nslot][64 CPL + HK_SLOT_EXTRA] state checkpoints of the dense gradient (shared
                           //   decay) with their groups' records
     int4* runinfo;        // [NBC][NRUN] per checkpoint run: first slot, groups, P0, P1
     // per-target decays (R-form forward, reverse adjoint for the gradient)

@@ -765,7 +765,7 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
         A.cpart_ = c.take<double>((size_t)nsp * M);
         if (!A.per_target) {
             A.nslot = A.CH / 64 + 2 * (int64_t)A.NBC * A.NRUN + 2;
-            A.kck = c.take<double>((size_t)A.nslot * (64 * A.CPL + 104));
+            A.kck = c.take<double>((size_t)A.nslot * (64 * A.CPL + HK_SLOT_EXTRA));
             A.runinfo = c.take<int4>((size_t)A.NBC * A.NRUN);
             A.NBO = (A.M + (1 << A.DRB) - 1) >> A.DRB;
             A.bo_cnt = c.take<int32_t>((size_t)A.NBO * A.nseg);
@@ -858,7 +858,7 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
     if (sup) A.gsup = A.gpart;
     // the dense-gradient kernels address checkpoints and records with
     // 32-bit byte offsets
-    if (A.grad && (uint64_t)A.nslot * (uint64_t)(64 * A.CPL + 104) * 8u >= (1ull << 32))
+    if (A.grad && (uint64_t)A.nslot * (uint64_t)(64 * A.CPL + HK_SLOT_EXTRA) * 8u >= (1ull << 32))
         return HAWKES_EUNSUPPORTED;
     // zero the carried state and accumulators
     hipLaunchKernelGGL(fill_d, dim3(1), dim3(256), 0, st, A.carry, (int64_t)2 * M, 0.0);
