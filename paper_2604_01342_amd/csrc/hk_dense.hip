@@ -51,7 +51,8 @@ namespace hk {
 // Checkpoint slot record, in float64 words: the state (W); the window's
 // header (8 words: the anchor time, the time of the group's last record,
 // then int32 the event index of that record, the record count, the next
-// slot of the column block's walk (-1: none) and the run); the group's 64
+// slot of the column block's walk (-1: none), the run and whether the
+// window is wide, beta (last record - anchor) > HK_WIDE); the group's 64
 // record times; its 64 record keys (u32, two per word; lanes past the
 // group's end hold 0xffffffff); then the records' factors
 // e^{beta (t_j - tau)} against the window's anchor (float32, two per word,
@@ -176,6 +177,9 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
             h[1] = nv;
             h[2] = nxt;
             h[3] = r;
+            // a window with column records spans at most to its last record
+            // (own events of index <= hi are not later): wide or not is known
+            h[4] = nv > 0 && !(bet * (tcl - tau) <= HK_WIDE);
         }
     };
     // group g with records q: checkpoint, records, then the state moves past
@@ -277,7 +281,7 @@ struct Win {
 // a window's header (wave-uniform, scalar loads)
 struct Hdr {
     double tau, tcl;
-    int32_t hi, nv, next, run;
+    int32_t hi, nv, next, run, wide;
 };
 
 template <int CPL, int DRB>
@@ -391,6 +395,7 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
         h.nv = hq[1];
         h.next = hq[2];
         h.run = hq[3];
+        h.wide = hq[4];
         return h;
     };
 
@@ -398,17 +403,24 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
     Hdr hc;           // and its header
     // own records of the window in o0 from lane p on (index <= hi): adds
     // their c_k to u and their pair terms to GP; returns how many there were
-    auto pass = [&](const Win<CPL>& w, int p, double tw, int hi, double tcl, bool cv, int cidx, int colj,
+    auto pass = [&](const Win<CPL>& w, int p, double tw, int hi, bool cv, int cidx, int colj,
                     double bj) -> int {
         const OwnBatch& b = o0;
         const bool own = qL + lane < Q1 && lane >= p && (int)(b.key >> DRB) <= hi;
         const int nsel = __builtin_popcountll(__ballot(own));
         if (nsel == 0) return 0;
         const int kend = p + nsel;   // own lanes are [p, kend)
-        const double tlo = rl_d(b.t, kend - 1);
-        const double tmax = tlo > tcl ? tlo : tcl;
+        // windows with column records: the header's flag; after a run's last
+        // group: from the last selected own event
+        bool narrow;
+        if (hc.nv > 0) {
+            narrow = hc.wide == 0;
+        } else {
+            const double tlo = rl_d(b.t, kend - 1);
+            narrow = bet * (tlo - tw) <= HK_WIDE;
+        }
         const int rowl = (int)(b.key & (DR - 1));
-        if (bet * (tmax - tw) <= HK_WIDE) {
+        if (narrow) {
             const float cf = own ? (float)(bet * (double)b.w) * exp2_f64arg((tw - b.t) * bl2) : 0.0f;
             if (own) {
                 atomicAdd(&UL[rowl], (double)cf);
@@ -472,7 +484,6 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
         const int nv = hc.nv;
         const int hi = hc.hi;
         const double tw = hc.tau;
-        const double tcl = hc.tcl;
         const bool cv = lane < nv;
         const int cidx = cv ? (int)(cur.ckey >> SH) : 0x7fffffff;
         const int colj = (int)(cur.ckey & (uint32_t)(W - 1));
@@ -492,7 +503,7 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
                 o0 = o1;
                 qL = q1s;
             }
-            const int n = pass(cur, q - qL, tw, hi, tcl, cv, cidx, colj, bj);
+            const int n = pass(cur, q - qL, tw, hi, cv, cidx, colj, bj);
             q += n;
             nown += n;
             if (n == 0 || q - qL < 64) break;
