@@ -280,7 +280,7 @@ struct Win {
 
 // a window's header (wave-uniform, scalar loads)
 struct Hdr {
-    double tau, tcl;
+    double tau;   // the window's anchor (the slot also keeps its last record's time)
     int32_t hi, nv, next, run, wide;
 };
 
@@ -390,7 +390,6 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
         const int32_t* hq = reinterpret_cast<const int32_t*>(hp + 2);
         Hdr h;
         h.tau = hp[0];
-        h.tcl = hp[1];
         h.hi = hq[0];
         h.nv = hq[1];
         h.next = hq[2];
