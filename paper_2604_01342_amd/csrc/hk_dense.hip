@@ -6,36 +6,40 @@
 // 16 x 128 and 16 x 64 for chunks whose event indices need more key bits).
 //   dense_ck     one wave per (column block, run of CKR segments): walks the
 //                block's records of the run once, in groups of 64, and stores
-//                the block's state K at the start of every group and after
-//                the last one (a checkpoint: W float64 values and the anchor
-//                time tau of the state, K_q(tau) = sum over the events j of
-//                node q before the group of e^{-beta (tau - t_j)}).  A run
+//                the block's state K at the start of every window (two
+//                groups, 128 records) and after the last one (a checkpoint:
+//                W float64 values and the anchor time tau of the state,
+//                K_q(tau) = sum over the events j of node q before the
+//                window of e^{-beta (tau - t_j)}).  A run
 //                starts from the scan's carry at its first segment, so the
 //                runs are independent.  The same pass sums, per column and
 //                run, the weights w_j (dL/dmu) and the compensator terms
 //                1 - e^{-beta (T - t_j)} (their alpha-derivative).
 //   large_dense  one wave per (row block, column block, event range of whole
 //                runs).  Window g of a run holds the wave's own events (the
-//                events of its row block) with index after group g-1's last
-//                record and up to group g's last record (after the last
-//                group: up to the run's end).  Own event k adds
+//                events of its row block) with index after window g-1's last
+//                record and up to window g's last record (after the last
+//                window: up to the run's end).  Own event k adds
 //                beta w_k K(t_k^-) to row m_k, where K(t_k^-) is checkpoint g
-//                decayed to t_k plus the events of group g that precede k.
+//                decayed to t_k plus the window's records that precede k.
 //                With c_k = beta w_k e^{-beta (t_k - tau_g)} and
 //                b_j = e^{beta (t_j - tau_g)} the window adds
 //                  u K_g^T, u_p = sum of c_k over its own events of row p
 //                (a rank-1 update: DR x W float64 FMAs into G held in
 //                registers, lane = column), and c_k b_j at (m_k, m_j) for the
-//                group's records j before k (one masked ds_add_f64 per own
-//                event into an LDS tile of pair terms).  The pair terms cost
-//                a wave instruction per own event and column block, so the
-//                wide tiles (fewer column blocks) are the fast ones.
+//                window's records j before k (one masked ds_add_f64 per own
+//                event and 64 records before it, into an LDS tile of pair
+//                terms).  The pair terms cost a wave instruction per own
+//                event and column block, so the wide tiles (fewer column
+//                blocks) are the fast ones; 128-record windows halve the
+//                per-window work and the rank-1 updates per event at about
+//                1.5 pair instructions per own event.
 // The state is shared through the checkpoints instead of being rebuilt by
 // every row block.  Every window issues the same loads at the same point
 // (the next window's checkpoint, column group and header, the next batch of
 // own records), one window ahead, so their latency hides behind a window of
 // work.  dense_ck writes each window's bounds into its slot's header (the
-// group's last record, the record count, the next slot of the walk), so the
+// window's last record, the record count, the next slot of the walk), so the
 // window loop reads them with scalar loads instead of tracking runs.
 #include "hk_device.h"
 #include "hk_large.h"
@@ -43,37 +47,40 @@
 
 namespace hk {
 
-// Checkpoint slots: group g of (column block sb, run r) uses slot
-// (P0 >> 6) + 2 (sb nrun + r) + g, with P0 the position of the run's first
-// record in the column block's share of the DR-node partition; the slots of
-// different (sb, r) never overlap, and there are at most
-// (events) / 64 + 2 NBC nrun + 1.
+// Checkpoint slots: window w (groups 2w and 2w + 1) of (column block sb,
+// run r) uses slot (P0 >> 7) + 2 (sb nrun + r) + w, with P0 the position of
+// the run's first record in the column block's share of the DR-node
+// partition; the slots of different (sb, r) never overlap, and there are at
+// most (events) / 128 + 2 NBC nrun + 1.
 // Checkpoint slot record, in float64 words: the state (W); the window's
-// header (8 words: the anchor time, the time of the group's last record,
-// then int32 the event index of that record, the record count, the next
-// slot of the column block's walk (-1: none), the run and whether the
-// window is wide, beta (last record - anchor) > HK_WIDE); the group's 64
-// record times; its 64 record keys (u32, two per word; lanes past the
-// group's end hold 0xffffffff); then the records' factors
-// e^{beta (t_j - tau)} against the window's anchor (float32, two per word,
-// 0 past the group's end), formed once here instead of once per row block.
-// The slot after a run's last group has state and header only (count 0;
-// its window runs to the run's end).
+// header (8 words: the anchor time, the time of the window's last record,
+// then int32 the event index of that record, the record count (<= 128), the
+// next slot of the column block's walk (-1: none), the run, whether the
+// window is wide, beta (last record - anchor) > HK_WIDE, and the event index
+// of its 65th record (INT_MAX if none)); the window's 128 record times; its
+// 128 record keys (u32, two per word; past the records: 0xffffffff in the
+// first 64, anything in the second, which the count excludes); then the
+// records' factors e^{beta (t_j - tau)} against the window's anchor
+// (float32, two per word, 0 past the records in the first 64), formed once
+// here instead of once per row block.  The slot after a run's last window
+// has state and header only (count 0; its window runs to the run's end).
 template <int CPL>
 struct Slot {
     static constexpr int W = 64 * CPL;
     static constexpr int TAU = W;
-    static constexpr int T = W + 8;
-    static constexpr int KEY = W + 72;
-    static constexpr int BJ = W + 104;
+    static constexpr int T = W + 8;      // 128 record times
+    static constexpr int KEY = W + 136;  // 128 keys (u32)
+    static constexpr int BJ = W + 200;   // 128 factors (float32)
     static constexpr int SIZE = W + HK_SLOT_EXTRA;
 };
 
 // One wave per (column block, run), in two phases.  (1) Scan the run's marks
 // (several batches of 64 in flight) and compact the keys of the column
 // block's events, in index order, into LDS.  (2) For every group of 64 keys
-// (times and weights loaded one group ahead): write the checkpoint and the
-// group's records into its slot, then fold the group into the state.  Runs r
+// (times and weights loaded three groups ahead): at a window's first group
+// write the checkpoint, write the group's records into the window's slot
+// (and, at its last group, the header), then fold the group into the
+// state.  Runs r
 // with the same r / 8 share an XCD (their column blocks read the same
 // events).  runinfo[sb][r] = (first slot, groups, P0, P1), P0..P1 the run's
 // positions in the column block's share of the DR-node partition.
@@ -115,7 +122,7 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
         P1 += bo_off[(int64_t)k * (nseg + 1) + sB];
     }
     const int32_t ng = (P1 - P0 + 63) >> 6;
-    const int32_t slot0 = (P0 >> 6) + 2 * (sb * nrun + r);
+    const int32_t slot0 = (P0 >> 7) + 2 * (sb * nrun + r);   // one slot per pair of groups
     if (lane == 0) runinfo[(int64_t)sb * nrun + r] = make_int4(slot0, ng, P0, P1);
 
     // (1) compaction (at most ckr * HK_SEG keys)
@@ -162,15 +169,21 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
         q.t = t[c0 + i];
         q.w = wchunk[i];
     };
-    // the state and the window's header: anchor time, time and event index
-    // of the group's last record (after the last group: the anchor and the
-    // run's last event), record count, next slot (-1: none), run
-    auto put_state = [&](int32_t g, double tcl, int32_t hi, int32_t nv, int32_t nxt) {
-        double* out = kck + (int64_t)(slot0 + g) * S::SIZE;
+    // a window's state (at its first group) and header: anchor time, time
+    // and event index of the window's last record (after the last window:
+    // the anchor and the run's last event), record count, next slot (-1:
+    // none), run, wide flag, index of the 65th record
+    double tau_w = tau;   // the current window's anchor (state time at its first group)
+    auto put_k = [&](int32_t w) {
+        double* out = kck + (int64_t)(slot0 + w) * S::SIZE;
 #pragma unroll
         for (int j = 0; j < CPL; ++j) out[j * 64 + lane] = K[j];
+        tau_w = tau;
+    };
+    auto put_hdr = [&](int32_t w, double tcl, int32_t hi, int32_t nv, int32_t nxt, int32_t first1) {
+        double* out = kck + (int64_t)(slot0 + w) * S::SIZE;
         if (lane == 0) {
-            out[S::TAU] = tau;
+            out[S::TAU] = tau_w;
             out[S::TAU + 1] = tcl;
             int32_t* h = reinterpret_cast<int32_t*>(out + S::TAU + 2);
             h[0] = hi;
@@ -179,7 +192,8 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
             h[3] = r;
             // a window with column records spans at most to its last record
             // (own events of index <= hi are not later): wide or not is known
-            h[4] = nv > 0 && !(bet * (tcl - tau) <= HK_WIDE);
+            h[4] = nv > 0 && !(bet * (tcl - tau_w) <= HK_WIDE);
+            h[5] = first1;
         }
     };
     // group g with records q: checkpoint, records, then the state moves past
@@ -189,12 +203,16 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
         const int nv = rem < 64 ? rem : 64;
         const bool v = lane < nv;
         const double tn = rl_d(q.t, nv - 1);
-        put_state(g, tn, (int32_t)((uint32_t)rl_i((int)q.key, nv - 1) >> SH), nv, slot0 + g + 1);
-        double* out = kck + (int64_t)(slot0 + g) * S::SIZE;
-        out[S::T + lane] = v ? q.t : 0.0;
-        reinterpret_cast<uint32_t*>(out + S::KEY)[lane] = q.key;
-        // the record's factor e^{beta (t_j - tau)} against the window's anchor
-        reinterpret_cast<float*>(out + S::BJ)[lane] = v ? exp2_f64arg((q.t - tau) * bl2) : 0.0f;
+        const int32_t w = g >> 1, half = (g & 1) * 64;
+        if (half == 0) put_k(w);
+        if (half != 0 || g + 1 == ng)
+            put_hdr(w, tn, (int32_t)((uint32_t)rl_i((int)q.key, nv - 1) >> SH), half + nv, slot0 + w + 1,
+                    half != 0 ? (int32_t)((uint32_t)rl_i((int)q.key, 0) >> SH) : 0x7fffffff);
+        double* out = kck + (int64_t)(slot0 + w) * S::SIZE;
+        out[S::T + half + lane] = v ? q.t : 0.0;
+        reinterpret_cast<uint32_t*>(out + S::KEY)[half + lane] = q.key;
+        // the record's factor e^{beta (t_j - tau_w)} against the window's anchor
+        reinterpret_cast<float*>(out + S::BJ)[half + lane] = v ? exp2_f64arg((q.t - tau_w) * bl2) : 0.0f;
         const double f = (double)exp2_f64arg((tau - tn) * bl2);
 #pragma unroll
         for (int j = 0; j < CPL; ++j) K[j] *= f;
@@ -235,7 +253,9 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
     }
     // after the last group: the window up to the run's end, then the next
     // run's first slot (its P0 is this run's P1)
-    put_state(ng, tau, sB * HK_SEG - 1, 0, sB < nseg ? (P1 >> 6) + 2 * (sb * nrun + r + 1) : -1);
+    const int32_t np = (ng + 1) >> 1;
+    put_k(np);
+    put_hdr(np, tau, sB * HK_SEG - 1, 0, sB < nseg ? (P1 >> 7) + 2 * (sb * nrun + r + 1) : -1, 0x7fffffff);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
@@ -269,19 +289,19 @@ struct OwnBatch {
     float w;
 };
 
-// Data of one window: checkpoint (state, anchor time) and the group's column
+// Data of one window: the checkpoint's state and the window's column
 // records.
 template <int CPL>
 struct Win {
     double K[CPL];
-    uint32_t ckey;
-    float bj;   // e^{beta (t_j - tau)} of the group's record j (0 past the group's end)
+    uint32_t ckey0, ckey1;   // records lane and 64 + lane of the window
+    float bj0, bj1;          // their e^{beta (t_j - tau)} (0 past the window's records)
 };
 
 // a window's header (wave-uniform, scalar loads)
 struct Hdr {
     double tau;   // the window's anchor (the slot also keeps its last record's time)
-    int32_t hi, nv, next, run, wide;
+    int32_t hi, nv, next, run, wide, first1;
 };
 
 template <int CPL, int DRB>
@@ -382,8 +402,10 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
         const uint32_t sl = (uint32_t)slot * S::SIZE;
 #pragma unroll
         for (int j = 0; j < CPL; ++j) w.K[j] = ld_f64(rK, sl + j * 64 + lane);
-        w.bj = ld_f32(rK, 2 * (sl + S::BJ) + lane);
-        w.ckey = ld_u32(rK, 2 * (sl + S::KEY) + lane);
+        w.bj0 = ld_f32(rK, 2 * (sl + S::BJ) + lane);
+        w.bj1 = ld_f32(rK, 2 * (sl + S::BJ) + 64 + lane);
+        w.ckey0 = ld_u32(rK, 2 * (sl + S::KEY) + lane);
+        w.ckey1 = ld_u32(rK, 2 * (sl + S::KEY) + 64 + lane);
     };
     auto load_hdr = [&](int32_t slot) -> Hdr {
         const double* hp = kck + (int64_t)slot * S::SIZE + S::TAU;
@@ -395,6 +417,7 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
         h.next = hq[2];
         h.run = hq[3];
         h.wide = hq[4];
+        h.first1 = hq[5];
         return h;
     };
 
@@ -402,8 +425,8 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
     Hdr hc;           // and its header
     // own records of the window in o0 from lane p on (index <= hi): adds
     // their c_k to u and their pair terms to GP; returns how many there were
-    auto pass = [&](const Win<CPL>& w, int p, double tw, int hi, bool cv, int cidx, int colj,
-                    double bj) -> int {
+    auto pass = [&](const Win<CPL>& w, int p, double tw, int hi, bool cv0, bool cv1, int cidx0, int cidx1,
+                    int colj0, int colj1, double bj0, double bj1) -> int {
         const OwnBatch& b = o0;
         const bool own = qL + lane < Q1 && lane >= p && (int)(b.key >> DRB) <= hi;
         const int nsel = __builtin_popcountll(__ballot(own));
@@ -428,11 +451,14 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
                 OD[lane] = make_double2(__hiloint2double(rowl * W, (int)(b.key >> DRB)), (double)cf);
             }
             // pair terms: own event k adds c_k b_j at (row_k, m_j) for the
-            // group's records j before it (zero elsewhere)
+            // window's records j before it (zero elsewhere)
             auto pair = [&](const double2 od) {
                 const int rofs = __double2hiint(od.x), ik = __double2loint(od.x);
-                const double v = cidx < ik ? od.y * bj : 0.0;
-                atomicAdd(&GP[rofs + colj], v);
+                atomicAdd(&GP[rofs + colj0], cidx0 < ik ? od.y * bj0 : 0.0);
+                // the window's second 64 records only for an own event after
+                // the first of them
+                if (__builtin_amdgcn_readfirstlane(ik) > hc.first1)
+                    atomicAdd(&GP[rofs + colj1], cidx1 < ik ? od.y * bj1 : 0.0);
             };
             // two at a time, the next two entries read before this pair's
             // atomics (entries past kend are read but not used)
@@ -453,15 +479,18 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
             if (own) atomicAdd(&UL[rowl], cw * (double)exp2_f64arg((tw - b.t) * bl2));
             // the records' times, waited for here so that no load of this
             // rare path stays in flight
-            const double ct = ld_f64(rK, (uint32_t)sc * S::SIZE + S::T + lane);
+            const double ct0 = ld_f64(rK, (uint32_t)sc * S::SIZE + S::T + lane);
+            const double ct1 = ld_f64(rK, (uint32_t)sc * S::SIZE + S::T + 64 + lane);
             __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
             for (int k = p; k < kend; ++k) {
                 const uint32_t key = (uint32_t)rl_i((int)b.key, k);
                 const int rofs = (int)(key & (DR - 1)) * W;
                 const double tk = rl_d(b.t, k);
                 const double ck = rl_d(cw, k);
-                if (cv && cidx < (int)(key >> DRB))
-                    atomicAdd(&GP[rofs + colj], ck * (double)exp2_f64arg((ct - tk) * bl2));
+                if (cv0 && cidx0 < (int)(key >> DRB))
+                    atomicAdd(&GP[rofs + colj0], ck * (double)exp2_f64arg((ct0 - tk) * bl2));
+                if (cv1 && cidx1 < (int)(key >> DRB))
+                    atomicAdd(&GP[rofs + colj1], ck * (double)exp2_f64arg((ct1 - tk) * bl2));
             }
         }
         return nsel;
@@ -483,10 +512,12 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
         const int nv = hc.nv;
         const int hi = hc.hi;
         const double tw = hc.tau;
-        const bool cv = lane < nv;
-        const int cidx = cv ? (int)(cur.ckey >> SH) : 0x7fffffff;
-        const int colj = (int)(cur.ckey & (uint32_t)(W - 1));
-        const double bj = (double)cur.bj;
+        const bool cv0 = lane < nv, cv1 = lane + 64 < nv;
+        const int cidx0 = cv0 ? (int)(cur.ckey0 >> SH) : 0x7fffffff;
+        const int cidx1 = cv1 ? (int)(cur.ckey1 >> SH) : 0x7fffffff;
+        const int colj0 = (int)(cur.ckey0 & (uint32_t)(W - 1));
+        const int colj1 = (int)(cur.ckey1 & (uint32_t)(W - 1));
+        const double bj0 = (double)cur.bj0, bj1 = (double)cur.bj1;
         int nown = 0;
         for (;;) {
             if (q - qL == 64) {
@@ -502,7 +533,7 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
                 o0 = o1;
                 qL = q1s;
             }
-            const int n = pass(cur, q - qL, tw, hi, cv, cidx, colj, bj);
+            const int n = pass(cur, q - qL, tw, hi, cv0, cv1, cidx0, cidx1, colj0, colj1, bj0, bj1);
             q += n;
             nown += n;
             if (n == 0 || q - qL < 64) break;

@@ -19,7 +19,7 @@
 #define HK_CKR 4           // segments per checkpoint run of the shared-decay dense gradient
 #endif
 #define HK_WIDE 60.0       // anchored-exponent limit inside one window of the dense kernel
-#define HK_SLOT_EXTRA 136  // float64 words of a dense-gradient checkpoint slot besides the state
+#define HK_SLOT_EXTRA 264  // float64 words of a dense-gradient checkpoint slot besides the state
 
 namespace hk {
 

@@ -764,7 +764,7 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
         A.spart = c.take<double>((size_t)nsp * M);
         A.cpart_ = c.take<double>((size_t)nsp * M);
         if (!A.per_target) {
-            A.nslot = A.CH / 64 + 2 * (int64_t)A.NBC * A.NRUN + 2;
+            A.nslot = A.CH / 128 + 2 * (int64_t)A.NBC * A.NRUN + 2;
             A.kck = c.take<double>((size_t)A.nslot * (64 * A.CPL + HK_SLOT_EXTRA));
             A.runinfo = c.take<int4>((size_t)A.NBC * A.NRUN);
             A.NBO = (A.M + (1 << A.DRB) - 1) >> A.DRB;
