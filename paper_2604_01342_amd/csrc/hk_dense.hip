@@ -64,14 +64,16 @@ namespace hk {
 // (float32, two per word, 0 past the records in the first 64), formed once
 // here instead of once per row block.  The slot after a run's last window
 // has state and header only (count 0; its window runs to the run's end).
-template <int CPL>
+template <int CPL, int NGW>
 struct Slot {
     static constexpr int W = 64 * CPL;
+    static constexpr int NR = 64 * NGW;          // records per window
     static constexpr int TAU = W;
-    static constexpr int T = W + 8;      // 128 record times
-    static constexpr int KEY = W + 136;  // 128 keys (u32)
-    static constexpr int BJ = W + 200;   // 128 factors (float32)
-    static constexpr int SIZE = W + HK_SLOT_EXTRA;
+    static constexpr int T = W + 8;              // NR record times
+    static constexpr int KEY = T + NR;           // NR keys (u32)
+    static constexpr int BJ = KEY + NR / 2;      // NR factors (float32)
+    static constexpr int SIZE = BJ + NR / 2;
+    static_assert(SIZE == HK_SLOT_WORDS(CPL, NGW), "slot layout");
 };
 
 // One wave per (column block, run), in two phases.  (1) Scan the run's marks
@@ -84,7 +86,7 @@ struct Slot {
 // with the same r / 8 share an XCD (their column blocks read the same
 // events).  runinfo[sb][r] = (first slot, groups, P0, P1), P0..P1 the run's
 // positions in the column block's share of the DR-node partition.
-template <int CPL, int DRB>
+template <int CPL, int DRB, int NGW>
 __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t M, int32_t NBC, int32_t NBO,
                                                int32_t nrun, int32_t ckr, int32_t nseg, double T,
                                                const double* __restrict__ t, const int32_t* __restrict__ marks,
@@ -94,7 +96,7 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
                                                const int32_t* __restrict__ bo_base, double* __restrict__ kck,
                                                int4* __restrict__ runinfo, double* __restrict__ spart,
                                                double* __restrict__ cpart) {
-    using S = Slot<CPL>;
+    using S = Slot<CPL, NGW>;
     constexpr int W = S::W;
     constexpr int DR = 1 << DRB;
     constexpr int SH = CPL == 4 ? 8 : CPL == 2 ? 7 : 6;   // bits of the local mark in a record key
@@ -122,7 +124,7 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
         P1 += bo_off[(int64_t)k * (nseg + 1) + sB];
     }
     const int32_t ng = (P1 - P0 + 63) >> 6;
-    const int32_t slot0 = (P0 >> 7) + 2 * (sb * nrun + r);   // one slot per pair of groups
+    const int32_t slot0 = (P0 >> (NGW == 2 ? 7 : 6)) + 2 * (sb * nrun + r);   // one slot per window
     if (lane == 0) runinfo[(int64_t)sb * nrun + r] = make_int4(slot0, ng, P0, P1);
 
     // (1) compaction (at most ckr * HK_SEG keys)
@@ -203,9 +205,9 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
         const int nv = rem < 64 ? rem : 64;
         const bool v = lane < nv;
         const double tn = rl_d(q.t, nv - 1);
-        const int32_t w = g >> 1, half = (g & 1) * 64;
+        const int32_t w = g / NGW, half = (g % NGW) * 64;
         if (half == 0) put_k(w);
-        if (half != 0 || g + 1 == ng)
+        if (half == 64 * (NGW - 1) || g + 1 == ng)
             put_hdr(w, tn, (int32_t)((uint32_t)rl_i((int)q.key, nv - 1) >> SH), half + nv, slot0 + w + 1,
                     half != 0 ? (int32_t)((uint32_t)rl_i((int)q.key, 0) >> SH) : 0x7fffffff);
         double* out = kck + (int64_t)(slot0 + w) * S::SIZE;
@@ -253,9 +255,10 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
     }
     // after the last group: the window up to the run's end, then the next
     // run's first slot (its P0 is this run's P1)
-    const int32_t np = (ng + 1) >> 1;
+    const int32_t np = (ng + NGW - 1) / NGW;
     put_k(np);
-    put_hdr(np, tau, sB * HK_SEG - 1, 0, sB < nseg ? (P1 >> 7) + 2 * (sb * nrun + r + 1) : -1, 0x7fffffff);
+    put_hdr(np, tau, sB * HK_SEG - 1, 0, sB < nseg ? (P1 >> (NGW == 2 ? 7 : 6)) + 2 * (sb * nrun + r + 1) : -1,
+            0x7fffffff);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
@@ -291,11 +294,11 @@ struct OwnBatch {
 
 // Data of one window: the checkpoint's state and the window's column
 // records.
-template <int CPL>
+template <int CPL, int NGW>
 struct Win {
     double K[CPL];
-    uint32_t ckey0, ckey1;   // records lane and 64 + lane of the window
-    float bj0, bj1;          // their e^{beta (t_j - tau)} (0 past the window's records)
+    uint32_t ckey[NGW];   // records lane and 64 + lane of the window
+    float bj[NGW];        // their e^{beta (t_j - tau)} (0 past the window's records)
 };
 
 // a window's header (wave-uniform, scalar loads)
@@ -304,7 +307,7 @@ struct Hdr {
     int32_t hi, nv, next, run, wide, first1;
 };
 
-template <int CPL, int DRB>
+template <int CPL, int DRB, int NGW>
 __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 << DRB) * CPL > 32 ? 2 : 3))) void large_dense(int32_t M, int32_t NBC, int32_t NBR, int32_t ER, int32_t rpr,
                                                   int32_t nrun, int32_t ckr, int32_t nseg, int32_t nrec,
                                                   int32_t nslot, const float* __restrict__ beta,
@@ -314,7 +317,7 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
                                                   const uint32_t* __restrict__ bo_key,
                                                   const double* __restrict__ bo_t, const float* __restrict__ bo_w,
                                                   const double* __restrict__ kck, double* __restrict__ gpart) {
-    using S = Slot<CPL>;
+    using S = Slot<CPL, NGW>;
     constexpr int W = S::W;
     constexpr int DR = 1 << DRB;
     constexpr int SH = CPL == 4 ? 8 : CPL == 2 ? 7 : 6;   // bits of the local mark in a column record key
@@ -398,14 +401,15 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
     OwnBatch o0, o1, o2;
     own_load(o0, Q0);
     own_load(o2, Q0);
-    auto load_win = [&](Win<CPL>& w, int32_t slot) {
+    auto load_win = [&](Win<CPL, NGW>& w, int32_t slot) {
         const uint32_t sl = (uint32_t)slot * S::SIZE;
 #pragma unroll
         for (int j = 0; j < CPL; ++j) w.K[j] = ld_f64(rK, sl + j * 64 + lane);
-        w.bj0 = ld_f32(rK, 2 * (sl + S::BJ) + lane);
-        w.bj1 = ld_f32(rK, 2 * (sl + S::BJ) + 64 + lane);
-        w.ckey0 = ld_u32(rK, 2 * (sl + S::KEY) + lane);
-        w.ckey1 = ld_u32(rK, 2 * (sl + S::KEY) + 64 + lane);
+#pragma unroll
+        for (int h = 0; h < NGW; ++h) {
+            w.bj[h] = ld_f32(rK, 2 * (sl + S::BJ) + 64 * h + lane);
+            w.ckey[h] = ld_u32(rK, 2 * (sl + S::KEY) + 64 * h + lane);
+        }
     };
     auto load_hdr = [&](int32_t slot) -> Hdr {
         const double* hp = kck + (int64_t)slot * S::SIZE + S::TAU;
@@ -425,7 +429,7 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
     Hdr hc;           // and its header
     // own records of the window in o0 from lane p on (index <= hi): adds
     // their c_k to u and their pair terms to GP; returns how many there were
-    auto pass = [&](const Win<CPL>& w, int p, double tw, int hi, bool cv0, bool cv1, int cidx0, int cidx1,
+    auto pass = [&](const Win<CPL, NGW>& w, int p, double tw, int hi, bool cv0, bool cv1, int cidx0, int cidx1,
                     int colj0, int colj1, double bj0, double bj1) -> int {
         const OwnBatch& b = o0;
         const bool own = qL + lane < Q1 && lane >= p && (int)(b.key >> DRB) <= hi;
@@ -457,7 +461,7 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
                 atomicAdd(&GP[rofs + colj0], cidx0 < ik ? od.y * bj0 : 0.0);
                 // the window's second 64 records only for an own event after
                 // the first of them
-                if (__builtin_amdgcn_readfirstlane(ik) > hc.first1)
+                if (NGW == 2 && __builtin_amdgcn_readfirstlane(ik) > hc.first1)
                     atomicAdd(&GP[rofs + colj1], cidx1 < ik ? od.y * bj1 : 0.0);
             };
             // two at a time, the next two entries read before this pair's
@@ -480,7 +484,7 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
             // the records' times, waited for here so that no load of this
             // rare path stays in flight
             const double ct0 = ld_f64(rK, (uint32_t)sc * S::SIZE + S::T + lane);
-            const double ct1 = ld_f64(rK, (uint32_t)sc * S::SIZE + S::T + 64 + lane);
+            const double ct1 = NGW == 2 ? ld_f64(rK, (uint32_t)sc * S::SIZE + S::T + 64 + lane) : 0.0;
             __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
             for (int k = p; k < kend; ++k) {
                 const uint32_t key = (uint32_t)rl_i((int)b.key, k);
@@ -489,7 +493,7 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
                 const double ck = rl_d(cw, k);
                 if (cv0 && cidx0 < (int)(key >> DRB))
                     atomicAdd(&GP[rofs + colj0], ck * (double)exp2_f64arg((ct0 - tk) * bl2));
-                if (cv1 && cidx1 < (int)(key >> DRB))
+                if (NGW == 2 && cv1 && cidx1 < (int)(key >> DRB))
                     atomicAdd(&GP[rofs + colj1], ck * (double)exp2_f64arg((ct1 - tk) * bl2));
             }
         }
@@ -499,7 +503,7 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
     // the current window: slot sc with header hc; each window loads the next
     // one's data and header first (the same window again after the wave's
     // last one, so that every window issues the same loads)
-    auto body = [&](Win<CPL>& cur, Win<CPL>& nxt) -> bool {
+    auto body = [&](Win<CPL, NGW>& cur, Win<CPL, NGW>& nxt) -> bool {
         const bool last = hc.nv == 0 && hc.run >= rB - 1;
         const int32_t sn = last ? sc : hc.next;
         load_win(nxt, sn);
@@ -512,12 +516,12 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
         const int nv = hc.nv;
         const int hi = hc.hi;
         const double tw = hc.tau;
-        const bool cv0 = lane < nv, cv1 = lane + 64 < nv;
-        const int cidx0 = cv0 ? (int)(cur.ckey0 >> SH) : 0x7fffffff;
-        const int cidx1 = cv1 ? (int)(cur.ckey1 >> SH) : 0x7fffffff;
-        const int colj0 = (int)(cur.ckey0 & (uint32_t)(W - 1));
-        const int colj1 = (int)(cur.ckey1 & (uint32_t)(W - 1));
-        const double bj0 = (double)cur.bj0, bj1 = (double)cur.bj1;
+        const bool cv0 = lane < nv, cv1 = NGW == 2 && lane + 64 < nv;
+        const int cidx0 = cv0 ? (int)(cur.ckey[0] >> SH) : 0x7fffffff;
+        const int cidx1 = cv1 ? (int)(cur.ckey[NGW - 1] >> SH) : 0x7fffffff;
+        const int colj0 = (int)(cur.ckey[0] & (uint32_t)(W - 1));
+        const int colj1 = (int)(cur.ckey[NGW - 1] & (uint32_t)(W - 1));
+        const double bj0 = (double)cur.bj[0], bj1 = (double)cur.bj[NGW - 1];
         int nown = 0;
         for (;;) {
             if (q - qL == 64) {
@@ -563,7 +567,7 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
     if (rA < rB) {
         sc = rinf[rA].x;   // the first slot of the wave's first run
         hc = load_hdr(sc);
-        Win<CPL> wa, wb;
+        Win<CPL, NGW> wa, wb;
         load_win(wa, sc);
         for (;;) {
             if (!body(wa, wb)) break;
@@ -594,13 +598,13 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
     }
 }
 
-template <int CPL, int DRB>
+template <int CPL, int DRB, int NGW>
 static void dense_launch_t(LargeArgs& A, int64_t c0, int32_t nev, int32_t nseg, int32_t nrun_c, hipStream_t st,
                            bool ck_only) {
     {
         TimedScope tk(7, st);
         const unsigned nck = (unsigned)(((nrun_c + 7) / 8) * 8 * A.NBC);
-        hipLaunchKernelGGL((dense_ck<CPL, DRB>), dim3(nck), dim3(64), 0, st, c0, nev, A.M, A.NBC, A.NBO, A.NRUN,
+        hipLaunchKernelGGL((dense_ck<CPL, DRB, NGW>), dim3(nck), dim3(64), 0, st, c0, nev, A.M, A.NBC, A.NBO, A.NRUN,
                            A.CKR, nseg, A.T, A.t, A.marks, A.wchunk, A.beta, A.carry_seg, A.bo_off, A.bo_base,
                            A.kck, A.runinfo, A.spart, A.cpart_);
     }
@@ -610,7 +614,7 @@ static void dense_launch_t(LargeArgs& A, int64_t c0, int32_t nev, int32_t nseg, 
     const int32_t nbb = A.NBR * A.NBC;
     const unsigned nblk = A.ER >= 8 ? (unsigned)(nbb * ((A.ER + 7) / 8) * 8)
                                     : (unsigned)(((nbb + 8 / A.ER - 1) / (8 / A.ER)) * 8);
-    hipLaunchKernelGGL((large_dense<CPL, DRB>), dim3(nblk), dim3(64 * HK_DW), 0, st, A.M, A.NBC, A.NBR, A.ER, rpr,
+    hipLaunchKernelGGL((large_dense<CPL, DRB, NGW>), dim3(nblk), dim3(64 * HK_DW), 0, st, A.M, A.NBC, A.NBR, A.ER, rpr,
                        A.NRUN, A.CKR, nseg, nev, (int32_t)A.nslot, A.beta, A.runinfo, A.bo_off, A.bo_base, A.bo_key,
                        A.bo_t, A.bo_w, A.kck, A.gpart);
 }
@@ -619,12 +623,22 @@ void large_dense_launch(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, hipS
     const int32_t nrun_c = (nseg + A.CKR - 1) / A.CKR;
     const int32_t nev = (int32_t)(c1 - c0);
     // the tiles the layout selects: 16 x 256, 16 x 128, 16 x 64
-    if (A.CPL == 4)
-        dense_launch_t<4, 4>(A, c0, nev, nseg, nrun_c, st, ck_only);
-    else if (A.CPL == 2)
-        dense_launch_t<2, 4>(A, c0, nev, nseg, nrun_c, st, ck_only);
-    else
-        dense_launch_t<1, 4>(A, c0, nev, nseg, nrun_c, st, ck_only);
+    // and the window length the layout selects (A.NGW groups of 64 records)
+    if (A.NGW == 2) {
+        if (A.CPL == 4)
+            dense_launch_t<4, 4, 2>(A, c0, nev, nseg, nrun_c, st, ck_only);
+        else if (A.CPL == 2)
+            dense_launch_t<2, 4, 2>(A, c0, nev, nseg, nrun_c, st, ck_only);
+        else
+            dense_launch_t<1, 4, 2>(A, c0, nev, nseg, nrun_c, st, ck_only);
+    } else {
+        if (A.CPL == 4)
+            dense_launch_t<4, 4, 1>(A, c0, nev, nseg, nrun_c, st, ck_only);
+        else if (A.CPL == 2)
+            dense_launch_t<2, 4, 1>(A, c0, nev, nseg, nrun_c, st, ck_only);
+        else
+            dense_launch_t<1, 4, 1>(A, c0, nev, nseg, nrun_c, st, ck_only);
+    }
 }
 
 }  // namespace hk

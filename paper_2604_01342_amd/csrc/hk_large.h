@@ -19,7 +19,9 @@
 #define HK_CKR 4           // segments per checkpoint run of the shared-decay dense gradient
 #endif
 #define HK_WIDE 60.0       // anchored-exponent limit inside one window of the dense kernel
-#define HK_SLOT_EXTRA 264  // float64 words of a dense-gradient checkpoint slot besides the state
+// float64 words of a dense-gradient checkpoint slot: state, header, and
+// per record (64 NGW of them) its time, key and factor
+#define HK_SLOT_WORDS(CPL, NGW) (64 * (CPL) + 8 + 128 * (NGW))
 
 namespace hk {
 
@@ -36,6 +38,7 @@ struct LargeArgs {
     int32_t NBR;          // row blocks of the dense kernel (DR rows shared decay, HK_RB per target)
     int32_t CPL;          // columns per lane of the shared-decay dense kernel (1, 2, 4 or 8)
     int32_t DRB;          // log2 of DR, the rows per block of the shared-decay dense kernel
+    int32_t NGW;          // groups of 64 column records per window of the shared-decay dense kernel (1, 2)
     int32_t NBC;          // column blocks of the dense kernel (64 CPL columns each)
     int32_t CKR;          // segments per checkpoint run (shared decay)
     int32_t NRUN;         // checkpoint runs per chunk (nseg / CKR)
@@ -65,7 +68,7 @@ struct LargeArgs {
     double* gsup;         // [min(8, ER)][M*M] support-restricted first term of eq. 9 in CSR order (the
                           //   first nnz(alpha) entries of each copy; shares gpart's space)
     int64_t nslot;        // checkpoint slots
-    double* kck;          // [nslot][64 CPL + HK_SLOT_EXTRA] state checkpoints of the dense gradient (shared
+    double* kck;          // [nslot][HK_SLOT_WORDS(CPL, NGW)] state checkpoints of the dense gradient (shared
                           //   decay) with their groups' records
     int4* runinfo;        // [NBC][NRUN] per checkpoint run: first slot, groups, P0, P1
     // per-target decays (R-form forward, reverse adjoint for the gradient)

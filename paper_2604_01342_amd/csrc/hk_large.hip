@@ -686,6 +686,14 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
         if (lg <= vlg) A.CPL = v;
     }
     A.DRB = 4;
+    // window length of the dense kernel: a 64-record window holds about
+    // 1024 / max(W, M) own events of a 16-row block; with fewer than 8 the
+    // rank-1 update's u is mostly zero, and 128-record windows halve the
+    // per-window work at about 1.5 pair instructions per own event
+    {
+        const int Wc = 64 * A.CPL;
+        A.NGW = !A.per_target && 1024 / (Wc > A.M ? Wc : A.M) < 8 ? 2 : 1;
+    }
     A.NBR = A.per_target ? A.NB : (A.M + (1 << A.DRB) - 1) >> A.DRB;
     A.NBC = A.per_target ? A.NB : (A.M + 64 * A.CPL - 1) / (64 * A.CPL);
     // event ranges per chunk for the dense kernel: a power of two so that the
@@ -764,8 +772,8 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
         A.spart = c.take<double>((size_t)nsp * M);
         A.cpart_ = c.take<double>((size_t)nsp * M);
         if (!A.per_target) {
-            A.nslot = A.CH / 128 + 2 * (int64_t)A.NBC * A.NRUN + 2;
-            A.kck = c.take<double>((size_t)A.nslot * (64 * A.CPL + HK_SLOT_EXTRA));
+            A.nslot = A.CH / (64 * A.NGW) + 2 * (int64_t)A.NBC * A.NRUN + 2;
+            A.kck = c.take<double>((size_t)A.nslot * HK_SLOT_WORDS(A.CPL, A.NGW));
             A.runinfo = c.take<int4>((size_t)A.NBC * A.NRUN);
             A.NBO = (A.M + (1 << A.DRB) - 1) >> A.DRB;
             A.bo_cnt = c.take<int32_t>((size_t)A.NBO * A.nseg);
@@ -858,7 +866,7 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
     if (sup) A.gsup = A.gpart;
     // the dense-gradient kernels address checkpoints and records with
     // 32-bit byte offsets
-    if (A.grad && (uint64_t)A.nslot * (uint64_t)(64 * A.CPL + HK_SLOT_EXTRA) * 8u >= (1ull << 32))
+    if (A.grad && (uint64_t)A.nslot * (uint64_t)HK_SLOT_WORDS(A.CPL, A.NGW) * 8u >= (1ull << 32))
         return HAWKES_EUNSUPPORTED;
     // zero the carried state and accumulators
     hipLaunchKernelGGL(fill_d, dim3(1), dim3(256), 0, st, A.carry, (int64_t)2 * M, 0.0);
