@@ -67,7 +67,7 @@
 extern "C" {
 #endif
 
-#define HAWKES_ABI_VERSION 3
+#define HAWKES_ABI_VERSION 4
 
 typedef enum hawkes_status {
     HAWKES_OK = 0,
@@ -197,7 +197,10 @@ hawkes_status hawkes_intensity(const hawkes_problem* p,
  * off-diagonal entries below h (compared as float32) and 0 elsewhere;
  * lambda1 = 0 gives the plain per-event NLL.  First and second moments are
  * float32, bias corrections come from a step counter kept in the device
- * state, then mu >= floor_mu, alpha >= 0, beta >= floor_beta.  All gradient
+ * state, then mu >= floor_mu, alpha >= 0, beta >= floor_beta.  Flag bits
+ * HAWKES_ADAM_LOG_MU and HAWKES_ADAM_LOG_BETA make the step act on log mu
+ * and log beta instead (gradient x dL/dx, update x <- x e^{-lr step}, then
+ * the floor): relative steps, for parameters far smaller than lr.  All gradient
  * outputs are required (they hold the gradient of L, without the penalty,
  * at the parameters before the step; so is loglik).  The call is
  * stream-ordered and host-sync-free, so a whole step can be captured in a
@@ -205,10 +208,14 @@ hawkes_status hawkes_intensity(const hawkes_problem* p,
  * The state (size from hawkes_adam_state_bytes, caller-owned device memory)
  * must be zeroed once with hawkes_adam_init before the first step.
  * ------------------------------------------------------------------------- */
+#define HAWKES_ADAM_LOG_MU 1u
+#define HAWKES_ADAM_LOG_BETA 2u
+
 typedef struct hawkes_adam {
     float lr, beta1, beta2, eps;   /* step size, moment decays, denominator floor */
     float floor_mu, floor_beta;    /* projection bounds (floor_beta > 0) */
     float lambda1, h;              /* penalty weight (>= 0) and hinge point (> 0 when lambda1 > 0) */
+    uint32_t flags;                /* HAWKES_ADAM_LOG_MU | HAWKES_ADAM_LOG_BETA; other bits must be 0 */
 } hawkes_adam;
 
 size_t hawkes_adam_state_bytes(const hawkes_problem* p);

@@ -52,12 +52,14 @@ __global__ void adam_update(int64_t M, int64_t MM, int64_t nb, double scale, haw
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
         float* x;
         double g, lo;
+        bool lg;   // step on log x
         if (i < M) {
-            x = mu + i; g = g_mu[i]; lo = cfg.floor_mu;
+            x = mu + i; g = g_mu[i]; lo = cfg.floor_mu; lg = (cfg.flags & HAWKES_ADAM_LOG_MU) != 0;
         } else if (i < M + MM) {
-            x = alpha + (i - M); g = g_alpha[i - M]; lo = 0.0;
+            x = alpha + (i - M); g = g_alpha[i - M]; lo = 0.0; lg = false;
         } else {
             x = beta + (i - M - MM); g = g_beta[i - M - MM]; lo = cfg.floor_beta;
+            lg = (cfg.flags & HAWKES_ADAM_LOG_BETA) != 0;
         }
         // gradient of the loss -L / scale, plus the penalty's lambda1 on the
         // off-diagonal alpha entries below the hinge point (float32 compare)
@@ -66,13 +68,16 @@ __global__ void adam_update(int64_t M, int64_t MM, int64_t nb, double scale, haw
             const int64_t a = i - M;
             if (a / M != a % M && *x < cfg.h) gl += (double)cfg.lambda1;
         }
+        const double x0 = (double)*x;
+        if (lg) gl *= x0;   // d loss / d log x
         float* m = mom + i;
         float* v = mom + np + i;
         const double mn = cfg.beta1 * (double)*m + (1.0 - cfg.beta1) * gl;
         const double vn = cfg.beta2 * (double)*v + (1.0 - cfg.beta2) * gl * gl;
         *m = (float)mn;
         *v = (float)vn;
-        double xn = (double)*x - cfg.lr * (mn / c1) / (sqrt(vn / c2) + cfg.eps);
+        const double stp = cfg.lr * (mn / c1) / (sqrt(vn / c2) + cfg.eps);
+        double xn = lg ? x0 * exp(-stp) : x0 - stp;
         if (xn < lo) xn = lo;
         *x = (float)xn;
     }
@@ -106,7 +111,8 @@ hawkes_status hawkes_adam_step(const hawkes_problem* p, const double* t, const i
         return HAWKES_EINVAL;
     if (!(cfg->lr > 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) ||
         !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) || !(cfg->eps > 0.0f) || !(cfg->floor_mu >= 0.0f) ||
-        !(cfg->floor_beta > 0.0f) || !(cfg->lambda1 >= 0.0f) || (cfg->lambda1 > 0.0f && !(cfg->h > 0.0f)))
+        !(cfg->floor_beta > 0.0f) || !(cfg->lambda1 >= 0.0f) || (cfg->lambda1 > 0.0f && !(cfg->h > 0.0f)) ||
+        (cfg->flags & ~(HAWKES_ADAM_LOG_MU | HAWKES_ADAM_LOG_BETA)) != 0)
         return HAWKES_EINVAL;
     const AdamLayout L = adam_layout(p);
     if (state_bytes < L.bytes) return HAWKES_EWORKSPACE;

@@ -204,6 +204,70 @@ def simulate_thinning_univariate(rng: np.random.Generator, mu: float, alpha: flo
     return t, np.zeros(n, dtype=np.int32)
 
 
+def scale_free_digraph(rng: np.random.Generator, M: int, a: float = 0.41, b: float = 0.54,
+                       c: float = 0.05, d_in: float = 0.2, d_out: float = 0.0) -> np.ndarray:
+    """Directed scale-free graph on M >= 3 nodes, grown by the preferential-
+    attachment process of Bollobas, Borgs, Chayes and Riordan (2003) from a
+    3-cycle: each step, with probability a a new node v gets an edge v -> w
+    (w drawn with probability proportional to its in-degree + d_in); with
+    probability b an edge v -> w joins existing nodes (v by out-degree +
+    d_out, w by in-degree + d_in); with probability c a new node w gets an
+    edge v -> w (v by out-degree + d_out).  Stops once M nodes exist.
+    Returns the distinct edges (v, w), v != w, as an int array [E, 2]."""
+    if M < 3:
+        raise ValueError("the process starts from 3 nodes")
+    indeg = np.zeros(M)
+    outdeg = np.zeros(M)
+    edges = {(0, 1), (1, 2), (2, 0)}
+    for v, w in edges:
+        outdeg[v] += 1
+        indeg[w] += 1
+    n = 3
+
+    def pick(deg, delta):
+        wgt = deg[:n] + delta
+        tot = wgt.sum()
+        if tot <= 0.0:
+            return int(rng.integers(0, n))
+        return int(min(np.searchsorted(np.cumsum(wgt), rng.random() * tot, side="right"), n - 1))
+
+    while n < M:
+        r = rng.random()
+        if r < a:
+            v, w = n, pick(indeg, d_in)
+            n += 1
+        elif r < a + b:
+            v, w = pick(outdeg, d_out), pick(indeg, d_in)
+        else:
+            v, w = pick(outdeg, d_out), n
+            n += 1
+        outdeg[v] += 1
+        indeg[w] += 1
+        if v != w:
+            edges.add((v, w))
+    return np.array(sorted(edges), dtype=np.int64)
+
+
+def make_recovery(M: int, n: int, seed: int = 0, mu: float = 0.001, beta: float = 1.0,
+                  rho: float = 0.5) -> Workload:
+    """Synthetic sequence for the parameter-recovery study: base rate mu for
+    every node, one decay beta, alpha on a directed scale-free graph
+    (alpha[w, v] > 0 for an edge v -> w: source v excites target w) plus
+    self-excitation on the diagonal, weights U[0.5, 1] rescaled to spectral
+    radius rho; n events by the cluster representation, T = t_n."""
+    rng = np.random.default_rng(np.random.SeedSequence([2604, 1342, 7, M, n, seed]))
+    e = scale_free_digraph(rng, M)
+    a = np.zeros((M, M))
+    a[e[:, 1], e[:, 0]] = rng.uniform(0.5, 1.0, size=e.shape[0])
+    a[np.arange(M), np.arange(M)] = rng.uniform(0.5, 1.0, size=M)
+    alpha = rescale_to_radius(a, rho)
+    mus = np.full(M, mu)
+    t, m = _simulate_n(rng, mus, alpha, np.array([beta]), n)
+    return Workload(t=t, m=m, mu=mus.astype(np.float32), alpha=alpha.astype(np.float32),
+                    beta=np.array([beta], dtype=np.float32), T=float(t[-1]), name=f"recovery_M{M}",
+                    meta={"edges": int(e.shape[0]), "rho": rho})
+
+
 def _expected_rate(mu: np.ndarray, alpha: np.ndarray) -> float:
     M = mu.shape[0]
     return float(np.ones(M) @ np.linalg.solve(np.eye(M) - alpha, mu))

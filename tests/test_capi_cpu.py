@@ -43,7 +43,7 @@ def test_library_exports_every_declared_symbol(H):
 
 def test_version_and_status_strings(H):
     L = H.lib()
-    assert L.hawkes_version() == 3
+    assert L.hawkes_version() == 4
     for s in range(5):
         assert L.hawkes_status_string(s)
     assert L.hawkes_status_string(2) == b"workspace missing or too small"
@@ -178,7 +178,11 @@ def test_host_argument_errors(H):
         pen = H._Adam(0.05, 0.9, 0.999, 1e-8, 1e-6, 1e-6, lam, h)
         assert L.hawkes_adam_step(ctypes.byref(p), FAKE, FAKE, FAKE, FAKE, FAKE, ctypes.byref(pen), FAKE, sb,
                                   *out4, FAKE, 1 << 30, nul) == 1
-    pen0 = H._Adam(0.05, 0.9, 0.999, 1e-8, 1e-6, 1e-6, 0.0, 0.0)
+    # unknown flag bits
+    badf = H._Adam(0.05, 0.9, 0.999, 1e-8, 1e-6, 1e-6, 0.0, 0.0, 4)
+    assert L.hawkes_adam_step(ctypes.byref(p), FAKE, FAKE, FAKE, FAKE, FAKE, ctypes.byref(badf), FAKE, sb, *out4,
+                              FAKE, 1 << 30, nul) == 1
+    pen0 = H._Adam(0.05, 0.9, 0.999, 1e-8, 1e-6, 1e-6, 0.0, 0.0, 3)
     assert L.hawkes_adam_step(ctypes.byref(p), FAKE, FAKE, FAKE, FAKE, FAKE, ctypes.byref(pen0), FAKE, sb, *out4,
                               FAKE, 16, nul) == 2
 
