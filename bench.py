@@ -208,7 +208,8 @@ def run_c5(args, dev):
     wall, per = _timed(lambda: H.loglik_grad(*d, w.T, args.chunk_log2), max(2, args.steps // 4), 1)
     kern = _kernels(H, lambda: H.loglik_grad(*d, w.T, args.chunk_log2), 2)
     log(f"c5 loglik+grad: {wall:.1f} ms per call")
-    opt = H.AdamMLE(*d, w.T, lr=args.c5_lr, chunk_log2=args.chunk_log2, lambda1=args.c5_lambda1, h=args.c5_h)
+    opt = H.AdamMLE(*d, w.T, lr=args.c5_lr, chunk_log2=args.chunk_log2, lambda1=args.c5_lambda1, h=args.c5_h,
+                    log_mu=True, log_beta=True)
     L0 = float(opt.step().item())
     torch.cuda.synchronize()
     opt.capture()
@@ -229,7 +230,7 @@ def run_c5(args, dev):
            "step_device_time": {"median_ms": per[len(per) // 2], "min_ms": per[0], "max_ms": per[-1]},
            "kernels_ms_per_step": kern,
            "adam": {"graph_replays": args.c5_adam_steps, "lr": args.c5_lr, "lambda1": args.c5_lambda1,
-                    "h": args.c5_h, "ms_per_step": adam_ms,
+                    "h": args.c5_h, "log_mu_beta": True, "ms_per_step": adam_ms,
                     "loglik_first": L0,
                     "loglik_last": Ls[-1] if Ls else None, "alpha_nonzeros_after": nnz}}
     print(json.dumps(out), flush=True)
