@@ -258,7 +258,7 @@ def run_recovery(args, dev):
     al0 = torch.full((M, M), 0.1 / M, dtype=torch.float32, device=dev)   # column sums 0.1: subcritical
     be0 = torch.full((1,), 0.5, dtype=torch.float32, device=dev)
     opt = H.AdamMLE(t, m, mu0, al0, be0, w.T, lr=args.rec_lr, lambda1=args.rec_lambda1, h=args.rec_h,
-                    log_mu=not args.rec_linear, log_beta=not args.rec_linear)
+                    log_mu=not args.rec_linear, log_beta=not args.rec_linear, log_alpha=args.rec_log_alpha)
     opt.step()
     torch.cuda.synchronize()
     opt.capture()
@@ -288,7 +288,7 @@ def run_recovery(args, dev):
            "config": {"workload": f"parameter recovery: M={M}, N={w.n}, scale-free alpha ({w.meta['edges']} edges) "
                                   f"+ diagonal, rho {w.meta['rho']}, mu 0.001, beta 1",
                       "n_over_m2": w.n / M ** 2, "lr": args.rec_lr, "lambda1": args.rec_lambda1, "h": args.rec_h,
-                      "log_mu_beta": not args.rec_linear},
+                      "log_mu_beta": not args.rec_linear, "log_alpha": args.rec_log_alpha},
            "loglik_per_event": {"fit": L_fit / w.n, "truth": L_true / w.n},
            "relative_l2_error": errs}
     print(json.dumps(out), flush=True)
@@ -331,6 +331,8 @@ def main() -> int:
     ap.add_argument("--rec-lr", type=float, default=0.05)
     ap.add_argument("--rec-lambda1", type=float, default=0.1)
     ap.add_argument("--rec-h", type=float, default=0.05)
+    ap.add_argument("--rec-log-alpha", action="store_true",
+                    help="steps on log alpha too (relative steps; alpha's zeros stay zero)")
     ap.add_argument("--rec-linear", action="store_true",
                     help="plain projected steps on mu and beta (default: steps on log mu and log beta)")
     args = ap.parse_args()

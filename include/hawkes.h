@@ -198,9 +198,11 @@ hawkes_status hawkes_intensity(const hawkes_problem* p,
  * lambda1 = 0 gives the plain per-event NLL.  First and second moments are
  * float32, bias corrections come from a step counter kept in the device
  * state, then mu >= floor_mu, alpha >= 0, beta >= floor_beta.  Flag bits
- * HAWKES_ADAM_LOG_MU and HAWKES_ADAM_LOG_BETA make the step act on log mu
- * and log beta instead (gradient x dL/dx, update x <- x e^{-lr step}, then
- * the floor): relative steps, for parameters far smaller than lr.  All gradient
+ * HAWKES_ADAM_LOG_MU, HAWKES_ADAM_LOG_BETA and HAWKES_ADAM_LOG_ALPHA make
+ * the step act on log mu, log beta, log alpha instead (gradient of the loss,
+ * penalty included, times x; update x <- x e^{-lr step}, then the floor):
+ * relative steps, for parameters far smaller than lr.  A zero alpha entry
+ * then stays zero (its gradient in log space is 0): the support is fixed.  All gradient
  * outputs are required (they hold the gradient of L, without the penalty,
  * at the parameters before the step; so is loglik).  The call is
  * stream-ordered and host-sync-free, so a whole step can be captured in a
@@ -210,12 +212,13 @@ hawkes_status hawkes_intensity(const hawkes_problem* p,
  * ------------------------------------------------------------------------- */
 #define HAWKES_ADAM_LOG_MU 1u
 #define HAWKES_ADAM_LOG_BETA 2u
+#define HAWKES_ADAM_LOG_ALPHA 4u
 
 typedef struct hawkes_adam {
     float lr, beta1, beta2, eps;   /* step size, moment decays, denominator floor */
     float floor_mu, floor_beta;    /* projection bounds (floor_beta > 0) */
     float lambda1, h;              /* penalty weight (>= 0) and hinge point (> 0 when lambda1 > 0) */
-    uint32_t flags;                /* HAWKES_ADAM_LOG_MU | HAWKES_ADAM_LOG_BETA; other bits must be 0 */
+    uint32_t flags;                /* HAWKES_ADAM_LOG_* bits; other bits must be 0 */
 } hawkes_adam;
 
 size_t hawkes_adam_state_bytes(const hawkes_problem* p);

@@ -424,7 +424,7 @@ class AdamMLE:
     """Maximum-likelihood fit by projected Adam on the per-event negative
     log-likelihood plus the hinge-l1 sparsity penalty lambda1 * sum over
     off-diagonal alpha_pq < h of alpha_pq (lambda1 = 0: no penalty; log_mu,
-    log_beta: steps on log mu, log beta), one
+    log_beta, log_alpha: steps on the logarithms), one
     hawkes_adam_step call per step (evaluation, gradient and update on the
     GPU, no host synchronisation).  Owns float32 copies of
     the parameters (updated in place), its workspace, the optimizer state and
@@ -433,7 +433,7 @@ class AdamMLE:
 
     def __init__(self, t, m, mu, alpha, beta, T, lr=0.05, betas=(0.9, 0.999), eps=1e-8, floor_mu=1e-6,
                  floor_beta=1e-6, chunk_log2: int = 0, lambda1: float = 0.0, h: float = 0.05,
-                 log_mu: bool = False, log_beta: bool = False):
+                 log_mu: bool = False, log_beta: bool = False, log_alpha: bool = False):
         dev, t, m, mu, alpha, beta = _prep(t, m, mu, alpha, beta)
         self.dev, self.t, self.m = dev, t, m
         self.mu, self.alpha, self.beta = mu.clone(), alpha.clone(), beta.clone()
@@ -446,7 +446,7 @@ class AdamMLE:
             raise ValueError("invalid problem for the Adam state")
         self.state = _aligned(dev, self.state_bytes)
         self.cfg = _Adam(lr, betas[0], betas[1], eps, floor_mu, floor_beta, lambda1, h,
-                         (1 if log_mu else 0) | (2 if log_beta else 0))
+                         (1 if log_mu else 0) | (2 if log_beta else 0) | (4 if log_alpha else 0))
         M = self.mu.numel()
         self.loglik = torch.empty(1, dtype=torch.float64, device=dev)
         self.g_mu = torch.empty(M, dtype=torch.float64, device=dev)

@@ -56,7 +56,7 @@ __global__ void adam_update(int64_t M, int64_t MM, int64_t nb, double scale, haw
         if (i < M) {
             x = mu + i; g = g_mu[i]; lo = cfg.floor_mu; lg = (cfg.flags & HAWKES_ADAM_LOG_MU) != 0;
         } else if (i < M + MM) {
-            x = alpha + (i - M); g = g_alpha[i - M]; lo = 0.0; lg = false;
+            x = alpha + (i - M); g = g_alpha[i - M]; lo = 0.0; lg = (cfg.flags & HAWKES_ADAM_LOG_ALPHA) != 0;
         } else {
             x = beta + (i - M - MM); g = g_beta[i - M - MM]; lo = cfg.floor_beta;
             lg = (cfg.flags & HAWKES_ADAM_LOG_BETA) != 0;
@@ -112,7 +112,7 @@ hawkes_status hawkes_adam_step(const hawkes_problem* p, const double* t, const i
     if (!(cfg->lr > 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) ||
         !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) || !(cfg->eps > 0.0f) || !(cfg->floor_mu >= 0.0f) ||
         !(cfg->floor_beta > 0.0f) || !(cfg->lambda1 >= 0.0f) || (cfg->lambda1 > 0.0f && !(cfg->h > 0.0f)) ||
-        (cfg->flags & ~(HAWKES_ADAM_LOG_MU | HAWKES_ADAM_LOG_BETA)) != 0)
+        (cfg->flags & ~(HAWKES_ADAM_LOG_MU | HAWKES_ADAM_LOG_BETA | HAWKES_ADAM_LOG_ALPHA)) != 0)
         return HAWKES_EINVAL;
     const AdamLayout L = adam_layout(p);
     if (state_bytes < L.bytes) return HAWKES_EWORKSPACE;

@@ -179,10 +179,10 @@ def test_host_argument_errors(H):
         assert L.hawkes_adam_step(ctypes.byref(p), FAKE, FAKE, FAKE, FAKE, FAKE, ctypes.byref(pen), FAKE, sb,
                                   *out4, FAKE, 1 << 30, nul) == 1
     # unknown flag bits
-    badf = H._Adam(0.05, 0.9, 0.999, 1e-8, 1e-6, 1e-6, 0.0, 0.0, 4)
+    badf = H._Adam(0.05, 0.9, 0.999, 1e-8, 1e-6, 1e-6, 0.0, 0.0, 8)
     assert L.hawkes_adam_step(ctypes.byref(p), FAKE, FAKE, FAKE, FAKE, FAKE, ctypes.byref(badf), FAKE, sb, *out4,
                               FAKE, 1 << 30, nul) == 1
-    pen0 = H._Adam(0.05, 0.9, 0.999, 1e-8, 1e-6, 1e-6, 0.0, 0.0, 3)
+    pen0 = H._Adam(0.05, 0.9, 0.999, 1e-8, 1e-6, 1e-6, 0.0, 0.0, 7)
     assert L.hawkes_adam_step(ctypes.byref(p), FAKE, FAKE, FAKE, FAKE, FAKE, ctypes.byref(pen0), FAKE, sb, *out4,
                               FAKE, 16, nul) == 2
 

@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _adam_reference(t, m, mu, al, be, T, steps, lr=0.05, b1=0.9, b2=0.999, eps=1e-8, floor=1e-6,
-                    per_target=False, lam=0.0, h=0.05, log_mu=False, log_beta=False):
+                    per_target=False, lam=0.0, h=0.05, log_mu=False, log_beta=False, log_alpha=False):
     """Projected Adam on -L/n plus the oracle's hinge-l1 penalty (weight lam,
     hinge h, decided in float32), with the oracle's gradient; moments and
     parameters rounded to float32 after each update, as the library stores
@@ -32,7 +32,7 @@ def _adam_reference(t, m, mu, al, be, T, steps, lr=0.05, b1=0.9, b2=0.999, eps=1
         pen = oracle.sparsity_penalty(x[1], lam, np.float32(h))[1]
         for j in range(3):
             g = -grads[j] / n + (pen if j == 1 else 0.0)
-            lg = (j == 0 and log_mu) or (j == 2 and log_beta)
+            lg = (j == 0 and log_mu) or (j == 2 and log_beta) or (j == 1 and log_alpha)
             if lg:
                 g = g * x[j].astype(np.float64)
             mn = b1 * mom[j].astype(np.float64) + (1 - b1) * g
@@ -53,16 +53,17 @@ def _adam_reference(t, m, mu, al, be, T, steps, lr=0.05, b1=0.9, b2=0.999, eps=1
                                                    (True, 20, 0.0, False), (False, 3, 0.1, False),
                                                    (False, 40, 0.1, False), (True, 20, 0.1, False),
                                                    (False, 3, 0.1, True), (False, 40, 0.1, True),
-                                                   (True, 20, 0.0, True)])
+                                                   (True, 20, 0.0, True), (False, 40, 0.1, "all"),
+                                                   (True, 20, 0.1, "all")])
 def test_adam_steps_match_reference(H, per_target, M, lam, logs):
     import torch
     t, m, mu, al, be, T = rand_problem(51 + M, 3000, M, per_target=per_target, density=0.5, rate=10.0)
-    ref = _adam_reference(t, m, mu, al, be, T, 4, per_target=per_target, lam=lam, h=0.07, log_mu=logs,
-                          log_beta=logs)
+    ref = _adam_reference(t, m, mu, al, be, T, 4, per_target=per_target, lam=lam, h=0.07, log_mu=bool(logs),
+                          log_beta=bool(logs), log_alpha=logs == "all")
     d = "cuda"
     opt = H.AdamMLE(torch.as_tensor(t, device=d), torch.as_tensor(m, device=d), torch.as_tensor(mu, device=d),
                     torch.as_tensor(al, device=d), torch.as_tensor(be, device=d), T, lambda1=lam, h=0.07,
-                    log_mu=logs, log_beta=logs)
+                    log_mu=bool(logs), log_beta=bool(logs), log_alpha=logs == "all")
     for k, (Lr, xr) in enumerate(ref):
         L = float(opt.step().item())
         torch.cuda.synchronize()
