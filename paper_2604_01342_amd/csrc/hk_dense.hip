@@ -6,8 +6,8 @@
 // 16 x 128 and 16 x 64 for chunks whose event indices need more key bits).
 //   dense_ck     one wave per (column block, run of CKR segments): walks the
 //                block's records of the run once, in groups of 64, and stores
-//                the block's state K at the start of every window (two
-//                groups, 128 records) and after the last one (a checkpoint:
+//                the block's state K at the start of every window (NGW
+//                groups: 64 or 128 records) and after the last one (a checkpoint:
 //                W float64 values and the anchor time tau of the state,
 //                K_q(tau) = sum over the events j of node q before the
 //                window of e^{-beta (tau - t_j)}).  A run
@@ -31,9 +31,10 @@
 //                event and 64 records before it, into an LDS tile of pair
 //                terms).  The pair terms cost a wave instruction per own
 //                event and column block, so the wide tiles (fewer column
-//                blocks) are the fast ones; 128-record windows halve the
-//                per-window work and the rank-1 updates per event at about
-//                1.5 pair instructions per own event.
+//                blocks) are the fast ones.  Where a 64-record window holds
+//                few own events (u mostly zero), 128-record windows (NGW = 2)
+//                halve the per-window work and the rank-1 updates per event
+//                at about 1.5 pair instructions per own event.
 // The state is shared through the checkpoints instead of being rebuilt by
 // every row block.  Every window issues the same loads at the same point
 // (the next window's checkpoint, column group and header, the next batch of
@@ -47,20 +48,20 @@
 
 namespace hk {
 
-// Checkpoint slots: window w (groups 2w and 2w + 1) of (column block sb,
-// run r) uses slot (P0 >> 7) + 2 (sb nrun + r) + w, with P0 the position of
-// the run's first record in the column block's share of the DR-node
-// partition; the slots of different (sb, r) never overlap, and there are at
-// most (events) / 128 + 2 NBC nrun + 1.
+// Checkpoint slots: window w (groups NGW w to NGW w + NGW - 1) of (column
+// block sb, run r) uses slot (P0 >> log2(64 NGW)) + 2 (sb nrun + r) + w,
+// with P0 the position of the run's first record in the column block's
+// share of the DR-node partition; the slots of different (sb, r) never
+// overlap, and there are at most (events) / (64 NGW) + 2 NBC nrun + 1.
 // Checkpoint slot record, in float64 words: the state (W); the window's
 // header (8 words: the anchor time, the time of the window's last record,
-// then int32 the event index of that record, the record count (<= 128), the
-// next slot of the column block's walk (-1: none), the run, whether the
+// then int32 the event index of that record, the record count (<= 64 NGW),
+// the next slot of the column block's walk (-1: none), the run, whether the
 // window is wide, beta (last record - anchor) > HK_WIDE, and the event index
-// of its 65th record (INT_MAX if none)); the window's 128 record times; its
-// 128 record keys (u32, two per word; past the records: 0xffffffff in the
-// first 64, anything in the second, which the count excludes); then the
-// records' factors e^{beta (t_j - tau)} against the window's anchor
+// of its 65th record (INT_MAX if none)); the window's 64 NGW record times;
+// its 64 NGW record keys (u32, two per word; past the records: 0xffffffff
+// in the first 64, anything in a second 64, which the count excludes); then
+// the records' factors e^{beta (t_j - tau)} against the window's anchor
 // (float32, two per word, 0 past the records in the first 64), formed once
 // here instead of once per row block.  The slot after a run's last window
 // has state and header only (count 0; its window runs to the run's end).
