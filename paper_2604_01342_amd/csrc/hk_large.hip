@@ -15,8 +15,10 @@
 // Per chunk:
 //   agg      one wave per segment folds its events into (K_run, J_run)
 //   scan     one thread per node chains the segment maps -> carry-in per segment
-//   forward  one wave per segment replays its events 64 at a time (one per
-//            lane).  Each node keeps a lazily decayed record (tau_q, K_q, J_q)
+//   forward  a workgroup of two waves per segment replays its events 64 at a
+//            time (one per lane; each wave takes every other nonzero of the
+//            event's row of alpha, the first wave adds the partial sums and
+//            does the rest).  Each node keeps a lazily decayed record (tau_q, K_q, J_q)
 //            in LDS; lambda_i needs only the nonzeros of alpha's row m_i
 //            (R = alpha_{m_i,:} . K, eq. 3), read from a CSR copy of alpha,
 //            plus the same-batch events found through a per-node lane mask.
@@ -301,14 +303,17 @@ __global__ void large_scan_apply(int32_t nseg, int32_t M, const double* __restri
 }
 
 // ------------------------------------------------------------------ forward
+#ifndef HK_FWW
+#define HK_FWW 2   // waves per forward-pass segment
+#endif
 // SUPP (with GRAD): also adds beta w_i K_q(t_i) to gsup[k] for every nonzero
 // k = (m_i, q) of alpha's CSR (hardware float64 atomics): the first term of
 // eq. 9 on alpha's support only.  Segment s adds into copy s & cmask (copies
 // MM apart): consecutive workgroups go to different XCDs, so each copy sees
 // mostly one XCD's atomics and a copy's addresses see a fraction of the
 // contention.
-template <bool GRAD, bool INTENS, bool SUPP>
-__global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int32_t M, double T,
+template <bool GRAD, bool INTENS, bool SUPP, int NW>
+__global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1, int32_t M, double T,
                                                     const double* __restrict__ t, const int32_t* __restrict__ marks,
                                                     const float* __restrict__ mu, const float* __restrict__ beta,
                                                     const int4* __restrict__ node_info,
@@ -324,8 +329,13 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
     uint64_t* rmask = (uint64_t*)(lds + M);               // [M] lanes of this batch with mark q
     double2* rKJ = reinterpret_cast<double2*>(lds + 2 * M);   // [M] (K_q, J_q) at rtau (event included)
     __shared__ double tb[64], eb[64];
+    __shared__ double Rs[(NW > 1 ? NW - 1 : 1) * 64], Ds[(NW > 1 ? NW - 1 : 1) * 64];   // other waves' partial sums
     const int32_t s = blockIdx.x;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    // NW waves share a segment's events; wave wv takes nonzeros wv, wv + NW, ...
+    // of each event's row of alpha
+    const int wv = NW == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    static_assert(!SUPP || NW == 1, "the support-restricted sums are formed by one wave");
     const int64_t a = c0 + (int64_t)s * HK_SEG;
     const int64_t b = a + HK_SEG < c1 ? a + HK_SEG : c1;
     const double bet = (double)beta[0];
@@ -340,7 +350,7 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
     // time rtau[q] and is decayed on use.
     const bool anch = bet * (t[b - 1] - tref) <= 600.0;
     const double* cs = carry_seg + (int64_t)s * 2 * M;
-    for (int32_t q = lane; q < M; q += 64) {
+    for (int32_t q = threadIdx.x; q < M; q += 64 * NW) {
         rtau[q] = tref;
         rKJ[q] = make_double2(cs[q], anch ? -cs[M + q] : cs[M + q]);
         rmask[q] = 0ull;
@@ -351,17 +361,18 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
     // three batches ahead, node records two ahead and the first FW nonzeros
     // of each event's row of alpha one ahead (clamped indices keep every load
     // valid), so the gathers' latency hides behind a batch of work
-    constexpr int FW = 16;
+    constexpr int FW = 16;         // nonzeros loaded ahead per event
+    constexpr int FWW = FW / NW;   // of which this wave's
     auto ld_tm = [&](int64_t base, double& tt, int& mm) {
         const int64_t j = base + lane;
         const int64_t jc = j < b ? j : b - 1;
         tt = t[jc];
         mm = clamp_mark(marks[jc], M);
     };
-    auto ld_row = [&](const int4& nv, int32_t (&qc)[FW], float (&qa)[FW]) {
+    auto ld_row = [&](const int4& nv, int32_t (&qc)[FWW], float (&qa)[FWW]) {
 #pragma unroll
-        for (int j = 0; j < FW; ++j) {
-            const int32_t k = nv.x + j < nv.y ? nv.x + j : nv.x;
+        for (int j = 0; j < FWW; ++j) {
+            const int32_t k = nv.x + NW * j + wv < nv.y ? nv.x + NW * j + wv : nv.x;
             qc[j] = csr_col[k];
             qa[j] = csr_val[k];
         }
@@ -372,8 +383,8 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
     ld_tm(a + 64, t1, m1);
     ld_tm(a + 128, t2, m2);
     int4 n0 = node_info[m0], n1 = node_info[m1];
-    int32_t qc0[FW];
-    float qa0[FW];
+    int32_t qc0[FWW];
+    float qa0[FWW];
     ld_row(n0, qc0, qa0);
     for (int64_t base = a; base < b; base += 64) {
         const int64_t i = base + lane;
@@ -386,19 +397,21 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
         int m3;
         ld_tm(base + 192, t3, m3);
         const int4 n2 = node_info[m2];
-        int32_t qc1[FW];
-        float qa1[FW];
+        int32_t qc1[FWW];
+        float qa1[FWW];
         ld_row(n1, qc1, qa1);
         const double ui = ti - tref;
-        const double eti = anch && valid ? exp_f64(bet * ui) : 0.0;   // e^{beta u_i}
-        tb[lane] = ti;
-        eb[lane] = eti;
-        if (valid) atomicOr((unsigned long long*)&rmask[mi], 1ull << lane);
+        if (wv == 0) {
+            const double eti = anch && valid ? exp_f64(bet * ui) : 0.0;   // e^{beta u_i}
+            tb[lane] = ti;
+            eb[lane] = eti;
+            if (valid) atomicOr((unsigned long long*)&rmask[mi], 1ull << lane);
+        }
         __syncthreads();
         double R = 0.0, Dd = 0.0, lam = 1.0, w = 0.0, em1 = 0.0;
-        if (valid) {
-            const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-            const int32_t k0 = ni.x, k1 = ni.y;
+        const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+        const int32_t k0 = ni.x, k1 = ni.y;
+        double ks[SUPP ? FW : 1];   // the first FW nonzeros' sums, for gsup (NW = 1)
             // anchored sums of source q (records plus the batch's earlier
             // events of q): K_q(t_i) = e^{-beta u_i} s0
             auto sums_a = [&](int32_t q, double& s0, double& s1) {
@@ -433,9 +446,8 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
                     if (GRAD) Jv = __builtin_fma(dj, ej, Jv);
                 }
             };
-            double ks[SUPP ? FW : 1];   // the first FW nonzeros' sums, for gsup
-            double ei = 1.0;            // e^{-beta u_i} (anchored records)
-            if (anch) {
+            if (!valid) {
+            } else if (anch) {
                 // source q with weight av
                 auto terma = [&](int32_t q, float av) -> double {
                     double s0, s1;
@@ -445,15 +457,12 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
                     return s0;
                 };
 #pragma unroll
-                for (int j = 0; j < FW; ++j)
-                    if (k0 + j < k1) {
+                for (int j = 0; j < FWW; ++j)
+                    if (k0 + NW * j + wv < k1) {
                         const double v = terma(qc0[j], qa0[j]);
                         if (SUPP) ks[j] = v;
                     }
-                for (int32_t k = k0 + FW; k < k1; ++k) terma(csr_col[k], csr_val[k]);
-                ei = exp_f64(-bet * ui);
-                R *= ei;
-                Dd *= ei;
+                for (int32_t k = k0 + FW + wv; k < k1; k += NW) terma(csr_col[k], csr_val[k]);
             } else {
             auto term = [&](int32_t q, float av) -> double {
                 double Kv, Jv;
@@ -463,12 +472,34 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
                 return Kv;
             };
 #pragma unroll
-            for (int j = 0; j < FW; ++j)
-                if (k0 + j < k1) {
+            for (int j = 0; j < FWW; ++j)
+                if (k0 + NW * j + wv < k1) {
                     const double v = term(qc0[j], qa0[j]);
                     if (SUPP) ks[j] = v;
                 }
-            for (int32_t k = k0 + FW; k < k1; ++k) term(csr_col[k], csr_val[k]);
+            for (int32_t k = k0 + FW + wv; k < k1; k += NW) term(csr_col[k], csr_val[k]);
+            }
+        if (NW > 1) {
+            // the other waves' partial sums to the first, added in wave order
+            if (wv > 0) {
+                Rs[(wv - 1) * 64 + lane] = R;
+                Ds[(wv - 1) * 64 + lane] = Dd;
+            }
+            __syncthreads();
+            if (wv == 0) {
+#pragma unroll
+                for (int v = 0; v < NW - 1; ++v) {
+                    R += Rs[v * 64 + lane];
+                    Dd += Ds[v * 64 + lane];
+                }
+            }
+        }
+        double ei = 1.0;   // e^{-beta u_i} (anchored records)
+        if (valid && wv == 0) {
+            if (anch) {
+                ei = exp_f64(-bet * ui);
+                R *= ei;
+                Dd *= ei;
             }
             lam = __builtin_fma(bet, R, (double)__int_as_float(ni.z));
         if (INTENS) lambda_out[i] = (float)lam;
@@ -500,12 +531,12 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
                 }
             }
         }
-        if (GRAD && valid) wchunk[i - c0] = (float)w;
+        if (GRAD && valid && wv == 0) wchunk[i - c0] = (float)w;
         __syncthreads();
         if (anch) {
             // anchored records: the batch's events of a node add their terms,
             // in index order, through one leader lane per node
-            if (valid) {
+            if (valid && wv == 0) {
                 uint64_t grp = rmask[mi];
                 if (__builtin_ctzll(grp) == lane) {
                     const double2 kj = rKJ[mi];
@@ -519,7 +550,7 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
                     rKJ[mi] = make_double2(s0, s1);
                 }
             }
-        } else if (valid) {
+        } else if (valid && wv == 0) {
             // lazy record update, one leader lane per node, events in index order
             uint64_t grp = rmask[mi];
             if (__builtin_ctzll(grp) == lane) {
@@ -540,7 +571,7 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
             }
         }
         __syncthreads();
-        if (valid) rmask[mi] = 0ull;
+        if (valid && wv == 0) rmask[mi] = 0ull;
         __syncthreads();
         t0 = t1;
         m0 = m1;
@@ -551,12 +582,14 @@ __global__ __launch_bounds__(64) void large_forward(int64_t c0, int64_t c1, int3
         n0 = n1;
         n1 = n2;
 #pragma unroll
-        for (int j = 0; j < FW; ++j) {
+        for (int j = 0; j < FWW; ++j) {
             qc0[j] = qc1[j];
             qa0[j] = qa1[j];
         }
     }
-    // deterministic wave reduction of the float64 partials
+    // deterministic wave reduction of the float64 partials (the first
+    // wave's; the others hold none)
+    if (wv != 0) return;
     for (int off = 32; off > 0; off >>= 1) {
         logsum += __shfl_down(logsum, off, 64);
         comp += __shfl_down(comp, off, 64);
@@ -854,10 +887,10 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
     const size_t lds_agg = (size_t)2 * M * sizeof(double);
     const size_t lds_fwd = (size_t)M * (sizeof(double) + sizeof(uint64_t) + 2 * sizeof(double));
     if (allow_lds((const void*)large_seg_agg, lds_agg) != HAWKES_OK ||
-        allow_lds((const void*)large_forward<true, false, false>, lds_fwd) != HAWKES_OK ||
-        allow_lds((const void*)large_forward<true, false, true>, lds_fwd) != HAWKES_OK ||
-        allow_lds((const void*)large_forward<false, true, false>, lds_fwd) != HAWKES_OK ||
-        allow_lds((const void*)large_forward<false, false, false>, lds_fwd) != HAWKES_OK)
+        allow_lds((const void*)large_forward<true, false, false, HK_FWW>, lds_fwd) != HAWKES_OK ||
+        allow_lds((const void*)large_forward<true, false, true, 1>, lds_fwd) != HAWKES_OK ||
+        allow_lds((const void*)large_forward<false, true, false, HK_FWW>, lds_fwd) != HAWKES_OK ||
+        allow_lds((const void*)large_forward<false, false, false, HK_FWW>, lds_fwd) != HAWKES_OK)
         return HAWKES_EUNSUPPORTED;
     const bool sup = A.grad && A.support;
     // support-restricted: the first term's copies (CSR order) take the place
@@ -898,19 +931,22 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
         {
             TimedScope ts(1, st);
             if (sup)
-                hipLaunchKernelGGL((large_forward<true, false, true>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1,
+                hipLaunchKernelGGL((large_forward<true, false, true, 1>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1,
                                    M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
                                    A.carry_seg, A.seg_part, A.wchunk, (float*)nullptr, A.gsup, ncopy - 1);
             else if (A.grad)
-                hipLaunchKernelGGL((large_forward<true, false, false>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1,
+                hipLaunchKernelGGL((large_forward<true, false, false, HK_FWW>), dim3(nseg), dim3(64 * HK_FWW), lds_fwd,
+                                   st, c0, c1,
                                    M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
                                    A.carry_seg, A.seg_part, A.wchunk, (float*)nullptr, (double*)nullptr, 0);
             else if (A.lambda_out)
-                hipLaunchKernelGGL((large_forward<false, true, false>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1,
+                hipLaunchKernelGGL((large_forward<false, true, false, HK_FWW>), dim3(nseg), dim3(64 * HK_FWW), lds_fwd,
+                                   st, c0, c1,
                                    M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
                                    A.carry_seg, A.seg_part, A.wchunk, A.lambda_out, (double*)nullptr, 0);
             else
-                hipLaunchKernelGGL((large_forward<false, false, false>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1,
+                hipLaunchKernelGGL((large_forward<false, false, false, HK_FWW>), dim3(nseg), dim3(64 * HK_FWW), lds_fwd,
+                                   st, c0, c1,
                                    M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
                                    A.carry_seg, A.seg_part, A.wchunk, (float*)nullptr, (double*)nullptr, 0);
         }
