@@ -44,7 +44,8 @@
  *    terms through LDS atomics of several waves, whose order (hence
  *    last-bit rounding) can vary between calls.
  *  - Size limits (LDS per workgroup, read from the device; 160 KiB on
- *    MI355X): shared decay m <= 5120, decay per target m <= 4352; larger m
+ *    MI355X, of which the shared-decay forward kernel keeps 2 KiB for
+ *    itself): shared decay m <= 5056, decay per target m <= 4352; larger m
  *    returns HAWKES_EUNSUPPORTED.  The per-target gradient also keeps one
  *    float32 per event (4 bytes x n) in the workspace for its reverse pass.
  *  - Errors: every function returns a hawkes_status.  Host-detectable

@@ -832,9 +832,12 @@ size_t lds_limit() {
     return (size_t)v;
 }
 
-// Kernels whose dynamic LDS exceeds 64 KiB are allowed the device maximum
-// once per (kernel, device); later calls (including ones under stream
-// capture) only look the pair up.
+// Kernels whose dynamic LDS exceeds 64 KiB are allowed, once per (kernel,
+// device), as much as the device's per-workgroup LDS leaves beside the
+// kernel's own static LDS (asking for more than that is refused); later calls
+// (including ones under stream capture) only look the pair up.  A refusal
+// clears the runtime's last-error state, so that it does not surface at an
+// unrelated later call.
 hawkes_status allow_lds(const void* kernel, size_t bytes) {
     const size_t lim = lds_limit();
     if (bytes > lim) return HAWKES_EUNSUPPORTED;
@@ -842,17 +845,29 @@ hawkes_status allow_lds(const void* kernel, size_t bytes) {
     static std::mutex mu;
     static const void* done_k[128];
     static int done_d[128];
+    static size_t done_cap[128];
     static int n_done = 0;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return HAWKES_EDEVICE;
     std::lock_guard<std::mutex> g(mu);
     for (int i = 0; i < n_done; ++i)
-        if (done_k[i] == kernel && done_d[i] == dev) return HAWKES_OK;
-    if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) != hipSuccess)
+        if (done_k[i] == kernel && done_d[i] == dev) return bytes <= done_cap[i] ? HAWKES_OK : HAWKES_EUNSUPPORTED;
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, kernel) != hipSuccess) {
+        (void)hipGetLastError();
+        return HAWKES_EDEVICE;
+    }
+    if (fa.sharedSizeBytes >= lim) return HAWKES_EUNSUPPORTED;
+    const size_t cap = lim - fa.sharedSizeBytes;
+    if (bytes > cap) return HAWKES_EUNSUPPORTED;
+    if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cap) != hipSuccess) {
+        (void)hipGetLastError();
         return HAWKES_EUNSUPPORTED;
+    }
     if (n_done < 128) {
         done_k[n_done] = kernel;
         done_d[n_done] = dev;
+        done_cap[n_done] = cap;
         ++n_done;
     }
     return HAWKES_OK;

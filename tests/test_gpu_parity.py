@@ -206,6 +206,32 @@ def test_loglik_only_matches(H, M):
     assert scalar_rel(L, Lr) < TOL
 
 
+# ------------------------------------------------------------- shared decay above 64 KiB of LDS
+# The shared-decay forward kernel keeps 32 bytes of LDS per node, so from
+# M = 2049 on it runs under the device's larger per-workgroup limit (160 KiB
+# on MI355X, less the kernel's own 2 KiB of static LDS: M <= 5056); one node
+# more is refused on the host, before any launch.
+def test_shared_decay_above_64k_lds(H):
+    t, m, mu, alpha, beta, T = rand_problem(71, 12000, 2600, density=0.002, rate=20.0)
+    ref = oracle.forward(t, m, mu, alpha, beta, T)
+    check(run_gpu(H, t, m, mu, alpha, beta, T), ref, label="large n=12000 M=2600")
+
+
+def test_shared_decay_node_limit(H):
+    import torch
+    for M, ok in ((5056, True), (5057, False)):
+        t, m, mu, alpha, beta, T = rand_problem(72, 3000, M, density=0.001, rate=20.0)
+        args = (dev(t, torch.float64), dev(m, torch.int32), dev(mu, torch.float32), dev(alpha, torch.float32),
+                dev(beta, torch.float32), T)
+        if ok:
+            L = H.loglik(*args).item()
+            assert scalar_rel(L, oracle.forward(t, m, mu, alpha, beta, T, grad=False)) < TOL
+        else:
+            with pytest.raises(H.HawkesError) as e:
+                H.loglik(*args)
+            assert e.value.status == 4
+
+
 # ------------------------------------------------------------- paper workloads, reduced sizes
 def test_c1_univariate_vs_bruteforce(H):
     from paper_2604_01342_amd import workloads as W
