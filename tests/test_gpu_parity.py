@@ -230,6 +230,13 @@ def test_shared_decay_node_limit(H):
             with pytest.raises(H.HawkesError) as e:
                 H.loglik(*args)
             assert e.value.status == 4
+    # a refusal leaves no pending runtime error behind: a fresh device
+    # allocation and a call at a supported size both still succeed
+    torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    t, m, mu, alpha, beta, T = rand_problem(74, 2000, 30, density=0.5, rate=10.0)
+    L = H.loglik(dev(t, torch.float64), dev(m, torch.int32), dev(mu, torch.float32), dev(alpha, torch.float32),
+                 dev(beta, torch.float32), T).item()
+    assert scalar_rel(L, oracle.forward(t, m, mu, alpha, beta, T, grad=False)) < TOL
 
 
 # ------------------------------------------------------------- paper workloads, reduced sizes

@@ -26,6 +26,25 @@ def test_per_target_matches_adjoint_oracle(H, seed, n, M, density, ties, chunk):
     check(run_gpu(H, t, m, mu, alpha, beta, T, chunk), ref, label=f"per-target n={n} M={M} chunk={chunk}")
 
 
+def test_per_target_node_limit(H):
+    # the per-target forward kernel keeps 32 bytes of LDS per node plus a
+    # 24 KiB staging area: M <= 4352 under MI355X's 160 KiB per workgroup,
+    # one node more is refused on the host before any launch
+    import torch
+    from tests.test_gpu_parity import dev
+    for M, ok in ((4352, True), (4353, False)):
+        t, m, mu, alpha, beta, T = rand_problem(73, 3000, M, per_target=True, density=0.001, rate=20.0)
+        args = (dev(t, torch.float64), dev(m, torch.int32), dev(mu, torch.float32), dev(alpha, torch.float32),
+                dev(beta, torch.float32), T)
+        if ok:
+            L = H.loglik(*args).item()
+            assert scalar_rel(L, oracle.adjoint(t, m, mu, alpha, beta, T, grad=False)) < TOL
+        else:
+            with pytest.raises(H.HawkesError) as e:
+                H.loglik(*args)
+            assert e.value.status == 4
+
+
 def test_per_target_matches_definition_tiny(H):
     t, m, mu, alpha, beta, T = rand_problem(41, 120, 4, per_target=True, ties=True, rate=3.0)
     ref = oracle.brute(t, m, mu, alpha, beta, T)
