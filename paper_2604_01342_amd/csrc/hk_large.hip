@@ -196,9 +196,9 @@ __global__ __launch_bounds__(64) void large_seg_agg(int64_t c0, int64_t c1, int3
 
 // beta_pt: per-target decays (R-form state) or nullptr (one shared decay,
 // seg_dec / gdec precomputed)
-// The thread of node 0 also writes its group's gspan/gdec and every
-// segment's seg_off/seg_offdec: the time from the event before the group to
-// the event before the segment, and its decay (shared decay beta[0]).
+// The threads also write the group's gspan/gdec and every segment's
+// seg_off/seg_offdec: the time from the event before the group to the event
+// before the segment, and its decay (shared decay beta[0]).
 __global__ __launch_bounds__(256) void large_scan_local(int32_t nseg, int32_t M, const double* __restrict__ agg,
                                  const double* __restrict__ seg_dec, const double* __restrict__ seg_span,
                                  double* __restrict__ carry_seg, double* __restrict__ gagg,
@@ -210,16 +210,22 @@ __global__ __launch_bounds__(256) void large_scan_local(int32_t nseg, int32_t M,
     if (gid >= (int64_t)ngr * M) return;
     const int32_t g = (int32_t)(gid / M), q = (int32_t)(gid % M);
     const int32_t s0 = g * HK_SG, s1 = s0 + HK_SG < nseg ? s0 + HK_SG : nseg;
-    if (q == 0) {
+    // offset u of the group (u = 0 .. s1 - s0, the last one the group's
+    // span) is summed by the threads q = u, u + M, ..: each sums the spans in
+    // the same order as one serial pass would, so the values do not depend on
+    // M, and the group's exps run side by side instead of one after another
+    for (int32_t u = q; u <= s1 - s0; u += M) {
         const double b0 = (double)beta[0];
         double D = 0.0;
-        for (int32_t s = s0; s < s1; ++s) {
-            seg_off[s] = D;
-            seg_offdec[s] = exp(-b0 * D);
-            D += seg_span[s];
+        for (int32_t s = s0; s < s0 + u; ++s) D += seg_span[s];
+        const double e = exp(-b0 * D);
+        if (u < s1 - s0) {
+            seg_off[s0 + u] = D;
+            seg_offdec[s0 + u] = e;
+        } else {
+            gspan[g] = D;
+            gdec[g] = e;
         }
-        gspan[g] = D;
-        gdec[g] = exp(-b0 * D);
     }
     double K = 0.0, J = 0.0;
     const double bq = beta_pt ? (double)beta_pt[q] : 0.0;
@@ -882,13 +888,15 @@ void large_build_index(int32_t M, const float* alpha, int trans, int32_t* ptr, i
 
 void large_scan(LargeArgs& A, int32_t nseg, const float* beta_pt, hipStream_t st) {
     const int32_t M = A.M;
-    const unsigned gM = (unsigned)((M + 255) / 256);
+    // the first two passes are serial chains per thread, ngr * M and M
+    // threads in all: workgroups of one wave spread them over every CU
+    const unsigned gM = (unsigned)((M + 63) / 64);
     const int32_t ngr = (nseg + HK_SG - 1) / HK_SG;
     const int64_t nloc = (int64_t)ngr * M, napp = (int64_t)nseg * M;
-    hipLaunchKernelGGL(large_scan_local, dim3((unsigned)((nloc + 255) / 256)), dim3(256), 0, st, nseg, M, A.agg,
+    hipLaunchKernelGGL(large_scan_local, dim3((unsigned)((nloc + 63) / 64)), dim3(64), 0, st, nseg, M, A.agg,
                        A.seg_dec, A.seg_span, A.carry_seg, A.gagg, beta_pt, A.beta, A.gspan, A.gdec, A.seg_off,
                        A.seg_offdec);
-    hipLaunchKernelGGL(large_scan_groups, dim3(gM), dim3(256), 0, st, nseg, M, A.gagg, A.gspan, A.gdec, A.gcarry,
+    hipLaunchKernelGGL(large_scan_groups, dim3(gM), dim3(64), 0, st, nseg, M, A.gagg, A.gspan, A.gdec, A.gcarry,
                        A.carry, beta_pt);
     hipLaunchKernelGGL(large_scan_apply, dim3((unsigned)((napp + 255) / 256)), dim3(256), 0, st, nseg, M,
                        A.seg_off, A.seg_offdec, A.gcarry, A.carry_seg, beta_pt);
