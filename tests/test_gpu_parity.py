@@ -91,12 +91,13 @@ def test_large_engine_matches_oracle(H, seed, n, M, density, ties, chunk):
 # hawkes_loglik_grad_support: the oracle's dense gradient with the entries off
 # alpha's support set to zero.  Large engine: rows with more nonzeros than the
 # forward pass keeps in registers (16), several chunks, anchored records
-# (rate 20) and per-record decays (rate 1: segments spanning beta u > 600);
-# small engine and per-target decays: the dense gradient, masked.
+# (rate 20) and per-record decays (rate 1: segments spanning beta u > 600),
+# M = 2600 (node records above 64 KiB of LDS); small engine and per-target decays: the dense gradient, masked.
 @pytest.mark.parametrize("seed,n,M,density,per_target,chunk,rate",
                          [(81, 6000, 4, 0.5, False, 0, 2.0), (82, 30000, 120, 0.3, False, 12, 20.0),
                           (83, 20000, 300, 0.01, False, 0, 20.0), (84, 12000, 40, 0.5, False, 12, 1.0),
-                          (85, 4000, 24, 0.3, True, 12, 5.0), (86, 1, 9, 1.0, False, 0, 1.0)])
+                          (85, 4000, 24, 0.3, True, 12, 5.0), (86, 1, 9, 1.0, False, 0, 1.0),
+                          (87, 12000, 2600, 0.002, False, 0, 20.0)])
 def test_support_gradient_is_the_masked_dense_gradient(H, seed, n, M, density, per_target, chunk, rate):
     import torch
     t, m, mu, alpha, beta, T = rand_problem(seed, n, M, per_target=per_target, density=density, rate=rate)
