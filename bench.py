@@ -36,6 +36,20 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
+def host_cpu() -> dict:
+    """The host's CPU model name and logical CPU count (the oracle baseline's machine)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
+
+
 def source_hash(*names) -> str:
     h = hashlib.sha256()
     for n in names:
@@ -139,7 +153,7 @@ def run_single_other(args, name, dev):
         c_dt = time.perf_counter() - c0
         g = [x.cpu().numpy() if hasattr(x, "cpu") else x for x in H.loglik_grad(*d, w.T, args.chunk_log2)]
         out["cpu_baseline"] = {"value": w.n / c_dt, "unit": "events/s", "cores": 1, "kind": "oracle",
-                               "sample": f"all {w.n} events, {c_dt:.1f} s"}
+                               "sample": f"all {w.n} events, {c_dt:.1f} s", **host_cpu()}
         out["err_vs_oracle"] = {"loglik": abs(float(g[0]) - ref[0]) / abs(ref[0]), "g_mu": rel(g[1], ref[1]),
                                 "g_alpha": rel(g[2], ref[2]), "g_beta": rel(g[3], ref[3])}
     print(json.dumps(out), flush=True)
@@ -186,7 +200,7 @@ def run_c3(args, dev):
             ne += ws.n
         c_dt = time.perf_counter() - c0
         out["cpu_baseline"] = {"value": ne / c_dt, "unit": "events/s", "cores": 1, "kind": "oracle",
-                               "sample": f"every 64th sequence ({ne} events), {c_dt:.1f} s"}
+                               "sample": f"every 64th sequence ({ne} events), {c_dt:.1f} s", **host_cpu()}
         out["err_vs_oracle"] = {"loglik_worst_sampled": worst}
     print(json.dumps(out), flush=True)
     return 0
@@ -474,7 +488,7 @@ def main() -> int:
         c_dt = time.perf_counter() - c0
         out["cpu_baseline"] = {"value": nc / c_dt, "unit": "events/s", "cores": 1, "kind": "oracle",
                                "sample": f"first {nc} events of the workload (T = t_{nc}), "
-                                         f"FP64 sequential recurrence, {c_dt:.1f} s"}
+                                         f"FP64 sequential recurrence, {c_dt:.1f} s", **host_cpu()}
         g = H.loglik_grad(t[:nc], m[:nc], mu, al, be, Tc, args.chunk_log2)
         torch.cuda.synchronize()
         gg = [g[1].cpu().numpy(), g[2].cpu().numpy(), g[3].cpu().numpy()]

@@ -6,10 +6,11 @@
  * Paper: "Massively Parallel Exact Inference for Hawkes Processes"
  * (arXiv 2604.01342).
  *
- *   Intensity (Background, eq. 1), one decay kernel (K = 1):
- *     lambda_p(t) = mu_p + sum_{j : t_j < t} alpha[p][m_j] * beta_p * exp(-beta_p (t - t_j))
- *   with beta_p = beta[0] for every p (HAWKES_BETA_SHARED, the paper's gamma)
- *   or one decay per target node (HAWKES_BETA_PER_TARGET).
+ *   Intensity (Background, eq. 1), K decay kernels:
+ *     lambda_p(t) = mu_p + sum_k sum_{j : t_j < t} alpha[k][p][m_j] * beta_k * exp(-beta_k (t - t_j))
+ *   with one decay per kernel shared by every node (HAWKES_BETA_SHARED,
+ *   beta[k] is the paper's gamma_k), or, with K = 1, one decay per target
+ *   node, beta_p in place of beta_k (HAWKES_BETA_PER_TARGET).
  *   Log-likelihood (eq. 2):
  *     L = sum_i log lambda_{m_i}(t_i) - sum_p int_0^T lambda_p(t) dt
  *   Gradients: eqs. 8, 9, 10 (Appendix "Parameter Gradient Formulas").
@@ -25,13 +26,14 @@
  *    captured into a HIP graph.  Two calls that share a workspace must be
  *    ordered on one stream.
  *  - Layouts: t[n] float64, nondecreasing, 0 <= t[i] <= T; marks[n] int32 in
- *    [0, m); mu[m] float32; alpha[m*m] float32 row-major, alpha[p*m + q] is
- *    the excitation of target p by a source event of node q (eq. 1 uses
- *    alpha_{p, m_j}); beta[1] or beta[m] float32 (> 0).
+ *    [0, m); mu[m] float32; alpha[k*m*m] float32, kernel-major then
+ *    row-major, alpha[(k*m + p)*m + q] is the excitation of target p by a
+ *    source event of node q through kernel k (eq. 1 uses alpha_{p, m_j});
+ *    beta[k] (shared decay) or beta[m] (per target, k = 1) float32 (> 0).
  *  - Ties: events with equal time stamps excite later events in index order,
  *    which is what the recurrence of eq. 4 computes.
- *  - Outputs are float64: loglik[1], g_mu[m], g_alpha[m*m] (same layout as
- *    alpha), g_beta[1] (shared) or g_beta[m] (per target).  Any gradient
+ *  - Outputs are float64: loglik[1], g_mu[m], g_alpha[k*m*m] (same layout as
+ *    alpha), g_beta[k] (shared) or g_beta[m] (per target).  Any gradient
  *    pointer may be NULL to skip that output.
  *  - Precision: time differences are formed in float64.  The forward pass
  *    (state, decays, intensities, log-likelihood and the dL/dmu, dL/dbeta
@@ -68,19 +70,22 @@
 extern "C" {
 #endif
 
-#define HAWKES_ABI_VERSION 4
+#define HAWKES_ABI_VERSION 5
+
+/* Decay kernels per problem (hawkes_problem.k), shared-decay mode. */
+#define HAWKES_MAX_KERNELS 8
 
 typedef enum hawkes_status {
     HAWKES_OK = 0,
     HAWKES_EINVAL = 1,        /* bad argument (NULL pointer, size, mode) */
     HAWKES_EWORKSPACE = 2,    /* workspace NULL or smaller than required */
     HAWKES_EDEVICE = 3,       /* a HIP call or kernel launch failed */
-    HAWKES_EUNSUPPORTED = 4   /* valid request this build does not implement (k > 1, m above the limits) */
+    HAWKES_EUNSUPPORTED = 4   /* valid request this build does not implement (m above the limits) */
 } hawkes_status;
 
 typedef enum hawkes_beta_mode {
-    HAWKES_BETA_SHARED = 0,     /* beta[1]: one decay for every target (eq. 1, K = 1) */
-    HAWKES_BETA_PER_TARGET = 1  /* beta[m]: decay beta_p of the target's kernel */
+    HAWKES_BETA_SHARED = 0,     /* beta[k]: one decay per kernel for every target (eq. 1) */
+    HAWKES_BETA_PER_TARGET = 1  /* beta[m]: decay beta_p of the target's kernel (k = 1) */
 } hawkes_beta_mode;
 
 /* One event sequence.  `chunk_log2` selects constant-memory processing: the
@@ -92,7 +97,8 @@ typedef enum hawkes_beta_mode {
 typedef struct hawkes_problem {
     int64_t n;           /* number of events, >= 0 */
     int32_t m;           /* number of nodes M, >= 1 */
-    int32_t k;           /* number of decay kernels; must be 1 */
+    int32_t k;           /* number of decay kernels, 1..HAWKES_MAX_KERNELS (1 with
+                            HAWKES_BETA_PER_TARGET; otherwise HAWKES_EINVAL) */
     int32_t beta_mode;   /* hawkes_beta_mode */
     int32_t chunk_log2;  /* 0 = default */
     double  T;           /* window end, >= 0 and >= t[n-1] */
@@ -257,6 +263,42 @@ hawkes_status hawkes_loglik_grad_batched(int32_t S, int64_t n_total, int32_t max
                                          const float* mu, const float* alpha, const float* beta,
                                          double* loglik, double* g_mu, double* g_alpha, double* g_beta,
                                          void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ----------------------------------------------------------------------------
+ * Simulation (input side, not part of the likelihood path): events of the
+ * process on [0, T0] from its branching (cluster) representation, the
+ * construction of the paper's synthetic studies (section "Results").  Node
+ * p's baseline events form a Poisson process of rate mu_p; every event of
+ * node q has Poisson(sum_{k,p} alpha[k][p][q]) children, each of (kernel k,
+ * node p) with probability proportional to alpha[k][p][q], delayed by an
+ * exponential time of rate beta[k] (HAWKES_BETA_SHARED, k kernels) or
+ * beta[p] (HAWKES_BETA_PER_TARGET, k = 1); children after T0 are dropped and
+ * generations repeat until none is left.  Parameters use the layouts of
+ * hawkes_loglik (device pointers).
+ * Output: every event on [0, T0], sorted by time (ties, which have
+ * probability zero, keep generation order), in t_out / marks_out (device,
+ * capacity entries each); *n_out (host) receives the count.  The result
+ * depends only on seed and the parameters (every random number is
+ * Philox4x64-10, Salmon et al. 2011, at a counter naming its use).
+ * The call SYNCHRONISES with the host (generation sizes are read back), so
+ * it cannot be captured in a graph.  If the events exceed capacity it
+ * returns HAWKES_EWORKSPACE with *n_out set to a count that already exceeds
+ * it: call again with a larger capacity (same seed, same result).
+ * Workspace: hawkes_simulate_workspace_bytes(m, k, capacity), about 40 bytes
+ * per event of capacity plus 12 bytes per entry of alpha.
+ * ------------------------------------------------------------------------- */
+size_t hawkes_simulate_workspace_bytes(int32_t m, int32_t k, int64_t capacity);
+
+hawkes_status hawkes_simulate(int32_t m, int32_t k, int32_t beta_mode,
+                              const float* mu, const float* alpha, const float* beta,
+                              double T0, uint64_t seed, int64_t capacity,
+                              double* t_out, int32_t* marks_out, int64_t* n_out,
+                              void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* The simulator's generator evaluated on the host: out = Philox4x64-10 of
+ * counter ctr under key (key[0], key[1]), for checking it against other
+ * implementations of the published definition. */
+void hawkes_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
 
 /* ----------------------------------------------------------------------------
  * Baseline: the sequential recurrence of the "Sequential Recurrence" section

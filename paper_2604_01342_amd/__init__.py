@@ -22,6 +22,8 @@ __all__ = [
     "HawkesError", "lib", "library_path", "workspace_bytes", "loglik", "loglik_grad",
     "intensity", "loglik_batched", "loglik_grad_batched", "sequential_loglik_grad",
     "check_inputs", "HawkesLogLik", "hawkes_loglik", "BETA_SHARED", "BETA_PER_TARGET", "AdamMLE",
+    "Batch", "BatchedGraph", "batched_workspace_bytes", "simulate", "simulate_n",
+    "stationary_rate", "philox4x64_10",
 ]
 
 BETA_SHARED = 0
@@ -96,11 +98,20 @@ def lib():
     L.hawkes_timing_read.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     for f in ("hawkes_timing_enable", "hawkes_timing_reset", "hawkes_timing_read"):
         getattr(L, f).restype = ctypes.c_int
+    L.hawkes_simulate_workspace_bytes.argtypes = [i32, i32, i64]
+    L.hawkes_simulate_workspace_bytes.restype = sz
+    L.hawkes_simulate.argtypes = [i32, i32, i32, vp, vp, vp, d, ctypes.c_uint64, i64, vp, vp,
+                                  ctypes.POINTER(ctypes.c_int64), vp, sz, vp]
+    L.hawkes_simulate.restype = ctypes.c_int
+    L.hawkes_philox4x64_10.argtypes = [ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+                                       ctypes.POINTER(ctypes.c_uint64)]
+    L.hawkes_philox4x64_10.restype = None
     L.hawkes_adam_state_bytes.argtypes = [P]
     L.hawkes_adam_state_bytes.restype = sz
     L.hawkes_adam_init.argtypes = [P, vp, sz, vp]
     L.hawkes_adam_step.argtypes = [P, vp, vp, vp, vp, vp, ctypes.POINTER(_Adam), vp, sz, vp, vp, vp, vp, vp, sz, vp]
-    for f in ("hawkes_loglik", "hawkes_loglik_grad", "hawkes_loglik_grad_support", "hawkes_intensity", "hawkes_sequential_loglik_grad",
+    for f in ("hawkes_loglik", "hawkes_loglik_grad", "hawkes_loglik_grad_support",
+              "hawkes_intensity", "hawkes_sequential_loglik_grad",
               "hawkes_check_inputs", "hawkes_loglik_batched", "hawkes_loglik_grad_batched", "hawkes_adam_init",
               "hawkes_adam_step"):
         getattr(L, f).restype = ctypes.c_int
@@ -144,19 +155,40 @@ def _prep(t, m, mu, alpha, beta):
     mu = mu.detach().to(dtype=torch.float32).contiguous()
     alpha = alpha.detach().to(dtype=torch.float32).contiguous()
     beta = beta.detach().to(device=dev, dtype=torch.float32).reshape(-1).contiguous()
-    if alpha.numel() != mu.numel() ** 2:
-        raise ValueError("alpha must be M x M")
+    M = mu.numel()
+    if alpha.numel() == 0 or alpha.numel() % (M * M):
+        raise ValueError("alpha must be M x M or K x M x M")
     if t.numel() != m.numel():
         raise ValueError("t and marks differ in length")
     return dev, t, m, mu, alpha, beta
 
 
-def _problem(t, mu, beta, T, chunk_log2):
+def _kernels(mu, alpha) -> int:
+    """Number of decay kernels K from alpha's size (K x M x M)."""
+    return alpha.numel() // (mu.numel() ** 2)
+
+
+def _problem(t, mu, beta, T, chunk_log2, alpha=None):
+    """K decay kernels (alpha K x M x M) share a decay each (beta[K]); with
+    K = 1, beta[M] selects one decay per target node."""
     M = mu.numel()
-    mode = BETA_SHARED if beta.numel() == 1 else BETA_PER_TARGET
-    if mode == BETA_PER_TARGET and beta.numel() != M:
-        raise ValueError("beta must have 1 or M entries")
-    return _Problem(t.numel(), M, 1, mode, int(chunk_log2), float(T))
+    K = 1 if alpha is None else _kernels(mu, alpha)
+    if K > 1:
+        if beta.numel() != K:
+            raise ValueError("with K kernels beta must have K entries")
+        mode = BETA_SHARED
+    else:
+        mode = BETA_SHARED if beta.numel() == 1 else BETA_PER_TARGET
+        if mode == BETA_PER_TARGET and beta.numel() != M:
+            raise ValueError("beta must have 1 or M entries")
+    return _Problem(t.numel(), M, K, mode, int(chunk_log2), float(T))
+
+
+def _gshape(mu, alpha):
+    """Shape of dL/dalpha: (M, M), or (K, M, M) with several kernels."""
+    M = mu.numel()
+    K = _kernels(mu, alpha)
+    return (M, M) if K == 1 else (K, M, M)
 
 
 def set_tuning(dense_cols: int = 0, dense_ranges: int = 0, item_log2: int = 0) -> None:
@@ -174,15 +206,16 @@ def get_tuning() -> dict:
     return {"dense_cols": t.dense_cols, "dense_ranges": t.dense_ranges, "item_log2": t.item_log2}
 
 
-def workspace_bytes(n: int, M: int, per_target: bool = False, grad: bool = True, chunk_log2: int = 0) -> int:
-    p = _Problem(n, M, 1, BETA_PER_TARGET if per_target else BETA_SHARED, chunk_log2, 1.0)
+def workspace_bytes(n: int, M: int, per_target: bool = False, grad: bool = True, chunk_log2: int = 0,
+                    K: int = 1) -> int:
+    p = _Problem(n, M, K, BETA_PER_TARGET if per_target else BETA_SHARED, chunk_log2, 1.0)
     return int(lib().hawkes_workspace_bytes(ctypes.byref(p), int(grad)))
 
 
 def loglik(t, m, mu, alpha, beta, T, chunk_log2: int = 0) -> torch.Tensor:
     """Log-likelihood (eq. 2) as a float64 0-d device tensor."""
     dev, t, m, mu, alpha, beta = _prep(t, m, mu, alpha, beta)
-    p = _problem(t, mu, beta, T, chunk_log2)
+    p = _problem(t, mu, beta, T, chunk_log2, alpha)
     L = lib()
     nb = L.hawkes_workspace_bytes(ctypes.byref(p), 0)
     ws = _workspace(dev, nb)
@@ -197,14 +230,14 @@ def loglik_grad(t, m, mu, alpha, beta, T, chunk_log2: int = 0, support: bool = F
     support=True: dL/dalpha only at alpha's nonzeros, 0 elsewhere
     (hawkes_loglik_grad_support)."""
     dev, t, m, mu, alpha, beta = _prep(t, m, mu, alpha, beta)
-    p = _problem(t, mu, beta, T, chunk_log2)
+    p = _problem(t, mu, beta, T, chunk_log2, alpha)
     L = lib()
     nb = L.hawkes_workspace_bytes(ctypes.byref(p), 1)
     ws = _workspace(dev, nb)
     M = mu.numel()
     out = torch.empty(1, dtype=torch.float64, device=dev)
     gmu = torch.empty(M, dtype=torch.float64, device=dev)
-    ga = torch.empty(M, M, dtype=torch.float64, device=dev)
+    ga = torch.empty(_gshape(mu, alpha), dtype=torch.float64, device=dev)
     gb = torch.empty(beta.numel(), dtype=torch.float64, device=dev)
     name = "hawkes_loglik_grad_support" if support else "hawkes_loglik_grad"
     _check(name, getattr(L, name)(ctypes.byref(p), _ptr(t), _ptr(m), _ptr(mu), _ptr(alpha), _ptr(beta), _ptr(out),
@@ -215,7 +248,7 @@ def loglik_grad(t, m, mu, alpha, beta, T, chunk_log2: int = 0, support: bool = F
 def intensity(t, m, mu, alpha, beta, T, chunk_log2: int = 0) -> torch.Tensor:
     """lambda_{m_i}(t_i) for every event (eq. 1), float32."""
     dev, t, m, mu, alpha, beta = _prep(t, m, mu, alpha, beta)
-    p = _problem(t, mu, beta, T, chunk_log2)
+    p = _problem(t, mu, beta, T, chunk_log2, alpha)
     L = lib()
     nb = L.hawkes_workspace_bytes(ctypes.byref(p), 0)
     ws = _workspace(dev, nb)
@@ -228,7 +261,7 @@ def intensity(t, m, mu, alpha, beta, T, chunk_log2: int = 0) -> torch.Tensor:
 def sequential_loglik_grad(t, m, mu, alpha, beta, T):
     """Same outputs as loglik_grad from the one-workgroup sequential baseline kernel."""
     dev, t, m, mu, alpha, beta = _prep(t, m, mu, alpha, beta)
-    p = _problem(t, mu, beta, T, 0)
+    p = _problem(t, mu, beta, T, 0, alpha)
     L = lib()
     M = mu.numel()
     nb = M * M * 8 + 512
@@ -241,6 +274,82 @@ def sequential_loglik_grad(t, m, mu, alpha, beta, T):
            L.hawkes_sequential_loglik_grad(ctypes.byref(p), _ptr(t), _ptr(m), _ptr(mu), _ptr(alpha), _ptr(beta),
                                            _ptr(out), _ptr(gmu), _ptr(ga), _ptr(gb), _ptr(ws), nb, _stream(dev)))
     return out[0], gmu, ga, gb
+
+
+def philox4x64_10(ctr, key) -> list:
+    """The simulator's counter-based generator (Philox4x64-10) evaluated on
+    the host: four 64-bit outputs for a 4-word counter and 2-word key."""
+    c = (ctypes.c_uint64 * 4)(*[int(x) & (2 ** 64 - 1) for x in ctr])
+    k = (ctypes.c_uint64 * 2)(*[int(x) & (2 ** 64 - 1) for x in key])
+    out = (ctypes.c_uint64 * 4)()
+    lib().hawkes_philox4x64_10(c, k, out)
+    return [int(x) for x in out]
+
+
+def stationary_rate(mu, alpha) -> float:
+    """Expected events per unit time of the stationary process,
+    1^T (I - sum_k alpha_k)^{-1} mu (host arithmetic on the parameters, for
+    sizing simulations; rho(sum_k alpha_k) < 1 is assumed)."""
+    import numpy as np
+    mu = np.asarray(mu.detach().cpu() if isinstance(mu, torch.Tensor) else mu, dtype=np.float64).reshape(-1)
+    a = np.asarray(alpha.detach().cpu() if isinstance(alpha, torch.Tensor) else alpha, dtype=np.float64)
+    M = mu.shape[0]
+    A = a.reshape(-1, M, M).sum(axis=0)
+    return float(np.linalg.solve(np.eye(M) - A, mu).sum())
+
+
+def simulate(mu, alpha, beta, T0: float, seed: int, capacity: int | None = None):
+    """Events of the process on [0, T0] by its branching representation, on
+    the GPU (hawkes_simulate): (t float64, marks int32) device tensors sorted
+    by time.  alpha M x M or K x M x M; beta [K] (a decay per kernel) or, with
+    K = 1, [M] (a decay per target node).  The result depends only on seed and
+    the parameters.  capacity: event slots to reserve (default: 1.25 times the
+    stationary expectation plus a margin; grown and retried if exceeded)."""
+    dev = mu.device
+    if dev.type != "cuda":
+        raise ValueError("tensors must be on a GPU device")
+    mu = mu.detach().to(dtype=torch.float32).contiguous()
+    alpha = alpha.detach().to(dtype=torch.float32).contiguous()
+    beta = beta.detach().to(device=dev, dtype=torch.float32).reshape(-1).contiguous()
+    M = mu.numel()
+    K = _kernels(mu, alpha)
+    if K > 1 and beta.numel() != K:
+        raise ValueError("with K kernels beta must have K entries")
+    mode = BETA_PER_TARGET if K == 1 and beta.numel() == M and M > 1 else BETA_SHARED
+    if mode == BETA_SHARED and beta.numel() != K:
+        raise ValueError("beta must have K or (with K = 1) M entries")
+    if capacity is None:
+        capacity = int(1.25 * T0 * stationary_rate(mu, alpha)) + 10_000
+    L = lib()
+    while True:
+        capacity = max(int(capacity), 1)
+        nb = int(L.hawkes_simulate_workspace_bytes(M, K, capacity))
+        if nb == 0:
+            raise HawkesError("hawkes_simulate_workspace_bytes", 1)
+        ws = _aligned(dev, nb)
+        t = torch.empty(capacity, dtype=torch.float64, device=dev)
+        m = torch.empty(capacity, dtype=torch.int32, device=dev)
+        n = ctypes.c_int64(0)
+        st = L.hawkes_simulate(M, K, mode, _ptr(mu), _ptr(alpha), _ptr(beta), float(T0), ctypes.c_uint64(seed),
+                               capacity, _ptr(t), _ptr(m), ctypes.byref(n), _ptr(ws), nb, _stream(dev))
+        if st == 2 and n.value > capacity:
+            capacity = max(2 * capacity, int(1.25 * n.value))
+            continue
+        _check("hawkes_simulate", st)
+        return t[:n.value], m[:n.value]
+
+
+def simulate_n(mu, alpha, beta, n: int, seed: int):
+    """The first n events of a simulated sequence and T = t_n (the window end
+    of an event-count-stopped sample): T0 = 1.2 n / stationary rate, enlarged
+    1.5 times (same seed) until the window holds n events."""
+    T0 = 1.2 * n / stationary_rate(mu, alpha)
+    while True:
+        t, m = simulate(mu, alpha, beta, T0, seed)
+        if t.numel() >= n:
+            t, m = t[:n].clone(), m[:n].clone()
+            return t, m, float(t[-1].item()) if n else 0.0
+        T0 *= 1.5
 
 
 TIMING_KERNELS = {0: "dense_dalpha", 1: "forward", 2: "segment_aggregate", 3: "segment_scan",
@@ -279,7 +388,7 @@ def timing_read() -> dict:
 def check_inputs(t, m, mu, alpha, beta, T) -> int:
     """Device-side precondition check; returns the status bit mask (0 = valid).  Synchronises."""
     dev, t, m, mu, alpha, beta = _prep(t, m, mu, alpha, beta)
-    p = _problem(t, mu, beta, T, 0)
+    p = _problem(t, mu, beta, T, 0, alpha)
     st = torch.zeros(1, dtype=torch.int32, device=dev)
     _check("hawkes_check_inputs", lib().hawkes_check_inputs(ctypes.byref(p), _ptr(t), _ptr(m), _ptr(mu),
                                                             _ptr(alpha), _ptr(beta), _ptr(st), _stream(dev)))
@@ -317,14 +426,25 @@ class Batch:
                    int(bw.m_s.max()))
 
 
-def _batched(b: Batch, grad: bool, out=None):
+def batched_workspace_bytes(b: Batch, grad: bool = True) -> int:
+    """Workspace bytes of a batched call on ``b`` (hawkes_batched_workspace_bytes)."""
+    nb = int(lib().hawkes_batched_workspace_bytes(b.S, b.t.numel(), b.max_m, int(grad)))
+    if nb == 0:
+        raise HawkesError("hawkes_batched_workspace_bytes", 1)
+    return nb
+
+
+def _batched(b: Batch, grad: bool, out=None, ws=None):
+    """ws: a caller-owned workspace (256-byte aligned, at least the queried
+    size) instead of the module's shared one."""
     dev = b.t.device
     L = lib()
     n_total = b.t.numel()
-    nb = L.hawkes_batched_workspace_bytes(b.S, n_total, b.max_m, int(grad))
-    if nb == 0:
-        raise HawkesError("hawkes_batched_workspace_bytes", 1)
-    ws = _workspace(dev, nb)
+    nb = batched_workspace_bytes(b, grad)
+    if ws is None:
+        ws = _workspace(dev, nb)
+    elif ws.numel() < nb or ws.data_ptr() % 256:
+        raise ValueError("workspace too small or not 256-byte aligned")
     if out is None:
         out = (torch.empty(b.S, dtype=torch.float64, device=dev),
                torch.empty(b.mu.numel(), dtype=torch.float64, device=dev) if grad else None,
@@ -359,8 +479,10 @@ class BatchedGraph:
 
     Every replay reads the batch's device arrays in place (new values of the
     same shapes written into them are picked up) and writes the same output
-    tensors, ``out``.  The launch tuning in effect at capture is baked in:
-    capture again after changing it."""
+    tensors, ``out``.  The graph owns its workspace (the captured kernels
+    point into it), so later calls of any size elsewhere cannot move it.  The
+    launch tuning in effect at capture is baked in: capture again after
+    changing it."""
 
     def __init__(self, b: Batch):
         self.b = b
@@ -369,13 +491,14 @@ class BatchedGraph:
                     torch.empty(b.mu.numel(), dtype=torch.float64, device=dev),
                     torch.empty(b.alpha.numel(), dtype=torch.float64, device=dev),
                     torch.empty(b.S, dtype=torch.float64, device=dev))
-        # an eager call first: loads the library, sizes the workspace and sets
-        # kernel attributes, so that nothing allocates during capture
-        _batched(b, True, self.out)
+        self.ws = _aligned(dev, batched_workspace_bytes(b, True))
+        # an eager call first: loads the library and sets kernel attributes,
+        # so that nothing allocates during capture
+        _batched(b, True, self.out, self.ws)
         torch.cuda.synchronize(dev)
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
-            _batched(b, True, self.out)
+            _batched(b, True, self.out, self.ws)
 
     def replay(self):
         """(loglik[S], g_mu, g_alpha, g_beta[S]) of the batch's current values."""
@@ -437,7 +560,7 @@ class AdamMLE:
         dev, t, m, mu, alpha, beta = _prep(t, m, mu, alpha, beta)
         self.dev, self.t, self.m = dev, t, m
         self.mu, self.alpha, self.beta = mu.clone(), alpha.clone(), beta.clone()
-        self.p = _problem(t, self.mu, self.beta, T, chunk_log2)
+        self.p = _problem(t, self.mu, self.beta, T, chunk_log2, self.alpha)
         L = lib()
         self.ws_bytes = int(L.hawkes_workspace_bytes(ctypes.byref(self.p), 1))
         self.ws = _aligned(dev, self.ws_bytes)
@@ -450,7 +573,7 @@ class AdamMLE:
         M = self.mu.numel()
         self.loglik = torch.empty(1, dtype=torch.float64, device=dev)
         self.g_mu = torch.empty(M, dtype=torch.float64, device=dev)
-        self.g_alpha = torch.empty(M, M, dtype=torch.float64, device=dev)
+        self.g_alpha = torch.empty(_gshape(self.mu, self.alpha), dtype=torch.float64, device=dev)
         self.g_beta = torch.empty(self.beta.numel(), dtype=torch.float64, device=dev)
         self.graph = None
         _check("hawkes_adam_init", L.hawkes_adam_init(ctypes.byref(self.p), _ptr(self.state), self.state_bytes,

@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhawkes.so")
-SOURCES = ["hawkes_capi.hip", "hk_small.hip", "hk_large.hip", "hk_pt.hip", "hk_misc.hip", "hk_timing.hip", "hk_adam.hip", "hk_bucket.hip", "hk_dense.hip"]
+SOURCES = ["hawkes_capi.hip", "hk_small.hip", "hk_large.hip", "hk_pt.hip", "hk_misc.hip", "hk_timing.hip", "hk_adam.hip", "hk_bucket.hip", "hk_dense.hip", "hk_sim.hip"]
 ARCH = "gfx950"
 
 

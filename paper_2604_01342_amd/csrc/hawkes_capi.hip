@@ -84,8 +84,10 @@ size_t small_layout(SmallArgs& A, int32_t S, int64_t n_total, int32_t max_m, boo
 
 static bool problem_ok(const hawkes_problem* p) {
     if (!p) return false;
-    if (p->n < 0 || p->m < 1 || p->k < 1) return false;
+    if (p->n < 0 || p->m < 1 || p->k < 1 || p->k > HAWKES_MAX_KERNELS) return false;
     if (p->beta_mode != HAWKES_BETA_SHARED && p->beta_mode != HAWKES_BETA_PER_TARGET) return false;
+    // a decay per target node is one kernel (beta[m])
+    if (p->beta_mode == HAWKES_BETA_PER_TARGET && p->k != 1) return false;
     if (!(p->T >= 0.0) || !isfinite(p->T)) return false;
     if (p->chunk_log2 != 0 && (p->chunk_log2 < 12 || p->chunk_log2 > 26)) return false;
     if ((int64_t)p->m * p->m > ((int64_t)1 << 31)) return false;
@@ -93,7 +95,7 @@ static bool problem_ok(const hawkes_problem* p) {
 }
 
 static bool use_small(const hawkes_problem* p) {
-    return p->beta_mode == HAWKES_BETA_SHARED && p->m <= 8;
+    return p->beta_mode == HAWKES_BETA_SHARED && p->m <= 8 && p->k == 1;
 }
 
 extern "C" {
@@ -133,7 +135,7 @@ hawkes_status hawkes_get_tuning(hawkes_tuning* t) {
 }
 
 size_t hawkes_workspace_bytes(const hawkes_problem* p, int with_grad) {
-    if (!problem_ok(p) || p->k != 1) return 0;
+    if (!problem_ok(p)) return 0;
     if (use_small(p)) {
         SmallArgs A;
         memset(&A, 0, sizeof(A));
@@ -153,7 +155,7 @@ __global__ void mask_to_support(int64_t n, const float* __restrict__ alpha, doub
 
 static hawkes_status mask_support(const hawkes_problem* p, const float* alpha, double* g_alpha, hipStream_t st) {
     if (!g_alpha) return HAWKES_OK;
-    const int64_t n = (int64_t)p->m * p->m;
+    const int64_t n = (int64_t)p->k * p->m * p->m;
     const int64_t nb = (n + 255) / 256;
     hipLaunchKernelGGL(mask_to_support, dim3((unsigned)(nb < 4096 ? nb : 4096)), dim3(256), 0, st, n, alpha,
                        g_alpha);
@@ -166,7 +168,6 @@ static hawkes_status run_single(const hawkes_problem* p, const double* t, const 
                                 size_t ws_bytes, hipStream_t stream, bool support = false) {
     if (!problem_ok(p) || !mu || !alpha || !beta) return HAWKES_EINVAL;
     if (!loglik && !lambda_out) return HAWKES_EINVAL;
-    if (p->k != 1) return HAWKES_EUNSUPPORTED;
     if (p->n > 0 && (!t || !marks)) return HAWKES_EINVAL;
     if (!ws) return HAWKES_EWORKSPACE;
     if (use_small(p)) {
@@ -193,11 +194,11 @@ static hawkes_status run_single(const hawkes_problem* p, const double* t, const 
     A.loglik = loglik ? loglik : A.ll_scratch;
     A.g_mu = g_mu; A.g_alpha = g_alpha; A.g_beta = g_beta;
     A.lambda_out = lambda_out;
-    // shared decay: the first term only on the support (forward pass); per
-    // target: the dense gradient, masked
-    A.support = support && !A.per_target;
+    // one shared decay: the first term only on the support (forward pass);
+    // per target or several kernels: the dense gradient, masked
+    A.support = support && !A.per_target && A.K == 1;
     const hawkes_status st = run_large(A, stream);
-    return st == HAWKES_OK && support && A.per_target ? mask_support(p, alpha, g_alpha, stream) : st;
+    return st == HAWKES_OK && support && !A.support ? mask_support(p, alpha, g_alpha, stream) : st;
 }
 
 hawkes_status hawkes_loglik(const hawkes_problem* p, const double* t, const int32_t* marks, const float* mu,

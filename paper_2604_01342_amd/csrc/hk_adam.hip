@@ -14,17 +14,17 @@
 namespace hk {
 
 // state layout (float64 header, then float32 moments):
-//   [0] step count, [1..31] unused, then m and v for mu[M], alpha[M*M], beta[nb]
+//   [0] step count, [1..31] unused, then m and v for mu[M], alpha[K*M*M], beta[nb]
 struct AdamLayout {
-    int64_t M, MM, nb, np;
+    int64_t M, MM, nb, np;   // MM: alpha entries over all K kernels
     size_t bytes;
 };
 
 static AdamLayout adam_layout(const hawkes_problem* p) {
     AdamLayout L;
     L.M = p->m;
-    L.MM = (int64_t)p->m * p->m;
-    L.nb = p->beta_mode == HAWKES_BETA_PER_TARGET ? p->m : 1;
+    L.MM = (int64_t)p->k * p->m * p->m;
+    L.nb = p->beta_mode == HAWKES_BETA_PER_TARGET ? p->m : p->k;
     L.np = L.M + L.MM + L.nb;
     L.bytes = 256 + (size_t)L.np * 2 * sizeof(float);
     return L;
@@ -65,7 +65,7 @@ __global__ void adam_update(int64_t M, int64_t MM, int64_t nb, double scale, haw
         // off-diagonal alpha entries below the hinge point (float32 compare)
         double gl = -g / scale;
         if (i >= M && i < M + MM) {
-            const int64_t a = i - M;
+            const int64_t a = (i - M) % (M * M);   // entry within its kernel's matrix
             if (a / M != a % M && *x < cfg.h) gl += (double)cfg.lambda1;
         }
         const double x0 = (double)*x;
@@ -90,12 +90,12 @@ using namespace hk;
 extern "C" {
 
 size_t hawkes_adam_state_bytes(const hawkes_problem* p) {
-    if (!p || p->m < 1 || p->k != 1) return 0;
+    if (!p || p->m < 1 || p->k < 1 || p->k > HAWKES_MAX_KERNELS) return 0;
     return adam_layout(p).bytes;
 }
 
 hawkes_status hawkes_adam_init(const hawkes_problem* p, void* state, size_t state_bytes, hipStream_t stream) {
-    if (!p || p->m < 1 || p->k != 1 || !state) return HAWKES_EINVAL;
+    if (!p || p->m < 1 || p->k < 1 || p->k > HAWKES_MAX_KERNELS || !state) return HAWKES_EINVAL;
     const AdamLayout L = adam_layout(p);
     if (state_bytes < L.bytes) return HAWKES_EWORKSPACE;
     float* mom = (float*)((char*)state + 256);

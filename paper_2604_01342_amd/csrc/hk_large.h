@@ -25,9 +25,12 @@
 
 namespace hk {
 
+#define HK_KMAX 8          // decay kernels per problem (shared decay per kernel)
+
 struct LargeArgs {
     int64_t n;
     int32_t M;
+    int32_t K;            // decay kernels (shared decay): alpha[K][M][M], beta[K]
     int32_t per_target;   // beta[M] instead of beta[1]
     double T;
     int64_t CH;           // events per chunk
@@ -47,9 +50,11 @@ struct LargeArgs {
     const double* t;
     const int32_t* marks;
     const float *mu, *alpha, *beta;
-    // workspace
+    // workspace (with K > 1 the per-kernel arrays below are K consecutive
+    // copies: csr_*, colsum, node_info, carry, carry_seg, gpart, spart, cpart_)
     int32_t *csr_ptr, *csr_col;
     float *csr_val, *colsum;
+    double *rk, *dk;      // K > 1: [K][CH] per event of the chunk, R_k and D_k (alpha row . K and . J)
     double* agg;          // [nseg][2M] segment maps (K_run, J_run)
     double* seg_span;     // [nseg] time from the event before the segment to its last event
     double* seg_dec;      // [nseg] e^{-beta (span of the segment from the preceding event)}
@@ -61,8 +66,8 @@ struct LargeArgs {
     int4* node_info;      // [M] (csr begin, csr end, mu, colsum)
     double* carry;        // [2M] chunk carry (K, J) at carry_t
     double* carry_t;      // [1] time of the carry (last event before the chunk)
-    double* seg_part;     // [nseg][4]
-    double* acc;          // [4] call-level sums: logsum, comp, E, gbeta
+    double* seg_part;     // [nseg][2 + 2K]
+    double* acc;          // [2 + 2K] call-level sums: logsum, comp, E[K], gbeta[K]
     double* ll_scratch;   // [1] log-likelihood slot when the caller wants intensities only
     double *gpart, *spart, *cpart_;  // [ER][M][M]; [ER][M] per target, [NRUN][M] shared decay
     double* gsup;         // [min(8, ER)][M*M] support-restricted first term of eq. 9 in CSR order (the
@@ -74,7 +79,9 @@ struct LargeArgs {
     // per-target decays (R-form forward, reverse adjoint for the gradient)
     int32_t *csc_ptr, *csc_row;   // alpha by column: targets p of source q
     float* csc_val;
-    float* wv;            // [n] w_i = 1/lambda_i per event
+    float* wv;            // [CH] w_i = 1/lambda_i of the chunk's events
+    double* pt_ck;        // [2 HK_PTCK][2M] chunk-start states (R, D): level-1 slots, then level-2 slots
+    int64_t pt_ckr;       // chunks per level-1 slot
     double* ebseg;        // [nseg][M] per segment: sum_j alpha_{p,m_j} (T - t_j) e^{-beta_p (T - t_j)}
                           //   minus sum_{i: m_i = p} w_i (R_i - beta_p D_i)
     double* ebacc;        // [M] the same over the whole sequence (= -dL/dbeta_p)
@@ -104,6 +111,7 @@ struct LargeArgs {
 };
 
 #define HK_SG 32           // segments per scan group
+#define HK_PTCK 64         // checkpoint slots per level of the per-target gradient (at most 64^2 chunks)
 
 size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, size_t ws_bytes);
 hawkes_status run_large(LargeArgs& A, hipStream_t st);
@@ -114,7 +122,7 @@ hawkes_status allow_lds(const void* kernel, size_t bytes);
 void large_build_index(int32_t M, const float* alpha, int trans, int32_t* ptr, int32_t* idx, float* val,
                        hipStream_t st);
 void large_scan(LargeArgs& A, int32_t nseg, const float* beta_pt, hipStream_t st);
-void large_chunk_acc_launch(int32_t nseg, const double* seg_part, double* acc, hipStream_t st);
+void large_chunk_acc_launch(int32_t nseg, int32_t width, const double* seg_part, double* acc, hipStream_t st);
 void bucket_chunk(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, const float* wchunk, int bs, hipStream_t st);
 void bucket_chunk_into(const LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, const float* wchunk, int bs,
                        int32_t* cnt, int32_t* off, int32_t* base, uint32_t* key, double* tt, float* ww,

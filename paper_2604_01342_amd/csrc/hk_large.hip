@@ -312,13 +312,16 @@ __global__ void large_scan_apply(int32_t nseg, int32_t M, const double* __restri
 #ifndef HK_FWW
 #define HK_FWW 2   // waves per forward-pass segment
 #endif
+// RM (several decay kernels): the pass runs once per kernel and writes, per
+// event, R = alpha_{m_i,:} . K(t_i) to rk and (GRAD) D = alpha_{m_i,:} . J(t_i)
+// to dk instead of forming lambda; large_combine then sums the kernels.
 // SUPP (with GRAD): also adds beta w_i K_q(t_i) to gsup[k] for every nonzero
 // k = (m_i, q) of alpha's CSR (hardware float64 atomics): the first term of
 // eq. 9 on alpha's support only.  Segment s adds into copy s & cmask (copies
 // MM apart): consecutive workgroups go to different XCDs, so each copy sees
 // mostly one XCD's atomics and a copy's addresses see a fraction of the
 // contention.
-template <bool GRAD, bool INTENS, bool SUPP, int NW>
+template <bool GRAD, bool INTENS, bool SUPP, int NW, bool RM = false>
 __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1, int32_t M, double T,
                                                     const double* __restrict__ t, const int32_t* __restrict__ marks,
                                                     const float* __restrict__ mu, const float* __restrict__ beta,
@@ -329,7 +332,8 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
                                                     double* __restrict__ seg_part,
                                                     float* __restrict__ wchunk,
                                                     float* __restrict__ lambda_out,
-                                                    double* __restrict__ gsup, int32_t cmask) {
+                                                    double* __restrict__ gsup, int32_t cmask,
+                                                    double* __restrict__ rk, double* __restrict__ dk) {
     extern __shared__ double lds[];
     double* rtau = lds;                                   // [M] time of the record
     uint64_t* rmask = (uint64_t*)(lds + M);               // [M] lanes of this batch with mark q
@@ -342,6 +346,7 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
     // of each event's row of alpha
     const int wv = NW == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     static_assert(!SUPP || NW == 1, "the support-restricted sums are formed by one wave");
+    static_assert(!(RM && (SUPP || INTENS)), "per-kernel sums only");
     const int64_t a = c0 + (int64_t)s * HK_SEG;
     const int64_t b = a + HK_SEG < c1 ? a + HK_SEG : c1;
     const double bet = (double)beta[0];
@@ -501,7 +506,15 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
             }
         }
         double ei = 1.0;   // e^{-beta u_i} (anchored records)
-        if (valid && wv == 0) {
+        if (RM && valid && wv == 0) {
+            if (anch) {
+                ei = exp_f64(-bet * ui);
+                R *= ei;
+                Dd *= ei;
+            }
+            rk[i - c0] = R;
+            if (GRAD) dk[i - c0] = Dd;
+        } else if (valid && wv == 0) {
             if (anch) {
                 ei = exp_f64(-bet * ui);
                 R *= ei;
@@ -537,7 +550,7 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
                 }
             }
         }
-        if (GRAD && valid && wv == 0) wchunk[i - c0] = (float)w;
+        if (!RM && GRAD && valid && wv == 0) wchunk[i - c0] = (float)w;
         __syncthreads();
         if (anch) {
             // anchored records: the batch's events of a node add their terms,
@@ -595,7 +608,7 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
     }
     // deterministic wave reduction of the float64 partials (the first
     // wave's; the others hold none)
-    if (wv != 0) return;
+    if (RM || wv != 0) return;
     for (int off = 32; off > 0; off >>= 1) {
         logsum += __shfl_down(logsum, off, 64);
         comp += __shfl_down(comp, off, 64);
@@ -608,15 +621,82 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
     }
 }
 
-// acc[k] += sum over segments of seg_part[s][k]; fixed-order tree (deterministic)
-__global__ __launch_bounds__(256) void large_chunk_acc(int32_t nseg, const double* __restrict__ seg_part,
+// acc[k] += sum over segments of seg_part[s][k] (width values per segment);
+// fixed-order tree (deterministic)
+__global__ __launch_bounds__(256) void large_chunk_acc(int32_t nseg, int32_t width,
+                                                       const double* __restrict__ seg_part,
                                                        double* __restrict__ acc) {
     __shared__ double sh[256];
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < width; ++k) {
         double v = 0.0;
-        for (int32_t s = threadIdx.x; s < nseg; s += 256) v += seg_part[(int64_t)s * 4 + k];
+        for (int32_t s = threadIdx.x; s < nseg; s += 256) v += seg_part[(int64_t)s * width + k];
         const double tot = block_sum_d<256>(v, sh);
         if (threadIdx.x == 0) acc[k] += tot;
+    }
+}
+
+// Several decay kernels (Background, eq. 1 with K > 1): the per-kernel
+// forward passes left R_k(i) = alpha^k_{m_i,:} . K^k(t_i) and D_k(i) =
+// alpha^k_{m_i,:} . J^k(t_i) for each event of the chunk; here
+//   lambda_i = mu_{m_i} + sum_k beta_k R_k(i),   w_i = 1 / lambda_i,
+// and the segment's float64 partials: log-sum, compensator
+// sum_k colsum_k[m_i] (1 - e^{-beta_k (T - t_i)}), and per kernel E_k (its
+// beta-derivative) and sum_i w_i (R_k(i) - beta_k D_k(i)) (eq. 10 per kernel).
+// One workgroup of 256 per segment, fixed-order block sums.
+template <bool GRAD, bool INTENS>
+__global__ __launch_bounds__(256) void large_combine(int64_t c0, int64_t c1, int32_t M, int32_t K, double T,
+                                                     const double* __restrict__ t,
+                                                     const int32_t* __restrict__ marks,
+                                                     const float* __restrict__ mu, const float* __restrict__ beta,
+                                                     const float* __restrict__ colsum,
+                                                     const double* __restrict__ rk, const double* __restrict__ dk,
+                                                     int64_t CH, double* __restrict__ seg_part,
+                                                     float* __restrict__ wchunk, float* __restrict__ lambda_out) {
+    __shared__ double sh[256];
+    const int32_t s = blockIdx.x;
+    const int64_t a = c0 + (int64_t)s * HK_SEG;
+    const int64_t b = a + HK_SEG < c1 ? a + HK_SEG : c1;
+    double logsum = 0.0, comp = 0.0, E[HK_KMAX], gb[HK_KMAX];
+#pragma unroll
+    for (int k = 0; k < HK_KMAX; ++k) E[k] = gb[k] = 0.0;
+    for (int64_t i = a + threadIdx.x; i < b; i += 256) {
+        const int mi = clamp_mark(marks[i], M);
+        const double ti = t[i];
+        const int64_t r = i - c0;
+        double lam = (double)mu[mi];
+        for (int k = 0; k < K; ++k) lam = __builtin_fma((double)beta[k], rk[k * CH + r], lam);
+        if (INTENS) lambda_out[i] = (float)lam;
+        logsum += log(lam);
+        const double w = 1.0 / lam;
+        if (GRAD) wchunk[r] = (float)w;
+#pragma unroll
+        for (int k = 0; k < HK_KMAX; ++k) {
+            if (k < K) {
+                const double bk = (double)beta[k];
+                const double x = bk * (T - ti);
+                const double cs = (double)colsum[(int64_t)k * M + mi];
+                comp += cs * -expm1(-x);
+                if (GRAD) {
+                    E[k] += cs * (T - ti) * exp_f64(-x);
+                    gb[k] += w * (rk[k * CH + r] - bk * dk[k * CH + r]);
+                }
+            }
+        }
+    }
+    const int W = 2 + 2 * K;
+    double* o = seg_part + (int64_t)s * W;
+    double v = block_sum_d<256>(logsum, sh);
+    if (threadIdx.x == 0) o[0] = v;
+    v = block_sum_d<256>(comp, sh);
+    if (threadIdx.x == 0) o[1] = v;
+#pragma unroll
+    for (int k = 0; k < HK_KMAX; ++k) {
+        if (k < K) {
+            v = block_sum_d<256>(E[k], sh);
+            if (threadIdx.x == 0) o[2 + k] = v;
+            v = block_sum_d<256>(gb[k], sh);
+            if (threadIdx.x == 0) o[2 + K + k] = v;
+        }
     }
 }
 
@@ -636,11 +716,15 @@ __global__ void large_colfold(int32_t M, int32_t NSC, double* __restrict__ spart
     cpart[q] = c;
 }
 
+// Kernel k of K (decay kernels): the log-likelihood and dL/dmu with k = 0,
+// dL/dbeta_k from the call-level sums acc = (logsum, comp, E[K], gbeta[K]),
+// dL/dalpha of kernel k from its partials (g_alpha, gpart and cpart point at
+// kernel k's).
 __global__ __launch_bounds__(256) void large_final(int32_t M, int32_t ER, int32_t NSC, double T, const float* __restrict__ mu,
                             const double* __restrict__ acc, const double* __restrict__ gpart,
                             const double* __restrict__ spart, const double* __restrict__ cpart,
                             double* __restrict__ loglik, double* __restrict__ g_mu, double* __restrict__ g_alpha,
-                            double* __restrict__ g_beta, int grad, int sup) {
+                            double* __restrict__ g_beta, int grad, int sup, int32_t K, int32_t k) {
     const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t MM = (int64_t)M * M;
     if (blockIdx.x == 0) {
@@ -655,8 +739,8 @@ __global__ __launch_bounds__(256) void large_final(int32_t M, int32_t ER, int32_
             __syncthreads();
         }
         if (threadIdx.x == 0) {
-            loglik[0] = acc[0] - T * ps[0] - acc[1];
-            if (grad && g_beta) g_beta[0] = acc[3] - acc[2];
+            if (k == 0) loglik[0] = acc[0] - T * ps[0] - acc[1];
+            if (grad && g_beta) g_beta[k] = acc[2 + K + k] - acc[2 + k];
         }
     }
     if (!grad) return;
@@ -669,7 +753,7 @@ __global__ __launch_bounds__(256) void large_final(int32_t M, int32_t ER, int32_
         for (int32_t e = 0; e < NSC; ++e) c += cpart[(int64_t)e * M + q];
         g_alpha[x] = g - c;
     }
-    if (x < M && g_mu) {
+    if (x < M && g_mu && k == 0) {
         double s = 0.0;
         for (int32_t e = 0; e < NSC; ++e) s += spart[(int64_t)e * M + x];
         g_mu[x] = s - T;
@@ -701,9 +785,13 @@ __global__ __launch_bounds__(64) void large_sup_scatter(int32_t M, int32_t ncopy
 size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, size_t ws_bytes) {
     A.n = p->n;
     A.M = p->m;
+    A.K = p->k;
     A.per_target = p->beta_mode == HAWKES_BETA_PER_TARGET;
     A.T = p->T;
-    const int lg = p->chunk_log2 ? p->chunk_log2 : 20;
+    // chunks no longer than the sequence needs (at least 2^12 events): the
+    // per-chunk buffers then scale with n for short sequences
+    int lg = p->chunk_log2 ? p->chunk_log2 : 20;
+    while (lg > 12 && ((int64_t)1 << (lg - 1)) >= p->n) --lg;
     A.CH = (int64_t)1 << lg;
     A.nchunks = (A.n + A.CH - 1) / A.CH;
     A.nseg = (int32_t)((A.CH + HK_SEG - 1) / HK_SEG);
@@ -746,7 +834,7 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
     const int64_t want = (target + nbb - 1) / nbb;
     int32_t er = 1;
     while (er < want) er <<= 1;
-    if (tu.dense_ranges > 0) er = tu.dense_ranges;
+    if (!A.per_target && tu.dense_ranges > 0) er = tu.dense_ranges;   // a knob of the shared-decay kernel only
     while (er > A.nseg && er > 1) er >>= 1;
     // shared decay: every wave of a dense workgroup gets at least one run
     while (!A.per_target && er > 1 && A.nseg / er < HK_DW) er >>= 1;
@@ -758,12 +846,16 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
     if (A.CKR < 1) A.CKR = 1;
     A.NRUN = A.nseg / A.CKR;
     A.grad = grad;
-    const int64_t M = A.M, MM = M * M;
+    const int64_t M = A.M, MM = M * M, K = A.K;
     Carve c(ws, ws_bytes);
-    A.csr_ptr = c.take<int32_t>(M + 1);
-    A.csr_col = c.take<int32_t>(MM);
-    A.csr_val = c.take<float>(MM);
-    A.colsum = c.take<float>(M);
+    A.csr_ptr = c.take<int32_t>(K * (M + 1));
+    A.csr_col = c.take<int32_t>(K * MM);
+    A.csr_val = c.take<float>(K * MM);
+    A.colsum = c.take<float>(K * M);
+    if (K > 1) {
+        A.rk = c.take<double>((size_t)K * A.CH);
+        if (grad) A.dk = c.take<double>((size_t)K * A.CH);
+    }
     A.agg = c.take<double>((size_t)A.nseg * 2 * M);
     A.seg_span = c.take<double>(A.nseg);
     A.seg_dec = c.take<double>(A.nseg);
@@ -774,12 +866,12 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
     A.gcarry = c.take<double>((size_t)A.ngr * 2 * M);
     A.gspan = c.take<double>(A.ngr);
     A.gdec = c.take<double>(A.ngr);
-    A.node_info = c.take<int4>(M);
-    A.carry_seg = c.take<double>((size_t)A.nseg * 2 * M);
-    A.carry = c.take<double>(2 * M);
+    A.node_info = c.take<int4>(K * M);
+    A.carry_seg = c.take<double>((size_t)K * A.nseg * 2 * M);
+    A.carry = c.take<double>(K * 2 * M);
     A.carry_t = c.take<double>(1);
-    A.seg_part = c.take<double>((size_t)A.nseg * 4);
-    A.acc = c.take<double>(4);
+    A.seg_part = c.take<double>((size_t)A.nseg * (2 + 2 * K));
+    A.acc = c.take<double>(2 + 2 * K);
     A.ll_scratch = c.take<double>(1);
     if (A.per_target) {
         A.csc_ptr = c.take<int32_t>(M + 1);
@@ -788,7 +880,13 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
         A.ebseg = c.take<double>((size_t)A.nseg * M);
         A.ebacc = c.take<double>(M);
         if (grad) {
-            A.wv = c.take<float>((size_t)(A.n > 0 ? A.n : 1));
+            // constant memory: w of one chunk, and two levels of chunk-start
+            // states (the chunks of each level-1 slot are chained again into
+            // the level-2 slots during the reverse sweep)
+            A.wv = c.take<float>((size_t)A.CH);
+            A.pt_ckr = (A.nchunks + HK_PTCK - 1) / HK_PTCK;
+            if (A.pt_ckr < 1) A.pt_ckr = 1;
+            A.pt_ck = c.take<double>((size_t)2 * HK_PTCK * 2 * M);
             A.aggA = c.take<double>((size_t)A.nseg * M);
             A.rcarry_seg = c.take<double>((size_t)A.nseg * M);
             A.rgagg = c.take<double>((size_t)A.ngr * M);
@@ -806,10 +904,10 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
             A.bk_t = c.take<double>(A.CH);
             A.bk_w = c.take<float>(A.CH);
         }
-        A.gpart = c.take<double>((size_t)A.ER * MM);
+        A.gpart = c.take<double>((size_t)K * A.ER * MM);
         const int64_t nsp = A.per_target ? A.ER : A.NRUN;
-        A.spart = c.take<double>((size_t)nsp * M);
-        A.cpart_ = c.take<double>((size_t)nsp * M);
+        A.spart = c.take<double>((size_t)K * nsp * M);
+        A.cpart_ = c.take<double>((size_t)K * nsp * M);
         if (!A.per_target) {
             A.nslot = A.CH / (64 * A.NGW) + 2 * (int64_t)A.NBC * A.NRUN + 2;
             A.kck = c.take<double>((size_t)A.nslot * HK_SLOT_WORDS(A.CPL, A.NGW));
@@ -826,8 +924,8 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
     return c.off + 256;
 }
 
-void large_chunk_acc_launch(int32_t nseg, const double* seg_part, double* acc, hipStream_t st) {
-    hipLaunchKernelGGL(large_chunk_acc, dim3(1), dim3(256), 0, st, nseg, seg_part, acc);
+void large_chunk_acc_launch(int32_t nseg, int32_t width, const double* seg_part, double* acc, hipStream_t st) {
+    hipLaunchKernelGGL(large_chunk_acc, dim3(1), dim3(256), 0, st, nseg, width, seg_part, acc);
 }
 
 size_t lds_limit() {
@@ -902,8 +1000,128 @@ void large_scan(LargeArgs& A, int32_t nseg, const float* beta_pt, hipStream_t st
                        A.seg_off, A.seg_offdec, A.gcarry, A.carry_seg, beta_pt);
 }
 
+// Several decay kernels (K > 1, shared decay per kernel; Background eq. 1,
+// gradients per kernel as in eqs. 8-10).  Per chunk: for each kernel k its
+// segment maps, carries and forward pass (R mode), then large_combine forms
+// lambda and the shared w_i = 1/lambda_i; with the gradient the chunk's events
+// are partitioned once and the dense dL/dalpha kernels run once per kernel
+// (decay beta_k, kernel k's state checkpoints and partial sums).
+static hawkes_status run_large_multi(LargeArgs& A, hipStream_t st) {
+    const int32_t M = A.M, K = A.K;
+    const int64_t MM = (int64_t)M * M;
+    const unsigned gM = (unsigned)((M + 255) / 256);
+    const size_t lds_agg = (size_t)2 * M * sizeof(double);
+    const size_t lds_fwd = (size_t)M * (sizeof(double) + sizeof(uint64_t) + 2 * sizeof(double));
+    if (allow_lds((const void*)large_seg_agg, lds_agg) != HAWKES_OK ||
+        allow_lds((const void*)large_forward<true, false, false, HK_FWW, true>, lds_fwd) != HAWKES_OK ||
+        allow_lds((const void*)large_forward<false, false, false, HK_FWW, true>, lds_fwd) != HAWKES_OK)
+        return HAWKES_EUNSUPPORTED;
+    if (A.grad && (uint64_t)A.nslot * (uint64_t)HK_SLOT_WORDS(A.CPL, A.NGW) * 8u >= (1ull << 32))
+        return HAWKES_EUNSUPPORTED;
+    const int32_t W = 2 + 2 * K;
+    hipLaunchKernelGGL(fill_d, dim3(16), dim3(256), 0, st, A.carry, (int64_t)K * 2 * M, 0.0);
+    hipLaunchKernelGGL(fill_d, dim3(1), dim3(64), 0, st, A.acc, (int64_t)W, 0.0);
+    if (A.grad) {
+        const int64_t ng = (int64_t)K * A.ER * MM;
+        hipLaunchKernelGGL(fill_d, dim3((unsigned)((ng + 255) / 256 < 65535 ? (ng + 255) / 256 : 65535)),
+                           dim3(256), 0, st, A.gpart, ng, 0.0);
+        hipLaunchKernelGGL(fill_d, dim3(64), dim3(256), 0, st, A.spart, (int64_t)K * A.NRUN * M, 0.0);
+        hipLaunchKernelGGL(fill_d, dim3(64), dim3(256), 0, st, A.cpart_, (int64_t)K * A.NRUN * M, 0.0);
+    }
+    // per kernel: column sums, CSR copy and node records of alpha^k
+    for (int32_t k = 0; k < K; ++k) {
+        const float* ak = A.alpha + (int64_t)k * MM;
+        int32_t* pk = A.csr_ptr + (int64_t)k * (M + 1);
+        hipLaunchKernelGGL(large_colsum, dim3((unsigned)((M + 63) / 64)), dim3(1024), 0, st, M, ak,
+                           A.colsum + (int64_t)k * M);
+        large_build_index(M, ak, 0, pk, A.csr_col + k * MM, A.csr_val + k * MM, st);
+        hipLaunchKernelGGL(large_node_info, dim3(gM), dim3(256), 0, st, M, pk, A.mu, A.colsum + (int64_t)k * M,
+                           A.node_info + (int64_t)k * M);
+    }
+    // kernel k's view of the per-kernel arrays
+    auto view = [&](int32_t k) {
+        LargeArgs B = A;
+        B.K = 1;
+        B.beta = A.beta + k;
+        B.carry = A.carry + (int64_t)k * 2 * M;
+        B.carry_seg = A.carry_seg + (int64_t)k * A.nseg * 2 * M;
+        B.gpart = A.gpart ? A.gpart + (int64_t)k * A.ER * MM : nullptr;
+        B.spart = A.spart ? A.spart + (int64_t)k * A.NRUN * M : nullptr;
+        B.cpart_ = A.cpart_ ? A.cpart_ + (int64_t)k * A.NRUN * M : nullptr;
+        return B;
+    };
+    for (int64_t ch = 0; ch < A.nchunks; ++ch) {
+        const int64_t c0 = ch * A.CH;
+        const int64_t c1 = c0 + A.CH < A.n ? c0 + A.CH : A.n;
+        const int32_t nseg = (int32_t)((c1 - c0 + HK_SEG - 1) / HK_SEG);
+        for (int32_t k = 0; k < K; ++k) {
+            LargeArgs B = view(k);
+            {
+                TimedScope ts(2, st);
+                hipLaunchKernelGGL(large_seg_agg, dim3(nseg), dim3(64), lds_agg, st, c0, c1, M, A.t, A.marks,
+                                   B.beta, B.agg, B.seg_span, B.seg_dec);
+            }
+            {
+                TimedScope ts(3, st);
+                large_scan(B, nseg, nullptr, st);
+            }
+            TimedScope ts(1, st);
+            if (A.grad)
+                hipLaunchKernelGGL((large_forward<true, false, false, HK_FWW, true>), dim3(nseg), dim3(64 * HK_FWW),
+                                   lds_fwd, st, c0, c1, M, A.T, A.t, A.marks, A.mu, B.beta,
+                                   A.node_info + (int64_t)k * M, A.csr_col + k * MM, A.csr_val + k * MM, B.carry_seg,
+                                   A.seg_part, A.wchunk, (float*)nullptr, (double*)nullptr, 0,
+                                   A.rk + (int64_t)k * A.CH, A.dk + (int64_t)k * A.CH);
+            else
+                hipLaunchKernelGGL((large_forward<false, false, false, HK_FWW, true>), dim3(nseg), dim3(64 * HK_FWW),
+                                   lds_fwd, st, c0, c1, M, A.T, A.t, A.marks, A.mu, B.beta,
+                                   A.node_info + (int64_t)k * M, A.csr_col + k * MM, A.csr_val + k * MM, B.carry_seg,
+                                   A.seg_part, A.wchunk, (float*)nullptr, (double*)nullptr, 0,
+                                   A.rk + (int64_t)k * A.CH, (double*)nullptr);
+        }
+        {
+            TimedScope ts(1, st);
+            if (A.grad)
+                hipLaunchKernelGGL((large_combine<true, false>), dim3(nseg), dim3(256), 0, st, c0, c1, M, K, A.T, A.t,
+                                   A.marks, A.mu, A.beta, A.colsum, A.rk, A.dk, A.CH, A.seg_part, A.wchunk,
+                                   (float*)nullptr);
+            else if (A.lambda_out)
+                hipLaunchKernelGGL((large_combine<false, true>), dim3(nseg), dim3(256), 0, st, c0, c1, M, K, A.T, A.t,
+                                   A.marks, A.mu, A.beta, A.colsum, A.rk, A.dk, A.CH, A.seg_part, A.wchunk,
+                                   A.lambda_out);
+            else
+                hipLaunchKernelGGL((large_combine<false, false>), dim3(nseg), dim3(256), 0, st, c0, c1, M, K, A.T,
+                                   A.t, A.marks, A.mu, A.beta, A.colsum, A.rk, A.dk, A.CH, A.seg_part, A.wchunk,
+                                   (float*)nullptr);
+        }
+        hipLaunchKernelGGL(large_chunk_acc, dim3(1), dim3(256), 0, st, nseg, W, A.seg_part, A.acc);
+        if (A.grad) {
+            {
+                TimedScope tb(6, st);
+                bucket_chunk_into(A, c0, c1, nseg, A.wchunk, A.DRB, A.bo_cnt, A.bo_off, A.bo_base, A.bo_key, A.bo_t,
+                                  A.bo_w, st);
+            }
+            for (int32_t k = 0; k < K; ++k) {
+                LargeArgs B = view(k);
+                large_dense_launch(B, c0, c1, nseg, st, false);
+            }
+        }
+    }
+    const int64_t nfin = A.grad ? (MM > M ? MM : M) : 1;
+    for (int32_t k = 0; k < K; ++k) {
+        LargeArgs B = view(k);
+        if (A.grad) hipLaunchKernelGGL(large_colfold, dim3(gM), dim3(256), 0, st, M, A.NRUN, B.spart, B.cpart_);
+        hipLaunchKernelGGL(large_final, dim3((unsigned)((nfin + 255) / 256)), dim3(256), 0, st, M, A.ER, 1, A.T,
+                           A.mu, A.acc, B.gpart, B.spart, B.cpart_, A.loglik, A.g_mu,
+                           A.g_alpha ? A.g_alpha + k * MM : nullptr, A.g_beta, A.grad ? 1 : 0, 0, K, k);
+        if (!A.grad) break;   // the log-likelihood needs one launch
+    }
+    return hipGetLastError() == hipSuccess ? HAWKES_OK : HAWKES_EDEVICE;
+}
+
 hawkes_status run_large(LargeArgs& A, hipStream_t st) {
     if (A.per_target) return run_large_pt(A, st);
+    if (A.K > 1) return run_large_multi(A, st);
     const int32_t M = A.M;
     const int64_t MM = (int64_t)M * M;
     const unsigned gM = (unsigned)((M + 255) / 256);
@@ -956,24 +1174,28 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
             if (sup)
                 hipLaunchKernelGGL((large_forward<true, false, true, 1>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1,
                                    M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
-                                   A.carry_seg, A.seg_part, A.wchunk, (float*)nullptr, A.gsup, ncopy - 1);
+                                   A.carry_seg, A.seg_part, A.wchunk, (float*)nullptr, A.gsup, ncopy - 1,
+                                   (double*)nullptr, (double*)nullptr);
             else if (A.grad)
                 hipLaunchKernelGGL((large_forward<true, false, false, HK_FWW>), dim3(nseg), dim3(64 * HK_FWW), lds_fwd,
                                    st, c0, c1,
                                    M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
-                                   A.carry_seg, A.seg_part, A.wchunk, (float*)nullptr, (double*)nullptr, 0);
+                                   A.carry_seg, A.seg_part, A.wchunk, (float*)nullptr, (double*)nullptr, 0,
+                                   (double*)nullptr, (double*)nullptr);
             else if (A.lambda_out)
                 hipLaunchKernelGGL((large_forward<false, true, false, HK_FWW>), dim3(nseg), dim3(64 * HK_FWW), lds_fwd,
                                    st, c0, c1,
                                    M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
-                                   A.carry_seg, A.seg_part, A.wchunk, A.lambda_out, (double*)nullptr, 0);
+                                   A.carry_seg, A.seg_part, A.wchunk, A.lambda_out, (double*)nullptr, 0,
+                                   (double*)nullptr, (double*)nullptr);
             else
                 hipLaunchKernelGGL((large_forward<false, false, false, HK_FWW>), dim3(nseg), dim3(64 * HK_FWW), lds_fwd,
                                    st, c0, c1,
                                    M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
-                                   A.carry_seg, A.seg_part, A.wchunk, (float*)nullptr, (double*)nullptr, 0);
+                                   A.carry_seg, A.seg_part, A.wchunk, (float*)nullptr, (double*)nullptr, 0,
+                                   (double*)nullptr, (double*)nullptr);
         }
-        hipLaunchKernelGGL(large_chunk_acc, dim3(1), dim3(256), 0, st, nseg, A.seg_part, A.acc);
+        hipLaunchKernelGGL(large_chunk_acc, dim3(1), dim3(256), 0, st, nseg, 4, A.seg_part, A.acc);
         if (A.grad) {
             {
                 TimedScope tb(6, st);
@@ -989,7 +1211,7 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
     if (A.grad) hipLaunchKernelGGL(large_colfold, dim3(gM), dim3(256), 0, st, M, A.NRUN, A.spart, A.cpart_);
     hipLaunchKernelGGL(large_final, dim3((unsigned)((nfin + 255) / 256)), dim3(256), 0, st, M, A.ER, 1, A.T, A.mu,
                        A.acc, A.gpart, A.spart, A.cpart_, A.loglik, A.g_mu, A.g_alpha, A.g_beta, A.grad ? 1 : 0,
-                       sup ? 1 : 0);
+                       sup ? 1 : 0, 1, 0);
     if (sup && A.g_alpha)
         hipLaunchKernelGGL(large_sup_scatter, dim3((unsigned)M), dim3(64), 0, st, M, ncopy, A.csr_ptr, A.csr_col,
                            A.gsup, A.cpart_, A.g_alpha);

@@ -132,10 +132,10 @@ __global__ void check_events(int64_t n, int32_t M, double T, const double* __res
     if (bad) atomicOr(status, bad);
 }
 
-__global__ void check_params(int32_t M, int32_t nbeta, const float* __restrict__ mu, const float* __restrict__ alpha,
-                             const float* __restrict__ beta, int32_t* status) {
+__global__ void check_params(int32_t M, int32_t K, int32_t nbeta, const float* __restrict__ mu,
+                             const float* __restrict__ alpha, const float* __restrict__ beta, int32_t* status) {
     int32_t bad = 0;
-    const int64_t MM = (int64_t)M * M;
+    const int64_t MM = (int64_t)K * M * M;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < MM; i += (int64_t)gridDim.x * blockDim.x) {
         const float a = alpha[i];
         if (!(a >= 0.0f) || !isfinite(a)) bad |= 16;
@@ -156,8 +156,8 @@ hawkes_status run_check_inputs(const hawkes_problem* p, const double* t, const i
     hipLaunchKernelGGL(check_zero, dim3(1), dim3(64), 0, st, status_out);
     if (p->n > 0)
         hipLaunchKernelGGL(check_events, dim3(1024), dim3(256), 0, st, p->n, p->m, p->T, t, marks, status_out);
-    const int32_t nb = p->beta_mode == HAWKES_BETA_PER_TARGET ? p->m : 1;
-    hipLaunchKernelGGL(check_params, dim3(256), dim3(256), 0, st, p->m, nb, mu, alpha, beta, status_out);
+    const int32_t nb = p->beta_mode == HAWKES_BETA_PER_TARGET ? p->m : p->k;
+    hipLaunchKernelGGL(check_params, dim3(256), dim3(256), 0, st, p->m, p->k, nb, mu, alpha, beta, status_out);
     return hipGetLastError() == hipSuccess ? HAWKES_OK : HAWKES_EDEVICE;
 }
 

@@ -42,6 +42,12 @@ __global__ void pt_fill(double* p, int64_t n, double v) {
         p[i] = v;
 }
 
+// dst[i] = src[i] (a chunk-start state into or out of a checkpoint slot)
+__global__ void pt_copy(double* __restrict__ dst, const double* __restrict__ src, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 // adjoint seed at T: A_p(T) = 1 / beta_p
 __global__ void pt_seed(int32_t M, const float* __restrict__ beta, double* __restrict__ a) {
     const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -147,6 +153,7 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
                                                  const double* __restrict__ carry_seg, double* __restrict__ seg_part,
                                                  double* __restrict__ ebseg, float* __restrict__ wv,
                                                  float* __restrict__ lambda_out) {
+    // wv: 1/lambda of the chunk's events, indexed from the chunk start c0
     extern __shared__ double lds[];
     double* rtau = lds;
     double* rR = lds + M;
@@ -267,7 +274,7 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
             if (INTENS) lambda_out[ie] = (float)lam;
             if (GRAD) {
                 const double w = 1.0 / lam;
-                wv[ie] = (float)w;
+                wv[ie - c0] = (float)w;
                 atomicAdd(&gbl[mv], w * (Rk - bm * Dk));
             }
         }
@@ -306,7 +313,7 @@ __device__ __forceinline__ double seg_first_time(const double* __restrict__ t, i
 }
 
 // aggA[s][p] = sum_{i in segment s, m_i = p} w_i e^{-beta_p (t_i - t_first(s))}
-// one wave per segment, LDS aA[M]
+// (wv indexed from the chunk start c0); one wave per segment, LDS aA[M]
 __global__ __launch_bounds__(64) void pt_rev_agg(int64_t c0, int64_t c1, int32_t M, const double* __restrict__ t,
                                                  const int32_t* __restrict__ marks, const float* __restrict__ beta,
                                                  const float* __restrict__ wv, double* __restrict__ aggA) {
@@ -323,7 +330,7 @@ __global__ __launch_bounds__(64) void pt_rev_agg(int64_t c0, int64_t c1, int32_t
         const int64_t i = base + lane;
         if (i < b) {
             const int p = clamp_mark(marks[i], M);
-            const double w = (double)wv[i];
+            const double w = (double)wv[i - c0];
             atomicAdd(&aA[p], w * (double)exp2_f64arg((tf - t[i]) * ((double)beta[p] * HK_LOG2E)));
         }
     }
@@ -629,6 +636,8 @@ hawkes_status run_large_pt(LargeArgs& A, hipStream_t st) {
         allow_lds((const void*)pt_forward<false, false>, lds_fwd) != HAWKES_OK ||
         allow_lds((const void*)pt_rev_agg, lds_rev) != HAWKES_OK)
         return HAWKES_EUNSUPPORTED;
+    // the gradient's two checkpoint levels hold at most HK_PTCK^2 chunks
+    if (A.grad && A.pt_ckr > HK_PTCK) return HAWKES_EUNSUPPORTED;
     auto fill = [&](double* p, int64_t cnt, double v) {
         const int64_t nb = (cnt + 255) / 256;
         hipLaunchKernelGGL(pt_fill, dim3((unsigned)(nb < 65535 ? (nb > 0 ? nb : 1) : 65535)), dim3(256), 0, st, p,
@@ -643,19 +652,25 @@ hawkes_status run_large_pt(LargeArgs& A, hipStream_t st) {
         fill(A.cpart_, (int64_t)A.ER * M, 0.0);
     }
     large_build_index(M, A.alpha, 1, A.csc_ptr, A.csc_row, A.csc_val, st);
-    for (int64_t ch = 0; ch < A.nchunks; ++ch) {
-        const int64_t c0 = ch * A.CH;
-        const int64_t c1 = c0 + A.CH < A.n ? c0 + A.CH : A.n;
-        const int32_t nseg = (int32_t)((c1 - c0 + HK_SEG - 1) / HK_SEG);
+    const int64_t M2 = 2 * (int64_t)M;
+    auto chunk_range = [&](int64_t ch, int64_t& c0, int64_t& c1) -> int32_t {
+        c0 = ch * A.CH;
+        c1 = c0 + A.CH < A.n ? c0 + A.CH : A.n;
+        return (int32_t)((c1 - c0 + HK_SEG - 1) / HK_SEG);
+    };
+    // segment maps and their scan: carry_seg of the chunk from A.carry (its
+    // start state), which moves to the chunk's end
+    auto agg_scan = [&](int64_t c0, int64_t c1, int32_t nseg) {
         {
             TimedScope ts(2, st);
             hipLaunchKernelGGL(pt_seg_agg, dim3(nseg), dim3(64), lds_agg, st, c0, c1, M, A.T, A.t, A.marks, A.beta,
                                A.csc_ptr, A.csc_row, A.csc_val, A.agg, A.seg_span, A.ebseg, A.seg_part);
         }
-        {
-            TimedScope ts(3, st);
-            large_scan(A, nseg, A.beta, st);
-        }
+        TimedScope ts(3, st);
+        large_scan(A, nseg, A.beta, st);
+    };
+    // the forward pass of a chunk (after agg_scan), then its call-level sums
+    auto forward = [&](int64_t c0, int64_t c1, int32_t nseg) {
         {
             TimedScope ts(1, st);
             if (A.grad)
@@ -671,40 +686,86 @@ hawkes_status run_large_pt(LargeArgs& A, hipStream_t st) {
                                    A.t, A.marks, A.mu, A.beta, A.csc_ptr, A.csc_row, A.csc_val, A.carry_seg,
                                    A.seg_part, A.ebseg, (float*)nullptr, (float*)nullptr);
         }
-        large_chunk_acc_launch(nseg, A.seg_part, A.acc, st);
+        large_chunk_acc_launch(nseg, 4, A.seg_part, A.acc, st);
         hipLaunchKernelGGL(pt_eb_reduce, dim3(gM), dim3(256), 0, st, nseg, M, A.ebseg, A.ebacc);
-    }
-    if (A.grad && A.n > 0) {
+    };
+    auto copy = [&](double* dst, const double* src) {
+        hipLaunchKernelGGL(pt_copy, dim3((unsigned)((M2 + 255) / 256)), dim3(256), 0, st, dst, src, M2);
+    };
+    if (!A.grad) {
+        // log-likelihood (or intensities) only: one pass in order
+        for (int64_t ch = 0; ch < A.nchunks; ++ch) {
+            int64_t c0, c1;
+            const int32_t nseg = chunk_range(ch, c0, c1);
+            agg_scan(c0, c1, nseg);
+            forward(c0, c1, nseg);
+        }
+    } else if (A.n > 0) {
+        // Gradient in constant memory (the batches of Algorithm 2, each
+        // forward pass followed by its backward pass; here the backward runs
+        // right to left, so the chunks are visited in reverse).  Pass 1 only
+        // chains the chunks' maps and keeps the state at the start of every
+        // r-th chunk (one block of r chunks per level-1 slot); pass 2 takes
+        // the blocks from the last: it chains the block's chunks again from
+        // its slot into the level-2 slots, then per chunk from the last:
+        // maps and scan from the chunk's start state, the forward pass (w_i
+        // of the chunk's events, the chunk's log-likelihood terms), the
+        // reverse scan of the adjoint state and the dense dL/dalpha.
+        const int64_t r = A.pt_ckr;
+        const int64_t nblk_c = (A.nchunks + r - 1) / r;
+        double* ck1 = A.pt_ck;
+        double* ck2 = A.pt_ck + (int64_t)HK_PTCK * M2;
+        for (int64_t ch = 0; ch < A.nchunks; ++ch) {
+            int64_t c0, c1;
+            const int32_t nseg = chunk_range(ch, c0, c1);
+            if (ch % r == 0) copy(ck1 + (ch / r) * M2, A.carry);
+            if (ch + 1 < A.nchunks) agg_scan(c0, c1, nseg);
+        }
         hipLaunchKernelGGL(pt_seed, dim3(gM), dim3(256), 0, st, M, A.beta, A.achunk);
-        for (int64_t ch = A.nchunks - 1; ch >= 0; --ch) {
-            const int64_t c0 = ch * A.CH;
-            const int64_t c1 = c0 + A.CH < A.n ? c0 + A.CH : A.n;
-            const int32_t nseg = (int32_t)((c1 - c0 + HK_SEG - 1) / HK_SEG);
-            const int32_t ngr = (nseg + HK_SG - 1) / HK_SG;
-            const int64_t nloc = (int64_t)ngr * M, napp = (int64_t)nseg * M;
-            {
-                TimedScope ts(3, st);
-                hipLaunchKernelGGL(pt_rev_agg, dim3(nseg), dim3(64), lds_rev, st, c0, c1, M, A.t, A.marks, A.beta,
-                                   A.wv, A.aggA);
-                hipLaunchKernelGGL(pt_rscan_local, dim3((unsigned)((nloc + 255) / 256)), dim3(256), 0, st, c0, c1,
-                                   A.n, A.T, nseg, M, A.t, A.beta, A.aggA, A.rcarry_seg, A.rgagg);
-                hipLaunchKernelGGL(pt_rscan_groups, dim3(gM), dim3(256), 0, st, c0, c1, A.n, A.T, nseg, M, A.t,
-                                   A.beta, A.rgagg, A.rgcarry, A.achunk);
-                hipLaunchKernelGGL(pt_rscan_apply, dim3((unsigned)((napp + 255) / 256)), dim3(256), 0, st, c0, c1,
-                                   A.n, A.T, nseg, M, A.t, A.beta, A.rgcarry, A.rcarry_seg);
+        for (int64_t b = nblk_c - 1; b >= 0; --b) {
+            const int64_t cb0 = b * r, cb1 = cb0 + r < A.nchunks ? cb0 + r : A.nchunks;
+            double* starts = r == 1 ? ck1 + b * M2 : ck2;
+            if (r > 1) {
+                copy(A.carry, ck1 + b * M2);
+                for (int64_t ch = cb0; ch < cb1; ++ch) {
+                    int64_t c0, c1;
+                    const int32_t nseg = chunk_range(ch, c0, c1);
+                    copy(ck2 + (ch - cb0) * M2, A.carry);
+                    if (ch + 1 < cb1) agg_scan(c0, c1, nseg);
+                }
             }
-            {
-                TimedScope tb(6, st);
-                bucket_chunk(A, c0, c1, nseg, A.wv + c0, 6, st);
+            for (int64_t ch = cb1 - 1; ch >= cb0; --ch) {
+                int64_t c0, c1;
+                const int32_t nseg = chunk_range(ch, c0, c1);
+                copy(A.carry, starts + (ch - cb0) * M2);
+                agg_scan(c0, c1, nseg);
+                forward(c0, c1, nseg);
+                const int32_t ngr = (nseg + HK_SG - 1) / HK_SG;
+                const int64_t nloc = (int64_t)ngr * M, napp = (int64_t)nseg * M;
+                {
+                    TimedScope ts(3, st);
+                    hipLaunchKernelGGL(pt_rev_agg, dim3(nseg), dim3(64), lds_rev, st, c0, c1, M, A.t, A.marks,
+                                       A.beta, A.wv, A.aggA);
+                    hipLaunchKernelGGL(pt_rscan_local, dim3((unsigned)((nloc + 255) / 256)), dim3(256), 0, st, c0,
+                                       c1, A.n, A.T, nseg, M, A.t, A.beta, A.aggA, A.rcarry_seg, A.rgagg);
+                    hipLaunchKernelGGL(pt_rscan_groups, dim3(gM), dim3(256), 0, st, c0, c1, A.n, A.T, nseg, M, A.t,
+                                       A.beta, A.rgagg, A.rgcarry, A.achunk);
+                    hipLaunchKernelGGL(pt_rscan_apply, dim3((unsigned)((napp + 255) / 256)), dim3(256), 0, st, c0,
+                                       c1, A.n, A.T, nseg, M, A.t, A.beta, A.rgcarry, A.rcarry_seg);
+                }
+                {
+                    TimedScope tb(6, st);
+                    bucket_chunk(A, c0, c1, nseg, A.wv, 6, st);
+                }
+                const int32_t spr = (nseg + A.ER - 1) / A.ER;
+                const int32_t nbb = A.NB * A.NB;
+                const unsigned nblk = A.ER >= 8 ? (unsigned)(nbb * ((A.ER + 7) / 8) * 8)
+                                                : (unsigned)(((nbb + 8 / A.ER - 1) / (8 / A.ER)) * 8);
+                TimedScope ts(0, st);
+                hipLaunchKernelGGL(pt_dense, dim3(nblk), dim3(64 * HK_DWP), 0, st, c0, c1, A.n, A.T, M, A.NB, A.ER,
+                                   spr, nseg, A.t, A.beta, A.rcarry_seg, A.rgcarry, A.bk_off, A.bk_base, A.bk_key,
+                                   A.bk_t, A.bk_w, A.gpart, A.spart, A.cpart_);
             }
-            const int32_t spr = (nseg + A.ER - 1) / A.ER;
-            const int32_t nbb = A.NB * A.NB;
-            const unsigned nblk = A.ER >= 8 ? (unsigned)(nbb * ((A.ER + 7) / 8) * 8)
-                                            : (unsigned)(((nbb + 8 / A.ER - 1) / (8 / A.ER)) * 8);
-            TimedScope ts(0, st);
-            hipLaunchKernelGGL(pt_dense, dim3(nblk), dim3(64 * HK_DWP), 0, st, c0, c1, A.n, A.T, M, A.NB, A.ER, spr, nseg, A.t,
-                               A.beta, A.rcarry_seg, A.rgcarry, A.bk_off, A.bk_base, A.bk_key, A.bk_t, A.bk_w, A.gpart,
-                               A.spart, A.cpart_);
         }
     }
     const int64_t nfin = A.grad ? (MM > M ? MM : M) : 1;

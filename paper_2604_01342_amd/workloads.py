@@ -34,7 +34,7 @@ import numpy as np
 __all__ = [
     "Workload", "BatchWorkload", "spectral_radius", "rescale_to_radius",
     "simulate_branching", "simulate_thinning_univariate", "make_config",
-    "make_batched", "random_params", "cached",
+    "make_batched", "random_params", "cached", "config_params", "c5_params",
 ]
 
 
@@ -287,29 +287,40 @@ def _simulate_n(rng, mu, alpha, beta, n):
 _FULL_N = {1: 10_000, 2: 1_000_000, 4: 10_000_000, 5: 50_000_000}
 
 
-def make_config(c: int, n: int | None = None) -> Workload:
-    """Single-sequence workload c in {1, 2, 4, 5}; ``n`` overrides the event count."""
-    if c not in _FULL_N:
-        raise ValueError(f"no single-sequence workload {c}")
-    N = _FULL_N[c] if n is None else int(n)
+def config_params(c: int):
+    """(mu, alpha, beta) of single-sequence workload c in {1, 2, 4, 5} as
+    float32 (the values the library receives), from seed 1000 c + 1."""
     rp = np.random.Generator(np.random.PCG64(1000 * c + 1))
-    re = np.random.Generator(np.random.PCG64(1000 * c + 2))
     if c == 1:
         mu, alpha, beta = np.array([0.5]), np.array([[0.5]]), np.array([1.0])
-        mu32, al32, be32 = (x.astype(np.float32) for x in (mu, alpha, beta))
-        t, m = simulate_thinning_univariate(re, float(mu32[0]), float(al32[0, 0]), float(be32[0]), N)
     elif c == 2:
         mu, alpha = random_params(rp, 16, 0.05, 0.2, 1.0, 0.7)
         beta = np.array([1.0])
     elif c == 4:
         mu, alpha = random_params(rp, 1000, 0.01, 0.05, 0.01, 0.8)
         beta = np.array([1.0])
-    else:
+    elif c == 5:
         mu, alpha = random_params(rp, 4096, 0.01, 0.05, 0.002, 0.85)
         beta = rp.uniform(0.5, 2.0, size=4096)
-    mu32 = mu.astype(np.float32)
-    al32 = alpha.astype(np.float32)
-    be32 = beta.astype(np.float32)
+    else:
+        raise ValueError(f"no single-sequence workload {c}")
+    return mu.astype(np.float32), alpha.astype(np.float32), beta.astype(np.float32)
+
+
+def c5_params():
+    """Parameters of workload c5 (M = 4096, decay per target node)."""
+    return config_params(5)
+
+
+def make_config(c: int, n: int | None = None) -> Workload:
+    """Single-sequence workload c in {1, 2, 4, 5}; ``n`` overrides the event count."""
+    if c not in _FULL_N:
+        raise ValueError(f"no single-sequence workload {c}")
+    N = _FULL_N[c] if n is None else int(n)
+    re = np.random.Generator(np.random.PCG64(1000 * c + 2))
+    mu32, al32, be32 = config_params(c)
+    if c == 1:
+        t, m = simulate_thinning_univariate(re, float(mu32[0]), float(al32[0, 0]), float(be32[0]), N)
     if c != 1:
         t, m = _simulate_n(re, mu32.astype(np.float64), al32.astype(np.float64),
                            be32.astype(np.float64), N)

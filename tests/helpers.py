@@ -31,3 +31,35 @@ def rand_problem(seed, n, M, per_target=False, ties=False, density=1.0, rate=1.0
     beta = (rng.uniform(0.5, 2.0, size=M) if per_target else rng.uniform(0.5, 2.0, size=1)).astype(np.float32)
     T = float(t[-1] + rng.uniform(0.0, 1.0)) if n else 1.5
     return t, m, mu, alpha, beta, T
+
+
+class PackedBatch:
+    """Packed arrays of S sequences in the batched ABI's layout (see hawkes.h)."""
+
+    def __init__(self, ev_off, m_s, T_s, t, m, mu, alpha, beta):
+        self.ev_off, self.m_s, self.T_s, self.t, self.m = ev_off, m_s, T_s, t, m
+        self.mu, self.alpha, self.beta = mu, alpha, beta
+        self.S = len(m_s)
+        self.mu_off = np.concatenate([[0], np.cumsum(m_s)]).astype(np.int64)
+        self.a_off = np.concatenate([[0], np.cumsum(m_s.astype(np.int64) ** 2)]).astype(np.int64)
+
+    def seq(self, s):
+        """(t, marks, mu, alpha [M, M], beta [1], T) of sequence s."""
+        M = int(self.m_s[s])
+        e0, e1 = int(self.ev_off[s]), int(self.ev_off[s + 1])
+        return (self.t[e0:e1], self.m[e0:e1], self.mu[self.mu_off[s]:self.mu_off[s + 1]],
+                self.alpha[self.a_off[s]:self.a_off[s + 1]].reshape(M, M), self.beta[s:s + 1], float(self.T_s[s]))
+
+
+def rand_batch(seed, S, m_choices, lo=1, hi=10_000, n_empty=0, rate=2.0):
+    """S random sorted sequences with node counts drawn from m_choices and
+    lengths log-uniform in [lo, hi] (the first n_empty sequences are empty)."""
+    rng = np.random.default_rng(seed)
+    m_s = rng.choice(np.asarray(m_choices), size=S).astype(np.int32)
+    lens = np.exp(rng.uniform(np.log(lo), np.log(hi), size=S)).round().astype(np.int64)
+    lens[:n_empty] = 0
+    parts = [rand_problem(int(rng.integers(1 << 30)), int(lens[s]), int(m_s[s]), rate=rate) for s in range(S)]
+    ev_off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    cat = lambda k, dt: (np.concatenate([np.ravel(p[k]) for p in parts]).astype(dt) if S else np.zeros(0, dt))
+    return PackedBatch(ev_off, m_s, np.array([p[5] for p in parts]), cat(0, np.float64), cat(1, np.int32),
+                       cat(2, np.float32), cat(3, np.float32), cat(4, np.float32))

@@ -26,6 +26,17 @@ def test_per_target_matches_adjoint_oracle(H, seed, n, M, density, ties, chunk):
     check(run_gpu(H, t, m, mu, alpha, beta, T, chunk), ref, label=f"per-target n={n} M={M} chunk={chunk}")
 
 
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("n,M", [(64 * 4096, 20), (64 * 4096 + 1, 20), (300_000, 30), (4096 * 200 + 77, 12)])
+def test_per_target_gradient_checkpoint_levels(H, n, M):
+    # the gradient keeps chunk-start states in 64 level-1 slots: 64 chunks of
+    # 2^12 events take one level, one event more makes two chunks per slot
+    # (level-2 slots refilled per block in the reverse sweep), and so on
+    t, m, mu, alpha, beta, T = rand_problem(60 + M, n, M, per_target=True, density=0.3, rate=20.0)
+    ref = oracle.adjoint(t, m, mu, alpha, beta, T)
+    check(run_gpu(H, t, m, mu, alpha, beta, T, 12), ref, label=f"per-target checkpoints n={n} M={M} chunk=12")
+
+
 def test_per_target_node_limit(H):
     # the per-target forward kernel keeps 32 bytes of LDS per node plus a
     # 24 KiB staging area: M <= 4352 under MI355X's 160 KiB per workgroup,
