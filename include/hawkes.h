@@ -164,6 +164,34 @@ hawkes_status hawkes_loglik_grad(const hawkes_problem* p,
                                  double* loglik, double* g_mu, double* g_alpha, double* g_beta,
                                  void* workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* ----------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as hawkes_loglik_grad, with the workspace taken from a fixed
+ * device array inside the library (HAWKES_NOALLOC_SCRATCH_BYTES per device,
+ * reserved when the library's code is loaded on a device and held until the
+ * process ends) instead of a caller argument.  The call allocates nothing:
+ * its first call on a device only resolves that array's address there (no
+ * allocation); every later call reuses it.  The caller still owns and passes
+ * the inputs and outputs, with the layouts and NULL rules of
+ * hawkes_loglik_grad (loglik is required).
+ * Limit: problems whose hawkes_workspace_bytes(p, 1) exceeds
+ * HAWKES_NOALLOC_SCRATCH_BYTES return HAWKES_EWORKSPACE before anything is
+ * launched; a smaller chunk_log2 shrinks the workspace of long sequences.
+ * Argument errors return what hawkes_loglik_grad returns.
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents (each call re-initialises what it needs): calls that may
+ * overlap on one device, on different streams or from different threads,
+ * race and must be ordered by the caller.
+ * ------------------------------------------------------------------------- */
+#define HAWKES_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+hawkes_status hawkes_loglik_grad_noalloc(const hawkes_problem* p,
+                                         const double* t, const int32_t* marks,
+                                         const float* mu, const float* alpha, const float* beta,
+                                         double* loglik, double* g_mu, double* g_alpha, double* g_beta,
+                                         hipStream_t stream);
+
 /* The same, with dL/dalpha restricted to alpha's support, for models with a
  * sparse interaction matrix (the sparse cross-node influence that the
  * penalty of section "Background" aims at; sections "Introduction" and

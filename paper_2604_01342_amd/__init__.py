@@ -22,7 +22,7 @@ __all__ = [
     "HawkesError", "lib", "library_path", "workspace_bytes", "loglik", "loglik_grad",
     "intensity", "loglik_batched", "loglik_grad_batched", "sequential_loglik_grad",
     "check_inputs", "HawkesLogLik", "hawkes_loglik", "BETA_SHARED", "BETA_PER_TARGET", "AdamMLE",
-    "Batch", "BatchedGraph", "batched_workspace_bytes", "simulate", "simulate_n",
+    "Batch", "BatchedGraph", "batched_workspace_bytes", "loglik_grad_noalloc", "simulate", "simulate_n",
     "stationary_rate", "philox4x64_10",
 ]
 
@@ -82,6 +82,7 @@ def lib():
     L.hawkes_loglik.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.hawkes_loglik_grad.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.hawkes_loglik_grad_support.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.hawkes_loglik_grad_noalloc.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.hawkes_intensity.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.hawkes_sequential_loglik_grad.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.hawkes_check_inputs.argtypes = [P, vp, vp, vp, vp, vp, vp, vp]
@@ -110,7 +111,7 @@ def lib():
     L.hawkes_adam_state_bytes.restype = sz
     L.hawkes_adam_init.argtypes = [P, vp, sz, vp]
     L.hawkes_adam_step.argtypes = [P, vp, vp, vp, vp, vp, ctypes.POINTER(_Adam), vp, sz, vp, vp, vp, vp, vp, sz, vp]
-    for f in ("hawkes_loglik", "hawkes_loglik_grad", "hawkes_loglik_grad_support",
+    for f in ("hawkes_loglik", "hawkes_loglik_grad", "hawkes_loglik_grad_support", "hawkes_loglik_grad_noalloc",
               "hawkes_intensity", "hawkes_sequential_loglik_grad",
               "hawkes_check_inputs", "hawkes_loglik_batched", "hawkes_loglik_grad_batched", "hawkes_adam_init",
               "hawkes_adam_step"):
@@ -243,6 +244,29 @@ def loglik_grad(t, m, mu, alpha, beta, T, chunk_log2: int = 0, support: bool = F
     _check(name, getattr(L, name)(ctypes.byref(p), _ptr(t), _ptr(m), _ptr(mu), _ptr(alpha), _ptr(beta), _ptr(out),
                                   _ptr(gmu), _ptr(ga), _ptr(gb), _ptr(ws), nb, _stream(dev)))
     return out[0], gmu, ga, gb
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # HAWKES_NOALLOC_SCRATCH_BYTES
+
+
+def loglik_grad_noalloc(t, m, mu, alpha, beta, T, chunk_log2: int = 0, out=None):
+    """As loglik_grad, through hawkes_loglik_grad_noalloc: the library takes
+    its workspace from its fixed per-device scratch (problems whose workspace
+    exceeds NOALLOC_SCRATCH_BYTES are refused).  ``out``: preallocated
+    (loglik[1], g_mu[M], g_alpha[M, M], g_beta) float64 tensors, so that the
+    call allocates nothing on this side either."""
+    dev, t, m, mu, alpha, beta = _prep(t, m, mu, alpha, beta)
+    p = _problem(t, mu, beta, T, chunk_log2, alpha)
+    M = mu.numel()
+    if out is None:
+        out = (torch.empty(1, dtype=torch.float64, device=dev), torch.empty(M, dtype=torch.float64, device=dev),
+               torch.empty(_gshape(mu, alpha), dtype=torch.float64, device=dev),
+               torch.empty(beta.numel(), dtype=torch.float64, device=dev))
+    ll, gmu, ga, gb = out
+    _check("hawkes_loglik_grad_noalloc",
+           lib().hawkes_loglik_grad_noalloc(ctypes.byref(p), _ptr(t), _ptr(m), _ptr(mu), _ptr(alpha), _ptr(beta),
+                                            _ptr(ll), _ptr(gmu), _ptr(ga), _ptr(gb), _stream(dev)))
+    return ll[0], gmu, ga, gb
 
 
 def intensity(t, m, mu, alpha, beta, T, chunk_log2: int = 0) -> torch.Tensor:

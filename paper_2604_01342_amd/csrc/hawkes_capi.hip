@@ -94,6 +94,38 @@ static bool problem_ok(const hawkes_problem* p) {
     return true;
 }
 
+// ---------------------------------------------------------------- fixed scratch
+// The workspace of hawkes_loglik_grad_noalloc: one array per device, part of
+// the library's code object, held until the process ends.  Host code never
+// passes `scratch` itself to a kernel (on the host the name is only a
+// stand-in, not a device address); it uses the address that
+// hipGetSymbolAddress returns for the current device, resolved once per device
+// at the entry point's first call there.
+static __device__ __align__(256) unsigned char scratch[HAWKES_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[HK_MAX_DEVICES];
+
+static hawkes_status scratch_address(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return HAWKES_EDEVICE;
+    }
+    if (dev < 0 || dev >= HK_MAX_DEVICES) return HAWKES_EDEVICE;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return HAWKES_EDEVICE;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return HAWKES_OK;
+}
+
 static bool use_small(const hawkes_problem* p) {
     return p->beta_mode == HAWKES_BETA_SHARED && p->m <= 8 && p->k == 1;
 }
@@ -214,6 +246,24 @@ hawkes_status hawkes_loglik_grad(const hawkes_problem* p, const double* t, const
                                  hipStream_t stream) {
     return run_single(p, t, marks, mu, alpha, beta, loglik, g_mu, g_alpha, g_beta, nullptr, true, workspace,
                       workspace_bytes, stream);
+}
+
+hawkes_status hawkes_loglik_grad_noalloc(const hawkes_problem* p, const double* t, const int32_t* marks,
+                                         const float* mu, const float* alpha, const float* beta, double* loglik,
+                                         double* g_mu, double* g_alpha, double* g_beta, hipStream_t stream) {
+    // every host check of hawkes_loglik_grad first, so that a bad argument
+    // gives the same status; then the problem's workspace must fit the
+    // fixed scratch
+    if (!problem_ok(p) || !mu || !alpha || !beta || !loglik) return HAWKES_EINVAL;
+    if (p->n > 0 && (!t || !marks)) return HAWKES_EINVAL;
+    const size_t need = hawkes_workspace_bytes(p, 1);
+    if (need == 0) return HAWKES_EUNSUPPORTED;
+    if (need > (size_t)HAWKES_NOALLOC_SCRATCH_BYTES) return HAWKES_EWORKSPACE;
+    void* ws = nullptr;
+    const hawkes_status st = scratch_address(&ws);
+    if (st != HAWKES_OK) return st;
+    return run_single(p, t, marks, mu, alpha, beta, loglik, g_mu, g_alpha, g_beta, nullptr, true, ws,
+                      (size_t)HAWKES_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 hawkes_status hawkes_loglik_grad_support(const hawkes_problem* p, const double* t, const int32_t* marks,

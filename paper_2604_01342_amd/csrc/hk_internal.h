@@ -6,6 +6,7 @@
 #include "../../include/hawkes.h"
 
 #define HK_RCH 256          // items per first-level reduction chunk (small engine)
+#define HK_MAX_DEVICES 64   // devices with a resolved fixed-scratch address
 
 namespace hk {
 

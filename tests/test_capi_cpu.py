@@ -31,7 +31,7 @@ def test_header_declares_expected_api():
               "hawkes_workspace_bytes", "hawkes_batched_workspace_bytes", "hawkes_sequential_loglik_grad",
               "hawkes_intensity", "hawkes_check_inputs", "hawkes_status_string", "hawkes_version",
               "hawkes_adam_state_bytes", "hawkes_adam_init", "hawkes_adam_step", "hawkes_set_tuning",
-              "hawkes_get_tuning", "hawkes_loglik_grad_support"):
+              "hawkes_get_tuning", "hawkes_loglik_grad_support", "hawkes_loglik_grad_noalloc"):
         assert f in names
 
 
@@ -160,6 +160,13 @@ def test_host_argument_errors(H):
     assert L.hawkes_loglik_grad_support(ctypes.byref(pl), nul, *args[1:], FAKE, FAKE, FAKE, FAKE, 1 << 30,
                                         nul) == 1
     assert L.hawkes_loglik_grad_support(ctypes.byref(p2), *args, FAKE, FAKE, FAKE, FAKE, 1 << 30, nul) == 1
+    # the allocation-free variant: the same argument checks; a workspace above
+    # its fixed scratch is refused
+    assert L.hawkes_loglik_grad_noalloc(ctypes.byref(p2), *args, FAKE, FAKE, FAKE, FAKE, nul) == 1
+    assert L.hawkes_loglik_grad_noalloc(ctypes.byref(p), nul, *args[1:], FAKE, FAKE, FAKE, FAKE, nul) == 1
+    big = P(H, n=3_000_000, m=1000)
+    assert L.hawkes_workspace_bytes(ctypes.byref(big), 1) > H.NOALLOC_SCRATCH_BYTES
+    assert L.hawkes_loglik_grad_noalloc(ctypes.byref(big), *args, FAKE, FAKE, FAKE, FAKE, nul) == 2
     # misaligned workspace
     assert L.hawkes_loglik(ctypes.byref(p), *args, ctypes.c_void_p(4096 + 8), 1 << 30, nul) == 2
     # intensity needs an output
