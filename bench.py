@@ -207,23 +207,46 @@ def run_c3(args, dev):
 
 
 def run_c5(args, dev):
-    """c5: M = 4096, 0.2% dense alpha, one decay per target; loglik+grad, then projected Adam steps on
-    the penalised per-event NLL (the paper's lr 0.05, lambda1 0.1, h 0.05 by default) captured in one
-    HIP graph and replayed."""
+    """c5: M = 4096, 0.2% dense alpha at spectral radius 0.85, one decay per target node, N = 5e7
+    events simulated on the GPU (hawkes_simulate, seed 5002); loglik+grad timed, then projected Adam
+    steps on the penalised per-event NLL (the paper's lr 0.05, lambda1 0.1, h 0.05 by default; steps
+    on log mu and log beta) captured in one HIP graph and replayed.  The CPU leg runs the oracle's
+    reverse-mode pass on a prefix and reports the GPU's error there."""
     import numpy as np
     import torch
     import paper_2604_01342_amd as H
     from paper_2604_01342_amd import workloads as W
     n = args.c5_events
+    mu0, al0, be0 = W.c5_params()
+    mu, al, be = (torch.as_tensor(x, device=dev) for x in (mu0, al0, be0))
     t0 = time.time()
-    w = W.cached(f"c5_{n}", lambda: W.make_config(5, n=n))
-    log(f"workload c5: n={w.n} M={w.M} ({time.time() - t0:.1f}s)")
-    d = [torch.as_tensor(x, device=dev) for x in (w.t, w.m, w.mu, w.alpha, w.beta)]
-    wall, per = _timed(lambda: H.loglik_grad(*d, w.T, args.chunk_log2), max(2, args.steps // 4), 1)
-    kern = _kernels(H, lambda: H.loglik_grad(*d, w.T, args.chunk_log2), 2)
+    t, m, T = H.simulate_n(mu, al, be, n, 5002)
+    torch.cuda.synchronize()
+    gen_s = time.time() - t0
+    log(f"workload c5: n={n} M=4096 T={T:.1f}, simulated on the GPU in {gen_s:.1f}s")
+    call = lambda: H.loglik_grad(t, m, mu, al, be, T, args.chunk_log2)
+    call()
+    torch.cuda.synchronize()
+    reps = max(2, args.c5_reps)
+    H.timing_reset()
+    H.timing_enable(True, kernels=[0])
+    wall, per = _timed(call, reps, 0)
+    H.timing_enable(False)
+    kt = H.timing_read()
     log(f"c5 loglik+grad: {wall:.1f} ms per call")
-    opt = H.AdamMLE(*d, w.T, lr=args.c5_lr, chunk_log2=args.chunk_log2, lambda1=args.c5_lambda1, h=args.c5_h,
-                    log_mu=True, log_beta=True)
+    dense_ms, dense_n = kt["dense_dalpha"]
+    roofline = None
+    if dense_n > 0:
+        avg_ms = dense_ms / dense_n
+        flops_per_launch = 2.0 * 4096 * (n * reps / dense_n)
+        achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+        roofline = {"kernel": "pt_dense (per-target dense dL/dalpha)", "bound": "alu",
+                    "achieved": round(achieved, 3), "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                    "avg_launch_ms": round(avg_ms, 4), "launches": dense_n, "flops_per_launch": flops_per_launch}
+    kern = _kernels(H, call, 1)
+    opt = H.AdamMLE(t, m, mu, al, be, T, lr=args.c5_lr, chunk_log2=args.chunk_log2, lambda1=args.c5_lambda1,
+                    h=args.c5_h, log_mu=True, log_beta=True)
     L0 = float(opt.step().item())
     torch.cuda.synchronize()
     opt.capture()
@@ -231,22 +254,91 @@ def run_c5(args, dev):
     g0 = time.perf_counter()
     for k in range(args.c5_adam_steps):
         Ls.append(float(opt.replay().item()))
-        log(f"adam replay {k + 1}/{args.c5_adam_steps}: L = {Ls[-1]:.6f}")
+        if (k + 1) % 10 == 0 or k + 1 == args.c5_adam_steps:
+            log(f"adam replay {k + 1}/{args.c5_adam_steps}: L = {Ls[-1]:.6f}")
     torch.cuda.synchronize()
     adam_ms = (time.perf_counter() - g0) * 1e3 / max(1, args.c5_adam_steps)
     nnz = int((opt.alpha != 0).sum().item())
-    out = {"metric": "events/sec for loglik+grad (c5 shape, per-target decays)", "value": w.n / (wall / 1e3),
-           "unit": "events/s", "n_gpus": 1, "steps": max(2, args.steps // 4), "warmup": 1, "ms_per_step": wall,
+    out = {"metric": "events/sec for loglik+grad (c5: M=4096, per-target decays)", "value": n / (wall / 1e3),
+           "unit": "events/s", "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": wall,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-           "data": "synthetic",
-           "config": {"workload": f"c5 shape: M=4096, 0.2% dense, beta per target, N={w.n} (reduced)",
-                      "n_events": w.n},
+           "data": "synthetic (simulated on the GPU by the branching representation)",
+           "config": {"workload": f"c5: M=4096, alpha 0.2% dense rho=0.85, beta_p~U[0.5,2], N={n}, "
+                                  f"chunks of 2^{args.chunk_log2}", "n_events": n, "simulate_s": round(gen_s, 2)},
+           "roofline": roofline,
            "step_device_time": {"median_ms": per[len(per) // 2], "min_ms": per[0], "max_ms": per[-1]},
            "kernels_ms_per_step": kern,
            "adam": {"graph_replays": args.c5_adam_steps, "lr": args.c5_lr, "lambda1": args.c5_lambda1,
                     "h": args.c5_h, "log_mu_beta": True, "ms_per_step": adam_ms,
-                    "loglik_first": L0,
+                    "events_per_s": n / (adam_ms / 1e3), "loglik_first": L0,
                     "loglik_last": Ls[-1] if Ls else None, "alpha_nonzeros_after": nnz}}
+    if not args.no_cpu:
+        import oracle
+        nc = min(args.c5_cpu_events, n)
+        th, mh = t[:nc].cpu().numpy(), m[:nc].cpu().numpy()
+        Tc = float(th[-1])
+        c0 = time.perf_counter()
+        ref = oracle.adjoint(th, mh, mu0, al0, be0, Tc)
+        c_dt = time.perf_counter() - c0
+        g = H.loglik_grad(t[:nc], m[:nc], mu, al, be, Tc, args.chunk_log2)
+        torch.cuda.synchronize()
+        out["cpu_baseline"] = {"value": nc / c_dt, "unit": "events/s", "cores": 1, "kind": "oracle",
+                               "sample": f"first {nc} events (T = t_{nc}), FP64 reverse-mode pass, {c_dt:.1f} s",
+                               **host_cpu()}
+        out["err_vs_oracle"] = {"loglik": float(f"{abs(g[0].item() - ref[0]) / abs(ref[0]):.3e}"),
+                                "g_mu": float(f"{rel(g[1].cpu().numpy(), ref[1]):.3e}"),
+                                "g_alpha": float(f"{rel(g[2].cpu().numpy(), ref[2]):.3e}"),
+                                "g_beta": float(f"{rel(g[3].cpu().numpy(), ref[3]):.3e}"),
+                                "sample": f"first {nc} events at the generating parameters"}
+        log(f"c5 oracle prefix: {out['err_vs_oracle']}")
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def run_c4_kernels(args, dev):
+    """c4 shape with K decay kernels (the paper's studies use K = 3): M = 1000, N = 1e7 simulated on
+    the GPU; alpha^k 1% dense each, the sum rescaled to spectral radius 0.8, decays (0.1, 1, 10)."""
+    import numpy as np
+    import torch
+    import paper_2604_01342_amd as H
+    from paper_2604_01342_amd import workloads as W
+    K, M, n = args.kernels, 1000, args.c4k_events
+    rp = np.random.Generator(np.random.PCG64(4101))
+    a = [W.random_params(rp, M, 0.01, 0.05, 0.01, 0.8)[1] for _ in range(K)]
+    mu0 = rp.uniform(0.01, 0.05, size=M).astype(np.float32)
+    A = np.stack(a)
+    A *= 0.8 / W.spectral_radius(A.sum(axis=0))
+    al0 = A.astype(np.float32)
+    be0 = np.array([0.1, 1.0, 10.0, 0.3, 3.0, 0.03, 30.0, 0.5][:K], np.float32)
+    mu, al, be = (torch.as_tensor(x, device=dev) for x in (mu0, al0, be0))
+    t0 = time.time()
+    t, m, T = H.simulate_n(mu, al, be, n, 4102)
+    torch.cuda.synchronize()
+    log(f"workload c4 with K={K}: n={n} M={M} T={T:.1f}, simulated in {time.time() - t0:.1f}s")
+    call = lambda: H.loglik_grad(t, m, mu, al, be, T, args.chunk_log2)
+    wall, per = _timed(call, args.steps, args.warmup)
+    kern = _kernels(H, call, 2)
+    out = {"metric": f"events/sec for loglik+grad (c4 shape, K={K} decay kernels)", "value": n / (wall / 1e3),
+           "unit": "events/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (simulated on the GPU)",
+           "config": {"workload": f"c4 shape, K={K}: M=1000, alpha^k 1% dense, rho(sum)=0.8, "
+                                  f"beta={be0.tolist()}, N={n}", "n_events": n, "kernels": K},
+           "step_device_time": {"median_ms": per[len(per) // 2], "min_ms": per[0], "max_ms": per[-1]},
+           "kernels_ms_per_step": kern}
+    if not args.no_cpu:
+        import oracle
+        nc = min(200_000, n)
+        th, mh = t[:nc].cpu().numpy(), m[:nc].cpu().numpy()
+        Tc = float(th[-1])
+        ref = oracle.forward(th, mh, mu0, al0, be0, Tc)
+        g = H.loglik_grad(t[:nc], m[:nc], mu, al, be, Tc, args.chunk_log2)
+        torch.cuda.synchronize()
+        out["err_vs_oracle"] = {"loglik": float(f"{abs(g[0].item() - ref[0]) / abs(ref[0]):.3e}"),
+                                "g_mu": float(f"{rel(g[1].cpu().numpy(), ref[1]):.3e}"),
+                                "g_alpha": float(f"{rel(g[2].cpu().numpy(), ref[2]):.3e}"),
+                                "g_beta": float(f"{rel(g[3].cpu().numpy(), ref[3]):.3e}"),
+                                "sample": f"first {nc} events at the generating parameters"}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -329,11 +421,16 @@ def main() -> int:
                     help="dense_cols,dense_ranges,item_log2 to use as given (no autotuning), e.g. 256,16,0")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (HBM counter calibration)")
-    ap.add_argument("--workload", choices=["c4", "c2", "c3", "c5", "recovery"], default="c4",
-                    help="c4 (default) is the headline metric; c2, c3 and c5 print their own line")
-    ap.add_argument("--c5-events", type=int, default=1 << 21,
-                    help="events of the c5 sequence (generated at that length)")
-    ap.add_argument("--c5-adam-steps", type=int, default=10, help="graph replays of the c5 Adam step")
+    ap.add_argument("--workload", choices=["c4", "c2", "c3", "c5", "c4k", "recovery"], default="c4",
+                    help="c4 (default) is the headline metric; c2, c3, c5 and c4k (c4 shape with --kernels "
+                         "decay kernels) print their own line")
+    ap.add_argument("--c5-events", type=int, default=50_000_000,
+                    help="events of the c5 sequence (simulated on the GPU at that length)")
+    ap.add_argument("--c5-reps", type=int, default=3, help="timed loglik+grad calls at c5")
+    ap.add_argument("--c5-cpu-events", type=int, default=20_000, help="prefix for the c5 oracle leg")
+    ap.add_argument("--c5-adam-steps", type=int, default=50, help="graph replays of the c5 Adam step")
+    ap.add_argument("--kernels", type=int, default=3, help="decay kernels of --workload c4k")
+    ap.add_argument("--c4k-events", type=int, default=10_000_000, help="events of --workload c4k")
     ap.add_argument("--c5-lr", type=float, default=0.05,
                     help="Adam step size for c5 (every one of the 4096^2 alpha entries moves by about lr per "
                          "step; without the sparsity penalty 0.05 drives the process explosive within a few steps)")
@@ -382,6 +479,8 @@ def main() -> int:
         return run_c3(args, dev)
     if args.workload == "c5":
         return run_c5(args, dev)
+    if args.workload == "c4k":
+        return run_c4_kernels(args, dev)
     if args.workload == "recovery":
         return run_recovery(args, dev)
 
