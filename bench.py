@@ -78,8 +78,8 @@ def _autotune(args, tune):
     launch tuning in effect; --no-autotune keeps the library's rules."""
     import paper_2604_01342_amd as H
     if args.tuning:
-        cols, ranges, item = (int(x) for x in args.tuning.split(","))
-        H.set_tuning(dense_cols=cols, dense_ranges=ranges, item_log2=item)
+        v = [int(x) for x in args.tuning.split(",")] + [0]
+        H.set_tuning(dense_cols=v[0], dense_ranges=v[1], item_log2=v[2], dense_rows=v[3])
     elif args.no_autotune:
         H.set_tuning()
     else:
@@ -418,7 +418,7 @@ def main() -> int:
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's own launch rules instead of timing the tuning candidates first")
     ap.add_argument("--tuning", default="",
-                    help="dense_cols,dense_ranges,item_log2 to use as given (no autotuning), e.g. 256,16,0")
+                    help="dense_cols,dense_ranges,item_log2[,dense_rows] to use as given (no autotuning), e.g. 256,16,0,32")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (HBM counter calibration)")
     ap.add_argument("--workload", choices=["c4", "c2", "c3", "c5", "c4k", "recovery"], default="c4",

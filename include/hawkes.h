@@ -123,12 +123,17 @@ typedef struct hawkes_problem {
  *   item_log2     small-M engine: log2 of the events per lane item, 4..16; a
  *                 value too small for the engine's bound on the item count
  *                 (and so on its workspace) is raised to the smallest that
- *                 fits */
+ *                 fits
+ *   dense_rows    the dense dL/dalpha kernel's tile height: 16 (float64
+ *                 register accumulators) or 32 (float32 register
+ *                 accumulators added to a float64 tile every few windows);
+ *                 32 applies only with 256-column tiles and 128-record
+ *                 windows (M > 128, chunk_log2 <= 24) */
 typedef struct hawkes_tuning {
     int32_t dense_cols;
     int32_t dense_ranges;
     int32_t item_log2;
-    int32_t reserved;   /* must be 0 */
+    int32_t dense_rows;
 } hawkes_tuning;
 
 /* Replace the process-wide tuning (NULL: all zero, the library's rules).

@@ -50,7 +50,7 @@ class _Problem(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("dense_cols", ctypes.c_int32), ("dense_ranges", ctypes.c_int32), ("item_log2", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("dense_rows", ctypes.c_int32)]
 
 
 class _Adam(ctypes.Structure):
@@ -192,11 +192,12 @@ def _gshape(mu, alpha):
     return (M, M) if K == 1 else (K, M, M)
 
 
-def set_tuning(dense_cols: int = 0, dense_ranges: int = 0, item_log2: int = 0) -> None:
+def set_tuning(dense_cols: int = 0, dense_ranges: int = 0, item_log2: int = 0, dense_rows: int = 0) -> None:
     """Process-wide launch tuning (hawkes_set_tuning): 0 keeps the library's
     rule.  dense_cols in {64, 128, 256}, dense_ranges a power of two up to
-    4096, item_log2 in 4..16.  Results agree to rounding whatever the values."""
-    t = _Tuning(int(dense_cols), int(dense_ranges), int(item_log2), 0)
+    4096, item_log2 in 4..16, dense_rows in {16, 32}.  Results agree to
+    rounding whatever the values."""
+    t = _Tuning(int(dense_cols), int(dense_ranges), int(item_log2), int(dense_rows))
     _check("hawkes_set_tuning", lib().hawkes_set_tuning(ctypes.byref(t)))
 
 
@@ -204,7 +205,8 @@ def get_tuning() -> dict:
     """The current process-wide launch tuning (hawkes_get_tuning)."""
     t = _Tuning()
     _check("hawkes_get_tuning", lib().hawkes_get_tuning(ctypes.byref(t)))
-    return {"dense_cols": t.dense_cols, "dense_ranges": t.dense_ranges, "item_log2": t.item_log2}
+    return {"dense_cols": t.dense_cols, "dense_ranges": t.dense_ranges, "item_log2": t.item_log2,
+            "dense_rows": t.dense_rows}
 
 
 def workspace_bytes(n: int, M: int, per_target: bool = False, grad: bool = True, chunk_log2: int = 0,

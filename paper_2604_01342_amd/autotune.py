@@ -9,8 +9,9 @@ candidate is at least 1% faster), applies it with
 class, so that later processes skip the timing.
 
 Knobs (see include/hawkes.h):
-  dense_cols, dense_ranges   the shared-decay large-M engine (M > 8): tile width
-                             of the dense dL/dalpha kernel and its event ranges
+  dense_cols, dense_ranges,  the shared-decay large-M engine (M > 8): tile width
+  dense_rows                 and height of the dense dL/dalpha kernel and its
+                             event ranges
   item_log2                  the small-M engine (M <= 8, single or batched):
                              events per lane item
 
@@ -69,7 +70,11 @@ def candidates_single(n: int, M: int, per_target: bool, chunk_log2: int) -> list
     if M <= 8:
         return [{"item_log2": k} for k in range(4, 11)]
     cols = [c for c in (64, 128, 256) if c <= max(64, 2 * M) and (c < 128 or lg <= (25 if c == 128 else 24))]
-    return [{"dense_cols": c, "dense_ranges": r} for c in cols for r in (4, 8, 16, 32, 64)]
+    out = [{"dense_cols": c, "dense_ranges": r} for c in cols for r in (4, 8, 16, 32, 64)]
+    if 256 in cols and M > 128:
+        # 32-row tiles (float32 register accumulators) exist for 256 columns
+        out += [{"dense_cols": 256, "dense_ranges": r, "dense_rows": h} for r in (8, 16, 32) for h in (16, 32)]
+    return out
 
 
 def candidates_batched(n_total: int) -> list[dict]:
@@ -156,7 +161,7 @@ def _search(key: str, cands: Iterable[dict], run: Callable[[], tuple], reps: int
     if ms > base_ms * (1.0 - MARGIN):
         ms, best = base_ms, {}
     out = {"tuning": {"dense_cols": best.get("dense_cols", 0), "dense_ranges": best.get("dense_ranges", 0),
-                      "item_log2": best.get("item_log2", 0)},
+                      "item_log2": best.get("item_log2", 0), "dense_rows": best.get("dense_rows", 0)},
            "ms": ms, "default_ms": base_ms}
     set_tuning(**out["tuning"])
     if use_cache:

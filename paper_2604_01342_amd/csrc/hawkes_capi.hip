@@ -153,7 +153,8 @@ hawkes_status hawkes_set_tuning(const hawkes_tuning* t) {
         const bool er_ok = v.dense_ranges == 0 ||
                            (v.dense_ranges >= 1 && v.dense_ranges <= 4096 && (v.dense_ranges & (v.dense_ranges - 1)) == 0);
         const bool item_ok = v.item_log2 == 0 || (v.item_log2 >= 4 && v.item_log2 <= 16);
-        if (!cols_ok || !er_ok || !item_ok || v.reserved != 0) return HAWKES_EINVAL;
+        const bool rows_ok = v.dense_rows == 0 || v.dense_rows == 16 || v.dense_rows == 32;
+        if (!cols_ok || !er_ok || !item_ok || !rows_ok) return HAWKES_EINVAL;
     }
     std::lock_guard<std::mutex> g(g_tuning_mu);
     g_tuning = v;

@@ -59,11 +59,13 @@ namespace hk {
 // the next slot of the column block's walk (-1: none), the run, whether the
 // window is wide, beta (last record - anchor) > HK_WIDE, and the event index
 // of its 65th record (INT_MAX if none)); the window's 64 NGW record times;
-// its 64 NGW record keys (u32, two per word; past the records: 0xffffffff
-// in the first 64, anything in a second 64, which the count excludes); then
-// the records' factors e^{beta (t_j - tau)} against the window's anchor
-// (float32, two per word, 0 past the records in the first 64), formed once
-// here instead of once per row block.  The slot after a run's last window
+// its 64 NGW record keys (u32, two per word; in a written group of 64 the
+// lanes past the records hold 0xffffffff; a second group is written only
+// when the window has more than 64 records); then the records' factors
+// e^{beta (t_j - tau)} against the window's anchor (float32, two per word,
+// 0 past the records), formed once here instead of once per row block.
+// Within each group of 64 the records are permuted over the lanes by LDS
+// bank (dense_ck), so validity is read from the key, not the lane.  The slot after a run's last window
 // has state and header only (count 0; its window runs to the run's end).
 template <int CPL, int NGW>
 struct Slot {
@@ -212,10 +214,32 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
             put_hdr(w, tn, (int32_t)((uint32_t)rl_i((int)q.key, nv - 1) >> SH), half + nv, slot0 + w + 1,
                     half != 0 ? (int32_t)((uint32_t)rl_i((int)q.key, 0) >> SH) : 0x7fffffff);
         double* out = kck + (int64_t)(slot0 + w) * S::SIZE;
-        out[S::T + half + lane] = v ? q.t : 0.0;
-        reinterpret_cast<uint32_t*>(out + S::KEY)[half + lane] = q.key;
+        // The record's lane in the slot.  The dense kernel adds each own
+        // event's pair terms with one LDS atomic over a group's 64 records,
+        // at the records' columns of one tile row; the LDS serves 16 lanes
+        // of 8-byte words a cycle from 16 banks (column mod 16), so records
+        // sharing a bank in one quarter-wave serialise.  Records sorted by
+        // bank (past the records: last) and dealt round-robin over the four
+        // quarter-waves share a bank in a quarter only when more than four
+        // have it.  Nothing else depends on the order (each lane carries its
+        // record's index, column, time and factor).
+        int pos;
+        {
+            const int bank = v ? (int)(q.key & 15u) : 16;
+            const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+            int before = 0, rank = 0;
+            for (int bv = 0; bv <= 16; ++bv) {
+                const uint64_t mb = __ballot(bank == bv);
+                before += bv < bank ? __builtin_popcountll(mb) : 0;
+                if (bv == bank) rank = __builtin_popcountll(mb & below);
+            }
+            const int sidx = before + rank;   // a permutation of 0..63
+            pos = (sidx & 3) * 16 + (sidx >> 2);
+        }
+        out[S::T + half + pos] = v ? q.t : 0.0;
+        reinterpret_cast<uint32_t*>(out + S::KEY)[half + pos] = q.key;
         // the record's factor e^{beta (t_j - tau_w)} against the window's anchor
-        reinterpret_cast<float*>(out + S::BJ)[half + lane] = v ? exp2_f64arg((q.t - tau_w) * bl2) : 0.0f;
+        reinterpret_cast<float*>(out + S::BJ)[half + pos] = v ? exp2_f64arg((q.t - tau_w) * bl2) : 0.0f;
         const double f = (double)exp2_f64arg((tau - tn) * bl2);
 #pragma unroll
         for (int j = 0; j < CPL; ++j) K[j] *= f;
@@ -517,7 +541,9 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
         const int nv = hc.nv;
         const int hi = hc.hi;
         const double tw = hc.tau;
-        const bool cv0 = lane < nv, cv1 = NGW == 2 && lane + 64 < nv;
+        // records are permuted within their group: valid lanes by key
+        const bool cv0 = nv > 0 && cur.ckey[0] != 0xffffffffu;
+        const bool cv1 = NGW == 2 && nv > 64 && cur.ckey[NGW - 1] != 0xffffffffu;
         const int cidx0 = cv0 ? (int)(cur.ckey[0] >> SH) : 0x7fffffff;
         const int cidx1 = cv1 ? (int)(cur.ckey[NGW - 1] >> SH) : 0x7fffffff;
         const int colj0 = (int)(cur.ckey[0] & (uint32_t)(W - 1));
@@ -599,6 +625,307 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
     }
 }
 
+// The same dense dL/dalpha for tiles of 32 rows (or more) at large M: the
+// rank-1 part of each window (u K_g^T) is accumulated in float32 registers
+// and added to the workgroup's float64 LDS tile every HK_FLUSH windows that
+// had own events, and at the end; the tile also takes the pair terms and
+// starts from the event range's float64 partials.  Twice the rows per tile
+// halve the window visits per event (the per-window loads, header and
+// bookkeeping) at the same register count; NWV waves share the tile.
+// float32 partial sums over at most HK_FLUSH windows, float64 beyond (the
+// float32 state of the precision plan, float64 reductions).
+#ifndef HK_FLUSH
+#define HK_FLUSH 16
+#endif
+template <int CPL, int DRB, int NGW, int NWV>
+__global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(2))) void large_dense_f(int32_t M, int32_t NBC, int32_t NBR, int32_t ER, int32_t rpr,
+                                                  int32_t nrun, int32_t ckr, int32_t nseg, int32_t nrec,
+                                                  int32_t nslot, const float* __restrict__ beta,
+                                                  const int4* __restrict__ runinfo,
+                                                  const int32_t* __restrict__ bo_off,
+                                                  const int32_t* __restrict__ bo_base,
+                                                  const uint32_t* __restrict__ bo_key,
+                                                  const double* __restrict__ bo_t, const float* __restrict__ bo_w,
+                                                  const double* __restrict__ kck, double* __restrict__ gpart) {
+    using S = Slot<CPL, NGW>;
+    constexpr int W = S::W;
+    constexpr int DR = 1 << DRB;
+    constexpr int SH = CPL == 4 ? 8 : CPL == 2 ? 7 : 6;   // bits of the local mark in a column record key
+    extern __shared__ double GP[];            // [DR * W] float64 tile, shared by the group's waves
+    __shared__ __align__(16) float ULs[NWV][DR];   // per wave: the window's u
+    __shared__ double2 ODs[NWV][66];          // per wave: own events of a pass (+2 read ahead)
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+    float* UL = ULs[wv];
+    double2* OD = ODs[wv];
+    const int32_t blk = blockIdx.x;
+    const int32_t nbb = NBR * NBC;
+    int32_t er, local;
+    if (ER >= 8) {
+        // blocks of one event range on one XCD (blockIdx % 8)
+        const int32_t slot = blk >> 3;
+        er = (slot / nbb) * 8 + (blk & 7);
+        local = slot % nbb;
+    } else {
+        // 8 / ER XCDs share one event range
+        const int32_t per = 8 / ER, x = blk & 7;
+        er = x / per;
+        local = (blk >> 3) * per + x % per;
+        if (local >= nbb) return;
+    }
+    if (er >= ER) return;
+    const int32_t nrun_c = (nseg + ckr - 1) / ckr;
+    const int32_t gA = er * rpr;
+    if (gA >= nrun_c) return;
+    const int32_t gB = gA + rpr < nrun_c ? gA + rpr : nrun_c;
+    // this wave's share of the range's runs (possibly none)
+    const int32_t rA = gA + (wv * (gB - gA)) / NWV;
+    const int32_t rB = gA + ((wv + 1) * (gB - gA)) / NWV;
+    const int32_t sb = local % NBC;
+    const int32_t rb = local / NBC;
+    const int32_t r0 = rb * DR, s0 = sb * W;
+    double* gp = gpart + (int64_t)er * M * M;
+    // the tile starts from the event range's partials so far (coalesced:
+    // a row of W columns per 64 NWV threads), zero outside the matrix
+    for (int x = threadIdx.x; x < DR * W; x += 64 * NWV) {
+        const int32_t row = r0 + x / W, col = s0 + x % W;
+        GP[x] = row < M && col < M ? gp[(int64_t)row * M + col] : 0.0;
+    }
+    // the rank-1 part in float32 registers (row i, column s0 + 64 j + lane)
+    float Gm[DR][CPL];
+#pragma unroll
+    for (int i = 0; i < DR; ++i)
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) Gm[i][j] = 0.0f;
+    int nacc = 0;   // windows added to Gm since its last flush
+    auto flush = [&]() {
+#pragma unroll
+        for (int i = 0; i < DR; ++i)
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) {
+                atomicAdd(&GP[i * W + j * 64 + lane], (double)Gm[i][j]);
+                Gm[i][j] = 0.0f;
+            }
+    };
+    if (lane < DR) UL[lane] = 0.0f;
+    const double bet = (double)beta[0];
+    const double bl2 = bet * HK_LOG2E;   // decays as powers of 2
+    const __amdgpu_buffer_rsrc_t rK = buf(kck, (uint32_t)nslot * S::SIZE * 8u);
+    const __amdgpu_buffer_rsrc_t rOk = buf(bo_key, (uint32_t)nrec * 4u);
+    const __amdgpu_buffer_rsrc_t rOt = buf(bo_t, (uint32_t)nrec * 8u);
+    const __amdgpu_buffer_rsrc_t rOw = buf(bo_w, (uint32_t)nrec * 4u);
+    const int4* rinf = runinfo + (int64_t)sb * nrun;
+    // own stream: records [Q0, Q1) of row block rb, q the next unconsumed
+    // one.  o0 holds records [qL, qL + 64).  Every window refills o2 from q
+    // and first moves the previous window's o2 to o1, so o1 (from q1s) is
+    // always one window old: when o0 runs out, o1 usually covers q.
+    const int32_t sA = rA * ckr, sB = rB * ckr < nseg ? rB * ckr : nseg;
+    const int32_t Q0 = bo_base[rb] + bo_off[(int64_t)rb * (nseg + 1) + sA];
+    const int32_t Q1 = bo_base[rb] + bo_off[(int64_t)rb * (nseg + 1) + sB];
+    auto own_load = [&](OwnBatch& o, int32_t from) {
+        const uint32_t e = (uint32_t)(from + lane);
+        o.key = ld_u32(rOk, e);
+        o.t = ld_f64(rOt, e);
+        o.w = ld_f32(rOw, e);
+    };
+    int32_t q = Q0, qL = Q0, q1s = Q0, q2s = Q0;
+    OwnBatch o0, o1, o2;
+    own_load(o0, Q0);
+    own_load(o2, Q0);
+    auto load_win = [&](Win<CPL, NGW>& w, int32_t slot) {
+        const uint32_t sl = (uint32_t)slot * S::SIZE;
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) w.K[j] = ld_f64(rK, sl + j * 64 + lane);
+#pragma unroll
+        for (int h = 0; h < NGW; ++h) {
+            w.bj[h] = ld_f32(rK, 2 * (sl + S::BJ) + 64 * h + lane);
+            w.ckey[h] = ld_u32(rK, 2 * (sl + S::KEY) + 64 * h + lane);
+        }
+    };
+    auto load_hdr = [&](int32_t slot) -> Hdr {
+        const double* hp = kck + (int64_t)slot * S::SIZE + S::TAU;
+        const int32_t* hq = reinterpret_cast<const int32_t*>(hp + 2);
+        Hdr h;
+        h.tau = hp[0];
+        h.hi = hq[0];
+        h.nv = hq[1];
+        h.next = hq[2];
+        h.run = hq[3];
+        h.wide = hq[4];
+        h.first1 = hq[5];
+        return h;
+    };
+
+    int32_t sc = 0;   // the current window's slot
+    Hdr hc;           // and its header
+    // own records of the window in o0 from lane p on (index <= hi): adds
+    // their c_k to u and their pair terms to GP; returns how many there were
+    auto pass = [&](const Win<CPL, NGW>& w, int p, double tw, int hi, bool cv0, bool cv1, int cidx0, int cidx1,
+                    int colj0, int colj1, double bj0, double bj1) -> int {
+        const OwnBatch& b = o0;
+        const bool own = qL + lane < Q1 && lane >= p && (int)(b.key >> DRB) <= hi;
+        const int nsel = __builtin_popcountll(__ballot(own));
+        if (nsel == 0) return 0;
+        const int kend = p + nsel;   // own lanes are [p, kend)
+        // windows with column records: the header's flag; after a run's last
+        // group: from the last selected own event
+        bool narrow;
+        if (hc.nv > 0) {
+            narrow = hc.wide == 0;
+        } else {
+            const double tlo = rl_d(b.t, kend - 1);
+            narrow = bet * (tlo - tw) <= HK_WIDE;
+        }
+        const int rowl = (int)(b.key & (DR - 1));
+        if (narrow) {
+            const float cf = own ? (float)(bet * (double)b.w) * exp2_f64arg((tw - b.t) * bl2) : 0.0f;
+            if (own) {
+                atomicAdd(&UL[rowl], cf);
+                // (row offset, index, c_k) of this own event for the pair
+                // loop, read back by every lane (broadcast)
+                OD[lane] = make_double2(__hiloint2double(rowl * W, (int)(b.key >> DRB)), (double)cf);
+            }
+            // pair terms: own event k adds c_k b_j at (row_k, m_j) for the
+            // window's records j before it (zero elsewhere)
+            auto pair = [&](const double2 od) {
+                const int rofs = __double2hiint(od.x), ik = __double2loint(od.x);
+                atomicAdd(&GP[rofs + colj0], cidx0 < ik ? od.y * bj0 : 0.0);
+                // the window's second 64 records only for an own event after
+                // the first of them
+                if (NGW == 2 && __builtin_amdgcn_readfirstlane(ik) > hc.first1)
+                    atomicAdd(&GP[rofs + colj1], cidx1 < ik ? od.y * bj1 : 0.0);
+            };
+            // two at a time, the next two entries read before this pair's
+            // atomics (entries past kend are read but not used)
+            double2 d1 = OD[p], d2 = OD[p + 1];
+            for (int k = p; k < kend; k += 2) {
+                const double2 n1 = OD[k + 2], n2 = OD[k + 3];
+                pair(d1);
+                if (k + 1 < kend) pair(d2);
+                d1 = n1;
+                d2 = n2;
+            }
+        } else {
+            // wide window (anchored factors would leave float32 range):
+            // c_k decayed from the window's anchor (below float32 range it
+            // is zero, and so is its product with the state), exact
+            // per-pair decays
+            const double cw = bet * (double)b.w;
+            if (own) atomicAdd(&UL[rowl], (float)(cw * (double)exp2_f64arg((tw - b.t) * bl2)));
+            // the records' times, waited for here so that no load of this
+            // rare path stays in flight
+            const double ct0 = ld_f64(rK, (uint32_t)sc * S::SIZE + S::T + lane);
+            const double ct1 = NGW == 2 ? ld_f64(rK, (uint32_t)sc * S::SIZE + S::T + 64 + lane) : 0.0;
+            __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+            for (int k = p; k < kend; ++k) {
+                const uint32_t key = (uint32_t)rl_i((int)b.key, k);
+                const int rofs = (int)(key & (DR - 1)) * W;
+                const double tk = rl_d(b.t, k);
+                const double ck = rl_d(cw, k);
+                if (cv0 && cidx0 < (int)(key >> DRB))
+                    atomicAdd(&GP[rofs + colj0], ck * (double)exp2_f64arg((ct0 - tk) * bl2));
+                if (NGW == 2 && cv1 && cidx1 < (int)(key >> DRB))
+                    atomicAdd(&GP[rofs + colj1], ck * (double)exp2_f64arg((ct1 - tk) * bl2));
+            }
+        }
+        return nsel;
+    };
+
+    // the current window: slot sc with header hc; each window loads the next
+    // one's data and header first (the same window again after the wave's
+    // last one, so that every window issues the same loads)
+    auto body = [&](Win<CPL, NGW>& cur, Win<CPL, NGW>& nxt) -> bool {
+        const bool last = hc.nv == 0 && hc.run >= rB - 1;
+        const int32_t sn = last ? sc : hc.next;
+        load_win(nxt, sn);
+        const Hdr hn = load_hdr(sn);
+        o1 = o2;
+        q1s = q2s;
+        own_load(o2, q);
+        q2s = q;
+
+        const int nv = hc.nv;
+        const int hi = hc.hi;
+        const double tw = hc.tau;
+        // records are permuted within their group: valid lanes by key
+        const bool cv0 = nv > 0 && cur.ckey[0] != 0xffffffffu;
+        const bool cv1 = NGW == 2 && nv > 64 && cur.ckey[NGW - 1] != 0xffffffffu;
+        const int cidx0 = cv0 ? (int)(cur.ckey[0] >> SH) : 0x7fffffff;
+        const int cidx1 = cv1 ? (int)(cur.ckey[NGW - 1] >> SH) : 0x7fffffff;
+        const int colj0 = (int)(cur.ckey[0] & (uint32_t)(W - 1));
+        const int colj1 = (int)(cur.ckey[NGW - 1] & (uint32_t)(W - 1));
+        const double bj0 = (double)cur.bj[0], bj1 = (double)cur.bj[NGW - 1];
+        int nown = 0;
+        for (;;) {
+            if (q - qL == 64) {
+                // o0 used up: continue in o1, which covers q unless more than
+                // 64 records went by in two windows (q >= q1s always); then
+                // load o1 now and wait for it here, so that the other path
+                // sees no load in flight
+                if (q >= q1s + 64) {
+                    own_load(o1, q);
+                    q1s = q;
+                    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+                }
+                o0 = o1;
+                qL = q1s;
+            }
+            const int n = pass(cur, q - qL, tw, hi, cv0, cv1, cidx0, cidx1, colj0, colj1, bj0, bj1);
+            q += n;
+            nown += n;
+            if (n == 0 || q - qL < 64) break;
+        }
+        if (nown) {
+            // rank-1 update G += u K_g^T in float32, then clear u (u is this
+            // wave's: its LDS operations complete in order, so only the
+            // compiler must not move them)
+            __builtin_amdgcn_wave_barrier();
+            float kf[CPL];
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) kf[j] = (float)cur.K[j];
+#pragma unroll
+            for (int i4 = 0; i4 < DR / 4; ++i4) {
+                const float4 u4 = reinterpret_cast<const float4*>(UL)[i4];
+                const float uu[4] = {u4.x, u4.y, u4.z, u4.w};
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int j = 0; j < CPL; ++j) Gm[4 * i4 + r][j] = __builtin_fmaf(uu[r], kf[j], Gm[4 * i4 + r][j]);
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (lane < DR) UL[lane] = 0.0f;
+            __builtin_amdgcn_wave_barrier();
+            if (++nacc == HK_FLUSH) {
+                flush();
+                nacc = 0;
+            }
+        }
+        sc = sn;
+        hc = hn;
+        return !last;
+    };
+
+    __syncthreads();
+    if (rA < rB) {
+        sc = rinf[rA].x;   // the first slot of the wave's first run
+        hc = load_hdr(sc);
+        Win<CPL, NGW> wa, wb;
+        load_win(wa, sc);
+        for (;;) {
+            if (!body(wa, wb)) break;
+            if (!body(wb, wa)) break;
+        }
+    }
+    // every wave adds what its registers hold to the tile, which then goes
+    // back to the event range's partials
+    if (nacc) flush();
+    __syncthreads();
+    for (int x = threadIdx.x; x < DR * W; x += 64 * NWV) {
+        const int32_t row = r0 + x / W, col = s0 + x % W;
+        if (row < M && col < M) gp[(int64_t)row * M + col] = GP[x];
+    }
+}
+
 template <int CPL, int DRB, int NGW>
 static void dense_launch_t(LargeArgs& A, int64_t c0, int32_t nev, int32_t nseg, int32_t nrun_c, hipStream_t st,
                            bool ck_only) {
@@ -615,9 +942,24 @@ static void dense_launch_t(LargeArgs& A, int64_t c0, int32_t nev, int32_t nseg, 
     const int32_t nbb = A.NBR * A.NBC;
     const unsigned nblk = A.ER >= 8 ? (unsigned)(nbb * ((A.ER + 7) / 8) * 8)
                                     : (unsigned)(((nbb + 8 / A.ER - 1) / (8 / A.ER)) * 8);
-    hipLaunchKernelGGL((large_dense<CPL, DRB, NGW>), dim3(nblk), dim3(64 * HK_DW), 0, st, A.M, A.NBC, A.NBR, A.ER, rpr,
-                       A.NRUN, A.CKR, nseg, nev, (int32_t)A.nslot, A.beta, A.runinfo, A.bo_off, A.bo_base, A.bo_key,
-                       A.bo_t, A.bo_w, A.kck, A.gpart);
+    if constexpr (DRB >= 5) {
+        hipLaunchKernelGGL((large_dense_f<CPL, DRB, NGW, HK_DWF>), dim3(nblk), dim3(64 * HK_DWF),
+                           (size_t)(1 << DRB) * 64 * CPL * sizeof(double), st, A.M, A.NBC, A.NBR, A.ER, rpr, A.NRUN,
+                           A.CKR, nseg, nev, (int32_t)A.nslot, A.beta, A.runinfo, A.bo_off, A.bo_base, A.bo_key,
+                           A.bo_t, A.bo_w, A.kck, A.gpart);
+    } else {
+        hipLaunchKernelGGL((large_dense<CPL, DRB, NGW>), dim3(nblk), dim3(64 * HK_DW), 0, st, A.M, A.NBC, A.NBR, A.ER,
+                           rpr, A.NRUN, A.CKR, nseg, nev, (int32_t)A.nslot, A.beta, A.runinfo, A.bo_off, A.bo_base,
+                           A.bo_key, A.bo_t, A.bo_w, A.kck, A.gpart);
+    }
+}
+
+// dynamic LDS of the float32-accumulator dense kernel (its float64 tile):
+// granted once per kernel and device above 64 KiB
+hawkes_status dense_allow_lds(const LargeArgs& A) {
+    if (A.DRB < 5) return HAWKES_OK;
+    const size_t bytes = (size_t)(1 << A.DRB) * 64 * A.CPL * sizeof(double);
+    return allow_lds((const void*)large_dense_f<4, 5, 2, HK_DWF>, bytes, true);
 }
 
 void large_dense_launch(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, hipStream_t st, bool ck_only) {
@@ -625,7 +967,10 @@ void large_dense_launch(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, hipS
     const int32_t nev = (int32_t)(c1 - c0);
     // the tiles the layout selects: 16 x 256, 16 x 128, 16 x 64
     // and the window length the layout selects (A.NGW groups of 64 records)
-    if (A.NGW == 2) {
+    if (A.DRB == 5) {
+        // the layout selects 32-row tiles only with 256 columns and 128-record windows
+        dense_launch_t<4, 5, 2>(A, c0, nev, nseg, nrun_c, st, ck_only);
+    } else if (A.NGW == 2) {
         if (A.CPL == 4)
             dense_launch_t<4, 4, 2>(A, c0, nev, nseg, nrun_c, st, ck_only);
         else if (A.CPL == 2)

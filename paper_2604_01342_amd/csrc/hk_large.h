@@ -19,6 +19,10 @@
 #define HK_CKR 4           // segments per checkpoint run of the shared-decay dense gradient
 #endif
 #define HK_WIDE 60.0       // anchored-exponent limit inside one window of the dense kernel
+#define HK_DWF 4           // waves per workgroup of the float32-accumulator dense kernel (32-row tiles)
+#ifndef HK_F32_MIN_M
+#define HK_F32_MIN_M 384   // nodes from which the 32-row float32-accumulator tiles are the rule
+#endif
 // float64 words of a dense-gradient checkpoint slot: state, header, and
 // per record (64 NGW of them) its time, key and factor
 #define HK_SLOT_WORDS(CPL, NGW) (64 * (CPL) + 8 + 128 * (NGW))
@@ -118,7 +122,9 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st);
 hawkes_status run_large_pt(LargeArgs& A, hipStream_t st);
 // helpers shared by the two large-M paths (host side)
 size_t lds_limit();
-hawkes_status allow_lds(const void* kernel, size_t bytes);
+hawkes_status allow_lds(const void* kernel, size_t bytes, bool with_static = false);
+// grants the float32-accumulator dense kernel its LDS tile (when the layout selects it)
+hawkes_status dense_allow_lds(const LargeArgs& A);
 void large_build_index(int32_t M, const float* alpha, int trans, int32_t* ptr, int32_t* idx, float* val,
                        hipStream_t st);
 void large_scan(LargeArgs& A, int32_t nseg, const float* beta_pt, hipStream_t st);

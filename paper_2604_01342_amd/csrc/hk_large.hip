@@ -821,6 +821,13 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
         const int Wc = 64 * A.CPL;
         A.NGW = !A.per_target && 1024 / (Wc > A.M ? Wc : A.M) < 8 ? 2 : 1;
     }
+    // 32-row tiles with float32 register accumulators (large_dense_f) for the
+    // widest tiles at large M: half the window visits per event; the tuning
+    // (dense_rows) can select either where the tiles are 256 x 128-record
+    if (!A.per_target && A.CPL == 4 && A.NGW == 2) {
+        if (tu.dense_rows == 32 || (tu.dense_rows == 0 && A.M >= HK_F32_MIN_M)) A.DRB = 5;
+    }
+    const int nwv = A.DRB == 5 ? HK_DWF : HK_DW;   // waves per dense workgroup
     A.NBR = A.per_target ? A.NB : (A.M + (1 << A.DRB) - 1) >> A.DRB;
     A.NBC = A.per_target ? A.NB : (A.M + 64 * A.CPL - 1) / (64 * A.CPL);
     // event ranges per chunk for the dense kernel: a power of two so that the
@@ -837,11 +844,11 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
     if (!A.per_target && tu.dense_ranges > 0) er = tu.dense_ranges;   // a knob of the shared-decay kernel only
     while (er > A.nseg && er > 1) er >>= 1;
     // shared decay: every wave of a dense workgroup gets at least one run
-    while (!A.per_target && er > 1 && A.nseg / er < HK_DW) er >>= 1;
+    while (!A.per_target && er > 1 && A.nseg / er < nwv) er >>= 1;
     A.ER = er;
-    // checkpoint runs: whole runs per event range, HK_DW or more per range
+    // checkpoint runs: whole runs per event range, nwv or more per range
     // (nseg and ER are powers of two)
-    A.CKR = A.nseg / (er * HK_DW);
+    A.CKR = A.nseg / (er * nwv);
     if (A.CKR > HK_CKR) A.CKR = HK_CKR;
     if (A.CKR < 1) A.CKR = 1;
     A.NRUN = A.nseg / A.CKR;
@@ -942,10 +949,12 @@ size_t lds_limit() {
 // (including ones under stream capture) only look the pair up.  A refusal
 // clears the runtime's last-error state, so that it does not surface at an
 // unrelated later call.
-hawkes_status allow_lds(const void* kernel, size_t bytes) {
+hawkes_status allow_lds(const void* kernel, size_t bytes, bool with_static) {
     const size_t lim = lds_limit();
     if (bytes > lim) return HAWKES_EUNSUPPORTED;
-    if (bytes <= 64 * 1024) return HAWKES_OK;
+    // with_static: the kernel's static LDS comes on top of `bytes`, so the
+    // grant is needed even at 64 KiB of dynamic LDS
+    if (!with_static && bytes <= 64 * 1024) return HAWKES_OK;
     static std::mutex mu;
     static const void* done_k[128];
     static int done_d[128];
@@ -1018,6 +1027,7 @@ static hawkes_status run_large_multi(LargeArgs& A, hipStream_t st) {
         return HAWKES_EUNSUPPORTED;
     if (A.grad && (uint64_t)A.nslot * (uint64_t)HK_SLOT_WORDS(A.CPL, A.NGW) * 8u >= (1ull << 32))
         return HAWKES_EUNSUPPORTED;
+    if (A.grad && dense_allow_lds(A) != HAWKES_OK) return HAWKES_EUNSUPPORTED;
     const int32_t W = 2 + 2 * K;
     hipLaunchKernelGGL(fill_d, dim3(16), dim3(256), 0, st, A.carry, (int64_t)K * 2 * M, 0.0);
     hipLaunchKernelGGL(fill_d, dim3(1), dim3(64), 0, st, A.acc, (int64_t)W, 0.0);
@@ -1133,6 +1143,7 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
         allow_lds((const void*)large_forward<false, true, false, HK_FWW>, lds_fwd) != HAWKES_OK ||
         allow_lds((const void*)large_forward<false, false, false, HK_FWW>, lds_fwd) != HAWKES_OK)
         return HAWKES_EUNSUPPORTED;
+    if (A.grad && !A.support && dense_allow_lds(A) != HAWKES_OK) return HAWKES_EUNSUPPORTED;
     const bool sup = A.grad && A.support;
     // support-restricted: the first term's copies (CSR order) take the place
     // of the dense partials, min(8, ER) of them (ER is a power of two)

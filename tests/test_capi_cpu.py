@@ -76,19 +76,21 @@ def test_tuning_round_trip_and_validation(H):
     # the launch tuning is host state: set, read back, reject bad values
     # (leaving the tuning unchanged), reset
     try:
-        H.set_tuning(dense_cols=128, dense_ranges=8, item_log2=7)
-        assert H.get_tuning() == {"dense_cols": 128, "dense_ranges": 8, "item_log2": 7}
+        good = {"dense_cols": 128, "dense_ranges": 8, "item_log2": 7, "dense_rows": 32}
+        H.set_tuning(**good)
+        assert H.get_tuning() == good
         for bad in ({"dense_cols": 96}, {"dense_cols": 512}, {"dense_ranges": 3}, {"dense_ranges": 8192},
-                    {"item_log2": 3}, {"item_log2": 17}, {"dense_ranges": -2}):
+                    {"item_log2": 3}, {"item_log2": 17}, {"dense_ranges": -2}, {"dense_rows": 8},
+                    {"dense_rows": 64}):
             with pytest.raises(H.HawkesError) as e:
                 H.set_tuning(**bad)
             assert e.value.status == 1
-            assert H.get_tuning() == {"dense_cols": 128, "dense_ranges": 8, "item_log2": 7}
+            assert H.get_tuning() == good
         L = H.lib()
         assert L.hawkes_get_tuning(None) == 1
     finally:
         H.set_tuning()
-    assert H.get_tuning() == {"dense_cols": 0, "dense_ranges": 0, "item_log2": 0}
+    assert H.get_tuning() == {"dense_cols": 0, "dense_ranges": 0, "item_log2": 0, "dense_rows": 0}
 
 
 def test_tuning_changes_the_workspace_layout(H):

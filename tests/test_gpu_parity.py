@@ -112,20 +112,39 @@ def test_support_gradient_is_the_masked_dense_gradient(H, seed, n, M, density, p
     assert int(np.count_nonzero(alpha)) > 0
 
 
-@pytest.mark.parametrize("cols,ranges,chunk", [(64, 0, 0), (64, 2, 12), (128, 0, 0), (128, 2, 12), (0, 1, 0),
-                                              (0, 2, 12), (0, 64, 0), (0, 1024, 0), (256, 0, 0), (256, 8, 12)])
-def test_dense_layouts_match_oracle(H, cols, ranges, chunk):
+@pytest.mark.parametrize("cols,ranges,chunk,rows", [(64, 0, 0, 0), (64, 2, 12, 0), (128, 0, 0, 0), (128, 2, 12, 0),
+                                                   (0, 1, 0, 0), (0, 2, 12, 0), (0, 64, 0, 0), (0, 1024, 0, 0),
+                                                   (256, 0, 0, 0), (256, 8, 12, 0), (256, 0, 0, 32),
+                                                   (256, 1, 12, 32), (256, 64, 0, 32), (256, 16, 14, 16)])
+def test_dense_layouts_match_oracle(H, cols, ranges, chunk, rows):
     # the dense dL/dalpha kernel's tile width (64, 128 or 256 nodes, set
-    # through the launch tuning) and event-range count change its run, slot
-    # and workgroup layout, never the result
+    # through the launch tuning), height (16 rows with float64 register
+    # accumulators, 32 with float32 ones flushed into a float64 tile) and
+    # event-range count change its run, slot and workgroup layout, never the
+    # result beyond rounding
     t, m, mu, alpha, beta, T = rand_problem(17, 30000, 200, density=0.1, rate=40.0)
     ref = oracle.forward(t, m, mu, alpha, beta, T)
     try:
-        H.set_tuning(dense_cols=cols, dense_ranges=ranges)
+        H.set_tuning(dense_cols=cols, dense_ranges=ranges, dense_rows=rows)
         got = run_gpu(H, t, m, mu, alpha, beta, T, chunk)
     finally:
         H.set_tuning()
-    check(got, ref, label=f"dense layout cols={cols or 'auto'} ranges={ranges or 'auto'} chunk={chunk}")
+    check(got, ref, label=f"dense layout cols={cols or 'auto'} ranges={ranges or 'auto'} chunk={chunk} "
+                          f"rows={rows or 'auto'}")
+
+
+@pytest.mark.parametrize("M,rows", [(400, 0), (1000, 16), (777, 32)])
+def test_dense_row_heights_at_large_m(H, M, rows):
+    # 32-row float32-accumulator tiles are the rule from 384 nodes; both
+    # heights against the oracle at several chunks, with rows past M
+    t, m, mu, alpha, beta, T = rand_problem(18 + M, 60000, M, density=0.02, rate=60.0)
+    ref = oracle.forward(t, m, mu, alpha, beta, T)
+    try:
+        H.set_tuning(dense_rows=rows)
+        got = run_gpu(H, t, m, mu, alpha, beta, T, 14)
+    finally:
+        H.set_tuning()
+    check(got, ref, label=f"dense rows={rows or 'auto'} M={M}")
 
 
 @pytest.mark.parametrize("item_log2", [4, 6, 9, 12])
