@@ -278,8 +278,15 @@ hawkes_status hawkes_adam_step(const hawkes_problem* p, const double* t, const i
  * device.  Outputs use the same packing: loglik[S], g_mu (like mu),
  * g_alpha (like alpha), g_beta[S].
  * Host arguments: S >= 1, n_total = ev_off[S] (the length of t), and
- * max_m >= every m_s[s] (sizes the kernels' register state; this build
- * supports max_m <= 8 and returns HAWKES_EUNSUPPORTED above that).
+ * max_m >= every m_s[s].
+ * With max_m <= 8 every sequence is evaluated by the small-M engine in one
+ * stream-ordered launch sequence that neither synchronises nor reads device
+ * memory from the host (graph-capturable).  With max_m > 8 the call reads
+ * ev_off, m_s and T_s to the host (it SYNCHRONISES the stream and cannot be
+ * captured in a graph), evaluates the sequences of at most 8 nodes with the
+ * small-M engine and each larger one with the large-M engine (node limit as
+ * for hawkes_loglik), one after another on the stream; m_s[s] outside
+ * [1, max_m] or offsets outside [0, n_total] then return HAWKES_EINVAL.
  * ------------------------------------------------------------------------- */
 size_t hawkes_batched_workspace_bytes(int32_t S, int64_t n_total, int32_t max_m, int with_grad);
 

@@ -511,6 +511,9 @@ class BatchedGraph:
     changing it."""
 
     def __init__(self, b: Batch):
+        if b.max_m > 8:
+            raise ValueError("a batch with more than 8 nodes in a sequence synchronises with the host "
+                             "(hawkes_loglik_grad_batched) and cannot be captured in a graph")
         self.b = b
         dev = b.t.device
         self.out = (torch.empty(b.S, dtype=torch.float64, device=dev),

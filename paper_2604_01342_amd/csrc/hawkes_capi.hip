@@ -4,6 +4,7 @@
 #include <math.h>
 #include <string.h>
 #include <mutex>
+#include <vector>
 #include "hk_device.h"
 #include "hk_internal.h"
 #include "hk_large.h"
@@ -284,11 +285,31 @@ hawkes_status hawkes_intensity(const hawkes_problem* p, const double* t, const i
                       workspace, workspace_bytes, stream);
 }
 
+// Batches with more than 8 nodes in some sequence: the small-M engine's
+// workspace for the whole batch (at 8 nodes), then the large-M engine's for
+// one sequence of up to n_total events and max_m nodes (constant beyond one
+// chunk), 256-byte aligned after it.
+static size_t batched_large_bytes(int64_t n_total, int32_t max_m, bool grad) {
+    hawkes_problem p;
+    memset(&p, 0, sizeof(p));
+    p.n = n_total;
+    p.m = max_m;
+    p.k = 1;
+    p.beta_mode = HAWKES_BETA_SHARED;
+    p.T = 1.0;
+    LargeArgs A;
+    memset(&A, 0, sizeof(A));
+    return large_layout(A, &p, grad, nullptr, 0);
+}
+
 size_t hawkes_batched_workspace_bytes(int32_t S, int64_t n_total, int32_t max_m, int with_grad) {
-    if (S < 1 || n_total < 0 || max_m < 1 || max_m > 8) return 0;
+    if (S < 1 || n_total < 0 || max_m < 1) return 0;
+    if ((int64_t)max_m * max_m > ((int64_t)1 << 31)) return 0;
     SmallArgs A;
     memset(&A, 0, sizeof(A));
-    return small_layout(A, S, n_total, max_m, with_grad != 0, nullptr, 0, false);
+    const size_t small = small_layout(A, S, n_total, max_m < 8 ? max_m : 8, with_grad != 0, nullptr, 0, false);
+    if (max_m <= 8) return small;
+    return ((small + 255) & ~(size_t)255) + batched_large_bytes(n_total, max_m, with_grad != 0);
 }
 
 static hawkes_status run_batched(int32_t S, int64_t n_total, int32_t max_m, const int64_t* ev_off,
@@ -297,19 +318,66 @@ static hawkes_status run_batched(int32_t S, int64_t n_total, int32_t max_m, cons
                                  double* g_mu, double* g_alpha, double* g_beta, bool grad, void* ws,
                                  size_t ws_bytes, hipStream_t stream) {
     if (S < 1 || n_total < 0 || max_m < 1) return HAWKES_EINVAL;
-    if (max_m > 8) return HAWKES_EUNSUPPORTED;
+    if ((int64_t)max_m * max_m > ((int64_t)1 << 31)) return HAWKES_EINVAL;
     if (!ev_off || !m_s || !T_s || !mu || !alpha || !beta || !loglik) return HAWKES_EINVAL;
     if (n_total > 0 && (!t || !marks)) return HAWKES_EINVAL;
     if (!ws) return HAWKES_EWORKSPACE;
+    const size_t need = hawkes_batched_workspace_bytes(S, n_total, max_m, grad ? 1 : 0);
+    if (need == 0) return HAWKES_EINVAL;
+    if (ws_bytes < need || ((uintptr_t)ws & 255) != 0) return HAWKES_EWORKSPACE;
     SmallArgs A;
     memset(&A, 0, sizeof(A));
-    const size_t need = small_layout(A, S, n_total, max_m, grad, ws, ws_bytes, false);
-    if (ws_bytes < need || ((uintptr_t)ws & 255) != 0) return HAWKES_EWORKSPACE;
+    const size_t small = small_layout(A, S, n_total, max_m < 8 ? max_m : 8, grad, ws, ws_bytes, false);
     A.ev_off = ev_off; A.m_s = m_s; A.T_s = T_s;
     A.t = t; A.marks = marks; A.mu = mu; A.alpha = alpha; A.beta = beta;
     A.loglik = loglik; A.g_mu = g_mu; A.g_alpha = g_alpha; A.g_beta = g_beta;
     A.lambda_out = nullptr;
-    return run_small(A, stream);
+    if (max_m <= 8) return run_small(A, stream);
+    // Sequences with more than 8 nodes: the offsets, node counts and window
+    // ends come to the host (the call synchronises the stream), the small-M
+    // engine evaluates the whole batch (its results for the larger
+    // sequences, computed on their first 8 nodes, are then overwritten), and
+    // the large-M engine evaluates each larger sequence in turn on the same
+    // stream, in the workspace after the small engine's.
+    std::vector<int64_t> off((size_t)S + 1);
+    std::vector<int32_t> ms((size_t)S);
+    std::vector<double> Ts((size_t)S);
+    if (hipMemcpyAsync(off.data(), ev_off, sizeof(int64_t) * (S + 1), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipMemcpyAsync(ms.data(), m_s, sizeof(int32_t) * S, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipMemcpyAsync(Ts.data(), T_s, sizeof(double) * S, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return HAWKES_EDEVICE;
+    }
+    bool any_small = false;
+    for (int32_t q = 0; q < S; ++q) {
+        if (ms[q] < 1 || ms[q] > max_m || off[q] < 0 || off[q + 1] < off[q] || off[q + 1] > n_total)
+            return HAWKES_EINVAL;
+        any_small = any_small || ms[q] <= 8;
+    }
+    hawkes_status st = any_small ? run_small(A, stream) : HAWKES_OK;
+    char* lws = (char*)ws + ((small + 255) & ~(size_t)255);
+    const size_t lbytes = ws_bytes - ((small + 255) & ~(size_t)255);
+    int64_t mu_o = 0, a_o = 0;
+    for (int32_t q = 0; q < S && st == HAWKES_OK; ++q) {
+        const int64_t mq = ms[q];
+        if (mq > 8) {
+            hawkes_problem p;
+            memset(&p, 0, sizeof(p));
+            p.n = off[q + 1] - off[q];
+            p.m = (int32_t)mq;
+            p.k = 1;
+            p.beta_mode = HAWKES_BETA_SHARED;
+            p.T = Ts[q];
+            const int64_t e0 = off[q];
+            st = run_single(&p, t ? t + e0 : nullptr, marks ? marks + e0 : nullptr, mu + mu_o, alpha + a_o,
+                            beta + q, loglik + q, g_mu ? g_mu + mu_o : nullptr, g_alpha ? g_alpha + a_o : nullptr,
+                            g_beta ? g_beta + q : nullptr, nullptr, grad, lws, lbytes, stream);
+        }
+        mu_o += mq;
+        a_o += mq * mq;
+    }
+    return st;
 }
 
 hawkes_status hawkes_loglik_batched(int32_t S, int64_t n_total, int32_t max_m, const int64_t* ev_off,

@@ -294,13 +294,26 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
     }
 }
 
-// ebacc[p] += sum over the chunk's segments, in segment order
-__global__ void pt_eb_reduce(int32_t nseg, int32_t M, const double* __restrict__ ebseg, double* __restrict__ ebacc) {
-    const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= M) return;
+// ebacc[p] += sum over the chunk's segments: a workgroup per 64 targets,
+// 16 slices of the segments summed side by side (each in segment order),
+// then the slices in order (a fixed order: repeatable)
+__global__ __launch_bounds__(1024) void pt_eb_reduce(int32_t nseg, int32_t M, const double* __restrict__ ebseg,
+                                                     double* __restrict__ ebacc) {
+    __shared__ double part[16][64];
+    const int lane = threadIdx.x & 63, sl = threadIdx.x >> 6;
+    const int32_t p = blockIdx.x * 64 + lane;
+    const int32_t per = (nseg + 15) / 16;
+    const int32_t s0 = sl * per, s1 = s0 + per < nseg ? s0 + per : nseg;
     double v = 0.0;
-    for (int32_t s = 0; s < nseg; ++s) v += ebseg[(int64_t)s * M + p];
-    ebacc[p] += v;
+    if (p < M)
+        for (int32_t s = s0; s < s1; ++s) v += ebseg[(int64_t)s * M + p];
+    part[sl][lane] = v;
+    __syncthreads();
+    if (sl == 0 && p < M) {
+        double tot = 0.0;
+        for (int k = 0; k < 16; ++k) tot += part[k][lane];
+        ebacc[p] += tot;
+    }
 }
 
 // ------------------------------------------------------------------ pass 2
@@ -687,7 +700,8 @@ hawkes_status run_large_pt(LargeArgs& A, hipStream_t st) {
                                    A.seg_part, A.ebseg, (float*)nullptr, (float*)nullptr);
         }
         large_chunk_acc_launch(nseg, 4, A.seg_part, A.acc, st);
-        hipLaunchKernelGGL(pt_eb_reduce, dim3(gM), dim3(256), 0, st, nseg, M, A.ebseg, A.ebacc);
+        hipLaunchKernelGGL(pt_eb_reduce, dim3((unsigned)((M + 63) / 64)), dim3(1024), 0, st, nseg, M, A.ebseg,
+                           A.ebacc);
     };
     auto copy = [&](double* dst, const double* src) {
         hipLaunchKernelGGL(pt_copy, dim3((unsigned)((M2 + 255) / 256)), dim3(256), 0, st, dst, src, M2);

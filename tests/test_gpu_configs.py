@@ -7,7 +7,9 @@ batches reach.
   32-bit word, and its checkpoint slots hold up to 1.7 GB addressed with
   32-bit offsets.  Each case has a full chunk and a ragged second one.
 * Batches whose sequences differ in node count (1..8) and length (0..1e4):
-  the device-side packing of each sequence's parameters and outputs.
+  the device-side packing of each sequence's parameters and outputs; and
+  batches with larger sequences (up to 100 nodes), which the library splits
+  between its small-M and large-M engines.
 
 Every result is compared with the FP64 oracle (oracle.forward) at 1e-6
 relative, per sequence for batches.
@@ -136,3 +138,21 @@ def test_batched_graph_keeps_its_workspace(H):
     for x, e in zip(got, eager):
         assert torch.equal(x, e)
     assert all(bool((f == 7.0).all()) for f in filler)
+
+
+def test_batch_with_large_node_counts(H):
+    # node counts 1..100 in one batch (sequences above 8 nodes go through the
+    # large-M engine one by one), every sequence checked against the oracle;
+    # the log-likelihood-only call agrees; such a batch cannot be captured
+    import torch
+    pb = rand_batch(777, 48, [1, 3, 8, 9, 16, 33, 64, 100], lo=1, hi=8000, n_empty=2, rate=10.0)
+    b = _batch_to_dev(H, pb)
+    assert b.max_m == 100
+    out = H.loglik_grad_batched(b)
+    torch.cuda.synchronize()
+    _check_batch(pb, out, "batch with M up to 100")
+    ll = H.loglik_batched(b).cpu().numpy()
+    for s in range(pb.S):
+        assert scalar_rel(ll[s], float(out[0][s])) <= 1e-12
+    with pytest.raises(ValueError):
+        H.BatchedGraph(b)
