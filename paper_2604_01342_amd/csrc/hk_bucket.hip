@@ -47,7 +47,8 @@ __global__ __launch_bounds__(64) void bucket_count(int64_t c0, int64_t c1, int32
 // boff[block][segment] relative to the block's start, boff[block][nseg] = its
 // total
 __global__ __launch_bounds__(256) void bucket_scan(int32_t nseg, const int32_t* __restrict__ cnt,
-                                                   int32_t* __restrict__ boff) {
+                                                   int32_t* __restrict__ boff, int32_t* __restrict__ done,
+                                                   int32_t* __restrict__ bbase) {
     __shared__ int32_t sh[256];
     const int32_t k = blockIdx.x;
     const int tid = threadIdx.x;
@@ -68,6 +69,34 @@ __global__ __launch_bounds__(256) void bucket_scan(int32_t nseg, const int32_t* 
         __syncthreads();
     }
     if (tid == 0) boff[(int64_t)k * (nseg + 1) + nseg] = carry;
+    if (!done) return;
+    // the last block to finish forms the blocks' bases (exclusive scan of
+    // their totals), instead of a launch of bucket_base
+    __shared__ int last;
+    __threadfence();
+    if (tid == 0) last = atomicAdd(done, 1) == (int)gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    const volatile int32_t* bo = boff;
+    const int32_t NB = (int32_t)gridDim.x;
+    int32_t run = 0;
+    for (int32_t base = 0; base < NB; base += 256) {
+        const int32_t b = base + tid;
+        const int32_t v = b < NB ? bo[(int64_t)b * (nseg + 1) + nseg] : 0;
+        sh[tid] = v;
+        __syncthreads();
+        for (int d = 1; d < 256; d <<= 1) {
+            const int32_t u = tid >= d ? sh[tid - d] : 0;
+            __syncthreads();
+            sh[tid] += u;
+            __syncthreads();
+        }
+        if (b < NB) bbase[b] = run + sh[tid] - v;
+        run += sh[255];
+        __syncthreads();
+    }
+    if (tid == 0) *done = 0;
 }
 
 // bbase[block] = number of records of the blocks before it (one workgroup,
@@ -156,14 +185,15 @@ __global__ __launch_bounds__(64) void bucket_scatter(int64_t c0, int64_t c1, int
 // (events per chunk) << bs < 2^32); records go to the given arrays
 void bucket_chunk_into(const LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, const float* wchunk, int bs,
                        int32_t* cnt, int32_t* off, int32_t* base, uint32_t* key, double* tt, float* ww,
-                       hipStream_t st) {
+                       hipStream_t st, bool counted, int32_t* done) {
     const int32_t nb = (A.M + (1 << bs) - 1) >> bs;
     int nbits = 0;
     while ((1 << nbits) < nb) ++nbits;
     const size_t lds = (size_t)nb * sizeof(int32_t);
-    hipLaunchKernelGGL(bucket_count, dim3(nseg), dim3(64), lds, st, c0, c1, A.M, nb, bs, A.marks, nseg, cnt);
-    hipLaunchKernelGGL(bucket_scan, dim3(nb), dim3(256), 0, st, nseg, cnt, off);
-    hipLaunchKernelGGL(bucket_base, dim3(1), dim3(256), 0, st, nb, nseg, off, base);
+    if (!counted)
+        hipLaunchKernelGGL(bucket_count, dim3(nseg), dim3(64), lds, st, c0, c1, A.M, nb, bs, A.marks, nseg, cnt);
+    hipLaunchKernelGGL(bucket_scan, dim3(nb), dim3(256), 0, st, nseg, cnt, off, done, base);
+    if (!done) hipLaunchKernelGGL(bucket_base, dim3(1), dim3(256), 0, st, nb, nseg, off, base);
     hipLaunchKernelGGL(bucket_scatter, dim3(nseg), dim3(64), lds, st, c0, c1, A.M, nb, nbits, bs, A.t, A.marks, wchunk,
                        nseg, off, base, key, tt, ww);
 }

@@ -95,6 +95,8 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
                                                const double* __restrict__ t, const int32_t* __restrict__ marks,
                                                const float* __restrict__ wchunk, const float* __restrict__ beta,
                                                const double* __restrict__ carry_seg,
+                                               const double* __restrict__ gcarry,
+                                               const double* __restrict__ seg_offdec,
                                                const int32_t* __restrict__ bo_off,
                                                const int32_t* __restrict__ bo_base, double* __restrict__ kck,
                                                int4* __restrict__ runinfo, double* __restrict__ spart,
@@ -160,6 +162,10 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
     for (int j = 0; j < CPL; ++j) {
         const int32_t col = s0 + j * 64 + lane;
         K[j] = col < M ? carry_seg[(int64_t)sA * 2 * M + col] : 0.0;
+        // carry_seg as in-group prefixes (gcarry given): add the scan group's
+        // carry moved to the run's first segment
+        if (gcarry && col < M)
+            K[j] = __builtin_fma(seg_offdec[sA], gcarry[(int64_t)(sA / HK_SG) * 2 * M + col], K[j]);
     }
     double tau = c0 + a > 0 ? t[c0 + a - 1] : t[c0];
     struct Rec {
@@ -933,7 +939,8 @@ static void dense_launch_t(LargeArgs& A, int64_t c0, int32_t nev, int32_t nseg, 
         TimedScope tk(7, st);
         const unsigned nck = (unsigned)(((nrun_c + 7) / 8) * 8 * A.NBC);
         hipLaunchKernelGGL((dense_ck<CPL, DRB, NGW>), dim3(nck), dim3(64), 0, st, c0, nev, A.M, A.NBC, A.NBO, A.NRUN,
-                           A.CKR, nseg, A.T, A.t, A.marks, A.wchunk, A.beta, A.carry_seg, A.bo_off, A.bo_base,
+                           A.CKR, nseg, A.T, A.t, A.marks, A.wchunk, A.beta, A.carry_seg,
+                           A.carry_prefix ? A.gcarry : (const double*)nullptr, A.seg_offdec, A.bo_off, A.bo_base,
                            A.kck, A.runinfo, A.spart, A.cpart_);
     }
     if (ck_only) return;

@@ -73,6 +73,8 @@ struct LargeArgs {
     double* seg_part;     // [nseg][2 + 2K]
     double* acc;          // [2 + 2K] call-level sums: logsum, comp, E[K], gbeta[K]
     double* ll_scratch;   // [1] log-likelihood slot when the caller wants intensities only
+    int32_t* ctr;         // [2] completion counters (the partition scan's in [1]), zero between launches
+    bool carry_prefix;    // carry_seg holds in-group prefixes (the scan's apply pass left out)
     double *gpart, *spart, *cpart_;  // [ER][M][M]; [ER][M] per target, [NRUN][M] shared decay
     double* gsup;         // [min(8, ER)][M*M] support-restricted first term of eq. 9 in CSR order (the
                           //   first nnz(alpha) entries of each copy; shares gpart's space)
@@ -115,6 +117,16 @@ struct LargeArgs {
 };
 
 #define HK_SG 32           // segments per scan group
+#define HK_NBO_MAX 256     // node blocks the forward pass can count for the partition
+
+// optional parts of the shared-decay forward pass (see large_forward)
+struct FwdExtra {
+    const double* gcarry;
+    const double* seg_off;
+    const double* seg_offdec;
+    int32_t* bcnt;
+    int32_t bs, nbo;
+};
 #define HK_PTCK 64         // checkpoint slots per level of the per-target gradient (at most 64^2 chunks)
 
 size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, size_t ws_bytes);
@@ -127,12 +139,17 @@ hawkes_status allow_lds(const void* kernel, size_t bytes, bool with_static = fal
 hawkes_status dense_allow_lds(const LargeArgs& A);
 void large_build_index(int32_t M, const float* alpha, int trans, int32_t* ptr, int32_t* idx, float* val,
                        hipStream_t st);
-void large_scan(LargeArgs& A, int32_t nseg, const float* beta_pt, hipStream_t st);
+// apply = false leaves carry_seg as in-group prefixes (the forward pass and
+// the checkpoint kernel then add the group carries themselves)
+void large_scan(LargeArgs& A, int32_t nseg, const float* beta_pt, hipStream_t st, bool apply = true);
 void large_chunk_acc_launch(int32_t nseg, int32_t width, const double* seg_part, double* acc, hipStream_t st);
 void bucket_chunk(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, const float* wchunk, int bs, hipStream_t st);
+// counted: cnt already holds the counts (the forward pass made them);
+// done: a zeroed completion counter (the last block of the scan of the
+// counts forms the blocks' bases)
 void bucket_chunk_into(const LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, const float* wchunk, int bs,
                        int32_t* cnt, int32_t* off, int32_t* base, uint32_t* key, double* tt, float* ww,
-                       hipStream_t st);
+                       hipStream_t st, bool counted = false, int32_t* done = nullptr);
 // ck_only: the checkpoint kernel alone (its per-column sums of dL/dmu and
 // the compensator), for the support-restricted gradient
 void large_dense_launch(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, hipStream_t st, bool ck_only);

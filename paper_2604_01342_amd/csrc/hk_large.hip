@@ -42,6 +42,11 @@ __global__ void fill_d(double* p, int64_t n, double v) {
         p[i] = v;
 }
 
+__global__ void fill_i(int32_t* p, int64_t n, int32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
 // colsum[q] = sum_p alpha[p][q]: a workgroup of 16 waves per 64 columns,
 // wave r sums rows r, r+16, ... (coalesced over q), then a fixed-order sum
 __global__ __launch_bounds__(1024) void large_colsum(int32_t M, const float* __restrict__ alpha,
@@ -321,6 +326,12 @@ __global__ void large_scan_apply(int32_t nseg, int32_t M, const double* __restri
 // MM apart): consecutive workgroups go to different XCDs, so each copy sees
 // mostly one XCD's atomics and a copy's addresses see a fraction of the
 // contention.
+// X (optional parts, each off when its pointer is null):
+//   gcarry    carry_seg holds only the in-group prefixes of the scan
+//             (large_scan without its apply pass): the state entering segment
+//             s is formed here from its group's carry, seg_off and seg_offdec
+//   bcnt      the chunk partition's counts, events per (node block of 2^bs
+//             nodes, segment), written as bucket_count would
 template <bool GRAD, bool INTENS, bool SUPP, int NW, bool RM = false>
 __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1, int32_t M, double T,
                                                     const double* __restrict__ t, const int32_t* __restrict__ marks,
@@ -333,7 +344,8 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
                                                     float* __restrict__ wchunk,
                                                     float* __restrict__ lambda_out,
                                                     double* __restrict__ gsup, int32_t cmask,
-                                                    double* __restrict__ rk, double* __restrict__ dk) {
+                                                    double* __restrict__ rk, double* __restrict__ dk,
+                                                    FwdExtra X) {
     extern __shared__ double lds[];
     double* rtau = lds;                                   // [M] time of the record
     uint64_t* rmask = (uint64_t*)(lds + M);               // [M] lanes of this batch with mark q
@@ -361,11 +373,25 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
     // time rtau[q] and is decayed on use.
     const bool anch = bet * (t[b - 1] - tref) <= 600.0;
     const double* cs = carry_seg + (int64_t)s * 2 * M;
+    const double* gc = X.gcarry ? X.gcarry + (int64_t)(s / HK_SG) * 2 * M : nullptr;
+    const double Dg = gc ? X.seg_off[s] : 0.0, exg = gc ? X.seg_offdec[s] : 0.0;
     for (int32_t q = threadIdx.x; q < M; q += 64 * NW) {
+        double Kq = cs[q], Jq = cs[M + q];
+        if (gc) {
+            // the group's carry moved to the segment start, plus the prefix
+            const double Kc = gc[q];
+            Jq = __builtin_fma(exg, __builtin_fma(Dg, Kc, gc[M + q]), Jq);
+            Kq = __builtin_fma(exg, Kc, Kq);
+        }
         rtau[q] = tref;
-        rKJ[q] = make_double2(cs[q], anch ? -cs[M + q] : cs[M + q]);
+        rKJ[q] = make_double2(Kq, anch ? -Jq : Jq);
         rmask[q] = 0ull;
     }
+    // events per node block (partition counts): dynamic LDS after the
+    // records, present when bcnt is given
+    int32_t* lcnt = reinterpret_cast<int32_t*>(lds + 4 * M);
+    if (X.bcnt)
+        for (int32_t k = threadIdx.x; k < X.nbo; k += 64 * NW) lcnt[k] = 0;
     __syncthreads();
     double logsum = 0.0, comp = 0.0, Esum = 0.0, gb = 0.0;
     // software pipeline over batches of 64 events: times and marks are loaded
@@ -417,6 +443,7 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
             tb[lane] = ti;
             eb[lane] = eti;
             if (valid) atomicOr((unsigned long long*)&rmask[mi], 1ull << lane);
+            if (X.bcnt && valid) atomicAdd(&lcnt[mi >> X.bs], 1);
         }
         __syncthreads();
         double R = 0.0, Dd = 0.0, lam = 1.0, w = 0.0, em1 = 0.0;
@@ -605,6 +632,10 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
             qc0[j] = qc1[j];
             qa0[j] = qa1[j];
         }
+    }
+    if (X.bcnt) {
+        __syncthreads();
+        for (int32_t k = threadIdx.x; k < X.nbo; k += 64 * NW) X.bcnt[(int64_t)k * gridDim.x + s] = lcnt[k];
     }
     // deterministic wave reduction of the float64 partials (the first
     // wave's; the others hold none)
@@ -879,6 +910,7 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
     A.carry_t = c.take<double>(1);
     A.seg_part = c.take<double>((size_t)A.nseg * (2 + 2 * K));
     A.acc = c.take<double>(2 + 2 * K);
+    A.ctr = c.take<int32_t>(2);
     A.ll_scratch = c.take<double>(1);
     if (A.per_target) {
         A.csc_ptr = c.take<int32_t>(M + 1);
@@ -993,7 +1025,7 @@ void large_build_index(int32_t M, const float* alpha, int trans, int32_t* ptr, i
     hipLaunchKernelGGL(large_csr_fill, dim3(M), dim3(64), 0, st, M, alpha, ptr, idx, val, trans);
 }
 
-void large_scan(LargeArgs& A, int32_t nseg, const float* beta_pt, hipStream_t st) {
+void large_scan(LargeArgs& A, int32_t nseg, const float* beta_pt, hipStream_t st, bool apply) {
     const int32_t M = A.M;
     // the first two passes are serial chains per thread, ngr * M and M
     // threads in all: workgroups of one wave spread them over every CU
@@ -1005,8 +1037,9 @@ void large_scan(LargeArgs& A, int32_t nseg, const float* beta_pt, hipStream_t st
                        A.seg_offdec);
     hipLaunchKernelGGL(large_scan_groups, dim3(gM), dim3(64), 0, st, nseg, M, A.gagg, A.gspan, A.gdec, A.gcarry,
                        A.carry, beta_pt);
-    hipLaunchKernelGGL(large_scan_apply, dim3((unsigned)((napp + 255) / 256)), dim3(256), 0, st, nseg, M,
-                       A.seg_off, A.seg_offdec, A.gcarry, A.carry_seg, beta_pt);
+    if (apply)
+        hipLaunchKernelGGL(large_scan_apply, dim3((unsigned)((napp + 255) / 256)), dim3(256), 0, st, nseg, M,
+                           A.seg_off, A.seg_offdec, A.gcarry, A.carry_seg, beta_pt);
 }
 
 // Several decay kernels (K > 1, shared decay per kernel; Background eq. 1,
@@ -1031,6 +1064,7 @@ static hawkes_status run_large_multi(LargeArgs& A, hipStream_t st) {
     const int32_t W = 2 + 2 * K;
     hipLaunchKernelGGL(fill_d, dim3(16), dim3(256), 0, st, A.carry, (int64_t)K * 2 * M, 0.0);
     hipLaunchKernelGGL(fill_d, dim3(1), dim3(64), 0, st, A.acc, (int64_t)W, 0.0);
+    hipLaunchKernelGGL(fill_i, dim3(1), dim3(64), 0, st, A.ctr, (int64_t)2, 0);
     if (A.grad) {
         const int64_t ng = (int64_t)K * A.ER * MM;
         hipLaunchKernelGGL(fill_d, dim3((unsigned)((ng + 255) / 256 < 65535 ? (ng + 255) / 256 : 65535)),
@@ -1081,13 +1115,13 @@ static hawkes_status run_large_multi(LargeArgs& A, hipStream_t st) {
                                    lds_fwd, st, c0, c1, M, A.T, A.t, A.marks, A.mu, B.beta,
                                    A.node_info + (int64_t)k * M, A.csr_col + k * MM, A.csr_val + k * MM, B.carry_seg,
                                    A.seg_part, A.wchunk, (float*)nullptr, (double*)nullptr, 0,
-                                   A.rk + (int64_t)k * A.CH, A.dk + (int64_t)k * A.CH);
+                                   A.rk + (int64_t)k * A.CH, A.dk + (int64_t)k * A.CH, FwdExtra{});
             else
                 hipLaunchKernelGGL((large_forward<false, false, false, HK_FWW, true>), dim3(nseg), dim3(64 * HK_FWW),
                                    lds_fwd, st, c0, c1, M, A.T, A.t, A.marks, A.mu, B.beta,
                                    A.node_info + (int64_t)k * M, A.csr_col + k * MM, A.csr_val + k * MM, B.carry_seg,
                                    A.seg_part, A.wchunk, (float*)nullptr, (double*)nullptr, 0,
-                                   A.rk + (int64_t)k * A.CH, (double*)nullptr);
+                                   A.rk + (int64_t)k * A.CH, (double*)nullptr, FwdExtra{});
         }
         {
             TimedScope ts(1, st);
@@ -1109,7 +1143,7 @@ static hawkes_status run_large_multi(LargeArgs& A, hipStream_t st) {
             {
                 TimedScope tb(6, st);
                 bucket_chunk_into(A, c0, c1, nseg, A.wchunk, A.DRB, A.bo_cnt, A.bo_off, A.bo_base, A.bo_key, A.bo_t,
-                                  A.bo_w, st);
+                                  A.bo_w, st, false, A.ctr + 1);
             }
             for (int32_t k = 0; k < K; ++k) {
                 LargeArgs B = view(k);
@@ -1153,9 +1187,32 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
     // 32-bit byte offsets
     if (A.grad && (uint64_t)A.nslot * (uint64_t)HK_SLOT_WORDS(A.CPL, A.NGW) * 8u >= (1ull << 32))
         return HAWKES_EUNSUPPORTED;
-    // zero the carried state and accumulators
+    // zero the carried state, accumulators and completion counters
     hipLaunchKernelGGL(fill_d, dim3(1), dim3(256), 0, st, A.carry, (int64_t)2 * M, 0.0);
     hipLaunchKernelGGL(fill_d, dim3(1), dim3(64), 0, st, A.acc, (int64_t)4, 0.0);
+    hipLaunchKernelGGL(fill_i, dim3(1), dim3(64), 0, st, A.ctr, (int64_t)2, 0);
+    // the forward pass adds the scan's group carries itself (the scan's
+    // apply pass is left out) and counts the partition (by blocks of 2^DRB
+    // nodes, when the gradient needs them and they fit its LDS).  Measured
+    // at c4: 6.483 -> 6.439 ms per step; also summing the chunk in the
+    // forward pass's last workgroup instead of large_chunk_acc cost 0.17 ms.
+    FwdExtra X;
+    X.gcarry = A.gcarry;
+    X.seg_off = A.seg_off;
+    X.seg_offdec = A.seg_offdec;
+    X.bs = A.DRB;
+    X.nbo = A.NBO;
+    X.bcnt = nullptr;
+    size_t lds_fwdc = lds_fwd;   // the gradient's forward pass, with the partition counts if they fit
+    if (A.grad && A.NBO <= HK_NBO_MAX) {
+        const void* kf = sup ? (const void*)large_forward<true, false, true, 1>
+                             : (const void*)large_forward<true, false, false, HK_FWW>;
+        if (allow_lds(kf, lds_fwd + HK_NBO_MAX * sizeof(int32_t)) == HAWKES_OK) {
+            X.bcnt = A.bo_cnt;
+            lds_fwdc = lds_fwd + HK_NBO_MAX * sizeof(int32_t);
+        }
+    }
+    A.carry_prefix = true;
     if (A.grad) {
         // the dense partials, or (support-restricted) the CSR-ordered sums
         const int64_t ng = (sup ? ncopy : A.ER) * MM;
@@ -1178,40 +1235,40 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
         }
         {
             TimedScope ts(3, st);
-            large_scan(A, nseg, nullptr, st);
+            large_scan(A, nseg, nullptr, st, false);
         }
         {
             TimedScope ts(1, st);
             if (sup)
-                hipLaunchKernelGGL((large_forward<true, false, true, 1>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1,
+                hipLaunchKernelGGL((large_forward<true, false, true, 1>), dim3(nseg), dim3(64), lds_fwdc, st, c0, c1,
                                    M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
                                    A.carry_seg, A.seg_part, A.wchunk, (float*)nullptr, A.gsup, ncopy - 1,
-                                   (double*)nullptr, (double*)nullptr);
+                                   (double*)nullptr, (double*)nullptr, X);
             else if (A.grad)
-                hipLaunchKernelGGL((large_forward<true, false, false, HK_FWW>), dim3(nseg), dim3(64 * HK_FWW), lds_fwd,
+                hipLaunchKernelGGL((large_forward<true, false, false, HK_FWW>), dim3(nseg), dim3(64 * HK_FWW), lds_fwdc,
                                    st, c0, c1,
                                    M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
                                    A.carry_seg, A.seg_part, A.wchunk, (float*)nullptr, (double*)nullptr, 0,
-                                   (double*)nullptr, (double*)nullptr);
+                                   (double*)nullptr, (double*)nullptr, X);
             else if (A.lambda_out)
                 hipLaunchKernelGGL((large_forward<false, true, false, HK_FWW>), dim3(nseg), dim3(64 * HK_FWW), lds_fwd,
                                    st, c0, c1,
                                    M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
                                    A.carry_seg, A.seg_part, A.wchunk, A.lambda_out, (double*)nullptr, 0,
-                                   (double*)nullptr, (double*)nullptr);
+                                   (double*)nullptr, (double*)nullptr, X);
             else
                 hipLaunchKernelGGL((large_forward<false, false, false, HK_FWW>), dim3(nseg), dim3(64 * HK_FWW), lds_fwd,
                                    st, c0, c1,
                                    M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
                                    A.carry_seg, A.seg_part, A.wchunk, (float*)nullptr, (double*)nullptr, 0,
-                                   (double*)nullptr, (double*)nullptr);
+                                   (double*)nullptr, (double*)nullptr, X);
         }
         hipLaunchKernelGGL(large_chunk_acc, dim3(1), dim3(256), 0, st, nseg, 4, A.seg_part, A.acc);
         if (A.grad) {
             {
                 TimedScope tb(6, st);
                 bucket_chunk_into(A, c0, c1, nseg, A.wchunk, A.DRB, A.bo_cnt, A.bo_off, A.bo_base, A.bo_key, A.bo_t,
-                                  A.bo_w, st);
+                                  A.bo_w, st, X.bcnt != nullptr, A.ctr + 1);
             }
             // support-restricted: only the checkpoint kernel's per-column
             // sums (dL/dmu, compensator) are needed
