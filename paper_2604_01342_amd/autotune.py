@@ -73,7 +73,7 @@ def candidates_single(n: int, M: int, per_target: bool, chunk_log2: int) -> list
     out = [{"dense_cols": c, "dense_ranges": r} for c in cols for r in (4, 8, 16, 32, 64)]
     if 256 in cols and M > 128:
         # 32-row tiles (float32 register accumulators) exist for 256 columns
-        out += [{"dense_cols": 256, "dense_ranges": r, "dense_rows": h} for r in (8, 16, 32) for h in (16, 32)]
+        out += [{"dense_cols": 256, "dense_ranges": r, "dense_rows": h} for r in (4, 8, 16, 32) for h in (16, 32)]
     return out
 
 

@@ -231,15 +231,22 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
         // record's index, column, time and factor).
         int pos;
         {
+            // rank of the record in (bank, lane) order from bit-sliced
+            // ballots: from the top bit down, the lanes that agree with
+            // this lane's bank so far and have a 0 where it has a 1 are
+            // smaller; the lanes left at the end share its bank
             const int bank = v ? (int)(q.key & 15u) : 16;
             const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-            int before = 0, rank = 0;
-            for (int bv = 0; bv <= 16; ++bv) {
-                const uint64_t mb = __ballot(bank == bv);
-                before += bv < bank ? __builtin_popcountll(mb) : 0;
-                if (bv == bank) rank = __builtin_popcountll(mb & below);
+            uint64_t eq = ~0ull;
+            int before = 0;
+#pragma unroll
+            for (int i = 4; i >= 0; --i) {
+                const uint64_t bi = __ballot((bank >> i) & 1);
+                const bool one = (bank >> i) & 1;
+                if (one) before += __builtin_popcountll(eq & ~bi);
+                eq &= one ? bi : ~bi;
             }
-            const int sidx = before + rank;   // a permutation of 0..63
+            const int sidx = before + __builtin_popcountll(eq & below);   // a permutation of 0..63
             pos = (sidx & 3) * 16 + (sidx >> 2);
         }
         out[S::T + half + pos] = v ? q.t : 0.0;

@@ -867,8 +867,12 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
     // rounds balance the waves' uneven work) or 2048 (per target, 34 KiB;
     // 16 x 256 tiles, 34 KiB and two waves per SIMD: measured best at c4's
     // size) unless the tuning (hawkes_set_tuning) sets it
+    // (32-row float32-accumulator tiles: 512 workgroups of four waves, two
+    // resident per CU, i.e. one round; measured at c4, dense ms per launch
+    // with 4 / 8 / 16 / 32 ranges: 0.416 / 0.420 / 0.434 / 0.534, and a
+    // quarter of the partials' traffic at 4)
     const int64_t nbb = (int64_t)A.NBR * A.NBC;
-    const int64_t target = A.per_target || A.CPL == 4 ? 2048 : 4096;
+    const int64_t target = A.DRB == 5 ? 512 : A.per_target || A.CPL == 4 ? 2048 : 4096;
     const int64_t want = (target + nbb - 1) / nbb;
     int32_t er = 1;
     while (er < want) er <<= 1;
