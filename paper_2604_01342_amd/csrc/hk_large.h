@@ -56,8 +56,9 @@ struct LargeArgs {
     const float *mu, *alpha, *beta;
     // workspace (with K > 1 the per-kernel arrays below are K consecutive
     // copies: csr_*, colsum, node_info, carry, carry_seg, gpart, spart, cpart_)
-    int32_t *csr_ptr, *csr_col;
-    float *csr_val, *colsum;
+    int32_t* csr_ptr;
+    int2* csr_cv;         // nonzeros of alpha by row: (column, float bits of the value)
+    float* colsum;
     double *rk, *dk;      // K > 1: [K][CH] per event of the chunk, R_k and D_k (alpha row . K and . J)
     double* agg;          // [nseg][2M] segment maps (K_run, J_run)
     double* seg_span;     // [nseg] time from the event before the segment to its last event
@@ -83,8 +84,8 @@ struct LargeArgs {
                           //   decay) with their groups' records
     int4* runinfo;        // [NBC][NRUN] per checkpoint run: first slot, groups, P0, P1
     // per-target decays (R-form forward, reverse adjoint for the gradient)
-    int32_t *csc_ptr, *csc_row;   // alpha by column: targets p of source q
-    float* csc_val;
+    int32_t* csc_ptr;   // alpha by column: targets p of source q
+    int2* csc_cv;       // (target, float bits of the value)
     float* wv;            // [CH] w_i = 1/lambda_i of the chunk's events
     double* pt_ck;        // [2 HK_PTCK][2M] chunk-start states (R, D): level-1 slots, then level-2 slots
     int64_t pt_ckr;       // chunks per level-1 slot
@@ -137,8 +138,11 @@ size_t lds_limit();
 hawkes_status allow_lds(const void* kernel, size_t bytes, bool with_static = false);
 // grants the float32-accumulator dense kernel its LDS tile (when the layout selects it)
 hawkes_status dense_allow_lds(const LargeArgs& A);
-void large_build_index(int32_t M, const float* alpha, int trans, int32_t* ptr, int32_t* idx, float* val,
-                       hipStream_t st);
+void large_build_index(int32_t M, const float* alpha, int trans, int32_t* ptr, int2* cv, hipStream_t st);
+// entries between consecutive kernels' packed rows of alpha: even (each
+// kernel's array starts 16-byte aligned for the forward pass's pair loads)
+// and at least one spare entry past the M^2 a dense alpha fills
+inline int64_t cv_stride(int64_t MM) { return (MM + 2) & ~(int64_t)1; }
 // apply = false leaves carry_seg as in-group prefixes (the forward pass and
 // the checkpoint kernel then add the group carries themselves)
 void large_scan(LargeArgs& A, int32_t nseg, const float* beta_pt, hipStream_t st, bool apply = true);

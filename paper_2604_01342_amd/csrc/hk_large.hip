@@ -115,7 +115,7 @@ __global__ __launch_bounds__(1024) void large_csr_scan(int32_t M, int32_t* __res
 // one wave per row: compact the nonzeros of row p in column order
 __global__ __launch_bounds__(64) void large_csr_fill(int32_t M, const float* __restrict__ alpha,
                                                      const int32_t* __restrict__ csr_ptr,
-                                                     int32_t* __restrict__ csr_col, float* __restrict__ csr_val,
+                                                     int2* __restrict__ csr_cv,
                                                      int trans) {
     const int32_t p = blockIdx.x;
     const int lane = threadIdx.x;
@@ -126,8 +126,7 @@ __global__ __launch_bounds__(64) void large_csr_fill(int32_t M, const float* __r
         const uint64_t nz = __ballot(a != 0.0f);
         if (a != 0.0f) {
             const int32_t r = __builtin_popcountll(nz & (lane ? (~0ull >> (64 - lane)) : 0ull));
-            csr_col[o + r] = q;
-            csr_val[o + r] = a;
+            csr_cv[o + r] = make_int2(q, __float_as_int(a));
         }
         o += __builtin_popcountll(nz);
     }
@@ -317,6 +316,9 @@ __global__ void large_scan_apply(int32_t nseg, int32_t M, const double* __restri
 #ifndef HK_FWW
 #define HK_FWW 2   // waves per forward-pass segment
 #endif
+#ifndef HK_FW
+#define HK_FW 16   // nonzeros of an event's row of alpha loaded one batch ahead
+#endif
 // RM (several decay kernels): the pass runs once per kernel and writes, per
 // event, R = alpha_{m_i,:} . K(t_i) to rk and (GRAD) D = alpha_{m_i,:} . J(t_i)
 // to dk instead of forming lambda; large_combine then sums the kernels.
@@ -337,8 +339,7 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
                                                     const double* __restrict__ t, const int32_t* __restrict__ marks,
                                                     const float* __restrict__ mu, const float* __restrict__ beta,
                                                     const int4* __restrict__ node_info,
-                                                    const int32_t* __restrict__ csr_col,
-                                                    const float* __restrict__ csr_val,
+                                                    const int2* __restrict__ csr_cv,
                                                     const double* __restrict__ carry_seg,
                                                     double* __restrict__ seg_part,
                                                     float* __restrict__ wchunk,
@@ -354,8 +355,8 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
     __shared__ double Rs[(NW > 1 ? NW - 1 : 1) * 64], Ds[(NW > 1 ? NW - 1 : 1) * 64];   // other waves' partial sums
     const int32_t s = blockIdx.x;
     const int lane = threadIdx.x & 63;
-    // NW waves share a segment's events; wave wv takes nonzeros wv, wv + NW, ...
-    // of each event's row of alpha
+    // NW waves share a segment's events; wave wv takes the aligned pairs of
+    // nonzeros wv, wv + NW, ... of each event's row of alpha
     const int wv = NW == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     static_assert(!SUPP || NW == 1, "the support-restricted sums are formed by one wave");
     static_assert(!(RM && (SUPP || INTENS)), "per-kernel sums only");
@@ -397,21 +398,29 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
     // software pipeline over batches of 64 events: times and marks are loaded
     // three batches ahead, node records two ahead and the first FW nonzeros
     // of each event's row of alpha one ahead (clamped indices keep every load
-    // valid), so the gathers' latency hides behind a batch of work
-    constexpr int FW = 16;         // nonzeros loaded ahead per event
-    constexpr int FWW = FW / NW;   // of which this wave's
+    // valid), so the gathers' latency hides behind a batch of work.  The row
+    // is read in aligned pairs of entries (pair P holds entries 2P and 2P + 1,
+    // one 16-byte load; the first and last pair may hold a neighbour row's
+    // entry, which is skipped): these gathers hit a different cache line per
+    // lane, so the number of load instructions, not bytes, sets their cost.
+    constexpr int FW = HK_FW;          // nonzeros loaded ahead per event
+    constexpr int FP = FW / (2 * NW);  // pairs of them loaded by this wave
+    static_assert(FP >= 1 && FP * 2 * NW == FW, "look-ahead must be whole pairs per wave");
+    const int4* __restrict__ cv4 = reinterpret_cast<const int4*>(csr_cv);
     auto ld_tm = [&](int64_t base, double& tt, int& mm) {
         const int64_t j = base + lane;
         const int64_t jc = j < b ? j : b - 1;
         tt = t[jc];
         mm = clamp_mark(marks[jc], M);
     };
-    auto ld_row = [&](const int4& nv, int32_t (&qc)[FWW], float (&qa)[FWW]) {
+    // pairs past the row's last entry are replaced by its first pair (an
+    // empty row reads pair nv.x / 2, inside the array's one spare pair)
+    auto ld_row = [&](const int4& nv, int4 (&pr)[FP]) {
+        const int32_t p0 = nv.x >> 1, pl = (nv.y - 1) >> 1;
 #pragma unroll
-        for (int j = 0; j < FWW; ++j) {
-            const int32_t k = nv.x + NW * j + wv < nv.y ? nv.x + NW * j + wv : nv.x;
-            qc[j] = csr_col[k];
-            qa[j] = csr_val[k];
+        for (int j = 0; j < FP; ++j) {
+            const int32_t P = p0 + NW * j + wv;
+            pr[j] = cv4[P <= pl ? P : p0];
         }
     };
     double t0, t1, t2;
@@ -420,9 +429,8 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
     ld_tm(a + 64, t1, m1);
     ld_tm(a + 128, t2, m2);
     int4 n0 = node_info[m0], n1 = node_info[m1];
-    int32_t qc0[FWW];
-    float qa0[FWW];
-    ld_row(n0, qc0, qa0);
+    int4 pr0[FP];
+    ld_row(n0, pr0);
     for (int64_t base = a; base < b; base += 64) {
         const int64_t i = base + lane;
         const bool valid = i < b;
@@ -434,9 +442,8 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
         int m3;
         ld_tm(base + 192, t3, m3);
         const int4 n2 = node_info[m2];
-        int32_t qc1[FWW];
-        float qa1[FWW];
-        ld_row(n1, qc1, qa1);
+        int4 pr1[FP];
+        ld_row(n1, pr1);
         const double ui = ti - tref;
         if (wv == 0) {
             const double eti = anch && valid ? exp_f64(bet * ui) : 0.0;   // e^{beta u_i}
@@ -448,8 +455,8 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
         __syncthreads();
         double R = 0.0, Dd = 0.0, lam = 1.0, w = 0.0, em1 = 0.0;
         const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-        const int32_t k0 = ni.x, k1 = ni.y;
-        double ks[SUPP ? FW : 1];   // the first FW nonzeros' sums, for gsup (NW = 1)
+        const int32_t k0 = ni.x, k1 = ni.y, p0 = k0 >> 1;
+        double ks[SUPP ? 2 * FP : 1];   // the loaded pairs' sums, for gsup (NW = 1)
             // anchored sums of source q (records plus the batch's earlier
             // events of q): K_q(t_i) = e^{-beta u_i} s0
             auto sums_a = [&](int32_t q, double& s0, double& s1) {
@@ -495,12 +502,24 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
                     return s0;
                 };
 #pragma unroll
-                for (int j = 0; j < FWW; ++j)
-                    if (k0 + NW * j + wv < k1) {
-                        const double v = terma(qc0[j], qa0[j]);
-                        if (SUPP) ks[j] = v;
+                for (int j = 0; j < FP; ++j) {
+                    const int32_t kb = 2 * (p0 + NW * j + wv);
+                    if (kb < k1) {
+                        if (kb >= k0) {
+                            const double v = terma(pr0[j].x, __int_as_float(pr0[j].y));
+                            if (SUPP) ks[2 * j] = v;
+                        }
+                        if (kb + 1 < k1) {
+                            const double v = terma(pr0[j].z, __int_as_float(pr0[j].w));
+                            if (SUPP) ks[2 * j + 1] = v;
+                        }
                     }
-                for (int32_t k = k0 + FW + wv; k < k1; k += NW) terma(csr_col[k], csr_val[k]);
+                }
+                for (int32_t kb = 2 * (p0 + NW * FP + wv); kb < k1; kb += 2 * NW) {
+                    const int4 e = cv4[kb >> 1];
+                    terma(e.x, __int_as_float(e.y));
+                    if (kb + 1 < k1) terma(e.z, __int_as_float(e.w));
+                }
             } else {
             auto term = [&](int32_t q, float av) -> double {
                 double Kv, Jv;
@@ -510,12 +529,24 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
                 return Kv;
             };
 #pragma unroll
-            for (int j = 0; j < FWW; ++j)
-                if (k0 + NW * j + wv < k1) {
-                    const double v = term(qc0[j], qa0[j]);
-                    if (SUPP) ks[j] = v;
+            for (int j = 0; j < FP; ++j) {
+                const int32_t kb = 2 * (p0 + NW * j + wv);
+                if (kb < k1) {
+                    if (kb >= k0) {
+                        const double v = term(pr0[j].x, __int_as_float(pr0[j].y));
+                        if (SUPP) ks[2 * j] = v;
+                    }
+                    if (kb + 1 < k1) {
+                        const double v = term(pr0[j].z, __int_as_float(pr0[j].w));
+                        if (SUPP) ks[2 * j + 1] = v;
+                    }
                 }
-            for (int32_t k = k0 + FW + wv; k < k1; k += NW) term(csr_col[k], csr_val[k]);
+            }
+            for (int32_t kb = 2 * (p0 + NW * FP + wv); kb < k1; kb += 2 * NW) {
+                const int4 e = cv4[kb >> 1];
+                term(e.x, __int_as_float(e.y));
+                if (kb + 1 < k1) term(e.z, __int_as_float(e.w));
+            }
             }
         if (NW > 1) {
             // the other waves' partial sums to the first, added in wave order
@@ -561,18 +592,20 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
             }
             if (SUPP) {
                 // beta w_i K_q(t_i) for each nonzero (m_i, q); the sums past
-                // the first FW nonzeros are formed again
+                // the loaded pairs are formed again
                 const double bw = bet * w * ei;
                 double* gs = gsup + (int64_t)(s & cmask) * M * M;
 #pragma unroll
-                for (int j = 0; j < FW; ++j)
-                    if (k0 + j < k1) unsafeAtomicAdd(&gs[k0 + j], bw * ks[j]);
-                for (int32_t k = k0 + FW; k < k1; ++k) {
+                for (int j = 0; j < 2 * FP; ++j) {
+                    const int32_t k = 2 * p0 + j;
+                    if (k >= k0 && k < k1) unsafeAtomicAdd(&gs[k], bw * ks[j]);
+                }
+                for (int32_t k = 2 * (p0 + FP); k < k1; ++k) {
                     double v, unused;
                     if (anch)
-                        sums_a(csr_col[k], v, unused);
+                        sums_a(csr_cv[k].x, v, unused);
                     else
-                        sums_w(csr_col[k], v, unused);
+                        sums_w(csr_cv[k].x, v, unused);
                     unsafeAtomicAdd(&gs[k], bw * v);
                 }
             }
@@ -628,10 +661,7 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
         n0 = n1;
         n1 = n2;
 #pragma unroll
-        for (int j = 0; j < FWW; ++j) {
-            qc0[j] = qc1[j];
-            qa0[j] = qa1[j];
-        }
+        for (int j = 0; j < FP; ++j) pr0[j] = pr1[j];
     }
     if (X.bcnt) {
         __syncthreads();
@@ -797,7 +827,7 @@ __global__ __launch_bounds__(256) void large_final(int32_t M, int32_t ER, int32_
 // after large_final zeroed g_alpha
 __global__ __launch_bounds__(64) void large_sup_scatter(int32_t M, int32_t ncopy,
                                                         const int32_t* __restrict__ csr_ptr,
-                                                        const int32_t* __restrict__ csr_col,
+                                                        const int2* __restrict__ csr_cv,
                                                         const double* __restrict__ gsup,
                                                         const double* __restrict__ cpart,
                                                         double* __restrict__ g_alpha) {
@@ -805,7 +835,7 @@ __global__ __launch_bounds__(64) void large_sup_scatter(int32_t M, int32_t ncopy
     const int64_t MM = (int64_t)M * M;
     const int32_t k1 = csr_ptr[p + 1];
     for (int32_t k = csr_ptr[p] + (int32_t)threadIdx.x; k < k1; k += 64) {
-        const int32_t q = csr_col[k];
+        const int32_t q = csr_cv[k].x;
         double g = 0.0;
         for (int32_t c = 0; c < ncopy; ++c) g += gsup[c * MM + k];
         g_alpha[(int64_t)p * M + q] = g - cpart[q];
@@ -891,8 +921,7 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
     const int64_t M = A.M, MM = M * M, K = A.K;
     Carve c(ws, ws_bytes);
     A.csr_ptr = c.take<int32_t>(K * (M + 1));
-    A.csr_col = c.take<int32_t>(K * MM);
-    A.csr_val = c.take<float>(K * MM);
+    A.csr_cv = c.take<int2>(K * cv_stride(MM));
     A.colsum = c.take<float>(K * M);
     if (K > 1) {
         A.rk = c.take<double>((size_t)K * A.CH);
@@ -918,8 +947,7 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
     A.ll_scratch = c.take<double>(1);
     if (A.per_target) {
         A.csc_ptr = c.take<int32_t>(M + 1);
-        A.csc_row = c.take<int32_t>(MM);
-        A.csc_val = c.take<float>(MM);
+        A.csc_cv = c.take<int2>(MM);
         A.ebseg = c.take<double>((size_t)A.nseg * M);
         A.ebacc = c.take<double>(M);
         if (grad) {
@@ -1022,11 +1050,10 @@ hawkes_status allow_lds(const void* kernel, size_t bytes, bool with_static) {
     return HAWKES_OK;
 }
 
-void large_build_index(int32_t M, const float* alpha, int trans, int32_t* ptr, int32_t* idx, float* val,
-                       hipStream_t st) {
+void large_build_index(int32_t M, const float* alpha, int trans, int32_t* ptr, int2* cv, hipStream_t st) {
     hipLaunchKernelGGL(large_rowcount, dim3(M), dim3(64), 0, st, M, alpha, ptr, trans);
     hipLaunchKernelGGL(large_csr_scan, dim3(1), dim3(1024), 0, st, M, ptr);
-    hipLaunchKernelGGL(large_csr_fill, dim3(M), dim3(64), 0, st, M, alpha, ptr, idx, val, trans);
+    hipLaunchKernelGGL(large_csr_fill, dim3(M), dim3(64), 0, st, M, alpha, ptr, cv, trans);
 }
 
 void large_scan(LargeArgs& A, int32_t nseg, const float* beta_pt, hipStream_t st, bool apply) {
@@ -1082,7 +1109,7 @@ static hawkes_status run_large_multi(LargeArgs& A, hipStream_t st) {
         int32_t* pk = A.csr_ptr + (int64_t)k * (M + 1);
         hipLaunchKernelGGL(large_colsum, dim3((unsigned)((M + 63) / 64)), dim3(1024), 0, st, M, ak,
                            A.colsum + (int64_t)k * M);
-        large_build_index(M, ak, 0, pk, A.csr_col + k * MM, A.csr_val + k * MM, st);
+        large_build_index(M, ak, 0, pk, A.csr_cv + k * cv_stride(MM), st);
         hipLaunchKernelGGL(large_node_info, dim3(gM), dim3(256), 0, st, M, pk, A.mu, A.colsum + (int64_t)k * M,
                            A.node_info + (int64_t)k * M);
     }
@@ -1117,13 +1144,13 @@ static hawkes_status run_large_multi(LargeArgs& A, hipStream_t st) {
             if (A.grad)
                 hipLaunchKernelGGL((large_forward<true, false, false, HK_FWW, true>), dim3(nseg), dim3(64 * HK_FWW),
                                    lds_fwd, st, c0, c1, M, A.T, A.t, A.marks, A.mu, B.beta,
-                                   A.node_info + (int64_t)k * M, A.csr_col + k * MM, A.csr_val + k * MM, B.carry_seg,
+                                   A.node_info + (int64_t)k * M, A.csr_cv + k * cv_stride(MM), B.carry_seg,
                                    A.seg_part, A.wchunk, (float*)nullptr, (double*)nullptr, 0,
                                    A.rk + (int64_t)k * A.CH, A.dk + (int64_t)k * A.CH, FwdExtra{});
             else
                 hipLaunchKernelGGL((large_forward<false, false, false, HK_FWW, true>), dim3(nseg), dim3(64 * HK_FWW),
                                    lds_fwd, st, c0, c1, M, A.T, A.t, A.marks, A.mu, B.beta,
-                                   A.node_info + (int64_t)k * M, A.csr_col + k * MM, A.csr_val + k * MM, B.carry_seg,
+                                   A.node_info + (int64_t)k * M, A.csr_cv + k * cv_stride(MM), B.carry_seg,
                                    A.seg_part, A.wchunk, (float*)nullptr, (double*)nullptr, 0,
                                    A.rk + (int64_t)k * A.CH, (double*)nullptr, FwdExtra{});
         }
@@ -1226,7 +1253,7 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
         hipLaunchKernelGGL(fill_d, dim3(64), dim3(256), 0, st, A.cpart_, (int64_t)A.NRUN * M, 0.0);
     }
     hipLaunchKernelGGL(large_colsum, dim3((unsigned)((M + 63) / 64)), dim3(1024), 0, st, M, A.alpha, A.colsum);
-    large_build_index(M, A.alpha, 0, A.csr_ptr, A.csr_col, A.csr_val, st);
+    large_build_index(M, A.alpha, 0, A.csr_ptr, A.csr_cv, st);
     hipLaunchKernelGGL(large_node_info, dim3(gM), dim3(256), 0, st, M, A.csr_ptr, A.mu, A.colsum, A.node_info);
     for (int64_t ch = 0; ch < A.nchunks; ++ch) {
         const int64_t c0 = ch * A.CH;
@@ -1245,25 +1272,25 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
             TimedScope ts(1, st);
             if (sup)
                 hipLaunchKernelGGL((large_forward<true, false, true, 1>), dim3(nseg), dim3(64), lds_fwdc, st, c0, c1,
-                                   M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
+                                   M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_cv,
                                    A.carry_seg, A.seg_part, A.wchunk, (float*)nullptr, A.gsup, ncopy - 1,
                                    (double*)nullptr, (double*)nullptr, X);
             else if (A.grad)
                 hipLaunchKernelGGL((large_forward<true, false, false, HK_FWW>), dim3(nseg), dim3(64 * HK_FWW), lds_fwdc,
                                    st, c0, c1,
-                                   M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
+                                   M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_cv,
                                    A.carry_seg, A.seg_part, A.wchunk, (float*)nullptr, (double*)nullptr, 0,
                                    (double*)nullptr, (double*)nullptr, X);
             else if (A.lambda_out)
                 hipLaunchKernelGGL((large_forward<false, true, false, HK_FWW>), dim3(nseg), dim3(64 * HK_FWW), lds_fwd,
                                    st, c0, c1,
-                                   M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
+                                   M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_cv,
                                    A.carry_seg, A.seg_part, A.wchunk, A.lambda_out, (double*)nullptr, 0,
                                    (double*)nullptr, (double*)nullptr, X);
             else
                 hipLaunchKernelGGL((large_forward<false, false, false, HK_FWW>), dim3(nseg), dim3(64 * HK_FWW), lds_fwd,
                                    st, c0, c1,
-                                   M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_col, A.csr_val,
+                                   M, A.T, A.t, A.marks, A.mu, A.beta, A.node_info, A.csr_cv,
                                    A.carry_seg, A.seg_part, A.wchunk, (float*)nullptr, (double*)nullptr, 0,
                                    (double*)nullptr, (double*)nullptr, X);
         }
@@ -1285,7 +1312,7 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
                        A.acc, A.gpart, A.spart, A.cpart_, A.loglik, A.g_mu, A.g_alpha, A.g_beta, A.grad ? 1 : 0,
                        sup ? 1 : 0, 1, 0);
     if (sup && A.g_alpha)
-        hipLaunchKernelGGL(large_sup_scatter, dim3((unsigned)M), dim3(64), 0, st, M, ncopy, A.csr_ptr, A.csr_col,
+        hipLaunchKernelGGL(large_sup_scatter, dim3((unsigned)M), dim3(64), 0, st, M, ncopy, A.csr_ptr, A.csr_cv,
                            A.gsup, A.cpart_, A.g_alpha);
     return hipGetLastError() == hipSuccess ? HAWKES_OK : HAWKES_EDEVICE;
 }

@@ -72,8 +72,7 @@ __device__ __forceinline__ double pt_rdl_d(double v, int k) {
 __global__ __launch_bounds__(64) void pt_seg_agg(int64_t c0, int64_t c1, int32_t M, double T,
                                                  const double* __restrict__ t, const int32_t* __restrict__ marks,
                                                  const float* __restrict__ beta, const int32_t* __restrict__ csc_ptr,
-                                                 const int32_t* __restrict__ csc_row,
-                                                 const float* __restrict__ csc_val, double* __restrict__ agg,
+                                                 const int2* __restrict__ csc_cv, double* __restrict__ agg,
                                                  double* __restrict__ seg_span, double* __restrict__ ebseg,
                                                  double* __restrict__ seg_part) {
     extern __shared__ double lds[];
@@ -101,8 +100,9 @@ __global__ __launch_bounds__(64) void pt_seg_agg(int64_t c0, int64_t c1, int32_t
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
                     const int32_t k = kb + j < k1 ? kb + j : k1 - 1;
-                    pv[j] = csc_row[k];
-                    av[j] = csc_val[k];
+                    const int2 e = csc_cv[k];
+                    pv[j] = e.x;
+                    av[j] = __int_as_float(e.y);
                 }
 #pragma unroll
                 for (int j = 0; j < 8; ++j) bv[j] = beta[pv[j]];
@@ -148,8 +148,7 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
                                                  const double* __restrict__ t, const int32_t* __restrict__ marks,
                                                  const float* __restrict__ mu, const float* __restrict__ beta,
                                                  const int32_t* __restrict__ csc_ptr,
-                                                 const int32_t* __restrict__ csc_row,
-                                                 const float* __restrict__ csc_val,
+                                                 const int2* __restrict__ csc_cv,
                                                  const double* __restrict__ carry_seg, double* __restrict__ seg_part,
                                                  double* __restrict__ ebseg, float* __restrict__ wv,
                                                  float* __restrict__ lambda_out) {
@@ -207,9 +206,10 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
                 const bool mine = lane >= k && lane < k2;
                 if (mine && cn <= 32) {
                     for (int32_t j = 0; j < cn; ++j) {
-                        const int32_t pr = csc_row[cb + j];
+                        const int2 e = csc_cv[cb + j];
+                        const int32_t pr = e.x;
                         st_row[off - o0 + j] = pr;
-                        st_val[off - o0 + j] = csc_val[cb + j];
+                        st_val[off - o0 + j] = __int_as_float(e.y);
                         st_bet[off - o0 + j] = beta[pr];
                     }
                 }
@@ -219,9 +219,10 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
                     big &= big - 1;
                     const int32_t nk = pt_rdl(cn, kk), ok = pt_rdl(off, kk) - o0, bk = pt_rdl(cb, kk);
                     for (int32_t j = lane; j < nk; j += 64) {
-                        const int32_t pr = csc_row[bk + j];
+                        const int2 e = csc_cv[bk + j];
+                        const int32_t pr = e.x;
                         st_row[ok + j] = pr;
-                        st_val[ok + j] = csc_val[bk + j];
+                        st_val[ok + j] = __int_as_float(e.y);
                         st_bet[ok + j] = beta[pr];
                     }
                 }
@@ -252,8 +253,9 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
                             av = st_val[ok + j];
                             bt = st_bet[ok + j];
                         } else {
-                            tp = csc_row[cbk + j];
-                            av = csc_val[cbk + j];
+                            const int2 e = csc_cv[cbk + j];
+                            tp = e.x;
+                            av = __int_as_float(e.y);
                             bt = beta[tp];
                         }
                         const double dd = ti - rtau[tp];
@@ -664,7 +666,7 @@ hawkes_status run_large_pt(LargeArgs& A, hipStream_t st) {
         fill(A.spart, (int64_t)A.ER * M, 0.0);
         fill(A.cpart_, (int64_t)A.ER * M, 0.0);
     }
-    large_build_index(M, A.alpha, 1, A.csc_ptr, A.csc_row, A.csc_val, st);
+    large_build_index(M, A.alpha, 1, A.csc_ptr, A.csc_cv, st);
     const int64_t M2 = 2 * (int64_t)M;
     auto chunk_range = [&](int64_t ch, int64_t& c0, int64_t& c1) -> int32_t {
         c0 = ch * A.CH;
@@ -677,7 +679,7 @@ hawkes_status run_large_pt(LargeArgs& A, hipStream_t st) {
         {
             TimedScope ts(2, st);
             hipLaunchKernelGGL(pt_seg_agg, dim3(nseg), dim3(64), lds_agg, st, c0, c1, M, A.T, A.t, A.marks, A.beta,
-                               A.csc_ptr, A.csc_row, A.csc_val, A.agg, A.seg_span, A.ebseg, A.seg_part);
+                               A.csc_ptr, A.csc_cv, A.agg, A.seg_span, A.ebseg, A.seg_part);
         }
         TimedScope ts(3, st);
         large_scan(A, nseg, A.beta, st);
@@ -688,15 +690,15 @@ hawkes_status run_large_pt(LargeArgs& A, hipStream_t st) {
             TimedScope ts(1, st);
             if (A.grad)
                 hipLaunchKernelGGL((pt_forward<true, false>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1, M, A.T, A.t,
-                                   A.marks, A.mu, A.beta, A.csc_ptr, A.csc_row, A.csc_val, A.carry_seg, A.seg_part,
+                                   A.marks, A.mu, A.beta, A.csc_ptr, A.csc_cv, A.carry_seg, A.seg_part,
                                    A.ebseg, A.wv, (float*)nullptr);
             else if (A.lambda_out)
                 hipLaunchKernelGGL((pt_forward<false, true>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1, M, A.T, A.t,
-                                   A.marks, A.mu, A.beta, A.csc_ptr, A.csc_row, A.csc_val, A.carry_seg, A.seg_part,
+                                   A.marks, A.mu, A.beta, A.csc_ptr, A.csc_cv, A.carry_seg, A.seg_part,
                                    A.ebseg, (float*)nullptr, A.lambda_out);
             else
                 hipLaunchKernelGGL((pt_forward<false, false>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1, M, A.T,
-                                   A.t, A.marks, A.mu, A.beta, A.csc_ptr, A.csc_row, A.csc_val, A.carry_seg,
+                                   A.t, A.marks, A.mu, A.beta, A.csc_ptr, A.csc_cv, A.carry_seg,
                                    A.seg_part, A.ebseg, (float*)nullptr, (float*)nullptr);
         }
         large_chunk_acc_launch(nseg, 4, A.seg_part, A.acc, st);

@@ -95,15 +95,21 @@ def test_tuning_round_trip_and_validation(H):
 
 def test_tuning_changes_the_workspace_layout(H):
     # the workspace follows the tuning (the dense kernel's checkpoint slots
-    # hold 64 x cols + 104 words; the small engine's items depend on their
-    # length), and zero restores the library's rule
+    # hold 64 x cols + 104 words, its partials ranges x M^2 float64; the
+    # small engine's items depend on their length), and zero restores the
+    # library's rule
     try:
         base = H.workspace_bytes(3_000_000, 1000, grad=True)
-        H.set_tuning(dense_cols=64)
-        narrow = H.workspace_bytes(3_000_000, 1000, grad=True)
         H.set_tuning(dense_cols=256)
+        assert H.workspace_bytes(3_000_000, 1000, grad=True) == base   # the rule's columns at M = 1000
+        H.set_tuning(dense_cols=64, dense_ranges=16, dense_rows=16)
+        narrow = H.workspace_bytes(3_000_000, 1000, grad=True)
+        H.set_tuning(dense_cols=256, dense_ranges=16, dense_rows=16)
         wide = H.workspace_bytes(3_000_000, 1000, grad=True)
-        assert narrow < wide and wide == base
+        assert narrow != wide   # same partials, slots per 64- or 256-column block
+        H.set_tuning(dense_cols=256, dense_ranges=4, dense_rows=16)
+        few = H.workspace_bytes(3_000_000, 1000, grad=True)
+        assert wide - few == 12 * 1000 * 1000 * 8   # 12 fewer M x M float64 partials
         H.set_tuning()
         s0 = H.workspace_bytes(200_000, 5, grad=True)
         H.set_tuning(item_log2=8)
