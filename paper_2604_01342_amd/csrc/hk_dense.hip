@@ -48,6 +48,10 @@
 
 namespace hk {
 
+#ifndef HK_CKW
+#define HK_CKW 4   // waves per checkpoint workgroup (dense_ck)
+#endif
+
 // Checkpoint slots: window w (groups NGW w to NGW w + NGW - 1) of (column
 // block sb, run r) uses slot (P0 >> log2(64 NGW)) + 2 (sb nrun + r) + w,
 // with P0 the position of the run's first record in the column block's
@@ -79,44 +83,61 @@ struct Slot {
     static_assert(SIZE == HK_SLOT_WORDS(CPL, NGW), "slot layout");
 };
 
-// One wave per (column block, run), in two phases.  (1) Scan the run's marks
-// (several batches of 64 in flight) and compact the keys of the column
-// block's events, in index order, into LDS.  (2) For every group of 64 keys
-// (times and weights loaded three groups ahead): at a window's first group
-// write the checkpoint, write the group's records into the window's slot
-// (and, at its last group, the header), then fold the group into the
-// state.  Runs r
-// with the same r / 8 share an XCD (their column blocks read the same
-// events).  runinfo[sb][r] = (first slot, groups, P0, P1), P0..P1 the run's
-// positions in the column block's share of the DR-node partition.
-template <int CPL, int DRB, int NGW>
-__global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t M, int32_t NBC, int32_t NBO,
-                                               int32_t nrun, int32_t ckr, int32_t nseg, double T,
-                                               const double* __restrict__ t, const int32_t* __restrict__ marks,
-                                               const float* __restrict__ wchunk, const float* __restrict__ beta,
-                                               const double* __restrict__ carry_seg,
-                                               const double* __restrict__ gcarry,
-                                               const double* __restrict__ seg_offdec,
-                                               const int32_t* __restrict__ bo_off,
-                                               const int32_t* __restrict__ bo_base, double* __restrict__ kck,
-                                               int4* __restrict__ runinfo, double* __restrict__ spart,
-                                               double* __restrict__ cpart) {
+// One workgroup of NWC waves per (column block, run), in three phases.
+// (1) Wave v compacts the keys of the column block's events among its
+// quarter of the run's marks, in index order, into its own LDS region
+// (record e of the run, in index order, sits in the region of the wave
+// whose prefix of counts brackets e).  (2) In rounds of NWC groups of 64
+// records, wave v takes group NWC rho + v: it writes the group's records
+// into its window's slot (and the window's header at the window's last
+// group), and stages per record its column, weight, compensator term and
+// decay to the group's last record.  (3) After each round the state walks
+// the round's groups in order, waves 0 .. CPL - 1 holding 64 columns each:
+// a window's checkpoint at its first group, then the state decays to the
+// group's last record and adds the group's staged records of its columns,
+// as do the per-column sums of weights and compensator terms (so every sum
+// is formed in the order of a single walk, whatever the waves' timing).  Runs r with the same r / 8 share an XCD (their
+// column blocks read the same events).  runinfo[sb][r] = (first slot,
+// groups, P0, P1), P0..P1 the run's positions in the column block's share
+// of the DR-node partition.
+template <int CPL, int DRB, int NGW, int NWC>
+__global__ __launch_bounds__(64 * NWC) void dense_ck(int64_t c0, int32_t nev, int32_t M, int32_t NBC, int32_t NBO,
+                                                     int32_t nrun, int32_t ckr, int32_t nseg, double T,
+                                                     const double* __restrict__ t, const int32_t* __restrict__ marks,
+                                                     const float* __restrict__ wchunk, const float* __restrict__ beta,
+                                                     const double* __restrict__ carry_seg,
+                                                     const double* __restrict__ gcarry,
+                                                     const double* __restrict__ seg_offdec,
+                                                     const int32_t* __restrict__ bo_off,
+                                                     const int32_t* __restrict__ bo_base, double* __restrict__ kck,
+                                                     int4* __restrict__ runinfo, double* __restrict__ spart,
+                                                     double* __restrict__ cpart) {
     using S = Slot<CPL, NGW>;
     constexpr int W = S::W;
     constexpr int DR = 1 << DRB;
     constexpr int SH = CPL == 4 ? 8 : CPL == 2 ? 7 : 6;   // bits of the local mark in a record key
     constexpr int UB = 16;                 // batches of marks in flight
-    __shared__ double DL[W], SL[W], CL[W];
+    static_assert((HK_CKR * HK_SEG) % (64 * NWC) == 0, "whole batches per wave's region");
+    static_assert(NWC >= CPL, "a wave per 64 columns of the state");
+    __shared__ double SL[W], CL[W], DLw[CPL][64];
+    __shared__ double Fr[NWC], st_c[NWC][64];
+    __shared__ int32_t st_col[NWC][64];
+    __shared__ float st_w[NWC][64], st_f[NWC][64];
     __shared__ uint32_t keys[HK_CKR * HK_SEG];
-    const int lane = threadIdx.x;
+    __shared__ int32_t wcnt[NWC];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int32_t x = (int32_t)(blockIdx.x & 7u), grp = (int32_t)(blockIdx.x >> 3);
     const int32_t sb = grp % NBC;
     const int32_t r = (grp / NBC) * 8 + x;
     const int32_t sA = r * ckr;
-    if (sA >= nseg) return;
+    if (sA >= nseg) return;   // the whole workgroup
     const int32_t sB = sA + ckr < nseg ? sA + ckr : nseg;
-#pragma unroll
-    for (int j = 0; j < CPL; ++j) DL[j * 64 + lane] = SL[j * 64 + lane] = CL[j * 64 + lane] = 0.0;
+    for (int i = threadIdx.x; i < W; i += 64 * NWC) {
+        SL[i] = 0.0;
+        CL[i] = 0.0;
+        (&DLw[0][0])[i] = 0.0;
+    }
     const int32_t a = sA * HK_SEG;
     const int32_t b = sB * HK_SEG < nev ? sB * HK_SEG : nev;
     const int32_t s0 = sb * W;
@@ -130,16 +151,22 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
     }
     const int32_t ng = (P1 - P0 + 63) >> 6;
     const int32_t slot0 = (P0 >> (NGW == 2 ? 7 : 6)) + 2 * (sb * nrun + r);   // one slot per window
-    if (lane == 0) runinfo[(int64_t)sb * nrun + r] = make_int4(slot0, ng, P0, P1);
+    if (threadIdx.x == 0) runinfo[(int64_t)sb * nrun + r] = make_int4(slot0, ng, P0, P1);
 
-    // (1) compaction (at most ckr * HK_SEG keys)
+    // (1) compaction: wave v takes the run's events [a + v PS, a + (v + 1) PS)
+    // (PS a multiple of 64; the regions fit the key array since the run has
+    // at most HK_CKR * HK_SEG events)
+    const int32_t PS = ((b - a + 64 * NWC - 1) / (64 * NWC)) * 64;
+    const int32_t pa = a + wv * PS;
+    const int32_t pb = pa + PS < b ? pa + PS : b;
+    uint32_t* kw = keys + wv * PS;
     int cnt = 0;
-    for (int32_t base = a; base < b; base += 64 * UB) {
+    for (int32_t base = pa; base < pb; base += 64 * UB) {
         int mk[UB];
 #pragma unroll
         for (int u = 0; u < UB; ++u) {
             const int32_t i = base + 64 * u + lane;
-            mk[u] = i < b ? clamp_mark(marks[c0 + i], M) : -1;
+            mk[u] = i < pb ? clamp_mark(marks[c0 + i], M) : -1;
         }
 #pragma unroll
         for (int u = 0; u < UB; ++u) {
@@ -148,53 +175,68 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
             const uint64_t bal = __ballot(sel);
             const int pos = cnt + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-            if (sel) keys[pos] = ((uint32_t)i << SH) | (uint32_t)(mk[u] - s0);
+            if (sel) kw[pos] = ((uint32_t)i << SH) | (uint32_t)(mk[u] - s0);
             cnt += __builtin_popcountll(bal);
         }
     }
+    if (lane == 0) wcnt[wv] = cnt;
     __syncthreads();
-
-    // (2) groups
+    int32_t pre[NWC + 1];   // wave-uniform
+    pre[0] = 0;
+#pragma unroll
+    for (int v = 0; v < NWC; ++v) pre[v + 1] = pre[v] + wcnt[v];
+    const int32_t cntT = pre[NWC];
+    // LDS position of record e (0 <= e < cntT)
+    auto kpos = [&](int32_t e) -> int32_t {
+        int32_t pos = e;
+#pragma unroll
+        for (int v = 1; v < NWC; ++v)
+            if (e >= pre[v]) pos = v * PS + (e - pre[v]);
+        return pos;
+    };
     const double bet = (double)beta[0];
     const double bl2 = bet * HK_LOG2E;   // decays as powers of 2
-    double K[CPL];
-#pragma unroll
-    for (int j = 0; j < CPL; ++j) {
-        const int32_t col = s0 + j * 64 + lane;
-        K[j] = col < M ? carry_seg[(int64_t)sA * 2 * M + col] : 0.0;
-        // carry_seg as in-group prefixes (gcarry given): add the scan group's
-        // carry moved to the run's first segment
-        if (gcarry && col < M)
-            K[j] = __builtin_fma(seg_offdec[sA], gcarry[(int64_t)(sA / HK_SG) * 2 * M + col], K[j]);
+    const double tau0 = c0 + a > 0 ? t[c0 + a - 1] : t[c0];
+    // the time of record e (wave-uniform e), or tau0 before the first
+    auto rec_t = [&](int32_t e) -> double { return e < 0 ? tau0 : t[c0 + (int32_t)(keys[kpos(e)] >> SH)]; };
+    // the state: wave v < CPL holds columns s0 + 64 v + lane
+    double K = 0.0;
+    {
+        const int32_t col = s0 + wv * 64 + lane;
+        if (wv < CPL && col < M) {
+            K = carry_seg[(int64_t)sA * 2 * M + col];
+            // carry_seg as in-group prefixes (gcarry given): add the scan
+            // group's carry moved to the run's first segment
+            if (gcarry) K = __builtin_fma(seg_offdec[sA], gcarry[(int64_t)(sA / HK_SG) * 2 * M + col], K);
+        }
     }
-    double tau = c0 + a > 0 ? t[c0 + a - 1] : t[c0];
+    // group g's records, with the state's time at the group's start (the
+    // time of the record before it) and the anchor of its window (the state's
+    // time at the window's first group), loaded a round ahead
     struct Rec {
         uint32_t key;
         double t;
         float w;
+        double tg, tw;
     };
     auto load = [&](Rec& q, int32_t g) {
         const int32_t e = 64 * g + lane;
-        q.key = e < cnt ? keys[e] : 0xffffffffu;
-        const int32_t i = e < cnt ? (int32_t)(q.key >> SH) : a;
+        q.key = e < cntT ? keys[kpos(e)] : 0xffffffffu;
+        const int32_t i = e < cntT ? (int32_t)(q.key >> SH) : a;
         q.t = t[c0 + i];
         q.w = wchunk[i];
+        q.tg = rec_t(64 * g - 1);
+        q.tw = g % NGW == 0 ? q.tg : rec_t(64 * NGW * (g / NGW) - 1);
     };
-    // a window's state (at its first group) and header: anchor time, time
-    // and event index of the window's last record (after the last window:
-    // the anchor and the run's last event), record count, next slot (-1:
-    // none), run, wide flag, index of the 65th record
-    double tau_w = tau;   // the current window's anchor (state time at its first group)
-    auto put_k = [&](int32_t w) {
-        double* out = kck + (int64_t)(slot0 + w) * S::SIZE;
-#pragma unroll
-        for (int j = 0; j < CPL; ++j) out[j * 64 + lane] = K[j];
-        tau_w = tau;
-    };
-    auto put_hdr = [&](int32_t w, double tcl, int32_t hi, int32_t nv, int32_t nxt, int32_t first1) {
+    const double tl = cntT > 0 ? rec_t(cntT - 1) : tau0;   // the state's time after the last group
+    // a window's header: anchor time, time and event index of the window's
+    // last record (after the last window: the anchor and the run's last
+    // event), record count, next slot (-1: none), run, wide flag, index of
+    // the 65th record
+    auto put_hdr = [&](int32_t w, double tw, double tcl, int32_t hi, int32_t nv, int32_t nxt, int32_t first1) {
         double* out = kck + (int64_t)(slot0 + w) * S::SIZE;
         if (lane == 0) {
-            out[S::TAU] = tau_w;
+            out[S::TAU] = tw;
             out[S::TAU + 1] = tcl;
             int32_t* h = reinterpret_cast<int32_t*>(out + S::TAU + 2);
             h[0] = hi;
@@ -203,107 +245,103 @@ __global__ __launch_bounds__(64) void dense_ck(int64_t c0, int32_t nev, int32_t 
             h[3] = r;
             // a window with column records spans at most to its last record
             // (own events of index <= hi are not later): wide or not is known
-            h[4] = nv > 0 && !(bet * (tcl - tau_w) <= HK_WIDE);
+            h[4] = nv > 0 && !(bet * (tcl - tw) <= HK_WIDE);
             h[5] = first1;
         }
     };
-    // group g with records q: checkpoint, records, then the state moves past
-    // the group
-    auto emit = [&](const Rec& q, int32_t g) {
-        const int rem = cnt - 64 * g;
-        const int nv = rem < 64 ? rem : 64;
-        const bool v = lane < nv;
-        const double tn = rl_d(q.t, nv - 1);
-        const int32_t w = g / NGW, half = (g % NGW) * 64;
-        if (half == 0) put_k(w);
-        if (half == 64 * (NGW - 1) || g + 1 == ng)
-            put_hdr(w, tn, (int32_t)((uint32_t)rl_i((int)q.key, nv - 1) >> SH), half + nv, slot0 + w + 1,
-                    half != 0 ? (int32_t)((uint32_t)rl_i((int)q.key, 0) >> SH) : 0x7fffffff);
-        double* out = kck + (int64_t)(slot0 + w) * S::SIZE;
-        // The record's lane in the slot.  The dense kernel adds each own
-        // event's pair terms with one LDS atomic over a group's 64 records,
-        // at the records' columns of one tile row; the LDS serves 16 lanes
-        // of 8-byte words a cycle from 16 banks (column mod 16), so records
-        // sharing a bank in one quarter-wave serialise.  Records sorted by
-        // bank (past the records: last) and dealt round-robin over the four
-        // quarter-waves share a bank in a quarter only when more than four
-        // have it.  Nothing else depends on the order (each lane carries its
-        // record's index, column, time and factor).
-        int pos;
-        {
-            // rank of the record in (bank, lane) order from bit-sliced
-            // ballots: from the top bit down, the lanes that agree with
-            // this lane's bank so far and have a 0 where it has a 1 are
-            // smaller; the lanes left at the end share its bank
-            const int bank = v ? (int)(q.key & 15u) : 16;
-            const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-            uint64_t eq = ~0ull;
-            int before = 0;
+    Rec q;
+    if (wv < ng) load(q, wv);
+    for (int32_t g0 = 0; g0 < ng; g0 += NWC) {
+        const int32_t g = g0 + wv;
+        Rec qn;
+        if (g + NWC < ng) load(qn, g + NWC);   // the next round's group in flight
+        if (g < ng) {
+            const int rem = cntT - 64 * g;
+            const int nv = rem < 64 ? rem : 64;
+            const bool v = lane < nv;
+            const double tn = rl_d(q.t, nv - 1);
+            const double tg = q.tg, tw = q.tw;
+            const int32_t w = g / NGW, half = (g % NGW) * 64;
+            if (half == 64 * (NGW - 1) || g + 1 == ng)
+                put_hdr(w, tw, tn, (int32_t)((uint32_t)rl_i((int)q.key, nv - 1) >> SH), half + nv, slot0 + w + 1,
+                        half != 0 ? (int32_t)((uint32_t)rl_i((int)q.key, 0) >> SH) : 0x7fffffff);
+            double* out = kck + (int64_t)(slot0 + w) * S::SIZE;
+            // The record's lane in the slot.  The dense kernel adds each own
+            // event's pair terms with one LDS atomic over a group's 64
+            // records, at the records' columns of one tile row; the LDS
+            // serves 16 lanes of 8-byte words a cycle from 16 banks (column
+            // mod 16), so records sharing a bank in one quarter-wave
+            // serialise.  Records sorted by bank (past the records: last)
+            // and dealt round-robin over the four quarter-waves share a
+            // bank in a quarter only when more than four have it.  Nothing
+            // else depends on the order (each lane carries its record's
+            // index, column, time and factor).
+            int pos;
+            {
+                // rank of the record in (bank, lane) order from bit-sliced
+                // ballots: from the top bit down, the lanes that agree with
+                // this lane's bank so far and have a 0 where it has a 1 are
+                // smaller; the lanes left at the end share its bank
+                const int bank = v ? (int)(q.key & 15u) : 16;
+                const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+                uint64_t eq = ~0ull;
+                int before = 0;
 #pragma unroll
-            for (int i = 4; i >= 0; --i) {
-                const uint64_t bi = __ballot((bank >> i) & 1);
-                const bool one = (bank >> i) & 1;
-                if (one) before += __builtin_popcountll(eq & ~bi);
-                eq &= one ? bi : ~bi;
+                for (int i = 4; i >= 0; --i) {
+                    const uint64_t bi = __ballot((bank >> i) & 1);
+                    const bool one = (bank >> i) & 1;
+                    if (one) before += __builtin_popcountll(eq & ~bi);
+                    eq &= one ? bi : ~bi;
+                }
+                const int sidx = before + __builtin_popcountll(eq & below);   // a permutation of 0..63
+                pos = (sidx & 3) * 16 + (sidx >> 2);
             }
-            const int sidx = before + __builtin_popcountll(eq & below);   // a permutation of 0..63
-            pos = (sidx & 3) * 16 + (sidx >> 2);
-        }
-        out[S::T + half + pos] = v ? q.t : 0.0;
-        reinterpret_cast<uint32_t*>(out + S::KEY)[half + pos] = q.key;
-        // the record's factor e^{beta (t_j - tau_w)} against the window's anchor
-        reinterpret_cast<float*>(out + S::BJ)[half + pos] = v ? exp2_f64arg((q.t - tau_w) * bl2) : 0.0f;
-        const double f = (double)exp2_f64arg((tau - tn) * bl2);
-#pragma unroll
-        for (int j = 0; j < CPL; ++j) K[j] *= f;
-        if (v) {
-            const int col = (int)(q.key & (uint32_t)(W - 1));
-            atomicAdd(&DL[col], (double)exp2_f64arg((q.t - tn) * bl2));
-            atomicAdd(&SL[col], (double)q.w);
-            atomicAdd(&CL[col], -expm1(-bet * (T - q.t)));
+            out[S::T + half + pos] = v ? q.t : 0.0;
+            reinterpret_cast<uint32_t*>(out + S::KEY)[half + pos] = q.key;
+            // the record's factor e^{beta (t_j - tau_w)} against the window's anchor
+            reinterpret_cast<float*>(out + S::BJ)[half + pos] = v ? exp2_f64arg((q.t - tw) * bl2) : 0.0f;
+            if (lane == 0) Fr[wv] = (double)exp2_f64arg((tg - tn) * bl2);
+            st_col[wv][lane] = v ? (int)(q.key & (uint32_t)(W - 1)) : -1;
+            st_w[wv][lane] = q.w;
+            st_f[wv][lane] = exp2_f64arg((q.t - tn) * bl2);
+            st_c[wv][lane] = -expm1(-bet * (T - q.t));
         }
         __syncthreads();
-#pragma unroll
-        for (int j = 0; j < CPL; ++j) {
-            K[j] += DL[j * 64 + lane];
-            DL[j * 64 + lane] = 0.0;
+        // (3) the state through the round's groups, in order
+        if (wv < CPL) {
+            for (int u = 0; u < NWC && g0 + u < ng; ++u) {
+                const int32_t gg = g0 + u;
+                if (gg % NGW == 0) kck[(int64_t)(slot0 + gg / NGW) * S::SIZE + wv * 64 + lane] = K;
+                K *= Fr[u];
+                const int col = st_col[u][lane];
+                if (col >= wv * 64 && col < wv * 64 + 64) {
+                    atomicAdd(&DLw[wv][col - wv * 64], (double)st_f[u][lane]);
+                    atomicAdd(&SL[col], (double)st_w[u][lane]);
+                    atomicAdd(&CL[col], st_c[u][lane]);
+                }
+                // the adds must land before the read below: an LDS read
+                // issued after an LDS atomic of the same wave can return the
+                // value from before it (lgkmcnt(0))
+                __builtin_amdgcn_s_waitcnt(0xc07f);
+                K += DLw[wv][lane];
+                DLw[wv][lane] = 0.0;
+            }
         }
-        tau = tn;
-    };
-    // records of four groups in flight (a group's wait then covers loads
-    // issued three groups earlier)
-    Rec r0, r1, r2, r3;
-    load(r0, 0);
-    load(r1, 1);
-    load(r2, 2);
-    int32_t g = 0;
-    while (g < ng) {
-        load(r3, g + 3);
-        emit(r0, g);
-        if (++g >= ng) break;
-        load(r0, g + 3);
-        emit(r1, g);
-        if (++g >= ng) break;
-        load(r1, g + 3);
-        emit(r2, g);
-        if (++g >= ng) break;
-        load(r2, g + 3);
-        emit(r3, g);
-        ++g;
+        __syncthreads();
+        q = qn;
     }
     // after the last group: the window up to the run's end, then the next
     // run's first slot (its P0 is this run's P1)
     const int32_t np = (ng + NGW - 1) / NGW;
-    put_k(np);
-    put_hdr(np, tau, sB * HK_SEG - 1, 0, sB < nseg ? (P1 >> (NGW == 2 ? 7 : 6)) + 2 * (sb * nrun + r + 1) : -1,
-            0x7fffffff);
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < CPL; ++j) {
-        const int32_t col = s0 + j * 64 + lane;
+    if (wv < CPL) kck[(int64_t)(slot0 + np) * S::SIZE + wv * 64 + lane] = K;
+    if (wv == 0)
+        put_hdr(np, tl, tl, sB * HK_SEG - 1, 0,
+                sB < nseg ? (P1 >> (NGW == 2 ? 7 : 6)) + 2 * (sb * nrun + r + 1) : -1, 0x7fffffff);
+    for (int i = threadIdx.x; i < W; i += 64 * NWC) {
+        const int32_t col = s0 + i;
         if (col < M) {
-            spart[(int64_t)r * M + col] += SL[j * 64 + lane];
-            cpart[(int64_t)r * M + col] += CL[j * 64 + lane];
+            spart[(int64_t)r * M + col] += SL[i];
+            cpart[(int64_t)r * M + col] += CL[i];
         }
     }
 }
@@ -945,7 +983,8 @@ static void dense_launch_t(LargeArgs& A, int64_t c0, int32_t nev, int32_t nseg, 
     {
         TimedScope tk(7, st);
         const unsigned nck = (unsigned)(((nrun_c + 7) / 8) * 8 * A.NBC);
-        hipLaunchKernelGGL((dense_ck<CPL, DRB, NGW>), dim3(nck), dim3(64), 0, st, c0, nev, A.M, A.NBC, A.NBO, A.NRUN,
+        hipLaunchKernelGGL((dense_ck<CPL, DRB, NGW, HK_CKW>), dim3(nck), dim3(64 * HK_CKW), 0, st, c0, nev, A.M, A.NBC,
+                           A.NBO, A.NRUN,
                            A.CKR, nseg, A.T, A.t, A.marks, A.wchunk, A.beta, A.carry_seg,
                            A.carry_prefix ? A.gcarry : (const double*)nullptr, A.seg_offdec, A.bo_off, A.bo_base,
                            A.kck, A.runinfo, A.spart, A.cpart_);
