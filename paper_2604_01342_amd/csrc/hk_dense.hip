@@ -621,10 +621,11 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
             if (n == 0 || q - qL < 64) break;
         }
         if (nown) {
-            // rank-1 update G += u K_g^T, then clear u (u is this wave's:
-            // its LDS operations complete in order, so only the compiler
-            // must not move them)
+            // rank-1 update G += u K_g^T, then clear u (u is this wave's;
+            // an LDS read can pass the wave's earlier LDS atomics, so they
+            // are waited for: lgkmcnt(0))
             __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_s_waitcnt(0xc07f);
             double u[DR];
 #pragma unroll
             for (int i = 0; i < DR; ++i) u[i] = UL[i];
@@ -928,9 +929,10 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(2))) v
         }
         if (nown) {
             // rank-1 update G += u K_g^T in float32, then clear u (u is this
-            // wave's: its LDS operations complete in order, so only the
-            // compiler must not move them)
+            // wave's; an LDS read can pass the wave's earlier LDS atomics, so
+            // they are waited for: lgkmcnt(0))
             __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_s_waitcnt(0xc07f);
             float kf[CPL];
 #pragma unroll
             for (int j = 0; j < CPL; ++j) kf[j] = (float)cur.K[j];
