@@ -319,12 +319,10 @@ __global__ __launch_bounds__(64 * NWC) void dense_ck(int64_t c0, int32_t nev, in
                     atomicAdd(&SL[col], (double)st_w[u][lane]);
                     atomicAdd(&CL[col], st_c[u][lane]);
                 }
-                // the adds must land before the read below: an LDS read
-                // issued after an LDS atomic of the same wave can return the
-                // value from before it (lgkmcnt(0))
-                __builtin_amdgcn_s_waitcnt(0xc07f);
+                lds_wait();   // the adds land before the read below
                 K += DLw[wv][lane];
                 DLw[wv][lane] = 0.0;
+                lds_wait();   // and the clear before the next group's adds
             }
         }
         __syncthreads();
@@ -622,10 +620,8 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
         }
         if (nown) {
             // rank-1 update G += u K_g^T, then clear u (u is this wave's;
-            // an LDS read can pass the wave's earlier LDS atomics, so they
-            // are waited for: lgkmcnt(0))
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_s_waitcnt(0xc07f);
+            // its atomics on u land before the reads)
+            lds_wait();
             double u[DR];
 #pragma unroll
             for (int i = 0; i < DR; ++i) u[i] = UL[i];
@@ -929,10 +925,8 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(2))) v
         }
         if (nown) {
             // rank-1 update G += u K_g^T in float32, then clear u (u is this
-            // wave's; an LDS read can pass the wave's earlier LDS atomics, so
-            // they are waited for: lgkmcnt(0))
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_s_waitcnt(0xc07f);
+            // wave's; its atomics on u land before the reads)
+            lds_wait();
             float kf[CPL];
 #pragma unroll
             for (int j = 0; j < CPL; ++j) kf[j] = (float)cur.K[j];

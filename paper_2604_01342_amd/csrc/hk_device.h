@@ -61,6 +61,16 @@ __device__ __forceinline__ double shfl_up_d(double v, int d) {
     return __shfl_up(v, d, HK_WAVE);
 }
 
+// Waits for this wave's outstanding LDS operations (lgkmcnt(0)); the
+// compiler fences keep LDS accesses from moving across it.  Needed where a
+// wave reads back what it has just written with LDS atomics: a read can
+// complete ahead of the same wave's earlier return-less LDS atomic.
+__device__ __forceinline__ void lds_wait() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 __device__ __forceinline__ int clamp_mark(int m, int M) {
     return m < 0 ? 0 : (m >= M ? M - 1 : m);
 }

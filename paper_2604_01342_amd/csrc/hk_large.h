@@ -74,7 +74,6 @@ struct LargeArgs {
     double* seg_part;     // [nseg][2 + 2K]
     double* acc;          // [2 + 2K] call-level sums: logsum, comp, E[K], gbeta[K]
     double* ll_scratch;   // [1] log-likelihood slot when the caller wants intensities only
-    int32_t* ctr;         // [2] completion counters (the partition scan's in [1]), zero between launches
     bool carry_prefix;    // carry_seg holds in-group prefixes (the scan's apply pass left out)
     double *gpart, *spart, *cpart_;  // [ER][M][M]; [ER][M] per target, [NRUN][M] shared decay
     double* gsup;         // [min(8, ER)][M*M] support-restricted first term of eq. 9 in CSR order (the
@@ -148,12 +147,10 @@ inline int64_t cv_stride(int64_t MM) { return (MM + 2) & ~(int64_t)1; }
 void large_scan(LargeArgs& A, int32_t nseg, const float* beta_pt, hipStream_t st, bool apply = true);
 void large_chunk_acc_launch(int32_t nseg, int32_t width, const double* seg_part, double* acc, hipStream_t st);
 void bucket_chunk(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, const float* wchunk, int bs, hipStream_t st);
-// counted: cnt already holds the counts (the forward pass made them);
-// done: a zeroed completion counter (the last block of the scan of the
-// counts forms the blocks' bases)
+// counted: cnt already holds the counts (the forward pass made them)
 void bucket_chunk_into(const LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, const float* wchunk, int bs,
                        int32_t* cnt, int32_t* off, int32_t* base, uint32_t* key, double* tt, float* ww,
-                       hipStream_t st, bool counted = false, int32_t* done = nullptr);
+                       hipStream_t st, bool counted = false);
 // ck_only: the checkpoint kernel alone (its per-column sums of dL/dmu and
 // the compensator), for the support-restricted gradient
 void large_dense_launch(LargeArgs& A, int64_t c0, int64_t c1, int32_t nseg, hipStream_t st, bool ck_only);

@@ -42,11 +42,6 @@ __global__ void fill_d(double* p, int64_t n, double v) {
         p[i] = v;
 }
 
-__global__ void fill_i(int32_t* p, int64_t n, int32_t v) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = v;
-}
-
 // colsum[q] = sum_p alpha[p][q]: a workgroup of 16 waves per 64 columns,
 // wave r sums rows r, r+16, ... (coalesced over q), then a fixed-order sum
 __global__ __launch_bounds__(1024) void large_colsum(int32_t M, const float* __restrict__ alpha,
@@ -943,7 +938,6 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
     A.carry_t = c.take<double>(1);
     A.seg_part = c.take<double>((size_t)A.nseg * (2 + 2 * K));
     A.acc = c.take<double>(2 + 2 * K);
-    A.ctr = c.take<int32_t>(2);
     A.ll_scratch = c.take<double>(1);
     if (A.per_target) {
         A.csc_ptr = c.take<int32_t>(M + 1);
@@ -1095,7 +1089,6 @@ static hawkes_status run_large_multi(LargeArgs& A, hipStream_t st) {
     const int32_t W = 2 + 2 * K;
     hipLaunchKernelGGL(fill_d, dim3(16), dim3(256), 0, st, A.carry, (int64_t)K * 2 * M, 0.0);
     hipLaunchKernelGGL(fill_d, dim3(1), dim3(64), 0, st, A.acc, (int64_t)W, 0.0);
-    hipLaunchKernelGGL(fill_i, dim3(1), dim3(64), 0, st, A.ctr, (int64_t)2, 0);
     if (A.grad) {
         const int64_t ng = (int64_t)K * A.ER * MM;
         hipLaunchKernelGGL(fill_d, dim3((unsigned)((ng + 255) / 256 < 65535 ? (ng + 255) / 256 : 65535)),
@@ -1174,7 +1167,7 @@ static hawkes_status run_large_multi(LargeArgs& A, hipStream_t st) {
             {
                 TimedScope tb(6, st);
                 bucket_chunk_into(A, c0, c1, nseg, A.wchunk, A.DRB, A.bo_cnt, A.bo_off, A.bo_base, A.bo_key, A.bo_t,
-                                  A.bo_w, st, false, A.ctr + 1);
+                                  A.bo_w, st, false);
             }
             for (int32_t k = 0; k < K; ++k) {
                 LargeArgs B = view(k);
@@ -1218,10 +1211,9 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
     // 32-bit byte offsets
     if (A.grad && (uint64_t)A.nslot * (uint64_t)HK_SLOT_WORDS(A.CPL, A.NGW) * 8u >= (1ull << 32))
         return HAWKES_EUNSUPPORTED;
-    // zero the carried state, accumulators and completion counters
+    // zero the carried state and accumulators
     hipLaunchKernelGGL(fill_d, dim3(1), dim3(256), 0, st, A.carry, (int64_t)2 * M, 0.0);
     hipLaunchKernelGGL(fill_d, dim3(1), dim3(64), 0, st, A.acc, (int64_t)4, 0.0);
-    hipLaunchKernelGGL(fill_i, dim3(1), dim3(64), 0, st, A.ctr, (int64_t)2, 0);
     // the forward pass adds the scan's group carries itself (the scan's
     // apply pass is left out) and counts the partition (by blocks of 2^DRB
     // nodes, when the gradient needs them and they fit its LDS).  Measured
@@ -1299,7 +1291,7 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
             {
                 TimedScope tb(6, st);
                 bucket_chunk_into(A, c0, c1, nseg, A.wchunk, A.DRB, A.bo_cnt, A.bo_off, A.bo_base, A.bo_key, A.bo_t,
-                                  A.bo_w, st, X.bcnt != nullptr, A.ctr + 1);
+                                  A.bo_w, st, X.bcnt != nullptr);
             }
             // support-restricted: only the checkpoint kernel's per-column
             // sums (dL/dmu, compensator) are needed

@@ -566,10 +566,8 @@ __global__ __launch_bounds__(64 * HK_DWP) void pt_dense(int64_t c0, int64_t c1, 
         if (sb == 0 && own) atomicAdd(&SL[pi], wi);
         if (rb == 0 && sl) atomicAdd(&NL[S.ck & 63u], 1.0);
         if (own) atomicAdd(&AL[pi], wi * (double)exp2_f64arg((tl - O.ct) * bo2));
-        // AL is this wave's; an LDS read can pass the wave's earlier LDS
-        // atomics, so they are waited for (lgkmcnt(0))
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_s_waitcnt(0xc07f);
+        // AL is this wave's; its atomics land before the read
+        lds_wait();
         Ah = __builtin_fma(Ah, (double)exp2_f64arg((tl - tw) * bp2), AL[lane]);
         __builtin_amdgcn_wave_barrier();
         AL[lane] = 0.0;
