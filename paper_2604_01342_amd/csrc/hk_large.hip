@@ -213,10 +213,18 @@ __global__ __launch_bounds__(256) void large_scan_local(int32_t nseg, int32_t M,
     // span) is summed by the threads q = u, u + M, ..: each sums the spans in
     // the same order as one serial pass would, so the values do not depend on
     // M, and the group's exps run side by side instead of one after another
+    if (q <= s1 - s0) {
+        // the group's spans, loaded together (not one dependent load per
+        // term of the sum)
+        double sp[HK_SG];
+#pragma unroll
+        for (int v = 0; v < HK_SG; ++v) sp[v] = seg_span[s0 + v < s1 ? s0 + v : s1 - 1];
     for (int32_t u = q; u <= s1 - s0; u += M) {
         const double b0 = (double)beta[0];
         double D = 0.0;
-        for (int32_t s = s0; s < s0 + u; ++s) D += seg_span[s];
+#pragma unroll
+        for (int v = 0; v < HK_SG; ++v)
+            if (v < u) D += sp[v];
         const double e = exp(-b0 * D);
         if (u < s1 - s0) {
             seg_off[s0 + u] = D;
@@ -225,6 +233,7 @@ __global__ __launch_bounds__(256) void large_scan_local(int32_t nseg, int32_t M,
             gspan[g] = D;
             gdec[g] = e;
         }
+    }
     }
     double K = 0.0, J = 0.0;
     const double bq = beta_pt ? (double)beta_pt[q] : 0.0;
@@ -440,6 +449,10 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
         int4 pr1[FP];
         ld_row(n1, pr1);
         const double ui = ti - tref;
+        // the last wave takes the batch's compensator terms (they do not need
+        // the sums), beside the first wave's logarithm and reciprocal (one
+        // wave: the first does all)
+        constexpr int WC = NW - 1;
         if (wv == 0) {
             const double eti = anch && valid ? exp_f64(bet * ui) : 0.0;   // e^{beta u_i}
             tb[lane] = ti;
@@ -559,9 +572,18 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
             }
         }
         double ei = 1.0;   // e^{-beta u_i} (anchored records)
+        if (anch && valid && wv == 0) ei = exp_f64(-bet * ui);
+        if (!RM && valid && wv == WC) {
+            // compensator terms of the event's node (eq. 2) and their
+            // beta-derivative part (eq. 10)
+            const double x = bet * (T - ti);
+            em1 = -expm1(-x);   // 1 - e^{-x}
+            const double cs_m = (double)__int_as_float(ni.w);
+            comp += cs_m * em1;
+            if (GRAD) Esum += cs_m * (T - ti) * exp_f64(-x);
+        }
         if (RM && valid && wv == 0) {
             if (anch) {
-                ei = exp_f64(-bet * ui);
                 R *= ei;
                 Dd *= ei;
             }
@@ -569,21 +591,15 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
             if (GRAD) dk[i - c0] = Dd;
         } else if (valid && wv == 0) {
             if (anch) {
-                ei = exp_f64(-bet * ui);
                 R *= ei;
                 Dd *= ei;
             }
             lam = __builtin_fma(bet, R, (double)__int_as_float(ni.z));
         if (INTENS) lambda_out[i] = (float)lam;
             logsum += log(lam);
-            const double x = bet * (T - ti);
-            em1 = -expm1(-x);   // 1 - e^{-x}
-            const double cs_m = (double)__int_as_float(ni.w);
-            comp += cs_m * em1;
             if (GRAD) {
                 w = 1.0 / lam;
                 gb += w * (R - bet * Dd);
-                Esum += cs_m * (T - ti) * exp_f64(-x);
             }
             if (SUPP) {
                 // beta w_i K_q(t_i) for each nonzero (m_i, q); the sums past
@@ -662,9 +678,9 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
         __syncthreads();
         for (int32_t k = threadIdx.x; k < X.nbo; k += 64 * NW) X.bcnt[(int64_t)k * gridDim.x + s] = lcnt[k];
     }
-    // deterministic wave reduction of the float64 partials (the first
-    // wave's; the others hold none)
-    if (RM || wv != 0) return;
+    // deterministic wave reductions of the float64 partials: the log-sum and
+    // dL/dbeta part in the first wave, the compensator sums in the last
+    if (RM || (wv != 0 && wv != NW - 1)) return;
     for (int off = 32; off > 0; off >>= 1) {
         logsum += __shfl_down(logsum, off, 64);
         comp += __shfl_down(comp, off, 64);
@@ -673,7 +689,14 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
     }
     if (lane == 0) {
         double* o = seg_part + (int64_t)s * 4;
-        o[0] = logsum; o[1] = comp; o[2] = Esum; o[3] = gb;
+        if (wv == 0) {
+            o[0] = logsum;
+            o[3] = gb;
+        }
+        if (wv == NW - 1) {
+            o[1] = comp;
+            o[2] = Esum;
+        }
     }
 }
 
