@@ -622,11 +622,13 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
             }
         }
         if (!RM && GRAD && valid && wv == 0) wchunk[i - c0] = (float)w;
-        __syncthreads();
+        // the records take the batch's events (the last wave, beside the
+        // first wave's work above: nothing there reads the records), then the
+        // batch's masks are cleared
         if (anch) {
             // anchored records: the batch's events of a node add their terms,
             // in index order, through one leader lane per node
-            if (valid && wv == 0) {
+            if (valid && wv == WC) {
                 uint64_t grp = rmask[mi];
                 if (__builtin_ctzll(grp) == lane) {
                     const double2 kj = rKJ[mi];
@@ -640,7 +642,7 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
                     rKJ[mi] = make_double2(s0, s1);
                 }
             }
-        } else if (valid && wv == 0) {
+        } else if (valid && wv == WC) {
             // lazy record update, one leader lane per node, events in index order
             uint64_t grp = rmask[mi];
             if (__builtin_ctzll(grp) == lane) {
@@ -660,8 +662,10 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
                 rKJ[mi] = make_double2(kq, jq);
             }
         }
-        __syncthreads();
-        if (valid && wv == 0) rmask[mi] = 0ull;
+        if (wv == WC) {
+            lds_wait();   // every lane's read of its mask before the clear
+            if (valid) rmask[mi] = 0ull;
+        }
         __syncthreads();
         t0 = t1;
         m0 = m1;
