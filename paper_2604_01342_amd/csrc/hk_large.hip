@@ -705,16 +705,29 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
 }
 
 // acc[k] += sum over segments of seg_part[s][k] (width values per segment);
-// fixed-order tree (deterministic)
+// per value a fixed-order tree (deterministic), four values per pass
 __global__ __launch_bounds__(256) void large_chunk_acc(int32_t nseg, int32_t width,
                                                        const double* __restrict__ seg_part,
                                                        double* __restrict__ acc) {
-    __shared__ double sh[256];
-    for (int k = 0; k < width; ++k) {
-        double v = 0.0;
-        for (int32_t s = threadIdx.x; s < nseg; s += 256) v += seg_part[(int64_t)s * width + k];
-        const double tot = block_sum_d<256>(v, sh);
-        if (threadIdx.x == 0) acc[k] += tot;
+    __shared__ double sh[4][256];
+    const int tid = threadIdx.x;
+    for (int k0 = 0; k0 < width; k0 += 4) {
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int32_t s = tid; s < nseg; s += 256)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (k0 + j < width) v[j] += seg_part[(int64_t)s * width + k0 + j];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sh[j][tid] = v[j];
+        __syncthreads();
+        for (int st = 128; st > 0; st >>= 1) {
+            if (tid < st)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) sh[j][tid] += sh[j][tid + st];
+            __syncthreads();
+        }
+        if (tid < 4 && k0 + tid < width) acc[k0 + tid] += sh[tid][0];
+        __syncthreads();
     }
 }
 
