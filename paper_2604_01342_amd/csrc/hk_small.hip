@@ -526,10 +526,14 @@ __global__ __launch_bounds__(256) void small_compute(int32_t S, int64_t n_total,
 // lane j mod LPI, before the in-order pass over the block and fetched from it
 // by the other lanes; R = alpha_{p,:} . K and D = alpha_{p,:} . J are summed
 // over the group (a butterfly, identical in every lane); the block's
-// logarithms are taken afterwards, again one event per lane.  The lanes'
-// scalar partials are summed in lane order.
+// logarithms are taken afterwards, again one event per lane.  The per-node
+// sums of the event's node (w, 1 - e^{-beta (T - t)} and (T - t)
+// e^{-beta (T - t)}) go to the item's LDS row by the event's lane (LDS
+// atomics: no selects over the nodes), and the compensator and its
+// beta-derivative come from them at the item's end, weighted by the column
+// sums of alpha.  The lanes' scalar partials are summed in lane order.
 template <int MP, int LPI>
-__global__ __launch_bounds__(256) void small_compute_c(int32_t S, int64_t n_total, const int64_t* __restrict__ ev_off,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void small_compute_c(int32_t S, int64_t n_total, const int64_t* __restrict__ ev_off,
                                                        const int64_t* __restrict__ item_off, int32_t L,
                                                        const double* __restrict__ t,
                                                        const int32_t* __restrict__ marks,
@@ -569,6 +573,10 @@ __global__ __launch_bounds__(256) void small_compute_c(int32_t S, int64_t n_tota
     constexpr int AW = MP * MP + (MP < 4 ? 4 : MP);   // floats per item, a multiple of 4
     __shared__ __align__(16) float ALs[4 * IPW][AW];
     float* A_ = ALs[(threadIdx.x >> 6) * IPW + lane / LPI];
+    // per node of the item: sum of w, of 1 - e^{-beta (T - t)}, of (T - t) e^{-beta (T - t)}
+    __shared__ double SCE[4 * IPW][3 * MP];
+    double* sce = SCE[(threadIdx.x >> 6) * IPW + lane / LPI];
+    for (int e = c; e < 3 * MP; e += LPI) sce[e] = 0.0;
     for (int e = c; e < AW; e += LPI) {
         const int pr = e / MP, qc = e % MP;
         float v = 0.0f;
@@ -579,15 +587,7 @@ __global__ __launch_bounds__(256) void small_compute_c(int32_t S, int64_t n_tota
         }
         A_[e] = v;
     }
-    __builtin_amdgcn_wave_barrier();
-    double colsum[MP];
-#pragma unroll
-    for (int q = 0; q < MP; ++q) {
-        double cs = 0.0;
-#pragma unroll
-        for (int p = 0; p < MP; ++p) cs += (double)A_[p * MP + q];
-        colsum[q] = cs;
-    }
+    lds_wait();   // the item's rows and cleared sums before any read or atomic
     double K[CL], J[CL];
 #pragma unroll
     for (int u = 0; u < CL; ++u) { K[u] = 0.0; J[u] = 0.0; }
@@ -617,15 +617,12 @@ __global__ __launch_bounds__(256) void small_compute_c(int32_t S, int64_t n_tota
             }
         }
     }
-    double lsum = 0.0, comp = 0.0, Esum = 0.0, gbs = 0.0;
-    double Sq[CL], Cq[CL], Gc[MP][CL];
+    double lsum = 0.0, gbs = 0.0;
+    double Gc[MP][CL];
 #pragma unroll
-    for (int u = 0; u < CL; ++u) {
-        Sq[u] = 0.0;
-        Cq[u] = 0.0;
+    for (int u = 0; u < CL; ++u)
 #pragma unroll
         for (int r = 0; r < MP; ++r) Gc[r][u] = 0.0;
-    }
     int mp = -1;
     // the items' events in rounds of NB, staged through LDS (coalesced
     // loads), the next round's loads in flight while one is processed
@@ -691,23 +688,21 @@ __global__ __launch_bounds__(256) void small_compute_c(int32_t S, int64_t n_tota
                 Dd += __shfl_xor(Dd, off, 64);
             }
             const double lam = (double)A_[MP * MP + p] + bet * R;
-            const double w = 1.0 / lam;
-            double csp = 0.0;
-#pragma unroll
-            for (int q = 0; q < MP; ++q) csp = (q == p) ? colsum[q] : csp;
+            // 1 / lambda: hardware reciprocal and two Newton steps
+            double w = __builtin_amdgcn_rcp(lam);
+            w = __builtin_fma(w, __builtin_fma(-lam, w, 1.0), w);
+            w = __builtin_fma(w, __builtin_fma(-lam, w, 1.0), w);
             if (c == j % LPI) {
                 lo[j / LPI] = lam;
                 ro[j / LPI] = w * (R - bet * Dd);
-                comp += csp * (1.0 - ex);
-                Esum += csp * (T - te) * ex;
+                atomicAdd(&sce[p], w);
+                atomicAdd(&sce[MP + p], 1.0 - ex);
+                atomicAdd(&sce[2 * MP + p], (T - te) * ex);
             }
 #pragma unroll
-            for (int u = 0; u < CL; ++u) {
-                Sq[u] += qa + u == p ? w : 0.0;
-                Cq[u] += qa + u == p ? 1.0 - ex : 0.0;
+            for (int u = 0; u < CL; ++u)
 #pragma unroll
                 for (int r = 0; r < MP; ++r) Gc[r][u] = __builtin_fma(r == p ? w : 0.0, K[u], Gc[r][u]);
-            }
             tp = te;
             mp = p;
         }
@@ -718,17 +713,27 @@ __global__ __launch_bounds__(256) void small_compute_c(int32_t S, int64_t n_tota
         }
     }
     // the group's scalar partials, summed in lane order
-    double tl = 0.0, tc = 0.0, te2 = 0.0, tg = 0.0;
+    double tl = 0.0, tg = 0.0;
 #pragma unroll
     for (int i = 0; i < LPI; ++i) {
         tl += __shfl(lsum, g0 + i, 64);
-        tc += __shfl(comp, g0 + i, 64);
-        te2 += __shfl(Esum, g0 + i, 64);
         tg += __shfl(gbs, g0 + i, 64);
     }
+    lds_wait();   // the per-node sums' atomics land before they are read
     if (!work) return;
     double* o = part + it * (int64_t)PW;
     if (c == 0) {
+        // compensator and its beta-derivative part from the per-node sums,
+        // weighted by the column sums of alpha
+        double tc = 0.0, te2 = 0.0;
+#pragma unroll
+        for (int q = 0; q < MP; ++q) {
+            double cs = 0.0;
+#pragma unroll
+            for (int p = 0; p < MP; ++p) cs += (double)A_[p * MP + q];
+            tc = __builtin_fma(cs, sce[MP + q], tc);
+            te2 = __builtin_fma(cs, sce[2 * MP + q], te2);
+        }
         o[0] = tl;
         o[1] = tc;
         o[2] = te2;
@@ -736,8 +741,8 @@ __global__ __launch_bounds__(256) void small_compute_c(int32_t S, int64_t n_tota
     }
 #pragma unroll
     for (int u = 0; u < CL; ++u) {
-        o[4 + qa + u] = Sq[u];
-        o[4 + MP + qa + u] = Cq[u];
+        o[4 + qa + u] = sce[qa + u];
+        o[4 + MP + qa + u] = sce[MP + qa + u];
 #pragma unroll
         for (int r = 0; r < MP; ++r) o[4 + 2 * MP + r * MP + qa + u] = Gc[r][u];
     }
