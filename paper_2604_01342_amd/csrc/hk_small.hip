@@ -213,22 +213,28 @@ __global__ __launch_bounds__(256) void small_agg(int32_t S, int64_t n_total, con
     if (wave * 64 >= n_items_cap) return;   // whole wave beyond the buffers (wave-uniform)
     ItemInfo inf = item_info(it, S, item_off, ev_off, L, n_total, n_items_cap);
     double K[MP], J[MP];
-#pragma unroll
-    for (int q = 0; q < MP; ++q) { K[q] = 0.0; J[q] = 0.0; }
     double D = 0.0;
     int reset = 1;
     double bet = 0.0;
     const bool work = inf.valid && inf.b > inf.a;
     int32_t M = 1;
-    double tref = 0.0;
+    double tref = 0.0, tl = 0.0;
     if (work) {
         M = m_s[inf.s] < 1 ? 1 : (m_s[inf.s] > MP ? MP : m_s[inf.s]);
         bet = (double)beta[inf.s];
         reset = inf.k == 0;
         tref = reset ? t[inf.a] : t[inf.a - 1];
+        tl = t[inf.b - 1];
     }
-    double tp = tref;
-    int mp = -1;
+    // the item's map, summed per node in LDS: each event adds its terms at
+    // the item's last event, e^{-beta (tl - t)} to K and (tl - t) e^{..} to J
+    // (rows of 2 MP + 1 doubles: an odd stride spreads the lanes over the banks)
+    constexpr int AR = 2 * MP + 1;
+    __shared__ double AG[4][64][AR];
+    double* ag = AG[threadIdx.x >> 6][lane];
+#pragma unroll
+    for (int q = 0; q < 2 * MP; ++q) ag[q] = 0.0;
+    lds_wait();
     // the wave's events in rounds of 8 per item, staged through LDS, the next
     // round's loads in flight while the current one is processed
     __shared__ double Tst[4][512];
@@ -256,26 +262,22 @@ __global__ __launch_bounds__(256) void small_agg(int32_t S, int64_t n_total, con
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 if (e0 + j < inf.b) {
-                    const double te = tv[j];
-                    const double d = te - tp;
-                    const double s = exp_f64(-bet * d);
-#pragma unroll
-                    for (int q = 0; q < MP; ++q) {
-                        const double k1 = s * (K[q] + (q == mp ? 1.0 : 0.0));
-                        J[q] = __builtin_fma(s, J[q], d * k1);
-                        K[q] = k1;
-                    }
-                    tp = te;
-                    mp = clamp_mark(mv[j], M);
+                    const double d = tl - tv[j];
+                    const double e = exp_f64(-bet * d);
+                    const int q = clamp_mark(mv[j], M);
+                    atomicAdd(&ag[q], e);
+                    atomicAdd(&ag[MP + q], d * e);
                 }
             }
         }
     }
-    if (work) {
+    lds_wait();   // the adds land before the reads
 #pragma unroll
-        for (int q = 0; q < MP; ++q) K[q] += (q == mp ? 1.0 : 0.0);
-        D = tp - tref;
+    for (int q = 0; q < MP; ++q) {
+        K[q] = ag[q];
+        J[q] = ag[MP + q];
     }
+    if (work) D = tl - tref;
     // segmented inclusive scan over the wave's 64 items
     for (int d = 1; d < 64; d <<= 1) {
         const double oD = shfl_up_d(D, d);
