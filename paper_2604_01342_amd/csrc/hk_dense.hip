@@ -673,10 +673,12 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
     }
 }
 
-// The same dense dL/dalpha for tiles of 32 rows (or more) at large M: the
-// rank-1 part of each window (u K_g^T) is accumulated in float32 registers
-// and added to the workgroup's float64 LDS tile every HK_FLUSH windows that
-// had own events, and at the end; the tile also takes the pair terms and
+// The same dense dL/dalpha for tiles of 32 x 256 at large M: the rank-1
+// part of each window (u K_g^T, a 32 x 256 outer product) runs on the matrix
+// cores as four float32 MFMAs (one per 64 columns, two 32 x 32 blocks each)
+// into float32 accumulators, added to the workgroup's float64 LDS tile every
+// HK_FLUSH windows that had own events, and at the end; the tile also takes
+// the pair terms and
 // starts from the event range's float64 partials.  Twice the rows per tile
 // halve the window visits per event (the per-window loads, header and
 // bookkeeping) at the same register count; NWV waves share the tile.
@@ -739,21 +741,31 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(2))) v
         const int32_t row = r0 + x / W, col = s0 + x % W;
         GP[x] = row < M && col < M ? gp[(int64_t)row * M + col] : 0.0;
     }
-    // the rank-1 part in float32 registers (row i, column s0 + 64 j + lane)
-    float Gm[DR][CPL];
+    // the rank-1 part in float32 matrix-core accumulators: for column group
+    // j (tile columns 64 j .. 64 j + 63), v_mfma_f32_32x32x1_2b_f32 adds the
+    // outer products of u (rows 0..31, the A operand of both blocks: lane l
+    // holds u[l mod 32]) with the state of columns 64 j + l (the B operand:
+    // lanes 0..31 block 0, lanes 32..63 block 1).  Result register r of
+    // lane l holds row 8 ((r mod 16) / 4) + 4 (l / 32) + r mod 4 of column
+    // 64 j + 32 (r / 16) + l mod 32 (layout measured on the device).
+    static_assert(DR == 32 && CPL == 4, "32 x 256 tiles");
+    typedef float f32x32 __attribute__((ext_vector_type(32)));
+    f32x32 acc0 = {}, acc1 = {}, acc2 = {}, acc3 = {};
+    int nacc = 0;   // windows added to the accumulators since their last flush
+    auto flush1 = [&](f32x32& a, int j) __attribute__((always_inline)) {
 #pragma unroll
-    for (int i = 0; i < DR; ++i)
-#pragma unroll
-        for (int j = 0; j < CPL; ++j) Gm[i][j] = 0.0f;
-    int nacc = 0;   // windows added to Gm since its last flush
-    auto flush = [&]() {
-#pragma unroll
-        for (int i = 0; i < DR; ++i)
-#pragma unroll
-            for (int j = 0; j < CPL; ++j) {
-                atomicAdd(&GP[i * W + j * 64 + lane], (double)Gm[i][j]);
-                Gm[i][j] = 0.0f;
-            }
+        for (int r = 0; r < 32; ++r) {
+            const int row = 8 * ((r & 15) >> 2) + 4 * (lane >> 5) + (r & 3);
+            const int col = 64 * j + 32 * (r >> 4) + (lane & 31);
+            atomicAdd(&GP[row * W + col], (double)a[r]);
+        }
+        a = f32x32{};
+    };
+    auto flush = [&]() __attribute__((always_inline)) {
+        flush1(acc0, 0);
+        flush1(acc1, 1);
+        flush1(acc2, 2);
+        flush1(acc3, 3);
     };
     if (lane < DR) UL[lane] = 0.0f;
     const double bet = (double)beta[0];
@@ -924,21 +936,14 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(2))) v
             if (n == 0 || q - qL < 64) break;
         }
         if (nown) {
-            // rank-1 update G += u K_g^T in float32, then clear u (u is this
-            // wave's; its atomics on u land before the reads)
+            // rank-1 update G += u K_g^T on the matrix cores (float32), then
+            // clear u (u is this wave's; its atomics on u land before the reads)
             lds_wait();
-            float kf[CPL];
-#pragma unroll
-            for (int j = 0; j < CPL; ++j) kf[j] = (float)cur.K[j];
-#pragma unroll
-            for (int i4 = 0; i4 < DR / 4; ++i4) {
-                const float4 u4 = reinterpret_cast<const float4*>(UL)[i4];
-                const float uu[4] = {u4.x, u4.y, u4.z, u4.w};
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-#pragma unroll
-                    for (int j = 0; j < CPL; ++j) Gm[4 * i4 + r][j] = __builtin_fmaf(uu[r], kf[j], Gm[4 * i4 + r][j]);
-            }
+            const float uv = UL[lane & 31];
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x1f32(uv, (float)cur.K[0], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x1f32(uv, (float)cur.K[1], acc1, 0, 0, 0);
+            acc2 = __builtin_amdgcn_mfma_f32_32x32x1f32(uv, (float)cur.K[2], acc2, 0, 0, 0);
+            acc3 = __builtin_amdgcn_mfma_f32_32x32x1f32(uv, (float)cur.K[3], acc3, 0, 0, 0);
             __builtin_amdgcn_wave_barrier();
             if (lane < DR) UL[lane] = 0.0f;
             __builtin_amdgcn_wave_barrier();
