@@ -36,6 +36,9 @@ namespace hk {
 
 // capacity of the per-batch staging of alpha columns in the forward kernel
 #define PT_STAGE 2048
+// largest beta_max (t_first - t_last) of a dense-kernel window that takes the
+// merged path: e^64 and e^-64 stay well inside float32's range
+#define HK_PT_MERGE_SPAN 64.0
 
 __global__ void pt_fill(double* p, int64_t n, double v) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -412,19 +415,23 @@ __global__ void pt_rscan_apply(int64_t c0, int64_t c1, int64_t n, double T, int3
 }
 
 // Dense adjoint kernel.  Block = (target block rb, source block sb, event
-// range er), one wave; lane l owns target p = r0 + l and its adjoint state
-// A_p (float64) from the events after the current read position, kept at an
-// anchor time.  The block reads only the bucketed records of its two node
-// blocks ("own": targets in rb; "slab": sources in sb), from the end of the
-// range backwards, merged by event index in windows of up to 64 + 64 records
-// (the window starts where either list's 64th record from the end is).  Per
+// range er), HK_DWP waves, each over its share of the range's segments; lane
+// l owns target p = r0 + l and beta_p A_p (float64), A_p the adjoint state
+// from the events after the current read position, kept at an anchor time.
+// The block reads only the bucketed records of its two node blocks ("own":
+// targets in rb; "slab": sources in sb), from the end of the range
+// backwards, merged by event index in windows of up to 64 + 64 records (the
+// window starts where either list's 64th record from the end is).  Per
 // window: A moves to the window's latest event time tw; every slab event k
-// adds to column m_k of the block beta_p A_p(t_k): the state decayed to t_k
-// plus the window's own-target events after k (one masked ds_add over those
-// lanes); then the window's own events enter A at its earliest event time.
-// G is kept in LDS column-major (stride 65 against bank conflicts).  Blocks
-// with sb == 0 also sum w_i per target, blocks with rb == 0 count the events
-// per source.
+// adds beta_p A_p(t_k) to column m_k of the block: the state decayed to t_k
+// plus the window's own-target events after k.  Three forms, by the window's
+// largest decay exponent beta_max (tw - t_last): short windows (<= 0.5) and
+// windows past HK_PT_MERGE_SPAN add the own events' part pairwise (one
+// masked ds_add per slab event) and then enter the own events into A at the
+// window's earliest time; the windows between enter them into A in event
+// order inside the slab loop.  G is kept in LDS column-major (stride 65
+// against bank conflicts).  Blocks with sb == 0 also sum w_i per target,
+// blocks with rb == 0 count the events per source.
 __global__ __launch_bounds__(64 * HK_DWP) void pt_dense(int64_t c0, int64_t c1, int64_t n, double T, int32_t M, int32_t NB,
                                                int32_t ER, int32_t segs_per_range, int32_t nseg,
                                                const double* __restrict__ t, const float* __restrict__ beta,
@@ -495,6 +502,7 @@ __global__ __launch_bounds__(64 * HK_DWP) void pt_dense(int64_t c0, int64_t c1, 
     const double bp = pv ? (double)beta[p] : 0.0;
     const double bp2 = bp * HK_LOG2E;                      // beta_p log2(e)
     const float bpl = (float)bp2;
+    const float bpl_lo = (float)(bp2 - (double)bpl);       // bp2 = bpl + bpl_lo to ~2^-48
     // largest decay of the block's targets
     double bmax = bp;
     for (int off = 32; off > 0; off >>= 1) {
@@ -504,16 +512,18 @@ __global__ __launch_bounds__(64 * HK_DWP) void pt_dense(int64_t c0, int64_t c1, 
     // adjoint state from the events after the range (and the seed) at tau
     const bool at_end = sB >= nseg;
     double tau = seg_first_time(t, c0, c1, n, nseg, at_end ? nseg : sB, T);
-    double Ah = 0.0;
+    double Ab = 0.0;   // beta_p A_p at the anchor tau
     if (pv) {
         const int32_t ngr = (nseg + HK_SG - 1) / HK_SG;
-        Ah = at_end ? rgcarry[(int64_t)(ngr - 1) * M + p] : rcarry_seg[(int64_t)sB * M + p];
+        Ab = bp * (at_end ? rgcarry[(int64_t)(ngr - 1) * M + p] : rcarry_seg[(int64_t)sB * M + p]);
     }
     RecStream<true> O, S;
     O.init(bk_key, bk_t, bk_w, (int64_t)bk_base[rb] + bk_off[(int64_t)rb * (nseg + 1) + sA],
            (int64_t)bk_base[rb] + bk_off[(int64_t)rb * (nseg + 1) + sB]);
     S.init(bk_key, bk_t, bk_w, (int64_t)bk_base[sb] + bk_off[(int64_t)sb * (nseg + 1) + sA],
            (int64_t)bk_base[sb] + bk_off[(int64_t)sb * (nseg + 1) + sB]);
+    O.settle();
+    S.settle();
     __syncthreads();
     for (;;) {
         if (sA >= sB) break;
@@ -534,47 +544,103 @@ __global__ __launch_bounds__(64 * HK_DWP) void pt_dense(int64_t c0, int64_t c1, 
             tw = a0 > tw ? a0 : tw;
             tl = a1 < tl ? a1 : tl;
         }
-        Ah *= (double)exp2_f64arg((tw - tau) * bp2);
+        Ab *= (double)exp2_f64arg((tw - tau) * bp2);
         const int pi = (int)(O.ck & 63u);
         const double bo = (double)BL[pi];
         const double bo2 = bo * HK_LOG2E;
         const float bol = (float)bo2;
         const double wi = (double)O.cw;
+        bool merged = false;
         if (bmax * (tw - tl) <= 0.5) {
-            // short window: every decay exponent is at most 0.5, so its
-            // float32 rounding costs at most 3e-8 relative and the hardware
-            // exp2 applies directly (the time differences are float64)
-            const double bA = bp * Ah, bw = bo * wi;
+            // short window: every decay exponent is at most 0.5 in magnitude,
+            // so float32 arguments cost at most 2.5e-7 relative and the
+            // hardware exp2 applies directly.  The time differences are taken
+            // in float64 once per lane (slab lane k: tw - t_k; own lane:
+            // t_i - tw, folded into the exponent's constant), then each slab
+            // event's offset and key are broadcast by one readlane apiece.
+            // Lanes without an own event add 0 to their own column slot (a
+            // finite 0: their exponent constant is 0, not a stale record's).
+            const float dks = (float)(tw - S.ct);
+            const float c2 = own ? -bol * (float)(O.ct - tw) : 0.0f;
+            const int pa = own ? pi : lane;
+            const double bA = Ab, bw = own ? bo * wi : 0.0;
+            const int keys = (int)S.ck;
             for (int k = 0; k < ns; ++k) {
-                const int qoff = (int)(rl_i((int)S.ck, k) & 63) * 65;
-                const double tk = rl_d(S.ct, k);
-                const int ik = rl_i(is, k);
-                const float dk = (float)(tw - tk);
-                atomicAdd(&G[qoff + lane], bA * (double)__builtin_amdgcn_exp2f(-bpl * dk));
-                if (own && io > ik)
-                    atomicAdd(&G[qoff + pi], bw * (double)__builtin_amdgcn_exp2f(-bol * (float)(O.ct - tk)));
+                const uint32_t key = (uint32_t)rl_i(keys, k);
+                const float dk = rl_f(dks, k);
+                const int qoff = (int)(key & 63u) * 65;
+                const float e1 = __builtin_amdgcn_exp2f(-bpl * dk);
+                const float e2 = __builtin_amdgcn_exp2f(__builtin_fmaf(-bol, dk, c2));
+                atomicAdd(&G[qoff + lane], bA * (double)e1);
+                // own event later than slab event k (both lists newest first)
+                atomicAdd(&G[qoff + pa], bw * (double)(io > (int)(key >> 6) ? e2 : 0.0f));
+            }
+        } else if (bmax * (tw - tl) <= HK_PT_MERGE_SPAN) {
+            // long window, merged: A is moved to the anchor tw, and the
+            // window's own events enter it in event order between the slab
+            // events (newest first), each as beta_{m_i} w_i e^{beta_{m_i}
+            // (tw - t_i)} on its target's lane, so every slab event needs one decay
+            // e^{-beta_p (tw - t_k)} per lane and one ds_add.  The span bound
+            // keeps both factors inside float32's exponent range.  The decay's
+            // exponent is split in two floats (tw - t_k = dh + dl, beta_p
+            // log2(e) = bpl + bpl_lo, and the product's rounding error by an
+            // fma), so 2^-x = 2^-xh (1 - xl ln2) is as accurate as the
+            // hardware exp2 at any x in range.
+            merged = true;
+            const double dd = tw - S.ct;
+            const float dh = (float)dd, dl = (float)(dd - (double)dh);
+            const double fo = own ? bo * wi * (double)exp2_f64arg((tw - O.ct) * bo2) : 0.0;
+            const int okeys = (int)O.ck, skeys = (int)S.ck;
+            const uint64_t omask = __builtin_amdgcn_ballot_w64(own);
+            int j = 0;
+            for (int k = 0; k < ns; ++k) {
+                const uint32_t key = (uint32_t)rl_i(skeys, k);
+                // own events later than slab event k (the first dk of the
+                // list, newest first) join A before it
+                const int dk = __builtin_popcountll(__builtin_amdgcn_ballot_w64(io > (int)(key >> 6)) & omask);
+                for (; j < dk; ++j) {
+                    const double f = rl_d(fo, j);
+                    if (lane == (rl_i(okeys, j) & 63)) Ab += f;
+                }
+                const float xh0 = rl_f(dh, k), xl0 = rl_f(dl, k);
+                const float xh = bpl * xh0;
+                const float xl = __builtin_fmaf(bpl, xl0, __builtin_fmaf(bpl_lo, xh0, __builtin_fmaf(bpl, xh0, -xh)));
+                const float e0 = __builtin_amdgcn_exp2f(-xh);
+                const float e = __builtin_fmaf(e0, xl * -0.69314718f, e0);
+                atomicAdd(&G[(int)(key & 63u) * 65 + lane], Ab * (double)e);
+            }
+            // own events older than every slab event of the window
+            for (; j < no; ++j) {
+                const double f = rl_d(fo, j);
+                if (lane == (rl_i(okeys, j) & 63)) Ab += f;
             }
         } else {
             for (int k = 0; k < ns; ++k) {
                 const int qoff = (int)(rl_i((int)S.ck, k) & 63) * 65;
                 const double tk = rl_d(S.ct, k);
                 const int ik = rl_i(is, k);
-                atomicAdd(&G[qoff + lane], bp * Ah * (double)exp2_f64arg((tk - tw) * bp2));
+                atomicAdd(&G[qoff + lane], Ab * (double)exp2_f64arg((tk - tw) * bp2));
                 if (own && io > ik) atomicAdd(&G[qoff + pi], bo * wi * (double)exp2_f64arg((tk - O.ct) * bo2));
             }
         }
         if (sb == 0 && own) atomicAdd(&SL[pi], wi);
         if (rb == 0 && sl) atomicAdd(&NL[S.ck & 63u], 1.0);
-        if (own) atomicAdd(&AL[pi], wi * (double)exp2_f64arg((tl - O.ct) * bo2));
-        // AL is this wave's; its atomics land before the read
-        lds_wait();
-        Ah = __builtin_fma(Ah, (double)exp2_f64arg((tl - tw) * bp2), AL[lane]);
-        __builtin_amdgcn_wave_barrier();
-        AL[lane] = 0.0;
-        __builtin_amdgcn_wave_barrier();
-        tau = tl;
-        O.consume(no);
-        S.consume(ns);
+        if (merged) {
+            tau = tw;   // A already holds the window's own events, anchored at tw
+        } else {
+            if (own) atomicAdd(&AL[pi], bo * wi * (double)exp2_f64arg((tl - O.ct) * bo2));
+            // AL is this wave's; its atomics land before the read
+            lds_wait();
+            Ab = __builtin_fma(Ab, (double)exp2_f64arg((tl - tw) * bp2), AL[lane]);
+            __builtin_amdgcn_wave_barrier();
+            AL[lane] = 0.0;
+            __builtin_amdgcn_wave_barrier();
+            tau = tl;
+        }
+        O.shift(no);
+        S.shift(ns);
+        O.refill();
+        S.refill();
     }
     __syncthreads();
     {

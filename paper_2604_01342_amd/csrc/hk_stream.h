@@ -19,22 +19,25 @@ __device__ __forceinline__ double rl_d(double v, int k) {
 
 // Records [lo, hi) of the arrays (key, t, w), read in order (REV = false: from
 // lo upward; REV = true: from hi downward).  Lane l of cur holds the record l
-// places ahead of the read position, lane l of nxt the record 64 + l places
-// ahead.  consume(n) moves the position by n (0 < n <= 64): both halves shift
-// by n lanes (ds_bpermute), and the lanes of nxt that run past the old window
-// are refilled by loads issued now and merged at the next consume, so their
-// latency hides behind one window of work.  Positions past the list hold a
-// clamped (valid, unused) record.
+// places ahead of the read position; the pending registers hold, once their
+// loads land, the record 64 + l places ahead.  A window move is split in two:
+// shift(n) (0 <= n <= 64) moves the position by n, taking the records that
+// enter cur from the pending ones by one ds_bpermute per word, and refill()
+// issues the loads of the next pending records.  A kernel with several
+// streams shifts all of them before it refills any, so that no shift waits
+// on a load issued in the same window: every load has one window of work to
+// land.  Every lane reloads (the lanes whose record did not change hit the
+// cache), so the count of loads in flight is the same on every path.
+// Positions past the list hold a clamped (valid, unused) record.
 template <bool REV>
 struct RecStream {
     const uint32_t* K;
     const double* Tm;
     const float* W;
     int64_t lo, hi, pos;
-    uint32_t ck, nk, pk;
-    double ct, nt, pt;
-    float cw, nw, pw;
-    int split;   // lanes >= split of nxt are still in (pk, pt, pw)
+    uint32_t ck, pk;
+    double ct, pt;
+    float cw, pw;
 
     __device__ __forceinline__ int64_t at(int64_t ahead) const {
         int64_t e = REV ? pos - 1 - ahead : pos + ahead;
@@ -51,44 +54,37 @@ struct RecStream {
         lo = lo_;
         hi = hi_;
         pos = REV ? hi : lo;
-        const int lane = threadIdx.x & 63;
-        const int64_t a = at(lane), b = at(64 + lane);
+        const int64_t a = at(threadIdx.x & 63);
         ck = K[a];
         ct = Tm[a];
         cw = W[a];
-        nk = K[b];
-        nt = Tm[b];
-        nw = W[b];
-        split = 64;
+        refill();
     }
+    // Called once after every stream of the kernel is set up: the initial
+    // loads of cur land here.  Otherwise they would still be in flight on the
+    // path into the window loop, and the wait the compiler places at the
+    // loop's head (merged over the paths into it) would make every window
+    // wait on the refill loads issued just before it.
+    __device__ __forceinline__ void settle() { asm volatile("" : "+v"(ck), "+v"(ct), "+v"(cw)); }
     __device__ __forceinline__ int64_t avail() const { return REV ? pos - lo : hi - pos; }
-    __device__ __forceinline__ void consume(int n) {
+    __device__ __forceinline__ void shift(int n) {
         if (n <= 0) return;
         const int lane = threadIdx.x & 63;
-        if (lane >= split) {
-            nk = pk;
-            nt = pt;
-            nw = pw;
-        }
         const int src = (lane + n) & 63;
         const bool from_cur = lane + n < 64;
-        const uint32_t sck = (uint32_t)__shfl((int)ck, src, 64), snk = (uint32_t)__shfl((int)nk, src, 64);
-        const double sct = __shfl(ct, src, 64), snt = __shfl(nt, src, 64);
-        const float scw = __shfl(cw, src, 64), snw = __shfl(nw, src, 64);
-        ck = from_cur ? sck : snk;
-        ct = from_cur ? sct : snt;
-        cw = from_cur ? scw : snw;
-        nk = snk;
-        nt = snt;
-        nw = snw;
+        const uint32_t sck = (uint32_t)__shfl((int)ck, src, 64), spk = (uint32_t)__shfl((int)pk, src, 64);
+        const double sct = __shfl(ct, src, 64), spt = __shfl(pt, src, 64);
+        const float scw = __shfl(cw, src, 64), spw = __shfl(pw, src, 64);
+        ck = from_cur ? sck : spk;
+        ct = from_cur ? sct : spt;
+        cw = from_cur ? scw : spw;
         pos = REV ? pos - n : pos + n;
-        if (!from_cur) {
-            const int64_t e = at(64 + lane);
-            pk = K[e];
-            pt = Tm[e];
-            pw = W[e];
-        }
-        split = 64 - n;
+    }
+    __device__ __forceinline__ void refill() {
+        const int64_t e = at(64 + (threadIdx.x & 63));
+        pk = K[e];
+        pt = Tm[e];
+        pw = W[e];
     }
 };
 

@@ -26,6 +26,34 @@ def test_per_target_matches_adjoint_oracle(H, seed, n, M, density, ties, chunk):
     check(run_gpu(H, t, m, mu, alpha, beta, T, chunk), ref, label=f"per-target n={n} M={M} chunk={chunk}")
 
 
+# The dense adjoint kernel handles a window of records by one of three forms,
+# chosen by its largest decay exponent beta_max (t_first - t_last): short
+# (<= 0.5), merged (up to 64) and pairwise-exact (beyond).  Stretches of
+# 5000, 20 and 0.1 events per unit time, with beta_p in [0.5, 2] and windows
+# of about 64 records per node block, give every form and every change
+# between two forms; M = 150 (three node blocks) adds blocks whose two record
+# lists differ.
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("M,chunk", [(20, 0), (150, 12)])
+def test_per_target_window_forms(H, M, chunk):
+    rng = np.random.default_rng(90 + M)
+    parts = [(3000, 5000.0), (3000, 20.0), (400, 0.1), (3000, 5000.0), (2000, 20.0), (300, 0.1)]
+    t = np.cumsum(np.concatenate([rng.exponential(1.0 / r, size=k) for k, r in parts]))
+    n = t.size
+    m = rng.integers(0, M, size=n).astype(np.int32)
+    mu = rng.uniform(0.05, 0.5, size=M).astype(np.float32)
+    a = rng.uniform(0.0, 1.0, size=(M, M)) * (rng.random((M, M)) < 0.3)
+    alpha = (a * (0.5 / a.sum(axis=0).max())).astype(np.float32)
+    beta = rng.uniform(0.5, 2.0, size=M).astype(np.float32)
+    T = float(t[-1] + 0.5)
+    # the stretches' spans over 64 events of one node block, times beta_max
+    blocks = (M + 63) // 64
+    spans = [float(beta.max()) * 64 * blocks / r for _, r in parts]
+    assert min(spans) < 0.5 and any(0.5 < x < 64 for x in spans) and max(spans) > 64
+    ref = oracle.adjoint(t, m, mu, alpha, beta, T)
+    check(run_gpu(H, t, m, mu, alpha, beta, T, chunk), ref, label=f"per-target window forms M={M} chunk={chunk}")
+
+
 @pytest.mark.timeout(300)
 @pytest.mark.parametrize("n,M", [(64 * 4096, 20), (64 * 4096 + 1, 20), (300_000, 30), (4096 * 200 + 77, 12)])
 def test_per_target_gradient_checkpoint_levels(H, n, M):
