@@ -35,7 +35,9 @@
 namespace hk {
 
 // capacity of the per-batch staging of alpha columns in the forward kernel
-#define PT_STAGE 2048
+// (12 bytes an entry); the forward kernel's batch area takes PT_BATCH_LDS
+#define PT_STAGE 1792
+#define PT_BATCH_LDS (64 * 3 * 8 + 128 * 8 + 128 * 4)
 // largest beta_max (t_first - t_last) of a dense-kernel window that takes the
 // merged path: e^64 and e^-64 stay well inside float32's range
 #define HK_PT_MERGE_SPAN 64.0
@@ -109,11 +111,13 @@ __global__ __launch_bounds__(64) void pt_seg_agg(int64_t c0, int64_t c1, int32_t
                 }
 #pragma unroll
                 for (int j = 0; j < 8; ++j) bv[j] = beta[pv[j]];
+                // no branch inside the eight: entries past the column add
+                // zeros (alpha taken as 0), so the eight entries' exp chains
+                // interleave
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
-                    if (kb + j >= k1) break;
                     const int32_t p = pv[j];
-                    const double al = (double)av[j], bp = (double)bv[j];
+                    const double al = kb + j < k1 ? (double)av[j] : 0.0, bp = (double)bv[j];
                     const double e = exp_f64(-bp * d);
                     atomicAdd(&aR[p], al * e);
                     atomicAdd(&aD[p], al * d * e);
@@ -140,12 +144,26 @@ __global__ __launch_bounds__(64) void pt_seg_agg(int64_t c0, int64_t c1, int32_t
     }
 }
 
-// Forward pass over one segment (one wave), events in index order.  LDS keeps
-// one lazy record per target (time, R, D at that time), initialised from the
-// scanned carry.  Each event reads its own target's record (R_p, D_p at t_i,
-// from the events before it), then pushes its alpha column into the records
-// of the targets it excites.  The alpha columns of a 64-event batch are first
-// staged in LDS so the serial walk reads no global memory.
+// slot of target p in the forward kernel's table of a batch's own targets
+// (128 slots for at most 64 keys, open addressing)
+__device__ __forceinline__ int pt_hslot(int p) { return (int)(((uint32_t)p * 2654435761u) >> 25); }
+
+// Forward pass over one segment (one wave), 64 events per batch.  LDS keeps
+// one lazy record per target (time tau_p, R_p and D_p at tau_p), initialised
+// from the scanned carry.  Per batch:
+//  1. read: lane i moves its own target's record to t_i: R_p(t_i), D_p(t_i)
+//     from the events before the batch;
+//  2. push: the batch's alpha-column entries (event j, target p, alpha),
+//     staged in LDS, 64 at a time, lanes over entries.  The first entry of a
+//     target in the batch moves its record to the batch's last time t_B (it
+//     claims the record by exchanging tau_p for t_B); then every entry adds
+//     alpha e^{-beta_p (t_B - t_j)} to R_p and (t_B - t_j) times that to D_p.
+//     An entry whose target is the own target of a later event i of the
+//     batch (a table of the batch's own targets) adds its share at t_i,
+//     alpha e^{-beta_p (t_i - t_j)}, to that event;
+//  3. finish: lane i adds its shares, lambda_i = mu_p + beta_p R_p(t_i).
+// Events tied in time keep index order (a later event sees an earlier one's
+// push at distance 0), as in the recurrence.
 template <bool GRAD, bool INTENS>
 __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t M, double T,
                                                  const double* __restrict__ t, const int32_t* __restrict__ marks,
@@ -161,9 +179,14 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
     double* rR = lds + M;
     double* rD = lds + 2 * M;
     double* gbl = lds + 3 * M;   // per-target sum of w_i (R_i - beta_p D_i) over the segment
-    int32_t* st_row = (int32_t*)(lds + 4 * M);
+    double* ev_t = lds + 4 * M;  // [64] the batch's event times
+    double* shR = ev_t + 64;     // [64] the batch's in-batch shares of R and D
+    double* shD = shR + 64;
+    uint64_t* hmask = (uint64_t*)(shD + 64);   // [128] events of the batch per own target
+    int32_t* hkey = (int32_t*)(hmask + 128);   // [128] own target of the slot, -1 empty
+    int32_t* st_row = hkey + 128;
     float* st_val = (float*)(st_row + PT_STAGE);
-    float* st_bet = st_val + PT_STAGE;
+    int32_t* st_evt = (int32_t*)(st_val + PT_STAGE);
     const int32_t s = blockIdx.x;
     const int lane = threadIdx.x;
     const int64_t a = c0 + (int64_t)s * HK_SEG;
@@ -176,7 +199,6 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
         rD[q] = cs[M + q];
         gbl[q] = 0.0;
     }
-    __syncthreads();
     double logsum = 0.0;
     for (int64_t base = a; base < b; base += 64) {
         const int64_t ie = base + lane;
@@ -185,6 +207,7 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
         const double tv = t[ic];
         const int mv = clamp_mark(marks[ic], M);
         const int nb = (int)(b - base < 64 ? b - base : 64);
+        const double tB = pt_rdl_d(tv, nb - 1);
         // column extents of the batch's marks and their exclusive prefix
         const int32_t cb = csc_ptr[mv];
         const int32_t cn = ve ? csc_ptr[mv + 1] - cb : 0;
@@ -194,15 +217,45 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
             if (lane >= d) off += u;
         }
         off -= cn;   // exclusive
-        double Rk = 0.0, Dk = 0.0;
+        ev_t[lane] = tv;
+        shR[lane] = 0.0;
+        shD[lane] = 0.0;
+        hkey[lane] = -1;
+        hkey[lane + 64] = -1;
+        hmask[lane] = 0ull;
+        hmask[lane + 64] = 0ull;
+        __syncthreads();   // also orders the previous batch's pushes before the reads
+        // 1. own target's record at t_i, and the table of own targets
+        const double bm = (double)beta[mv];
+        double Rk, Dk;
+        {
+            const double d = tv - rtau[mv];
+            const double e = exp_f64(-bm * d);
+            const double r = rR[mv];
+            Rk = e * r;
+            Dk = e * __builtin_fma(d, r, rD[mv]);
+        }
+        if (ve) {
+            int sl = pt_hslot(mv);
+            for (;;) {
+                const int old = atomicCAS(&hkey[sl], -1, mv);
+                if (old == -1 || old == mv) {
+                    atomicOr((unsigned long long*)&hmask[sl], 1ull << lane);
+                    break;
+                }
+                sl = (sl + 1) & 127;
+            }
+        }
+        __syncthreads();
+        // 2. pushes, in stretches of events [k, k2) whose entries fit the stage
         int k = 0;
         while (k < nb) {
-            // stage the columns of events [k, k2) (at least one event; an
-            // event whose column alone exceeds the stage reads it directly)
             const int32_t o0 = pt_rdl(off, k);
             int k2 = k + 1;
             while (k2 < nb && pt_rdl(off, k2) + pt_rdl(cn, k2) - o0 <= PT_STAGE) ++k2;
             const bool staged = pt_rdl(off, k) + pt_rdl(cn, k) - o0 <= PT_STAGE;
+            const int32_t ne = pt_rdl(off, k2 - 1) + pt_rdl(cn, k2 - 1) - o0;
+            const int32_t cbk = pt_rdl(cb, k);
             if (staged) {
                 // short columns: each lane copies its own event's column;
                 // long ones: all lanes copy one column at a time (coalesced)
@@ -210,10 +263,9 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
                 if (mine && cn <= 32) {
                     for (int32_t j = 0; j < cn; ++j) {
                         const int2 e = csc_cv[cb + j];
-                        const int32_t pr = e.x;
-                        st_row[off - o0 + j] = pr;
+                        st_row[off - o0 + j] = e.x;
                         st_val[off - o0 + j] = __int_as_float(e.y);
-                        st_bet[off - o0 + j] = beta[pr];
+                        st_evt[off - o0 + j] = lane;
                     }
                 }
                 uint64_t big = __ballot(mine && cn > 32);
@@ -223,57 +275,77 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
                     const int32_t nk = pt_rdl(cn, kk), ok = pt_rdl(off, kk) - o0, bk = pt_rdl(cb, kk);
                     for (int32_t j = lane; j < nk; j += 64) {
                         const int2 e = csc_cv[bk + j];
-                        const int32_t pr = e.x;
-                        st_row[ok + j] = pr;
+                        st_row[ok + j] = e.x;
                         st_val[ok + j] = __int_as_float(e.y);
-                        st_bet[ok + j] = beta[pr];
+                        st_evt[ok + j] = kk;
                     }
                 }
                 __syncthreads();
             }
-            for (; k < k2; ++k) {
-                const double ti = pt_rdl_d(tv, k);
-                const int p = pt_rdl(mv, k);
-                const double bp = (double)beta[p];
-                // record of the event's own target, moved to t_i
-                const double d = ti - rtau[p];
-                const double e = exp_f64(-bp * d);
-                const double r = rR[p];
-                const double Rv = e * r;
-                const double Dv = e * __builtin_fma(d, r, rD[p]);
-                if (lane == k) { Rk = Rv; Dk = Dv; }
-                // push the event's alpha column (targets excited by mark p)
-                const int32_t n_k = pt_rdl(cn, k);
-                const int32_t ok = pt_rdl(off, k) - o0;
-                const int32_t cbk = pt_rdl(cb, k);
-                for (int32_t j0 = 0; j0 < n_k; j0 += 64) {
-                    const int32_t j = j0 + lane;
-                    if (j < n_k) {
-                        int32_t tp;
-                        float av, bt;
-                        if (staged) {
-                            tp = st_row[ok + j];
-                            av = st_val[ok + j];
-                            bt = st_bet[ok + j];
-                        } else {
-                            const int2 e = csc_cv[cbk + j];
-                            tp = e.x;
-                            av = __int_as_float(e.y);
-                            bt = beta[tp];
-                        }
-                        const double dd = ti - rtau[tp];
-                        const double ee = exp_f64(-(double)bt * dd);
-                        const double r0 = rR[tp];
-                        rD[tp] = ee * __builtin_fma(dd, r0, rD[tp]);
-                        rR[tp] = __builtin_fma(ee, r0, (double)av);
-                        rtau[tp] = ti;
+            for (int32_t g = 0; g < ne; g += 64) {
+                const int32_t f = g + lane;
+                const bool vf = f < ne;
+                int32_t tp = 0, ej = k;
+                float av = 0.0f;
+                if (vf) {
+                    if (staged) {
+                        tp = st_row[f];
+                        av = st_val[f];
+                        ej = st_evt[f];
+                    } else {
+                        const int2 e = csc_cv[cbk + f];
+                        tp = e.x;
+                        av = __int_as_float(e.y);
                     }
                 }
+                const double bt = (double)beta[tp];
+                const double tj = ev_t[ej];
+                // claim: the first entry of its target moves the record to tB
+                double told = tB;
+                if (vf) told = __longlong_as_double((long long)atomicExch(
+                             (unsigned long long*)&rtau[tp], (unsigned long long)__double_as_longlong(tB)));
+                if (vf && told != tB) {
+                    const double d0 = tB - told;
+                    const double e0 = exp_f64(-bt * d0);
+                    const double r0 = rR[tp];
+                    rD[tp] = e0 * __builtin_fma(d0, r0, rD[tp]);
+                    rR[tp] = e0 * r0;
+                }
+                lds_wait();   // the moves land before any entry's add
+                const double dB = tB - tj;
+                const double c = (double)av * exp_f64(-bt * dB);
+                if (vf) {
+                    atomicAdd(&rR[tp], c);
+                    atomicAdd(&rD[tp], dB * c);
+                    // later events of the batch whose own target is tp
+                    uint64_t mk = 0ull;
+                    int sl = pt_hslot(tp);
+                    for (;;) {
+                        const int key = hkey[sl];
+                        if (key == tp) { mk = hmask[sl]; break; }
+                        if (key == -1) break;
+                        sl = (sl + 1) & 127;
+                    }
+                    mk &= ~((2ull << ej) - 1ull);
+                    while (mk) {
+                        const int i = __builtin_ctzll(mk);
+                        mk &= mk - 1;
+                        const double di = ev_t[i] - tj;
+                        const double ci = (double)av * exp_f64(-bt * di);
+                        atomicAdd(&shR[i], ci);
+                        atomicAdd(&shD[i], di * ci);
+                    }
+                }
+                lds_wait();
             }
-            __syncthreads();
+            if (staged) __syncthreads();   // the stage is free again
+            k = k2;
         }
+        __syncthreads();
+        // 3. the event's intensity
         if (ve) {
-            const double bm = (double)beta[mv];
+            Rk += shR[lane];
+            Dk += shD[lane];
             const double lam = (double)mu[mv] + bm * Rk;
             logsum += log(lam);
             if (INTENS) lambda_out[ie] = (float)lam;
@@ -709,7 +781,7 @@ hawkes_status run_large_pt(LargeArgs& A, hipStream_t st) {
     const int64_t MM = (int64_t)M * M;
     const unsigned gM = (unsigned)((M + 255) / 256);
     const size_t lds_agg = (size_t)3 * M * sizeof(double);
-    const size_t lds_fwd = (size_t)4 * M * sizeof(double) + (size_t)PT_STAGE * 12;
+    const size_t lds_fwd = (size_t)4 * M * sizeof(double) + PT_BATCH_LDS + (size_t)PT_STAGE * 12;
     const size_t lds_rev = (size_t)M * sizeof(double);
     if (allow_lds((const void*)pt_seg_agg, lds_agg) != HAWKES_OK ||
         allow_lds((const void*)pt_forward<true, false>, lds_fwd) != HAWKES_OK ||

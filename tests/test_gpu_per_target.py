@@ -66,8 +66,8 @@ def test_per_target_gradient_checkpoint_levels(H, n, M):
 
 
 def test_per_target_node_limit(H):
-    # the per-target forward kernel keeps 32 bytes of LDS per node plus a
-    # 24 KiB staging area: M <= 4352 under MI355X's 160 KiB per workgroup,
+    # the per-target forward kernel keeps 32 bytes of LDS per node plus 24 KiB
+    # of staging and batch tables: M <= 4352 under MI355X's 160 KiB per workgroup,
     # one node more is refused on the host before any launch
     import torch
     from tests.test_gpu_parity import dev
