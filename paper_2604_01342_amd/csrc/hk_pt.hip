@@ -35,9 +35,13 @@
 namespace hk {
 
 // capacity of the per-batch staging of alpha columns in the forward kernel
-// (12 bytes an entry); the forward kernel's batch area takes PT_BATCH_LDS
-#define PT_STAGE 1792
-#define PT_BATCH_LDS (64 * 3 * 8 + 128 * 8 + 128 * 4)
+// (16 bytes an entry); the forward kernel's batch area (event times, shares,
+// the table of own targets with PT_HS slots) takes PT_BATCH_LDS; PT_U column
+// entries a lane per pass of its pushes
+#define PT_STAGE 1248
+#define PT_HS 256
+#define PT_BATCH_LDS (64 * 3 * 8 + PT_HS * 8 + PT_HS * 4)
+#define PT_U 4
 // largest beta_max (t_first - t_last) of a dense-kernel window that takes the
 // merged path: e^64 and e^-64 stay well inside float32's range
 #define HK_PT_MERGE_SPAN 64.0
@@ -145,8 +149,8 @@ __global__ __launch_bounds__(64) void pt_seg_agg(int64_t c0, int64_t c1, int32_t
 }
 
 // slot of target p in the forward kernel's table of a batch's own targets
-// (128 slots for at most 64 keys, open addressing)
-__device__ __forceinline__ int pt_hslot(int p) { return (int)(((uint32_t)p * 2654435761u) >> 25); }
+// (PT_HS = 256 slots for at most 64 keys, open addressing)
+__device__ __forceinline__ int pt_hslot(int p) { return (int)(((uint32_t)p * 2654435761u) >> 24); }
 
 // Forward pass over one segment (one wave), 64 events per batch.  LDS keeps
 // one lazy record per target (time tau_p, R_p and D_p at tau_p), initialised
@@ -182,35 +186,70 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
     double* ev_t = lds + 4 * M;  // [64] the batch's event times
     double* shR = ev_t + 64;     // [64] the batch's in-batch shares of R and D
     double* shD = shR + 64;
-    uint64_t* hmask = (uint64_t*)(shD + 64);   // [128] events of the batch per own target
-    int32_t* hkey = (int32_t*)(hmask + 128);   // [128] own target of the slot, -1 empty
-    int32_t* st_row = hkey + 128;
-    float* st_val = (float*)(st_row + PT_STAGE);
-    int32_t* st_evt = (int32_t*)(st_val + PT_STAGE);
+    uint64_t* hmask = (uint64_t*)(shD + 64);     // [PT_HS] events of the batch per own target
+    int32_t* hkey = (int32_t*)(hmask + PT_HS);   // [PT_HS] own target of the slot, -1 empty
+    int4* stg = (int4*)(hkey + PT_HS);           // [PT_STAGE] (target, alpha, event, beta)
     const int32_t s = blockIdx.x;
     const int lane = threadIdx.x;
     const int64_t a = c0 + (int64_t)s * HK_SEG;
     const int64_t b = a + HK_SEG < c1 ? a + HK_SEG : c1;
     const double tref = a > 0 ? t[a - 1] : t[a];
     const double* cs = carry_seg + (int64_t)s * 2 * M;
-    for (int32_t q = lane; q < M; q += 64) {
-        rtau[q] = tref;
-        rR[q] = cs[q];
-        rD[q] = cs[M + q];
-        gbl[q] = 0.0;
+    // records from the carry, eight rows of 64 in flight at a time
+    for (int32_t q0 = 0; q0 < M; q0 += 512) {
+        double r[8], d[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int32_t q = q0 + 64 * u + lane < M ? q0 + 64 * u + lane : M - 1;
+            r[u] = cs[q];
+            d[u] = cs[M + q];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int32_t q = q0 + 64 * u + lane;
+            if (q < M) {
+                rtau[q] = tref;
+                rR[q] = r[u];
+                rD[q] = d[u];
+                gbl[q] = 0.0;
+            }
+        }
     }
     double logsum = 0.0;
+    // the next batch's event, its column extent, decay and base rate are
+    // loaded one batch ahead (one wave per CU: nothing else hides the
+    // latency of global memory)
+    double tv_n;
+    int mv_n;
+    int32_t cb_n, ce_n;
+    float bm_n, mu_n;
+    {
+        const int64_t ic = a + lane < b ? a + lane : b - 1;
+        tv_n = t[ic];
+        mv_n = clamp_mark(marks[ic], M);
+        cb_n = csc_ptr[mv_n];
+        ce_n = csc_ptr[mv_n + 1];
+        bm_n = beta[mv_n];
+        mu_n = mu[mv_n];
+    }
     for (int64_t base = a; base < b; base += 64) {
         const int64_t ie = base + lane;
         const bool ve = ie < b;
-        const int64_t ic = ve ? ie : b - 1;
-        const double tv = t[ic];
-        const int mv = clamp_mark(marks[ic], M);
+        const double tv = tv_n;
+        const int mv = mv_n;
         const int nb = (int)(b - base < 64 ? b - base : 64);
         const double tB = pt_rdl_d(tv, nb - 1);
+        const double bm = (double)bm_n, mub = (double)mu_n;
         // column extents of the batch's marks and their exclusive prefix
-        const int32_t cb = csc_ptr[mv];
-        const int32_t cn = ve ? csc_ptr[mv + 1] - cb : 0;
+        const int32_t cb = cb_n;
+        const int32_t cn = ve ? ce_n - cb : 0;
+        int mraw_n = 0;
+        {
+            const int64_t i2 = base + 64 + lane;
+            const int64_t ic2 = i2 < b ? i2 : b - 1;
+            tv_n = t[ic2];
+            mraw_n = marks[ic2];
+        }
         int32_t off = cn;
         for (int d = 1; d < 64; d <<= 1) {
             const int32_t u = __shfl_up(off, d, 64);
@@ -220,13 +259,13 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
         ev_t[lane] = tv;
         shR[lane] = 0.0;
         shD[lane] = 0.0;
-        hkey[lane] = -1;
-        hkey[lane + 64] = -1;
-        hmask[lane] = 0ull;
-        hmask[lane + 64] = 0ull;
+#pragma unroll
+        for (int u = 0; u < PT_HS / 64; ++u) {
+            hkey[lane + 64 * u] = -1;
+            hmask[lane + 64 * u] = 0ull;
+        }
         __syncthreads();   // also orders the previous batch's pushes before the reads
         // 1. own target's record at t_i, and the table of own targets
-        const double bm = (double)beta[mv];
         double Rk, Dk;
         {
             const double d = tv - rtau[mv];
@@ -243,29 +282,45 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
                     atomicOr((unsigned long long*)&hmask[sl], 1ull << lane);
                     break;
                 }
-                sl = (sl + 1) & 127;
+                sl = (sl + 1) & (PT_HS - 1);
             }
         }
+        mv_n = clamp_mark(mraw_n, M);
+        cb_n = csc_ptr[mv_n];
+        ce_n = csc_ptr[mv_n + 1];
+        bm_n = beta[mv_n];
+        mu_n = mu[mv_n];
         __syncthreads();
         // 2. pushes, in stretches of events [k, k2) whose entries fit the stage
+        const int32_t cend = off + cn;   // end of the event's entries in the batch
         int k = 0;
         while (k < nb) {
             const int32_t o0 = pt_rdl(off, k);
-            int k2 = k + 1;
-            while (k2 < nb && pt_rdl(off, k2) + pt_rdl(cn, k2) - o0 <= PT_STAGE) ++k2;
-            const bool staged = pt_rdl(off, k) + pt_rdl(cn, k) - o0 <= PT_STAGE;
-            const int32_t ne = pt_rdl(off, k2 - 1) + pt_rdl(cn, k2 - 1) - o0;
+            // events from k on whose entries end inside the stage (a prefix,
+            // the ends grow with the lane); at least event k
+            const int nfit = __builtin_popcountll(
+                __builtin_amdgcn_ballot_w64(lane >= k && lane < nb && cend - o0 <= PT_STAGE));
+            const bool staged = nfit > 0;
+            const int k2 = staged ? k + nfit : k + 1;
+            const int32_t ne = pt_rdl(cend, k2 - 1) - o0;
             const int32_t cbk = pt_rdl(cb, k);
             if (staged) {
                 // short columns: each lane copies its own event's column;
                 // long ones: all lanes copy one column at a time (coalesced)
                 const bool mine = lane >= k && lane < k2;
                 if (mine && cn <= 32) {
-                    for (int32_t j = 0; j < cn; ++j) {
-                        const int2 e = csc_cv[cb + j];
-                        st_row[off - o0 + j] = e.x;
-                        st_val[off - o0 + j] = __int_as_float(e.y);
-                        st_evt[off - o0 + j] = lane;
+                    for (int32_t j0 = 0; j0 < cn; j0 += 8) {
+                        // eight loads in flight, then their targets' decays
+                        int2 e[8];
+                        float bb[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) e[u] = csc_cv[cb + (j0 + u < cn ? j0 + u : cn - 1)];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) bb[u] = beta[e[u].x];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u)
+                            if (j0 + u < cn)
+                                stg[off - o0 + j0 + u] = make_int4(e[u].x, e[u].y, lane, __float_as_int(bb[u]));
                     }
                 }
                 uint64_t big = __ballot(mine && cn > 32);
@@ -275,68 +330,95 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
                     const int32_t nk = pt_rdl(cn, kk), ok = pt_rdl(off, kk) - o0, bk = pt_rdl(cb, kk);
                     for (int32_t j = lane; j < nk; j += 64) {
                         const int2 e = csc_cv[bk + j];
-                        st_row[ok + j] = e.x;
-                        st_val[ok + j] = __int_as_float(e.y);
-                        st_evt[ok + j] = kk;
+                        stg[ok + j] = make_int4(e.x, e.y, kk, __float_as_int(beta[e.x]));
                     }
                 }
                 __syncthreads();
             }
-            for (int32_t g = 0; g < ne; g += 64) {
-                const int32_t f = g + lane;
-                const bool vf = f < ne;
-                int32_t tp = 0, ej = k;
-                float av = 0.0f;
-                if (vf) {
+            // PT_U entries a lane per pass: their loads, claims and table
+            // probes in flight together, their decays as straight-line code
+            for (int32_t g = 0; g < ne; g += 64 * PT_U) {
+                int32_t tp[PT_U], ej[PT_U];
+                double av[PT_U], bt[PT_U];
+                bool vf[PT_U];
+#pragma unroll
+                for (int u = 0; u < PT_U; ++u) {
+                    const int32_t f = g + 64 * u + lane;
+                    vf[u] = f < ne;
                     if (staged) {
-                        tp = st_row[f];
-                        av = st_val[f];
-                        ej = st_evt[f];
+                        const int4 r = stg[vf[u] ? f : 0];
+                        tp[u] = r.x;
+                        av[u] = (double)__int_as_float(r.y);
+                        ej[u] = r.z;
+                        bt[u] = (double)__int_as_float(r.w);
                     } else {
-                        const int2 e = csc_cv[cbk + f];
-                        tp = e.x;
-                        av = __int_as_float(e.y);
+                        const int2 e = csc_cv[cbk + (vf[u] ? f : 0)];
+                        tp[u] = e.x;
+                        av[u] = (double)__int_as_float(e.y);
+                        ej[u] = k;
+                        bt[u] = (double)beta[e.x];
                     }
                 }
-                const double bt = (double)beta[tp];
-                const double tj = ev_t[ej];
                 // claim: the first entry of its target moves the record to tB
-                double told = tB;
-                if (vf) told = __longlong_as_double((long long)atomicExch(
-                             (unsigned long long*)&rtau[tp], (unsigned long long)__double_as_longlong(tB)));
-                if (vf && told != tB) {
-                    const double d0 = tB - told;
-                    const double e0 = exp_f64(-bt * d0);
-                    const double r0 = rR[tp];
-                    rD[tp] = e0 * __builtin_fma(d0, r0, rD[tp]);
-                    rR[tp] = e0 * r0;
+                double told[PT_U], tj[PT_U];
+                int key[PT_U], sl[PT_U];
+                uint64_t hm[PT_U];
+#pragma unroll
+                for (int u = 0; u < PT_U; ++u) {
+                    tj[u] = ev_t[ej[u]];
+                    told[u] = tB;
+                    if (vf[u])
+                        told[u] = __longlong_as_double((long long)atomicExch(
+                            (unsigned long long*)&rtau[tp[u]], (unsigned long long)__double_as_longlong(tB)));
+                    sl[u] = pt_hslot(tp[u]);
+                    key[u] = hkey[sl[u]];
+                    hm[u] = hmask[sl[u]];
+                }
+                double e0[PT_U], c[PT_U], dB[PT_U];
+#pragma unroll
+                for (int u = 0; u < PT_U; ++u) {
+                    e0[u] = exp_f64(-bt[u] * (tB - told[u]));   // 1 unless claimed
+                    dB[u] = tB - tj[u];
+                    c[u] = av[u] * exp_f64(-bt[u] * dB[u]);
+                }
+#pragma unroll
+                for (int u = 0; u < PT_U; ++u) {
+                    if (vf[u] && told[u] != tB) {
+                        const double d0 = tB - told[u];
+                        const double r0 = rR[tp[u]];
+                        rD[tp[u]] = e0[u] * __builtin_fma(d0, r0, rD[tp[u]]);
+                        rR[tp[u]] = e0[u] * r0;
+                    }
                 }
                 lds_wait();   // the moves land before any entry's add
-                const double dB = tB - tj;
-                const double c = (double)av * exp_f64(-bt * dB);
-                if (vf) {
-                    atomicAdd(&rR[tp], c);
-                    atomicAdd(&rD[tp], dB * c);
-                    // later events of the batch whose own target is tp
-                    uint64_t mk = 0ull;
-                    int sl = pt_hslot(tp);
-                    for (;;) {
-                        const int key = hkey[sl];
-                        if (key == tp) { mk = hmask[sl]; break; }
-                        if (key == -1) break;
-                        sl = (sl + 1) & 127;
-                    }
-                    mk &= ~((2ull << ej) - 1ull);
-                    while (mk) {
-                        const int i = __builtin_ctzll(mk);
-                        mk &= mk - 1;
-                        const double di = ev_t[i] - tj;
-                        const double ci = (double)av * exp_f64(-bt * di);
-                        atomicAdd(&shR[i], ci);
-                        atomicAdd(&shD[i], di * ci);
+#pragma unroll
+                for (int u = 0; u < PT_U; ++u) {
+                    if (vf[u]) {
+                        atomicAdd(&rR[tp[u]], c[u]);
+                        atomicAdd(&rD[tp[u]], dB[u] * c[u]);
                     }
                 }
-                lds_wait();
+                // later events of the batch whose own target is tp: their
+                // share at t_i (rare: the batch has 64 own targets of M)
+#pragma unroll
+                for (int u = 0; u < PT_U; ++u) {
+                    if (vf[u]) {
+                        while (key[u] != tp[u] && key[u] != -1) {
+                            sl[u] = (sl[u] + 1) & (PT_HS - 1);
+                            key[u] = hkey[sl[u]];
+                            hm[u] = hmask[sl[u]];
+                        }
+                        uint64_t mk = key[u] == tp[u] ? hm[u] & ~((2ull << ej[u]) - 1ull) : 0ull;
+                        while (mk) {
+                            const int i = __builtin_ctzll(mk);
+                            mk &= mk - 1;
+                            const double di = ev_t[i] - tj[u];
+                            const double ci = av[u] * exp_f64(-bt[u] * di);
+                            atomicAdd(&shR[i], ci);
+                            atomicAdd(&shD[i], di * ci);
+                        }
+                    }
+                }
             }
             if (staged) __syncthreads();   // the stage is free again
             k = k2;
@@ -346,7 +428,7 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
         if (ve) {
             Rk += shR[lane];
             Dk += shD[lane];
-            const double lam = (double)mu[mv] + bm * Rk;
+            const double lam = mub + bm * Rk;
             logsum += log(lam);
             if (INTENS) lambda_out[ie] = (float)lam;
             if (GRAD) {
@@ -360,7 +442,16 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
         // the segment's row of ebseg becomes EB - GB (minus its dL/dbeta share)
         __syncthreads();
         double* oe = ebseg + (int64_t)s * M;
-        for (int32_t q = lane; q < M; q += 64) oe[q] -= gbl[q];
+        for (int32_t q0 = 0; q0 < M; q0 += 512) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = oe[q0 + 64 * u + lane < M ? q0 + 64 * u + lane : M - 1];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int32_t q = q0 + 64 * u + lane;
+                if (q < M) oe[q] = v[u] - gbl[q];
+            }
+        }
     }
     for (int off = 32; off > 0; off >>= 1) logsum += __shfl_down(logsum, off, 64);
     if (lane == 0) {
@@ -781,7 +872,7 @@ hawkes_status run_large_pt(LargeArgs& A, hipStream_t st) {
     const int64_t MM = (int64_t)M * M;
     const unsigned gM = (unsigned)((M + 255) / 256);
     const size_t lds_agg = (size_t)3 * M * sizeof(double);
-    const size_t lds_fwd = (size_t)4 * M * sizeof(double) + PT_BATCH_LDS + (size_t)PT_STAGE * 12;
+    const size_t lds_fwd = (size_t)4 * M * sizeof(double) + PT_BATCH_LDS + (size_t)PT_STAGE * 16;
     const size_t lds_rev = (size_t)M * sizeof(double);
     if (allow_lds((const void*)pt_seg_agg, lds_agg) != HAWKES_OK ||
         allow_lds((const void*)pt_forward<true, false>, lds_fwd) != HAWKES_OK ||
