@@ -36,11 +36,10 @@ namespace hk {
 
 // capacity of the per-batch staging of alpha columns in the forward kernel
 // (16 bytes an entry); the forward kernel's batch area (event times, shares,
-// the table of own targets with PT_HS slots) takes PT_BATCH_LDS; PT_U column
-// entries a lane per pass of its pushes
-#define PT_STAGE 1248
-#define PT_HS 256
-#define PT_BATCH_LDS (64 * 3 * 8 + PT_HS * 8 + PT_HS * 4)
+// events per own target) takes PT_BATCH_LDS, its table of own targets one
+// byte per node; PT_U column entries a lane per pass of its pushes
+#define PT_STAGE 1136
+#define PT_BATCH_LDS (64 * 4 * 8)
 #define PT_U 4
 // largest beta_max (t_first - t_last) of a dense-kernel window that takes the
 // merged path: e^64 and e^-64 stay well inside float32's range
@@ -148,10 +147,6 @@ __global__ __launch_bounds__(64) void pt_seg_agg(int64_t c0, int64_t c1, int32_t
     }
 }
 
-// slot of target p in the forward kernel's table of a batch's own targets
-// (PT_HS = 256 slots for at most 64 keys, open addressing)
-__device__ __forceinline__ int pt_hslot(int p) { return (int)(((uint32_t)p * 2654435761u) >> 24); }
-
 // Forward pass over one segment (one wave), 64 events per batch.  LDS keeps
 // one lazy record per target (time tau_p, R_p and D_p at tau_p), initialised
 // from the scanned carry.  Per batch:
@@ -186,9 +181,10 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
     double* ev_t = lds + 4 * M;  // [64] the batch's event times
     double* shR = ev_t + 64;     // [64] the batch's in-batch shares of R and D
     double* shD = shR + 64;
-    uint64_t* hmask = (uint64_t*)(shD + 64);     // [PT_HS] events of the batch per own target
-    int32_t* hkey = (int32_t*)(hmask + PT_HS);   // [PT_HS] own target of the slot, -1 empty
-    int4* stg = (int4*)(hkey + PT_HS);           // [PT_STAGE] (target, alpha, event, beta)
+    uint64_t* smask = (uint64_t*)(shD + 64);   // [64] events of the batch with event i's own target
+    int4* stg = (int4*)(smask + 64);           // [PT_STAGE] (target, alpha, event, beta)
+    // [M] per target: an event of the batch with that own target, 0xff none
+    uint8_t* tev = (uint8_t*)(stg + PT_STAGE);
     const int32_t s = blockIdx.x;
     const int lane = threadIdx.x;
     const int64_t a = c0 + (int64_t)s * HK_SEG;
@@ -215,6 +211,7 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
             }
         }
     }
+    for (int32_t q = lane; q < M; q += 64) tev[q] = 0xff;
     double logsum = 0.0;
     // the next batch's event, its column extent, decay and base rate are
     // loaded one batch ahead (one wave per CU: nothing else hides the
@@ -259,11 +256,7 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
         ev_t[lane] = tv;
         shR[lane] = 0.0;
         shD[lane] = 0.0;
-#pragma unroll
-        for (int u = 0; u < PT_HS / 64; ++u) {
-            hkey[lane + 64 * u] = -1;
-            hmask[lane + 64 * u] = 0ull;
-        }
+        smask[lane] = 0ull;
         __syncthreads();   // also orders the previous batch's pushes before the reads
         // 1. own target's record at t_i, and the table of own targets
         double Rk, Dk;
@@ -274,17 +267,11 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
             Rk = e * r;
             Dk = e * __builtin_fma(d, r, rD[mv]);
         }
-        if (ve) {
-            int sl = pt_hslot(mv);
-            for (;;) {
-                const int old = atomicCAS(&hkey[sl], -1, mv);
-                if (old == -1 || old == mv) {
-                    atomicOr((unsigned long long*)&hmask[sl], 1ull << lane);
-                    break;
-                }
-                sl = (sl + 1) & (PT_HS - 1);
-            }
-        }
+        // one event per own target stands for all of them (the store that
+        // lands last), and collects their mask
+        if (ve) tev[mv] = (uint8_t)lane;
+        lds_wait();
+        if (ve) atomicOr((unsigned long long*)&smask[tev[mv]], 1ull << lane);
         mv_n = clamp_mark(mraw_n, M);
         cb_n = csc_ptr[mv_n];
         ce_n = csc_ptr[mv_n + 1];
@@ -361,8 +348,7 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
                 }
                 // claim: the first entry of its target moves the record to tB
                 double told[PT_U], tj[PT_U];
-                int key[PT_U], sl[PT_U];
-                uint64_t hm[PT_U];
+                int rep[PT_U];
 #pragma unroll
                 for (int u = 0; u < PT_U; ++u) {
                     tj[u] = ev_t[ej[u]];
@@ -370,10 +356,14 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
                     if (vf[u])
                         told[u] = __longlong_as_double((long long)atomicExch(
                             (unsigned long long*)&rtau[tp[u]], (unsigned long long)__double_as_longlong(tB)));
-                    sl[u] = pt_hslot(tp[u]);
-                    key[u] = hkey[sl[u]];
-                    hm[u] = hmask[sl[u]];
+                    rep[u] = tev[tp[u]];
                 }
+                // events of the batch after the entry's event whose own
+                // target is the entry's (rare: 64 own targets of M)
+                uint64_t mk[PT_U];
+#pragma unroll
+                for (int u = 0; u < PT_U; ++u)
+                    mk[u] = vf[u] && rep[u] != 0xff ? smask[rep[u] & 63] & ~((2ull << ej[u]) - 1ull) : 0ull;
                 double e0[PT_U], c[PT_U], dB[PT_U];
 #pragma unroll
                 for (int u = 0; u < PT_U; ++u) {
@@ -398,25 +388,33 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
                         atomicAdd(&rD[tp[u]], dB[u] * c[u]);
                     }
                 }
-                // later events of the batch whose own target is tp: their
-                // share at t_i (rare: the batch has 64 own targets of M)
+                // their shares at t_i, one (entry, event) pair a lane per round
+                for (;;) {
+                    int i = -1;
+                    double tju = 0.0, avu = 0.0, btu = 0.0;
 #pragma unroll
-                for (int u = 0; u < PT_U; ++u) {
-                    if (vf[u]) {
-                        while (key[u] != tp[u] && key[u] != -1) {
-                            sl[u] = (sl[u] + 1) & (PT_HS - 1);
-                            key[u] = hkey[sl[u]];
-                            hm[u] = hmask[sl[u]];
+                    for (int u = PT_U - 1; u >= 0; --u) {
+                        if (mk[u]) {
+                            i = __builtin_ctzll(mk[u]);
+                            tju = tj[u];
+                            avu = av[u];
+                            btu = bt[u];
                         }
-                        uint64_t mk = key[u] == tp[u] ? hm[u] & ~((2ull << ej[u]) - 1ull) : 0ull;
-                        while (mk) {
-                            const int i = __builtin_ctzll(mk);
-                            mk &= mk - 1;
-                            const double di = ev_t[i] - tj[u];
-                            const double ci = av[u] * exp_f64(-bt[u] * di);
-                            atomicAdd(&shR[i], ci);
-                            atomicAdd(&shD[i], di * ci);
+                    }
+                    if (!__builtin_amdgcn_ballot_w64(i >= 0)) break;
+                    bool done = false;
+#pragma unroll
+                    for (int u = 0; u < PT_U; ++u) {
+                        if (!done && mk[u]) {
+                            mk[u] &= mk[u] - 1;
+                            done = true;
                         }
+                    }
+                    if (i >= 0) {
+                        const double di = ev_t[i] - tju;
+                        const double ci = avu * exp_f64(-btu * di);
+                        atomicAdd(&shR[i], ci);
+                        atomicAdd(&shD[i], di * ci);
                     }
                 }
             }
@@ -424,6 +422,7 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
             k = k2;
         }
         __syncthreads();
+        if (ve) tev[mv] = 0xff;   // the table is empty again for the next batch
         // 3. the event's intensity
         if (ve) {
             Rk += shR[lane];
@@ -872,7 +871,8 @@ hawkes_status run_large_pt(LargeArgs& A, hipStream_t st) {
     const int64_t MM = (int64_t)M * M;
     const unsigned gM = (unsigned)((M + 255) / 256);
     const size_t lds_agg = (size_t)3 * M * sizeof(double);
-    const size_t lds_fwd = (size_t)4 * M * sizeof(double) + PT_BATCH_LDS + (size_t)PT_STAGE * 16;
+    const size_t lds_fwd = (size_t)4 * M * sizeof(double) + PT_BATCH_LDS + (size_t)PT_STAGE * 16 +
+                           (size_t)((M + 15) & ~15);
     const size_t lds_rev = (size_t)M * sizeof(double);
     if (allow_lds((const void*)pt_seg_agg, lds_agg) != HAWKES_OK ||
         allow_lds((const void*)pt_forward<true, false>, lds_fwd) != HAWKES_OK ||
