@@ -56,6 +56,15 @@ __global__ void pt_copy(double* __restrict__ dst, const double* __restrict__ src
         dst[i] = src[i];
 }
 
+// csc_b[k] = beta of the target of column entry k (the decay that entry's
+// push uses, so a pass reads it with the entry instead of a second gather)
+__global__ void pt_csc_beta(int32_t M, const int32_t* __restrict__ csc_ptr, const int2* __restrict__ csc_cv,
+                            const float* __restrict__ beta, float* __restrict__ csc_b) {
+    const int32_t nnz = csc_ptr[M];
+    for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nnz; k += gridDim.x * blockDim.x)
+        csc_b[k] = beta[csc_cv[k].x];
+}
+
 // adjoint seed at T: A_p(T) = 1 / beta_p
 __global__ void pt_seed(int32_t M, const float* __restrict__ beta, double* __restrict__ a) {
     const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -80,7 +89,8 @@ __device__ __forceinline__ double pt_rdl_d(double v, int k) {
 __global__ __launch_bounds__(64) void pt_seg_agg(int64_t c0, int64_t c1, int32_t M, double T,
                                                  const double* __restrict__ t, const int32_t* __restrict__ marks,
                                                  const float* __restrict__ beta, const int32_t* __restrict__ csc_ptr,
-                                                 const int2* __restrict__ csc_cv, double* __restrict__ agg,
+                                                 const int2* __restrict__ csc_cv, const float* __restrict__ csc_b,
+                                                 double* __restrict__ agg,
                                                  double* __restrict__ seg_span, double* __restrict__ ebseg,
                                                  double* __restrict__ seg_part) {
     extern __shared__ double lds[];
@@ -111,9 +121,8 @@ __global__ __launch_bounds__(64) void pt_seg_agg(int64_t c0, int64_t c1, int32_t
                     const int2 e = csc_cv[k];
                     pv[j] = e.x;
                     av[j] = __int_as_float(e.y);
+                    bv[j] = csc_b[k];
                 }
-#pragma unroll
-                for (int j = 0; j < 8; ++j) bv[j] = beta[pv[j]];
                 // no branch inside the eight: entries past the column add
                 // zeros (alpha taken as 0), so the eight entries' exp chains
                 // interleave
@@ -168,7 +177,7 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
                                                  const double* __restrict__ t, const int32_t* __restrict__ marks,
                                                  const float* __restrict__ mu, const float* __restrict__ beta,
                                                  const int32_t* __restrict__ csc_ptr,
-                                                 const int2* __restrict__ csc_cv,
+                                                 const int2* __restrict__ csc_cv, const float* __restrict__ csc_b,
                                                  const double* __restrict__ carry_seg, double* __restrict__ seg_part,
                                                  double* __restrict__ ebseg, float* __restrict__ wv,
                                                  float* __restrict__ lambda_out) {
@@ -297,13 +306,15 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
                 const bool mine = lane >= k && lane < k2;
                 if (mine && cn <= 32) {
                     for (int32_t j0 = 0; j0 < cn; j0 += 8) {
-                        // eight loads in flight, then their targets' decays
+                        // eight entries and their targets' decays in flight
                         int2 e[8];
                         float bb[8];
 #pragma unroll
-                        for (int u = 0; u < 8; ++u) e[u] = csc_cv[cb + (j0 + u < cn ? j0 + u : cn - 1)];
-#pragma unroll
-                        for (int u = 0; u < 8; ++u) bb[u] = beta[e[u].x];
+                        for (int u = 0; u < 8; ++u) {
+                            const int32_t kq = cb + (j0 + u < cn ? j0 + u : cn - 1);
+                            e[u] = csc_cv[kq];
+                            bb[u] = csc_b[kq];
+                        }
 #pragma unroll
                         for (int u = 0; u < 8; ++u)
                             if (j0 + u < cn)
@@ -317,7 +328,7 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
                     const int32_t nk = pt_rdl(cn, kk), ok = pt_rdl(off, kk) - o0, bk = pt_rdl(cb, kk);
                     for (int32_t j = lane; j < nk; j += 64) {
                         const int2 e = csc_cv[bk + j];
-                        stg[ok + j] = make_int4(e.x, e.y, kk, __float_as_int(beta[e.x]));
+                        stg[ok + j] = make_int4(e.x, e.y, kk, __float_as_int(csc_b[bk + j]));
                     }
                 }
                 __syncthreads();
@@ -339,11 +350,12 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
                         ej[u] = r.z;
                         bt[u] = (double)__int_as_float(r.w);
                     } else {
-                        const int2 e = csc_cv[cbk + (vf[u] ? f : 0)];
+                        const int32_t kq = cbk + (vf[u] ? f : 0);
+                        const int2 e = csc_cv[kq];
                         tp[u] = e.x;
                         av[u] = (double)__int_as_float(e.y);
                         ej[u] = k;
-                        bt[u] = (double)beta[e.x];
+                        bt[u] = (double)csc_b[kq];
                     }
                 }
                 // claim: the first entry of its target moves the record to tB
@@ -896,6 +908,10 @@ hawkes_status run_large_pt(LargeArgs& A, hipStream_t st) {
         fill(A.cpart_, (int64_t)A.ER * M, 0.0);
     }
     large_build_index(M, A.alpha, 1, A.csc_ptr, A.csc_cv, st);
+    // the per-target engine builds no row index: its buffer holds the decay
+    // of every column entry's target
+    float* csc_b = reinterpret_cast<float*>(A.csr_cv);
+    hipLaunchKernelGGL(pt_csc_beta, dim3(1024), dim3(256), 0, st, M, A.csc_ptr, A.csc_cv, A.beta, csc_b);
     const int64_t M2 = 2 * (int64_t)M;
     auto chunk_range = [&](int64_t ch, int64_t& c0, int64_t& c1) -> int32_t {
         c0 = ch * A.CH;
@@ -908,7 +924,7 @@ hawkes_status run_large_pt(LargeArgs& A, hipStream_t st) {
         {
             TimedScope ts(2, st);
             hipLaunchKernelGGL(pt_seg_agg, dim3(nseg), dim3(64), lds_agg, st, c0, c1, M, A.T, A.t, A.marks, A.beta,
-                               A.csc_ptr, A.csc_cv, A.agg, A.seg_span, A.ebseg, A.seg_part);
+                               A.csc_ptr, A.csc_cv, csc_b, A.agg, A.seg_span, A.ebseg, A.seg_part);
         }
         TimedScope ts(3, st);
         large_scan(A, nseg, A.beta, st);
@@ -919,15 +935,15 @@ hawkes_status run_large_pt(LargeArgs& A, hipStream_t st) {
             TimedScope ts(1, st);
             if (A.grad)
                 hipLaunchKernelGGL((pt_forward<true, false>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1, M, A.T, A.t,
-                                   A.marks, A.mu, A.beta, A.csc_ptr, A.csc_cv, A.carry_seg, A.seg_part,
+                                   A.marks, A.mu, A.beta, A.csc_ptr, A.csc_cv, csc_b, A.carry_seg, A.seg_part,
                                    A.ebseg, A.wv, (float*)nullptr);
             else if (A.lambda_out)
                 hipLaunchKernelGGL((pt_forward<false, true>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1, M, A.T, A.t,
-                                   A.marks, A.mu, A.beta, A.csc_ptr, A.csc_cv, A.carry_seg, A.seg_part,
+                                   A.marks, A.mu, A.beta, A.csc_ptr, A.csc_cv, csc_b, A.carry_seg, A.seg_part,
                                    A.ebseg, (float*)nullptr, A.lambda_out);
             else
                 hipLaunchKernelGGL((pt_forward<false, false>), dim3(nseg), dim3(64), lds_fwd, st, c0, c1, M, A.T,
-                                   A.t, A.marks, A.mu, A.beta, A.csc_ptr, A.csc_cv, A.carry_seg,
+                                   A.t, A.marks, A.mu, A.beta, A.csc_ptr, A.csc_cv, csc_b, A.carry_seg,
                                    A.seg_part, A.ebseg, (float*)nullptr, (float*)nullptr);
         }
         large_chunk_acc_launch(nseg, 4, A.seg_part, A.acc, st);
