@@ -41,6 +41,8 @@ namespace hk {
 #define PT_STAGE 1136
 #define PT_BATCH_LDS (64 * 4 * 8)
 #define PT_U 4
+// capacity of the segment aggregation's stage (16 bytes an entry)
+#define PT_STAGE_AGG 2048
 // largest beta_max (t_first - t_last) of a dense-kernel window that takes the
 // merged path: e^64 and e^-64 stay well inside float32's range
 #define HK_PT_MERGE_SPAN 64.0
@@ -84,60 +86,131 @@ __device__ __forceinline__ double pt_rdl_d(double v, int k) {
 // segment's own events.  Also the two compensator sums of the segment:
 // sum_j sum_p alpha_{p,m_j} (1 - e^{-beta_p (T - t_j)}) into seg_part[s][1]
 // and, per target, sum_j alpha_{p,m_j} (T - t_j) e^{-beta_p (T - t_j)}.
-// One wave per segment; lanes take events and push their alpha column.
-// LDS: aR[M], aD[M], aE[M] (float64).
+// One wave per segment.  The terms are plain sums, so the alpha-column entries
+// of 64 events at a time are staged in LDS and taken PT_U a lane per pass
+// (lanes over entries, not events: a column averages a few entries).  An
+// entry's compensator terms need e^{-beta_p (T - t_j)}, zero in float64 past
+// an exponent of 745: then the entry adds its alpha to the sum and nothing
+// to the per-target one, with no exponential (every entry of a segment far
+// from T).  LDS: aR[M], aD[M], aE[M] (float64), the batch's event times and
+// the stage.
 __global__ __launch_bounds__(64) void pt_seg_agg(int64_t c0, int64_t c1, int32_t M, double T,
                                                  const double* __restrict__ t, const int32_t* __restrict__ marks,
                                                  const float* __restrict__ beta, const int32_t* __restrict__ csc_ptr,
                                                  const int2* __restrict__ csc_cv, const float* __restrict__ csc_b,
-                                                 double* __restrict__ agg,
-                                                 double* __restrict__ seg_span, double* __restrict__ ebseg,
-                                                 double* __restrict__ seg_part) {
+                                                 double* __restrict__ agg, double* __restrict__ seg_span,
+                                                 double* __restrict__ ebseg, double* __restrict__ seg_part) {
     extern __shared__ double lds[];
     double* aR = lds;
     double* aD = lds + M;
     double* aE = lds + 2 * M;
+    double* ev_t = lds + 3 * M;          // [64]
+    int4* stg = (int4*)(ev_t + 64);      // [PT_STAGE_AGG] (target, alpha, event, beta)
     const int32_t s = blockIdx.x;
     const int64_t a = c0 + (int64_t)s * HK_SEG;
     const int64_t b = a + HK_SEG < c1 ? a + HK_SEG : c1;
     const int lane = threadIdx.x;
     for (int32_t q = lane; q < M; q += 64) { aR[q] = 0.0; aD[q] = 0.0; aE[q] = 0.0; }
-    __syncthreads();
     const double te = t[b - 1];
     double comp = 0.0;
     for (int64_t base = a; base < b; base += 64) {
         const int64_t i = base + lane;
-        if (i < b) {
-            const double ti = t[i];
-            const int q = clamp_mark(marks[i], M);
-            const double d = te - ti, x0 = T - ti;
-            const int32_t k0 = csc_ptr[q], k1 = csc_ptr[q + 1];
-            for (int32_t kb = k0; kb < k1; kb += 8) {
-                int32_t pv[8];
-                float av[8], bv[8];
+        const bool ve = i < b;
+        const int64_t ic = ve ? i : b - 1;
+        const double tv = t[ic];
+        const int q = clamp_mark(marks[ic], M);
+        const int32_t cb = csc_ptr[q];
+        const int32_t cn = ve ? csc_ptr[q + 1] - cb : 0;
+        int32_t off = cn;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int32_t u = __shfl_up(off, d, 64);
+            if (lane >= d) off += u;
+        }
+        off -= cn;   // exclusive
+        const int32_t cend = off + cn;
+        const int nb = (int)(b - base < 64 ? b - base : 64);
+        __syncthreads();   // the previous batch is done with ev_t and the stage
+        ev_t[lane] = tv;
+        int k = 0;
+        while (k < nb) {
+            const int32_t o0 = pt_rdl(off, k);
+            const int nfit = __builtin_popcountll(
+                __builtin_amdgcn_ballot_w64(lane >= k && lane < nb && cend - o0 <= PT_STAGE_AGG));
+            const bool staged = nfit > 0;
+            const int k2 = staged ? k + nfit : k + 1;
+            const int32_t ne = pt_rdl(cend, k2 - 1) - o0;
+            const int32_t cbk = pt_rdl(cb, k);
+            if (staged) {
+                const bool mine = lane >= k && lane < k2;
+                if (mine && cn <= 32) {
+                    for (int32_t j0 = 0; j0 < cn; j0 += 8) {
+                        int2 e[8];
+                        float bb[8];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const int32_t k = kb + j < k1 ? kb + j : k1 - 1;
-                    const int2 e = csc_cv[k];
-                    pv[j] = e.x;
-                    av[j] = __int_as_float(e.y);
-                    bv[j] = csc_b[k];
+                        for (int u = 0; u < 8; ++u) {
+                            const int32_t kq = cb + (j0 + u < cn ? j0 + u : cn - 1);
+                            e[u] = csc_cv[kq];
+                            bb[u] = csc_b[kq];
+                        }
+#pragma unroll
+                        for (int u = 0; u < 8; ++u)
+                            if (j0 + u < cn)
+                                stg[off - o0 + j0 + u] = make_int4(e[u].x, e[u].y, lane, __float_as_int(bb[u]));
+                    }
                 }
-                // no branch inside the eight: entries past the column add
-                // zeros (alpha taken as 0), so the eight entries' exp chains
-                // interleave
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const int32_t p = pv[j];
-                    const double al = kb + j < k1 ? (double)av[j] : 0.0, bp = (double)bv[j];
-                    const double e = exp_f64(-bp * d);
-                    atomicAdd(&aR[p], al * e);
-                    atomicAdd(&aD[p], al * d * e);
-                    const double x = bp * x0;
-                    atomicAdd(&aE[p], al * x0 * exp_f64(-x));
-                    comp += al * -expm1(-x);
+                uint64_t big = __ballot(mine && cn > 32);
+                while (big) {
+                    const int kk = __builtin_ctzll(big);
+                    big &= big - 1;
+                    const int32_t nk = pt_rdl(cn, kk), ok = pt_rdl(off, kk) - o0, bk = pt_rdl(cb, kk);
+                    for (int32_t j = lane; j < nk; j += 64) {
+                        const int2 e = csc_cv[bk + j];
+                        stg[ok + j] = make_int4(e.x, e.y, kk, __float_as_int(csc_b[bk + j]));
+                    }
                 }
             }
+            __syncthreads();
+            for (int32_t g = 0; g < ne; g += 64 * PT_U) {
+                int32_t tp[PT_U];
+                double al[PT_U], bt[PT_U], tj[PT_U];
+#pragma unroll
+                for (int u = 0; u < PT_U; ++u) {
+                    const int32_t f = g + 64 * u + lane;
+                    const bool vf = f < ne;
+                    int ej = k;
+                    if (staged) {
+                        const int4 r = stg[vf ? f : 0];
+                        tp[u] = r.x;
+                        al[u] = vf ? (double)__int_as_float(r.y) : 0.0;
+                        ej = r.z;
+                        bt[u] = (double)__int_as_float(r.w);
+                    } else {
+                        const int32_t kq = cbk + (vf ? f : 0);
+                        const int2 e = csc_cv[kq];
+                        tp[u] = e.x;
+                        al[u] = vf ? (double)__int_as_float(e.y) : 0.0;
+                        bt[u] = (double)csc_b[kq];
+                    }
+                    tj[u] = ev_t[ej];
+                }
+                // entries past the list carry alpha = 0 and add zeros
+#pragma unroll
+                for (int u = 0; u < PT_U; ++u) {
+                    const double d = te - tj[u], x0 = T - tj[u];
+                    const double e = exp_f64(-bt[u] * d);
+                    atomicAdd(&aR[tp[u]], al[u] * e);
+                    atomicAdd(&aD[tp[u]], al[u] * d * e);
+                    const double x = bt[u] * x0;
+                    if (x <= 745.0) {
+                        atomicAdd(&aE[tp[u]], al[u] * x0 * exp_f64(-x));
+                        comp += al[u] * -expm1(-x);
+                    } else {
+                        comp += al[u];
+                    }
+                }
+            }
+            __syncthreads();   // the stage is free again
+            k = k2;
         }
     }
     __syncthreads();
@@ -155,6 +228,7 @@ __global__ __launch_bounds__(64) void pt_seg_agg(int64_t c0, int64_t c1, int32_t
         seg_part[(int64_t)s * 4 + 1] = comp;
     }
 }
+
 
 // Forward pass over one segment (one wave), 64 events per batch.  LDS keeps
 // one lazy record per target (time tau_p, R_p and D_p at tau_p), initialised
@@ -882,7 +956,7 @@ hawkes_status run_large_pt(LargeArgs& A, hipStream_t st) {
     const int32_t M = A.M;
     const int64_t MM = (int64_t)M * M;
     const unsigned gM = (unsigned)((M + 255) / 256);
-    const size_t lds_agg = (size_t)3 * M * sizeof(double);
+    const size_t lds_agg = (size_t)3 * M * sizeof(double) + 64 * sizeof(double) + (size_t)PT_STAGE_AGG * 16;
     const size_t lds_fwd = (size_t)4 * M * sizeof(double) + PT_BATCH_LDS + (size_t)PT_STAGE * 16 +
                            (size_t)((M + 15) & ~15);
     const size_t lds_rev = (size_t)M * sizeof(double);
