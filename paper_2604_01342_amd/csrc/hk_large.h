@@ -12,9 +12,6 @@
 #ifndef HK_DW
 #define HK_DW 2            // waves per workgroup of the shared-decay dense kernel
 #endif
-#ifndef HK_DWP
-#define HK_DWP 4           // waves per workgroup of the per-target dense kernel
-#endif
 #ifndef HK_CKR
 #define HK_CKR 4           // segments per checkpoint run of the shared-decay dense gradient
 #endif

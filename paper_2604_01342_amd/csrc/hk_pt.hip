@@ -43,6 +43,12 @@ namespace hk {
 #define PT_U 4
 // capacity of the segment aggregation's stage (16 bytes an entry)
 #define PT_STAGE_AGG 2048
+// waves per workgroup of the dense kernel: eight share the 64 x 64 LDS tile,
+// three workgroups a CU (measured at c5: 3.36 ms per launch against 4.01 with
+// four waves, 4.19 with seven, 4.49 with nine)
+#ifndef HK_DWP
+#define HK_DWP 8
+#endif
 // largest beta_max (t_first - t_last) of a dense-kernel window that takes the
 // merged path: e^64 and e^-64 stay well inside float32's range
 #define HK_PT_MERGE_SPAN 64.0
