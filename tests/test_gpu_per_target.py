@@ -54,6 +54,16 @@ def test_per_target_window_forms(H, M, chunk):
     check(run_gpu(H, t, m, mu, alpha, beta, T, chunk), ref, label=f"per-target window forms M={M} chunk={chunk}")
 
 
+# Columns of alpha longer than the forward kernel's stage (1136 entries) and
+# the segment aggregation's (2048): every event's column is pushed straight
+# from global memory, a whole column per pass group.
+@pytest.mark.timeout(300)
+def test_per_target_columns_past_the_stages(H):
+    t, m, mu, alpha, beta, T = rand_problem(57, 2500, 2100, per_target=True, density=1.0, rate=40.0)
+    ref = oracle.adjoint(t, m, mu, alpha, beta, T)
+    check(run_gpu(H, t, m, mu, alpha, beta, T, 0), ref, label="per-target M=2100 dense columns")
+
+
 @pytest.mark.timeout(300)
 @pytest.mark.parametrize("n,M", [(64 * 4096, 20), (64 * 4096 + 1, 20), (300_000, 30), (4096 * 200 + 77, 12)])
 def test_per_target_gradient_checkpoint_levels(H, n, M):
