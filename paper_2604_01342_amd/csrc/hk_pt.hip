@@ -119,14 +119,29 @@ __global__ __launch_bounds__(64) void pt_seg_agg(int64_t c0, int64_t c1, int32_t
     for (int32_t q = lane; q < M; q += 64) { aR[q] = 0.0; aD[q] = 0.0; aE[q] = 0.0; }
     const double te = t[b - 1];
     double comp = 0.0;
+    // the next batch's events and column extents are loaded one batch ahead
+    double tv_n;
+    int32_t cb_n, ce_n;
+    {
+        const int64_t ic = a + lane < b ? a + lane : b - 1;
+        tv_n = t[ic];
+        const int q = clamp_mark(marks[ic], M);
+        cb_n = csc_ptr[q];
+        ce_n = csc_ptr[q + 1];
+    }
     for (int64_t base = a; base < b; base += 64) {
         const int64_t i = base + lane;
         const bool ve = i < b;
-        const int64_t ic = ve ? i : b - 1;
-        const double tv = t[ic];
-        const int q = clamp_mark(marks[ic], M);
-        const int32_t cb = csc_ptr[q];
-        const int32_t cn = ve ? csc_ptr[q + 1] - cb : 0;
+        const double tv = tv_n;
+        const int32_t cb = cb_n;
+        const int32_t cn = ve ? ce_n - cb : 0;
+        int mraw_n;
+        {
+            const int64_t i2 = base + 64 + lane;
+            const int64_t ic2 = i2 < b ? i2 : b - 1;
+            tv_n = t[ic2];
+            mraw_n = marks[ic2];
+        }
         int32_t off = cn;
         for (int d = 1; d < 64; d <<= 1) {
             const int32_t u = __shfl_up(off, d, 64);
@@ -174,6 +189,11 @@ __global__ __launch_bounds__(64) void pt_seg_agg(int64_t c0, int64_t c1, int32_t
                         stg[ok + j] = make_int4(e.x, e.y, kk, __float_as_int(csc_b[bk + j]));
                     }
                 }
+            }
+            if (k == 0) {
+                const int qn = clamp_mark(mraw_n, M);
+                cb_n = csc_ptr[qn];
+                ce_n = csc_ptr[qn + 1];
             }
             __syncthreads();
             for (int32_t g = 0; g < ne; g += 64 * PT_U) {
