@@ -874,7 +874,13 @@ __global__ __launch_bounds__(64 * HK_DWP) void pt_dense(int64_t c0, int64_t c1, 
                 const int dk = __builtin_popcountll(__builtin_amdgcn_ballot_w64(io > (int)(key >> 6)) & omask);
                 for (; j < dk; ++j) {
                     const double f = rl_d(fo, j);
-                    if (lane == (rl_i(okeys, j) & 63)) Ab += f;
+                    if (lane == (rl_i(okeys, j) & 63)) {
+                        Ab += f;
+                        // keeps the add under the lane's exec mask (else the
+                        // compiler adds on every lane and selects: two more
+                        // vector instructions per own event)
+                        __asm__ volatile("" : "+v"(Ab));
+                    }
                 }
                 const float xh0 = rl_f(dh, k), xl0 = rl_f(dl, k);
                 const float xh = bpl * xh0;
@@ -886,7 +892,10 @@ __global__ __launch_bounds__(64 * HK_DWP) void pt_dense(int64_t c0, int64_t c1, 
             // own events older than every slab event of the window
             for (; j < no; ++j) {
                 const double f = rl_d(fo, j);
-                if (lane == (rl_i(okeys, j) & 63)) Ab += f;
+                if (lane == (rl_i(okeys, j) & 63)) {
+                    Ab += f;
+                    __asm__ volatile("" : "+v"(Ab));
+                }
             }
         } else {
             for (int k = 0; k < ns; ++k) {
