@@ -255,19 +255,19 @@ __global__ __launch_bounds__(64) void pt_seg_agg(int64_t c0, int64_t c1, int32_t
     }
 }
 
-
 // Forward pass over one segment (one wave), 64 events per batch.  LDS keeps
 // one lazy record per target (time tau_p, R_p and D_p at tau_p), initialised
 // from the scanned carry.  Per batch:
 //  1. read: lane i moves its own target's record to t_i: R_p(t_i), D_p(t_i)
 //     from the events before the batch;
 //  2. push: the batch's alpha-column entries (event j, target p, alpha),
-//     staged in LDS, 64 at a time, lanes over entries.  The first entry of a
-//     target in the batch moves its record to the batch's last time t_B (it
-//     claims the record by exchanging tau_p for t_B); then every entry adds
-//     alpha e^{-beta_p (t_B - t_j)} to R_p and (t_B - t_j) times that to D_p.
-//     An entry whose target is the own target of a later event i of the
-//     batch (a table of the batch's own targets) adds its share at t_i,
+//     staged in LDS, PT_U a lane per pass, lanes over entries.  The first
+//     entry of a target in the batch moves its record to the batch's last
+//     time t_B (it claims the record by exchanging tau_p for t_B); then every
+//     entry adds alpha e^{-beta_p (t_B - t_j)} to R_p and (t_B - t_j) times
+//     that to D_p.  An entry whose target is the own target of a later event
+//     i of the batch (a byte per node names one batch event with that own
+//     target, a mask per event all of them) adds its share at t_i,
 //     alpha e^{-beta_p (t_i - t_j)}, to that event;
 //  3. finish: lane i adds its shares, lambda_i = mu_p + beta_p R_p(t_i).
 // Events tied in time keep index order (a later event sees an earlier one's
