@@ -43,6 +43,11 @@ namespace hk {
 #define PT_U 4
 // capacity of the segment aggregation's stage (16 bytes an entry)
 #define PT_STAGE_AGG 2048
+// events per workgroup of the chunk chain (512 workgroups for 2^20 events;
+// measured at c5 against 1024 and 4096), and its stage (two workgroups a CU
+// at M = 4096)
+#define PT_CHAIN_EV 2048
+#define PT_STAGE_CHAIN 960
 // waves per workgroup of the dense kernel: eight share the 64 x 64 LDS tile,
 // three workgroups a CU (measured at c5: 3.36 ms per launch against 4.01 with
 // four waves, 4.19 with seven, 4.49 with nine)
@@ -253,6 +258,185 @@ __global__ __launch_bounds__(64) void pt_seg_agg(int64_t c0, int64_t c1, int32_t
         seg_span[s] = te - tr;
         seg_part[(int64_t)s * 4 + 1] = comp;
     }
+}
+
+// Pass 1 of the constant-memory gradient only carries the state from chunk to
+// chunk: the state just after the chunk's last event t_e from the state just
+// after the previous chunk's last event, with no per-segment maps and no
+// scan.  pt_chain_part: a workgroup (one wave) takes PT_CHAIN_EV events of the
+// chunk and sums their alpha-column pushes anchored at t_e in LDS, R_p +=
+// alpha e^{-beta_p (t_e - t_j)} and D_p += (t_e - t_j) alpha e^{...}, lanes
+// over staged column entries as in pt_seg_agg, and writes its partials.
+// pt_chain_fold moves the carry to t_e and adds the partials in workgroup
+// order (fixed order: the state, and every result after it, repeat bitwise).
+template <int STG>
+__global__ __launch_bounds__(64) void pt_chain_part(int64_t c0, int64_t c1, int32_t M, const double* __restrict__ t,
+                                                    const int32_t* __restrict__ marks,
+                                                    const int32_t* __restrict__ csc_ptr,
+                                                    const int2* __restrict__ csc_cv, const float* __restrict__ csc_b,
+                                                    double* __restrict__ part) {
+    extern __shared__ double lds[];
+    double* aR = lds;
+    double* aD = lds + M;
+    double* ev_t = lds + 2 * M;          // [64]
+    int4* stg = (int4*)(ev_t + 64);      // [STG] (target, alpha, event, beta)
+    const int32_t w = blockIdx.x;
+    const int64_t a = c0 + (int64_t)w * PT_CHAIN_EV;
+    const int64_t b = a + PT_CHAIN_EV < c1 ? a + PT_CHAIN_EV : c1;
+    const int lane = threadIdx.x;
+    for (int32_t q = lane; q < M; q += 64) { aR[q] = 0.0; aD[q] = 0.0; }
+    const double te = t[c1 - 1];
+    double tv_n;
+    int32_t cb_n, ce_n;
+    {
+        const int64_t ic = a + lane < b ? a + lane : b - 1;
+        tv_n = t[ic];
+        const int q = clamp_mark(marks[ic], M);
+        cb_n = csc_ptr[q];
+        ce_n = csc_ptr[q + 1];
+    }
+    for (int64_t base = a; base < b; base += 64) {
+        const bool ve = base + lane < b;
+        const double tv = tv_n;
+        const int32_t cb = cb_n;
+        const int32_t cn = ve ? ce_n - cb : 0;
+        int mraw_n;
+        {
+            const int64_t i2 = base + 64 + lane;
+            const int64_t ic2 = i2 < b ? i2 : b - 1;
+            tv_n = t[ic2];
+            mraw_n = marks[ic2];
+        }
+        int32_t off = cn;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int32_t u = __shfl_up(off, d, 64);
+            if (lane >= d) off += u;
+        }
+        off -= cn;   // exclusive
+        const int32_t cend = off + cn;
+        const int nb = (int)(b - base < 64 ? b - base : 64);
+        __syncthreads();   // the previous batch is done with ev_t and the stage
+        ev_t[lane] = tv;
+        int k = 0;
+        while (k < nb) {
+            const int32_t o0 = pt_rdl(off, k);
+            const int nfit = __builtin_popcountll(
+                __builtin_amdgcn_ballot_w64(lane >= k && lane < nb && cend - o0 <= STG));
+            const bool staged = nfit > 0;
+            const int k2 = staged ? k + nfit : k + 1;
+            const int32_t ne = pt_rdl(cend, k2 - 1) - o0;
+            const int32_t cbk = pt_rdl(cb, k);
+            if (staged) {
+                const bool mine = lane >= k && lane < k2;
+                if (mine && cn <= 32) {
+                    for (int32_t j0 = 0; j0 < cn; j0 += 8) {
+                        int2 e[8];
+                        float bb[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            const int32_t kq = cb + (j0 + u < cn ? j0 + u : cn - 1);
+                            e[u] = csc_cv[kq];
+                            bb[u] = csc_b[kq];
+                        }
+#pragma unroll
+                        for (int u = 0; u < 8; ++u)
+                            if (j0 + u < cn)
+                                stg[off - o0 + j0 + u] = make_int4(e[u].x, e[u].y, lane, __float_as_int(bb[u]));
+                    }
+                }
+                uint64_t big = __ballot(mine && cn > 32);
+                while (big) {
+                    const int kk = __builtin_ctzll(big);
+                    big &= big - 1;
+                    const int32_t nk = pt_rdl(cn, kk), ok = pt_rdl(off, kk) - o0, bk = pt_rdl(cb, kk);
+                    for (int32_t j = lane; j < nk; j += 64) {
+                        const int2 e = csc_cv[bk + j];
+                        stg[ok + j] = make_int4(e.x, e.y, kk, __float_as_int(csc_b[bk + j]));
+                    }
+                }
+            }
+            if (k == 0) {
+                const int qn = clamp_mark(mraw_n, M);
+                cb_n = csc_ptr[qn];
+                ce_n = csc_ptr[qn + 1];
+            }
+            __syncthreads();
+            for (int32_t g = 0; g < ne; g += 64 * PT_U) {
+                int32_t tp[PT_U];
+                double al[PT_U], bt[PT_U], tj[PT_U];
+#pragma unroll
+                for (int u = 0; u < PT_U; ++u) {
+                    const int32_t f = g + 64 * u + lane;
+                    const bool vf = f < ne;
+                    int ej = k;
+                    if (staged) {
+                        const int4 r = stg[vf ? f : 0];
+                        tp[u] = r.x;
+                        al[u] = vf ? (double)__int_as_float(r.y) : 0.0;
+                        ej = r.z;
+                        bt[u] = (double)__int_as_float(r.w);
+                    } else {
+                        const int32_t kq = cbk + (vf ? f : 0);
+                        const int2 e = csc_cv[kq];
+                        tp[u] = e.x;
+                        al[u] = vf ? (double)__int_as_float(e.y) : 0.0;
+                        bt[u] = (double)csc_b[kq];
+                    }
+                    tj[u] = ev_t[ej];
+                }
+                // entries past the list carry alpha = 0 and add zeros
+#pragma unroll
+                for (int u = 0; u < PT_U; ++u) {
+                    const double d = te - tj[u];
+                    const double e = exp_f64(-bt[u] * d);
+                    atomicAdd(&aR[tp[u]], al[u] * e);
+                    atomicAdd(&aD[tp[u]], al[u] * d * e);
+                }
+            }
+            __syncthreads();   // the stage is free again
+            k = k2;
+        }
+    }
+    __syncthreads();
+    double* o = part + (int64_t)w * 2 * M;
+    for (int32_t q = lane; q < M; q += 64) {
+        o[q] = aR[q];
+        o[M + q] = aD[q];
+    }
+}
+
+// carry (R, D just after t_r, the previous chunk's last event; t_r = t_0 for
+// the first chunk, whose carry is zero) moved to t_e and the nw partials
+// added: a workgroup of 8 waves per 64 targets, wave g sums its eighth of the
+// partials in order, wave 0 adds the eighths in order
+__global__ __launch_bounds__(512) void pt_chain_fold(int64_t c0, int64_t c1, int32_t M, int32_t nw,
+                                                     const double* __restrict__ t, const float* __restrict__ beta,
+                                                     const double* __restrict__ part, double* __restrict__ carry) {
+    __shared__ double sR[8][64], sD[8][64];
+    const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int32_t p = blockIdx.x * 64 + lane;
+    const int32_t pc = p < M ? p : M - 1;
+    const int32_t w0 = (int32_t)(((int64_t)g * nw) / 8), w1 = (int32_t)(((int64_t)(g + 1) * nw) / 8);
+    double r = 0.0, d = 0.0;
+    for (int32_t w = w0; w < w1; ++w) {
+        r += part[(int64_t)w * 2 * M + pc];
+        d += part[(int64_t)w * 2 * M + M + pc];
+    }
+    sR[g][lane] = r;
+    sD[g][lane] = d;
+    __syncthreads();
+    if (g != 0 || p >= M) return;
+    const double tr = c0 > 0 ? t[c0 - 1] : t[c0], te = t[c1 - 1];
+    const double span = te - tr;
+    const double ex = exp(-(double)beta[p] * span);
+    const double k0 = carry[p];
+    double R = ex * k0, D = ex * __builtin_fma(span, k0, carry[M + p]);
+    for (int h = 0; h < 8; ++h) {
+        R += sR[h][lane];
+        D += sD[h][lane];
+    }
+    carry[p] = R;
+    carry[M + p] = D;
 }
 
 // Forward pass over one segment (one wave), 64 events per batch.  LDS keeps
@@ -995,11 +1179,13 @@ hawkes_status run_large_pt(LargeArgs& A, hipStream_t st) {
     const size_t lds_fwd = (size_t)4 * M * sizeof(double) + PT_BATCH_LDS + (size_t)PT_STAGE * 16 +
                            (size_t)((M + 15) & ~15);
     const size_t lds_rev = (size_t)M * sizeof(double);
+    const size_t lds_chain = (size_t)2 * M * sizeof(double) + 64 * sizeof(double) + (size_t)PT_STAGE_CHAIN * 16;
     if (allow_lds((const void*)pt_seg_agg, lds_agg) != HAWKES_OK ||
         allow_lds((const void*)pt_forward<true, false>, lds_fwd) != HAWKES_OK ||
         allow_lds((const void*)pt_forward<false, true>, lds_fwd) != HAWKES_OK ||
         allow_lds((const void*)pt_forward<false, false>, lds_fwd) != HAWKES_OK ||
-        allow_lds((const void*)pt_rev_agg, lds_rev) != HAWKES_OK)
+        allow_lds((const void*)pt_rev_agg, lds_rev) != HAWKES_OK ||
+        allow_lds((const void*)pt_chain_part<PT_STAGE_CHAIN>, lds_chain) != HAWKES_OK)
         return HAWKES_EUNSUPPORTED;
     // the gradient's two checkpoint levels hold at most HK_PTCK^2 chunks
     if (A.grad && A.pt_ckr > HK_PTCK) return HAWKES_EUNSUPPORTED;
@@ -1038,6 +1224,18 @@ hawkes_status run_large_pt(LargeArgs& A, hipStream_t st) {
         TimedScope ts(3, st);
         large_scan(A, nseg, A.beta, st);
     };
+    // the carry moved over a chunk (pass 1 of the gradient)
+    auto chain = [&](int64_t c0, int64_t c1) {
+        const int32_t nw = (int32_t)((c1 - c0 + PT_CHAIN_EV - 1) / PT_CHAIN_EV);
+        {
+            TimedScope ts(2, st);
+            hipLaunchKernelGGL(pt_chain_part<PT_STAGE_CHAIN>, dim3(nw), dim3(64), lds_chain, st, c0, c1, M, A.t,
+                               A.marks, A.csc_ptr, A.csc_cv, csc_b, A.agg);
+        }
+        TimedScope ts(3, st);
+        hipLaunchKernelGGL(pt_chain_fold, dim3((unsigned)((M + 63) / 64)), dim3(512), 0, st, c0, c1, M, nw, A.t,
+                           A.beta, A.agg, A.carry);
+    };
     // the forward pass of a chunk (after agg_scan), then its call-level sums
     auto forward = [&](int64_t c0, int64_t c1, int32_t nseg) {
         {
@@ -1074,10 +1272,10 @@ hawkes_status run_large_pt(LargeArgs& A, hipStream_t st) {
         // Gradient in constant memory (the batches of Algorithm 2, each
         // forward pass followed by its backward pass; here the backward runs
         // right to left, so the chunks are visited in reverse).  Pass 1 only
-        // chains the chunks' maps and keeps the state at the start of every
-        // r-th chunk (one block of r chunks per level-1 slot); pass 2 takes
-        // the blocks from the last: it chains the block's chunks again from
-        // its slot into the level-2 slots, then per chunk from the last:
+        // carries the state over the chunks (pt_chain_*) and keeps it at the
+        // start of every r-th chunk (one block of r chunks per level-1 slot);
+        // pass 2 takes the blocks from the last: it carries the block's chunks
+        // again from its slot into the level-2 slots, then per chunk from the last:
         // maps and scan from the chunk's start state, the forward pass (w_i
         // of the chunk's events, the chunk's log-likelihood terms), the
         // reverse scan of the adjoint state and the dense dL/dalpha.
@@ -1087,9 +1285,9 @@ hawkes_status run_large_pt(LargeArgs& A, hipStream_t st) {
         double* ck2 = A.pt_ck + (int64_t)HK_PTCK * M2;
         for (int64_t ch = 0; ch < A.nchunks; ++ch) {
             int64_t c0, c1;
-            const int32_t nseg = chunk_range(ch, c0, c1);
+            chunk_range(ch, c0, c1);
             if (ch % r == 0) copy(ck1 + (ch / r) * M2, A.carry);
-            if (ch + 1 < A.nchunks) agg_scan(c0, c1, nseg);
+            if (ch + 1 < A.nchunks) chain(c0, c1);
         }
         hipLaunchKernelGGL(pt_seed, dim3(gM), dim3(256), 0, st, M, A.beta, A.achunk);
         for (int64_t b = nblk_c - 1; b >= 0; --b) {
@@ -1099,9 +1297,9 @@ hawkes_status run_large_pt(LargeArgs& A, hipStream_t st) {
                 copy(A.carry, ck1 + b * M2);
                 for (int64_t ch = cb0; ch < cb1; ++ch) {
                     int64_t c0, c1;
-                    const int32_t nseg = chunk_range(ch, c0, c1);
+                    chunk_range(ch, c0, c1);
                     copy(ck2 + (ch - cb0) * M2, A.carry);
-                    if (ch + 1 < cb1) agg_scan(c0, c1, nseg);
+                    if (ch + 1 < cb1) chain(c0, c1);
                 }
             }
             for (int64_t ch = cb1 - 1; ch >= cb0; --ch) {
