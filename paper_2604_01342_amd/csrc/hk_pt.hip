@@ -105,23 +105,35 @@ __device__ __forceinline__ double pt_rdl_d(double v, int k) {
 // to the per-target one, with no exponential (every entry of a segment far
 // from T).  LDS: aR[M], aD[M], aE[M] (float64), the batch's event times and
 // the stage.
+// FAR: the variant for a chunk in which every entry's e^{-beta_p (T - t_j)}
+// is zero (beta_min (T - t_last) > 745, decided on the device into *near):
+// no per-target compensator array, so two workgroups share a CU at M = 4096;
+// of the two variants launched for a chunk, the one that does not apply
+// returns at once.
+template <bool FAR, int STG>
 __global__ __launch_bounds__(64) void pt_seg_agg(int64_t c0, int64_t c1, int32_t M, double T,
                                                  const double* __restrict__ t, const int32_t* __restrict__ marks,
                                                  const float* __restrict__ beta, const int32_t* __restrict__ csc_ptr,
                                                  const int2* __restrict__ csc_cv, const float* __restrict__ csc_b,
                                                  double* __restrict__ agg, double* __restrict__ seg_span,
-                                                 double* __restrict__ ebseg, double* __restrict__ seg_part) {
+                                                 double* __restrict__ ebseg, double* __restrict__ seg_part,
+                                                 const int32_t* __restrict__ near) {
+    if ((*near != 0) == FAR) return;   // the other variant takes this chunk
     extern __shared__ double lds[];
     double* aR = lds;
     double* aD = lds + M;
-    double* aE = lds + 2 * M;
-    double* ev_t = lds + 3 * M;          // [64]
-    int4* stg = (int4*)(ev_t + 64);      // [PT_STAGE_AGG] (target, alpha, event, beta)
+    double* aE = lds + 2 * M;                  // (unused when FAR)
+    double* ev_t = lds + (FAR ? 2 : 3) * M;    // [64]
+    int4* stg = (int4*)(ev_t + 64);            // [STG] (target, alpha, event, beta)
     const int32_t s = blockIdx.x;
     const int64_t a = c0 + (int64_t)s * HK_SEG;
     const int64_t b = a + HK_SEG < c1 ? a + HK_SEG : c1;
     const int lane = threadIdx.x;
-    for (int32_t q = lane; q < M; q += 64) { aR[q] = 0.0; aD[q] = 0.0; aE[q] = 0.0; }
+    for (int32_t q = lane; q < M; q += 64) {
+        aR[q] = 0.0;
+        aD[q] = 0.0;
+        if (!FAR) aE[q] = 0.0;
+    }
     const double te = t[b - 1];
     double comp = 0.0;
     // the next batch's events and column extents are loaded one batch ahead
@@ -161,7 +173,7 @@ __global__ __launch_bounds__(64) void pt_seg_agg(int64_t c0, int64_t c1, int32_t
         while (k < nb) {
             const int32_t o0 = pt_rdl(off, k);
             const int nfit = __builtin_popcountll(
-                __builtin_amdgcn_ballot_w64(lane >= k && lane < nb && cend - o0 <= PT_STAGE_AGG));
+                __builtin_amdgcn_ballot_w64(lane >= k && lane < nb && cend - o0 <= STG));
             const bool staged = nfit > 0;
             const int k2 = staged ? k + nfit : k + 1;
             const int32_t ne = pt_rdl(cend, k2 - 1) - o0;
@@ -232,7 +244,7 @@ __global__ __launch_bounds__(64) void pt_seg_agg(int64_t c0, int64_t c1, int32_t
                     atomicAdd(&aR[tp[u]], al[u] * e);
                     atomicAdd(&aD[tp[u]], al[u] * d * e);
                     const double x = bt[u] * x0;
-                    if (x <= 745.0) {
+                    if (!FAR && x <= 745.0) {
                         atomicAdd(&aE[tp[u]], al[u] * x0 * exp_f64(-x));
                         comp += al[u] * -expm1(-x);
                     } else {
@@ -250,7 +262,7 @@ __global__ __launch_bounds__(64) void pt_seg_agg(int64_t c0, int64_t c1, int32_t
     for (int32_t q = lane; q < M; q += 64) {
         o[q] = aR[q];
         o[M + q] = aD[q];
-        oe[q] = aE[q];
+        oe[q] = FAR ? 0.0 : aE[q];
     }
     for (int off = 32; off > 0; off >>= 1) comp += __shfl_down(comp, off, 64);
     if (lane == 0) {
@@ -258,6 +270,27 @@ __global__ __launch_bounds__(64) void pt_seg_agg(int64_t c0, int64_t c1, int32_t
         seg_span[s] = te - tr;
         seg_part[(int64_t)s * 4 + 1] = comp;
     }
+}
+
+// beta_min over the targets, into flags[0] (a float), once per call
+__global__ __launch_bounds__(256) void pt_bmin(int32_t M, const float* __restrict__ beta, float* __restrict__ flags) {
+    __shared__ float sm[256];
+    float v = 3.0e38f;
+    for (int32_t p = threadIdx.x; p < M; p += 256) v = beta[p] < v ? beta[p] : v;
+    sm[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h && sm[threadIdx.x + h] < sm[threadIdx.x]) sm[threadIdx.x] = sm[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) flags[0] = sm[0];
+}
+
+// flags[1] (an int): 1 when some entry of the chunk [c0, c1) can have
+// beta_p (T - t_j) <= 745 (its compensator terms are not all zero)
+__global__ void pt_near(int64_t c1, double T, const double* __restrict__ t, float* __restrict__ flags) {
+    if (threadIdx.x == 0)
+        reinterpret_cast<int32_t*>(flags)[1] = (double)flags[0] * (T - t[c1 - 1]) <= 745.0 ? 1 : 0;
 }
 
 // Pass 1 of the constant-memory gradient only carries the state from chunk to
@@ -1176,11 +1209,13 @@ hawkes_status run_large_pt(LargeArgs& A, hipStream_t st) {
     const int64_t MM = (int64_t)M * M;
     const unsigned gM = (unsigned)((M + 255) / 256);
     const size_t lds_agg = (size_t)3 * M * sizeof(double) + 64 * sizeof(double) + (size_t)PT_STAGE_AGG * 16;
+    const size_t lds_agg_far = (size_t)2 * M * sizeof(double) + 64 * sizeof(double) + (size_t)PT_STAGE_CHAIN * 16;
     const size_t lds_fwd = (size_t)4 * M * sizeof(double) + PT_BATCH_LDS + (size_t)PT_STAGE * 16 +
                            (size_t)((M + 15) & ~15);
     const size_t lds_rev = (size_t)M * sizeof(double);
     const size_t lds_chain = (size_t)2 * M * sizeof(double) + 64 * sizeof(double) + (size_t)PT_STAGE_CHAIN * 16;
-    if (allow_lds((const void*)pt_seg_agg, lds_agg) != HAWKES_OK ||
+    if (allow_lds((const void*)pt_seg_agg<false, PT_STAGE_AGG>, lds_agg) != HAWKES_OK ||
+        allow_lds((const void*)pt_seg_agg<true, PT_STAGE_CHAIN>, lds_agg_far) != HAWKES_OK ||
         allow_lds((const void*)pt_forward<true, false>, lds_fwd) != HAWKES_OK ||
         allow_lds((const void*)pt_forward<false, true>, lds_fwd) != HAWKES_OK ||
         allow_lds((const void*)pt_forward<false, false>, lds_fwd) != HAWKES_OK ||
@@ -1207,6 +1242,10 @@ hawkes_status run_large_pt(LargeArgs& A, hipStream_t st) {
     // of every column entry's target
     float* csc_b = reinterpret_cast<float*>(A.csr_cv);
     hipLaunchKernelGGL(pt_csc_beta, dim3(1024), dim3(256), 0, st, M, A.csc_ptr, A.csc_cv, A.beta, csc_b);
+    // beta_min and a chunk's flag, in the shared-decay engine's carry-time
+    // word (8 bytes this engine does not otherwise use)
+    float* flags = reinterpret_cast<float*>(A.carry_t);
+    hipLaunchKernelGGL(pt_bmin, dim3(1), dim3(256), 0, st, M, A.beta, flags);
     const int64_t M2 = 2 * (int64_t)M;
     auto chunk_range = [&](int64_t ch, int64_t& c0, int64_t& c1) -> int32_t {
         c0 = ch * A.CH;
@@ -1218,8 +1257,14 @@ hawkes_status run_large_pt(LargeArgs& A, hipStream_t st) {
     auto agg_scan = [&](int64_t c0, int64_t c1, int32_t nseg) {
         {
             TimedScope ts(2, st);
-            hipLaunchKernelGGL(pt_seg_agg, dim3(nseg), dim3(64), lds_agg, st, c0, c1, M, A.T, A.t, A.marks, A.beta,
-                               A.csc_ptr, A.csc_cv, csc_b, A.agg, A.seg_span, A.ebseg, A.seg_part);
+            hipLaunchKernelGGL(pt_near, dim3(1), dim3(64), 0, st, c1, A.T, A.t, flags);
+            const int32_t* nearf = reinterpret_cast<const int32_t*>(flags) + 1;
+            hipLaunchKernelGGL((pt_seg_agg<true, PT_STAGE_CHAIN>), dim3(nseg), dim3(64), lds_agg_far, st, c0, c1, M,
+                               A.T, A.t, A.marks, A.beta, A.csc_ptr, A.csc_cv, csc_b, A.agg, A.seg_span, A.ebseg,
+                               A.seg_part, nearf);
+            hipLaunchKernelGGL((pt_seg_agg<false, PT_STAGE_AGG>), dim3(nseg), dim3(64), lds_agg, st, c0, c1, M, A.T,
+                               A.t, A.marks, A.beta, A.csc_ptr, A.csc_cv, csc_b, A.agg, A.seg_span, A.ebseg,
+                               A.seg_part, nearf);
         }
         TimedScope ts(3, st);
         large_scan(A, nseg, A.beta, st);
