@@ -482,7 +482,9 @@ __global__ __launch_bounds__(512) void pt_chain_fold(int64_t c0, int64_t c1, int
 //     entry of a target in the batch moves its record to the batch's last
 //     time t_B (it claims the record by exchanging tau_p for t_B); then every
 //     entry adds alpha e^{-beta_p (t_B - t_j)} to R_p and (t_B - t_j) times
-//     that to D_p.  An entry whose target is the own target of a later event
+//     that to D_p (in a segment short enough for anchored records, below,
+//     the entry only adds to its target's sums).  An entry whose target is
+//     the own target of a later event
 //     i of the batch (a byte per node names one batch event with that own
 //     target, a mask per event all of them) adds its share at t_i,
 //     alpha e^{-beta_p (t_i - t_j)}, to that event;
@@ -517,6 +519,20 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
     const int64_t b = a + HK_SEG < c1 ? a + HK_SEG : c1;
     const double tref = a > 0 ? t[a - 1] : t[a];
     const double* cs = carry_seg + (int64_t)s * 2 * M;
+    // Anchored records when the segment's span allows, beta_max (t_last -
+    // t_ref) <= 600: with u = t - t_ref, rR[p] = S0_p = sum_j alpha e^{beta_p u_j}
+    // and rD[p] = S1_p = sum_j alpha u_j e^{beta_p u_j} over the pushes so far
+    // (the carry enters as S0 = R(t_ref), S1 = -D(t_ref)); then R_p(t) =
+    // e^{-beta_p u} S0_p and D_p(t) = e^{-beta_p u} (u S0_p - S1_p), pushes are
+    // plain additions and no record is claimed or moved.  Otherwise each
+    // record keeps its own time rtau[p] and is moved on use.
+    float bmx = 0.0f;
+    for (int32_t q = lane; q < M; q += 64) bmx = beta[q] > bmx ? beta[q] : bmx;
+    for (int o = 32; o > 0; o >>= 1) {
+        const float v = __shfl_xor(bmx, o, 64);
+        bmx = v > bmx ? v : bmx;
+    }
+    const bool anch = __builtin_amdgcn_readfirstlane((int)((double)bmx * (t[b - 1] - tref) <= 600.0)) != 0;
     // records from the carry, eight rows of 64 in flight at a time
     for (int32_t q0 = 0; q0 < M; q0 += 512) {
         double r[8], d[8];
@@ -532,7 +548,7 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
             if (q < M) {
                 rtau[q] = tref;
                 rR[q] = r[u];
-                rD[q] = d[u];
+                rD[q] = anch ? -d[u] : d[u];
                 gbl[q] = 0.0;
             }
         }
@@ -586,7 +602,13 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
         __syncthreads();   // also orders the previous batch's pushes before the reads
         // 1. own target's record at t_i, and the table of own targets
         double Rk, Dk;
-        {
+        if (anch) {
+            const double u = tv - tref;
+            const double e = exp_f64(-bm * u);
+            const double s0 = rR[mv];
+            Rk = e * s0;
+            Dk = e * __builtin_fma(u, s0, -rD[mv]);
+        } else {
             const double d = tv - rtau[mv];
             const double e = exp_f64(-bm * d);
             const double r = rR[mv];
@@ -675,48 +697,72 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
                         bt[u] = (double)csc_b[kq];
                     }
                 }
-                // claim: the first entry of its target moves the record to tB
-                double told[PT_U], tj[PT_U];
+                double tj[PT_U];
                 int rep[PT_U];
+                uint64_t mk[PT_U];
+                if (anch) {
+                    // anchored: every entry adds alpha e^{beta u_j} (and u_j
+                    // times that) to its target's sums
 #pragma unroll
-                for (int u = 0; u < PT_U; ++u) {
-                    tj[u] = ev_t[ej[u]];
-                    told[u] = tB;
-                    if (vf[u])
-                        told[u] = __longlong_as_double((long long)atomicExch(
-                            (unsigned long long*)&rtau[tp[u]], (unsigned long long)__double_as_longlong(tB)));
-                    rep[u] = tev[tp[u]];
+                    for (int u = 0; u < PT_U; ++u) {
+                        tj[u] = ev_t[ej[u]];
+                        rep[u] = tev[tp[u]];
+                    }
+                    double g[PT_U], uj[PT_U];
+#pragma unroll
+                    for (int u = 0; u < PT_U; ++u) {
+                        uj[u] = tj[u] - tref;
+                        g[u] = av[u] * exp_f64(bt[u] * uj[u]);
+                    }
+#pragma unroll
+                    for (int u = 0; u < PT_U; ++u) {
+                        if (vf[u]) {
+                            atomicAdd(&rR[tp[u]], g[u]);
+                            atomicAdd(&rD[tp[u]], uj[u] * g[u]);
+                        }
+                    }
+                } else {
+                    // claim: the first entry of its target moves the record to tB
+                    double told[PT_U];
+#pragma unroll
+                    for (int u = 0; u < PT_U; ++u) {
+                        tj[u] = ev_t[ej[u]];
+                        told[u] = tB;
+                        if (vf[u])
+                            told[u] = __longlong_as_double((long long)atomicExch(
+                                (unsigned long long*)&rtau[tp[u]], (unsigned long long)__double_as_longlong(tB)));
+                        rep[u] = tev[tp[u]];
+                    }
+                    double e0[PT_U], c[PT_U], dB[PT_U];
+#pragma unroll
+                    for (int u = 0; u < PT_U; ++u) {
+                        e0[u] = exp_f64(-bt[u] * (tB - told[u]));   // 1 unless claimed
+                        dB[u] = tB - tj[u];
+                        c[u] = av[u] * exp_f64(-bt[u] * dB[u]);
+                    }
+#pragma unroll
+                    for (int u = 0; u < PT_U; ++u) {
+                        if (vf[u] && told[u] != tB) {
+                            const double d0 = tB - told[u];
+                            const double r0 = rR[tp[u]];
+                            rD[tp[u]] = e0[u] * __builtin_fma(d0, r0, rD[tp[u]]);
+                            rR[tp[u]] = e0[u] * r0;
+                        }
+                    }
+                    lds_wait();   // the moves land before any entry's add
+#pragma unroll
+                    for (int u = 0; u < PT_U; ++u) {
+                        if (vf[u]) {
+                            atomicAdd(&rR[tp[u]], c[u]);
+                            atomicAdd(&rD[tp[u]], dB[u] * c[u]);
+                        }
+                    }
                 }
                 // events of the batch after the entry's event whose own
                 // target is the entry's (rare: 64 own targets of M)
-                uint64_t mk[PT_U];
 #pragma unroll
                 for (int u = 0; u < PT_U; ++u)
                     mk[u] = vf[u] && rep[u] != 0xff ? smask[rep[u] & 63] & ~((2ull << ej[u]) - 1ull) : 0ull;
-                double e0[PT_U], c[PT_U], dB[PT_U];
-#pragma unroll
-                for (int u = 0; u < PT_U; ++u) {
-                    e0[u] = exp_f64(-bt[u] * (tB - told[u]));   // 1 unless claimed
-                    dB[u] = tB - tj[u];
-                    c[u] = av[u] * exp_f64(-bt[u] * dB[u]);
-                }
-#pragma unroll
-                for (int u = 0; u < PT_U; ++u) {
-                    if (vf[u] && told[u] != tB) {
-                        const double d0 = tB - told[u];
-                        const double r0 = rR[tp[u]];
-                        rD[tp[u]] = e0[u] * __builtin_fma(d0, r0, rD[tp[u]]);
-                        rR[tp[u]] = e0[u] * r0;
-                    }
-                }
-                lds_wait();   // the moves land before any entry's add
-#pragma unroll
-                for (int u = 0; u < PT_U; ++u) {
-                    if (vf[u]) {
-                        atomicAdd(&rR[tp[u]], c[u]);
-                        atomicAdd(&rD[tp[u]], dB[u] * c[u]);
-                    }
-                }
                 // their shares at t_i, one (entry, event) pair a lane per round
                 for (;;) {
                     int i = -1;
