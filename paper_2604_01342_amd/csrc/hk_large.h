@@ -66,8 +66,8 @@ struct LargeArgs {
     int32_t ngr;          // scan groups per chunk
     double *gagg, *gcarry, *gspan, *gdec;   // group maps, carries, spans, decays
     int4* node_info;      // [M] (csr begin, csr end, mu, colsum)
-    double* carry;        // [2M] chunk carry (K, J) at carry_t
-    double* carry_t;      // [1] time of the carry (last event before the chunk)
+    double* carry;        // [2M] chunk carry (K, J) just after the chunk's last event
+    float* pt_flags;      // [2] per-target engine: beta_min, and (int) whether a chunk is near T
     double* seg_part;     // [nseg][2 + 2K]
     double* acc;          // [2 + 2K] call-level sums: logsum, comp, E[K], gbeta[K]
     double* ll_scratch;   // [1] log-likelihood slot when the caller wants intensities only

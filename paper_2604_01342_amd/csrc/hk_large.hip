@@ -975,7 +975,7 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
     A.node_info = c.take<int4>(K * M);
     A.carry_seg = c.take<double>((size_t)K * A.nseg * 2 * M);
     A.carry = c.take<double>(K * 2 * M);
-    A.carry_t = c.take<double>(1);
+    A.pt_flags = c.take<float>(2);
     A.seg_part = c.take<double>((size_t)A.nseg * (2 + 2 * K));
     A.acc = c.take<double>(2 + 2 * K);
     A.ll_scratch = c.take<double>(1);

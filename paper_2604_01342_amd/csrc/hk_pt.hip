@@ -1288,9 +1288,8 @@ hawkes_status run_large_pt(LargeArgs& A, hipStream_t st) {
     // of every column entry's target
     float* csc_b = reinterpret_cast<float*>(A.csr_cv);
     hipLaunchKernelGGL(pt_csc_beta, dim3(1024), dim3(256), 0, st, M, A.csc_ptr, A.csc_cv, A.beta, csc_b);
-    // beta_min and a chunk's flag, in the shared-decay engine's carry-time
-    // word (8 bytes this engine does not otherwise use)
-    float* flags = reinterpret_cast<float*>(A.carry_t);
+    // beta_min and a chunk's flag (near T or not)
+    float* flags = A.pt_flags;
     hipLaunchKernelGGL(pt_bmin, dim3(1), dim3(256), 0, st, M, A.beta, flags);
     const int64_t M2 = 2 * (int64_t)M;
     auto chunk_range = [&](int64_t ch, int64_t& c0, int64_t& c1) -> int32_t {
