@@ -1125,19 +1125,35 @@ __global__ __launch_bounds__(64 * HK_DWP) void pt_dense(int64_t c0, int64_t c1, 
             // hardware exp2 at any x in range.
             merged = true;
             const double dd = tw - S.ct;
-            const float dh = (float)dd, dl = (float)(dd - (double)dh);
+            const float dh = (float)dd, dl0 = (float)(dd - (double)dh);
+            // per slab lane k: the own events later than it, the first dcnt of
+            // the own list (both lists newest first: a binary search over the
+            // own indices), and with its column in the 13 low mantissa bits of
+            // the low part of its offset (dl changes by at most 2^-10 of
+            // itself, 2^-34 of the offset), so that one readlane gives all
+            int dcnt = 0;
+#pragma unroll
+            for (int step = 64; step >= 1; step >>= 1) {
+                const int probe = dcnt + step - 1;
+                const int ov = __shfl(io, probe & 63, 64);
+                if (probe < no && ov > is) dcnt += step;
+            }
+            const float dl = __int_as_float((__float_as_int(dl0) & ~8191) | (dcnt << 6) | (int)(S.ck & 63u));
+            // the own event's target lane rides in the 6 low mantissa bits of
+            // its weight (a change of at most 2^-46 relative), so one pair
+            // of readlanes gives both
             const double fo = own ? bo * wi * (double)exp2_f64arg((tw - O.ct) * bo2) : 0.0;
-            const int okeys = (int)O.ck, skeys = (int)S.ck;
-            const uint64_t omask = __builtin_amdgcn_ballot_w64(own);
+            const double fop = __longlong_as_double((__double_as_longlong(fo) & ~63ll) | (long long)pi);
             int j = 0;
             for (int k = 0; k < ns; ++k) {
-                const uint32_t key = (uint32_t)rl_i(skeys, k);
+                const float xl0 = rl_f(dl, k);
+                const int kb = __float_as_int(xl0);
                 // own events later than slab event k (the first dk of the
                 // list, newest first) join A before it
-                const int dk = __builtin_popcountll(__builtin_amdgcn_ballot_w64(io > (int)(key >> 6)) & omask);
+                const int dk = (kb >> 6) & 127;
                 for (; j < dk; ++j) {
-                    const double f = rl_d(fo, j);
-                    if (lane == (rl_i(okeys, j) & 63)) {
+                    const double f = rl_d(fop, j);
+                    if (lane == (int)(__double_as_longlong(f) & 63)) {
                         Ab += f;
                         // keeps the add under the lane's exec mask (else the
                         // compiler adds on every lane and selects: two more
@@ -1145,17 +1161,17 @@ __global__ __launch_bounds__(64 * HK_DWP) void pt_dense(int64_t c0, int64_t c1, 
                         __asm__ volatile("" : "+v"(Ab));
                     }
                 }
-                const float xh0 = rl_f(dh, k), xl0 = rl_f(dl, k);
+                const float xh0 = rl_f(dh, k);
                 const float xh = bpl * xh0;
                 const float xl = __builtin_fmaf(bpl, xl0, __builtin_fmaf(bpl_lo, xh0, __builtin_fmaf(bpl, xh0, -xh)));
                 const float e0 = __builtin_amdgcn_exp2f(-xh);
                 const float e = __builtin_fmaf(e0, xl * -0.69314718f, e0);
-                atomicAdd(&G[(int)(key & 63u) * 65 + lane], Ab * (double)e);
+                atomicAdd(&G[(kb & 63) * 65 + lane], Ab * (double)e);
             }
             // own events older than every slab event of the window
             for (; j < no; ++j) {
-                const double f = rl_d(fo, j);
-                if (lane == (rl_i(okeys, j) & 63)) {
+                const double f = rl_d(fop, j);
+                if (lane == (int)(__double_as_longlong(f) & 63)) {
                     Ab += f;
                     __asm__ volatile("" : "+v"(Ab));
                 }
