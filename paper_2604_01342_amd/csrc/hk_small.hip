@@ -534,6 +534,17 @@ __global__ __launch_bounds__(256) void small_compute(int32_t S, int64_t n_total,
 // atomics: no selects over the nodes), and the compensator and its
 // beta-derivative come from them at the item's end, weighted by the column
 // sums of alpha.  The lanes' scalar partials are summed in lane order.
+// Lane l's double from lane (l & ~1) + S of its pair (CTL 0xA0: S = 0, 0xF5:
+// S = 1) or from lane l ^ 1 (0xB1): DPP quad permutations on the vector ALU,
+// where __shfl would take an LDS round trip.  Both lanes of a pair are active
+// together (they walk the same item).
+template <int CTL>
+__device__ __forceinline__ double pair_dpp(double x) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
 template <int MP, int LPI>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void small_compute_c(int32_t S, int64_t n_total, const int64_t* __restrict__ ev_off,
                                                        const int64_t* __restrict__ item_off, int32_t L,
@@ -668,9 +679,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
             if (e0 + j >= inf.b) break;
-            const int src = g0 + j % LPI;
-            const double sj = __shfl(so[j / LPI], src, 64);
-            const double ex = __shfl(xo[j / LPI], src, 64);
+            double sj, ex;
+            if (LPI == 2) {
+                sj = j % 2 == 0 ? pair_dpp<0xA0>(so[j / 2]) : pair_dpp<0xF5>(so[j / 2]);
+                ex = j % 2 == 0 ? pair_dpp<0xA0>(xo[j / 2]) : pair_dpp<0xF5>(xo[j / 2]);
+            } else {
+                const int src = g0 + j % LPI;
+                sj = __shfl(so[j / LPI], src, 64);
+                ex = __shfl(xo[j / LPI], src, 64);
+            }
             const double te = tv[j];
             const double d = te - tp;
             const int p = clamp_mark(mv[j], M);
@@ -684,10 +701,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
                 R = __builtin_fma(a, K[u], R);
                 Dd = __builtin_fma(a, J[u], Dd);
             }
+            if (LPI == 2) {
+                R += pair_dpp<0xB1>(R);
+                Dd += pair_dpp<0xB1>(Dd);
+            } else {
 #pragma unroll
-            for (int off = 1; off < LPI; off <<= 1) {
-                R += __shfl_xor(R, off, 64);
-                Dd += __shfl_xor(Dd, off, 64);
+                for (int off = 1; off < LPI; off <<= 1) {
+                    R += __shfl_xor(R, off, 64);
+                    Dd += __shfl_xor(Dd, off, 64);
+                }
             }
             const double lam = (double)A_[MP * MP + p] + bet * R;
             // 1 / lambda: hardware reciprocal and two Newton steps
