@@ -162,12 +162,7 @@ __global__ __launch_bounds__(64) void pt_seg_agg(int64_t c0, int64_t c1, int32_t
             tv_n = t[ic2];
             mraw_n = marks[ic2];
         }
-        int32_t off = cn;
-        for (int d = 1; d < 64; d <<= 1) {
-            const int32_t u = __shfl_up(off, d, 64);
-            if (lane >= d) off += u;
-        }
-        off -= cn;   // exclusive
+        const int32_t off = wave_incl_scan_dpp(cn) - cn;   // exclusive
         const int32_t cend = off + cn;
         const int nb = (int)(b - base < 64 ? b - base : 64);
         __syncthreads();   // the previous batch is done with ev_t and the stage
@@ -343,12 +338,7 @@ __global__ __launch_bounds__(64) void pt_chain_part(int64_t c0, int64_t c1, int3
             tv_n = t[ic2];
             mraw_n = marks[ic2];
         }
-        int32_t off = cn;
-        for (int d = 1; d < 64; d <<= 1) {
-            const int32_t u = __shfl_up(off, d, 64);
-            if (lane >= d) off += u;
-        }
-        off -= cn;   // exclusive
+        const int32_t off = wave_incl_scan_dpp(cn) - cn;   // exclusive
         const int32_t cend = off + cn;
         const int nb = (int)(b - base < 64 ? b - base : 64);
         __syncthreads();   // the previous batch is done with ev_t and the stage
@@ -592,12 +582,7 @@ __global__ __launch_bounds__(64) void pt_forward(int64_t c0, int64_t c1, int32_t
             tv_n = t[ic2];
             mraw_n = marks[ic2];
         }
-        int32_t off = cn;
-        for (int d = 1; d < 64; d <<= 1) {
-            const int32_t u = __shfl_up(off, d, 64);
-            if (lane >= d) off += u;
-        }
-        off -= cn;   // exclusive
+        const int32_t off = wave_incl_scan_dpp(cn) - cn;   // exclusive
         ev_t[lane] = tv;
         shR[lane] = 0.0;
         shD[lane] = 0.0;
