@@ -61,21 +61,6 @@ __device__ __forceinline__ double shfl_up_d(double v, int d) {
     return __shfl_up(v, d, HK_WAVE);
 }
 
-// Inclusive prefix sum over the 64 lanes of a wave on the vector ALU (DPP):
-// shifts within rows of 16 lanes (row_shr 1, 2, 4, 8), then each row's total
-// carried forward (row_bcast 15 into rows 1 and 3, row_bcast 31 into rows 2
-// and 3).  A lane that a shift or broadcast does not reach adds 0.  Every
-// lane of the wave must be active.
-__device__ __forceinline__ int32_t wave_incl_scan_dpp(int32_t v) {
-    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);
-    return v;
-}
-
 // Waits for this wave's outstanding LDS operations (lgkmcnt(0)); the
 // compiler fences keep LDS accesses from moving across it.  Needed where a
 // wave reads back what it has just written with LDS atomics: a read can

@@ -61,6 +61,21 @@ namespace hk {
 // merged path: e^64 and e^-64 stay well inside float32's range
 #define HK_PT_MERGE_SPAN 64.0
 
+// Inclusive prefix sum over the 64 lanes of a wave on the vector ALU (DPP):
+// shifts within rows of 16 lanes (row_shr 1, 2, 4, 8), then each row's total
+// carried forward (row_bcast 15 into rows 1 and 3, row_bcast 31 into rows 2
+// and 3).  A lane that a shift or broadcast does not reach adds 0.  Every
+// lane of the wave must be active.
+__device__ __forceinline__ int32_t wave_incl_scan_dpp(int32_t v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);
+    return v;
+}
+
 __global__ void pt_fill(double* p, int64_t n, double v) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
