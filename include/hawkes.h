@@ -47,9 +47,9 @@
  *    last-bit rounding) can vary between calls.
  *  - Size limits (LDS per workgroup, read from the device; 160 KiB on
  *    MI355X, of which the shared-decay forward kernel keeps 2 KiB for
- *    itself): shared decay m <= 5056, decay per target m <= 4352; larger m
- *    returns HAWKES_EUNSUPPORTED.  The per-target gradient also keeps one
- *    float32 per event (4 bytes x n) in the workspace for its reverse pass.
+ *    itself): shared decay m <= 6741, decay per target m <= 4352; larger m
+ *    returns HAWKES_EUNSUPPORTED.  The workspace of every large-M call is
+ *    independent of n (the events are taken in chunks).
  *  - Errors: every function returns a hawkes_status.  Host-detectable
  *    argument errors return HAWKES_EINVAL (or HAWKES_EWORKSPACE for a short
  *    workspace) before anything is launched, and the outputs are untouched.

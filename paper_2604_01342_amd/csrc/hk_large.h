@@ -16,7 +16,9 @@
 #define HK_CKR 4           // segments per checkpoint run of the shared-decay dense gradient
 #endif
 #define HK_WIDE 60.0       // anchored-exponent limit inside one window of the dense kernel
+#ifndef HK_DWF
 #define HK_DWF 4           // waves per workgroup of the float32-accumulator dense kernel (32-row tiles)
+#endif
 #ifndef HK_F32_MIN_M
 #define HK_F32_MIN_M 384   // nodes from which the 32-row float32-accumulator tiles are the rule
 #endif
@@ -118,6 +120,8 @@ struct LargeArgs {
 
 // optional parts of the shared-decay forward pass (see large_forward)
 struct FwdExtra {
+    double* rtau;         // [nseg][2M] scratch (the segment maps' buffer, consumed by the scan):
+                          // the first M doubles of segment s hold its lazy records' times
     const double* gcarry;
     const double* seg_off;
     const double* seg_offdec;

@@ -352,9 +352,8 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
                                                     double* __restrict__ rk, double* __restrict__ dk,
                                                     FwdExtra X) {
     extern __shared__ double lds[];
-    double* rtau = lds;                                   // [M] time of the record
-    uint64_t* rmask = (uint64_t*)(lds + M);               // [M] lanes of this batch with mark q
-    double2* rKJ = reinterpret_cast<double2*>(lds + 2 * M);   // [M] (K_q, J_q) at rtau (event included)
+    double2* rKJ = reinterpret_cast<double2*>(lds);       // [M] (K_q, J_q) at rtau (event included)
+    uint64_t* rmask = (uint64_t*)(lds + 2 * M);           // [M] lanes of this batch with mark q
     __shared__ double tb[64], eb[64];
     __shared__ double Rs[(NW > 1 ? NW - 1 : 1) * 64], Ds[(NW > 1 ? NW - 1 : 1) * 64];   // other waves' partial sums
     const int32_t s = blockIdx.x;
@@ -377,6 +376,11 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
     // Otherwise (beta u could overflow float64) each record keeps its own
     // time rtau[q] and is decayed on use.
     const bool anch = bet * (t[b - 1] - tref) <= 600.0;
+    // [M] the lazy records' times, in the segment's slot of a global scratch
+    // buffer (24 bytes of LDS per node instead of 32: M up to 6741).  Three
+    // waves per SIMD (168 registers, six workgroups per CU at M = 1000) made
+    // the pass slower at c4's shape: 0.674 against 0.591 ms per step
+    double* rtau = X.rtau + (int64_t)s * 2 * M;
     const double* cs = carry_seg + (int64_t)s * 2 * M;
     const double* gc = X.gcarry ? X.gcarry + (int64_t)(s / HK_SG) * 2 * M : nullptr;
     const double Dg = gc ? X.seg_off[s] : 0.0, exg = gc ? X.seg_offdec[s] : 0.0;
@@ -388,13 +392,13 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
             Jq = __builtin_fma(exg, __builtin_fma(Dg, Kc, gc[M + q]), Jq);
             Kq = __builtin_fma(exg, Kc, Kq);
         }
-        rtau[q] = tref;
+        if (!anch) rtau[q] = tref;
         rKJ[q] = make_double2(Kq, anch ? -Jq : Jq);
         rmask[q] = 0ull;
     }
     // events per node block (partition counts): dynamic LDS after the
     // records, present when bcnt is given
-    int32_t* lcnt = reinterpret_cast<int32_t*>(lds + 4 * M);
+    int32_t* lcnt = reinterpret_cast<int32_t*>(lds + 3 * M);
     if (X.bcnt)
         for (int32_t k = threadIdx.x; k < X.nbo; k += 64 * NW) lcnt[k] = 0;
     __syncthreads();
@@ -937,7 +941,7 @@ size_t large_layout(LargeArgs& A, const hawkes_problem* p, bool grad, void* ws, 
     // with 4 / 8 / 16 / 32 ranges: 0.416 / 0.420 / 0.434 / 0.534, and a
     // quarter of the partials' traffic at 4)
     const int64_t nbb = (int64_t)A.NBR * A.NBC;
-    const int64_t target = A.DRB == 5 ? 512 : A.per_target || A.CPL == 4 ? 2048 : 4096;
+    const int64_t target = A.DRB == 5 ? 2048 / HK_DWF : A.per_target || A.CPL == 4 ? 2048 : 4096;
     const int64_t want = (target + nbb - 1) / nbb;
     int32_t er = 1;
     while (er < want) er <<= 1;
@@ -1118,7 +1122,7 @@ static hawkes_status run_large_multi(LargeArgs& A, hipStream_t st) {
     const int64_t MM = (int64_t)M * M;
     const unsigned gM = (unsigned)((M + 255) / 256);
     const size_t lds_agg = (size_t)2 * M * sizeof(double);
-    const size_t lds_fwd = (size_t)M * (sizeof(double) + sizeof(uint64_t) + 2 * sizeof(double));
+    const size_t lds_fwd = (size_t)M * (sizeof(uint64_t) + 2 * sizeof(double));
     if (allow_lds((const void*)large_seg_agg, lds_agg) != HAWKES_OK ||
         allow_lds((const void*)large_forward<true, false, false, HK_FWW, true>, lds_fwd) != HAWKES_OK ||
         allow_lds((const void*)large_forward<false, false, false, HK_FWW, true>, lds_fwd) != HAWKES_OK)
@@ -1164,6 +1168,10 @@ static hawkes_status run_large_multi(LargeArgs& A, hipStream_t st) {
         const int32_t nseg = (int32_t)((c1 - c0 + HK_SEG - 1) / HK_SEG);
         for (int32_t k = 0; k < K; ++k) {
             LargeArgs B = view(k);
+            // the lazy records' times go to the segment maps' buffer, which
+            // the scan has consumed by then
+            FwdExtra Xm{};
+            Xm.rtau = B.agg;
             {
                 TimedScope ts(2, st);
                 hipLaunchKernelGGL(large_seg_agg, dim3(nseg), dim3(64), lds_agg, st, c0, c1, M, A.t, A.marks,
@@ -1179,13 +1187,13 @@ static hawkes_status run_large_multi(LargeArgs& A, hipStream_t st) {
                                    lds_fwd, st, c0, c1, M, A.T, A.t, A.marks, A.mu, B.beta,
                                    A.node_info + (int64_t)k * M, A.csr_cv + k * cv_stride(MM), B.carry_seg,
                                    A.seg_part, A.wchunk, (float*)nullptr, (double*)nullptr, 0,
-                                   A.rk + (int64_t)k * A.CH, A.dk + (int64_t)k * A.CH, FwdExtra{});
+                                   A.rk + (int64_t)k * A.CH, A.dk + (int64_t)k * A.CH, Xm);
             else
                 hipLaunchKernelGGL((large_forward<false, false, false, HK_FWW, true>), dim3(nseg), dim3(64 * HK_FWW),
                                    lds_fwd, st, c0, c1, M, A.T, A.t, A.marks, A.mu, B.beta,
                                    A.node_info + (int64_t)k * M, A.csr_cv + k * cv_stride(MM), B.carry_seg,
                                    A.seg_part, A.wchunk, (float*)nullptr, (double*)nullptr, 0,
-                                   A.rk + (int64_t)k * A.CH, (double*)nullptr, FwdExtra{});
+                                   A.rk + (int64_t)k * A.CH, (double*)nullptr, Xm);
         }
         {
             TimedScope ts(1, st);
@@ -1234,7 +1242,7 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
     const int64_t MM = (int64_t)M * M;
     const unsigned gM = (unsigned)((M + 255) / 256);
     const size_t lds_agg = (size_t)2 * M * sizeof(double);
-    const size_t lds_fwd = (size_t)M * (sizeof(double) + sizeof(uint64_t) + 2 * sizeof(double));
+    const size_t lds_fwd = (size_t)M * (sizeof(uint64_t) + 2 * sizeof(double));
     if (allow_lds((const void*)large_seg_agg, lds_agg) != HAWKES_OK ||
         allow_lds((const void*)large_forward<true, false, false, HK_FWW>, lds_fwd) != HAWKES_OK ||
         allow_lds((const void*)large_forward<true, false, true, 1>, lds_fwd) != HAWKES_OK ||
@@ -1260,6 +1268,7 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
     // at c4: 6.483 -> 6.439 ms per step; also summing the chunk in the
     // forward pass's last workgroup instead of large_chunk_acc cost 0.17 ms.
     FwdExtra X;
+    X.rtau = A.agg;   // free once the scan has run
     X.gcarry = A.gcarry;
     X.seg_off = A.seg_off;
     X.seg_offdec = A.seg_offdec;
@@ -1270,9 +1279,9 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
     if (A.grad && A.NBO <= HK_NBO_MAX) {
         const void* kf = sup ? (const void*)large_forward<true, false, true, 1>
                              : (const void*)large_forward<true, false, false, HK_FWW>;
-        if (allow_lds(kf, lds_fwd + HK_NBO_MAX * sizeof(int32_t)) == HAWKES_OK) {
+        if (allow_lds(kf, lds_fwd + (size_t)A.NBO * sizeof(int32_t)) == HAWKES_OK) {
             X.bcnt = A.bo_cnt;
-            lds_fwdc = lds_fwd + HK_NBO_MAX * sizeof(int32_t);
+            lds_fwdc = lds_fwd + (size_t)A.NBO * sizeof(int32_t);
         }
     }
     A.carry_prefix = true;

@@ -202,6 +202,38 @@ def test_determinism_bitwise(H):
     assert a[0] == b[0] and all(np.array_equal(x, y) for x, y in zip(a[1:], b[1:]))
 
 
+# ------------------------------------------------------------- per-record decays in the forward pass
+# A segment of 1024 events whose span times beta exceeds 600 would overflow
+# the anchored records (e^{beta u} past float64 range), so its records keep
+# their own times and are decayed on use.  Rate 1 with beta >= 1 makes every
+# segment such a one; a sequence alternating rate-1 and rate-40 stretches
+# mixes both forms across the segments of one chunk.  The gradient, the
+# loglik-only and the intensity forms of the forward pass are checked.
+@pytest.mark.parametrize("mixed", [False, True])
+def test_large_engine_per_record_decays(H, mixed):
+    import torch
+    n, M = 9000, 40
+    t, m, mu, alpha, beta, T = rand_problem(91 + mixed, n, M, density=0.3, rate=1.0)
+    beta = np.array([1.25], np.float32)
+    if mixed:
+        rng = np.random.default_rng(93)
+        gaps = np.concatenate([rng.exponential(1.0 if (k // 1024) % 2 == 0 else 1.0 / 40.0, 1024)
+                               for k in range(0, n, 1024)])[:n]
+        t = np.cumsum(gaps)
+        T = float(t[-1] + 0.5)
+    spans = [float(beta[0]) * (t[min(k + 1023, n - 1)] - t[max(k - 1, 0)]) for k in range(0, n, 1024)]
+    assert max(spans) > 600.0 and (not mixed or min(spans) < 600.0)
+    ref = oracle.forward(t, m, mu, alpha, beta, T)
+    check(run_gpu(H, t, m, mu, alpha, beta, T, 12), ref, label=f"per-record decays mixed={mixed}")
+    args = (dev(t, torch.float64), dev(m, torch.int32), dev(mu, torch.float32), dev(alpha, torch.float32),
+            dev(beta, torch.float32), T)
+    assert scalar_rel(H.loglik(*args, 12).item(), ref[0]) < TOL
+    lam = H.intensity(*args, 12).cpu().numpy()
+    idx = np.unique(np.linspace(0, n - 1, 80).astype(np.int64))
+    lref = oracle.intensity_at(t, m, mu, alpha, beta, idx)
+    assert np.max(np.abs(lam[idx] - lref) / lref) < 1e-6
+
+
 # ------------------------------------------------------------- intensities and loglik-only
 @pytest.mark.parametrize("M", [1, 6, 40])
 def test_intensity_matches_definition(H, M):
@@ -227,9 +259,9 @@ def test_loglik_only_matches(H, M):
 
 
 # ------------------------------------------------------------- shared decay above 64 KiB of LDS
-# The shared-decay forward kernel keeps 32 bytes of LDS per node, so from
-# M = 2049 on it runs under the device's larger per-workgroup limit (160 KiB
-# on MI355X, less the kernel's own 2 KiB of static LDS: M <= 5056); one node
+# The shared-decay forward kernel keeps 24 bytes of LDS per node, so from
+# M = 2731 on it runs under the device's larger per-workgroup limit (160 KiB
+# on MI355X, less the kernel's own 2 KiB of static LDS: M <= 6741); one node
 # more is refused on the host, before any launch.
 def test_shared_decay_above_64k_lds(H):
     t, m, mu, alpha, beta, T = rand_problem(71, 12000, 2600, density=0.002, rate=20.0)
@@ -239,7 +271,7 @@ def test_shared_decay_above_64k_lds(H):
 
 def test_shared_decay_node_limit(H):
     import torch
-    for M, ok in ((5056, True), (5057, False)):
+    for M, ok in ((6741, True), (6742, False)):
         t, m, mu, alpha, beta, T = rand_problem(72, 3000, M, density=0.001, rate=20.0)
         args = (dev(t, torch.float64), dev(m, torch.int32), dev(mu, torch.float32), dev(alpha, torch.float32),
                 dev(beta, torch.float32), T)
