@@ -695,15 +695,17 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
         Esum += __shfl_down(Esum, off, 64);
         gb += __shfl_down(gb, off, 64);
     }
+    // the segment slot's sums over the chunks so far (slot s of every chunk,
+    // in chunk order; one reduction over the slots ends the call)
     if (lane == 0) {
         double* o = seg_part + (int64_t)s * 4;
         if (wv == 0) {
-            o[0] = logsum;
-            o[3] = gb;
+            o[0] += logsum;
+            o[3] += gb;
         }
         if (wv == NW - 1) {
-            o[1] = comp;
-            o[2] = Esum;
+            o[1] += comp;
+            o[2] += Esum;
         }
     }
 }
@@ -1262,6 +1264,9 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
     // zero the carried state and accumulators
     hipLaunchKernelGGL(fill_d, dim3(1), dim3(256), 0, st, A.carry, (int64_t)2 * M, 0.0);
     hipLaunchKernelGGL(fill_d, dim3(1), dim3(64), 0, st, A.acc, (int64_t)4, 0.0);
+    // per-segment-slot sums of the forward pass, accumulated over the chunks
+    // (one reduction after the last chunk instead of one launch per chunk)
+    hipLaunchKernelGGL(fill_d, dim3(4), dim3(256), 0, st, A.seg_part, (int64_t)A.nseg * 4, 0.0);
     // the forward pass adds the scan's group carries itself (the scan's
     // apply pass is left out) and counts the partition (by blocks of 2^DRB
     // nodes, when the gradient needs them and they fit its LDS).  Measured
@@ -1335,7 +1340,6 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
                                    A.carry_seg, A.seg_part, A.wchunk, (float*)nullptr, (double*)nullptr, 0,
                                    (double*)nullptr, (double*)nullptr, X);
         }
-        hipLaunchKernelGGL(large_chunk_acc, dim3(1), dim3(256), 0, st, nseg, 4, A.seg_part, A.acc);
         if (A.grad) {
             {
                 TimedScope tb(6, st);
@@ -1347,6 +1351,7 @@ hawkes_status run_large(LargeArgs& A, hipStream_t st) {
             large_dense_launch(A, c0, c1, nseg, st, sup);
         }
     }
+    hipLaunchKernelGGL(large_chunk_acc, dim3(1), dim3(256), 0, st, A.nseg, 4, A.seg_part, A.acc);
     const int64_t nfin = A.grad ? (MM > M ? MM : M) : 1;
     if (A.grad) hipLaunchKernelGGL(large_colfold, dim3(gM), dim3(256), 0, st, M, A.NRUN, A.spart, A.cpart_);
     hipLaunchKernelGGL(large_final, dim3((unsigned)((nfin + 255) / 256)), dim3(256), 0, st, M, A.ER, 1, A.T, A.mu,
