@@ -706,7 +706,7 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(2))) v
     constexpr int SH = CPL == 4 ? 8 : CPL == 2 ? 7 : 6;   // bits of the local mark in a column record key
     extern __shared__ double GP[];            // [DR * W] float64 tile, shared by the group's waves
     __shared__ __align__(16) float ULs[NWV][DR];   // per wave: the window's u
-    __shared__ double2 ODs[NWV][66];          // per wave: own events of a pass (+2 read ahead)
+    __shared__ double2 ODs[NWV][68];          // per wave: own events of a pass (+3 read ahead)
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     float* UL = ULs[wv];
@@ -849,25 +849,42 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(2))) v
                 OD[lane] = make_double2(__hiloint2double(rowl * W, (int)(b.key >> DRB)), (double)cf);
             }
             // pair terms: own event k adds c_k b_j at (row_k, m_j) for the
-            // window's records j before it (zero elsewhere)
-            auto pair = [&](const double2 od) {
+            // window's records j before it (zero elsewhere); the window's
+            // second 64 records only for an own event after the first of
+            // them.  The own events are in index order, so those before it
+            // are the first kmid - p of the pass: two loops, no test per event
+            auto pair1 = [&](const double2 od) {
                 const int rofs = __double2hiint(od.x), ik = __double2loint(od.x);
                 atomicAdd(&GP[rofs + colj0], cidx0 < ik ? od.y * bj0 : 0.0);
-                // the window's second 64 records only for an own event after
-                // the first of them
-                if (NGW == 2 && __builtin_amdgcn_readfirstlane(ik) > hc.first1)
-                    atomicAdd(&GP[rofs + colj1], cidx1 < ik ? od.y * bj1 : 0.0);
             };
-            // two at a time, the next two entries read before this pair's
-            // atomics (entries past kend are read but not used)
-            double2 d1 = OD[p], d2 = OD[p + 1];
-            for (int k = p; k < kend; k += 2) {
-                const double2 n1 = OD[k + 2], n2 = OD[k + 3];
-                pair(d1);
-                if (k + 1 < kend) pair(d2);
-                d1 = n1;
-                d2 = n2;
-            }
+            auto pair2 = [&](const double2 od) {
+                const int rofs = __double2hiint(od.x), ik = __double2loint(od.x);
+                atomicAdd(&GP[rofs + colj0], cidx0 < ik ? od.y * bj0 : 0.0);
+                atomicAdd(&GP[rofs + colj1], cidx1 < ik ? od.y * bj1 : 0.0);
+            };
+            const int kmid = NGW == 2 ? p + __builtin_popcountll(__ballot(own && (int)(b.key >> DRB) <= hc.first1))
+                                      : kend;
+            // entries [ka, kb), two at a time, the next two read before this
+            // pair's atomics (unrolled by two so that the entries read ahead
+            // need no register moves; entries up to kb + 2 are read, those
+            // past kb not used)
+            auto run = [&](int ka, int kb, auto&& pf) __attribute__((always_inline)) {
+                if (ka >= kb) return;
+                double2 d1 = OD[ka], d2 = OD[ka + 1];
+                for (int k = ka;; k += 4) {
+                    const double2 n1 = OD[k + 2], n2 = OD[k + 3];
+                    pf(d1);
+                    if (k + 1 < kb) pf(d2);
+                    if (k + 2 >= kb) break;
+                    d1 = OD[k + 4];
+                    d2 = OD[k + 5];
+                    pf(n1);
+                    if (k + 3 < kb) pf(n2);
+                    if (k + 4 >= kb) break;
+                }
+            };
+            run(p, kmid, pair1);
+            if (NGW == 2) run(kmid, kend, pair2);
         } else {
             // wide window (anchored factors would leave float32 range):
             // c_k decayed from the window's anchor (below float32 range it
