@@ -705,11 +705,11 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(2))) v
     constexpr int DR = 1 << DRB;
     constexpr int SH = CPL == 4 ? 8 : CPL == 2 ? 7 : 6;   // bits of the local mark in a column record key
     extern __shared__ double GP[];            // [DR * W] float64 tile, shared by the group's waves
-    __shared__ __align__(16) float ULs[NWV][DR];   // per wave: the window's u
+    __shared__ double ULs[NWV][DR];           // per wave: the window's u (float64: LDS float32 atomics are slow)
     __shared__ double2 ODs[NWV][68];          // per wave: own events of a pass (+3 read ahead)
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
-    float* UL = ULs[wv];
+    double* UL = ULs[wv];
     double2* OD = ODs[wv];
     const int32_t blk = blockIdx.x;
     const int32_t nbb = NBR * NBC;
@@ -770,7 +770,7 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(2))) v
         flush1(acc2, 2);
         flush1(acc3, 3);
     };
-    if (lane < DR) UL[lane] = 0.0f;
+    if (lane < DR) UL[lane] = 0.0;
     const double bet = (double)beta[0];
     const double bl2 = bet * HK_LOG2E;   // decays as powers of 2
     const __amdgpu_buffer_rsrc_t rK = buf(kck, (uint32_t)nslot * S::SIZE * 8u);
@@ -843,7 +843,7 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(2))) v
         if (narrow) {
             const float cf = own ? (float)(bet * (double)b.w) * exp2_f64arg((tw - b.t) * bl2) : 0.0f;
             if (own) {
-                atomicAdd(&UL[rowl], cf);
+                atomicAdd(&UL[rowl], (double)cf);
                 // (row offset, index, c_k) of this own event for the pair
                 // loop, read back by every lane (broadcast)
                 OD[lane] = make_double2(__hiloint2double(rowl * W, (int)(b.key >> DRB)), (double)cf);
@@ -891,7 +891,7 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(2))) v
             // is zero, and so is its product with the state), exact
             // per-pair decays
             const double cw = bet * (double)b.w;
-            if (own) atomicAdd(&UL[rowl], (float)(cw * (double)exp2_f64arg((tw - b.t) * bl2)));
+            if (own) atomicAdd(&UL[rowl], cw * (double)exp2_f64arg((tw - b.t) * bl2));
             // the records' times, waited for here so that no load of this
             // rare path stays in flight
             const double ct0 = ld_f64(rK, (uint32_t)sc * S::SIZE + S::T + lane);
@@ -959,13 +959,13 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(2))) v
             // rank-1 update G += u K_g^T on the matrix cores (float32), then
             // clear u (u is this wave's; its atomics on u land before the reads)
             lds_wait();
-            const float uv = UL[lane & 31];
+            const float uv = (float)UL[lane & 31];
             acc0 = __builtin_amdgcn_mfma_f32_32x32x1f32(uv, (float)cur.K[0], acc0, 0, 0, 0);
             acc1 = __builtin_amdgcn_mfma_f32_32x32x1f32(uv, (float)cur.K[1], acc1, 0, 0, 0);
             acc2 = __builtin_amdgcn_mfma_f32_32x32x1f32(uv, (float)cur.K[2], acc2, 0, 0, 0);
             acc3 = __builtin_amdgcn_mfma_f32_32x32x1f32(uv, (float)cur.K[3], acc3, 0, 0, 0);
             __builtin_amdgcn_wave_barrier();
-            if (lane < DR) UL[lane] = 0.0f;
+            if (lane < DR) UL[lane] = 0.0;
             __builtin_amdgcn_wave_barrier();
             if (++nacc == HK_FLUSH) {
                 flush();
