@@ -855,12 +855,12 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(2))) v
             // are the first kmid - p of the pass: two loops, no test per event
             auto pair1 = [&](const double2 od) {
                 const int rofs = __double2hiint(od.x), ik = __double2loint(od.x);
-                atomicAdd(&GP[rofs + colj0], cidx0 < ik ? od.y * bj0 : 0.0);
+                if (cidx0 < ik) atomicAdd(&GP[rofs + colj0], od.y * bj0);
             };
             auto pair2 = [&](const double2 od) {
                 const int rofs = __double2hiint(od.x), ik = __double2loint(od.x);
-                atomicAdd(&GP[rofs + colj0], cidx0 < ik ? od.y * bj0 : 0.0);
-                atomicAdd(&GP[rofs + colj1], cidx1 < ik ? od.y * bj1 : 0.0);
+                if (cidx0 < ik) atomicAdd(&GP[rofs + colj0], od.y * bj0);
+                if (cidx1 < ik) atomicAdd(&GP[rofs + colj1], od.y * bj1);
             };
             const int kmid = NGW == 2 ? p + __builtin_popcountll(__ballot(own && (int)(b.key >> DRB) <= hc.first1))
                                       : kend;
