@@ -805,17 +805,35 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(2))) v
             w.ckey[h] = ld_u32(rK, 2 * (sl + S::KEY) + 64 * h + lane);
         }
     };
-    auto load_hdr = [&](int32_t slot) -> Hdr {
-        const double* hp = kck + (int64_t)slot * S::SIZE + S::TAU;
-        const int32_t* hq = reinterpret_cast<const int32_t*>(hp + 2);
+    // window headers by vector loads (every lane the same address), made
+    // wave-uniform only when their window starts: a scalar load shares the
+    // LDS operations' wait counter, so every LDS wait of the window before
+    // would also wait for the next header to arrive from memory
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    struct HdrV {
+        u32x2 tau;      // the anchor's bits
+        u32x4 a;        // hi, nv, next, run
+        u32x2 b;        // wide, first1
+    };
+    auto load_hdr = [&](int32_t slot) -> HdrV {
+        const uint32_t o = ((uint32_t)slot * S::SIZE + S::TAU) * 8u;
+        HdrV h;
+        h.tau = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rK, o, 0, 0));
+        h.a = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rK, o + 16u, 0, 0));
+        h.b = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rK, o + 32u, 0, 0));
+        return h;
+    };
+    auto uniform = [](const HdrV& v) -> Hdr {
+        auto rf = [](uint32_t x) { return __builtin_amdgcn_readfirstlane((int)x); };
         Hdr h;
-        h.tau = hp[0];
-        h.hi = hq[0];
-        h.nv = hq[1];
-        h.next = hq[2];
-        h.run = hq[3];
-        h.wide = hq[4];
-        h.first1 = hq[5];
+        h.tau = __hiloint2double(rf(v.tau.y), rf(v.tau.x));
+        h.hi = rf(v.a.x);
+        h.nv = rf(v.a.y);
+        h.next = rf(v.a.z);
+        h.run = rf(v.a.w);
+        h.wide = rf(v.b.x);
+        h.first1 = rf(v.b.y);
         return h;
     };
 
@@ -918,7 +936,7 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(2))) v
         const bool last = hc.nv == 0 && hc.run >= rB - 1;
         const int32_t sn = last ? sc : hc.next;
         load_win(nxt, sn);
-        const Hdr hn = load_hdr(sn);
+        const HdrV hn = load_hdr(sn);
         o1 = o2;
         q1s = q2s;
         own_load(o2, q);
@@ -973,14 +991,14 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(2))) v
             }
         }
         sc = sn;
-        hc = hn;
+        hc = uniform(hn);
         return !last;
     };
 
     __syncthreads();
     if (rA < rB) {
         sc = rinf[rA].x;   // the first slot of the wave's first run
-        hc = load_hdr(sc);
+        hc = uniform(load_hdr(sc));
         Win<CPL, NGW> wa, wb;
         load_win(wa, sc);
         for (;;) {
