@@ -684,11 +684,15 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
 // bookkeeping) at the same register count; NWV waves share the tile.
 // float32 partial sums over at most HK_FLUSH windows, float64 beyond (the
 // float32 state of the precision plan, float64 reductions).
-// HK_FLUSH: 64 windows (measured at c4, dense ms per step with 16 / 32 /
-// 64: 3.89 / 3.77 / 3.69; dL/dalpha's error against the oracle at
-// theta_pert 4.1e-8 at 16 and 5.0e-8 at 64, on all 1e7 events)
+// HK_FLUSH: 256 windows, more than a wave visits in one launch at c4's
+// chunks of 2^20 events (about 150), so there the accumulators are flushed
+// once, at the end; longer chunks flush every 256 windows (measured at c4,
+// dense ms per step with 16 / 32 / 64: 3.89 / 3.77 / 3.69 in an earlier form
+// of the kernel, and with 64 / 128 / 256 now: 3.33 / 3.31 / 3.28;
+// dL/dalpha's error against the oracle at theta_pert on all 1e7 events
+// 4.1e-8 at 16, 4.9e-8 at 64, 6.6e-8 at 256)
 #ifndef HK_FLUSH
-#define HK_FLUSH 64
+#define HK_FLUSH 256
 #endif
 template <int CPL, int DRB, int NGW, int NWV>
 __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(2))) void large_dense_f(int32_t M, int32_t NBC, int32_t NBR, int32_t ER, int32_t rpr,
