@@ -72,6 +72,31 @@ def test_long_chunks_match_oracle(H, lg, M):
     check(gpu, ref, f"chunk_log2={lg} M={M} n={n}")
 
 
+# The 32-row dense kernel adds its float32 rank-1 accumulators to the float64
+# tile every 256 windows that had own events.  At c4's shape a wave visits
+# about 150 windows per launch, so there only the final flush runs; here one
+# event range per chunk (the launch tuning) gives each of a tile's four waves
+# a quarter of a 2^20-event chunk, about 1300 windows with own events at
+# M = 400, so the periodic flush runs several times per wave.
+@pytest.mark.timeout(300)
+def test_dense_float32_accumulators_flush_periodically(H):
+    import torch
+    M, n = 400, (1 << 20) + 54321
+    print(f"periodic flush case: M={M} n={n} one event range", flush=True)
+    t, m, mu, alpha, beta, T = rand_problem(951, n, M, density=0.05, rate=60.0)
+    args = (dev(t, torch.float64), dev(m, torch.int32), dev(mu, torch.float32), dev(alpha, torch.float32),
+            dev(beta, torch.float32))
+    try:
+        H.set_tuning(dense_ranges=1, dense_rows=32)
+        L, gmu, ga, gb = H.loglik_grad(*args, T, 20)
+        torch.cuda.synchronize()
+    finally:
+        H.set_tuning()
+    gpu = (float(L.item()), gmu.cpu().numpy(), ga.cpu().numpy(), gb.cpu().numpy())
+    ref = oracle.forward(t, m, mu, alpha, beta, T)
+    check(gpu, ref, f"periodic flush M={M} n={n}")
+
+
 def _batch_to_dev(H, pb):
     import torch
     return H.Batch(dev(pb.ev_off, torch.int64), dev(pb.m_s, torch.int32), dev(pb.T_s, torch.float64),
