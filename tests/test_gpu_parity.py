@@ -171,11 +171,15 @@ def test_chunk_size_invariance(H):
         assert rel_err(x, y) < 1e-7
 
 
-def test_wide_batches_with_long_gaps(H):
+@pytest.mark.parametrize("M,rows", [(20, 0), (200, 32)])
+def test_wide_batches_with_long_gaps(H, M, rows):
     # gaps far longer than 1/beta inside 64-event batches exercise the
-    # per-event rescaling path of the dense kernel
+    # per-event rescaling path of the dense kernel: the 16-row kernel (M = 20)
+    # and the 32-row one (M = 200 with 256-column tiles, set through the
+    # launch tuning), whose wide windows add their own events' c_k to u and
+    # their pair terms with per-pair decays
     rng = np.random.default_rng(31)
-    n, M = 3000, 20
+    n = 3000
     gaps = rng.exponential(0.05, size=n)
     gaps[rng.random(n) < 0.05] = 200.0
     t = np.cumsum(gaps)
@@ -183,7 +187,12 @@ def test_wide_batches_with_long_gaps(H):
     _, _, mu, alpha, beta, _ = rand_problem(31, 10, M)
     T = float(t[-1] + 0.5)
     ref = oracle.forward(t, m, mu, alpha, beta, T)
-    check(run_gpu(H, t, m, mu, alpha, beta, T), ref, label="wide")
+    try:
+        H.set_tuning(dense_cols=256 if rows else 0, dense_rows=rows)
+        got = run_gpu(H, t, m, mu, alpha, beta, T)
+    finally:
+        H.set_tuning()
+    check(got, ref, label=f"wide M={M} rows={rows or 'auto'}")
 
 
 def test_determinism_bitwise(H):
