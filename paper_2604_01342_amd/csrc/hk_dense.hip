@@ -879,9 +879,12 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(2))) v
                 const int rofs = __double2hiint(od.x), ik = __double2loint(od.x);
                 if (cidx0 < ik) atomicAdd(&GP[rofs + colj0], od.y * bj0);
             };
+            // (an own event after the second group's first record follows
+            // all 64 records of the first group, which is full whenever a
+            // second one exists: its first atomic needs no mask)
             auto pair2 = [&](const double2 od) {
                 const int rofs = __double2hiint(od.x), ik = __double2loint(od.x);
-                if (cidx0 < ik) atomicAdd(&GP[rofs + colj0], od.y * bj0);
+                atomicAdd(&GP[rofs + colj0], od.y * bj0);
                 if (cidx1 < ik) atomicAdd(&GP[rofs + colj1], od.y * bj1);
             };
             const int kmid = NGW == 2 ? p + __builtin_popcountll(__ballot(own && (int)(b.key >> DRB) <= hc.first1))
