@@ -229,6 +229,14 @@ __global__ __launch_bounds__(64 * NWC) void dense_ck(int64_t c0, int32_t nev, in
         q.tw = g % NGW == 0 ? q.tg : rec_t(64 * NGW * (g / NGW) - 1);
     };
     const double tl = cntT > 0 ? rec_t(cntT - 1) : tau0;   // the state's time after the last group
+    // a checkpoint's state (this wave's 64 columns): float64, or float32 in
+    // the first half of the state words for the 32-row kernel
+    auto put_state = [&](int32_t slot, double K) {
+        if constexpr (DRB >= 5)
+            reinterpret_cast<float*>(kck + (int64_t)slot * S::SIZE)[wv * 64 + lane] = (float)K;
+        else
+            kck[(int64_t)slot * S::SIZE + wv * 64 + lane] = K;
+    };
     // a window's header: anchor time, time and event index of the window's
     // last record (after the last window: the anchor and the run's last
     // event), record count, next slot (-1: none), run, wide flag, index of
@@ -311,7 +319,7 @@ __global__ __launch_bounds__(64 * NWC) void dense_ck(int64_t c0, int32_t nev, in
         if (wv < CPL) {
             for (int u = 0; u < NWC && g0 + u < ng; ++u) {
                 const int32_t gg = g0 + u;
-                if (gg % NGW == 0) kck[(int64_t)(slot0 + gg / NGW) * S::SIZE + wv * 64 + lane] = K;
+                if (gg % NGW == 0) put_state(slot0 + gg / NGW, K);
                 K *= Fr[u];
                 const int col = st_col[u][lane];
                 if (col >= wv * 64 && col < wv * 64 + 64) {
@@ -331,7 +339,7 @@ __global__ __launch_bounds__(64 * NWC) void dense_ck(int64_t c0, int32_t nev, in
     // after the last group: the window up to the run's end, then the next
     // run's first slot (its P0 is this run's P1)
     const int32_t np = (ng + NGW - 1) / NGW;
-    if (wv < CPL) kck[(int64_t)(slot0 + np) * S::SIZE + wv * 64 + lane] = K;
+    if (wv < CPL) put_state(slot0 + np, K);
     if (wv == 0)
         put_hdr(np, tl, tl, sB * HK_SEG - 1, 0,
                 sB < nseg ? (P1 >> (NGW == 2 ? 7 : 6)) + 2 * (sb * nrun + r + 1) : -1, 0x7fffffff);
@@ -373,6 +381,15 @@ struct Win {
     double K[CPL];
     uint32_t ckey[NGW];   // records lane and 64 + lane of the window
     float bj[NGW];        // their e^{beta (t_j - tau)} (0 past the window's records)
+};
+// The same for the 32-row kernel, whose checkpoints keep the state in float32
+// (the matrix cores take it in float32; the first half of the slot's state
+// words holds it, so a window reads half the state bytes)
+template <int CPL, int NGW>
+struct WinF {
+    float K[CPL];
+    uint32_t ckey[NGW];
+    float bj[NGW];
 };
 
 // a window's header (wave-uniform, scalar loads)
@@ -799,10 +816,10 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(2))) v
     OwnBatch o0, o1, o2;
     own_load(o0, Q0);
     own_load(o2, Q0);
-    auto load_win = [&](Win<CPL, NGW>& w, int32_t slot) {
+    auto load_win = [&](WinF<CPL, NGW>& w, int32_t slot) {
         const uint32_t sl = (uint32_t)slot * S::SIZE;
 #pragma unroll
-        for (int j = 0; j < CPL; ++j) w.K[j] = ld_f64(rK, sl + j * 64 + lane);
+        for (int j = 0; j < CPL; ++j) w.K[j] = ld_f32(rK, 2 * sl + j * 64 + lane);
 #pragma unroll
         for (int h = 0; h < NGW; ++h) {
             w.bj[h] = ld_f32(rK, 2 * (sl + S::BJ) + 64 * h + lane);
@@ -845,7 +862,7 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(2))) v
     Hdr hc;           // and its header
     // own records of the window in o0 from lane p on (index <= hi): adds
     // their c_k to u and their pair terms to GP; returns how many there were
-    auto pass = [&](const Win<CPL, NGW>& w, int p, double tw, int hi, bool cv0, bool cv1, int cidx0, int cidx1,
+    auto pass = [&](const WinF<CPL, NGW>& w, int p, double tw, int hi, bool cv0, bool cv1, int cidx0, int cidx1,
                     int colj0, int colj1, double bj0, double bj1) -> int {
         const OwnBatch& b = o0;
         const bool own = qL + lane < Q1 && lane >= p && (int)(b.key >> DRB) <= hi;
@@ -939,7 +956,7 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(2))) v
     // the current window: slot sc with header hc; each window loads the next
     // one's data and header first (the same window again after the wave's
     // last one, so that every window issues the same loads)
-    auto body = [&](Win<CPL, NGW>& cur, Win<CPL, NGW>& nxt) -> bool {
+    auto body = [&](WinF<CPL, NGW>& cur, WinF<CPL, NGW>& nxt) -> bool {
         const bool last = hc.nv == 0 && hc.run >= rB - 1;
         const int32_t sn = last ? sc : hc.next;
         load_win(nxt, sn);
@@ -985,10 +1002,10 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(2))) v
             // clear u (u is this wave's; its atomics on u land before the reads)
             lds_wait();
             const float uv = (float)UL[lane & 31];
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x1f32(uv, (float)cur.K[0], acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x1f32(uv, (float)cur.K[1], acc1, 0, 0, 0);
-            acc2 = __builtin_amdgcn_mfma_f32_32x32x1f32(uv, (float)cur.K[2], acc2, 0, 0, 0);
-            acc3 = __builtin_amdgcn_mfma_f32_32x32x1f32(uv, (float)cur.K[3], acc3, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x1f32(uv, cur.K[0], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x1f32(uv, cur.K[1], acc1, 0, 0, 0);
+            acc2 = __builtin_amdgcn_mfma_f32_32x32x1f32(uv, cur.K[2], acc2, 0, 0, 0);
+            acc3 = __builtin_amdgcn_mfma_f32_32x32x1f32(uv, cur.K[3], acc3, 0, 0, 0);
             __builtin_amdgcn_wave_barrier();
             if (lane < DR) UL[lane] = 0.0;
             __builtin_amdgcn_wave_barrier();
@@ -1006,7 +1023,7 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(2))) v
     if (rA < rB) {
         sc = rinf[rA].x;   // the first slot of the wave's first run
         hc = uniform(load_hdr(sc));
-        Win<CPL, NGW> wa, wb;
+        WinF<CPL, NGW> wa, wb;
         load_win(wa, sc);
         for (;;) {
             if (!body(wa, wb)) break;
