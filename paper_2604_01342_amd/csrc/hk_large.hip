@@ -457,8 +457,9 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
         // the sums), beside the first wave's logarithm and reciprocal (one
         // wave: the first does all)
         constexpr int WC = NW - 1;
+        double eti = 0.0;   // e^{beta u_i} (anchored records; the first wave)
         if (wv == 0) {
-            const double eti = anch && valid ? exp_f64(bet * ui) : 0.0;   // e^{beta u_i}
+            eti = anch && valid ? exp_f64(bet * ui) : 0.0;
             tb[lane] = ti;
             eb[lane] = eti;
             if (valid) atomicOr((unsigned long long*)&rmask[mi], 1ull << lane);
@@ -575,16 +576,26 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
                 }
             }
         }
-        double ei = 1.0;   // e^{-beta u_i} (anchored records)
-        if (anch && valid && wv == 0) ei = exp_f64(-bet * ui);
+        // e^{-beta u_i} (anchored records) as the reciprocal of e^{beta u_i}
+        // (1 <= e^{beta u_i} <= e^600): a division instead of a second
+        // exponential on the first wave, whose share of the batch is the longer
+        double ei = 1.0;
+        if (anch && valid && wv == 0) ei = 1.0 / eti;
         if (!RM && valid && wv == WC) {
             // compensator terms of the event's node (eq. 2) and their
             // beta-derivative part (eq. 10)
             const double x = bet * (T - ti);
-            em1 = -expm1(-x);   // 1 - e^{-x}
+            const double ex = exp_f64(-x);
+            // 1 - e^{-x}: by subtraction when every event of the batch has
+            // x >= 0.5 (then 1 - e^{-x} >= 0.39 and the subtraction loses
+            // nothing), else by expm1 (a wave-uniform choice)
+            if (__ballot(x < 0.5) == 0)
+                em1 = 1.0 - ex;
+            else
+                em1 = -expm1(-x);
             const double cs_m = (double)__int_as_float(ni.w);
             comp += cs_m * em1;
-            if (GRAD) Esum += cs_m * (T - ti) * exp_f64(-x);
+            if (GRAD) Esum += cs_m * (T - ti) * ex;
         }
         if (RM && valid && wv == 0) {
             if (anch) {
