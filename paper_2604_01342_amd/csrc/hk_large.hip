@@ -338,6 +338,15 @@ __global__ void large_scan_apply(int32_t nseg, int32_t M, const double* __restri
 //             s is formed here from its group's carry, seg_off and seg_offdec
 //   bcnt      the chunk partition's counts, events per (node block of 2^bs
 //             nodes, segment), written as bucket_count would
+// 1 / x for a positive normal float64 x: the hardware reciprocal and two
+// Newton steps (within about 1 ulp; an IEEE division takes twice the
+// instructions)
+__device__ __forceinline__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+}
+
 template <bool GRAD, bool INTENS, bool SUPP, int NW, bool RM = false>
 __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1, int32_t M, double T,
                                                     const double* __restrict__ t, const int32_t* __restrict__ marks,
@@ -580,7 +589,7 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
         // (1 <= e^{beta u_i} <= e^600): a division instead of a second
         // exponential on the first wave, whose share of the batch is the longer
         double ei = 1.0;
-        if (anch && valid && wv == 0) ei = 1.0 / eti;
+        if (anch && valid && wv == 0) ei = recip(eti);
         if (!RM && valid && wv == WC) {
             // compensator terms of the event's node (eq. 2) and their
             // beta-derivative part (eq. 10)
@@ -613,7 +622,7 @@ __global__ __launch_bounds__(64 * NW) void large_forward(int64_t c0, int64_t c1,
         if (INTENS) lambda_out[i] = (float)lam;
             logsum += log(lam);
             if (GRAD) {
-                w = 1.0 / lam;
+                w = recip(lam);
                 gb += w * (R - bet * Dd);
             }
             if (SUPP) {
