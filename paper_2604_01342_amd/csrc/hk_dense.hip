@@ -392,11 +392,44 @@ struct WinF {
     float bj[NGW];
 };
 
-// a window's header (wave-uniform, scalar loads)
+// a window's header (wave-uniform)
 struct Hdr {
     double tau;   // the window's anchor (the slot also keeps its last record's time)
     int32_t hi, nv, next, run, wide, first1;
 };
+
+// A window's header as read by vector loads (every lane the same address)
+// and made wave-uniform only when its window starts: a scalar load shares
+// the LDS operations' wait counter, so while one is in flight every LDS wait
+// of the window before would also wait for the header to arrive from memory.
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+struct HdrV {
+    u32x2 tau;   // the anchor's bits
+    u32x4 a;     // hi, nv, next, run
+    u32x2 b;     // wide, first1
+};
+template <class S>
+__device__ __forceinline__ HdrV load_hdr_v(__amdgpu_buffer_rsrc_t r, int32_t slot) {
+    const uint32_t o = ((uint32_t)slot * S::SIZE + S::TAU) * 8u;
+    HdrV h;
+    h.tau = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(r, o, 0, 0));
+    h.a = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, o + 16u, 0, 0));
+    h.b = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(r, o + 32u, 0, 0));
+    return h;
+}
+__device__ __forceinline__ Hdr hdr_uniform(const HdrV& v) {
+    auto rf = [](uint32_t x) { return __builtin_amdgcn_readfirstlane((int)x); };
+    Hdr h;
+    h.tau = __hiloint2double(rf(v.tau.y), rf(v.tau.x));
+    h.hi = rf(v.a.x);
+    h.nv = rf(v.a.y);
+    h.next = rf(v.a.z);
+    h.run = rf(v.a.w);
+    h.wide = rf(v.b.x);
+    h.first1 = rf(v.b.y);
+    return h;
+}
 
 template <int CPL, int DRB, int NGW>
 __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 << DRB) * CPL > 32 ? 2 : 3))) void large_dense(int32_t M, int32_t NBC, int32_t NBR, int32_t ER, int32_t rpr,
@@ -414,7 +447,7 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
     constexpr int SH = CPL == 4 ? 8 : CPL == 2 ? 7 : 6;   // bits of the local mark in a column record key
     __shared__ double GP[DR * W];             // pair terms, shared by the group's waves
     __shared__ double ULs[HK_DW][DR];         // per wave: the window's u
-    __shared__ double2 ODs[HK_DW][66];        // per wave: own events of a pass (+2 read ahead)
+    __shared__ double2 ODs[HK_DW][68];        // per wave: own events of a pass (+3 read ahead)
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     double* UL = ULs[wv];
@@ -502,19 +535,9 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
             w.ckey[h] = ld_u32(rK, 2 * (sl + S::KEY) + 64 * h + lane);
         }
     };
-    auto load_hdr = [&](int32_t slot) -> Hdr {
-        const double* hp = kck + (int64_t)slot * S::SIZE + S::TAU;
-        const int32_t* hq = reinterpret_cast<const int32_t*>(hp + 2);
-        Hdr h;
-        h.tau = hp[0];
-        h.hi = hq[0];
-        h.nv = hq[1];
-        h.next = hq[2];
-        h.run = hq[3];
-        h.wide = hq[4];
-        h.first1 = hq[5];
-        return h;
-    };
+    // window headers by vector loads, made wave-uniform when their window
+    // starts (a scalar load would make the window's LDS waits wait for it)
+    auto load_hdr = [&](int32_t slot) -> HdrV { return load_hdr_v<S>(rK, slot); };
 
     int32_t sc = 0;   // the current window's slot
     Hdr hc;           // and its header
@@ -547,24 +570,42 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
             }
             // pair terms: own event k adds c_k b_j at (row_k, m_j) for the
             // window's records j before it (zero elsewhere)
-            auto pair = [&](const double2 od) {
+            // (the window's second 64 records only for an own event after the
+            // first of them; the own events are in index order, so those
+            // before it are the first kmid - p of the pass, and an own event
+            // after it follows all 64 records of the full first group)
+            auto pair1 = [&](const double2 od) {
                 const int rofs = __double2hiint(od.x), ik = __double2loint(od.x);
-                atomicAdd(&GP[rofs + colj0], cidx0 < ik ? od.y * bj0 : 0.0);
-                // the window's second 64 records only for an own event after
-                // the first of them
-                if (NGW == 2 && __builtin_amdgcn_readfirstlane(ik) > hc.first1)
-                    atomicAdd(&GP[rofs + colj1], cidx1 < ik ? od.y * bj1 : 0.0);
+                if (cidx0 < ik) atomicAdd(&GP[rofs + colj0], od.y * bj0);
             };
-            // two at a time, the next two entries read before this pair's
-            // atomics (entries past kend are read but not used)
-            double2 d1 = OD[p], d2 = OD[p + 1];
-            for (int k = p; k < kend; k += 2) {
-                const double2 n1 = OD[k + 2], n2 = OD[k + 3];
-                pair(d1);
-                if (k + 1 < kend) pair(d2);
-                d1 = n1;
-                d2 = n2;
-            }
+            auto pair2 = [&](const double2 od) {
+                const int rofs = __double2hiint(od.x), ik = __double2loint(od.x);
+                atomicAdd(&GP[rofs + colj0], od.y * bj0);
+                if (cidx1 < ik) atomicAdd(&GP[rofs + colj1], od.y * bj1);
+            };
+            const int kmid = NGW == 2 ? p + __builtin_popcountll(__ballot(own && (int)(b.key >> DRB) <= hc.first1))
+                                      : kend;
+            // entries [ka, kb), two at a time, the next two read before this
+            // pair's atomics (unrolled by two so that the entries read ahead
+            // need no register moves; entries up to kb + 2 are read, those
+            // past kb not used)
+            auto run = [&](int ka, int kb, auto&& pf) __attribute__((always_inline)) {
+                if (ka >= kb) return;
+                double2 d1 = OD[ka], d2 = OD[ka + 1];
+                for (int k = ka;; k += 4) {
+                    const double2 n1 = OD[k + 2], n2 = OD[k + 3];
+                    pf(d1);
+                    if (k + 1 < kb) pf(d2);
+                    if (k + 2 >= kb) break;
+                    d1 = OD[k + 4];
+                    d2 = OD[k + 5];
+                    pf(n1);
+                    if (k + 3 < kb) pf(n2);
+                    if (k + 4 >= kb) break;
+                }
+            };
+            run(p, kmid, pair1);
+            if (NGW == 2) run(kmid, kend, pair2);
         } else {
             // wide window (anchored factors would leave float32 range):
             // c_k decayed from the window's anchor (below float32 range it
@@ -598,7 +639,7 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
         const bool last = hc.nv == 0 && hc.run >= rB - 1;
         const int32_t sn = last ? sc : hc.next;
         load_win(nxt, sn);
-        const Hdr hn = load_hdr(sn);
+        const HdrV hn = load_hdr(sn);
         o1 = o2;
         q1s = q2s;
         own_load(o2, q);
@@ -651,14 +692,14 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
             __builtin_amdgcn_wave_barrier();
         }
         sc = sn;
-        hc = hn;
+        hc = hdr_uniform(hn);
         return !last;
     };
 
     __syncthreads();
     if (rA < rB) {
         sc = rinf[rA].x;   // the first slot of the wave's first run
-        hc = load_hdr(sc);
+        hc = hdr_uniform(load_hdr(sc));
         Win<CPL, NGW> wa, wb;
         load_win(wa, sc);
         for (;;) {
@@ -826,37 +867,9 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(2))) v
             w.ckey[h] = ld_u32(rK, 2 * (sl + S::KEY) + 64 * h + lane);
         }
     };
-    // window headers by vector loads (every lane the same address), made
-    // wave-uniform only when their window starts: a scalar load shares the
-    // LDS operations' wait counter, so every LDS wait of the window before
-    // would also wait for the next header to arrive from memory
-    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-    struct HdrV {
-        u32x2 tau;      // the anchor's bits
-        u32x4 a;        // hi, nv, next, run
-        u32x2 b;        // wide, first1
-    };
-    auto load_hdr = [&](int32_t slot) -> HdrV {
-        const uint32_t o = ((uint32_t)slot * S::SIZE + S::TAU) * 8u;
-        HdrV h;
-        h.tau = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rK, o, 0, 0));
-        h.a = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rK, o + 16u, 0, 0));
-        h.b = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rK, o + 32u, 0, 0));
-        return h;
-    };
-    auto uniform = [](const HdrV& v) -> Hdr {
-        auto rf = [](uint32_t x) { return __builtin_amdgcn_readfirstlane((int)x); };
-        Hdr h;
-        h.tau = __hiloint2double(rf(v.tau.y), rf(v.tau.x));
-        h.hi = rf(v.a.x);
-        h.nv = rf(v.a.y);
-        h.next = rf(v.a.z);
-        h.run = rf(v.a.w);
-        h.wide = rf(v.b.x);
-        h.first1 = rf(v.b.y);
-        return h;
-    };
+    // window headers by vector loads, made wave-uniform when their window
+    // starts (a scalar load would make the window's LDS waits wait for it)
+    auto load_hdr = [&](int32_t slot) -> HdrV { return load_hdr_v<S>(rK, slot); };
 
     int32_t sc = 0;   // the current window's slot
     Hdr hc;           // and its header
@@ -1015,14 +1028,14 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(2))) v
             }
         }
         sc = sn;
-        hc = uniform(hn);
+        hc = hdr_uniform(hn);
         return !last;
     };
 
     __syncthreads();
     if (rA < rB) {
         sc = rinf[rA].x;   // the first slot of the wave's first run
-        hc = uniform(load_hdr(sc));
+        hc = hdr_uniform(load_hdr(sc));
         WinF<CPL, NGW> wa, wb;
         load_win(wa, sc);
         for (;;) {
