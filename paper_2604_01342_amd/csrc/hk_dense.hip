@@ -41,7 +41,8 @@
 // own records), one window ahead, so their latency hides behind a window of
 // work.  dense_ck writes each window's bounds into its slot's header (the
 // window's last record, the record count, the next slot of the walk), so the
-// window loop reads them with scalar loads instead of tracking runs.
+// window loop reads them (vector loads, made wave-uniform when the window
+// starts) instead of tracking runs.
 #include "hk_device.h"
 #include "hk_large.h"
 #include "hk_stream.h"
@@ -736,8 +737,9 @@ __global__ __launch_bounds__(64 * HK_DW) __attribute__((amdgpu_waves_per_eu((1 <
 // cores as four float32 MFMAs (one per 64 columns, two 32 x 32 blocks each)
 // into float32 accumulators, added to the workgroup's float64 LDS tile every
 // HK_FLUSH windows that had own events, and at the end; the tile also takes
-// the pair terms and
-// starts from the event range's float64 partials.  Twice the rows per tile
+// the pair terms and starts from the event range's float64 partials; the
+// checkpoints keep this layout's state in float32, the form the matrix cores
+// take.  Twice the rows per tile
 // halve the window visits per event (the per-window loads, header and
 // bookkeeping) at the same register count; NWV waves share the tile.
 // float32 partial sums over at most HK_FLUSH windows, float64 beyond (the
